@@ -1,0 +1,179 @@
+/*
+ * ddeig.h -- C ABI of the MI355X library for the smallest eigenpair of the
+ * Q1 finite-element Schroedinger operator -Laplace + V on anisotropically
+ * long boxes, by sigma-shifted inverse iteration whose inner solves are CG
+ * preconditioned by two-level additive Schwarz with the PerFact coarse space
+ * (Theisen & Stamm, arXiv 2311.08757).
+ *
+ * Problem (§1, eq:schroedingerEquation, eq:geometry-description):
+ *   -Laplace(phi) + V phi = lambda phi on Omega_L = (0,L)^p x (0,ell)^q,
+ *   phi = 0 on the boundary, V of period 1 in every expanding direction x_i
+ *   (assumption A1) and bounded (A2).
+ * Discretisation (§2, eq:discrete-weak-form): Q1 elements on the uniform
+ * Cartesian grid of spacing h = 1/n_e made of translated copies of the unit
+ * cell mesh; the potential term uses the tensor 2-point Gauss-Legendre rule
+ * per element with V evaluated at cell-local x coordinates.  The algebraic
+ * problem is A x = lambda M x with A = K + M_V (stiffness + potential mass)
+ * and M the mass matrix (the paper's B); A_sigma = A - sigma M.
+ *
+ * Vector layout at this boundary: every vector is FP64, device resident, of
+ * length n_dof, holding the interior nodes (Dirichlet nodes eliminated) in
+ * lexicographic order with x1 fastest, then x2 (p = 2), then y1, then y2.
+ * A node with 1-based grid index i_a (1 <= i_a <= L n_e - 1 in expanding,
+ * 1 <= i_a <= ell n_e - 1 in fixed directions) sits at coordinate i_a h.
+ * Cell vectors (psi) hold the unit-cell nodes with x indices 0..n_e-1
+ * (periodic) and fixed-direction indices 1..ell n_e - 1, same ordering.
+ *
+ * Ownership: the handle owns every internal buffer; the caller owns every
+ * vector passed in (e.g. torch tensors, by data pointer).  Inputs and outputs
+ * must not alias.  All device work runs on the stream given to
+ * ddeig_assemble.  apply_op and apply_precond are asynchronous on that
+ * stream; cell_shift, pcg_solve and inverse_iteration synchronise it and
+ * return host scalars.
+ *
+ * Errors: every call returns a ddeig_status; no exception crosses the ABI.
+ * ddeig_last_error() returns a message for the last failing call of the
+ * calling thread.  One handle must not be used from two threads at once.
+ */
+#ifndef DDEIG_H
+#define DDEIG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DDEIG_OK = 0,
+  DDEIG_EINVAL = -1,     /* invalid argument (geometry, h, overlap, NULL, NaN) */
+  DDEIG_ENOMEM = -2,     /* device allocation failed */
+  DDEIG_EHIP = -3,       /* a HIP runtime call failed */
+  DDEIG_ENOTSPD = -4,    /* CG breakdown: p.A_sigma p <= 0 or r.z <= 0, or a
+                            non-positive pivot while factorising */
+  DDEIG_ENOCONV = -5,    /* iteration limit reached; outputs hold the last iterate */
+  DDEIG_ESTATE = -6,     /* call order violated (e.g. pcg_solve before cell_shift) */
+  DDEIG_EINTERNAL = -7
+} ddeig_status;
+
+/* Omega_L = (0,L)^p x (0,ell)^q (eq:geometry-description).  L >= 1 integer,
+ * p >= 1, q >= 1, p + q in {2, 3}; ell * n_e must be an integer. */
+typedef struct {
+  int p, q;
+  int L;
+  double ell;
+} ddeig_geometry;
+
+/* Periodic potentials V (period 1 in x, assumption A1).
+ *   CONST        V = c0
+ *   SEP_FOURIER  V = sum_t a_t cos(2 pi k_t x1 + phi_t) (1 + cy prod_j sin(pi y_j / ell))
+ *   FOURIER2     V = sum_t a_t cos(2 pi (k_t x1 + m_t x2) + phi_t)       (p = 2)
+ *   SIN4         V = c0 prod_i sin^4(pi x_i) prod_j sin^4(pi y_j / ell)    (§4.1)
+ *   SEP_SUM      V = c0 + sum_t a_t sin(2 pi k_t z_{m_t}) + sum_j g_j y_j  (§4.3;
+ *                m_t is the 0-based coordinate index of term t)
+ * Arrays have nterms entries (g has q); at most DDEIG_MAX_TERMS terms. */
+typedef enum {
+  DDEIG_V_CONST = 0,
+  DDEIG_V_SEP_FOURIER = 1,
+  DDEIG_V_FOURIER2 = 2,
+  DDEIG_V_SIN4 = 3,
+  DDEIG_V_SEP_SUM = 4
+} ddeig_vkind;
+
+#define DDEIG_MAX_TERMS 64
+
+typedef struct {
+  ddeig_vkind kind;
+  int nterms;
+  const double* a;    /* host arrays */
+  const double* phi;
+  const int* k;
+  const int* m;
+  double cy;
+  double c0;
+  const double* g;
+} ddeig_potential;
+
+typedef struct {
+  int pu;          /* partition of unity: 0 equal weights 1/#covering subdomains (§2.2),
+                      1 distance-based chi_i = d_i / sum_j d_j (§4.1.2) */
+  int coarse;      /* 0 one-level AS (eq:dd-preconditioners), 1 two-level AS with the
+                      PerFact coarse space (eq:two-level-preconditioners,
+                      def:algebraic-perfact-coarse-space) */
+  int local_prec;  /* local subdomain solves: 0 FP64, 1 FP32 factors with FP32 arithmetic */
+  int batch_iters; /* PCG iterations queued between host convergence checks (0: default 8) */
+} ddeig_options;
+
+typedef struct ddeig_problem ddeig_problem;
+
+typedef struct {
+  int iters;          /* PCG iterations performed */
+  double relres;      /* ||r_k||_2 / ||r_0||_2 of the recursively updated residual */
+  int breakdown;      /* 1 if p.A_sigma p <= 0, 2 if r.z <= 0 */
+  double* hist;       /* optional host array: hist[k] = ||r_k|| / ||r_0||, k = 0..iters */
+  int hist_cap;       /* capacity of hist */
+} ddeig_pcg_info;
+
+typedef struct {
+  double lambda;      /* sigma + x^T A_sigma x for the M-normalised x */
+  double dx_M;        /* ||x_k - x_{k-1}||_M of the last step */
+  int outer_its;
+  long inner_sum;
+  int inner_max;
+  double t_solve_ms;
+} ddeig_eig_info;
+
+/* Builds the period-cell operator tables (K, M, M_V at one period cell: §2,
+ * assumption A1), the decomposition of Omega_L into the L^p unit cells
+ * extended by `overlap` element layers (§3, §4.1) and the device buffers.
+ * h must be 1/n_e with n_e >= 3 an integer (checked to 1e-12 relative);
+ * 1 <= overlap and 2 overlap <= n_e.  `hip_stream` is a hipStream_t (NULL:
+ * the null stream).  Returns a new handle in *out. */
+ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_potential* V,
+                            int overlap, const ddeig_options* opts, void* hip_stream,
+                            ddeig_problem** out);
+
+/* Solves the periodic cell problem (eq:cell-problem, eq:weak-form-cell-problem)
+ * on the device: sigma = smallest eigenvalue of (K# + M_V#) psi = sigma M# psi,
+ * psi > 0, psi^T M# psi = 1.  Then finishes every sigma-dependent set-up: the
+ * shifted operator, the local subdomain factorisations of A_sigma,i
+ * (eq:twoLevelASMPreconditioner), the coarse basis and coarse matrix.
+ * psi_cell_host (nullable) receives n_cell values. */
+ddeig_status ddeig_cell_shift(ddeig_problem* P, double* sigma_out, double* psi_cell_host);
+
+/* Test/debug override of the shift: uses the given sigma and cell vector
+ * (n_cell host values, nullable for one-level preconditioning only) instead of
+ * solving the cell problem, then does the same set-up as ddeig_cell_shift. */
+ddeig_status ddeig_set_shift(ddeig_problem* P, double sigma, const double* psi_cell_host);
+
+/* y = Op x on the device, Op = 0: A_sigma, 1: A = K + M_V, 2: M, 3: K.
+ * which = 0 needs a shift (cell_shift or set_shift); the others only assemble. */
+ddeig_status ddeig_apply_op(ddeig_problem* P, int which, const double* x, double* y);
+
+/* z = M_AS,2^{-1} r (or M_AS,1^{-1} r with options.coarse = 0):
+ * sum_i R_i^T A_sigma,i^{-1} R_i r + R_0^T A_sigma,0^{-1} R_0 r  (§3). */
+ddeig_status ddeig_apply_precond(ddeig_problem* P, const double* r, double* z);
+
+/* Preconditioned CG for A_sigma x = b (§2.1, §3): x holds x0 on entry and the
+ * iterate on exit; stops when ||r_k||_2 <= rtol ||r_0||_2 (§4.1).  Returns
+ * DDEIG_ENOCONV after maxit iterations, DDEIG_ENOTSPD on breakdown. */
+ddeig_status ddeig_pcg_solve(ddeig_problem* P, const double* b, double* x, double rtol,
+                             int maxit, ddeig_pcg_info* info);
+
+/* sigma-shifted inverse iteration (§2): x_{k+1} = A_sigma^{-1} M x_k solved by
+ * PCG from a zero guess to rtol_inner, M-normalised, sign fixed so that
+ * 1^T M x > 0; stops when ||x_{k+1} - x_k||_M <= tol_x or after maxit_outer
+ * steps.  x: on entry the start vector (all zeros selects 1/||1||_M); on exit
+ * the M-normalised eigenvector. */
+ddeig_status ddeig_inverse_iteration(ddeig_problem* P, double* x, double tol_x, int maxit_outer,
+                                     double rtol_inner, int maxit_inner, ddeig_eig_info* info);
+
+/* Sizes: interior unknowns, cell unknowns, number of subdomains (= coarse dimension). */
+ddeig_status ddeig_query(const ddeig_problem* P, long* n_dof, long* n_cell, int* n_sub);
+
+void ddeig_destroy(ddeig_problem* P);
+const char* ddeig_status_string(ddeig_status s);
+const char* ddeig_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDEIG_H */

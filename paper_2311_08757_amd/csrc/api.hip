@@ -1,0 +1,677 @@
+// Host side of libddeig: argument validation, decomposition bookkeeping,
+// device memory, and the drivers of the cell problem, PCG and inverse
+// iteration.  Every call returns a ddeig_status; HIP failures and
+// allocation failures are turned into status codes here.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "k_common.h"
+
+using namespace ddeig;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Failure {
+  ddeig_status status;
+  std::string msg;
+};
+
+ddeig_status set_error(ddeig_status s, const std::string& m) {
+  g_last_error = m;
+  return s;
+}
+
+template <typename T>
+T* dalloc(ddeig_problem* P, size_t count) {
+  void* p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(&p, count * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Failure{DDEIG_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+  }
+  P->allocs.push_back(p);
+  return static_cast<T*>(p);
+}
+
+void dfree(ddeig_problem* P, void* p) {
+  if (!p) return;
+  auto it = std::find(P->allocs.begin(), P->allocs.end(), p);
+  if (it != P->allocs.end()) P->allocs.erase(it);
+  (void)hipFree(p);
+}
+
+void sync(ddeig_problem* P) { check_hip(hipStreamSynchronize(P->stream), "hipStreamSynchronize"); }
+
+void check_launch(const char* what) { check_hip(hipGetLastError(), what); }
+
+double host_sum(ddeig_problem* P, const double* part) {
+  launch_sum_partials(part, P->scal, P->stream);
+  double v = 0.0;
+  check_hip(hipMemcpyAsync(&v, P->scal, sizeof(double), hipMemcpyDeviceToHost, P->stream),
+            "copy scalar");
+  sync(P);
+  return v;
+}
+
+double* slot(ddeig_problem* P, int i) { return P->part + (long)i * kRedBlocks; }
+
+// The cell box: whole unit cell, periodic in x (origin -1 so that the node
+// index equals the cell index), all fixed-direction unknowns.
+Box cell_box(const Geo& g) {
+  Box b;
+  for (int a = 0; a < 3; ++a) {
+    if (a >= g.D) {
+      b.o[a] = 0; b.m[a] = 1; b.per[a] = 0;
+    } else if (g.isx[a]) {
+      b.o[a] = -1; b.m[a] = g.ne; b.per[a] = 1;
+    } else {
+      b.o[a] = 0; b.m[a] = g.N[a]; b.per[a] = 0;
+    }
+  }
+  b.b = 1;
+  for (int a = 0; a < g.D - 1; ++a) b.b *= b.m[a];
+  b.nch = b.m[g.D - 1];
+  return b;
+}
+
+// Smallest generalised eigenvalue of the 1-D Dirichlet linear-element pair
+// with nel elements: mu(theta) = (6/h^2)(1 - cos theta)/(2 + cos theta), theta = pi / nel.
+double mu_min(int nel, double h) {
+  const double th = M_PI / nel;
+  return 6.0 / (h * h) * (1.0 - std::cos(th)) / (2.0 + std::cos(th));
+}
+
+// min of V over the 2-point Gauss points of the cell elements
+double cell_vmin(const ddeig_problem* P) {
+  const Geo& g = P->g;
+  const double xs[2] = {0.5 * (1.0 - 1.0 / std::sqrt(3.0)), 0.5 * (1.0 + 1.0 / std::sqrt(3.0))};
+  int ecount[3] = {1, 1, 1};
+  for (int a = 0; a < g.D; ++a) ecount[a] = g.isx[a] ? g.ne : g.nel[a];
+  double vmin = INFINITY;
+  for (int e2 = 0; e2 < ecount[2]; ++e2)
+    for (int e1 = 0; e1 < ecount[1]; ++e1)
+      for (int e0 = 0; e0 < ecount[0]; ++e0) {
+        const int ee[3] = {e0, e1, e2};
+        for (int qi = 0; qi < (1 << g.D); ++qi) {
+          double z[3] = {0, 0, 0};
+          for (int a = 0; a < g.D; ++a) z[a] = (ee[a] + xs[(qi >> a) & 1]) * g.h;
+          vmin = std::min(vmin, eval_V(P->vs, z));
+        }
+      }
+  return vmin;
+}
+
+void factor_types(ddeig_problem* P) {
+  for (auto& t : P->types) {
+    chain_factor(P, t.box, P->tabAs, t.W, P->stream);
+    if (P->opt.local_prec == 1)
+      launch_to_float(t.W, t.W32, (long)t.box.nch * t.box.b * t.box.b, P->stream);
+  }
+  check_launch("local factorisation");
+}
+
+int read_flag(ddeig_problem* P) {
+  int f = 0;
+  check_hip(hipMemcpyAsync(&f, P->flag, sizeof(int), hipMemcpyDeviceToHost, P->stream), "flag");
+  sync(P);
+  return f;
+}
+
+void clear_flag(ddeig_problem* P) {
+  check_hip(hipMemsetAsync(P->flag, 0, sizeof(int), P->stream), "memset flag");
+}
+
+// sigma-dependent set-up: shifted table, local factors, coarse matrix.
+ddeig_status finish_shift(ddeig_problem* P) {
+  launch_shift_table(P, P->stream);
+  clear_flag(P);
+  factor_types(P);
+  if (read_flag(P)) return set_error(DDEIG_ENOTSPD, "a local matrix A_sigma,i is not positive definite");
+  if (P->opt.coarse) {
+    build_coarse_matrix(P, P->A0inv, P->stream);
+    launch_gj_invert(P, P->A0inv, P->nsub, P->stream);
+    launch_symmetrise(P->A0inv, P->nsub, P->stream);
+    check_launch("coarse set-up");
+    if (read_flag(P)) return set_error(DDEIG_ENOTSPD, "the coarse matrix A_sigma,0 is not positive definite");
+  }
+  P->shifted = 1;
+  return DDEIG_OK;
+}
+
+void precond_apply(ddeig_problem* P, const double* r, double* z, double* dot, const PcgState* st) {
+  const int coarse = P->opt.coarse;
+  launch_restrict(P, r, coarse, st, P->stream);
+  launch_local_solves(P, st, P->stream);
+  if (coarse) launch_coarse_solve(P, st, P->stream);
+  launch_extend(P, r, z, coarse, dot, st, P->stream);
+}
+
+struct PcgOut {
+  int iters = 0;
+  double relres = 0.0;
+  int done = 0;
+};
+
+// PCG on A_sigma x = b (x holds x0).  Queues `batch` iterations between host checks.
+PcgOut pcg_run(ddeig_problem* P, const double* b, double* x, double rtol, int maxit) {
+  const hipStream_t s = P->stream;
+  const int batch = P->opt.batch_iters > 0 ? P->opt.batch_iters : 8;
+  launch_stencil(P, P->tabAs, x, P->q, nullptr, nullptr, s);
+  launch_resid_init(P, b, P->q, P->r, slot(P, 1), s);
+  launch_pcg_init(P, rtol, slot(P, 1), s);
+  precond_apply(P, P->r, P->z, slot(P, 2), P->st);
+  launch_pcg_start(P, P->z, P->p, slot(P, 2), s);
+  check_launch("pcg start");
+  PcgState hs{};
+  int k = 0;
+  if (maxit <= 0) {
+    check_hip(hipMemcpyAsync(&hs, P->st, sizeof(PcgState), hipMemcpyDeviceToHost, s), "state");
+    sync(P);
+  }
+  while (k < maxit) {
+    const int kend = std::min(maxit, k + batch);
+    for (++k; k <= kend; ++k) {
+      launch_stencil(P, P->tabAs, P->p, P->q, slot(P, 0), nullptr, s);
+      launch_pcg_update_xr(P, x, P->p, P->q, P->r, slot(P, 0), slot(P, 1), k, s);
+      launch_pcg_check(P, slot(P, 1), k, maxit, s);
+      precond_apply(P, P->r, P->z, slot(P, 2), P->st);
+      launch_pcg_update_p(P, P->z, P->p, slot(P, 2), k, s);
+    }
+    --k;
+    check_launch("pcg iteration");
+    check_hip(hipMemcpyAsync(&hs, P->st, sizeof(PcgState), hipMemcpyDeviceToHost, s), "state");
+    sync(P);
+    if (hs.done) break;
+  }
+  PcgOut o;
+  o.iters = hs.iters;
+  o.relres = hs.relres;
+  o.done = hs.done;
+  if (maxit <= 0 && hs.done == 0) o.done = 4;
+  return o;
+}
+
+ddeig_status validate_vec(const void* p, const char* name) {
+  if (p == nullptr) return set_error(DDEIG_EINVAL, std::string(name) + " is NULL");
+  return DDEIG_OK;
+}
+
+}  // namespace
+
+namespace ddeig {
+void check_hip(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Failure{DDEIG_EHIP, std::string(what) + ": " + hipGetErrorString(e)};
+  }
+}
+}  // namespace ddeig
+
+#define API_GUARD_BEGIN try {
+#define API_GUARD_END                                                  \
+  }                                                                    \
+  catch (const Failure& f) {                                           \
+    return set_error(f.status, f.msg);                                 \
+  }                                                                    \
+  catch (const std::bad_alloc&) {                                      \
+    return set_error(DDEIG_ENOMEM, "host allocation failed");          \
+  }                                                                    \
+  catch (...) {                                                        \
+    return set_error(DDEIG_EINTERNAL, "unexpected internal exception"); \
+  }
+
+extern "C" {
+
+const char* ddeig_status_string(ddeig_status s) {
+  switch (s) {
+    case DDEIG_OK: return "ok";
+    case DDEIG_EINVAL: return "invalid argument";
+    case DDEIG_ENOMEM: return "out of memory";
+    case DDEIG_EHIP: return "HIP runtime error";
+    case DDEIG_ENOTSPD: return "operator or preconditioner not positive definite";
+    case DDEIG_ENOCONV: return "iteration limit reached";
+    case DDEIG_ESTATE: return "call order violated";
+    case DDEIG_EINTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+const char* ddeig_last_error(void) { return g_last_error.c_str(); }
+
+ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_potential* V,
+                            int overlap, const ddeig_options* opts, void* hip_stream,
+                            ddeig_problem** out) {
+  if (out == nullptr) return set_error(DDEIG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (geom == nullptr || V == nullptr) return set_error(DDEIG_EINVAL, "geometry or potential is NULL");
+  const int p = geom->p, q = geom->q, L = geom->L;
+  if (p < 1 || q < 1 || p + q < 2 || p + q > 3)
+    return set_error(DDEIG_EINVAL, "need p >= 1, q >= 1 and p + q in {2, 3}");
+  if (L < 1) return set_error(DDEIG_EINVAL, "L must be >= 1");
+  if (!std::isfinite(h) || h <= 0.0) return set_error(DDEIG_EINVAL, "h must be positive and finite");
+  const double ne_d = 1.0 / h;
+  const long ne_l = std::lround(ne_d);
+  if (std::fabs(ne_d - (double)ne_l) > 1e-12 * ne_d || ne_l < 3 || ne_l > 4096)
+    return set_error(DDEIG_EINVAL, "1/h must be an integer n_e with 3 <= n_e <= 4096");
+  const int ne = (int)ne_l;
+  const double ell = geom->ell;
+  if (!std::isfinite(ell) || ell <= 0.0) return set_error(DDEIG_EINVAL, "ell must be positive");
+  const double elne_d = ell * ne;
+  const long elne = std::lround(elne_d);
+  if (std::fabs(elne_d - (double)elne) > 1e-9 * elne_d || elne < 2)
+    return set_error(DDEIG_EINVAL, "ell * n_e must be an integer >= 2");
+  if (overlap < 1 || 2 * overlap > ne)
+    return set_error(DDEIG_EINVAL, "overlap must satisfy 1 <= overlap and 2 overlap <= n_e");
+  if (V->nterms < 0 || V->nterms > DDEIG_MAX_TERMS)
+    return set_error(DDEIG_EINVAL, "nterms out of range");
+  if ((int)V->kind < 0 || (int)V->kind > 4) return set_error(DDEIG_EINVAL, "unknown potential kind");
+  if (V->kind == DDEIG_V_FOURIER2 && p != 2)
+    return set_error(DDEIG_EINVAL, "FOURIER2 potentials need p = 2");
+  ddeig_options o{0, 1, 0, 8};
+  if (opts) o = *opts;
+  if (o.pu < 0 || o.pu > 1 || o.coarse < 0 || o.coarse > 1 || o.local_prec < 0 ||
+      o.local_prec > 1 || o.batch_iters < 0)
+    return set_error(DDEIG_EINVAL, "invalid options");
+
+  ddeig::VSpec vs{};
+  vs.kind = (int)V->kind;
+  vs.nterms = V->nterms;
+  vs.p = p;
+  vs.q = q;
+  vs.cy = V->cy;
+  vs.c0 = V->c0;
+  vs.ell = ell;
+  const bool needs_terms = V->kind == DDEIG_V_SEP_FOURIER || V->kind == DDEIG_V_FOURIER2 ||
+                           V->kind == DDEIG_V_SEP_SUM;
+  if (needs_terms && V->nterms > 0) {
+    if (V->a == nullptr || V->k == nullptr) return set_error(DDEIG_EINVAL, "potential arrays are NULL");
+    if ((V->kind != DDEIG_V_SEP_SUM) && V->phi == nullptr)
+      return set_error(DDEIG_EINVAL, "potential phases are NULL");
+    if ((V->kind == DDEIG_V_FOURIER2 || V->kind == DDEIG_V_SEP_SUM) && V->m == nullptr)
+      return set_error(DDEIG_EINVAL, "potential m array is NULL");
+    for (int t = 0; t < V->nterms; ++t) {
+      vs.a[t] = V->a[t];
+      vs.phi[t] = V->phi ? V->phi[t] : 0.0;
+      vs.k[t] = V->k[t];
+      vs.m[t] = V->m ? V->m[t] : 0;
+      if (!std::isfinite(vs.a[t]) || !std::isfinite(vs.phi[t]))
+        return set_error(DDEIG_EINVAL, "non-finite potential coefficient");
+      if (V->kind == DDEIG_V_SEP_SUM && (vs.m[t] < 0 || vs.m[t] >= p + q))
+        return set_error(DDEIG_EINVAL, "SEP_SUM axis out of range");
+    }
+  }
+  if (V->kind == DDEIG_V_SEP_SUM && V->g != nullptr)
+    for (int j = 0; j < q; ++j) vs.g[j] = V->g[j];
+  if (!std::isfinite(vs.cy) || !std::isfinite(vs.c0)) return set_error(DDEIG_EINVAL, "non-finite cy/c0");
+
+  ddeig::Geo g{};
+  g.p = p; g.q = q; g.D = p + q; g.L = L; g.ne = ne;
+  g.h = 1.0 / ne; g.ell = ell;
+  g.ntaps = g.D == 2 ? 9 : 27;
+  long n = 1, ts = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (a >= g.D) {
+      g.nel[a] = 1; g.N[a] = 1; g.P[a] = 1; g.isx[a] = 0;
+      continue;
+    }
+    g.isx[a] = a < p;
+    g.nel[a] = g.isx[a] ? L * ne : (int)elne;
+    g.N[a] = g.nel[a] - 1;
+    g.P[a] = g.isx[a] ? ne : g.N[a];
+    n *= g.N[a];
+    ts *= g.P[a];
+  }
+  if (n < 1) return set_error(DDEIG_EINVAL, "no interior unknowns");
+  if (n > (1L << 34)) return set_error(DDEIG_EINVAL, "problem too large");
+  g.n = n;
+  g.tsize = ts;
+
+  ddeig_problem* P = new (std::nothrow) ddeig_problem();
+  if (!P) return set_error(DDEIG_ENOMEM, "host allocation failed");
+  P->g = g;
+  P->vs = vs;
+  P->delta = overlap;
+  P->opt = o;
+  P->stream = static_cast<hipStream_t>(hip_stream);
+  try {
+    const hipStream_t s = P->stream;
+    const long tt = g.tsize * g.ntaps;
+    P->tabK = dalloc<double>(P, tt);
+    P->tabM = dalloc<double>(P, tt);
+    P->tabA = dalloc<double>(P, tt);
+    P->tabAs = dalloc<double>(P, tt);
+    P->dVS = dalloc<ddeig::VSpec>(P, 1);
+    check_hip(hipMemcpyAsync(P->dVS, &P->vs, sizeof(ddeig::VSpec), hipMemcpyHostToDevice, s), "copy V");
+    launch_build_tables(P, s);
+    check_launch("build tables");
+
+    // decomposition into the L^p unit cells with `overlap` layers (§3, §4.1)
+    const int nsub = p == 1 ? L : L * L;
+    P->nsub = nsub;
+    std::map<std::vector<int>, int> type_of;
+    P->subs.resize(nsub);
+    for (int sid = 0; sid < nsub; ++sid) {
+      int c[3] = {sid % L + 1, p == 2 ? sid / L + 1 : 0, 0};
+      ddeig::SubDev sd{};
+      Box bx{};
+      std::vector<int> key;
+      for (int a = 0; a < 3; ++a) {
+        bx.per[a] = 0;
+        if (a >= g.D) { bx.o[a] = 0; bx.m[a] = 1; continue; }
+        if (g.isx[a]) {
+          const int lo = std::max((c[a] - 1) * ne - overlap + 1, 1);
+          const int hi = std::min(c[a] * ne + overlap - 1, L * ne - 1);
+          bx.o[a] = lo - 1;
+          bx.m[a] = hi - lo + 1;
+          const int cls = (L == 1) ? 3 : (c[a] == 1 ? 0 : (c[a] == L ? 2 : 1));
+          key.push_back(cls);
+        } else {
+          bx.o[a] = 0;
+          bx.m[a] = g.N[a];
+        }
+      }
+      bx.b = 1;
+      for (int a = 0; a < g.D - 1; ++a) bx.b *= bx.m[a];
+      bx.nch = bx.m[g.D - 1];
+      for (int a = 0; a < 3; ++a) { sd.o[a] = bx.o[a]; sd.c[a] = c[a]; }
+      auto it = type_of.find(key);
+      int tid;
+      if (it == type_of.end()) {
+        tid = (int)P->types.size();
+        type_of[key] = tid;
+        ddeig::SubType t;
+        t.box = bx;
+        t.nmem = 0;
+        P->types.push_back(t);
+      } else {
+        tid = it->second;
+      }
+      auto& T = P->types[tid];
+      sd.type = tid;
+      sd.slot = T.nmem++;
+      T.members.push_back(sid);
+      P->subs[sid] = sd;
+    }
+    int maxb = 0;
+    std::vector<ddeig::TypeDev> tdev(P->types.size());
+    for (size_t t = 0; t < P->types.size(); ++t) {
+      auto& T = P->types[t];
+      maxb = std::max(maxb, T.box.b);
+      const long mm = (long)T.box.nch * T.box.b;
+      T.batch = dalloc<double>(P, (size_t)T.nmem * mm);
+      T.W = dalloc<double>(P, (size_t)T.box.nch * T.box.b * T.box.b);
+      if (o.local_prec == 1) T.W32 = dalloc<float>(P, (size_t)T.box.nch * T.box.b * T.box.b);
+      for (int a = 0; a < 3; ++a) tdev[t].m[a] = T.box.m[a];
+      tdev[t].b = T.box.b;
+      tdev[t].nch = T.box.nch;
+      tdev[t].W = T.W;
+      tdev[t].W32 = T.W32;
+      tdev[t].batch = T.batch;
+    }
+    P->maxb = std::max(maxb, 1);
+    const Box cb = cell_box(g);
+    const int gjmax = std::max(std::max(maxb, cb.b), nsub);
+    P->dSubs = dalloc<ddeig::SubDev>(P, nsub);
+    P->dTypes = dalloc<ddeig::TypeDev>(P, tdev.size());
+    check_hip(hipMemcpyAsync(P->dSubs, P->subs.data(), sizeof(ddeig::SubDev) * nsub,
+                             hipMemcpyHostToDevice, s), "copy subdomains");
+    check_hip(hipMemcpyAsync(P->dTypes, tdev.data(), sizeof(ddeig::TypeDev) * tdev.size(),
+                             hipMemcpyHostToDevice, s), "copy types");
+    P->r = dalloc<double>(P, n);
+    P->z = dalloc<double>(P, n);
+    P->p = dalloc<double>(P, n);
+    P->q = dalloc<double>(P, n);
+    P->u = dalloc<double>(P, n);
+    P->w = dalloc<double>(P, n);
+    P->part = dalloc<double>(P, 8 * (size_t)kRedBlocks);
+    P->st = dalloc<ddeig::PcgState>(P, 1);
+    P->hist_cap = 10001;
+    P->hist = dalloc<double>(P, P->hist_cap);
+    P->scal = dalloc<double>(P, 8);
+    P->flag = dalloc<int>(P, 1);
+    P->gjbuf = dalloc<double>(P, 4 * (size_t)gjmax);
+    P->gj_stride = gjmax;
+    P->psi = dalloc<double>(P, g.tsize);
+    P->crhs = dalloc<double>(P, nsub);
+    P->cy = dalloc<double>(P, nsub);
+    P->A0inv = dalloc<double>(P, (size_t)nsub * nsub);
+    check_hip(hipMemsetAsync(P->flag, 0, sizeof(int), s), "memset flag");
+    check_hip(hipMemsetAsync(P->psi, 0, sizeof(double) * g.tsize, s), "memset psi");
+    sync(P);
+  } catch (const Failure& f) {
+    ddeig_destroy(P);
+    return set_error(f.status, f.msg);
+  } catch (...) {
+    ddeig_destroy(P);
+    return set_error(DDEIG_EINTERNAL, "unexpected exception in assemble");
+  }
+  *out = P;
+  return DDEIG_OK;
+}
+
+void ddeig_destroy(ddeig_problem* P) {
+  if (!P) return;
+  if (P->stream) (void)hipStreamSynchronize(P->stream);
+  else (void)hipDeviceSynchronize();
+  for (void* p : P->allocs) (void)hipFree(p);
+  P->allocs.clear();
+  delete P;
+}
+
+ddeig_status ddeig_query(const ddeig_problem* P, long* n_dof, long* n_cell, int* n_sub) {
+  if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
+  if (n_dof) *n_dof = P->g.n;
+  if (n_cell) *n_cell = P->g.tsize;
+  if (n_sub) *n_sub = P->nsub;
+  return DDEIG_OK;
+}
+
+ddeig_status ddeig_set_shift(ddeig_problem* P, double sigma, const double* psi_cell_host) {
+  if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
+  if (!std::isfinite(sigma)) return set_error(DDEIG_EINVAL, "sigma must be finite");
+  if (psi_cell_host == nullptr && P->opt.coarse)
+    return set_error(DDEIG_EINVAL, "the two-level preconditioner needs the cell vector psi");
+  API_GUARD_BEGIN
+  P->shifted = 0;
+  P->sigma = sigma;
+  if (psi_cell_host)
+    check_hip(hipMemcpyAsync(P->psi, psi_cell_host, sizeof(double) * P->g.tsize,
+                             hipMemcpyHostToDevice, P->stream), "copy psi");
+  sync(P);
+  return finish_shift(P);
+  API_GUARD_END
+}
+
+ddeig_status ddeig_cell_shift(ddeig_problem* P, double* sigma_out, double* psi_cell_host) {
+  if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
+  API_GUARD_BEGIN
+  P->shifted = 0;
+  const Geo& g = P->g;
+  const hipStream_t s = P->stream;
+  const Box cb = cell_box(g);
+  const long nc = g.tsize;
+  // a guaranteed lower bound of sigma: the stiffness in every fixed direction is
+  // at least mu_min times the mass, the x parts are non-negative, and the
+  // 2-point rule integrates the mass exactly, so M_V >= min V M
+  double s0 = cell_vmin(P) - 1.0;
+  for (int a = 0; a < g.D; ++a)
+    if (!g.isx[a]) s0 += mu_min(g.nel[a], g.h);
+  P->sigma = s0;
+  launch_shift_table(P, s);
+  double* Wc = dalloc<double>(P, (size_t)cb.nch * cb.b * cb.b);
+  double* v0 = dalloc<double>(P, nc);  // psi_k
+  double* v1 = dalloc<double>(P, nc);  // M psi_k
+  double* v2 = dalloc<double>(P, nc);  // solve
+  double* v3 = dalloc<double>(P, nc);  // M solve
+  clear_flag(P);
+  chain_factor(P, cb, P->tabAs, Wc, s);
+  check_launch("cell factorisation");
+  if (read_flag(P)) {
+    dfree(P, Wc); dfree(P, v0); dfree(P, v1); dfree(P, v2); dfree(P, v3);
+    return set_error(DDEIG_ENOTSPD, "cell operator shifted below its spectrum is not positive definite");
+  }
+  launch_fill(v0, nc, 1.0, s);
+  double prev = INFINITY;
+  int it = 0;
+  for (; it < 2000; ++it) {
+    launch_box_stencil(P, cb, P->tabM, v0, v1, nullptr, nullptr, s);
+    launch_copy(v2, v1, nc, s);
+    launch_chain_solve_box(P, cb, P->tabAs, Wc, v2, 1, s);
+    launch_box_stencil(P, cb, P->tabM, v2, v3, slot(P, 4), slot(P, 5), s);
+    launch_ipm_normalise(nc, v2, v3, v0, v1, slot(P, 4), slot(P, 5), slot(P, 6), s);
+    check_launch("cell iteration");
+    const double d2 = host_sum(P, slot(P, 6));
+    const double d = std::sqrt(std::max(d2, 0.0));
+    if (d <= 1e-14) break;
+    if (it > 10 && d < 1e-12 && d > 0.8 * prev) break;  // stagnated at rounding level
+    prev = d;
+  }
+  // sigma = psi^T A# psi with psi M#-normalised
+  launch_box_stencil(P, cb, P->tabA, v0, v1, slot(P, 4), nullptr, s);
+  const double sig = host_sum(P, slot(P, 4));
+  launch_copy(P->psi, v0, nc, s);
+  if (psi_cell_host)
+    check_hip(hipMemcpyAsync(psi_cell_host, v0, sizeof(double) * nc, hipMemcpyDeviceToHost, s), "copy psi");
+  sync(P);
+  dfree(P, Wc); dfree(P, v0); dfree(P, v1); dfree(P, v2); dfree(P, v3);
+  P->sigma = sig;
+  if (sigma_out) *sigma_out = sig;
+  return finish_shift(P);
+  API_GUARD_END
+}
+
+ddeig_status ddeig_apply_op(ddeig_problem* P, int which, const double* x, double* y) {
+  if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
+  if (validate_vec(x, "x") || validate_vec(y, "y")) return DDEIG_EINVAL;
+  if (x == y) return set_error(DDEIG_EINVAL, "x and y must not alias");
+  const double* tab = nullptr;
+  switch (which) {
+    case 0:
+      if (!P->shifted) return set_error(DDEIG_ESTATE, "apply_op(A_sigma) before the shift is set");
+      tab = P->tabAs;
+      break;
+    case 1: tab = P->tabA; break;
+    case 2: tab = P->tabM; break;
+    case 3: tab = P->tabK; break;
+    default: return set_error(DDEIG_EINVAL, "which must be 0..3");
+  }
+  API_GUARD_BEGIN
+  launch_stencil(P, tab, x, y, nullptr, nullptr, P->stream);
+  check_launch("apply_op");
+  return DDEIG_OK;
+  API_GUARD_END
+}
+
+ddeig_status ddeig_apply_precond(ddeig_problem* P, const double* r, double* z) {
+  if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
+  if (validate_vec(r, "r") || validate_vec(z, "z")) return DDEIG_EINVAL;
+  if (r == z) return set_error(DDEIG_EINVAL, "r and z must not alias");
+  if (!P->shifted) return set_error(DDEIG_ESTATE, "apply_precond before the shift is set");
+  API_GUARD_BEGIN
+  precond_apply(P, r, z, nullptr, nullptr);
+  check_launch("apply_precond");
+  return DDEIG_OK;
+  API_GUARD_END
+}
+
+ddeig_status ddeig_pcg_solve(ddeig_problem* P, const double* b, double* x, double rtol, int maxit,
+                             ddeig_pcg_info* info) {
+  if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
+  if (validate_vec(b, "b") || validate_vec(x, "x")) return DDEIG_EINVAL;
+  if (b == x) return set_error(DDEIG_EINVAL, "b and x must not alias");
+  if (!(rtol >= 0.0) || !std::isfinite(rtol) || maxit < 0)
+    return set_error(DDEIG_EINVAL, "need rtol >= 0 and maxit >= 0");
+  if (!P->shifted) return set_error(DDEIG_ESTATE, "pcg_solve before the shift is set");
+  API_GUARD_BEGIN
+  const PcgOut o = pcg_run(P, b, x, rtol, maxit);
+  if (info) {
+    info->iters = o.iters;
+    info->relres = o.relres;
+    info->breakdown = o.done == 2 ? 1 : (o.done == 3 ? 2 : 0);
+    if (info->hist && info->hist_cap > 0) {
+      const int cnt = std::min(std::min(info->hist_cap, o.iters + 1), P->hist_cap);
+      check_hip(hipMemcpyAsync(info->hist, P->hist, sizeof(double) * cnt, hipMemcpyDeviceToHost,
+                               P->stream), "copy history");
+      sync(P);
+    }
+  }
+  if (o.done == 2 || o.done == 3)
+    return set_error(DDEIG_ENOTSPD, o.done == 2 ? "CG breakdown: p.A_sigma p <= 0"
+                                                : "CG breakdown: r.z <= 0");
+  if (o.done != 1) return set_error(DDEIG_ENOCONV, "PCG reached maxit");
+  return DDEIG_OK;
+  API_GUARD_END
+}
+
+ddeig_status ddeig_inverse_iteration(ddeig_problem* P, double* x, double tol_x, int maxit_outer,
+                                     double rtol_inner, int maxit_inner, ddeig_eig_info* info) {
+  if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
+  if (validate_vec(x, "x")) return DDEIG_EINVAL;
+  if (!(tol_x >= 0.0) || maxit_outer < 1 || !(rtol_inner >= 0.0) || maxit_inner < 1)
+    return set_error(DDEIG_EINVAL, "invalid tolerances or iteration limits");
+  if (!P->shifted) return set_error(DDEIG_ESTATE, "inverse_iteration before the shift is set");
+  API_GUARD_BEGIN
+  const hipStream_t s = P->stream;
+  const long n = P->g.n;
+  const auto t0 = std::chrono::steady_clock::now();
+  // start vector: x, or 1/||1||_M if x is all zeros
+  launch_dot(x, x, n, slot(P, 3), s);
+  if (host_sum(P, slot(P, 3)) == 0.0) {
+    launch_fill(P->u, n, 1.0, s);
+    launch_stencil(P, P->tabM, P->u, P->w, slot(P, 3), nullptr, s);
+    launch_scale_copy(n, x, P->u, slot(P, 3), s);
+  }
+  double lam = 0.0, dx = INFINITY;
+  long inner_sum = 0;
+  int inner_max = 0, k = 0;
+  ddeig_status st = DDEIG_ENOCONV;
+  for (k = 1; k <= maxit_outer; ++k) {
+    launch_stencil(P, P->tabM, x, P->w, nullptr, nullptr, s);  // b = M x
+    launch_fill(P->u, n, 0.0, s);
+    const PcgOut o = pcg_run(P, P->w, P->u, rtol_inner, maxit_inner);
+    if (o.done == 2 || o.done == 3) {
+      st = set_error(DDEIG_ENOTSPD, "CG breakdown inside inverse iteration");
+      break;
+    }
+    inner_sum += o.iters;
+    inner_max = std::max(inner_max, o.iters);
+    launch_stencil(P, P->tabM, P->u, P->z, slot(P, 4), slot(P, 5), s);  // Mu, u.Mu, sum(Mu)
+    launch_ipm_normalise(n, P->u, P->z, x, P->w, slot(P, 4), slot(P, 5), slot(P, 6), s);
+    launch_stencil(P, P->tabAs, x, P->q, slot(P, 7), nullptr, s);      // x.A_sigma x
+    launch_sum_partials(slot(P, 6), P->scal, s);
+    launch_sum_partials(slot(P, 7), P->scal + 1, s);
+    double hs[2];
+    check_hip(hipMemcpyAsync(hs, P->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s), "copy");
+    sync(P);
+    dx = std::sqrt(std::max(hs[0], 0.0));
+    lam = P->sigma + hs[1];
+    if (dx <= tol_x) {
+      st = DDEIG_OK;
+      break;
+    }
+  }
+  const auto t1 = std::chrono::steady_clock::now();
+  if (info) {
+    info->lambda = lam;
+    info->dx_M = dx;
+    info->outer_its = std::min(k, maxit_outer);
+    info->inner_sum = inner_sum;
+    info->inner_max = inner_max;
+    info->t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  }
+  if (st == DDEIG_ENOCONV) return set_error(st, "inverse iteration reached maxit_outer");
+  return st;
+  API_GUARD_END
+}
+
+}  // extern "C"

@@ -1,0 +1,191 @@
+// Internal structures of libddeig: geometry, period-cell operator tables,
+// subdomain boxes and the kernels' launch helpers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ddeig.h"
+
+namespace ddeig {
+
+constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
+constexpr int kRedBlocks = 512;    // fixed grid of every reducing kernel (deterministic sums)
+constexpr int kMaxTaps = 27;
+
+// Geometry of Omega_L on the internal 3-D index space (N0, N1, N2), dim 0 = x1.
+// p + q = D in {2, 3}; for D = 2 the third dim has N2 = 1.  The stencil of a
+// node couples the 3^D neighbours; a tap is t = (d0+1) + 3 (d1+1) + 9 (d2+1).
+struct Geo {
+  int p, q, D;
+  int L, ne;
+  int nel[3];     // elements per dim
+  int N[3];       // interior unknowns per dim
+  int P[3];       // period-cell table extent per dim: ne in x dims, N[a] in y dims
+  int isx[3];     // 1 for expanding (x) dims
+  int ntaps;      // 3^D
+  long n;         // N0 N1 N2
+  long tsize;     // P0 P1 P2 (table nodes == cell unknowns)
+  double h, ell;
+};
+
+// Potential description copied to the device (see ddeig_potential).
+struct VSpec {
+  int kind, nterms, p, q;
+  double cy, c0, ell;
+  double a[DDEIG_MAX_TERMS], phi[DDEIG_MAX_TERMS];
+  int k[DDEIG_MAX_TERMS], m[DDEIG_MAX_TERMS];
+  double g[3];
+};
+
+// A box of unknowns: origin o[a] (0-based interior unknown index of the first
+// node; the cell problem uses o = -1 in x dims so that node index == cell
+// index), extent m[a], periodic flag per dim (cell problem only).  Block
+// chains run along the last dim (a fixed y direction): slice size
+// b = prod_{a < D-1} m[a], chain length m[D-1].
+struct Box {
+  int o[3];
+  int m[3];
+  int per[3];
+  int b;      // slice size
+  int nch;    // chain length
+};
+
+// A class of subdomains sharing one local matrix (same cell-local offsets and extents).
+struct SubType {
+  Box box;                  // box of the first member (o of that member)
+  int nmem;
+  std::vector<int> members; // subdomain ids (x1-fastest cell numbering)
+  double* W = nullptr;      // nch * b * b FP64 Schur-complement inverses
+  float* W32 = nullptr;     // FP32 copy (local_prec = 1)
+  double* batch = nullptr;  // nmem * nch * b local vectors
+};
+
+// Per-subdomain data on the device.
+struct SubDev {
+  int o[3];     // box origin
+  int type;     // SubType index
+  int slot;     // member slot within the type
+  int c[3];     // 1-based cell multi-index (x dims), 0 for y dims
+};
+
+struct TypeDev {
+  int m[3];
+  int b, nch;
+  const double* W;
+  const float* W32;
+  double* batch;
+};
+
+// PCG device state (one per problem).
+struct PcgState {
+  int done;      // 0 running, 1 converged, 2 p.Ap <= 0, 3 r.z <= 0, 4 maxit
+  int iters;
+  double rho[2]; // r.z of iterations of even / odd parity
+  double r0n2;
+  double tol2;
+  double relres;
+};
+
+}  // namespace ddeig
+
+struct ddeig_problem {
+  ddeig::Geo g;
+  ddeig::VSpec vs;
+  int delta;
+  ddeig_options opt;
+  hipStream_t stream;
+  // operator tables, tap-major: tab[tap * tsize + tnode]
+  double* tabK = nullptr;
+  double* tabM = nullptr;
+  double* tabA = nullptr;   // K + M_V
+  double* tabAs = nullptr;  // A - sigma M
+  ddeig::VSpec* dVS = nullptr;
+  // shift
+  int shifted = 0;
+  double sigma = 0.0;
+  double* psi = nullptr;    // tsize cell vector
+  // decomposition
+  int nsub = 0;
+  std::vector<ddeig::SubType> types;
+  std::vector<ddeig::SubDev> subs;
+  ddeig::SubDev* dSubs = nullptr;
+  ddeig::TypeDev* dTypes = nullptr;
+  int maxb = 0;
+  // coarse space
+  double* A0inv = nullptr;  // nsub x nsub
+  double* crhs = nullptr;   // nsub
+  double* cy = nullptr;     // nsub
+  // work vectors (n each)
+  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *u = nullptr, *w = nullptr;
+  double* part = nullptr;   // partial sums: 4 slots of kRedBlocks
+  ddeig::PcgState* st = nullptr;
+  double* hist = nullptr;   // device residual history
+  int hist_cap = 0;
+  double* scal = nullptr;   // small device scalars
+  int* flag = nullptr;      // factorisation error flag
+  double* gjbuf = nullptr;  // Gauss-Jordan row/column buffers (4 x gj_stride)
+  int gj_stride = 0;
+  double* cellS = nullptr;  // scratch for Schur builds (maxb^2)
+  std::vector<void*> allocs;
+};
+
+namespace ddeig {
+
+// ---- kernels' host launchers (k_*.hip) ------------------------------------
+void launch_build_tables(const ddeig_problem* P, hipStream_t s);
+void launch_shift_table(const ddeig_problem* P, hipStream_t s);
+// y = T x (T one of the tables); dot != nullptr: partial sums of x.y into dot[0..kRedBlocks)
+void launch_stencil(const ddeig_problem* P, const double* tab, const double* x, double* y,
+                    double* dot, double* sum, hipStream_t s);
+// box operator (cell problem): y = T x on a periodic box, partials of x.y and sum(y)
+void launch_box_stencil(const ddeig_problem* P, const Box& bx, const double* tab, const double* x,
+                        double* y, double* dot, double* sum, hipStream_t s);
+
+// chain factorisation of a box: W[i] = S_i^{-1}; flag set on a non-positive pivot
+void chain_factor(ddeig_problem* P, const Box& bx, const double* tab, double* W, hipStream_t s);
+void launch_gj_invert(ddeig_problem* P, double* A, int b, hipStream_t s);
+// chain solve in place on nrhs right-hand sides stored contiguously (nch*b each)
+void launch_chain_solve_box(const ddeig_problem* P, const Box& bx, const double* tab,
+                            const double* W, double* v, int nrhs, hipStream_t s);
+
+// preconditioner pieces
+void launch_restrict(const ddeig_problem* P, const double* r, int coarse, const PcgState* st,
+                     hipStream_t s);
+void launch_local_solves(const ddeig_problem* P, const PcgState* st, hipStream_t s);
+void launch_coarse_solve(const ddeig_problem* P, const PcgState* st, hipStream_t s);
+void launch_extend(const ddeig_problem* P, const double* r, double* z, int coarse, double* dot,
+                   const PcgState* st, hipStream_t s);
+void launch_symmetrise(double* A, int N, hipStream_t s);
+void launch_to_float(const double* src, float* dst, long n, hipStream_t s);
+void build_coarse_matrix(ddeig_problem* P, double* A0, hipStream_t s);
+
+// PCG / IPM vector kernels
+void launch_resid_init(const ddeig_problem* P, const double* b, const double* q, double* r,
+                       double* part, hipStream_t s);
+void launch_pcg_init(const ddeig_problem* P, double rtol, const double* part, hipStream_t s);
+void launch_pcg_start(const ddeig_problem* P, const double* z, double* p, const double* part,
+                      hipStream_t s);
+void launch_pcg_update_xr(const ddeig_problem* P, double* x, const double* pvec,
+                          const double* qvec, double* r, const double* part_g, double* part_r,
+                          int k, hipStream_t s);
+void launch_pcg_check(const ddeig_problem* P, const double* part_r, int k, int maxit,
+                      hipStream_t s);
+void launch_pcg_update_p(const ddeig_problem* P, const double* z, double* pvec,
+                         const double* part_rz, int k, hipStream_t s);
+void launch_fill(double* x, long n, double v, hipStream_t s);
+void launch_copy(double* dst, const double* src, long n, hipStream_t s);
+void launch_scale_copy(long n, double* dst, const double* src, const double* part,
+                       hipStream_t s);
+void launch_ipm_normalise(long n, const double* u, const double* Mu, double* x, const double* b,
+                          const double* part_uMu, const double* part_sum, double* part_dx,
+                          hipStream_t s);
+void launch_sum_partials(const double* part, double* out, hipStream_t s);
+void launch_dot(const double* x, const double* y, long n, double* part, hipStream_t s);
+
+void check_hip(hipError_t e, const char* what);
+
+}  // namespace ddeig

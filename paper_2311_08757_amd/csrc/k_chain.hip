@@ -1,0 +1,276 @@
+// Block-tridiagonal ("chain") factorisation and solves of box operators.
+//
+// The local matrices A_sigma,i = R_i A_sigma R_i^T of §3
+// (eq:twoLevelASMPreconditioner) and the cell operator of
+// eq:weak-form-cell-problem are the stencil operator restricted to a box of
+// unknowns.  Ordered slice by slice along the last (fixed, Dirichlet) grid
+// direction they are block tridiagonal: diagonal blocks D_i (couplings inside
+// slice i, with the periodic wrap of the cell problem inside the slice) and
+// sub-diagonal blocks E_i (slice i to slice i-1).  Block elimination gives
+//   S_0 = D_0,  S_i = D_i - E_i S_{i-1}^{-1} E_i^T,  W_i = S_i^{-1},
+// and a solve is
+//   forward   t_i = W_i (b_i - E_i t_{i-1}),
+//   backward  x_{n-1} = t_{n-1},  x_i = t_i - W_i E_{i+1}^T x_{i+1}.
+// E_i and D_i are never stored: they are read from the period-cell table.
+// W_i is stored dense (b x b); since it is symmetric, W_i[s][r] is read with
+// r running over the threads, which coalesces.
+#include "k_common.h"
+
+namespace ddeig {
+
+// In-slice neighbour of box-local u (slice coordinates a < D-1) along tap d.
+__device__ inline bool slice_nbr(const Box& bx, int D, const int* u, const int* d, int& rn) {
+  int idx = 0, stride = 1;
+  for (int a = 0; a < D - 1; ++a) {
+    int w = u[a] + d[a];
+    if (bx.per[a]) w = (w + bx.m[a]) % bx.m[a];
+    else if (w < 0 || w >= bx.m[a]) return false;
+    idx += w * stride;
+    stride *= bx.m[a];
+  }
+  rn = idx;
+  return true;
+}
+
+__device__ inline void slice_coords(const Box& bx, int D, int r, int* u) {
+  u[0] = 0; u[1] = 0; u[2] = 0;
+  for (int a = 0; a < D - 1; ++a) {
+    u[a] = r % bx.m[a];
+    r /= bx.m[a];
+  }
+}
+
+__device__ inline long box_tnode(const Geo& g, const Box& bx, const int* u) {
+  return table_node(g, bx.o[0] + u[0], bx.o[1] + u[1], bx.o[2] + u[2]);
+}
+
+// S = D_i - E_i Wprev E_i^T for slice i (Wprev = nullptr for i = 0), row-major b x b.
+__global__ void k_schur_build(Geo g, Box bx, int i, const double* __restrict__ T,
+                              const double* __restrict__ Wprev, double* __restrict__ S) {
+  const int b = bx.b, D = g.D, last = D - 1;
+  const long bb = (long)b * b;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < bb;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(idx / b), s = (int)(idx % b);
+    int ur[3], us[3];
+    slice_coords(bx, D, r, ur);
+    slice_coords(bx, D, s, us);
+    ur[last] = i;
+    us[last] = i;
+    const long tr = box_tnode(g, bx, ur);
+    double v = 0.0;
+    for (int t = 0; t < g.ntaps; ++t) {
+      int d[3];
+      tap_offsets(t, g.ntaps, d[0], d[1], d[2]);
+      if (d[last] != 0) continue;
+      int rn;
+      if (slice_nbr(bx, D, ur, d, rn) && rn == s) v += T[t * g.tsize + tr];
+    }
+    if (Wprev != nullptr) {
+      const long ts = box_tnode(g, bx, us);
+      double corr = 0.0;
+      for (int t1 = 0; t1 < g.ntaps; ++t1) {
+        int d1[3];
+        tap_offsets(t1, g.ntaps, d1[0], d1[1], d1[2]);
+        if (d1[last] != -1) continue;
+        int n1;
+        if (!slice_nbr(bx, D, ur, d1, n1)) continue;
+        const double e1 = T[t1 * g.tsize + tr];
+        double inner = 0.0;
+        for (int t2 = 0; t2 < g.ntaps; ++t2) {
+          int d2[3];
+          tap_offsets(t2, g.ntaps, d2[0], d2[1], d2[2]);
+          if (d2[last] != -1) continue;
+          int n2;
+          if (!slice_nbr(bx, D, us, d2, n2)) continue;
+          inner += T[t2 * g.tsize + ts] * Wprev[(long)n1 * b + n2];
+        }
+        corr += e1 * inner;
+      }
+      v -= corr;
+    }
+    S[idx] = v;
+  }
+}
+
+// Gauss-Jordan inversion in place, one launch per pivot.  rowk/colk hold row
+// and column k of the matrix before step k; the launch also records row and
+// column k+1 after step k into rown/coln for the next pivot.
+__global__ void k_gj_step(double* __restrict__ A, int b, int k, const double* __restrict__ rowk,
+                          const double* __restrict__ colk, double* __restrict__ rown,
+                          double* __restrict__ coln, int* __restrict__ flag) {
+  const double piv = rowk[k];
+  if (!(piv > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
+    return;
+  }
+  const double ipiv = 1.0 / piv;
+  const long bb = (long)b * b;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < bb;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / b), j = (int)(idx % b);
+    double v;
+    if (i == k) {
+      v = (j == k) ? ipiv : rowk[j] * ipiv;
+    } else {
+      const double f = colk[i];
+      v = (j == k) ? -f * ipiv : A[idx] - f * (rowk[j] * ipiv);
+    }
+    A[idx] = v;
+    if (i == k + 1) rown[j] = v;
+    if (j == k + 1) coln[i] = v;
+  }
+}
+
+__global__ void k_gj_init(const double* __restrict__ A, int b, double* __restrict__ row0,
+                          double* __restrict__ col0) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < b; j += gridDim.x * blockDim.x) {
+    row0[j] = A[j];
+    col0[j] = A[(long)j * b];
+  }
+}
+
+void launch_gj_invert(ddeig_problem* P, double* A, int b, hipStream_t s) {
+  const long st = P->gj_stride;
+  double* bufs[2][2] = {{P->gjbuf, P->gjbuf + st}, {P->gjbuf + 2 * st, P->gjbuf + 3 * st}};
+  hipLaunchKernelGGL(k_gj_init, dim3((b + kBlock - 1) / kBlock), dim3(kBlock), 0, s, A, b,
+                     bufs[0][0], bufs[0][1]);
+  const long bb = (long)b * b;
+  const int blocks = (int)std::min<long>((bb + kBlock - 1) / kBlock, 4096);
+  for (int k = 0; k < b; ++k) {
+    double** cur = bufs[k & 1];
+    double** nxt = bufs[(k + 1) & 1];
+    hipLaunchKernelGGL(k_gj_step, dim3(blocks), dim3(kBlock), 0, s, A, b, k, cur[0], cur[1],
+                       nxt[0], nxt[1], P->flag);
+  }
+}
+
+void chain_factor(ddeig_problem* P, const Box& bx, const double* tab, double* W, hipStream_t s) {
+  const long bb = (long)bx.b * bx.b;
+  const int blocks = (int)std::min<long>((bb + kBlock - 1) / kBlock, 4096);
+  for (int i = 0; i < bx.nch; ++i) {
+    double* Wi = W + (long)i * bb;
+    const double* Wp = i > 0 ? W + (long)(i - 1) * bb : nullptr;
+    hipLaunchKernelGGL(k_schur_build, dim3(blocks), dim3(kBlock), 0, s, P->g, bx, i, tab, Wp, Wi);
+    launch_gj_invert(P, Wi, bx.b, s);
+  }
+}
+
+// One workgroup solves one right-hand side v (nch * b values, slice-major,
+// overwritten by the solution).  sh holds 2 b doubles of LDS.
+template <typename WT>
+__device__ void chain_solve_block(const Geo& g, const Box& bx, const double* __restrict__ T,
+                                  const WT* __restrict__ W, double* __restrict__ v, double* sh) {
+  const int b = bx.b, nch = bx.nch, D = g.D, last = D - 1;
+  double* gb = sh;
+  double* tb = sh + b;
+  const long bb = (long)b * b;
+  // forward sweep
+  for (int i = 0; i < nch; ++i) {
+    for (int r = threadIdx.x; r < b; r += blockDim.x) {
+      double val = v[(long)i * b + r];
+      if (i > 0) {
+        int u[3];
+        slice_coords(bx, D, r, u);
+        u[last] = i;
+        const long tn = box_tnode(g, bx, u);
+        for (int t = 0; t < g.ntaps; ++t) {
+          int d[3];
+          tap_offsets(t, g.ntaps, d[0], d[1], d[2]);
+          if (d[last] != -1) continue;
+          int rn;
+          if (slice_nbr(bx, D, u, d, rn)) val -= T[t * g.tsize + tn] * tb[rn];
+        }
+      }
+      gb[r] = val;
+    }
+    __syncthreads();
+    const WT* Wi = W + (long)i * bb;
+    for (int r = threadIdx.x; r < b; r += blockDim.x) {
+      double acc = 0.0;
+      for (int s2 = 0; s2 < b; ++s2) acc += (double)Wi[(long)s2 * b + r] * gb[s2];
+      v[(long)i * b + r] = acc;
+      tb[r] = acc;
+    }
+    __syncthreads();
+  }
+  // backward sweep; tb holds x_{i+1}
+  for (int i = nch - 2; i >= 0; --i) {
+    for (int r = threadIdx.x; r < b; r += blockDim.x) {
+      int u[3];
+      slice_coords(bx, D, r, u);
+      u[last] = i;
+      const long tn = box_tnode(g, bx, u);
+      double val = 0.0;
+      for (int t = 0; t < g.ntaps; ++t) {
+        int d[3];
+        tap_offsets(t, g.ntaps, d[0], d[1], d[2]);
+        if (d[last] != 1) continue;
+        int rn;
+        if (slice_nbr(bx, D, u, d, rn)) val += T[t * g.tsize + tn] * tb[rn];
+      }
+      gb[r] = val;
+    }
+    __syncthreads();
+    const WT* Wi = W + (long)i * bb;
+    for (int r = threadIdx.x; r < b; r += blockDim.x) {
+      double acc = 0.0;
+      for (int s2 = 0; s2 < b; ++s2) acc += (double)Wi[(long)s2 * b + r] * gb[s2];
+      const double x = v[(long)i * b + r] - acc;
+      v[(long)i * b + r] = x;
+      tb[r] = x;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_chain_solve_box(Geo g, Box bx,
+                                                            const double* __restrict__ T,
+                                                            const double* __restrict__ W,
+                                                            double* __restrict__ v) {
+  extern __shared__ double sh[];
+  chain_solve_block<double>(g, bx, T, W, v + (long)blockIdx.x * bx.nch * bx.b, sh);
+}
+
+void launch_chain_solve_box(const ddeig_problem* P, const Box& bx, const double* tab,
+                            const double* W, double* v, int nrhs, hipStream_t s) {
+  const size_t lds = 2 * (size_t)bx.b * sizeof(double);
+  hipLaunchKernelGGL(k_chain_solve_box, dim3(nrhs), dim3(kBlock), lds, s, P->g, bx, tab, W, v);
+}
+
+// All local subdomain solves of the level-1 preconditioner in one launch:
+// workgroup = subdomain, solved with its class's shared factor.
+template <typename WT>
+__global__ void __launch_bounds__(kBlock) k_local_solves(Geo g, const double* __restrict__ T,
+                                                         const TypeDev* __restrict__ types,
+                                                         const SubDev* __restrict__ subs,
+                                                         const PcgState* __restrict__ st) {
+  extern __shared__ double sh[];
+  if (st != nullptr && st->done) return;
+  const SubDev sd = subs[blockIdx.x];
+  const TypeDev td = types[sd.type];
+  Box bx;
+  for (int a = 0; a < 3; ++a) {
+    bx.o[a] = sd.o[a];
+    bx.m[a] = td.m[a];
+    bx.per[a] = 0;
+  }
+  bx.b = td.b;
+  bx.nch = td.nch;
+  const WT* W;
+  if constexpr (sizeof(WT) == 4) W = reinterpret_cast<const WT*>(td.W32);
+  else W = reinterpret_cast<const WT*>(td.W);
+  chain_solve_block<WT>(g, bx, T, W, td.batch + (long)sd.slot * td.nch * td.b, sh);
+}
+
+void launch_local_solves(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
+  const size_t lds = 2 * (size_t)P->maxb * sizeof(double);
+  if (P->opt.local_prec == 1)
+    hipLaunchKernelGGL(k_local_solves<float>, dim3(P->nsub), dim3(kBlock), lds, s, P->g,
+                       P->tabAs, P->dTypes, P->dSubs, st);
+  else
+    hipLaunchKernelGGL(k_local_solves<double>, dim3(P->nsub), dim3(kBlock), lds, s, P->g,
+                       P->tabAs, P->dTypes, P->dSubs, st);
+}
+
+}  // namespace ddeig

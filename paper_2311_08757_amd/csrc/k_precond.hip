@@ -1,0 +1,257 @@
+// Restriction, extension and coarse space of the two-level additive Schwarz
+// preconditioner (§2.2 eq:dd-preconditioners, eq:two-level-preconditioners,
+// §2.3 def:algebraic-perfact-coarse-space, §3 eq:twoLevelASMPreconditioner).
+//
+// Subdomains are the L^p unit cells extended by delta element layers in every
+// expanding direction (§3, §4.1): along an expanding axis, cell c (1-based)
+// owns the node indices [(c-1) n_e - delta + 1, c n_e + delta - 1] clipped to
+// [1, L n_e - 1]; fixed directions are not split.  With 2 delta <= n_e a node
+// lies in at most two cells per axis.  The extension sums, for every node, the
+// local solutions of the subdomains covering it in a fixed order (no atomics).
+#include "k_common.h"
+
+namespace ddeig {
+
+// 1-based cells covering node index gi (1-based) along one expanding axis.
+__device__ inline void covering(int gi, int ne, int L, int delta, int& clo, int& chi) {
+  // g <= c ne + delta - 1  <=>  c >= (g - delta + 1) / ne
+  const int num = gi - delta + 1;
+  clo = num <= 0 ? 1 : (num + ne - 1) / ne;
+  chi = (gi + delta - 1) / ne + 1;
+  if (clo < 1) clo = 1;
+  if (chi > L) chi = L;
+}
+
+// Distance from node coordinate (index gi, in units of h) to the faces of
+// cell c's box along one axis that are not on the global boundary; INT_MAX if none.
+__device__ inline int face_dist(int gi, int c, int ne, int L, int delta) {
+  int dmin = 0x7fffffff;
+  if (c > 1) {
+    const int lo = (c - 1) * ne - delta;  // face at ((c-1) n_e - delta) h
+    dmin = min(dmin, gi - lo);
+  }
+  if (c < L) {
+    const int hi = c * ne + delta;
+    dmin = min(dmin, hi - gi);
+  }
+  return dmin;
+}
+
+// Partition-of-unity weight of subdomain with cell index c at the node with
+// 0-based unknown indices i.  pu = 0: 1 / #covering subdomains (§2.2);
+// pu = 1: distance-based d_c / sum_c' d_c' (§4.1.2) with the distance to the
+// interior faces of the box (the minimum over axes of perpendicular distances).
+__device__ inline double pu_weight(const Geo& g, int delta, int pu, const int* c, const int* i) {
+  if (pu == 0) {
+    double w = 1.0;
+    for (int a = 0; a < g.p; ++a) {
+      int clo, chi;
+      covering(i[a] + 1, g.ne, g.L, delta, clo, chi);
+      w /= (double)(chi - clo + 1);
+    }
+    return w;
+  }
+  int lo[2] = {1, 1}, hi[2] = {1, 1};
+  for (int a = 0; a < g.p; ++a) covering(i[a] + 1, g.ne, g.L, delta, lo[a], hi[a]);
+  auto dist = [&](const int* cc) {
+    int dm = 0x7fffffff;
+    for (int a = 0; a < g.p; ++a) dm = min(dm, face_dist(i[a] + 1, cc[a], g.ne, g.L, delta));
+    return dm;
+  };
+  const int dc = dist(c);
+  if (dc == 0x7fffffff) return 1.0;  // a single subdomain: no interior faces
+  double tot = 0.0;
+  for (int c1 = lo[1]; c1 <= hi[1]; ++c1)
+    for (int c0 = lo[0]; c0 <= hi[0]; ++c0) {
+      const int cc[2] = {c0, c1};
+      tot += (double)dist(cc);
+    }
+  return (double)dc / tot;
+}
+
+__device__ inline int sub_index(const Geo& g, const int* c) {
+  return g.p == 1 ? c[0] - 1 : (c[0] - 1) + g.L * (c[1] - 1);
+}
+
+// Gather r into the subdomain batches (box natural order) and, with the
+// coarse level, c_sub = sum_k D_sub(k) psi_ext(k) r(k)  (R_0 r).
+__global__ void __launch_bounds__(kBlock) k_restrict(Geo g, int delta, int pu, int coarse,
+                                                     const PcgState* __restrict__ st,
+                                                     const double* __restrict__ r,
+                                                     const TypeDev* __restrict__ types,
+                                                     const SubDev* __restrict__ subs,
+                                                     const double* __restrict__ psi,
+                                                     double* __restrict__ crhs) {
+  if (st != nullptr && st->done) return;
+  const SubDev sd = subs[blockIdx.x];
+  const TypeDev td = types[sd.type];
+  const long mtot = (long)td.m[0] * td.m[1] * td.m[2];
+  double* dst = td.batch + (long)sd.slot * mtot;
+  double acc = 0.0;
+  for (long e = threadIdx.x; e < mtot; e += blockDim.x) {
+    const int u0 = (int)(e % td.m[0]);
+    const int u1 = (int)((e / td.m[0]) % td.m[1]);
+    const int u2 = (int)(e / ((long)td.m[0] * td.m[1]));
+    const int i[3] = {sd.o[0] + u0, sd.o[1] + u1, sd.o[2] + u2};
+    const long k = i[0] + (long)g.N[0] * (i[1] + (long)g.N[1] * i[2]);
+    const double rv = r[k];
+    dst[e] = rv;
+    if (coarse) acc += pu_weight(g, delta, pu, sd.c, i) * psi[table_node(g, i[0], i[1], i[2])] * rv;
+  }
+  if (coarse) {
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) crhs[blockIdx.x] = s;
+  }
+}
+
+void launch_restrict(const ddeig_problem* P, const double* r, int coarse, const PcgState* st,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_restrict, dim3(P->nsub), dim3(kBlock), 0, s, P->g, P->delta, P->opt.pu,
+                     coarse, st, r, P->dTypes, P->dSubs, P->psi, P->crhs);
+}
+
+// y0 = A0^{-1} c with the dense symmetric inverse (read column-wise).
+__global__ void k_coarse_solve(int N, const PcgState* __restrict__ st,
+                               const double* __restrict__ A0inv, const double* __restrict__ c,
+                               double* __restrict__ y) {
+  if (st != nullptr && st->done) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int j = 0; j < N; ++j) acc += A0inv[(long)j * N + i] * c[j];
+    y[i] = acc;
+  }
+}
+
+void launch_coarse_solve(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_solve, dim3((P->nsub + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                     P->nsub, st, P->A0inv, P->crhs, P->cy);
+}
+
+// z = sum_c R_c^T y_c (+ R_0^T y0), partials of r.z.
+__global__ void __launch_bounds__(kBlock) k_extend(Geo g, int delta, int pu, int coarse,
+                                                   const PcgState* __restrict__ st,
+                                                   const TypeDev* __restrict__ types,
+                                                   const SubDev* __restrict__ subs,
+                                                   const double* __restrict__ psi,
+                                                   const double* __restrict__ y0,
+                                                   const double* __restrict__ r,
+                                                   double* __restrict__ z,
+                                                   double* __restrict__ dot) {
+  if (st != nullptr && st->done) return;
+  double acc = 0.0;
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < g.n;
+       k += (long)gridDim.x * blockDim.x) {
+    int i[3];
+    unflatten(g, k, i[0], i[1], i[2]);
+    int lo[2] = {1, 1}, hi[2] = {1, 1};
+    for (int a = 0; a < g.p; ++a) covering(i[a] + 1, g.ne, g.L, delta, lo[a], hi[a]);
+    double zl = 0.0, zc = 0.0;
+    for (int c1 = lo[1]; c1 <= hi[1]; ++c1)
+      for (int c0 = lo[0]; c0 <= hi[0]; ++c0) {
+        const int c[3] = {c0, c1, 0};
+        const int sid = sub_index(g, c);
+        const SubDev sd = subs[sid];
+        const TypeDev td = types[sd.type];
+        const long e = (i[0] - sd.o[0]) +
+                       (long)td.m[0] * ((i[1] - sd.o[1]) + (long)td.m[1] * (i[2] - sd.o[2]));
+        zl += td.batch[(long)sd.slot * td.m[0] * td.m[1] * td.m[2] + e];
+        if (coarse) zc += pu_weight(g, delta, pu, c, i) * y0[sid];
+      }
+    double zv = zl;
+    if (coarse) zv += psi[table_node(g, i[0], i[1], i[2])] * zc;
+    z[k] = zv;
+    acc += r[k] * zv;
+  }
+  if (dot) {
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) dot[blockIdx.x] = s;
+  }
+}
+
+void launch_extend(const ddeig_problem* P, const double* r, double* z, int coarse, double* dot,
+                   const PcgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_extend, dim3(kRedBlocks), dim3(kBlock), 0, s, P->g, P->delta, P->opt.pu,
+                     coarse, st, P->dTypes, P->dSubs, P->psi, P->cy, r, z, dot);
+}
+
+// phi_c(k) = D_c(k) psi_ext(k) on box c, 0 elsewhere (column c of R_0^T).
+__device__ inline double coarse_phi(const Geo& g, int delta, int pu, const SubDev& sd,
+                                    const TypeDev& td, const double* psi, const int* i) {
+  for (int a = 0; a < g.D; ++a)
+    if (i[a] < sd.o[a] || i[a] >= sd.o[a] + td.m[a]) return 0.0;
+  return pu_weight(g, delta, pu, sd.c, i) * psi[table_node(g, i[0], i[1], i[2])];
+}
+
+// A0[c][d] = phi_d^T A_sigma phi_c for neighbouring cells (one workgroup per pair).
+__global__ void __launch_bounds__(kBlock) k_coarse_matrix(Geo g, int delta, int pu,
+                                                          const double* __restrict__ T,
+                                                          const TypeDev* __restrict__ types,
+                                                          const SubDev* __restrict__ subs,
+                                                          const double* __restrict__ psi,
+                                                          double* __restrict__ A0) {
+  const int N = gridDim.x;
+  const int cid = blockIdx.x;
+  const int nb = blockIdx.y;  // neighbour offset in {-1,0,1}^p
+  const SubDev sc = subs[cid];
+  int dc[2] = {nb % 3 - 1, nb / 3 - 1};
+  int cd[3] = {sc.c[0] + dc[0], g.p == 2 ? sc.c[1] + dc[1] : 0, 0};
+  if (g.p == 1 && dc[1] != -1) return;  // only nb in {0,1,2} for p = 1
+  for (int a = 0; a < g.p; ++a)
+    if (cd[a] < 1 || cd[a] > g.L) return;
+  const int did = sub_index(g, cd);
+  const SubDev sdd = subs[did];
+  const TypeDev tc = types[sc.type];
+  const TypeDev tdd = types[sdd.type];
+  const long mtot = (long)tdd.m[0] * tdd.m[1] * tdd.m[2];
+  double acc = 0.0;
+  for (long e = threadIdx.x; e < mtot; e += blockDim.x) {
+    const int i[3] = {sdd.o[0] + (int)(e % tdd.m[0]), sdd.o[1] + (int)((e / tdd.m[0]) % tdd.m[1]),
+                      sdd.o[2] + (int)(e / ((long)tdd.m[0] * tdd.m[1]))};
+    const double phid = coarse_phi(g, delta, pu, sdd, tdd, psi, i);
+    const long tn = table_node(g, i[0], i[1], i[2]);
+    double aphi = 0.0;
+    for (int t = 0; t < g.ntaps; ++t) {
+      int d[3];
+      tap_offsets(t, g.ntaps, d[0], d[1], d[2]);
+      const int j[3] = {i[0] + d[0], i[1] + d[1], g.D == 3 ? i[2] + d[2] : 0};
+      bool in = true;
+      for (int a = 0; a < g.D; ++a) in = in && j[a] >= 0 && j[a] < g.N[a];
+      if (!in) continue;
+      aphi += T[t * g.tsize + tn] * coarse_phi(g, delta, pu, sc, tc, psi, j);
+    }
+    acc += phid * aphi;
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) A0[(long)cid * N + did] = s;
+}
+
+__global__ void k_symmetrise(double* A, int N) {
+  const long nn = (long)N * N;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < nn;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / N), j = (int)(idx % N);
+    if (j > i) {
+      const double v = 0.5 * (A[idx] + A[(long)j * N + i]);
+      A[idx] = v;
+      A[(long)j * N + i] = v;
+    }
+  }
+}
+
+void launch_symmetrise(double* A, int N, hipStream_t s) {
+  const long nn = (long)N * N;
+  const int blocks = (int)std::min<long>((nn + kBlock - 1) / kBlock, 4096);
+  hipLaunchKernelGGL(k_symmetrise, dim3(blocks), dim3(kBlock), 0, s, A, N);
+}
+
+void build_coarse_matrix(ddeig_problem* P, double* A0, hipStream_t s) {
+  const int N = P->nsub;
+  check_hip(hipMemsetAsync(A0, 0, sizeof(double) * (size_t)N * N, s), "memset A0");
+  const int nnb = P->g.p == 1 ? 3 : 9;
+  // for p = 1 the neighbour offsets are encoded as nb = 0,1,2 with dc[1] = -1
+  hipLaunchKernelGGL(k_coarse_matrix, dim3(N, nnb), dim3(kBlock), 0, s, P->g, P->delta,
+                     P->opt.pu, P->tabAs, P->dTypes, P->dSubs, P->psi, A0);
+  launch_symmetrise(A0, N, s);
+}
+
+}  // namespace ddeig

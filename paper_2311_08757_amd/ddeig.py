@@ -1,0 +1,282 @@
+"""Thin ctypes binding of libddeig (include/ddeig.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+Vectors are torch float64 tensors on the GPU (contiguous); the library works
+on the torch stream that is current when ``assemble`` is called.  There is no
+CPU fallback: a missing library raises at import of the first call.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libddeig.so")
+
+DDEIG_OK = 0
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTSPD", -5: "ENOCONV",
+          -6: "ESTATE", -7: "EINTERNAL"}
+V_KINDS = {"const": 0, "sep_fourier": 1, "fourier2": 2, "sin4": 3, "sep_sum": 4}
+OPS = {"A_sigma": 0, "A": 1, "M": 2, "K": 3}
+MAX_TERMS = 64
+
+
+class DdeigError(RuntimeError):
+    def __init__(self, status, func, msg):
+        self.status = status
+        self.code = STATUS.get(status, str(status))
+        super().__init__(f"{func}: {self.code}: {msg}")
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int), ("q", ctypes.c_int), ("L", ctypes.c_int),
+                ("ell", ctypes.c_double)]
+
+
+class Potential(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("nterms", ctypes.c_int),
+                ("a", ctypes.POINTER(ctypes.c_double)), ("phi", ctypes.POINTER(ctypes.c_double)),
+                ("k", ctypes.POINTER(ctypes.c_int)), ("m", ctypes.POINTER(ctypes.c_int)),
+                ("cy", ctypes.c_double), ("c0", ctypes.c_double),
+                ("g", ctypes.POINTER(ctypes.c_double))]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("pu", ctypes.c_int), ("coarse", ctypes.c_int), ("local_prec", ctypes.c_int),
+                ("batch_iters", ctypes.c_int)]
+
+
+class PcgInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("relres", ctypes.c_double), ("breakdown", ctypes.c_int),
+                ("hist", ctypes.POINTER(ctypes.c_double)), ("hist_cap", ctypes.c_int)]
+
+
+class EigInfo(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("dx_M", ctypes.c_double),
+                ("outer_its", ctypes.c_int), ("inner_sum", ctypes.c_long),
+                ("inner_max", ctypes.c_int), ("t_solve_ms", ctypes.c_double)]
+
+
+EXPORTS = ["ddeig_assemble", "ddeig_cell_shift", "ddeig_set_shift", "ddeig_apply_op",
+           "ddeig_apply_precond", "ddeig_pcg_solve", "ddeig_inverse_iteration", "ddeig_query",
+           "ddeig_destroy", "ddeig_status_string", "ddeig_last_error"]
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Loads libddeig.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2311_08757_amd.build_lib.build()")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.ddeig_assemble.argtypes = [ctypes.POINTER(Geometry), ctypes.c_double,
+                                   ctypes.POINTER(Potential), ctypes.c_int,
+                                   ctypes.POINTER(Options), P, ctypes.POINTER(P)]
+    lib.ddeig_cell_shift.argtypes = [P, dp, dp]
+    lib.ddeig_set_shift.argtypes = [P, ctypes.c_double, dp]
+    lib.ddeig_apply_op.argtypes = [P, ctypes.c_int, P, P]
+    lib.ddeig_apply_precond.argtypes = [P, P, P]
+    lib.ddeig_pcg_solve.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int,
+                                    ctypes.POINTER(PcgInfo)]
+    lib.ddeig_inverse_iteration.argtypes = [P, P, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                            ctypes.c_int, ctypes.POINTER(EigInfo)]
+    lib.ddeig_query.argtypes = [P, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long),
+                                ctypes.POINTER(ctypes.c_int)]
+    lib.ddeig_destroy.argtypes = [P]
+    lib.ddeig_destroy.restype = None
+    lib.ddeig_status_string.argtypes = [ctypes.c_int]
+    lib.ddeig_status_string.restype = ctypes.c_char_p
+    lib.ddeig_last_error.argtypes = []
+    lib.ddeig_last_error.restype = ctypes.c_char_p
+    for f in EXPORTS:
+        if f not in ("ddeig_destroy", "ddeig_status_string", "ddeig_last_error"):
+            getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status, func):
+    if status != DDEIG_OK:
+        msg = load_library().ddeig_last_error().decode()
+        raise DdeigError(status, func, msg)
+
+
+def _ptr(t, n=None, name="vector"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a CUDA float64 tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """Owns a ddeig_problem handle (destroyed with the object)."""
+
+    def __init__(self, handle, n_dof, n_cell, n_sub, stream):
+        self.handle = handle
+        self.n_dof, self.n_cell, self.n_sub = n_dof, n_cell, n_sub
+        self.stream = stream
+        self.sigma = None
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            load_library().ddeig_destroy(self.handle)
+            self.handle = None
+
+
+def _potential(spec):
+    kind = spec["kind"]
+    keep = []
+
+    def darr(x):
+        a = (ctypes.c_double * max(len(x), 1))(*[float(v) for v in x])
+        keep.append(a)
+        return ctypes.cast(a, ctypes.POINTER(ctypes.c_double))
+
+    def iarr(x):
+        a = (ctypes.c_int * max(len(x), 1))(*[int(v) for v in x])
+        keep.append(a)
+        return ctypes.cast(a, ctypes.POINTER(ctypes.c_int))
+
+    V = Potential()
+    V.kind = V_KINDS[kind]
+    V.nterms = 0
+    V.cy = 0.0
+    V.c0 = 0.0
+    if kind == "const":
+        V.c0 = float(spec["c"])
+    elif kind == "sep_fourier":
+        V.nterms = len(spec["a"])
+        V.a, V.phi, V.k = darr(spec["a"]), darr(spec["phi"]), iarr(spec["k"])
+        V.cy = float(spec["cy"])
+    elif kind == "fourier2":
+        V.nterms = len(spec["a"])
+        V.a, V.phi = darr(spec["a"]), darr(spec["phi"])
+        V.k, V.m = iarr(spec["k"]), iarr(spec["m"])
+    elif kind == "sin4":
+        V.c0 = float(spec["amp"])
+    elif kind == "sep_sum":
+        terms = spec["terms"]
+        V.nterms = len(terms)
+        V.a = darr([t[0] for t in terms])
+        V.m = iarr([t[1] for t in terms])
+        V.k = iarr([t[2] for t in terms])
+        V.c0 = float(spec["c0"])
+        V.g = darr(spec.get("g", []))
+    else:
+        raise ValueError(kind)
+    return V, keep
+
+
+def assemble(p, q, L, ne, V, delta, ell=1, pu="equal", coarse=True, local_prec="fp64",
+             batch_iters=8, stream=None):
+    """ddeig_assemble: geometry (0,L)^p x (0,ell)^q, h = 1/ne, potential dict V."""
+    import torch
+    lib = load_library()
+    geom = Geometry(p, q, L, float(ell))
+    Vs, keep = _potential(V)
+    opts = Options({"equal": 0, "distance": 1}[pu], 1 if coarse else 0,
+                   {"fp64": 0, "fp32": 1}[local_prec], batch_iters)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    handle = ctypes.c_void_p()
+    st = lib.ddeig_assemble(ctypes.byref(geom), 1.0 / ne, ctypes.byref(Vs), delta,
+                            ctypes.byref(opts), ctypes.c_void_p(stream.cuda_stream),
+                            ctypes.byref(handle))
+    del keep
+    _check(st, "ddeig_assemble")
+    n_dof, n_cell, n_sub = query_handle(handle)
+    return Problem(handle, n_dof, n_cell, n_sub, stream)
+
+
+def query_handle(handle):
+    lib = load_library()
+    nd, nc, ns = ctypes.c_long(), ctypes.c_long(), ctypes.c_int()
+    _check(lib.ddeig_query(handle, ctypes.byref(nd), ctypes.byref(nc), ctypes.byref(ns)),
+           "ddeig_query")
+    return nd.value, nc.value, ns.value
+
+
+def query(prob):
+    return query_handle(prob.handle)
+
+
+def cell_shift(prob):
+    """ddeig_cell_shift: returns (sigma, psi as a numpy array of n_cell values)."""
+    lib = load_library()
+    sig = ctypes.c_double()
+    psi = np.zeros(prob.n_cell)
+    _check(lib.ddeig_cell_shift(prob.handle, ctypes.byref(sig),
+                                psi.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "ddeig_cell_shift")
+    prob.sigma = sig.value
+    return sig.value, psi
+
+
+def set_shift(prob, sigma, psi=None):
+    lib = load_library()
+    ptr = None
+    if psi is not None:
+        psi = np.ascontiguousarray(psi, dtype=np.float64)
+        if psi.size != prob.n_cell:
+            raise ValueError("psi must have n_cell entries")
+        ptr = psi.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(lib.ddeig_set_shift(prob.handle, float(sigma), ptr), "ddeig_set_shift")
+    prob.sigma = float(sigma)
+
+
+def apply_op(prob, which, x, y):
+    """ddeig_apply_op: y = Op x, which in {"A_sigma", "A", "M", "K"} or 0..3."""
+    w = OPS[which] if isinstance(which, str) else int(which)
+    _check(load_library().ddeig_apply_op(prob.handle, w, _ptr(x, prob.n_dof, "x"),
+                                         _ptr(y, prob.n_dof, "y")), "ddeig_apply_op")
+
+
+def apply_precond(prob, r, z):
+    _check(load_library().ddeig_apply_precond(prob.handle, _ptr(r, prob.n_dof, "r"),
+                                              _ptr(z, prob.n_dof, "z")), "ddeig_apply_precond")
+
+
+def pcg_solve(prob, b, x, rtol=1e-10, maxit=1000, hist_cap=0, raise_on_error=True):
+    """ddeig_pcg_solve; returns dict(status, iters, relres, breakdown, hist)."""
+    lib = load_library()
+    info = PcgInfo()
+    hist = np.zeros(max(hist_cap, 1))
+    info.hist = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if hist_cap > 0 else None
+    info.hist_cap = hist_cap
+    st = lib.ddeig_pcg_solve(prob.handle, _ptr(b, prob.n_dof, "b"), _ptr(x, prob.n_dof, "x"),
+                             float(rtol), int(maxit), ctypes.byref(info))
+    out = dict(status=STATUS.get(st, st), iters=info.iters, relres=info.relres,
+               breakdown=info.breakdown,
+               hist=hist[:min(hist_cap, info.iters + 1)] if hist_cap > 0 else None)
+    if raise_on_error and st != DDEIG_OK:
+        _check(st, "ddeig_pcg_solve")
+    return out
+
+
+def inverse_iteration(prob, x, tol_x=1e-9, maxit_outer=100, rtol_inner=1e-10, maxit_inner=1000,
+                      raise_on_error=True):
+    """ddeig_inverse_iteration; x (in: start or zeros, out: eigenvector)."""
+    lib = load_library()
+    info = EigInfo()
+    st = lib.ddeig_inverse_iteration(prob.handle, _ptr(x, prob.n_dof, "x"), float(tol_x),
+                                     int(maxit_outer), float(rtol_inner), int(maxit_inner),
+                                     ctypes.byref(info))
+    out = dict(status=STATUS.get(st, st), lam=info.lambda_, dx_M=info.dx_M,
+               outer_its=info.outer_its, inner_sum=info.inner_sum, inner_max=info.inner_max,
+               t_solve_ms=info.t_solve_ms)
+    if raise_on_error and st != DDEIG_OK:
+        _check(st, "ddeig_inverse_iteration")
+    return out
+
+
+def status_string(code):
+    return load_library().ddeig_status_string(int(code)).decode()
