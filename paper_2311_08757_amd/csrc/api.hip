@@ -118,6 +118,19 @@ void factor_types(ddeig_problem* P) {
       launch_to_float(t.W, t.W32, (long)t.box.nch * t.box.b * t.box.b, P->stream);
   }
   check_launch("local factorisation");
+  if (P->opt.local_prec == 2) {
+    // dense inverses: chain solves of the identity columns, then bf16 hi/lo split
+    for (auto& t : P->types) {
+      const int m = t.box.nch * t.box.b;
+      double* Ainv = dalloc<double>(P, (size_t)m * m);
+      launch_identity(Ainv, m, P->stream);
+      launch_chain_solve_box(P, t.box, P->tabAs, t.W, Ainv, m, P->stream);
+      launch_split_inverse(Ainv, m, t.ld, t.Ah, t.Al, P->stream);
+      check_launch("dense inverse");
+      sync(P);
+      dfree(P, Ainv);
+    }
+  }
 }
 
 int read_flag(ddeig_problem* P) {
@@ -280,7 +293,7 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
   ddeig_options o{0, 1, 0, 8};
   if (opts) o = *opts;
   if (o.pu < 0 || o.pu > 1 || o.coarse < 0 || o.coarse > 1 || o.local_prec < 0 ||
-      o.local_prec > 1 || o.batch_iters < 0)
+      o.local_prec > 2 || o.batch_iters < 0)
     return set_error(DDEIG_EINVAL, "invalid options");
 
   ddeig::VSpec vs{};
@@ -404,11 +417,26 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
     }
     int maxb = 0;
     std::vector<ddeig::TypeDev> tdev(P->types.size());
+    const bool dense = o.local_prec == 2;
+    // dense classes: split K so that the grouped GEMM has enough workgroups
+    if (dense) {
+      long tiles = 0;
+      int minkb = 1 << 30;
+      for (auto& T : P->types) {
+        const int m = T.box.nch * T.box.b;
+        T.ld = (m + 127) / 128 * 128;
+        T.mp = (T.nmem + 127) / 128 * 128;
+        tiles += (long)(T.mp / 128) * (T.ld / 128);
+        minkb = std::min(minkb, T.ld / 32);
+      }
+      P->ksplit = (int)std::max<long>(1, std::min<long>(std::min(8, minkb), (384 + tiles - 1) / tiles));
+    }
+    std::vector<ddeig::GemmTile> tiles;
+    std::vector<ddeig::GemmType> gtypes;
     for (size_t t = 0; t < P->types.size(); ++t) {
       auto& T = P->types[t];
       maxb = std::max(maxb, T.box.b);
       const long mm = (long)T.box.nch * T.box.b;
-      T.batch = dalloc<double>(P, (size_t)T.nmem * mm);
       T.W = dalloc<double>(P, (size_t)T.box.nch * T.box.b * T.box.b);
       if (o.local_prec == 1) T.W32 = dalloc<float>(P, (size_t)T.box.nch * T.box.b * T.box.b);
       for (int a = 0; a < 3; ++a) tdev[t].m[a] = T.box.m[a];
@@ -416,7 +444,50 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
       tdev[t].nch = T.box.nch;
       tdev[t].W = T.W;
       tdev[t].W32 = T.W32;
+      tdev[t].dense = dense ? 1 : 0;
+      if (dense) {
+        const size_t aa = (size_t)T.ld * T.ld, rr = (size_t)T.mp * T.ld;
+        T.Ah = dalloc<__bf16>(P, aa);
+        T.Al = dalloc<__bf16>(P, aa);
+        T.Rh = dalloc<__bf16>(P, rr);
+        T.Rl = dalloc<__bf16>(P, rr);
+        T.Z = dalloc<float>(P, (size_t)P->ksplit * rr);
+        check_hip(hipMemsetAsync(T.Rh, 0, rr * sizeof(__bf16), s), "memset Rh");
+        check_hip(hipMemsetAsync(T.Rl, 0, rr * sizeof(__bf16), s), "memset Rl");
+        T.batch = dalloc<double>(P, 1);
+        tdev[t].ld = T.ld;
+        tdev[t].ksplit = P->ksplit;
+        tdev[t].Rh = T.Rh;
+        tdev[t].Rl = T.Rl;
+        tdev[t].Z = T.Z;
+        tdev[t].zsplit = (long)rr;
+        ddeig::GemmType gt{T.Ah, T.Al, T.Rh, T.Rl, T.Z, (long)rr, T.ld};
+        gtypes.push_back(gt);
+        const int nkb = T.ld / 32;
+        for (int sp = 0; sp < P->ksplit; ++sp) {
+          const int kb0 = (int)((long)nkb * sp / P->ksplit), kb1 = (int)((long)nkb * (sp + 1) / P->ksplit);
+          for (int nt = 0; nt < T.ld / 128; ++nt)
+            for (int mt = 0; mt < T.mp / 128; ++mt)
+              tiles.push_back(ddeig::GemmTile{(int)t, mt * 128, nt * 128, kb0 * 32, kb1 * 32, sp});
+        }
+      } else {
+        T.batch = dalloc<double>(P, (size_t)T.nmem * mm);
+        tdev[t].ld = 0;
+        tdev[t].ksplit = 0;
+        tdev[t].Rh = tdev[t].Rl = nullptr;
+        tdev[t].Z = nullptr;
+        tdev[t].zsplit = 0;
+      }
       tdev[t].batch = T.batch;
+    }
+    if (dense) {
+      P->ntiles = (int)tiles.size();
+      P->dTiles = dalloc<ddeig::GemmTile>(P, tiles.size());
+      P->dGtypes = dalloc<ddeig::GemmType>(P, gtypes.size());
+      check_hip(hipMemcpyAsync(P->dTiles, tiles.data(), sizeof(ddeig::GemmTile) * tiles.size(),
+                               hipMemcpyHostToDevice, s), "copy tiles");
+      check_hip(hipMemcpyAsync(P->dGtypes, gtypes.data(), sizeof(ddeig::GemmType) * gtypes.size(),
+                               hipMemcpyHostToDevice, s), "copy gemm types");
     }
     P->maxb = std::max(maxb, 1);
     const Box cb = cell_box(g);

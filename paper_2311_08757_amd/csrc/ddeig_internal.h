@@ -62,6 +62,10 @@ struct SubType {
   double* W = nullptr;      // nch * b * b FP64 Schur-complement inverses
   float* W32 = nullptr;     // FP32 copy (local_prec = 1)
   double* batch = nullptr;  // nmem * nch * b local vectors
+  // dense-inverse class data (local_prec = 2)
+  int ld = 0, mp = 0;
+  __bf16 *Ah = nullptr, *Al = nullptr, *Rh = nullptr, *Rl = nullptr;
+  float* Z = nullptr;
 };
 
 // Per-subdomain data on the device.
@@ -78,6 +82,28 @@ struct TypeDev {
   const double* W;
   const float* W32;
   double* batch;
+  // dense-inverse classes (local_prec = 2): bf16 hi/lo residual rows and
+  // split-K partial results Z[split][slot][e]
+  int dense, ld, ksplit;
+  __bf16* Rh;
+  __bf16* Rl;
+  const float* Z;
+  long zsplit;
+};
+
+// Operands of the grouped MFMA GEMM of one dense class (ld x ld inverse).
+struct GemmType {
+  const __bf16* Ah;
+  const __bf16* Al;
+  const __bf16* Rh;
+  const __bf16* Rl;
+  float* Z;
+  long zsplit;
+  int ld;
+};
+
+struct GemmTile {
+  int type, m0, n0, k0, k1, split;
 };
 
 // PCG device state (one per problem).
@@ -115,6 +141,10 @@ struct ddeig_problem {
   ddeig::SubDev* dSubs = nullptr;
   ddeig::TypeDev* dTypes = nullptr;
   int maxb = 0;
+  // grouped GEMM of the dense classes
+  int ntiles = 0, ksplit = 1;
+  ddeig::GemmTile* dTiles = nullptr;
+  ddeig::GemmType* dGtypes = nullptr;
   // coarse space
   double* A0inv = nullptr;  // nsub x nsub
   double* crhs = nullptr;   // nsub
@@ -160,6 +190,9 @@ void launch_coarse_solve(const ddeig_problem* P, const PcgState* st, hipStream_t
 void launch_extend(const ddeig_problem* P, const double* r, double* z, int coarse, double* dot,
                    const PcgState* st, hipStream_t s);
 void launch_symmetrise(double* A, int N, hipStream_t s);
+void launch_split_inverse(const double* Ainv, int m, int ld, void* Ah, void* Al, hipStream_t s);
+void launch_identity(double* v, int m, hipStream_t s);
+void launch_dense_gemm(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 void launch_to_float(const double* src, float* dst, long n, hipStream_t s);
 void build_coarse_matrix(ddeig_problem* P, double* A0, hipStream_t s);
 

@@ -263,13 +263,193 @@ __global__ void __launch_bounds__(kBlock) k_local_solves(Geo g, const double* __
   chain_solve_block<WT>(g, bx, T, W, td.batch + (long)sd.slot * td.nch * td.b, sh);
 }
 
+bool local_solves_fast_ok(const ddeig_problem* P);
+void launch_local_solves_fast(const ddeig_problem* P, const PcgState* st, hipStream_t s);
+
 void launch_local_solves(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
+  if (P->opt.local_prec == 2) {
+    launch_dense_gemm(P, st, s);
+    return;
+  }
+  if (local_solves_fast_ok(P)) {
+    launch_local_solves_fast(P, st, s);
+    return;
+  }
   const size_t lds = 2 * (size_t)P->maxb * sizeof(double);
   if (P->opt.local_prec == 1)
     hipLaunchKernelGGL(k_local_solves<float>, dim3(P->nsub), dim3(kBlock), lds, s, P->g,
                        P->tabAs, P->dTypes, P->dSubs, st);
   else
     hipLaunchKernelGGL(k_local_solves<double>, dim3(P->nsub), dim3(kBlock), lds, s, P->g,
+                       P->tabAs, P->dTypes, P->dSubs, st);
+}
+
+}  // namespace ddeig
+
+namespace ddeig {
+
+// Local solves of the 2-D decompositions (slices along x of at most kFastB
+// unknowns, chain along y).  W_i is staged in LDS with double buffering;
+// while step i computes from LDS, every thread already holds its share of
+// W_{i+1} (W_{i-1} in the backward sweep), the next slice of the right-hand
+// side and the next coupling coefficients in registers.  Each row's dot
+// product is split over np = floor(256 / b) thread groups and the parts are
+// added in a fixed order.  In 2-D the couplings to the neighbouring slice are
+// the taps (d0, d1) = (-1..1, -1) (forward) and (-1..1, +1) (backward), i.e.
+// table taps 0..2 and 6..8, with in-slice neighbours r-1, r, r+1.
+constexpr int kFastB = 72;
+constexpr int kFastRegs = (kFastB * kFastB + kBlock - 1) / kBlock;
+template <typename WT>
+__device__ inline double dot_part(const WT* __restrict__ wc, const double* __restrict__ gv, int b,
+                                  int r, int s0, int s1) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int s = s0;
+  for (; s + 3 < s1; s += 4) {
+    a0 += (double)wc[s * b + r] * gv[s];
+    a1 += (double)wc[(s + 1) * b + r] * gv[s + 1];
+    a2 += (double)wc[(s + 2) * b + r] * gv[s + 2];
+    a3 += (double)wc[(s + 3) * b + r] * gv[s + 3];
+  }
+  for (; s < s1; ++s) a0 += (double)wc[s * b + r] * gv[s];
+  return (a0 + a1) + (a2 + a3);
+}
+template <typename WT>
+__global__ void __launch_bounds__(kBlock) k_local_solves_2d(Geo g, const double* __restrict__ T,
+                                                            const TypeDev* __restrict__ types,
+                                                            const SubDev* __restrict__ subs,
+                                                            const PcgState* __restrict__ st) {
+  __shared__ WT wbuf[2][kFastB * kFastB];
+  __shared__ double gb[kFastB];
+  __shared__ double tb[kFastB];
+  __shared__ double red[kBlock];
+  if (st != nullptr && st->done) return;
+  const SubDev sd = subs[blockIdx.x];
+  const TypeDev td = types[sd.type];
+  const int b = td.b, nch = td.nch;
+  const int bb = b * b;
+  const int tid = threadIdx.x;
+  const int np = kBlock / b;  // thread groups per row
+  const int chunk = (b + np - 1) / np;
+  const int part = tid / b, rr = tid - part * b;
+  const bool dot_thread = part < np;
+  const int s0 = min(b, part * chunk), s1 = min(b, s0 + chunk);
+  const WT* __restrict__ W;
+  if constexpr (sizeof(WT) == 4) W = reinterpret_cast<const WT*>(td.W32);
+  else W = reinterpret_cast<const WT*>(td.W);
+  double* __restrict__ v = td.batch + (long)sd.slot * nch * b;
+  const bool row = tid < b;
+  const int jx = row ? (sd.o[0] + tid + 1) % g.ne : 0;
+  const bool has_l = tid > 0, has_r = tid + 1 < b;
+  WT pre[kFastRegs];
+  for (int j = tid; j < bb; j += kBlock) wbuf[0][j] = W[j];
+  double vnext = row ? v[tid] : 0.0;
+  double cn0 = 0.0, cn1 = 0.0, cn2 = 0.0;
+  __syncthreads();
+  // forward sweep: t_i = W_i (b_i - E_i t_{i-1})
+  for (int i = 0; i < nch; ++i) {
+    const double vi = vnext, c0 = cn0, c1 = cn1, c2 = cn2;
+    if (i + 1 < nch) {
+      const WT* Wn = W + (long)(i + 1) * bb;
+#pragma unroll
+      for (int j = 0; j < kFastRegs; ++j) {
+        const int idx = tid + j * kBlock;
+        if (idx < bb) pre[j] = Wn[idx];
+      }
+      if (row) {
+        vnext = v[(long)(i + 1) * b + tid];
+        const long tn = jx + (long)g.P[0] * (sd.o[1] + i + 1);
+        cn0 = T[0 * g.tsize + tn];
+        cn1 = T[1 * g.tsize + tn];
+        cn2 = T[2 * g.tsize + tn];
+      }
+    }
+    if (row) {
+      double val = vi;
+      if (i > 0) {
+        if (has_l) val -= c0 * tb[tid - 1];
+        val -= c1 * tb[tid];
+        if (has_r) val -= c2 * tb[tid + 1];
+      }
+      gb[tid] = val;
+    }
+    __syncthreads();
+    if (dot_thread) red[tid] = dot_part(wbuf[i & 1], gb, b, rr, s0, s1);
+    __syncthreads();
+    if (row) {
+      double acc = red[tid];
+      for (int pp = 1; pp < np; ++pp) acc += red[pp * b + tid];
+      v[(long)i * b + tid] = acc;
+      tb[tid] = acc;
+    }
+    if (i + 1 < nch) {
+#pragma unroll
+      for (int j = 0; j < kFastRegs; ++j) {
+        const int idx = tid + j * kBlock;
+        if (idx < bb) wbuf[(i + 1) & 1][idx] = pre[j];
+      }
+    }
+    __syncthreads();
+  }
+  // backward sweep: x_i = t_i - W_i E_{i+1}^T x_{i+1}; W_{nch-2} is still in wbuf[nch & 1]
+  if (nch >= 2 && row) {
+    const long tn = jx + (long)g.P[0] * (sd.o[1] + nch - 2);
+    cn0 = T[6 * g.tsize + tn];
+    cn1 = T[7 * g.tsize + tn];
+    cn2 = T[8 * g.tsize + tn];
+    vnext = v[(long)(nch - 2) * b + tid];
+  }
+  for (int i = nch - 2; i >= 0; --i) {
+    const double vi = vnext, c0 = cn0, c1 = cn1, c2 = cn2;
+    if (i >= 1) {
+      const WT* Wn = W + (long)(i - 1) * bb;
+#pragma unroll
+      for (int j = 0; j < kFastRegs; ++j) {
+        const int idx = tid + j * kBlock;
+        if (idx < bb) pre[j] = Wn[idx];
+      }
+      if (row) {
+        vnext = v[(long)(i - 1) * b + tid];
+        const long tn = jx + (long)g.P[0] * (sd.o[1] + i - 1);
+        cn0 = T[6 * g.tsize + tn];
+        cn1 = T[7 * g.tsize + tn];
+        cn2 = T[8 * g.tsize + tn];
+      }
+    }
+    if (row) {
+      double val = c1 * tb[tid];
+      if (has_l) val += c0 * tb[tid - 1];
+      if (has_r) val += c2 * tb[tid + 1];
+      gb[tid] = val;
+    }
+    __syncthreads();
+    if (dot_thread) red[tid] = dot_part(wbuf[i & 1], gb, b, rr, s0, s1);
+    __syncthreads();
+    if (row) {
+      double acc = red[tid];
+      for (int pp = 1; pp < np; ++pp) acc += red[pp * b + tid];
+      const double x = vi - acc;
+      v[(long)i * b + tid] = x;
+      tb[tid] = x;
+    }
+    if (i >= 1) {
+#pragma unroll
+      for (int j = 0; j < kFastRegs; ++j) {
+        const int idx = tid + j * kBlock;
+        if (idx < bb) wbuf[(i - 1) & 1][idx] = pre[j];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+bool local_solves_fast_ok(const ddeig_problem* P) { return P->maxb <= kFastB && P->g.D == 2; }
+
+void launch_local_solves_fast(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
+  if (P->opt.local_prec == 1)
+    hipLaunchKernelGGL(k_local_solves_2d<float>, dim3(P->nsub), dim3(kBlock), 0, s, P->g,
+                       P->tabAs, P->dTypes, P->dSubs, st);
+  else
+    hipLaunchKernelGGL(k_local_solves_2d<double>, dim3(P->nsub), dim3(kBlock), 0, s, P->g,
                        P->tabAs, P->dTypes, P->dSubs, st);
 }
 

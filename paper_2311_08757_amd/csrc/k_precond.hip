@@ -95,7 +95,15 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Geo g, int delta, int pu, i
     const int i[3] = {sd.o[0] + u0, sd.o[1] + u1, sd.o[2] + u2};
     const long k = i[0] + (long)g.N[0] * (i[1] + (long)g.N[1] * i[2]);
     const double rv = r[k];
-    dst[e] = rv;
+    if (td.dense) {
+      __bf16 hi, lo;
+      hi = (__bf16)(float)rv;
+      lo = (__bf16)(float)(rv - (double)(float)hi);
+      td.Rh[(long)sd.slot * td.ld + e] = hi;
+      td.Rl[(long)sd.slot * td.ld + e] = lo;
+    } else {
+      dst[e] = rv;
+    }
     if (coarse) acc += pu_weight(g, delta, pu, sd.c, i) * psi[table_node(g, i[0], i[1], i[2])] * rv;
   }
   if (coarse) {
@@ -110,21 +118,25 @@ void launch_restrict(const ddeig_problem* P, const double* r, int coarse, const 
                      coarse, st, r, P->dTypes, P->dSubs, P->psi, P->crhs);
 }
 
-// y0 = A0^{-1} c with the dense symmetric inverse (read column-wise).
+// y0 = A0^{-1} c with the dense symmetric inverse: one wave64 per row, lanes
+// stride the row (coalesced), fixed-order shuffle reduction.
 __global__ void k_coarse_solve(int N, const PcgState* __restrict__ st,
                                const double* __restrict__ A0inv, const double* __restrict__ c,
                                double* __restrict__ y) {
   if (st != nullptr && st->done) return;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    for (int j = 0; j < N; ++j) acc += A0inv[(long)j * N + i] * c[j];
-    y[i] = acc;
-  }
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (row >= N) return;
+  double acc = 0.0;
+  for (int j = lane; j < N; j += 64) acc += A0inv[(long)row * N + j] * c[j];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) y[row] = acc;
 }
 
 void launch_coarse_solve(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_coarse_solve, dim3((P->nsub + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                     P->nsub, st, P->A0inv, P->crhs, P->cy);
+  const int rows_per_block = kBlock / 64;
+  hipLaunchKernelGGL(k_coarse_solve, dim3((P->nsub + rows_per_block - 1) / rows_per_block),
+                     dim3(kBlock), 0, s, P->nsub, st, P->A0inv, P->crhs, P->cy);
 }
 
 // z = sum_c R_c^T y_c (+ R_0^T y0), partials of r.z.
@@ -154,7 +166,14 @@ __global__ void __launch_bounds__(kBlock) k_extend(Geo g, int delta, int pu, int
         const TypeDev td = types[sd.type];
         const long e = (i[0] - sd.o[0]) +
                        (long)td.m[0] * ((i[1] - sd.o[1]) + (long)td.m[1] * (i[2] - sd.o[2]));
-        zl += td.batch[(long)sd.slot * td.m[0] * td.m[1] * td.m[2] + e];
+        if (td.dense) {
+          const float* zp = td.Z + (long)sd.slot * td.ld + e;
+          float zs = 0.0f;
+          for (int sp = 0; sp < td.ksplit; ++sp) zs += zp[sp * td.zsplit];
+          zl += (double)zs;
+        } else {
+          zl += td.batch[(long)sd.slot * td.m[0] * td.m[1] * td.m[2] + e];
+        }
         if (coarse) zc += pu_weight(g, delta, pu, c, i) * y0[sid];
       }
     double zv = zl;

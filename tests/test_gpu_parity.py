@@ -184,3 +184,35 @@ def test_errors(torch):
     out = dd.pcg_solve(prob, _dev(torch, W.random_vector(prob.n_dof, 1)), x, rtol=1e-14, maxit=3,
                        raise_on_error=False)
     assert out["status"] == "ENOCONV" and out["iters"] == 3
+
+
+PREC_CASES = [CASES[0], CASES[1], CASES[4], CASES[5]]
+PREC_IDS = [IDS[0], IDS[1], IDS[4], IDS[5]]
+
+
+@pytest.mark.parametrize("case", PREC_CASES, ids=PREC_IDS)
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_reduced_precision_local_solves(torch, case, prec):
+    """FP32 chain factors or bf16x3 dense inverses on MFMA change only the
+    preconditioner: z stays close to the exact M^{-1} r (2^-16-level splits,
+    tolerance 1e-3 relative), PCG stays FP64, so the eigenpair meets the same
+    1e-10 / 1e-8 bar as the FP64 path."""
+    import paper_2311_08757_amd as dd
+    from oracle.ipm import inverse_iteration_direct
+    P = _oracle(case)
+    prob = _assemble(case, local_prec=prec)
+    dd.set_shift(prob, P.sigma, P.cell["psi"])
+    r = W.random_vector(P.grid.n, 7)
+    z = torch.empty(P.grid.n, dtype=torch.float64, device="cuda")
+    dd.apply_precond(prob, _dev(torch, r), z)
+    torch.cuda.synchronize()
+    zr = P.preconditioner(True).apply(r)
+    assert np.linalg.norm(z.cpu().numpy() - zr) <= 1e-3 * np.linalg.norm(zr)
+    prob2 = _assemble(case, local_prec=prec)
+    dd.cell_shift(prob2)
+    x = torch.zeros(P.grid.n, dtype=torch.float64, device="cuda")
+    out = dd.inverse_iteration(prob2, x, tol_x=1e-9, rtol_inner=1e-10)
+    ref = inverse_iteration_direct(P.A, P.M, P.sigma, P.grid if P.grid.d == 2 else None)
+    assert abs(out["lam"] - ref["lam"]) <= 1e-10 * abs(ref["lam"])
+    d = x.cpu().numpy() - ref["x"]
+    assert np.sqrt(d @ (P.M @ d)) <= 1e-8
