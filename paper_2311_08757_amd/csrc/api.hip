@@ -54,16 +54,18 @@ void sync(ddeig_problem* P) { check_hip(hipStreamSynchronize(P->stream), "hipStr
 
 void check_launch(const char* what) { check_hip(hipGetLastError(), what); }
 
-double host_sum(ddeig_problem* P, const double* part) {
-  launch_sum_partials(part, P->scal, P->stream);
+Red slot(ddeig_problem* P, int i) {
+  return Red{P->red_part + (long)i * kMaxRed, 0, P->red_val + i};
+}
+
+double host_sum(ddeig_problem* P, Red r) {
+  launch_finish_sum(r, P->stream);
   double v = 0.0;
-  check_hip(hipMemcpyAsync(&v, P->scal, sizeof(double), hipMemcpyDeviceToHost, P->stream),
+  check_hip(hipMemcpyAsync(&v, r.val, sizeof(double), hipMemcpyDeviceToHost, P->stream),
             "copy scalar");
   sync(P);
   return v;
 }
-
-double* slot(ddeig_problem* P, int i) { return P->part + (long)i * kRedBlocks; }
 
 // The cell box: whole unit cell, periodic in x (origin -1 so that the node
 // index equals the cell index), all fixed-direction unknowns.
@@ -161,7 +163,8 @@ ddeig_status finish_shift(ddeig_problem* P) {
   return DDEIG_OK;
 }
 
-void precond_apply(ddeig_problem* P, const double* r, double* z, double* dot, const PcgState* st) {
+void precond_apply(ddeig_problem* P, const double* r, double* z, Red* dot,
+                   const PcgState* st) {
   const int coarse = P->opt.coarse;
   launch_restrict(P, r, coarse, st, P->stream);
   launch_local_solves(P, st, P->stream);
@@ -179,11 +182,12 @@ struct PcgOut {
 PcgOut pcg_run(ddeig_problem* P, const double* b, double* x, double rtol, int maxit) {
   const hipStream_t s = P->stream;
   const int batch = P->opt.batch_iters > 0 ? P->opt.batch_iters : 8;
+  Red g = slot(P, 0), rr = slot(P, 1), rz = slot(P, 2);
   launch_stencil(P, P->tabAs, x, P->q, nullptr, nullptr, s);
-  launch_resid_init(P, b, P->q, P->r, slot(P, 1), s);
-  launch_pcg_init(P, rtol, slot(P, 1), s);
-  precond_apply(P, P->r, P->z, slot(P, 2), P->st);
-  launch_pcg_start(P, P->z, P->p, slot(P, 2), s);
+  launch_resid_init(P, b, P->q, P->r, rr, s);
+  launch_pcg_init(P, rtol, rr, s);
+  precond_apply(P, P->r, P->z, &rz, P->st);
+  launch_pcg_start(P, P->z, P->p, rz, s);
   check_launch("pcg start");
   PcgState hs{};
   int k = 0;
@@ -194,11 +198,11 @@ PcgOut pcg_run(ddeig_problem* P, const double* b, double* x, double rtol, int ma
   while (k < maxit) {
     const int kend = std::min(maxit, k + batch);
     for (++k; k <= kend; ++k) {
-      launch_stencil(P, P->tabAs, P->p, P->q, slot(P, 0), nullptr, s);
-      launch_pcg_update_xr(P, x, P->p, P->q, P->r, slot(P, 0), slot(P, 1), k, s);
-      launch_pcg_check(P, slot(P, 1), k, maxit, s);
-      precond_apply(P, P->r, P->z, slot(P, 2), P->st);
-      launch_pcg_update_p(P, P->z, P->p, slot(P, 2), k, s);
+      launch_stencil(P, P->tabAs, P->p, P->q, &g, nullptr, s);
+      launch_pcg_update_xr(P, x, P->p, P->q, P->r, g, rr, k, maxit, s);
+      launch_pcg_check(P, rr, k, maxit, s);
+      precond_apply(P, P->r, P->z, &rz, P->st);
+      launch_pcg_update_p(P, P->z, P->p, rz, k, s);
     }
     --k;
     check_launch("pcg iteration");
@@ -348,6 +352,9 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
   if (n > (1L << 34)) return set_error(DDEIG_EINVAL, "problem too large");
   g.n = n;
   g.tsize = ts;
+  g.fN0 = ddeig::make_fastdiv((unsigned)g.N[0]);
+  g.fN1 = ddeig::make_fastdiv((unsigned)g.N[1]);
+  g.fne = ddeig::make_fastdiv((unsigned)ne);
 
   ddeig_problem* P = new (std::nothrow) ddeig_problem();
   if (!P) return set_error(DDEIG_ENOMEM, "host allocation failed");
@@ -504,7 +511,8 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
     P->q = dalloc<double>(P, n);
     P->u = dalloc<double>(P, n);
     P->w = dalloc<double>(P, n);
-    P->part = dalloc<double>(P, 8 * (size_t)kRedBlocks);
+    P->red_part = dalloc<double>(P, (size_t)kRedSlots * kMaxRed);
+    P->red_val = dalloc<double>(P, kRedSlots);
     P->st = dalloc<ddeig::PcgState>(P, 1);
     P->hist_cap = 10001;
     P->hist = dalloc<double>(P, P->hist_cap);
@@ -513,7 +521,55 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
     P->gjbuf = dalloc<double>(P, 4 * (size_t)gjmax);
     P->gj_stride = gjmax;
     P->psi = dalloc<double>(P, g.tsize);
-    P->crhs = dalloc<double>(P, nsub);
+    // restriction: enough workgroups per subdomain to fill the chip
+    {
+      int minl = 1 << 30;
+      for (auto& T : P->types) minl = std::min(minl, T.box.m[1] * T.box.m[2]);
+      const int want = (1024 + nsub - 1) / nsub;
+      P->restrict_rb = std::max(1, std::min(std::min(16, want), minl));
+    }
+    P->crhs = dalloc<double>(P, (size_t)nsub * P->restrict_rb);
+    // per-axis covering tables of the expanding directions
+    for (int a = 0; a < p; ++a) {
+      std::vector<ddeig::XCover> xc(g.N[a]);
+      for (int i = 0; i < g.N[a]; ++i) {
+        const int gi = i + 1;
+        const int num = gi - overlap + 1;
+        int clo = num <= 0 ? 1 : (num + ne - 1) / ne;
+        int chi = (gi + overlap - 1) / ne + 1;
+        clo = std::max(clo, 1);
+        chi = std::min(chi, L);
+        ddeig::XCover c{};
+        long dsum = 0;
+        long dist[2] = {0, 0};
+        for (int q2 = 0; q2 < 2; ++q2) {
+          const int cc = clo + q2;
+          if (cc > chi) { c.c[q2] = 0; c.u[q2] = 0; c.w[q2] = 0.0; continue; }
+          c.c[q2] = cc;
+          const int lo = std::max((cc - 1) * ne - overlap + 1, 1);
+          c.u[q2] = i - (lo - 1);
+          long dm = -1;  // distance (in units of h) to the interior faces of the box
+          if (cc > 1) dm = gi - ((cc - 1) * ne - overlap);
+          if (cc < L) {
+            const long dh = (long)cc * ne + overlap - gi;
+            dm = dm < 0 ? dh : std::min(dm, dh);
+          }
+          dist[q2] = dm;
+          dsum += dm;
+        }
+        const int cnt = chi - clo + 1;
+        for (int q2 = 0; q2 < cnt; ++q2) {
+          if (o.pu == 0 || L == 1) c.w[q2] = 1.0 / cnt;
+          else c.w[q2] = (double)dist[q2] / (double)dsum;
+        }
+        xc[i] = c;
+      }
+      P->dXC[a] = dalloc<ddeig::XCover>(P, xc.size());
+      check_hip(hipMemcpyAsync(P->dXC[a], xc.data(), sizeof(ddeig::XCover) * xc.size(),
+                               hipMemcpyHostToDevice, s), "copy covering table");
+      sync(P);  // xc is released at the end of this scope
+    }
+    if (p == 1) P->dXC[1] = P->dXC[0];  // unused second axis
     P->cy = dalloc<double>(P, nsub);
     P->A0inv = dalloc<double>(P, (size_t)nsub * nsub);
     check_hip(hipMemsetAsync(P->flag, 0, sizeof(int), s), "memset flag");
@@ -598,18 +654,20 @@ ddeig_status ddeig_cell_shift(ddeig_problem* P, double* sigma_out, double* psi_c
     launch_box_stencil(P, cb, P->tabM, v0, v1, nullptr, nullptr, s);
     launch_copy(v2, v1, nc, s);
     launch_chain_solve_box(P, cb, P->tabAs, Wc, v2, 1, s);
-    launch_box_stencil(P, cb, P->tabM, v2, v3, slot(P, 4), slot(P, 5), s);
-    launch_ipm_normalise(nc, v2, v3, v0, v1, slot(P, 4), slot(P, 5), slot(P, 6), s);
+    Red s4 = slot(P, 4), s5 = slot(P, 5), s6 = slot(P, 6);
+    launch_box_stencil(P, cb, P->tabM, v2, v3, &s4, &s5, s);
+    launch_ipm_normalise(nc, v2, v3, v0, v1, s4, s5, s6, s);
     check_launch("cell iteration");
-    const double d2 = host_sum(P, slot(P, 6));
+    const double d2 = host_sum(P, s6);
     const double d = std::sqrt(std::max(d2, 0.0));
     if (d <= 1e-14) break;
     if (it > 10 && d < 1e-12 && d > 0.8 * prev) break;  // stagnated at rounding level
     prev = d;
   }
   // sigma = psi^T A# psi with psi M#-normalised
-  launch_box_stencil(P, cb, P->tabA, v0, v1, slot(P, 4), nullptr, s);
-  const double sig = host_sum(P, slot(P, 4));
+  Red s4 = slot(P, 4);
+  launch_box_stencil(P, cb, P->tabA, v0, v1, &s4, nullptr, s);
+  const double sig = host_sum(P, s4);
   launch_copy(P->psi, v0, nc, s);
   if (psi_cell_host)
     check_hip(hipMemcpyAsync(psi_cell_host, v0, sizeof(double) * nc, hipMemcpyDeviceToHost, s), "copy psi");
@@ -696,11 +754,12 @@ ddeig_status ddeig_inverse_iteration(ddeig_problem* P, double* x, double tol_x, 
   const long n = P->g.n;
   const auto t0 = std::chrono::steady_clock::now();
   // start vector: x, or 1/||1||_M if x is all zeros
-  launch_dot(x, x, n, slot(P, 3), s);
-  if (host_sum(P, slot(P, 3)) == 0.0) {
+  Red s3 = slot(P, 3);
+  launch_dot(x, x, n, s3, s);
+  if (host_sum(P, s3) == 0.0) {
     launch_fill(P->u, n, 1.0, s);
-    launch_stencil(P, P->tabM, P->u, P->w, slot(P, 3), nullptr, s);
-    launch_scale_copy(n, x, P->u, slot(P, 3), s);
+    launch_stencil(P, P->tabM, P->u, P->w, &s3, nullptr, s);
+    launch_scale_copy(n, x, P->u, s3, s);
   }
   double lam = 0.0, dx = INFINITY;
   long inner_sum = 0;
@@ -716,13 +775,15 @@ ddeig_status ddeig_inverse_iteration(ddeig_problem* P, double* x, double tol_x, 
     }
     inner_sum += o.iters;
     inner_max = std::max(inner_max, o.iters);
-    launch_stencil(P, P->tabM, P->u, P->z, slot(P, 4), slot(P, 5), s);  // Mu, u.Mu, sum(Mu)
-    launch_ipm_normalise(n, P->u, P->z, x, P->w, slot(P, 4), slot(P, 5), slot(P, 6), s);
-    launch_stencil(P, P->tabAs, x, P->q, slot(P, 7), nullptr, s);      // x.A_sigma x
-    launch_sum_partials(slot(P, 6), P->scal, s);
-    launch_sum_partials(slot(P, 7), P->scal + 1, s);
+    Red s4 = slot(P, 4), s5 = slot(P, 5), s6 = slot(P, 6), s7 = slot(P, 7);
+    launch_stencil(P, P->tabM, P->u, P->z, &s4, &s5, s);  // Mu, u.Mu, sum(Mu)
+    launch_ipm_normalise(n, P->u, P->z, x, P->w, s4, s5, s6, s);
+    launch_stencil(P, P->tabAs, x, P->q, &s7, nullptr, s);  // x.A_sigma x
+    launch_finish_sum(s6, s);
+    launch_finish_sum(s7, s);
     double hs[2];
-    check_hip(hipMemcpyAsync(hs, P->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s), "copy");
+    check_hip(hipMemcpyAsync(hs, P->red_val + 6, 2 * sizeof(double), hipMemcpyDeviceToHost, s),
+              "copy");
     sync(P);
     dx = std::sqrt(std::max(hs[0], 0.0));
     lam = P->sigma + hs[1];

@@ -13,8 +13,34 @@
 namespace ddeig {
 
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
-constexpr int kRedBlocks = 512;    // fixed grid of every reducing kernel (deterministic sums)
+constexpr int kRedBlocks = 512;    // grid of the coarse-setup style reducing kernels
+constexpr int kMaxRed = 1024;      // largest grid of a reducing kernel (partial-sum capacity)
+constexpr int kRedSlots = 16;
+
+// A global sum: the producing kernel writes one partial per block into part
+// (np blocks); every consumer adds the np partials in block order, so all
+// consumers see the same bits.  val receives the sum when the host needs it.
+struct Red {
+  double* part;
+  int np;
+  double* val;
+};
 constexpr int kMaxTaps = 27;
+
+// Division by a run-time constant d >= 1 through a multiply-high
+// (Granlund-Montgomery): q = (umulhi(n, mul) + n) >> shift, exact for n < 2^31.
+struct FastDiv {
+  unsigned d, mul, shift;
+};
+
+inline FastDiv make_fastdiv(unsigned d) {
+  FastDiv f{d, 0u, 0u};
+  unsigned s = 0;
+  while ((1ull << s) < d) ++s;
+  f.shift = s;
+  f.mul = (unsigned)(((1ull << 32) * ((1ull << s) - d)) / d + 1);
+  return f;
+}
 
 // Geometry of Omega_L on the internal 3-D index space (N0, N1, N2), dim 0 = x1.
 // p + q = D in {2, 3}; for D = 2 the third dim has N2 = 1.  The stencil of a
@@ -30,6 +56,16 @@ struct Geo {
   long n;         // N0 N1 N2
   long tsize;     // P0 P1 P2 (table nodes == cell unknowns)
   double h, ell;
+  FastDiv fN0, fN1, fne;
+};
+
+// Subdomains covering one grid line along an expanding axis: at most two
+// cells (2 delta <= n_e), their 1-based index (0: none), the box-local index
+// of the node, and the partition-of-unity factor of this axis.
+struct XCover {
+  int c[2];
+  int u[2];
+  double w[2];
 };
 
 // Potential description copied to the device (see ddeig_potential).
@@ -141,6 +177,8 @@ struct ddeig_problem {
   ddeig::SubDev* dSubs = nullptr;
   ddeig::TypeDev* dTypes = nullptr;
   int maxb = 0;
+  ddeig::XCover* dXC[2] = {nullptr, nullptr};   // per expanding axis, N[a] entries
+  int restrict_rb = 1;                            // row blocks per subdomain in the restriction
   // grouped GEMM of the dense classes
   int ntiles = 0, ksplit = 1;
   ddeig::GemmTile* dTiles = nullptr;
@@ -151,7 +189,8 @@ struct ddeig_problem {
   double* cy = nullptr;     // nsub
   // work vectors (n each)
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *u = nullptr, *w = nullptr;
-  double* part = nullptr;   // partial sums: 4 slots of kRedBlocks
+  double* red_part = nullptr;   // kRedSlots x kMaxRed partial sums
+  double* red_val = nullptr;    // kRedSlots results
   ddeig::PcgState* st = nullptr;
   double* hist = nullptr;   // device residual history
   int hist_cap = 0;
@@ -170,10 +209,10 @@ void launch_build_tables(const ddeig_problem* P, hipStream_t s);
 void launch_shift_table(const ddeig_problem* P, hipStream_t s);
 // y = T x (T one of the tables); dot != nullptr: partial sums of x.y into dot[0..kRedBlocks)
 void launch_stencil(const ddeig_problem* P, const double* tab, const double* x, double* y,
-                    double* dot, double* sum, hipStream_t s);
+                    Red* dot, Red* sum, hipStream_t s);
 // box operator (cell problem): y = T x on a periodic box, partials of x.y and sum(y)
 void launch_box_stencil(const ddeig_problem* P, const Box& bx, const double* tab, const double* x,
-                        double* y, double* dot, double* sum, hipStream_t s);
+                        double* y, Red* dot, Red* sum, hipStream_t s);
 
 // chain factorisation of a box: W[i] = S_i^{-1}; flag set on a non-positive pivot
 void chain_factor(ddeig_problem* P, const Box& bx, const double* tab, double* W, hipStream_t s);
@@ -187,7 +226,7 @@ void launch_restrict(const ddeig_problem* P, const double* r, int coarse, const 
                      hipStream_t s);
 void launch_local_solves(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 void launch_coarse_solve(const ddeig_problem* P, const PcgState* st, hipStream_t s);
-void launch_extend(const ddeig_problem* P, const double* r, double* z, int coarse, double* dot,
+void launch_extend(const ddeig_problem* P, const double* r, double* z, int coarse, Red* dot,
                    const PcgState* st, hipStream_t s);
 void launch_symmetrise(double* A, int N, hipStream_t s);
 void launch_split_inverse(const double* Ainv, int m, int ld, void* Ah, void* Al, hipStream_t s);
@@ -197,27 +236,24 @@ void launch_to_float(const double* src, float* dst, long n, hipStream_t s);
 void build_coarse_matrix(ddeig_problem* P, double* A0, hipStream_t s);
 
 // PCG / IPM vector kernels
+int red_grid(long work_items);
 void launch_resid_init(const ddeig_problem* P, const double* b, const double* q, double* r,
-                       double* part, hipStream_t s);
-void launch_pcg_init(const ddeig_problem* P, double rtol, const double* part, hipStream_t s);
-void launch_pcg_start(const ddeig_problem* P, const double* z, double* p, const double* part,
-                      hipStream_t s);
+                       Red& rr, hipStream_t s);
+void launch_finish_sum(const Red& r, hipStream_t s);
+void launch_pcg_init(const ddeig_problem* P, double rtol, Red rr, hipStream_t s);
+void launch_pcg_start(const ddeig_problem* P, const double* z, double* p, Red rz, hipStream_t s);
 void launch_pcg_update_xr(const ddeig_problem* P, double* x, const double* pvec,
-                          const double* qvec, double* r, const double* part_g, double* part_r,
-                          int k, hipStream_t s);
-void launch_pcg_check(const ddeig_problem* P, const double* part_r, int k, int maxit,
-                      hipStream_t s);
-void launch_pcg_update_p(const ddeig_problem* P, const double* z, double* pvec,
-                         const double* part_rz, int k, hipStream_t s);
+                          const double* qvec, double* r, Red g, Red& rr, int k, int maxit,
+                          hipStream_t s);
+void launch_pcg_check(const ddeig_problem* P, Red rr, int k, int maxit, hipStream_t s);
+void launch_pcg_update_p(const ddeig_problem* P, const double* z, double* pvec, Red rz, int k,
+                         hipStream_t s);
 void launch_fill(double* x, long n, double v, hipStream_t s);
 void launch_copy(double* dst, const double* src, long n, hipStream_t s);
-void launch_scale_copy(long n, double* dst, const double* src, const double* part,
-                       hipStream_t s);
+void launch_scale_copy(long n, double* dst, const double* src, Red nrm2, hipStream_t s);
 void launch_ipm_normalise(long n, const double* u, const double* Mu, double* x, const double* b,
-                          const double* part_uMu, const double* part_sum, double* part_dx,
-                          hipStream_t s);
-void launch_sum_partials(const double* part, double* out, hipStream_t s);
-void launch_dot(const double* x, const double* y, long n, double* part, hipStream_t s);
+                          Red uMu, Red sumMu, Red& dx, hipStream_t s);
+void launch_dot(const double* x, const double* y, long n, Red& out, hipStream_t s);
 
 void check_hip(hipError_t e, const char* what);
 

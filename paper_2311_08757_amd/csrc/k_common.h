@@ -24,11 +24,16 @@ __device__ inline double block_sum(double v) {
   return sh_red[kBlock / 64];
 }
 
-// Every workgroup reduces the kRedBlocks partial sums of a previous kernel
-// in the same fixed order, so all workgroups obtain the same value.
-__device__ inline double sum_partials(const double* part) {
+// One partial sum per block (see Red).
+__device__ inline void write_partial(double v, double* part) {
+  const double b = block_sum(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+
+// The sum of the np partials of a producing kernel, added in block order.
+__device__ inline double sum_partials(const double* part, int np) {
   double v = 0.0;
-  for (int i = threadIdx.x; i < kRedBlocks; i += kBlock) v += part[i];
+  for (int i = threadIdx.x; i < np; i += kBlock) v += part[i];
   return block_sum(v);
 }
 
@@ -92,6 +97,19 @@ __host__ __device__ inline double eval_V(const VSpec& v, const double* z) {
       out = 0.0;
   }
   return out;
+}
+
+__device__ inline FastDiv make_fastdiv_dev(unsigned d) {
+  FastDiv f{d, 0u, 0u};
+  unsigned s = 0;
+  while ((1ull << s) < d) ++s;
+  f.shift = s;
+  f.mul = (unsigned)(((1ull << 32) * ((1ull << s) - d)) / d + 1);
+  return f;
+}
+
+__device__ inline unsigned fdiv(unsigned n, const FastDiv& f) {
+  return (unsigned)(((unsigned long long)__umulhi(n, f.mul) + n) >> f.shift);
 }
 
 __device__ inline void unflatten(const Geo& g, long k, int& i0, int& i1, int& i2) {

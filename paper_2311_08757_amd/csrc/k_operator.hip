@@ -115,60 +115,71 @@ void launch_shift_table(const ddeig_problem* P, hipStream_t s) {
 }
 
 // y = T x over all interior unknowns of Omega_L; neighbours on the Dirichlet
-// boundary are eliminated (skipped).  Optional partial sums of x.y per block.
+// boundary are eliminated (skipped).  Work items are row segments of kBlock
+// consecutive x1 positions (one grid line of dims 1..D-1 each), visited
+// grid-stride by a fixed grid of kRedBlocks workgroups, so the index
+// arithmetic is one division per segment.  Optional partial sums of x.y and of y.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_stencil(Geo g, const double* __restrict__ T,
                                                     const double* __restrict__ x,
-                                                    double* __restrict__ y,
-                                                    double* __restrict__ dot,
-                                                    double* __restrict__ sum) {
+                                                    double* __restrict__ y, int use_dot, Red dot,
+                                                    int use_sum, Red sum) {
   double acc = 0.0, accs = 0.0;
-  const long N0 = g.N[0], N01 = (long)g.N[0] * g.N[1];
-  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < g.n;
-       k += (long)gridDim.x * blockDim.x) {
-    int i0, i1, i2;
-    unflatten(g, k, i0, i1, i2);
-    const long tn = table_node(g, i0, i1, i2);
+  const int N0 = g.N[0], N1 = g.N[1], N2 = g.N[2];
+  const long N01 = (long)N0 * N1;
+  const int segs = (N0 + kBlock - 1) / kBlock;
+  const long items = (long)segs * N1 * N2;
+  const long tsize = g.tsize;
+  for (long it = blockIdx.x; it < items; it += gridDim.x) {
+    const int line = (int)(it / segs);
+    const int i0 = (int)(it - (long)line * segs) * kBlock + threadIdx.x;
+    if (i0 >= N0) continue;
+    // line = i1r + N1 i2
+    const int i2 = D == 3 ? (int)fdiv((unsigned)line, g.fN1) : 0;
+    const int i1r = line - i2 * N1;
+    const long k = i0 + (long)N0 * line;
+    const int j0 = (int)((unsigned)(i0 + 1) - g.ne * fdiv((unsigned)(i0 + 1), g.fne));
+    int j1 = i1r;
+    if (g.isx[1]) j1 = (int)((unsigned)(i1r + 1) - g.ne * fdiv((unsigned)(i1r + 1), g.fne));
+    const long tn = j0 + (long)g.P[0] * (j1 + (long)g.P[1] * i2);
     double s = 0.0;
 #pragma unroll
     for (int t = 0; t < (D == 2 ? 9 : 27); ++t) {
-      // 2-D tables use taps 0..8 (dim 2 absent): the dim-2 offset is 0 there
       const int d0 = t % 3 - 1, d1 = (t / 3) % 3 - 1, d2 = (D == 2) ? 0 : t / 9 - 1;
-      const int j0 = i0 + d0, j1 = i1 + d1, j2 = i2 + d2;
-      const bool in = (j0 >= 0) && (j0 < g.N[0]) && (j1 >= 0) && (j1 < g.N[1]) &&
-                      (D == 2 || ((j2 >= 0) && (j2 < g.N[2])));
-      if (in) s += T[t * g.tsize + tn] * x[k + d0 + N0 * d1 + N01 * d2];
+      const bool in = (i0 + d0 >= 0) && (i0 + d0 < N0) && (i1r + d1 >= 0) && (i1r + d1 < N1) &&
+                      (D == 2 || ((i2 + d2 >= 0) && (i2 + d2 < N2)));
+      if (in) s += T[t * tsize + tn] * x[k + d0 + (long)N0 * d1 + N01 * d2];
     }
     y[k] = s;
     acc += x[k] * s;
     accs += s;
   }
-  if (dot) {
-    const double b = block_sum(acc);
-    if (threadIdx.x == 0) dot[blockIdx.x] = b;
-  }
-  if (sum) {
-    const double b = block_sum(accs);
-    if (threadIdx.x == 0) sum[blockIdx.x] = b;
-  }
+  if (use_dot) write_partial(acc, dot.part);
+  if (use_sum) write_partial(accs, sum.part);
 }
 
 void launch_stencil(const ddeig_problem* P, const double* tab, const double* x, double* y,
-                    double* dot, double* sum, hipStream_t s) {
+                    Red* dot, Red* sum, hipStream_t s) {
+  const long segs = (P->g.N[0] + kBlock - 1) / kBlock;
+  const long items = segs * P->g.N[1] * P->g.N[2];
+  const int blocks = (int)std::min<long>(items, kMaxRed);
+  const Red none{nullptr, 0, nullptr};
+  if (dot) dot->np = blocks;
+  if (sum) sum->np = blocks;
   if (P->g.D == 2)
-    hipLaunchKernelGGL(k_stencil<2>, dim3(kRedBlocks), dim3(kBlock), 0, s, P->g, tab, x, y, dot,
-                       sum);
+    hipLaunchKernelGGL(k_stencil<2>, dim3(blocks), dim3(kBlock), 0, s, P->g, tab, x, y,
+                       dot ? 1 : 0, dot ? *dot : none, sum ? 1 : 0, sum ? *sum : none);
   else
-    hipLaunchKernelGGL(k_stencil<3>, dim3(kRedBlocks), dim3(kBlock), 0, s, P->g, tab, x, y, dot,
-                       sum);
+    hipLaunchKernelGGL(k_stencil<3>, dim3(blocks), dim3(kBlock), 0, s, P->g, tab, x, y,
+                       dot ? 1 : 0, dot ? *dot : none, sum ? 1 : 0, sum ? *sum : none);
 }
 
 // Box operator with periodic wrap in the flagged dims (the cell problem of
 // eq:weak-form-cell-problem, periodic in x, Dirichlet in y).  The box vector
 // uses the box's natural order (dim 0 fastest).  Partials of x.y and sum(y).
 __global__ void k_box_stencil(Geo g, Box bx, const double* __restrict__ T,
-                              const double* __restrict__ x, double* __restrict__ y,
-                              double* __restrict__ dot, double* __restrict__ sum) {
+                              const double* __restrict__ x, double* __restrict__ y, int use_dot,
+                              Red dot, int use_sum, Red sum) {
   const long nb = (long)bx.m[0] * bx.m[1] * bx.m[2];
   double acc = 0.0, accs = 0.0;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nb;
@@ -194,20 +205,19 @@ __global__ void k_box_stencil(Geo g, Box bx, const double* __restrict__ T,
     acc += x[e] * s;
     accs += s;
   }
-  if (dot) {
-    const double b = block_sum(acc);
-    if (threadIdx.x == 0) dot[blockIdx.x] = b;
-  }
-  if (sum) {
-    const double b = block_sum(accs);
-    if (threadIdx.x == 0) sum[blockIdx.x] = b;
-  }
+  if (use_dot) write_partial(acc, dot.part);
+  if (use_sum) write_partial(accs, sum.part);
 }
 
 void launch_box_stencil(const ddeig_problem* P, const Box& bx, const double* tab, const double* x,
-                        double* y, double* dot, double* sum, hipStream_t s) {
-  hipLaunchKernelGGL(k_box_stencil, dim3(kRedBlocks), dim3(kBlock), 0, s, P->g, bx, tab, x, y,
-                     dot, sum);
+                        double* y, Red* dot, Red* sum, hipStream_t s) {
+  const long nb = (long)bx.m[0] * bx.m[1] * bx.m[2];
+  const int blocks = red_grid(nb);
+  const Red none{nullptr, 0, nullptr};
+  if (dot) dot->np = blocks;
+  if (sum) sum->np = blocks;
+  hipLaunchKernelGGL(k_box_stencil, dim3(blocks), dim3(kBlock), 0, s, P->g, bx, tab, x, y,
+                     dot ? 1 : 0, dot ? *dot : none, sum ? 1 : 0, sum ? *sum : none);
 }
 
 }  // namespace ddeig

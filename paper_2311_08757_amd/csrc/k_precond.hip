@@ -73,62 +73,96 @@ __device__ inline int sub_index(const Geo& g, const int* c) {
   return g.p == 1 ? c[0] - 1 : (c[0] - 1) + g.L * (c[1] - 1);
 }
 
-// Gather r into the subdomain batches (box natural order) and, with the
-// coarse level, c_sub = sum_k D_sub(k) psi_ext(k) r(k)  (R_0 r).
-__global__ void __launch_bounds__(kBlock) k_restrict(Geo g, int delta, int pu, int coarse,
+// Partition-of-unity weight of cell c at a node from the per-axis covering
+// tables: the product of the per-axis factors, except for the distance-based
+// weights with two expanding axes, which are not separable (pu_weight).
+__device__ inline double cover_weight(const Geo& g, int delta, int pu, const XCover* const* xc,
+                                      const int* c, const int* i, const int* which) {
+  if (pu == 1 && g.p == 2) return pu_weight(g, delta, pu, c, i);
+  double w = xc[0][i[0]].w[which[0]];
+  if (g.p == 2) w *= xc[1][i[1]].w[which[1]];
+  return w;
+}
+
+// Gather r into the subdomain batches (box natural order; bf16 hi/lo rows for
+// dense classes) and, with the coarse level, the partial sums of
+// c_sub = sum_k D_sub(k) psi_ext(k) r(k) (R_0 r) over this workgroup's share
+// of the box (grid: subdomain x rb row blocks).
+__global__ void __launch_bounds__(kBlock) k_restrict(Geo g, int delta, int pu, int coarse, int rb,
                                                      const PcgState* __restrict__ st,
                                                      const double* __restrict__ r,
                                                      const TypeDev* __restrict__ types,
                                                      const SubDev* __restrict__ subs,
+                                                     const XCover* __restrict__ xc0,
+                                                     const XCover* __restrict__ xc1,
                                                      const double* __restrict__ psi,
-                                                     double* __restrict__ crhs) {
+                                                     double* __restrict__ cpart) {
   if (st != nullptr && st->done) return;
-  const SubDev sd = subs[blockIdx.x];
+  const int sid = blockIdx.x / rb, part = blockIdx.x - sid * rb;
+  const SubDev sd = subs[sid];
   const TypeDev td = types[sd.type];
-  const long mtot = (long)td.m[0] * td.m[1] * td.m[2];
-  double* dst = td.batch + (long)sd.slot * mtot;
+  const int m0 = td.m[0];
+  const int nl = td.m[1] * td.m[2];
+  const int l0 = (int)((long)nl * part / rb), l1 = (int)((long)nl * (part + 1) / rb);
+  const int f1 = (l1 - l0) * m0;
+  const FastDiv fm0 = make_fastdiv_dev(m0);
+  const XCover* xc[2] = {xc0, xc1};
+  double* dst = td.batch + (long)sd.slot * td.nch * td.b;
   double acc = 0.0;
-  for (long e = threadIdx.x; e < mtot; e += blockDim.x) {
-    const int u0 = (int)(e % td.m[0]);
-    const int u1 = (int)((e / td.m[0]) % td.m[1]);
-    const int u2 = (int)(e / ((long)td.m[0] * td.m[1]));
+  for (int f = threadIdx.x; f < f1; f += blockDim.x) {
+    const int ll = (int)fdiv((unsigned)f, fm0);
+    const int u0 = f - ll * m0;
+    const int line = l0 + ll;                 // u1 + m1 u2
+    const int u2 = line / td.m[1];
+    const int u1 = line - u2 * td.m[1];
     const int i[3] = {sd.o[0] + u0, sd.o[1] + u1, sd.o[2] + u2};
     const long k = i[0] + (long)g.N[0] * (i[1] + (long)g.N[1] * i[2]);
+    const int e = u0 + m0 * line;
     const double rv = r[k];
     if (td.dense) {
-      __bf16 hi, lo;
-      hi = (__bf16)(float)rv;
-      lo = (__bf16)(float)(rv - (double)(float)hi);
+      const __bf16 hi = (__bf16)(float)rv;
+      const __bf16 lo = (__bf16)(float)(rv - (double)(float)hi);
       td.Rh[(long)sd.slot * td.ld + e] = hi;
       td.Rl[(long)sd.slot * td.ld + e] = lo;
     } else {
       dst[e] = rv;
     }
-    if (coarse) acc += pu_weight(g, delta, pu, sd.c, i) * psi[table_node(g, i[0], i[1], i[2])] * rv;
+    if (coarse) {
+      int which[2] = {0, 0};
+      for (int a = 0; a < g.p; ++a) which[a] = xc[a][i[a]].c[0] == sd.c[a] ? 0 : 1;
+      acc += cover_weight(g, delta, pu, xc, sd.c, i, which) *
+             psi[table_node(g, i[0], i[1], i[2])] * rv;
+    }
   }
   if (coarse) {
     const double s = block_sum(acc);
-    if (threadIdx.x == 0) crhs[blockIdx.x] = s;
+    if (threadIdx.x == 0) cpart[blockIdx.x] = s;
   }
 }
 
 void launch_restrict(const ddeig_problem* P, const double* r, int coarse, const PcgState* st,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_restrict, dim3(P->nsub), dim3(kBlock), 0, s, P->g, P->delta, P->opt.pu,
-                     coarse, st, r, P->dTypes, P->dSubs, P->psi, P->crhs);
+  hipLaunchKernelGGL(k_restrict, dim3(P->nsub * P->restrict_rb), dim3(kBlock), 0, s, P->g,
+                     P->delta, P->opt.pu, coarse, P->restrict_rb, st, r, P->dTypes, P->dSubs,
+                     P->dXC[0], P->dXC[1], P->psi, P->crhs);
 }
 
 // y0 = A0^{-1} c with the dense symmetric inverse: one wave64 per row, lanes
-// stride the row (coalesced), fixed-order shuffle reduction.
-__global__ void k_coarse_solve(int N, const PcgState* __restrict__ st,
-                               const double* __restrict__ A0inv, const double* __restrict__ c,
+// stride the row (coalesced), fixed-order shuffle reduction; c_j is the sum of
+// the rb restriction partials of subdomain j in order.
+__global__ void k_coarse_solve(int N, int rb, const PcgState* __restrict__ st,
+                               const double* __restrict__ A0inv, const double* __restrict__ cpart,
                                double* __restrict__ y) {
   if (st != nullptr && st->done) return;
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   if (row >= N) return;
   double acc = 0.0;
-  for (int j = lane; j < N; j += 64) acc += A0inv[(long)row * N + j] * c[j];
+  for (int j = lane; j < N; j += 64) {
+    double c = 0.0;
+    for (int q = 0; q < rb; ++q) c += cpart[(long)j * rb + q];
+    acc += A0inv[(long)row * N + j] * c;
+  }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) y[row] = acc;
 }
@@ -136,61 +170,83 @@ __global__ void k_coarse_solve(int N, const PcgState* __restrict__ st,
 void launch_coarse_solve(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
   const int rows_per_block = kBlock / 64;
   hipLaunchKernelGGL(k_coarse_solve, dim3((P->nsub + rows_per_block - 1) / rows_per_block),
-                     dim3(kBlock), 0, s, P->nsub, st, P->A0inv, P->crhs, P->cy);
+                     dim3(kBlock), 0, s, P->nsub, P->restrict_rb, st, P->A0inv, P->crhs, P->cy);
 }
 
-// z = sum_c R_c^T y_c (+ R_0^T y0), partials of r.z.
+// z = sum_c R_c^T y_c (+ R_0^T y0), partials of r.z.  Work items are row
+// segments of kBlock x1 positions (as in the stencil); the covering cells of
+// a node come from the per-axis tables and are summed in a fixed order.
 __global__ void __launch_bounds__(kBlock) k_extend(Geo g, int delta, int pu, int coarse,
                                                    const PcgState* __restrict__ st,
                                                    const TypeDev* __restrict__ types,
                                                    const SubDev* __restrict__ subs,
+                                                   const XCover* __restrict__ xc0,
+                                                   const XCover* __restrict__ xc1,
                                                    const double* __restrict__ psi,
                                                    const double* __restrict__ y0,
                                                    const double* __restrict__ r,
-                                                   double* __restrict__ z,
-                                                   double* __restrict__ dot) {
+                                                   double* __restrict__ z, int use_dot,
+                                                   Red dot) {
   if (st != nullptr && st->done) return;
+  const XCover* xc[2] = {xc0, xc1};
   double acc = 0.0;
-  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < g.n;
-       k += (long)gridDim.x * blockDim.x) {
-    int i[3];
-    unflatten(g, k, i[0], i[1], i[2]);
-    int lo[2] = {1, 1}, hi[2] = {1, 1};
-    for (int a = 0; a < g.p; ++a) covering(i[a] + 1, g.ne, g.L, delta, lo[a], hi[a]);
+  const int N0 = g.N[0], N1 = g.N[1];
+  const int segs = (N0 + kBlock - 1) / kBlock;
+  const long items = (long)segs * N1 * g.N[2];
+  for (long it = blockIdx.x; it < items; it += gridDim.x) {
+    const int line = (int)(it / segs);
+    const int i0 = (int)(it - (long)line * segs) * kBlock + threadIdx.x;
+    if (i0 >= N0) continue;
+    const int i2 = g.D == 3 ? (int)fdiv((unsigned)line, g.fN1) : 0;
+    const int i[3] = {i0, line - i2 * N1, i2};
+    const long k = i0 + (long)N0 * line;
+    const XCover a0 = xc0[i0];
+    XCover a1;
+    a1.c[0] = 1; a1.c[1] = 0; a1.u[0] = i[1]; a1.u[1] = 0; a1.w[0] = 1.0; a1.w[1] = 0.0;
+    if (g.p == 2) a1 = xc1[i[1]];
     double zl = 0.0, zc = 0.0;
-    for (int c1 = lo[1]; c1 <= hi[1]; ++c1)
-      for (int c0 = lo[0]; c0 <= hi[0]; ++c0) {
-        const int c[3] = {c0, c1, 0};
+    for (int q1 = 0; q1 < 2; ++q1) {
+      if (a1.c[q1] == 0) continue;
+      for (int q0 = 0; q0 < 2; ++q0) {
+        if (a0.c[q0] == 0) continue;
+        const int c[3] = {a0.c[q0], g.p == 2 ? a1.c[q1] : 0, 0};
         const int sid = sub_index(g, c);
         const SubDev sd = subs[sid];
         const TypeDev td = types[sd.type];
-        const long e = (i[0] - sd.o[0]) +
-                       (long)td.m[0] * ((i[1] - sd.o[1]) + (long)td.m[1] * (i[2] - sd.o[2]));
+        const int u1 = g.p == 2 ? a1.u[q1] : i[1];
+        const long e = a0.u[q0] + (long)td.m[0] * (u1 + (long)td.m[1] * (i2 - sd.o[2]));
         if (td.dense) {
           const float* zp = td.Z + (long)sd.slot * td.ld + e;
           float zs = 0.0f;
           for (int sp = 0; sp < td.ksplit; ++sp) zs += zp[sp * td.zsplit];
           zl += (double)zs;
         } else {
-          zl += td.batch[(long)sd.slot * td.m[0] * td.m[1] * td.m[2] + e];
+          zl += td.batch[(long)sd.slot * td.nch * td.b + e];
         }
-        if (coarse) zc += pu_weight(g, delta, pu, c, i) * y0[sid];
+        if (coarse) {
+          const int which[2] = {q0, q1};
+          zc += cover_weight(g, delta, pu, xc, c, i, which) * y0[sid];
+        }
       }
+    }
     double zv = zl;
     if (coarse) zv += psi[table_node(g, i[0], i[1], i[2])] * zc;
     z[k] = zv;
     acc += r[k] * zv;
   }
-  if (dot) {
-    const double s = block_sum(acc);
-    if (threadIdx.x == 0) dot[blockIdx.x] = s;
-  }
+  if (use_dot) write_partial(acc, dot.part);
 }
 
-void launch_extend(const ddeig_problem* P, const double* r, double* z, int coarse, double* dot,
+void launch_extend(const ddeig_problem* P, const double* r, double* z, int coarse, Red* dot,
                    const PcgState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_extend, dim3(kRedBlocks), dim3(kBlock), 0, s, P->g, P->delta, P->opt.pu,
-                     coarse, st, P->dTypes, P->dSubs, P->psi, P->cy, r, z, dot);
+  const long segs = (P->g.N[0] + kBlock - 1) / kBlock;
+  const long items = segs * P->g.N[1] * P->g.N[2];
+  const int blocks = (int)std::min<long>(items, kMaxRed);
+  const Red none{nullptr, 0, nullptr};
+  if (dot) dot->np = blocks;
+  hipLaunchKernelGGL(k_extend, dim3(blocks), dim3(kBlock), 0, s, P->g, P->delta, P->opt.pu,
+                     coarse, st, P->dTypes, P->dSubs, P->dXC[0], P->dXC[1], P->psi, P->cy, r, z,
+                     dot ? 1 : 0, dot ? *dot : none);
 }
 
 // phi_c(k) = D_c(k) psi_ext(k) on box c, 0 elsewhere (column c of R_0^T).

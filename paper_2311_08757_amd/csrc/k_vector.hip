@@ -1,17 +1,23 @@
 // Vector kernels of preconditioned CG (§3 eq:cg-energy-norm-error-reduction,
 // stopping rule of §4.1) and of the shifted inverse iteration with
-// B-normalisation (§2).  Scalars stay on the device: each kernel that needs a
-// global sum re-reduces the fixed-size partial sums of the kernel before it,
-// so no host round trip is needed inside an iteration and sums are
-// deterministic.  After convergence or breakdown the state's `done` flag
+// B-normalisation (§2).  Scalars stay on the device: a kernel that needs a
+// global sum adds the per-block partials of the kernel before it in a fixed
+// order (Red), so no host round trip is needed inside an iteration and sums
+// are deterministic.  After convergence or breakdown the state's `done` flag
 // turns every later iteration kernel into a no-op, so the host can queue
 // several iterations between checks.
 #include "k_common.h"
 
 namespace ddeig {
 
+// Grid of a reducing elementwise kernel: two elements per thread, at most kMaxRed blocks.
+int red_grid(long work) {
+  const long b = (work + 2L * kBlock - 1) / (2L * kBlock);
+  return (int)std::max<long>(1, std::min<long>(b, kMaxRed));
+}
+
 __global__ void k_resid_init(long n, const double* __restrict__ b, const double* __restrict__ q,
-                             double* __restrict__ r, double* __restrict__ part) {
+                             double* __restrict__ r, Red rr) {
   double acc = 0.0;
   for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n;
        k += (long)gridDim.x * blockDim.x) {
@@ -19,18 +25,26 @@ __global__ void k_resid_init(long n, const double* __restrict__ b, const double*
     r[k] = v;
     acc += v * v;
   }
-  const double s = block_sum(acc);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  write_partial(acc, rr.part);
 }
 
 void launch_resid_init(const ddeig_problem* P, const double* b, const double* q, double* r,
-                       double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_resid_init, dim3(kRedBlocks), dim3(kBlock), 0, s, P->g.n, b, q, r, part);
+                       Red& rr, hipStream_t s) {
+  rr.np = red_grid(P->g.n);
+  hipLaunchKernelGGL(k_resid_init, dim3(rr.np), dim3(kBlock), 0, s, P->g.n, b, q, r, rr);
 }
 
-__global__ void k_pcg_init(PcgState* st, double rtol, const double* __restrict__ part,
-                           double* __restrict__ hist) {
-  const double r0n2 = sum_partials(part);
+__global__ void k_finish_sum(Red r) {
+  const double v = sum_partials(r.part, r.np);
+  if (threadIdx.x == 0) *r.val = v;
+}
+
+void launch_finish_sum(const Red& r, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_sum, dim3(1), dim3(kBlock), 0, s, r);
+}
+
+__global__ void k_pcg_init(PcgState* st, double rtol, Red rr, double* __restrict__ hist) {
+  const double r0n2 = sum_partials(rr.part, rr.np);
   if (threadIdx.x == 0) {
     st->r0n2 = r0n2;
     st->tol2 = rtol * rtol * r0n2;
@@ -42,14 +56,14 @@ __global__ void k_pcg_init(PcgState* st, double rtol, const double* __restrict__
   }
 }
 
-void launch_pcg_init(const ddeig_problem* P, double rtol, const double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(kBlock), 0, s, P->st, rtol, part, P->hist);
+void launch_pcg_init(const ddeig_problem* P, double rtol, Red rr, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(kBlock), 0, s, P->st, rtol, rr, P->hist);
 }
 
 // p = z, rho_0 = r.z
 __global__ void k_pcg_start(long n, PcgState* st, const double* __restrict__ z,
-                            double* __restrict__ p, const double* __restrict__ part) {
-  const double rho = sum_partials(part);
+                            double* __restrict__ p, Red rz) {
+  const double rho = sum_partials(rz.part, rz.np);
   if (st->done) return;
   if (!(rho > 0.0)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 3;
@@ -61,18 +75,17 @@ __global__ void k_pcg_start(long n, PcgState* st, const double* __restrict__ z,
     p[k] = z[k];
 }
 
-void launch_pcg_start(const ddeig_problem* P, const double* z, double* p, const double* part,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_start, dim3(kRedBlocks), dim3(kBlock), 0, s, P->g.n, P->st, z, p, part);
+void launch_pcg_start(const ddeig_problem* P, const double* z, double* p, Red rz, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_start, dim3(red_grid(P->g.n)), dim3(kBlock), 0, s, P->g.n, P->st, z,
+                     p, rz);
 }
 
 // Iteration k: alpha = rho_{k-1} / (p.q); x += alpha p; r -= alpha q; partials of ||r||^2.
 __global__ void k_pcg_update_xr(long n, PcgState* st, int k, double* __restrict__ x,
                                 const double* __restrict__ p, const double* __restrict__ q,
-                                double* __restrict__ r, const double* __restrict__ part_g,
-                                double* __restrict__ part_r) {
+                                double* __restrict__ r, Red g, Red rr) {
   if (st->done) return;
-  const double gamma = sum_partials(part_g);
+  const double gamma = sum_partials(g.part, g.np);
   if (!(gamma > 0.0)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       st->done = 2;
@@ -89,22 +102,23 @@ __global__ void k_pcg_update_xr(long n, PcgState* st, int k, double* __restrict_
     r[i] = rv;
     acc += rv * rv;
   }
-  const double s = block_sum(acc);
-  if (threadIdx.x == 0) part_r[blockIdx.x] = s;
+  write_partial(acc, rr.part);
 }
 
 void launch_pcg_update_xr(const ddeig_problem* P, double* x, const double* pvec,
-                          const double* qvec, double* r, const double* part_g, double* part_r,
-                          int k, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_update_xr, dim3(kRedBlocks), dim3(kBlock), 0, s, P->g.n, P->st, k, x,
-                     pvec, qvec, r, part_g, part_r);
+                          const double* qvec, double* r, Red g, Red& rr, int k, int maxit,
+                          hipStream_t s) {
+  (void)maxit;
+  rr.np = red_grid(P->g.n);
+  hipLaunchKernelGGL(k_pcg_update_xr, dim3(rr.np), dim3(kBlock), 0, s, P->g.n, P->st, k, x, pvec,
+                     qvec, r, g, rr);
 }
 
-// Convergence test ||r_k|| <= rtol ||r_0|| after the update of iteration k.
-__global__ void k_pcg_check(PcgState* st, int k, int maxit, const double* __restrict__ part_r,
-                            double* __restrict__ hist, int hist_cap) {
+// Stopping test ||r_k|| <= rtol ||r_0|| after the update of iteration k; history.
+__global__ void k_pcg_check(PcgState* st, int k, int maxit, Red rr, double* __restrict__ hist,
+                            int hist_cap) {
   if (st->done) return;
-  const double rn2 = sum_partials(part_r);
+  const double rn2 = sum_partials(rr.part, rr.np);
   if (threadIdx.x == 0) {
     st->relres = sqrt(rn2 / st->r0n2);
     if (hist && k < hist_cap) hist[k] = st->relres;
@@ -114,17 +128,16 @@ __global__ void k_pcg_check(PcgState* st, int k, int maxit, const double* __rest
   }
 }
 
-void launch_pcg_check(const ddeig_problem* P, const double* part_r, int k, int maxit,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(kBlock), 0, s, P->st, k, maxit, part_r, P->hist,
+void launch_pcg_check(const ddeig_problem* P, Red rr, int k, int maxit, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(kBlock), 0, s, P->st, k, maxit, rr, P->hist,
                      P->hist_cap);
 }
 
 // beta = rho_k / rho_{k-1}; p = z + beta p.
 __global__ void k_pcg_update_p(long n, PcgState* st, int k, const double* __restrict__ z,
-                               double* __restrict__ p, const double* __restrict__ part_rz) {
+                               double* __restrict__ p, Red rz) {
+  const double rho = sum_partials(rz.part, rz.np);
   if (st->done) return;
-  const double rho = sum_partials(part_rz);
   if (!(rho > 0.0)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 3;
     return;
@@ -136,10 +149,10 @@ __global__ void k_pcg_update_p(long n, PcgState* st, int k, const double* __rest
   if (blockIdx.x == 0 && threadIdx.x == 0) st->rho[k & 1] = rho;
 }
 
-void launch_pcg_update_p(const ddeig_problem* P, const double* z, double* pvec,
-                         const double* part_rz, int k, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_update_p, dim3(kRedBlocks), dim3(kBlock), 0, s, P->g.n, P->st, k, z,
-                     pvec, part_rz);
+void launch_pcg_update_p(const ddeig_problem* P, const double* z, double* pvec, Red rz, int k,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_update_p, dim3(red_grid(P->g.n)), dim3(kBlock), 0, s, P->g.n, P->st,
+                     k, z, pvec, rz);
 }
 
 __global__ void k_fill(double* x, long n, double v) {
@@ -164,33 +177,28 @@ void launch_copy(double* dst, const double* src, long n, hipStream_t s) {
   if (blocks > 0) hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(kBlock), 0, s, dst, src, n);
 }
 
-// dst = src / sqrt(sum(part))  (mode 0: M-normalisation of a start vector)
+// dst = src / sqrt(nrm2)  (M-normalisation of a start vector)
 __global__ void k_scale_copy(long n, double* __restrict__ dst, const double* __restrict__ src,
-                             const double* __restrict__ part) {
-  const double nrm2 = sum_partials(part);
-  const double sc = 1.0 / sqrt(nrm2);
+                             Red nrm2) {
+  const double sc = 1.0 / sqrt(sum_partials(nrm2.part, nrm2.np));
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
        i += (long)gridDim.x * blockDim.x)
     dst[i] = src[i] * sc;
 }
 
-void launch_scale_copy(long n, double* dst, const double* src, const double* part,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_copy, dim3(kRedBlocks), dim3(kBlock), 0, s, n, dst, src, part);
+void launch_scale_copy(long n, double* dst, const double* src, Red nrm2, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(red_grid(n)), dim3(kBlock), 0, s, n, dst, src, nrm2);
 }
 
 // Inverse-iteration normalisation (§2): with u = A_sigma^{-1} b, b = M x,
-// Mu = M u, scale = sign(1^T M u) / sqrt(u^T M u): x_new = scale u and the
-// partials of ||x_new - x||_M^2 = (x_new - x)^T (scale Mu - b); x is
-// overwritten by x_new.
+// Mu = M u, scale = sign(1^T M u) / sqrt(u^T M u): x_new = scale u and
+// ||x_new - x||_M^2 = (x_new - x)^T (scale Mu - b); x is overwritten by x_new.
 __global__ void k_ipm_normalise(long n, const double* __restrict__ u, const double* __restrict__ Mu,
-                                double* __restrict__ x, const double* __restrict__ b,
-                                const double* __restrict__ part_uMu,
-                                const double* __restrict__ part_sum,
-                                double* __restrict__ part_dx) {
-  const double uMu = sum_partials(part_uMu);
-  const double ssum = sum_partials(part_sum);
-  const double sc = (ssum < 0.0 ? -1.0 : 1.0) / sqrt(uMu);
+                                double* __restrict__ x, const double* __restrict__ b, Red uMu,
+                                Red sumMu, Red dx) {
+  const double ssum = sum_partials(sumMu.part, sumMu.np);
+  const double uu = sum_partials(uMu.part, uMu.np);
+  const double sc = (ssum < 0.0 ? -1.0 : 1.0) / sqrt(uu);
   double acc = 0.0;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
        i += (long)gridDim.x * blockDim.x) {
@@ -199,43 +207,28 @@ __global__ void k_ipm_normalise(long n, const double* __restrict__ u, const doub
     acc += d * (sc * Mu[i] - b[i]);
     x[i] = xn;
   }
-  const double s = block_sum(acc);
-  if (threadIdx.x == 0) part_dx[blockIdx.x] = s;
+  write_partial(acc, dx.part);
 }
 
 void launch_ipm_normalise(long n, const double* u, const double* Mu, double* x, const double* b,
-                          const double* part_uMu, const double* part_sum, double* part_dx,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_ipm_normalise, dim3(kRedBlocks), dim3(kBlock), 0, s, n, u, Mu, x, b,
-                     part_uMu, part_sum, part_dx);
+                          Red uMu, Red sumMu, Red& dx, hipStream_t s) {
+  dx.np = red_grid(n);
+  hipLaunchKernelGGL(k_ipm_normalise, dim3(dx.np), dim3(kBlock), 0, s, n, u, Mu, x, b, uMu,
+                     sumMu, dx);
 }
 
-__global__ void k_sum_partials(const double* __restrict__ part, double* __restrict__ out) {
-  const double v = sum_partials(part);
-  if (threadIdx.x == 0) *out = v;
-}
-
-void launch_sum_partials(const double* part, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, part, out);
-}
-
-__global__ void k_dot(const double* __restrict__ x, const double* __restrict__ y, long n,
-                      double* __restrict__ part) {
+__global__ void k_dot(const double* __restrict__ x, const double* __restrict__ y, long n, Red out) {
   double acc = 0.0;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
        i += (long)gridDim.x * blockDim.x)
     acc += x[i] * y[i];
-  const double s = block_sum(acc);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  write_partial(acc, out.part);
 }
 
-void launch_dot(const double* x, const double* y, long n, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_dot, dim3(kRedBlocks), dim3(kBlock), 0, s, x, y, n, part);
+void launch_dot(const double* x, const double* y, long n, Red& out, hipStream_t s) {
+  out.np = red_grid(n);
+  hipLaunchKernelGGL(k_dot, dim3(out.np), dim3(kBlock), 0, s, x, y, n, out);
 }
-
-}  // namespace ddeig
-
-namespace ddeig {
 
 __global__ void k_to_float(const double* __restrict__ s, float* __restrict__ d, long n) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
