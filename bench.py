@@ -33,7 +33,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--local-prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--local-prec", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-sample", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
@@ -178,7 +178,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f64 (f32 local solves)",
-                  "bf16x3": "f64 (bf16x3 MFMA local solves, f32 accumulate)"}[args.local_prec],
+                  "bf16x3": "f64 (bf16x3 MFMA local solves, f32 accumulate)",
+                  "bf16": "f64 (bf16 MFMA local solves, f32 accumulate)"}[args.local_prec],
         "data": "synthetic (seeded periodic potential)",
         "config": {"workload": cfg["name"], "p": cfg["p"], "q": cfg["q"], "L": cfg["L"],
                    "h": f"1/{cfg['ne']}", "overlap": cfg["delta"], "n_dof": n,

@@ -98,7 +98,10 @@ typedef struct {
   int coarse;      /* 0 one-level AS (eq:dd-preconditioners), 1 two-level AS with the
                       PerFact coarse space (eq:two-level-preconditioners,
                       def:algebraic-perfact-coarse-space) */
-  int local_prec;  /* local subdomain solves: 0 FP64, 1 FP32 factors with FP32 arithmetic */
+  int local_prec;  /* local subdomain solves: 0 FP64 block-chain factors, 1 FP32 factors with
+                      FP32 arithmetic, 2 dense inverses as bf16 hi/lo pairs applied on MFMA
+                      (bf16x3, FP32 accumulation), 3 dense inverses in bf16 (two MFMA
+                      products, FP32 accumulation); the outer CG is FP64 in every case */
   int batch_iters; /* PCG iterations queued between host convergence checks (0: default 8) */
 } ddeig_options;
 

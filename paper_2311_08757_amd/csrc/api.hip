@@ -120,8 +120,8 @@ void factor_types(ddeig_problem* P) {
       launch_to_float(t.W, t.W32, (long)t.box.nch * t.box.b * t.box.b, P->stream);
   }
   check_launch("local factorisation");
-  if (P->opt.local_prec == 2) {
-    // dense inverses: chain solves of the identity columns, then bf16 hi/lo split
+  if (P->opt.local_prec >= 2) {
+    // dense inverses: chain solves of the identity columns, then bf16 hi (/lo) split
     for (auto& t : P->types) {
       const int m = t.box.nch * t.box.b;
       double* Ainv = dalloc<double>(P, (size_t)m * m);
@@ -153,6 +153,7 @@ ddeig_status finish_shift(ddeig_problem* P) {
   factor_types(P);
   if (read_flag(P)) return set_error(DDEIG_ENOTSPD, "a local matrix A_sigma,i is not positive definite");
   if (P->opt.coarse) {
+    launch_coarse_phi(P, P->stream);
     build_coarse_matrix(P, P->A0inv, P->stream);
     launch_gj_invert(P, P->A0inv, P->nsub, P->stream);
     launch_symmetrise(P->A0inv, P->nsub, P->stream);
@@ -163,12 +164,30 @@ ddeig_status finish_shift(ddeig_problem* P) {
   return DDEIG_OK;
 }
 
-void precond_apply(ddeig_problem* P, const double* r, double* z, Red* dot,
-                   const PcgState* st) {
+// restrict -> {local solves | boundary GEMV + coarse solve on the second
+// stream} -> extend.  chk (nullable) folds the PCG stopping test into the
+// restriction.
+void precond_apply(ddeig_problem* P, const double* r, double* z, Red* dot, PcgState* st,
+                   const CheckArgs* chk = nullptr) {
   const int coarse = P->opt.coarse;
-  launch_restrict(P, r, coarse, st, P->stream);
+  CheckArgs off{};
+  off.on = 0;
+  launch_restrict(P, r, coarse, st, chk ? *chk : off, P->stream);
+  const bool side = coarse || (P->opt.local_prec >= 2 && P->ngemv > 0);
+  if (side) {
+    check_hip(hipEventRecord(P->ev_fork, P->stream), "record fork");
+    check_hip(hipStreamWaitEvent(P->aux, P->ev_fork, 0), "wait fork");
+  }
   launch_local_solves(P, st, P->stream);
-  if (coarse) launch_coarse_solve(P, st, P->stream);
+  if (P->opt.local_prec >= 2) launch_dense_gemv(P, st, P->aux);
+  if (coarse) {
+    launch_coarse_rhs(P, r, st, P->aux);
+    launch_coarse_solve(P, st, P->aux);
+  }
+  if (side) {
+    check_hip(hipEventRecord(P->ev_join, P->aux), "record join");
+    check_hip(hipStreamWaitEvent(P->stream, P->ev_join, 0), "wait join");
+  }
   launch_extend(P, r, z, coarse, dot, st, P->stream);
 }
 
@@ -200,8 +219,8 @@ PcgOut pcg_run(ddeig_problem* P, const double* b, double* x, double rtol, int ma
     for (++k; k <= kend; ++k) {
       launch_stencil(P, P->tabAs, P->p, P->q, &g, nullptr, s);
       launch_pcg_update_xr(P, x, P->p, P->q, P->r, g, rr, k, maxit, s);
-      launch_pcg_check(P, rr, k, maxit, s);
-      precond_apply(P, P->r, P->z, &rz, P->st);
+      const CheckArgs chk{1, k, maxit, P->hist_cap, rr, P->hist};
+      precond_apply(P, P->r, P->z, &rz, P->st, &chk);
       launch_pcg_update_p(P, P->z, P->p, rz, k, s);
     }
     --k;
@@ -297,7 +316,7 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
   ddeig_options o{0, 1, 0, 8};
   if (opts) o = *opts;
   if (o.pu < 0 || o.pu > 1 || o.coarse < 0 || o.coarse > 1 || o.local_prec < 0 ||
-      o.local_prec > 2 || o.batch_iters < 0)
+      o.local_prec > 3 || o.batch_iters < 0)
     return set_error(DDEIG_EINVAL, "invalid options");
 
   ddeig::VSpec vs{};
@@ -424,21 +443,28 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
     }
     int maxb = 0;
     std::vector<ddeig::TypeDev> tdev(P->types.size());
-    const bool dense = o.local_prec == 2;
-    // dense classes: split K so that the grouped GEMM has enough workgroups
+    const bool dense = o.local_prec >= 2;
+    // dense classes: 128 x 128 MFMA tiles for classes with more than kGemvMax
+    // members, K split so that the grouped GEMM has enough workgroups; the
+    // small (boundary) classes use the streaming matrix-vector kernel
+    auto big = [](const ddeig::SubType& T) { return T.nmem > ddeig::kGemvMax; };
     if (dense) {
       long tiles = 0;
       int minkb = 1 << 30;
       for (auto& T : P->types) {
         const int m = T.box.nch * T.box.b;
         T.ld = (m + 127) / 128 * 128;
-        T.mp = (T.nmem + 127) / 128 * 128;
-        tiles += (long)(T.mp / 128) * (T.ld / 128);
-        minkb = std::min(minkb, T.ld / 32);
+        T.mp = big(T) ? (T.nmem + 127) / 128 * 128 : ddeig::kGemvMax;
+        if (big(T)) {
+          tiles += (long)(T.mp / 128) * (T.ld / 128);
+          minkb = std::min(minkb, T.ld / 32);
+        }
       }
-      P->ksplit = (int)std::max<long>(1, std::min<long>(std::min(8, minkb), (384 + tiles - 1) / tiles));
+      if (tiles > 0)
+        P->ksplit = (int)std::max<long>(1, std::min<long>(std::min(3, minkb), (256 + tiles - 1) / tiles));
     }
     std::vector<ddeig::GemmTile> tiles;
+    std::vector<ddeig::GemvRows> gemv;
     std::vector<ddeig::GemmType> gtypes;
     for (size_t t = 0; t < P->types.size(); ++t) {
       auto& T = P->types[t];
@@ -455,7 +481,7 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
       if (dense) {
         const size_t aa = (size_t)T.ld * T.ld, rr = (size_t)T.mp * T.ld;
         T.Ah = dalloc<__bf16>(P, aa);
-        T.Al = dalloc<__bf16>(P, aa);
+        T.Al = o.local_prec == 2 ? dalloc<__bf16>(P, aa) : nullptr;
         T.Rh = dalloc<__bf16>(P, rr);
         T.Rl = dalloc<__bf16>(P, rr);
         T.Z = dalloc<float>(P, (size_t)P->ksplit * rr);
@@ -470,12 +496,20 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
         tdev[t].zsplit = (long)rr;
         ddeig::GemmType gt{T.Ah, T.Al, T.Rh, T.Rl, T.Z, (long)rr, T.ld};
         gtypes.push_back(gt);
-        const int nkb = T.ld / 32;
-        for (int sp = 0; sp < P->ksplit; ++sp) {
-          const int kb0 = (int)((long)nkb * sp / P->ksplit), kb1 = (int)((long)nkb * (sp + 1) / P->ksplit);
-          for (int nt = 0; nt < T.ld / 128; ++nt)
-            for (int mt = 0; mt < T.mp / 128; ++mt)
-              tiles.push_back(ddeig::GemmTile{(int)t, mt * 128, nt * 128, kb0 * 32, kb1 * 32, sp});
+        if (big(T)) {
+          const int nkb = T.ld / 32;
+          for (int sp = 0; sp < P->ksplit; ++sp) {
+            const int kb0 = (int)((long)nkb * sp / P->ksplit);
+            const int kb1 = (int)((long)nkb * (sp + 1) / P->ksplit);
+            for (int nt = 0; nt < T.ld / 128; ++nt)
+              for (int mt = 0; mt < T.mp / 128; ++mt)
+                tiles.push_back(ddeig::GemmTile{(int)t, mt * 128, nt * 128, kb0 * 32, kb1 * 32, sp});
+          }
+        } else {
+          tdev[t].ksplit = 1;
+          const int m = T.box.nch * T.box.b;
+          for (int r0 = 0; r0 < m; r0 += kBlock / 64)
+            gemv.push_back(ddeig::GemvRows{(int)t, r0, std::min(m, r0 + kBlock / 64), T.nmem});
         }
       } else {
         T.batch = dalloc<double>(P, (size_t)T.nmem * mm);
@@ -486,9 +520,38 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
         tdev[t].zsplit = 0;
       }
       tdev[t].batch = T.batch;
+      T.phi = dalloc<double>(P, mm);
+      tdev[t].phi = T.phi;
+      tdev[t].fm0 = ddeig::make_fastdiv((unsigned)T.box.m[0]);
+    }
+    if (P->types.size() > (size_t)ddeig::kMaxTypes) throw Failure{DDEIG_EINTERNAL, "too many classes"};
+    {
+      std::vector<ddeig::SubTS> ts(nsub);
+      for (int sid = 0; sid < nsub; ++sid) ts[sid] = ddeig::SubTS{P->subs[sid].type, P->subs[sid].slot};
+      std::vector<int> first(P->types.size());
+      std::vector<double*> phis(P->types.size());
+      for (size_t t = 0; t < P->types.size(); ++t) {
+        first[t] = P->types[t].members[0];
+        phis[t] = P->types[t].phi;
+      }
+      P->dSubTS = dalloc<ddeig::SubTS>(P, nsub);
+      P->dFirst = dalloc<int>(P, first.size());
+      P->dPhis = dalloc<double*>(P, phis.size());
+      check_hip(hipMemcpyAsync(P->dSubTS, ts.data(), sizeof(ddeig::SubTS) * nsub,
+                               hipMemcpyHostToDevice, s), "copy sub table");
+      check_hip(hipMemcpyAsync(P->dFirst, first.data(), sizeof(int) * first.size(),
+                               hipMemcpyHostToDevice, s), "copy first members");
+      check_hip(hipMemcpyAsync(P->dPhis, phis.data(), sizeof(double*) * phis.size(),
+                               hipMemcpyHostToDevice, s), "copy phi pointers");
+      sync(P);
     }
     if (dense) {
       P->ntiles = (int)tiles.size();
+      P->ngemv = (int)gemv.size();
+      P->dGemv = dalloc<ddeig::GemvRows>(P, std::max<size_t>(gemv.size(), 1));
+      if (!gemv.empty())
+        check_hip(hipMemcpyAsync(P->dGemv, gemv.data(), sizeof(ddeig::GemvRows) * gemv.size(),
+                                 hipMemcpyHostToDevice, s), "copy gemv rows");
       P->dTiles = dalloc<ddeig::GemmTile>(P, tiles.size());
       P->dGtypes = dalloc<ddeig::GemmType>(P, gtypes.size());
       check_hip(hipMemcpyAsync(P->dTiles, tiles.data(), sizeof(ddeig::GemmTile) * tiles.size(),
@@ -518,17 +581,13 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
     P->hist = dalloc<double>(P, P->hist_cap);
     P->scal = dalloc<double>(P, 8);
     P->flag = dalloc<int>(P, 1);
+    check_hip(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking), "create stream");
+    check_hip(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming), "create event");
+    check_hip(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming), "create event");
     P->gjbuf = dalloc<double>(P, 4 * (size_t)gjmax);
     P->gj_stride = gjmax;
     P->psi = dalloc<double>(P, g.tsize);
-    // restriction: enough workgroups per subdomain to fill the chip
-    {
-      int minl = 1 << 30;
-      for (auto& T : P->types) minl = std::min(minl, T.box.m[1] * T.box.m[2]);
-      const int want = (1024 + nsub - 1) / nsub;
-      P->restrict_rb = std::max(1, std::min(std::min(16, want), minl));
-    }
-    P->crhs = dalloc<double>(P, (size_t)nsub * P->restrict_rb);
+    P->crhs = dalloc<double>(P, nsub);
     // per-axis covering tables of the expanding directions
     for (int a = 0; a < p; ++a) {
       std::vector<ddeig::XCover> xc(g.N[a]);
@@ -590,6 +649,12 @@ void ddeig_destroy(ddeig_problem* P) {
   if (!P) return;
   if (P->stream) (void)hipStreamSynchronize(P->stream);
   else (void)hipDeviceSynchronize();
+  if (P->aux) {
+    (void)hipStreamSynchronize(P->aux);
+    (void)hipStreamDestroy(P->aux);
+  }
+  if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+  if (P->ev_join) (void)hipEventDestroy(P->ev_join);
   for (void* p : P->allocs) (void)hipFree(p);
   P->allocs.clear();
   delete P;
@@ -707,7 +772,7 @@ ddeig_status ddeig_apply_precond(ddeig_problem* P, const double* r, double* z) {
   if (r == z) return set_error(DDEIG_EINVAL, "r and z must not alias");
   if (!P->shifted) return set_error(DDEIG_ESTATE, "apply_precond before the shift is set");
   API_GUARD_BEGIN
-  precond_apply(P, r, z, nullptr, nullptr);
+  precond_apply(P, r, z, nullptr, nullptr, nullptr);
   check_launch("apply_precond");
   return DDEIG_OK;
   API_GUARD_END

@@ -98,6 +98,7 @@ struct SubType {
   double* W = nullptr;      // nch * b * b FP64 Schur-complement inverses
   float* W32 = nullptr;     // FP32 copy (local_prec = 1)
   double* batch = nullptr;  // nmem * nch * b local vectors
+  double* phi = nullptr;    // coarse weights of the class (box order)
   // dense-inverse class data (local_prec = 2)
   int ld = 0, mp = 0;
   __bf16 *Ah = nullptr, *Al = nullptr, *Rh = nullptr, *Rl = nullptr;
@@ -125,6 +126,17 @@ struct TypeDev {
   __bf16* Rl;
   const float* Z;
   long zsplit;
+  // coarse weights of the class: phi[e] = D(e) psi_ext(e) on the box of any
+  // member (equal for all members by periodicity), and division by m[0]
+  const double* phi;
+  FastDiv fm0;
+};
+
+constexpr int kMaxTypes = 9;  // 3 classes per expanding axis, p <= 2
+
+// Subdomain -> (class, slot), packed for the node-parallel kernels.
+struct SubTS {
+  int type, slot;
 };
 
 // Operands of the grouped MFMA GEMM of one dense class (ld x ld inverse).
@@ -140,6 +152,12 @@ struct GemmType {
 
 struct GemmTile {
   int type, m0, n0, k0, k1, split;
+};
+
+// Rows [r0, r1) of one small dense class for the streaming kernel.
+constexpr int kGemvMax = 4;
+struct GemvRows {
+  int type, r0, r1, nmem;
 };
 
 // PCG device state (one per problem).
@@ -160,6 +178,9 @@ struct ddeig_problem {
   int delta;
   ddeig_options opt;
   hipStream_t stream;
+  // second stream (default priority) for work that overlaps the local solves
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // operator tables, tap-major: tab[tap * tsize + tnode]
   double* tabK = nullptr;
   double* tabM = nullptr;
@@ -178,10 +199,13 @@ struct ddeig_problem {
   ddeig::TypeDev* dTypes = nullptr;
   int maxb = 0;
   ddeig::XCover* dXC[2] = {nullptr, nullptr};   // per expanding axis, N[a] entries
-  int restrict_rb = 1;                            // row blocks per subdomain in the restriction
+  ddeig::SubTS* dSubTS = nullptr;
+  int* dFirst = nullptr;          // first member of every class
+  double** dPhis = nullptr;       // per-class coarse weights (device pointer array)
   // grouped GEMM of the dense classes
-  int ntiles = 0, ksplit = 1;
+  int ntiles = 0, ngemv = 0, ksplit = 1;
   ddeig::GemmTile* dTiles = nullptr;
+  ddeig::GemvRows* dGemv = nullptr;
   ddeig::GemmType* dGtypes = nullptr;
   // coarse space
   double* A0inv = nullptr;  // nsub x nsub
@@ -222,16 +246,26 @@ void launch_chain_solve_box(const ddeig_problem* P, const Box& bx, const double*
                             const double* W, double* v, int nrhs, hipStream_t s);
 
 // preconditioner pieces
-void launch_restrict(const ddeig_problem* P, const double* r, int coarse, const PcgState* st,
-                     hipStream_t s);
+// Convergence test folded into the restriction (PCG iteration k): the first
+// workgroup adds the ||r||^2 partials and updates the state.
+struct CheckArgs {
+  int on, k, maxit, hist_cap;
+  Red rr;
+  double* hist;
+};
+void launch_restrict(const ddeig_problem* P, const double* r, int coarse, PcgState* st,
+                     const CheckArgs& chk, hipStream_t s);
 void launch_local_solves(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 void launch_coarse_solve(const ddeig_problem* P, const PcgState* st, hipStream_t s);
+void launch_coarse_rhs(const ddeig_problem* P, const double* r, const PcgState* st, hipStream_t s);
+void launch_coarse_phi(const ddeig_problem* P, hipStream_t s);
 void launch_extend(const ddeig_problem* P, const double* r, double* z, int coarse, Red* dot,
                    const PcgState* st, hipStream_t s);
 void launch_symmetrise(double* A, int N, hipStream_t s);
 void launch_split_inverse(const double* Ainv, int m, int ld, void* Ah, void* Al, hipStream_t s);
 void launch_identity(double* v, int m, hipStream_t s);
 void launch_dense_gemm(const ddeig_problem* P, const PcgState* st, hipStream_t s);
+void launch_dense_gemv(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 void launch_to_float(const double* src, float* dst, long n, hipStream_t s);
 void build_coarse_matrix(ddeig_problem* P, double* A0, hipStream_t s);
 

@@ -267,8 +267,8 @@ bool local_solves_fast_ok(const ddeig_problem* P);
 void launch_local_solves_fast(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 
 void launch_local_solves(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
-  if (P->opt.local_prec == 2) {
-    launch_dense_gemm(P, st, s);
+  if (P->opt.local_prec >= 2) {
+    launch_dense_gemm(P, st, s);  // the small classes go through launch_dense_gemv
     return;
   }
   if (local_solves_fast_ok(P)) {

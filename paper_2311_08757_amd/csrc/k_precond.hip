@@ -84,85 +84,148 @@ __device__ inline double cover_weight(const Geo& g, int delta, int pu, const XCo
   return w;
 }
 
-// Gather r into the subdomain batches (box natural order; bf16 hi/lo rows for
-// dense classes) and, with the coarse level, the partial sums of
-// c_sub = sum_k D_sub(k) psi_ext(k) r(k) (R_0 r) over this workgroup's share
-// of the box (grid: subdomain x rb row blocks).
-__global__ void __launch_bounds__(kBlock) k_restrict(Geo g, int delta, int pu, int coarse, int rb,
-                                                     const PcgState* __restrict__ st,
+// Scatter r into the subdomain batches (box natural order; bf16 hi/lo rows for
+// dense classes): node-parallel over row segments of kBlock x1 positions;
+// every node writes its copy into each covering subdomain (at most 2^p), so
+// reads of r and writes of a batch row are both coalesced.  With chk.on the
+// first workgroup also applies the PCG stopping test of iteration k.
+__global__ void __launch_bounds__(kBlock) k_restrict(Geo g, int ntypes, PcgState* __restrict__ st,
+                                                     CheckArgs chk,
                                                      const double* __restrict__ r,
                                                      const TypeDev* __restrict__ types,
-                                                     const SubDev* __restrict__ subs,
+                                                     const SubTS* __restrict__ subts,
                                                      const XCover* __restrict__ xc0,
-                                                     const XCover* __restrict__ xc1,
-                                                     const double* __restrict__ psi,
-                                                     double* __restrict__ cpart) {
+                                                     const XCover* __restrict__ xc1) {
+  __shared__ TypeDev stypes[kMaxTypes];
   if (st != nullptr && st->done) return;
-  const int sid = blockIdx.x / rb, part = blockIdx.x - sid * rb;
-  const SubDev sd = subs[sid];
-  const TypeDev td = types[sd.type];
-  const int m0 = td.m[0];
-  const int nl = td.m[1] * td.m[2];
-  const int l0 = (int)((long)nl * part / rb), l1 = (int)((long)nl * (part + 1) / rb);
-  const int f1 = (l1 - l0) * m0;
-  const FastDiv fm0 = make_fastdiv_dev(m0);
-  const XCover* xc[2] = {xc0, xc1};
-  double* dst = td.batch + (long)sd.slot * td.nch * td.b;
-  double acc = 0.0;
-  for (int f = threadIdx.x; f < f1; f += blockDim.x) {
-    const int ll = (int)fdiv((unsigned)f, fm0);
-    const int u0 = f - ll * m0;
-    const int line = l0 + ll;                 // u1 + m1 u2
-    const int u2 = line / td.m[1];
-    const int u1 = line - u2 * td.m[1];
-    const int i[3] = {sd.o[0] + u0, sd.o[1] + u1, sd.o[2] + u2};
-    const long k = i[0] + (long)g.N[0] * (i[1] + (long)g.N[1] * i[2]);
-    const int e = u0 + m0 * line;
-    const double rv = r[k];
-    if (td.dense) {
-      const __bf16 hi = (__bf16)(float)rv;
-      const __bf16 lo = (__bf16)(float)(rv - (double)(float)hi);
-      td.Rh[(long)sd.slot * td.ld + e] = hi;
-      td.Rl[(long)sd.slot * td.ld + e] = lo;
-    } else {
-      dst[e] = rv;
-    }
-    if (coarse) {
-      int which[2] = {0, 0};
-      for (int a = 0; a < g.p; ++a) which[a] = xc[a][i[a]].c[0] == sd.c[a] ? 0 : 1;
-      acc += cover_weight(g, delta, pu, xc, sd.c, i, which) *
-             psi[table_node(g, i[0], i[1], i[2])] * rv;
+  if (chk.on && blockIdx.x == 0) {
+    // stopping test ||r_k|| <= rtol ||r_0|| of PCG iteration k, with the history;
+    // later kernels of the iteration see `done` and do nothing
+    const double rn2 = sum_partials(chk.rr.part, chk.rr.np);
+    if (threadIdx.x == 0) {
+      st->relres = sqrt(rn2 / st->r0n2);
+      if (chk.hist && chk.k < chk.hist_cap) chk.hist[chk.k] = st->relres;
+      st->iters = chk.k;
+      if (rn2 <= st->tol2) st->done = 1;
+      else if (chk.k >= chk.maxit) st->done = 4;
     }
   }
-  if (coarse) {
-    const double s = block_sum(acc);
-    if (threadIdx.x == 0) cpart[blockIdx.x] = s;
+  if (threadIdx.x < ntypes) stypes[threadIdx.x] = types[threadIdx.x];
+  __syncthreads();
+  const int N0 = g.N[0], N1 = g.N[1];
+  const int segs = (N0 + kBlock - 1) / kBlock;
+  const long items = (long)segs * N1 * g.N[2];
+  for (long it = blockIdx.x; it < items; it += gridDim.x) {
+    const int line = (int)(it / segs);
+    const int i0 = (int)(it - (long)line * segs) * kBlock + threadIdx.x;
+    if (i0 >= N0) continue;
+    const int i2 = g.D == 3 ? (int)fdiv((unsigned)line, g.fN1) : 0;
+    const int i1 = line - i2 * N1;
+    const double rv = r[i0 + (long)N0 * line];
+    const __bf16 hi = (__bf16)(float)rv;
+    const __bf16 lo = (__bf16)(float)(rv - (double)(float)hi);
+    const XCover a0 = xc0[i0];
+    XCover a1;
+    a1.c[0] = 1; a1.c[1] = 0; a1.u[0] = i1; a1.u[1] = 0;
+    if (g.p == 2) a1 = xc1[i1];
+    for (int q1 = 0; q1 < 2; ++q1) {
+      if (a1.c[q1] == 0) continue;
+      for (int q0 = 0; q0 < 2; ++q0) {
+        if (a0.c[q0] == 0) continue;
+        const int sid = g.p == 1 ? a0.c[q0] - 1 : (a0.c[q0] - 1) + g.L * (a1.c[q1] - 1);
+        const SubTS ts = subts[sid];
+        const TypeDev& td = stypes[ts.type];
+        const long e = a0.u[q0] + (long)td.m[0] * (a1.u[q1] + (long)td.m[1] * i2);
+        if (td.dense) {
+          td.Rh[(long)ts.slot * td.ld + e] = hi;
+          td.Rl[(long)ts.slot * td.ld + e] = lo;
+        } else {
+          td.batch[(long)ts.slot * td.nch * td.b + e] = rv;
+        }
+      }
+    }
   }
 }
 
-void launch_restrict(const ddeig_problem* P, const double* r, int coarse, const PcgState* st,
-                     hipStream_t s) {
-  hipLaunchKernelGGL(k_restrict, dim3(P->nsub * P->restrict_rb), dim3(kBlock), 0, s, P->g,
-                     P->delta, P->opt.pu, coarse, P->restrict_rb, st, r, P->dTypes, P->dSubs,
-                     P->dXC[0], P->dXC[1], P->psi, P->crhs);
+void launch_restrict(const ddeig_problem* P, const double* r, int coarse, PcgState* st,
+                     const CheckArgs& chk, hipStream_t s) {
+  (void)coarse;
+  const long segs = (P->g.N[0] + kBlock - 1) / kBlock;
+  const long items = segs * P->g.N[1] * P->g.N[2];
+  const int blocks = (int)std::min<long>(items, 16384);
+  hipLaunchKernelGGL(k_restrict, dim3(blocks), dim3(kBlock), 0, s, P->g, (int)P->types.size(),
+                     st, chk, r, P->dTypes, P->dSubTS, P->dXC[0], P->dXC[1]);
+}
+
+// c_sub = phi_class . R_sub r  (R_0 r of def:algebraic-perfact-coarse-space):
+// one workgroup per subdomain, the box traversed in natural order.
+__global__ void __launch_bounds__(kBlock) k_coarse_rhs(Geo g, const PcgState* __restrict__ st,
+                                                       const double* __restrict__ r,
+                                                       const TypeDev* __restrict__ types,
+                                                       const SubDev* __restrict__ subs,
+                                                       double* __restrict__ crhs) {
+  if (st != nullptr && st->done) return;
+  const SubDev sd = subs[blockIdx.x];
+  const TypeDev td = types[sd.type];
+  const int m0 = td.m[0], m1 = td.m[1];
+  const int mtot = m0 * m1 * td.m[2];
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < mtot; e += blockDim.x) {
+    const int line = (int)fdiv((unsigned)e, td.fm0);
+    const int u0 = e - line * m0;
+    const int u2 = line / m1, u1 = line - u2 * m1;
+    const long k = (sd.o[0] + u0) + (long)g.N[0] * ((sd.o[1] + u1) + (long)g.N[1] * (sd.o[2] + u2));
+    acc += td.phi[e] * r[k];
+  }
+  const double sum = block_sum(acc);
+  if (threadIdx.x == 0) crhs[blockIdx.x] = sum;
+}
+
+void launch_coarse_rhs(const ddeig_problem* P, const double* r, const PcgState* st,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_rhs, dim3(P->nsub), dim3(kBlock), 0, s, P->g, st, r, P->dTypes,
+                     P->dSubs, P->crhs);
+}
+
+// phi of every class from its first member's box: D_c(k) psi_ext(k).
+__global__ void k_coarse_phi(Geo g, int delta, int pu, const TypeDev* __restrict__ types,
+                             const SubDev* __restrict__ subs, const int* __restrict__ first,
+                             const XCover* __restrict__ xc0, const XCover* __restrict__ xc1,
+                             const double* __restrict__ psi, double* const* __restrict__ phis) {
+  const int t = blockIdx.y;
+  const TypeDev td = types[t];
+  const SubDev sd = subs[first[t]];
+  const XCover* xc[2] = {xc0, xc1};
+  const int m0 = td.m[0], m1 = td.m[1];
+  const int mtot = m0 * m1 * td.m[2];
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < mtot; e += gridDim.x * blockDim.x) {
+    const int line = e / m0, u0 = e - line * m0;
+    const int u2 = line / m1, u1 = line - u2 * m1;
+    const int i[3] = {sd.o[0] + u0, sd.o[1] + u1, sd.o[2] + u2};
+    int which[2] = {0, 0};
+    for (int a = 0; a < g.p; ++a) which[a] = xc[a][i[a]].c[0] == sd.c[a] ? 0 : 1;
+    phis[t][e] = cover_weight(g, delta, pu, xc, sd.c, i, which) *
+                 psi[table_node(g, i[0], i[1], i[2])];
+  }
+}
+
+void launch_coarse_phi(const ddeig_problem* P, hipStream_t s) {
+  const int nt = (int)P->types.size();
+  hipLaunchKernelGGL(k_coarse_phi, dim3(64, nt), dim3(kBlock), 0, s, P->g, P->delta, P->opt.pu,
+                     P->dTypes, P->dSubs, P->dFirst, P->dXC[0], P->dXC[1], P->psi, P->dPhis);
 }
 
 // y0 = A0^{-1} c with the dense symmetric inverse: one wave64 per row, lanes
-// stride the row (coalesced), fixed-order shuffle reduction; c_j is the sum of
-// the rb restriction partials of subdomain j in order.
-__global__ void k_coarse_solve(int N, int rb, const PcgState* __restrict__ st,
-                               const double* __restrict__ A0inv, const double* __restrict__ cpart,
+// stride the row (coalesced), fixed-order shuffle reduction.
+__global__ void k_coarse_solve(int N, const PcgState* __restrict__ st,
+                               const double* __restrict__ A0inv, const double* __restrict__ c,
                                double* __restrict__ y) {
   if (st != nullptr && st->done) return;
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   if (row >= N) return;
   double acc = 0.0;
-  for (int j = lane; j < N; j += 64) {
-    double c = 0.0;
-    for (int q = 0; q < rb; ++q) c += cpart[(long)j * rb + q];
-    acc += A0inv[(long)row * N + j] * c;
-  }
+  for (int j = lane; j < N; j += 64) acc += A0inv[(long)row * N + j] * c[j];
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) y[row] = acc;
 }
@@ -170,16 +233,16 @@ __global__ void k_coarse_solve(int N, int rb, const PcgState* __restrict__ st,
 void launch_coarse_solve(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
   const int rows_per_block = kBlock / 64;
   hipLaunchKernelGGL(k_coarse_solve, dim3((P->nsub + rows_per_block - 1) / rows_per_block),
-                     dim3(kBlock), 0, s, P->nsub, P->restrict_rb, st, P->A0inv, P->crhs, P->cy);
+                     dim3(kBlock), 0, s, P->nsub, st, P->A0inv, P->crhs, P->cy);
 }
 
 // z = sum_c R_c^T y_c (+ R_0^T y0), partials of r.z.  Work items are row
 // segments of kBlock x1 positions (as in the stencil); the covering cells of
 // a node come from the per-axis tables and are summed in a fixed order.
 __global__ void __launch_bounds__(kBlock) k_extend(Geo g, int delta, int pu, int coarse,
-                                                   const PcgState* __restrict__ st,
+                                                   int ntypes, const PcgState* __restrict__ st,
                                                    const TypeDev* __restrict__ types,
-                                                   const SubDev* __restrict__ subs,
+                                                   const SubTS* __restrict__ subts,
                                                    const XCover* __restrict__ xc0,
                                                    const XCover* __restrict__ xc1,
                                                    const double* __restrict__ psi,
@@ -187,7 +250,10 @@ __global__ void __launch_bounds__(kBlock) k_extend(Geo g, int delta, int pu, int
                                                    const double* __restrict__ r,
                                                    double* __restrict__ z, int use_dot,
                                                    Red dot) {
+  __shared__ TypeDev stypes[kMaxTypes];
   if (st != nullptr && st->done) return;
+  if (threadIdx.x < ntypes) stypes[threadIdx.x] = types[threadIdx.x];
+  __syncthreads();
   const XCover* xc[2] = {xc0, xc1};
   double acc = 0.0;
   const int N0 = g.N[0], N1 = g.N[1];
@@ -211,17 +277,17 @@ __global__ void __launch_bounds__(kBlock) k_extend(Geo g, int delta, int pu, int
         if (a0.c[q0] == 0) continue;
         const int c[3] = {a0.c[q0], g.p == 2 ? a1.c[q1] : 0, 0};
         const int sid = sub_index(g, c);
-        const SubDev sd = subs[sid];
-        const TypeDev td = types[sd.type];
+        const SubTS ts = subts[sid];
+        const TypeDev& td = stypes[ts.type];
         const int u1 = g.p == 2 ? a1.u[q1] : i[1];
-        const long e = a0.u[q0] + (long)td.m[0] * (u1 + (long)td.m[1] * (i2 - sd.o[2]));
+        const long e = a0.u[q0] + (long)td.m[0] * (u1 + (long)td.m[1] * i2);
         if (td.dense) {
-          const float* zp = td.Z + (long)sd.slot * td.ld + e;
+          const float* zp = td.Z + (long)ts.slot * td.ld + e;
           float zs = 0.0f;
           for (int sp = 0; sp < td.ksplit; ++sp) zs += zp[sp * td.zsplit];
           zl += (double)zs;
         } else {
-          zl += td.batch[(long)sd.slot * td.nch * td.b + e];
+          zl += td.batch[(long)ts.slot * td.nch * td.b + e];
         }
         if (coarse) {
           const int which[2] = {q0, q1};
@@ -245,7 +311,8 @@ void launch_extend(const ddeig_problem* P, const double* r, double* z, int coars
   const Red none{nullptr, 0, nullptr};
   if (dot) dot->np = blocks;
   hipLaunchKernelGGL(k_extend, dim3(blocks), dim3(kBlock), 0, s, P->g, P->delta, P->opt.pu,
-                     coarse, st, P->dTypes, P->dSubs, P->dXC[0], P->dXC[1], P->psi, P->cy, r, z,
+                     coarse, (int)P->types.size(), st, P->dTypes, P->dSubTS, P->dXC[0], P->dXC[1],
+                     P->psi, P->cy, r, z,
                      dot ? 1 : 0, dot ? *dot : none);
 }
 

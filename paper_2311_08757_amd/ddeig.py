@@ -188,7 +188,7 @@ def assemble(p, q, L, ne, V, delta, ell=1, pu="equal", coarse=True, local_prec="
     geom = Geometry(p, q, L, float(ell))
     Vs, keep = _potential(V)
     opts = Options({"equal": 0, "distance": 1}[pu], 1 if coarse else 0,
-                   {"fp64": 0, "fp32": 1, "bf16x3": 2}[local_prec], batch_iters)
+                   {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16": 3}[local_prec], batch_iters)
     if stream is None:
         stream = torch.cuda.current_stream()
     handle = ctypes.c_void_p()

@@ -191,12 +191,13 @@ PREC_IDS = [IDS[0], IDS[1], IDS[4], IDS[5]]
 
 
 @pytest.mark.parametrize("case", PREC_CASES, ids=PREC_IDS)
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
 def test_reduced_precision_local_solves(torch, case, prec):
-    """FP32 chain factors or bf16x3 dense inverses on MFMA change only the
-    preconditioner: z stays close to the exact M^{-1} r (2^-16-level splits,
-    tolerance 1e-3 relative), PCG stays FP64, so the eigenpair meets the same
-    1e-10 / 1e-8 bar as the FP64 path."""
+    """FP32 chain factors or bf16x3 / bf16 dense inverses on MFMA change only the
+    preconditioner: z stays close to the exact M^{-1} r (tolerance 1e-3
+    relative for the split forms, 3e-2 for the single bf16 inverse, whose
+    entries carry 2^-9 relative rounding), PCG stays FP64, so the eigenpair
+    meets the same 1e-10 / 1e-8 bar as the FP64 path."""
     import paper_2311_08757_amd as dd
     from oracle.ipm import inverse_iteration_direct
     P = _oracle(case)
@@ -207,7 +208,8 @@ def test_reduced_precision_local_solves(torch, case, prec):
     dd.apply_precond(prob, _dev(torch, r), z)
     torch.cuda.synchronize()
     zr = P.preconditioner(True).apply(r)
-    assert np.linalg.norm(z.cpu().numpy() - zr) <= 1e-3 * np.linalg.norm(zr)
+    tol = 3e-2 if prec == "bf16" else 1e-3
+    assert np.linalg.norm(z.cpu().numpy() - zr) <= tol * np.linalg.norm(zr)
     prob2 = _assemble(case, local_prec=prec)
     dd.cell_shift(prob2)
     x = torch.zeros(P.grid.n, dtype=torch.float64, device="cuda")
