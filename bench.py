@@ -10,10 +10,14 @@ matrix) happens once before the timed region.  value = n_dof * (sum of PCG
 iterations) / time.  The eigenvalue of every timed solve is checked against
 the stored oracle result.
 
+The default local solves are the dense bf16 inverses on MFMA (FP32
+accumulation; CG, residuals, Rayleigh quotient and coarse solve in FP64); the
+same solve with FP64 block-chain local solves is timed as the comparison.
 Also reports the roofline of the dominant kernel (live HIP-event timing on the
 library's stream) and the oracle's CPU throughput on a bounded sample.
 """
 import argparse
+import hashlib
 import json
 import os
 import subprocess
@@ -25,6 +29,30 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+BF16_PEAK_TFLOPS = 2500.0
+
+# HBM bytes per launch of the dense local-solve GEMM on the 2-D L=256, h=1/64
+# workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs, each scaled by
+# what the counter read for a plain device copy of known size (FETCH x 2.0,
+# WRITE x 1.0).  Valid only for the kernel source they were taken from: when
+# that file changes the figure is reported as null until the counters are
+# taken again.
+COUNTED_TRAFFIC = {
+    "source": "paper_2311_08757_amd/csrc/k_dense.hip",
+    "sha256": "c7f49510a4573fef865c640bdb664950fa780e7dad79661140c0dcc34487de3e",
+    "workload": "2d-L256-ne64", "local_prec": "bf16",
+    "fetch_kib": 48908.4, "fetch_factor": 2.0, "write_kib": 13440.0, "write_factor": 1.0,
+}
+
+
+def counted_traffic(workload, local_prec):
+    c = COUNTED_TRAFFIC
+    if workload != c["workload"] or local_prec != c["local_prec"]:
+        return None
+    with open(os.path.join(ROOT, c["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != c["sha256"]:
+            return None
+    return 1024.0 * (c["fetch_kib"] * c["fetch_factor"] + c["write_kib"] * c["write_factor"])
 
 
 def parse():
@@ -33,8 +61,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--local-prec", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16"])
+    ap.add_argument("--local-prec", default="bf16", choices=["fp64", "fp32", "bf16x3", "bf16"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison solve")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="set-up, then only the per-kernel timings (for counter runs)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this size (counter calibration)")
     ap.add_argument("--cpu-sample", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
@@ -100,6 +133,11 @@ def main():
     n = prob.n_dof
     x = torch.zeros(n, dtype=torch.float64, device="cuda")
     print(f"# setup {t_setup:.2f}s n={n} sigma={sigma:.12f}", file=sys.stderr, flush=True)
+    if args.kernels_only:
+        args.warmup = 0
+        args.steps = 0
+        args.no_compare = True
+        args.no_cpu = True
     for i in range(args.warmup):
         x.zero_()
         out = dd.inverse_iteration(prob, x, tol_x=1e-9, rtol_inner=1e-10, maxit_inner=2000)
@@ -117,46 +155,72 @@ def main():
         lams.append(out["lam"])
         outers.append(out["outer_its"])
     torch.cuda.synchronize()
-    T = time.perf_counter() - t0
+    T = max(time.perf_counter() - t0, 1e-9)
     print(f"# timed {args.steps} solves in {T:.3f}s, inner={inner}", file=sys.stderr, flush=True)
     lam_err = None
-    if gold is not None:
+    if gold is not None and lams:
         lam_err = max(abs(l - gold["lam"]) / abs(gold["lam"]) for l in lams)
         xs = x.cpu().numpy()[gold["sample_idx"]]
         vec_err = float(np.max(np.abs(xs - np.array(gold["sample_x"]))))
         print(f"# lambda rel err vs oracle {lam_err:.3e}, max sampled |x - x_ref| {vec_err:.3e}",
               file=sys.stderr, flush=True)
 
-    # roofline of the stencil operator (one kernel per apply_op call), live HIP events
+    # roofline of the dominant kernel (the local solves) and of the stencil,
+    # timed live with HIP events on the library's stream
     y = torch.empty_like(x)
-    reps = 200
-    for _ in range(10):
-        dd.apply_op(prob, "A_sigma", x, y)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        dd.apply_op(prob, "A_sigma", x, y)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t_op = e0.elapsed_time(e1) / reps * 1e-3
-    bytes_op = 16.0 * n
-    # preconditioner apply (restrict + local solves + coarse + extend)
     z = torch.empty_like(x)
-    for _ in range(3):
-        dd.apply_precond(prob, x, z)
-    e0.record(stream)
-    rp = 20
-    for _ in range(rp):
-        dd.apply_precond(prob, x, z)
-    e1.record(stream)
+    dd.apply_precond(prob, x, z)
+    t_loc, work_loc = dd.profile_kernel(prob, "local", reps=20)
+    t_op, bytes_op = dd.profile_kernel(prob, "stencil", reps=200, x=x, y=y)
+    t_pre, _ = dd.profile_kernel(prob, "precond", reps=20, x=x, y=z)
     torch.cuda.synchronize()
-    t_pre = e0.elapsed_time(e1) / rp * 1e-3
-    print(f"# apply_op {t_op * 1e6:.2f} us ({bytes_op / t_op / 1e9:.1f} GB/s), "
-          f"apply_precond {t_pre * 1e6:.1f} us", file=sys.stderr, flush=True)
-    roof = {"bound": "hbm", "kernel": "k_stencil<2> (apply_op A_sigma)",
-            "achieved": bytes_op / t_op / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": bytes_op / t_op / 1e9 / HBM_PEAK_GBS, "traffic": None,
-            "launch_us": t_op * 1e6}
+    print(f"# local solves {t_loc:.2f} us ({work_loc / t_loc / 1e6:.1f} TFLOP/s), stencil "
+          f"{t_op:.2f} us ({bytes_op / t_op / 1e3:.1f} GB/s), apply_precond {t_pre:.1f} us",
+          file=sys.stderr, flush=True)
+    dense = args.local_prec in ("bf16", "bf16x3")
+    if dense:
+        roof = {"bound": "mfma", "kernel": "k_dense_gemm (bf16 MFMA local solves of the interior class)",
+                "achieved": work_loc / t_loc / 1e6, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": work_loc / t_loc / 1e6 / BF16_PEAK_TFLOPS,
+                "traffic": counted_traffic(cfg["name"], args.local_prec), "traffic_unit": "B",
+                "launch_us": t_loc, "work_per_launch_flop": work_loc}
+    else:
+        roof = {"bound": "alu", "kernel": "k_local_solves_2d (FP64 block-chain local solves)",
+                "achieved": work_loc / t_loc / 1e6, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": work_loc / t_loc / 1e6 / FP64_PEAK_TFLOPS, "traffic": None,
+                "launch_us": t_loc, "work_per_launch_flop": work_loc}
+    stencil_roof = {"bound": "hbm", "kernel": "k_stencil<2> (A_sigma apply)",
+                    "achieved": bytes_op / t_op / 1e3, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": bytes_op / t_op / 1e3 / HBM_PEAK_GBS, "launch_us": t_op,
+                    "bytes_per_launch": bytes_op}
+    if args.calib_copy_mib > 0:
+        nb = args.calib_copy_mib * (1 << 20) // 8
+        a = torch.empty(nb, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    # the same eigen-solve with FP64 block-chain local solves
+    cmp = None
+    if not args.no_compare and args.local_prec != "fp64":
+        p64 = dd.assemble(cfg["p"], cfg["q"], cfg["L"], cfg["ne"], cfg["V"], cfg["delta"],
+                          local_prec="fp64")
+        dd.cell_shift(p64)
+        x.zero_()
+        dd.inverse_iteration(p64, x, tol_x=1e-9, rtol_inner=1e-10, maxit_inner=2000)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x.zero_()
+        o64 = dd.inverse_iteration(p64, x, tol_x=1e-9, rtol_inner=1e-10, maxit_inner=2000)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        cmp = {"fp64_time_to_eigenpair_ms": t64 * 1e3, "fp64_pcg_iters": o64["inner_sum"],
+               "fp64_lambda": o64["lam"],
+               "speedup_vs_fp64": t64 / (T / max(args.steps, 1))}
+        print(f"# fp64 comparison: {t64 * 1e3:.1f} ms, inner={o64['inner_sum']}", file=sys.stderr,
+              flush=True)
+        del p64
 
     cpu = None
     if not args.no_cpu:
@@ -173,7 +237,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": T / args.steps * 1e3,
+        "ms_per_step": T / max(args.steps, 1) * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -184,10 +248,13 @@ def main():
         "config": {"workload": cfg["name"], "p": cfg["p"], "q": cfg["q"], "L": cfg["L"],
                    "h": f"1/{cfg['ne']}", "overlap": cfg["delta"], "n_dof": n,
                    "subdomains": prob.n_sub, "local_prec": args.local_prec,
-                   "time_to_eigenpair_ms": T / args.steps * 1e3, "setup_s": t_setup,
-                   "outer_its": outers[-1], "pcg_iters_per_solve": inner / args.steps,
-                   "lambda": lams[-1], "lambda_rel_err_vs_oracle": lam_err},
+                   "time_to_eigenpair_ms": T / max(args.steps, 1) * 1e3, "setup_s": t_setup,
+                   "outer_its": outers[-1] if outers else None,
+                   "pcg_iters_per_solve": inner / max(args.steps, 1),
+                   "lambda": lams[-1] if lams else None, "lambda_rel_err_vs_oracle": lam_err},
         "roofline": roof,
+        "stencil_roofline": stencil_roof,
+        "fp64_comparison": cmp,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

@@ -169,6 +169,19 @@ ddeig_status ddeig_pcg_solve(ddeig_problem* P, const double* b, double* x, doubl
 ddeig_status ddeig_inverse_iteration(ddeig_problem* P, double* x, double tol_x, int maxit_outer,
                                      double rtol_inner, int maxit_inner, ddeig_eig_info* info);
 
+/* Measurement support: launches one kernel of the hot path `reps` times on the
+ * library's stream between two HIP events and returns the mean duration of one
+ * launch in *avg_us (synchronises).  which = 0: the A_sigma stencil on x
+ * (y receives A_sigma x); 1: the level-1 local solves on the batch left by the
+ * last apply_precond (dense classes: the MFMA GEMM of the classes with many
+ * members; otherwise the block-chain solves), so call apply_precond first;
+ * 2: the whole preconditioner on x (y receives z).  *work receives the
+ * algorithmic work of one launch: bytes for which = 0 (16 per unknown), flops
+ * for which = 1 (2 m^2 per subdomain solved by the kernel: dense inverse
+ * applied once; 4 nch b^2 for block-chain solves), 0 for which = 2. */
+ddeig_status ddeig_profile_kernel(ddeig_problem* P, int which, int reps, const double* x, double* y,
+                                  double* avg_us, double* work);
+
 /* Sizes: interior unknowns, cell unknowns, number of subdomains (= coarse dimension). */
 ddeig_status ddeig_query(const ddeig_problem* P, long* n_dof, long* n_cell, int* n_sub);
 

@@ -660,6 +660,51 @@ void ddeig_destroy(ddeig_problem* P) {
   delete P;
 }
 
+ddeig_status ddeig_profile_kernel(ddeig_problem* P, int which, int reps, const double* x, double* y,
+                                  double* avg_us, double* work) {
+  if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
+  if (reps < 1 || which < 0 || which > 2 || !avg_us) return set_error(DDEIG_EINVAL, "invalid arguments");
+  if ((which == 0 || which == 2) && (validate_vec(x, "x") || validate_vec(y, "y"))) return DDEIG_EINVAL;
+  if (!P->shifted) return set_error(DDEIG_ESTATE, "profile_kernel before the shift is set");
+  API_GUARD_BEGIN
+  const hipStream_t s = P->stream;
+  double w = 0.0;
+  if (which == 0) {
+    w = 16.0 * (double)P->g.n;
+  } else if (which == 1) {
+    for (auto& t : P->types) {
+      const double m = (double)t.box.nch * t.box.b;
+      if (P->opt.local_prec >= 2) {
+        if (t.nmem > ddeig::kGemvMax) w += 2.0 * m * m * t.nmem;
+      } else {
+        w += 4.0 * t.box.nch * (double)t.box.b * t.box.b * t.nmem;
+      }
+    }
+  }
+  auto launch = [&]() {
+    if (which == 0) launch_stencil(P, P->tabAs, x, y, nullptr, nullptr, s);
+    else if (which == 1) launch_local_solves(P, nullptr, s);
+    else precond_apply(P, x, y, nullptr, nullptr, nullptr);
+  };
+  launch();
+  hipEvent_t e0, e1;
+  check_hip(hipEventCreate(&e0), "event");
+  check_hip(hipEventCreate(&e1), "event");
+  check_hip(hipEventRecord(e0, s), "record");
+  for (int i = 0; i < reps; ++i) launch();
+  check_hip(hipEventRecord(e1, s), "record");
+  check_hip(hipEventSynchronize(e1), "event sync");
+  float ms = 0.0f;
+  check_hip(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  check_launch("profile kernel");
+  *avg_us = 1000.0 * ms / reps;
+  if (work) *work = w;
+  return DDEIG_OK;
+  API_GUARD_END
+}
+
 ddeig_status ddeig_query(const ddeig_problem* P, long* n_dof, long* n_cell, int* n_sub) {
   if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
   if (n_dof) *n_dof = P->g.n;

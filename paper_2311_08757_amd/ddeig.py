@@ -58,8 +58,9 @@ class EigInfo(ctypes.Structure):
 
 
 EXPORTS = ["ddeig_assemble", "ddeig_cell_shift", "ddeig_set_shift", "ddeig_apply_op",
-           "ddeig_apply_precond", "ddeig_pcg_solve", "ddeig_inverse_iteration", "ddeig_query",
-           "ddeig_destroy", "ddeig_status_string", "ddeig_last_error"]
+           "ddeig_apply_precond", "ddeig_pcg_solve", "ddeig_inverse_iteration",
+           "ddeig_profile_kernel", "ddeig_query", "ddeig_destroy", "ddeig_status_string",
+           "ddeig_last_error"]
 
 _lib = None
 
@@ -85,6 +86,7 @@ def load_library(path=LIB_PATH):
                                     ctypes.POINTER(PcgInfo)]
     lib.ddeig_inverse_iteration.argtypes = [P, P, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                             ctypes.c_int, ctypes.POINTER(EigInfo)]
+    lib.ddeig_profile_kernel.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, dp, dp]
     lib.ddeig_query.argtypes = [P, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long),
                                 ctypes.POINTER(ctypes.c_int)]
     lib.ddeig_destroy.argtypes = [P]
@@ -284,3 +286,16 @@ def inverse_iteration(prob, x, tol_x=1e-9, maxit_outer=100, rtol_inner=1e-10, ma
 
 def status_string(code):
     return load_library().ddeig_status_string(int(code)).decode()
+
+
+def profile_kernel(prob, which, reps=20, x=None, y=None):
+    """ddeig_profile_kernel: mean launch time (us) of one hot kernel and its algorithmic work."""
+    lib = load_library()
+    avg = ctypes.c_double()
+    work = ctypes.c_double()
+    xp = _ptr(x, prob.n_dof, "x") if x is not None else None
+    yp = _ptr(y, prob.n_dof, "y") if y is not None else None
+    w = {"stencil": 0, "local": 1, "precond": 2}[which] if isinstance(which, str) else int(which)
+    _check(lib.ddeig_profile_kernel(prob.handle, w, int(reps), xp, yp, ctypes.byref(avg),
+                                    ctypes.byref(work)), "ddeig_profile_kernel")
+    return avg.value, work.value
