@@ -165,14 +165,17 @@ ddeig_status finish_shift(ddeig_problem* P) {
 }
 
 // restrict -> {local solves | boundary GEMV + coarse solve on the second
-// stream} -> extend.  chk (nullable) folds the PCG stopping test into the
-// restriction.
-void precond_apply(ddeig_problem* P, const double* r, double* z, Red* dot, PcgState* st,
-                   const CheckArgs* chk = nullptr) {
+// stream} -> extend.  xr (nullable) fuses the CG update of x and r into the
+// restriction (partials of ||r||^2 into *rr); chk (nullable) folds the PCG
+// stopping test into the extension.
+void precond_apply(ddeig_problem* P, double* r, double* z, Red* dot, PcgState* st,
+                   const XrArgs* xr = nullptr, Red* rr = nullptr, const CheckArgs* chk = nullptr) {
   const int coarse = P->opt.coarse;
-  CheckArgs off{};
-  off.on = 0;
-  launch_restrict(P, r, coarse, st, chk ? *chk : off, P->stream);
+  XrArgs xoff{};
+  xoff.on = 0;
+  CheckArgs coff{};
+  coff.on = 0;
+  launch_restrict(P, r, st, xr ? *xr : xoff, rr, P->stream);
   const bool side = coarse || (P->opt.local_prec >= 2 && P->ngemv > 0);
   if (side) {
     check_hip(hipEventRecord(P->ev_fork, P->stream), "record fork");
@@ -188,7 +191,9 @@ void precond_apply(ddeig_problem* P, const double* r, double* z, Red* dot, PcgSt
     check_hip(hipEventRecord(P->ev_join, P->aux), "record join");
     check_hip(hipStreamWaitEvent(P->stream, P->ev_join, 0), "wait join");
   }
-  launch_extend(P, r, z, coarse, dot, st, P->stream);
+  CheckArgs c = chk ? *chk : coff;
+  if (chk && rr) c.rr = *rr;
+  launch_extend(P, r, z, coarse, dot, st, c, P->stream);
 }
 
 struct PcgOut {
@@ -197,7 +202,11 @@ struct PcgOut {
   int done = 0;
 };
 
-// PCG on A_sigma x = b (x holds x0).  Queues `batch` iterations between host checks.
+// PCG on A_sigma x = b (x holds x0).  One iteration is four kernels on the
+// library stream: the stencil with the direction update, the restriction with
+// the x / r update, the local solves and the extension with the stopping test
+// (plus the coarse solve on the second stream).  `batch` iterations are queued
+// between host checks of the device state.
 PcgOut pcg_run(ddeig_problem* P, const double* b, double* x, double rtol, int maxit) {
   const hipStream_t s = P->stream;
   const int batch = P->opt.batch_iters > 0 ? P->opt.batch_iters : 8;
@@ -206,7 +215,6 @@ PcgOut pcg_run(ddeig_problem* P, const double* b, double* x, double rtol, int ma
   launch_resid_init(P, b, P->q, P->r, rr, s);
   launch_pcg_init(P, rtol, rr, s);
   precond_apply(P, P->r, P->z, &rz, P->st);
-  launch_pcg_start(P, P->z, P->p, rz, s);
   check_launch("pcg start");
   PcgState hs{};
   int k = 0;
@@ -217,11 +225,13 @@ PcgOut pcg_run(ddeig_problem* P, const double* b, double* x, double rtol, int ma
   while (k < maxit) {
     const int kend = std::min(maxit, k + batch);
     for (++k; k <= kend; ++k) {
-      launch_stencil(P, P->tabAs, P->p, P->q, &g, nullptr, s);
-      launch_pcg_update_xr(P, x, P->p, P->q, P->r, g, rr, k, maxit, s);
+      double* pold = P->pp[(k - 1) & 1];
+      double* pnew = P->pp[k & 1];
+      const DirArgs dir{P->st, k, rz};
+      launch_stencil_dir(P, P->z, pold, pnew, P->q, dir, g, s);
+      const XrArgs xr{1, k, g, x, pnew, P->q};
       const CheckArgs chk{1, k, maxit, P->hist_cap, rr, P->hist};
-      precond_apply(P, P->r, P->z, &rz, P->st, &chk);
-      launch_pcg_update_p(P, P->z, P->p, rz, k, s);
+      precond_apply(P, P->r, P->z, &rz, P->st, &xr, &rr, &chk);
     }
     --k;
     check_launch("pcg iteration");
@@ -570,7 +580,8 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
                              hipMemcpyHostToDevice, s), "copy types");
     P->r = dalloc<double>(P, n);
     P->z = dalloc<double>(P, n);
-    P->p = dalloc<double>(P, n);
+    P->pp[0] = dalloc<double>(P, n);
+    P->pp[1] = dalloc<double>(P, n);
     P->q = dalloc<double>(P, n);
     P->u = dalloc<double>(P, n);
     P->w = dalloc<double>(P, n);
@@ -684,7 +695,7 @@ ddeig_status ddeig_profile_kernel(ddeig_problem* P, int which, int reps, const d
   auto launch = [&]() {
     if (which == 0) launch_stencil(P, P->tabAs, x, y, nullptr, nullptr, s);
     else if (which == 1) launch_local_solves(P, nullptr, s);
-    else precond_apply(P, x, y, nullptr, nullptr, nullptr);
+    else precond_apply(P, const_cast<double*>(x), y, nullptr, nullptr);
   };
   launch();
   hipEvent_t e0, e1;
@@ -817,7 +828,7 @@ ddeig_status ddeig_apply_precond(ddeig_problem* P, const double* r, double* z) {
   if (r == z) return set_error(DDEIG_EINVAL, "r and z must not alias");
   if (!P->shifted) return set_error(DDEIG_ESTATE, "apply_precond before the shift is set");
   API_GUARD_BEGIN
-  precond_apply(P, r, z, nullptr, nullptr, nullptr);
+  precond_apply(P, const_cast<double*>(r), z, nullptr, nullptr);
   check_launch("apply_precond");
   return DDEIG_OK;
   API_GUARD_END

@@ -212,7 +212,8 @@ struct ddeig_problem {
   double* crhs = nullptr;   // nsub
   double* cy = nullptr;     // nsub
   // work vectors (n each)
-  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *u = nullptr, *w = nullptr;
+  double *r = nullptr, *z = nullptr, *q = nullptr, *u = nullptr, *w = nullptr;
+  double* pp[2] = {nullptr, nullptr};  // CG directions of even / odd iterations
   double* red_part = nullptr;   // kRedSlots x kMaxRed partial sums
   double* red_val = nullptr;    // kRedSlots results
   ddeig::PcgState* st = nullptr;
@@ -231,10 +232,18 @@ namespace ddeig {
 // ---- kernels' host launchers (k_*.hip) ------------------------------------
 void launch_build_tables(const ddeig_problem* P, hipStream_t s);
 void launch_shift_table(const ddeig_problem* P, hipStream_t s);
-// y = T x (T one of the tables); dot != nullptr: partial sums of x.y into dot[0..kRedBlocks)
+// y = T x (T one of the tables); dot / sum != nullptr: partial sums of x.y / of y
 void launch_stencil(const ddeig_problem* P, const double* tab, const double* x, double* y,
                     Red* dot, Red* sum, hipStream_t s);
-// box operator (cell problem): y = T x on a periodic box, partials of x.y and sum(y)
+// PCG iteration k, first kernel: p_k = z + beta_k p_{k-1} (p_1 = z) into pnew,
+// q = A_sigma p_k, partials of p_k.q into gam.
+struct DirArgs {
+  PcgState* st;
+  int k;
+  Red rz;  // partials of r_{k-1}.z_{k-1}
+};
+void launch_stencil_dir(const ddeig_problem* P, const double* z, const double* pold, double* pnew,
+                        double* q, const DirArgs& dir, Red& gam, hipStream_t s);
 void launch_box_stencil(const ddeig_problem* P, const Box& bx, const double* tab, const double* x,
                         double* y, Red* dot, Red* sum, hipStream_t s);
 
@@ -246,21 +255,31 @@ void launch_chain_solve_box(const ddeig_problem* P, const Box& bx, const double*
                             const double* W, double* v, int nrhs, hipStream_t s);
 
 // preconditioner pieces
-// Convergence test folded into the restriction (PCG iteration k): the first
-// workgroup adds the ||r||^2 partials and updates the state.
+// PCG iteration k, update fused into the restriction: alpha = rho_{k-1} / gamma
+// with gamma = p_k.q from the stencil's partials; x += alpha p_k,
+// r -= alpha q, partials of ||r||^2 into rr.
+struct XrArgs {
+  int on, k;
+  Red gam;
+  double* x;
+  const double* p;
+  const double* q;
+};
+// Stopping test of PCG iteration k folded into the extension: the kernel adds
+// the ||r_k||^2 partials, records the history and ends CG on convergence or at maxit.
 struct CheckArgs {
   int on, k, maxit, hist_cap;
   Red rr;
   double* hist;
 };
-void launch_restrict(const ddeig_problem* P, const double* r, int coarse, PcgState* st,
-                     const CheckArgs& chk, hipStream_t s);
+void launch_restrict(const ddeig_problem* P, double* r, PcgState* st, const XrArgs& xr, Red* rr,
+                     hipStream_t s);
 void launch_local_solves(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 void launch_coarse_solve(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 void launch_coarse_rhs(const ddeig_problem* P, const double* r, const PcgState* st, hipStream_t s);
 void launch_coarse_phi(const ddeig_problem* P, hipStream_t s);
 void launch_extend(const ddeig_problem* P, const double* r, double* z, int coarse, Red* dot,
-                   const PcgState* st, hipStream_t s);
+                   PcgState* st, const CheckArgs& chk, hipStream_t s);
 void launch_symmetrise(double* A, int N, hipStream_t s);
 void launch_split_inverse(const double* Ainv, int m, int ld, void* Ah, void* Al, hipStream_t s);
 void launch_identity(double* v, int m, hipStream_t s);
@@ -275,13 +294,6 @@ void launch_resid_init(const ddeig_problem* P, const double* b, const double* q,
                        Red& rr, hipStream_t s);
 void launch_finish_sum(const Red& r, hipStream_t s);
 void launch_pcg_init(const ddeig_problem* P, double rtol, Red rr, hipStream_t s);
-void launch_pcg_start(const ddeig_problem* P, const double* z, double* p, Red rz, hipStream_t s);
-void launch_pcg_update_xr(const ddeig_problem* P, double* x, const double* pvec,
-                          const double* qvec, double* r, Red g, Red& rr, int k, int maxit,
-                          hipStream_t s);
-void launch_pcg_check(const ddeig_problem* P, Red rr, int k, int maxit, hipStream_t s);
-void launch_pcg_update_p(const ddeig_problem* P, const double* z, double* pvec, Red rz, int k,
-                         hipStream_t s);
 void launch_fill(double* x, long n, double v, hipStream_t s);
 void launch_copy(double* dst, const double* src, long n, hipStream_t s);
 void launch_scale_copy(long n, double* dst, const double* src, Red nrm2, hipStream_t s);

@@ -114,64 +114,172 @@ void launch_shift_table(const ddeig_problem* P, hipStream_t s) {
                      P->sigma, P->tabAs);
 }
 
-// y = T x over all interior unknowns of Omega_L; neighbours on the Dirichlet
-// boundary are eliminated (skipped).  Work items are row segments of kBlock
-// consecutive x1 positions (one grid line of dims 1..D-1 each), visited
-// grid-stride by a fixed grid of kRedBlocks workgroups, so the index
-// arithmetic is one division per segment.  Optional partial sums of x.y and of y.
+// y = T x over all interior unknowns of Omega_L, as an LDS-staged tile sweep.
+// A workgroup takes a TX x TY (x TZ) box of unknowns at a time: it stages the
+// box plus a one-node halo of the input in LDS (coalesced row loads; nodes on
+// the Dirichlet boundary or outside Omega_L are staged as zero, which removes
+// their taps), then each wave applies the 3^D stencil to whole rows of the box
+// from LDS.  Lane l owns the x1 positions l + 64 s of a row; when n_e divides
+// 64 these share one cell-local position, so the row's 3^D table coefficients
+// are loaded once per lane and reused across the 64-node strides.  Taps are
+// added in the order t = 0 .. 3^D - 1 for every node.
+//
+// MODE 1 fuses the direction update of preconditioned CG (§3,
+// eq:cg-energy-norm-error-reduction): the staged vector is
+// p_k = z_{k-1} + beta_k p_{k-1}, beta_k = rho_{k-1} / rho_{k-2} (p_1 = z_0),
+// with rho_{k-1} = r_{k-1}.z_{k-1} from the partial sums of the extension;
+// the owned nodes of p_k are written to a second buffer (other tiles still
+// read p_{k-1} in their halos), and the sweep returns q = A_sigma p_k with the
+// partials of p_k.q.  A non-positive rho ends CG with a breakdown.
 template <int D>
+struct TileShape;
+template <>
+struct TileShape<2> {
+  static constexpr int TX = 256, TY = 8, TZ = 1;
+};
+template <>
+struct TileShape<3> {
+  static constexpr int TX = 64, TY = 4, TZ = 4;
+};
+
+template <int D, int MODE>
 __global__ void __launch_bounds__(kBlock) k_stencil(Geo g, const double* __restrict__ T,
                                                     const double* __restrict__ x,
-                                                    double* __restrict__ y, int use_dot, Red dot,
-                                                    int use_sum, Red sum) {
-  double acc = 0.0, accs = 0.0;
+                                                    const double* __restrict__ pold,
+                                                    double* __restrict__ pnew,
+                                                    double* __restrict__ y, DirArgs dir,
+                                                    int use_dot, Red dot, int use_sum, Red sum) {
+  constexpr int TX = TileShape<D>::TX, TY = TileShape<D>::TY, TZ = TileShape<D>::TZ;
+  constexpr int HX = TX + 2, HY = TY + 2, HZ = D == 3 ? TZ + 2 : 1;
+  constexpr int NT = D == 2 ? 9 : 27;
+  constexpr int RX = TX / 64;
+  __shared__ double sv[HX * HY * HZ];
+  double beta = 0.0;
+  if constexpr (MODE == 1) {
+    const double rho = sum_partials(dir.rz.part, dir.rz.np);
+    if (dir.st->done) return;
+    if (!(rho > 0.0)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        dir.st->done = 3;
+        dir.st->iters = dir.k - 1;
+      }
+      return;
+    }
+    if (dir.k > 1) beta = rho / dir.st->rho[(dir.k - 2) & 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) dir.st->rho[(dir.k - 1) & 1] = rho;
+  }
   const int N0 = g.N[0], N1 = g.N[1], N2 = g.N[2];
   const long N01 = (long)N0 * N1;
-  const int segs = (N0 + kBlock - 1) / kBlock;
-  const long items = (long)segs * N1 * N2;
+  const int nbx = (N0 + TX - 1) / TX, nby = (N1 + TY - 1) / TY;
+  const int nbz = D == 3 ? (N2 + TZ - 1) / TZ : 1;
+  const long ntiles = (long)nbx * nby * nbz;
   const long tsize = g.tsize;
-  for (long it = blockIdx.x; it < items; it += gridDim.x) {
-    const int line = (int)(it / segs);
-    const int i0 = (int)(it - (long)line * segs) * kBlock + threadIdx.x;
-    if (i0 >= N0) continue;
-    // line = i1r + N1 i2
-    const int i2 = D == 3 ? (int)fdiv((unsigned)line, g.fN1) : 0;
-    const int i1r = line - i2 * N1;
-    const long k = i0 + (long)N0 * line;
-    const int j0 = (int)((unsigned)(i0 + 1) - g.ne * fdiv((unsigned)(i0 + 1), g.fne));
-    int j1 = i1r;
-    if (g.isx[1]) j1 = (int)((unsigned)(i1r + 1) - g.ne * fdiv((unsigned)(i1r + 1), g.fne));
-    const long tn = j0 + (long)g.P[0] * (j1 + (long)g.P[1] * i2);
-    double s = 0.0;
-#pragma unroll
-    for (int t = 0; t < (D == 2 ? 9 : 27); ++t) {
-      const int d0 = t % 3 - 1, d1 = (t / 3) % 3 - 1, d2 = (D == 2) ? 0 : t / 9 - 1;
-      const bool in = (i0 + d0 >= 0) && (i0 + d0 < N0) && (i1r + d1 >= 0) && (i1r + d1 < N1) &&
-                      (D == 2 || ((i2 + d2 >= 0) && (i2 + d2 < N2)));
-      if (in) s += T[t * tsize + tn] * x[k + d0 + (long)N0 * d1 + N01 * d2];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double acc = 0.0, accs = 0.0;
+  for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int bx = (int)(tile % nbx);
+    const long rest = tile / nbx;
+    const int by = (int)(rest % nby), bz = (int)(rest / nby);
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+    __syncthreads();  // the previous tile's reads of sv are complete
+    for (int e = threadIdx.x; e < HX * HY * HZ; e += kBlock) {
+      const int ex = e % HX, er = e / HX;
+      const int ey = er % HY, ez = er / HY;
+      const int gx = x0 - 1 + ex, gy = y0 - 1 + ey, gz = D == 3 ? z0 - 1 + ez : 0;
+      double v = 0.0;
+      if (gx >= 0 && gx < N0 && gy >= 0 && gy < N1 && gz >= 0 && gz < N2) {
+        const long k = gx + (long)N0 * gy + N01 * gz;
+        v = x[k];
+        if constexpr (MODE == 1) {
+          if (dir.k > 1) v += beta * pold[k];
+          const bool own = ex >= 1 && ex <= TX && ey >= 1 && ey <= TY &&
+                           (D == 2 || (ez >= 1 && ez <= TZ));
+          if (own) pnew[k] = v;
+        }
+      }
+      sv[e] = v;
     }
-    y[k] = s;
-    acc += x[k] * s;
-    accs += s;
+    __syncthreads();
+    for (int row = w; row < TY * TZ; row += kBlock / 64) {
+      const int ty = row % TY, tz = row / TY;
+      const int gy = y0 + ty, gz = z0 + tz;
+      if (gy >= N1 || (D == 3 && gz >= N2)) continue;
+      const int j1 = g.isx[1] ? (int)((unsigned)(gy + 1) - g.ne * fdiv((unsigned)(gy + 1), g.fne)) : gy;
+      int j2 = 0;
+      if constexpr (D == 3)
+        j2 = g.isx[2] ? (int)((unsigned)(gz + 1) - g.ne * fdiv((unsigned)(gz + 1), g.fne)) : gz;
+      const long trow = (long)g.P[0] * (j1 + (long)g.P[1] * j2);
+      double c[NT];
+      long tn_prev = -1;
+#pragma unroll
+      for (int s = 0; s < RX; ++s) {
+        const int gx = x0 + lane + 64 * s;
+        if (gx >= N0) continue;
+        const int j0 = (int)((unsigned)(gx + 1) - g.ne * fdiv((unsigned)(gx + 1), g.fne));
+        const long tn = j0 + trow;
+        if (tn != tn_prev) {
+#pragma unroll
+          for (int t = 0; t < NT; ++t) c[t] = T[t * tsize + tn];
+          tn_prev = tn;
+        }
+        const int cx = lane + 64 * s + 1;
+        double a = 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int d0 = t % 3 - 1, d1 = (t / 3) % 3 - 1, d2 = D == 2 ? 0 : t / 9 - 1;
+          a += c[t] * sv[(cx + d0) + HX * ((ty + 1 + d1) + HY * (D == 3 ? tz + 1 + d2 : 0))];
+        }
+        const long k = gx + (long)N0 * gy + N01 * gz;
+        y[k] = a;
+        acc += sv[cx + HX * ((ty + 1) + HY * (D == 3 ? tz + 1 : 0))] * a;
+        accs += a;
+      }
+    }
   }
   if (use_dot) write_partial(acc, dot.part);
   if (use_sum) write_partial(accs, sum.part);
 }
 
+int stencil_grid(const Geo& g) {
+  long nt;
+  if (g.D == 2)
+    nt = (long)((g.N[0] + TileShape<2>::TX - 1) / TileShape<2>::TX) *
+         ((g.N[1] + TileShape<2>::TY - 1) / TileShape<2>::TY);
+  else
+    nt = (long)((g.N[0] + TileShape<3>::TX - 1) / TileShape<3>::TX) *
+         ((g.N[1] + TileShape<3>::TY - 1) / TileShape<3>::TY) *
+         ((g.N[2] + TileShape<3>::TZ - 1) / TileShape<3>::TZ);
+  return (int)std::max<long>(1, std::min<long>(nt, kMaxRed));
+}
+
 void launch_stencil(const ddeig_problem* P, const double* tab, const double* x, double* y,
                     Red* dot, Red* sum, hipStream_t s) {
-  const long segs = (P->g.N[0] + kBlock - 1) / kBlock;
-  const long items = segs * P->g.N[1] * P->g.N[2];
-  const int blocks = (int)std::min<long>(items, kMaxRed);
+  const int blocks = stencil_grid(P->g);
   const Red none{nullptr, 0, nullptr};
+  const DirArgs nodir{nullptr, 0, none};
   if (dot) dot->np = blocks;
   if (sum) sum->np = blocks;
   if (P->g.D == 2)
-    hipLaunchKernelGGL(k_stencil<2>, dim3(blocks), dim3(kBlock), 0, s, P->g, tab, x, y,
-                       dot ? 1 : 0, dot ? *dot : none, sum ? 1 : 0, sum ? *sum : none);
+    hipLaunchKernelGGL((k_stencil<2, 0>), dim3(blocks), dim3(kBlock), 0, s, P->g, tab, x,
+                       nullptr, nullptr, y, nodir, dot ? 1 : 0, dot ? *dot : none, sum ? 1 : 0,
+                       sum ? *sum : none);
   else
-    hipLaunchKernelGGL(k_stencil<3>, dim3(blocks), dim3(kBlock), 0, s, P->g, tab, x, y,
-                       dot ? 1 : 0, dot ? *dot : none, sum ? 1 : 0, sum ? *sum : none);
+    hipLaunchKernelGGL((k_stencil<3, 0>), dim3(blocks), dim3(kBlock), 0, s, P->g, tab, x,
+                       nullptr, nullptr, y, nodir, dot ? 1 : 0, dot ? *dot : none, sum ? 1 : 0,
+                       sum ? *sum : none);
+}
+
+void launch_stencil_dir(const ddeig_problem* P, const double* z, const double* pold, double* pnew,
+                        double* q, const DirArgs& dir, Red& gam, hipStream_t s) {
+  const int blocks = stencil_grid(P->g);
+  const Red none{nullptr, 0, nullptr};
+  gam.np = blocks;
+  if (P->g.D == 2)
+    hipLaunchKernelGGL((k_stencil<2, 1>), dim3(blocks), dim3(kBlock), 0, s, P->g, P->tabAs, z,
+                       pold, pnew, q, dir, 1, gam, 0, none);
+  else
+    hipLaunchKernelGGL((k_stencil<3, 1>), dim3(blocks), dim3(kBlock), 0, s, P->g, P->tabAs, z,
+                       pold, pnew, q, dir, 1, gam, 0, none);
 }
 
 // Box operator with periodic wrap in the flagged dims (the cell problem of

@@ -87,41 +87,49 @@ __device__ inline double cover_weight(const Geo& g, int delta, int pu, const XCo
 // Scatter r into the subdomain batches (box natural order; bf16 hi/lo rows for
 // dense classes): node-parallel over row segments of kBlock x1 positions;
 // every node writes its copy into each covering subdomain (at most 2^p), so
-// reads of r and writes of a batch row are both coalesced.  With chk.on the
-// first workgroup also applies the PCG stopping test of iteration k.
+// reads of r and writes of a batch row are both coalesced.  With xr.on the
+// node first takes the CG update of iteration k (x += alpha p, r -= alpha q,
+// written back) and the kernel leaves the partials of ||r||^2 in rr.
 __global__ void __launch_bounds__(kBlock) k_restrict(Geo g, int ntypes, PcgState* __restrict__ st,
-                                                     CheckArgs chk,
-                                                     const double* __restrict__ r,
+                                                     XrArgs xr, Red rr, double* __restrict__ r,
                                                      const TypeDev* __restrict__ types,
                                                      const SubTS* __restrict__ subts,
                                                      const XCover* __restrict__ xc0,
                                                      const XCover* __restrict__ xc1) {
   __shared__ TypeDev stypes[kMaxTypes];
   if (st != nullptr && st->done) return;
-  if (chk.on && blockIdx.x == 0) {
-    // stopping test ||r_k|| <= rtol ||r_0|| of PCG iteration k, with the history;
-    // later kernels of the iteration see `done` and do nothing
-    const double rn2 = sum_partials(chk.rr.part, chk.rr.np);
-    if (threadIdx.x == 0) {
-      st->relres = sqrt(rn2 / st->r0n2);
-      if (chk.hist && chk.k < chk.hist_cap) chk.hist[chk.k] = st->relres;
-      st->iters = chk.k;
-      if (rn2 <= st->tol2) st->done = 1;
-      else if (chk.k >= chk.maxit) st->done = 4;
+  double alpha = 0.0;
+  if (xr.on) {
+    const double gamma = sum_partials(xr.gam.part, xr.gam.np);
+    if (!(gamma > 0.0)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->done = 2;
+        st->iters = xr.k - 1;
+      }
+      return;
     }
+    alpha = st->rho[(xr.k - 1) & 1] / gamma;
   }
   if (threadIdx.x < ntypes) stypes[threadIdx.x] = types[threadIdx.x];
   __syncthreads();
   const int N0 = g.N[0], N1 = g.N[1];
   const int segs = (N0 + kBlock - 1) / kBlock;
   const long items = (long)segs * N1 * g.N[2];
+  double acc = 0.0;
   for (long it = blockIdx.x; it < items; it += gridDim.x) {
     const int line = (int)(it / segs);
     const int i0 = (int)(it - (long)line * segs) * kBlock + threadIdx.x;
     if (i0 >= N0) continue;
     const int i2 = g.D == 3 ? (int)fdiv((unsigned)line, g.fN1) : 0;
     const int i1 = line - i2 * N1;
-    const double rv = r[i0 + (long)N0 * line];
+    const long k = i0 + (long)N0 * line;
+    double rv = r[k];
+    if (xr.on) {
+      rv -= alpha * xr.q[k];
+      xr.x[k] += alpha * xr.p[k];
+      r[k] = rv;
+      acc += rv * rv;
+    }
     const __bf16 hi = (__bf16)(float)rv;
     const __bf16 lo = (__bf16)(float)(rv - (double)(float)hi);
     const XCover a0 = xc0[i0];
@@ -145,16 +153,18 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Geo g, int ntypes, PcgState
       }
     }
   }
+  if (xr.on) write_partial(acc, rr.part);
 }
 
-void launch_restrict(const ddeig_problem* P, const double* r, int coarse, PcgState* st,
-                     const CheckArgs& chk, hipStream_t s) {
-  (void)coarse;
+void launch_restrict(const ddeig_problem* P, double* r, PcgState* st, const XrArgs& xr, Red* rr,
+                     hipStream_t s) {
   const long segs = (P->g.N[0] + kBlock - 1) / kBlock;
   const long items = segs * P->g.N[1] * P->g.N[2];
-  const int blocks = (int)std::min<long>(items, 16384);
+  const int blocks = (int)std::min<long>(items, xr.on ? kMaxRed : 16384);
+  const Red none{nullptr, 0, nullptr};
+  if (xr.on) rr->np = blocks;
   hipLaunchKernelGGL(k_restrict, dim3(blocks), dim3(kBlock), 0, s, P->g, (int)P->types.size(),
-                     st, chk, r, P->dTypes, P->dSubTS, P->dXC[0], P->dXC[1]);
+                     st, xr, xr.on ? *rr : none, r, P->dTypes, P->dSubTS, P->dXC[0], P->dXC[1]);
 }
 
 // c_sub = phi_class . R_sub r  (R_0 r of def:algebraic-perfact-coarse-space):
@@ -237,10 +247,14 @@ void launch_coarse_solve(const ddeig_problem* P, const PcgState* st, hipStream_t
 }
 
 // z = sum_c R_c^T y_c (+ R_0^T y0), partials of r.z.  Work items are row
-// segments of kBlock x1 positions (as in the stencil); the covering cells of
-// a node come from the per-axis tables and are summed in a fixed order.
+// segments of kBlock x1 positions (as in the restriction); the covering cells
+// of a node come from the per-axis tables and are summed in a fixed order.
+// With chk.on the kernel first applies the stopping test of PCG iteration k,
+// ||r_k|| <= rtol ||r_0|| (§4.1), records the history and, once CG stops,
+// does nothing else (every later kernel of the iteration sees `done`).
 __global__ void __launch_bounds__(kBlock) k_extend(Geo g, int delta, int pu, int coarse,
-                                                   int ntypes, const PcgState* __restrict__ st,
+                                                   int ntypes, PcgState* __restrict__ st,
+                                                   CheckArgs chk,
                                                    const TypeDev* __restrict__ types,
                                                    const SubTS* __restrict__ subts,
                                                    const XCover* __restrict__ xc0,
@@ -252,6 +266,18 @@ __global__ void __launch_bounds__(kBlock) k_extend(Geo g, int delta, int pu, int
                                                    Red dot) {
   __shared__ TypeDev stypes[kMaxTypes];
   if (st != nullptr && st->done) return;
+  if (chk.on) {
+    const double rn2 = sum_partials(chk.rr.part, chk.rr.np);
+    const bool conv = rn2 <= st->tol2, last = chk.k >= chk.maxit;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->relres = sqrt(rn2 / st->r0n2);
+      if (chk.hist && chk.k < chk.hist_cap) chk.hist[chk.k] = st->relres;
+      st->iters = chk.k;
+      if (conv) st->done = 1;
+      else if (last) st->done = 4;
+    }
+    if (conv || last) return;
+  }
   if (threadIdx.x < ntypes) stypes[threadIdx.x] = types[threadIdx.x];
   __syncthreads();
   const XCover* xc[2] = {xc0, xc1};
@@ -304,14 +330,15 @@ __global__ void __launch_bounds__(kBlock) k_extend(Geo g, int delta, int pu, int
 }
 
 void launch_extend(const ddeig_problem* P, const double* r, double* z, int coarse, Red* dot,
-                   const PcgState* st, hipStream_t s) {
+                   PcgState* st, const CheckArgs& chk, hipStream_t s) {
   const long segs = (P->g.N[0] + kBlock - 1) / kBlock;
   const long items = segs * P->g.N[1] * P->g.N[2];
   const int blocks = (int)std::min<long>(items, kMaxRed);
   const Red none{nullptr, 0, nullptr};
   if (dot) dot->np = blocks;
   hipLaunchKernelGGL(k_extend, dim3(blocks), dim3(kBlock), 0, s, P->g, P->delta, P->opt.pu,
-                     coarse, (int)P->types.size(), st, P->dTypes, P->dSubTS, P->dXC[0], P->dXC[1],
+                     coarse, (int)P->types.size(), st, chk, P->dTypes, P->dSubTS, P->dXC[0],
+                     P->dXC[1],
                      P->psi, P->cy, r, z,
                      dot ? 1 : 0, dot ? *dot : none);
 }

@@ -1,11 +1,13 @@
-// Vector kernels of preconditioned CG (§3 eq:cg-energy-norm-error-reduction,
-// stopping rule of §4.1) and of the shifted inverse iteration with
-// B-normalisation (§2).  Scalars stay on the device: a kernel that needs a
-// global sum adds the per-block partials of the kernel before it in a fixed
-// order (Red), so no host round trip is needed inside an iteration and sums
-// are deterministic.  After convergence or breakdown the state's `done` flag
-// turns every later iteration kernel into a no-op, so the host can queue
-// several iterations between checks.
+// Vector kernels of the start of preconditioned CG (§3
+// eq:cg-energy-norm-error-reduction, stopping rule of §4.1) and of the shifted
+// inverse iteration with B-normalisation (§2).  The CG iteration itself is
+// fused into the stencil (direction update), the restriction (x and r update)
+// and the extension (stopping test).  Scalars stay on the device: a kernel
+// that needs a global sum adds the per-block partials of the kernel before it
+// in a fixed order (Red), so no host round trip is needed inside an iteration
+// and sums are deterministic.  After convergence or breakdown the state's
+// `done` flag turns every later iteration kernel into a no-op, so the host can
+// queue several iterations between checks.
 #include "k_common.h"
 
 namespace ddeig {
@@ -58,101 +60,6 @@ __global__ void k_pcg_init(PcgState* st, double rtol, Red rr, double* __restrict
 
 void launch_pcg_init(const ddeig_problem* P, double rtol, Red rr, hipStream_t s) {
   hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(kBlock), 0, s, P->st, rtol, rr, P->hist);
-}
-
-// p = z, rho_0 = r.z
-__global__ void k_pcg_start(long n, PcgState* st, const double* __restrict__ z,
-                            double* __restrict__ p, Red rz) {
-  const double rho = sum_partials(rz.part, rz.np);
-  if (st->done) return;
-  if (!(rho > 0.0)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 3;
-    return;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->rho[0] = rho;
-  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n;
-       k += (long)gridDim.x * blockDim.x)
-    p[k] = z[k];
-}
-
-void launch_pcg_start(const ddeig_problem* P, const double* z, double* p, Red rz, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_start, dim3(red_grid(P->g.n)), dim3(kBlock), 0, s, P->g.n, P->st, z,
-                     p, rz);
-}
-
-// Iteration k: alpha = rho_{k-1} / (p.q); x += alpha p; r -= alpha q; partials of ||r||^2.
-__global__ void k_pcg_update_xr(long n, PcgState* st, int k, double* __restrict__ x,
-                                const double* __restrict__ p, const double* __restrict__ q,
-                                double* __restrict__ r, Red g, Red rr) {
-  if (st->done) return;
-  const double gamma = sum_partials(g.part, g.np);
-  if (!(gamma > 0.0)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      st->done = 2;
-      st->iters = k - 1;
-    }
-    return;
-  }
-  const double alpha = st->rho[(k - 1) & 1] / gamma;
-  double acc = 0.0;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
-       i += (long)gridDim.x * blockDim.x) {
-    x[i] += alpha * p[i];
-    const double rv = r[i] - alpha * q[i];
-    r[i] = rv;
-    acc += rv * rv;
-  }
-  write_partial(acc, rr.part);
-}
-
-void launch_pcg_update_xr(const ddeig_problem* P, double* x, const double* pvec,
-                          const double* qvec, double* r, Red g, Red& rr, int k, int maxit,
-                          hipStream_t s) {
-  (void)maxit;
-  rr.np = red_grid(P->g.n);
-  hipLaunchKernelGGL(k_pcg_update_xr, dim3(rr.np), dim3(kBlock), 0, s, P->g.n, P->st, k, x, pvec,
-                     qvec, r, g, rr);
-}
-
-// Stopping test ||r_k|| <= rtol ||r_0|| after the update of iteration k; history.
-__global__ void k_pcg_check(PcgState* st, int k, int maxit, Red rr, double* __restrict__ hist,
-                            int hist_cap) {
-  if (st->done) return;
-  const double rn2 = sum_partials(rr.part, rr.np);
-  if (threadIdx.x == 0) {
-    st->relres = sqrt(rn2 / st->r0n2);
-    if (hist && k < hist_cap) hist[k] = st->relres;
-    st->iters = k;
-    if (rn2 <= st->tol2) st->done = 1;
-    else if (k >= maxit) st->done = 4;
-  }
-}
-
-void launch_pcg_check(const ddeig_problem* P, Red rr, int k, int maxit, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(kBlock), 0, s, P->st, k, maxit, rr, P->hist,
-                     P->hist_cap);
-}
-
-// beta = rho_k / rho_{k-1}; p = z + beta p.
-__global__ void k_pcg_update_p(long n, PcgState* st, int k, const double* __restrict__ z,
-                               double* __restrict__ p, Red rz) {
-  const double rho = sum_partials(rz.part, rz.np);
-  if (st->done) return;
-  if (!(rho > 0.0)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 3;
-    return;
-  }
-  const double beta = rho / st->rho[(k - 1) & 1];
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
-       i += (long)gridDim.x * blockDim.x)
-    p[i] = z[i] + beta * p[i];
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->rho[k & 1] = rho;
-}
-
-void launch_pcg_update_p(const ddeig_problem* P, const double* z, double* pvec, Red rz, int k,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_update_p, dim3(red_grid(P->g.n)), dim3(kBlock), 0, s, P->g.n, P->st,
-                     k, z, pvec, rz);
 }
 
 __global__ void k_fill(double* x, long n, double v) {
