@@ -458,6 +458,9 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
     // members, K split so that the grouped GEMM has enough workgroups; the
     // small (boundary) classes use the streaming matrix-vector kernel
     auto big = [](const ddeig::SubType& T) { return T.nmem > ddeig::kGemvMax; };
+    // K columns per GEMM stage (the kernel's pipeline depth): 64 with a single
+    // bf16 inverse, 32 with the hi/lo pair
+    const int bk = o.local_prec == 2 ? 32 : 64;
     if (dense) {
       long tiles = 0;
       int minkb = 1 << 30;
@@ -467,12 +470,15 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
         T.mp = big(T) ? (T.nmem + 127) / 128 * 128 : ddeig::kGemvMax;
         if (big(T)) {
           tiles += (long)(T.mp / 128) * (T.ld / 128);
-          minkb = std::min(minkb, T.ld / 32);
+          minkb = std::min(minkb, T.ld / bk / 2);
         }
       }
       if (tiles > 0)
         P->ksplit = (int)std::max<long>(1, std::min<long>(std::min(3, minkb), (256 + tiles - 1) / tiles));
     }
+    // tiles that read the same rows of an inverse (one group: the member tiles
+    // of one column tile and K split)
+    std::vector<std::vector<ddeig::GemmTile>> groups;
     std::vector<ddeig::GemmTile> tiles;
     std::vector<ddeig::GemvRows> gemv;
     std::vector<ddeig::GemmType> gtypes;
@@ -493,10 +499,10 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
         T.Ah = dalloc<__bf16>(P, aa);
         T.Al = o.local_prec == 2 ? dalloc<__bf16>(P, aa) : nullptr;
         T.Rh = dalloc<__bf16>(P, rr);
-        T.Rl = dalloc<__bf16>(P, rr);
+        T.Rl = o.local_prec == 2 ? dalloc<__bf16>(P, rr) : nullptr;
         T.Z = dalloc<float>(P, (size_t)P->ksplit * rr);
         check_hip(hipMemsetAsync(T.Rh, 0, rr * sizeof(__bf16), s), "memset Rh");
-        check_hip(hipMemsetAsync(T.Rl, 0, rr * sizeof(__bf16), s), "memset Rl");
+        if (T.Rl) check_hip(hipMemsetAsync(T.Rl, 0, rr * sizeof(__bf16), s), "memset Rl");
         T.batch = dalloc<double>(P, 1);
         tdev[t].ld = T.ld;
         tdev[t].ksplit = P->ksplit;
@@ -507,13 +513,17 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
         ddeig::GemmType gt{T.Ah, T.Al, T.Rh, T.Rl, T.Z, (long)rr, T.ld};
         gtypes.push_back(gt);
         if (big(T)) {
-          const int nkb = T.ld / 32;
+          // K split at even stage counts (the kernel multiplies two stages per trip)
+          const int npair = T.ld / bk / 2;
           for (int sp = 0; sp < P->ksplit; ++sp) {
-            const int kb0 = (int)((long)nkb * sp / P->ksplit);
-            const int kb1 = (int)((long)nkb * (sp + 1) / P->ksplit);
-            for (int nt = 0; nt < T.ld / 128; ++nt)
+            const int kb0 = 2 * (int)((long)npair * sp / P->ksplit);
+            const int kb1 = 2 * (int)((long)npair * (sp + 1) / P->ksplit);
+            for (int nt = 0; nt < T.ld / 128; ++nt) {
+              std::vector<ddeig::GemmTile> grp;
               for (int mt = 0; mt < T.mp / 128; ++mt)
-                tiles.push_back(ddeig::GemmTile{(int)t, mt * 128, nt * 128, kb0 * 32, kb1 * 32, sp});
+                grp.push_back(ddeig::GemmTile{(int)t, mt * 128, nt * 128, kb0 * bk, kb1 * bk, sp});
+              groups.push_back(grp);
+            }
           }
         } else {
           tdev[t].ksplit = 1;
@@ -556,6 +566,22 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
       sync(P);
     }
     if (dense) {
+      // workgroup i runs on XCD i mod 8: eight groups of equal size at a time
+      // are interleaved so that the tiles of one group get ids 8 apart and
+      // share that XCD's L2 copy of the inverse rows they read
+      size_t gi = 0;
+      while (gi < groups.size()) {
+        size_t gj = gi;
+        while (gj < groups.size() && gj - gi < 8 && groups[gj].size() == groups[gi].size()) ++gj;
+        if (gj - gi == 8) {
+          for (size_t i = 0; i < groups[gi].size(); ++i)
+            for (size_t j = gi; j < gj; ++j) tiles.push_back(groups[j][i]);
+        } else {
+          for (size_t j = gi; j < gj; ++j)
+            for (auto& tl : groups[j]) tiles.push_back(tl);
+        }
+        gi = gj;
+      }
       P->ntiles = (int)tiles.size();
       P->ngemv = (int)gemv.size();
       P->dGemv = dalloc<ddeig::GemvRows>(P, std::max<size_t>(gemv.size(), 1));

@@ -8,17 +8,21 @@
 // Ainv is symmetric, so the rows of Ainv serve as the columns of the B
 // operand and both operands are read row-wise.
 //
-// Precision: R is split into bf16 pairs r = r_hi + r_lo.  With local_prec = 2
-// Ainv is split the same way and Z = R_hi A_hi + R_hi A_lo + R_lo A_hi is
-// accumulated in FP32 on v_mfma_f32_32x32x16_bf16 (about 16 significant bits);
-// with local_prec = 3 Ainv is a single bf16 (Z = R_hi A + R_lo A, half the
-// bytes; the rounded inverse stays positive definite for these local
-// matrices, and CG reports a breakdown if it does not).  The extension adds Z
-// to the FP64 residual path; the outer CG stays FP64.
+// Precision: with local_prec = 2 the residual and Ainv are split into bf16
+// pairs x = x_hi + x_lo and Z = R_hi A_hi + R_hi A_lo + R_lo A_hi is
+// accumulated in FP32 on v_mfma_f32_32x32x16_bf16 (about 16 significant bits).
+// With local_prec = 3 both are single bf16 and Z = R A (one product; the
+// rounded inverse stays positive definite for these local matrices, and CG
+// reports a breakdown if it does not).  Rounding the residual makes the
+// preconditioner vary slightly between iterations (relative 2^-9); the outer
+// CG is FP64 and its residual is updated by the exact recurrence, so this
+// changes the iteration count a little, not the attainable accuracy.  The
+// extension adds Z to the FP64 residual path.
 //
-// Tiling: 128 x 128 output tiles (4 waves of 2 x 2 MFMA tiles), BK = 32 per
-// stage with LDS double buffering, split-K partial tiles summed in a fixed
-// order by the extension kernel.  Classes with at most kGemvMax members (the
+// Tiling: 128 x 128 output tiles (4 waves of 2 x 2 MFMA tiles), 64 (bf16) or
+// 32 (bf16x3) K columns per stage, two stages of global loads in flight and
+// LDS double buffering, split-K partial tiles summed in a fixed order by the
+// extension kernel.  Classes with at most kGemvMax members (the
 // boundary cells) use a streaming matrix-vector kernel instead.
 #include "k_common.h"
 
@@ -27,7 +31,6 @@ namespace ddeig {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
 
-constexpr int kTK = 32, kLdsK = kTK + 8;
 
 __device__ inline void split_bf16(double x, __bf16& hi, __bf16& lo) {
   hi = (__bf16)(float)x;
@@ -74,55 +77,85 @@ void launch_identity(double* v, int m, hipStream_t s) {
 // One 128 x 128 tile of Z (rows: subdomains of one class, columns: local
 // unknowns) over the K range [k0, k1) of one split.  4 waves as 2 x 2, each
 // owning 2 x 2 MFMA tiles of 32 x 32.  Operands go global -> registers -> LDS
-// (double buffered, BK = 32 per stage, rows padded to kLdsK so that the
-// 16-byte LDS reads of a wave hit distinct banks).  Each thread moves 32
-// bytes of one row of each of R_hi, R_lo, Ainv_hi, Ainv_lo per stage.
+// in stages of BK columns of K (LDS double buffered, rows padded to BK + 8 so
+// that the 16-byte fragment reads of a wave spread over the banks):
+//  - the global loads of stage s + 2 are issued before the MFMAs of stage s,
+//    so two stages of loads are in flight while the matrix cores work;
+//  - inside a stage the fragments of MFMA sub-step j + 1 are read from LDS
+//    and a share of stage s + 1's registers is written to the other LDS
+//    buffer while the MFMAs of sub-step j run.
+// Operands: R_hi, R_lo (RLO), A_hi, A_lo (ALO).
 constexpr int kTM = 128, kTN = 128;
 
-// ALO: Ainv carries a bf16 lo part (bf16x3 products); without it the inverse
-// is a single bf16 and Z = R_hi A + R_lo A (two products, half the bytes).
-template <bool ALO>
+template <bool RLO, bool ALO>
+struct GemmCfg {
+  static constexpr int BK = (RLO && ALO) ? 32 : 64;  // K columns per stage
+  static constexpr int LDK = BK + 8;                 // padded LDS row
+  static constexpr int NR = RLO ? 2 : 1, NA = ALO ? 2 : 1;
+  static constexpr int NOP = NR + NA;                // operands staged per stage
+  static constexpr int NV = BK / 16;                 // 16-byte vectors per thread and operand
+  static constexpr int NVT = NOP * NV;               // vectors per thread per stage
+  static constexpr int NS = BK / 16;                 // MFMA sub-steps per stage
+  static constexpr int WPS = (NVT + NS - 1) / NS;    // vectors staged per sub-step
+};
+
+typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4;
+
+template <bool RLO, bool ALO>
 __global__ void __launch_bounds__(kBlock) k_dense_gemm(const GemmTile* __restrict__ tiles,
                                                        const GemmType* __restrict__ gtypes,
                                                        const PcgState* __restrict__ st) {
-  __shared__ __bf16 sA[2][2][kTM * kLdsK];  // [buffer][hi/lo][row * kLdsK + k]  (R rows)
-  __shared__ __bf16 sB[2][ALO ? 2 : 1][kTN * kLdsK];  // [buffer][hi/lo][col * kLdsK + k]
+  using C = GemmCfg<RLO, ALO>;
+  constexpr int BK = C::BK, LDK = C::LDK, NR = C::NR, NOP = C::NOP, NV = C::NV, NVT = C::NVT;
+  constexpr int NS = C::NS, WPS = C::WPS;
+  // [buffer][operand][row * LDK + k]; operands: R parts first, then A parts
+  __shared__ __bf16 sm[2][NOP][kTM * LDK];
   if (st != nullptr && st->done) return;
   const GemmTile t = tiles[blockIdx.x];
   const GemmType gt = gtypes[t.type];
   const int ld = gt.ld;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
-  const int lrow = tid >> 1, lhalf = tid & 1;
-  const __bf16* gRh = gt.Rh + (long)(t.m0 + lrow) * ld + lhalf * 16;
-  const __bf16* gRl = gt.Rl + (long)(t.m0 + lrow) * ld + lhalf * 16;
-  const __bf16* gAh = gt.Ah + (long)(t.n0 + lrow) * ld + lhalf * 16;
-  const __bf16* gAl = gt.Al + (long)(t.n0 + lrow) * ld + lhalf * 16;
-  const int soff = lrow * kLdsK + lhalf * 16;
-  typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4;
-  u32x4 pre[8];
-  auto load = [&](int k) {
-    pre[0] = *reinterpret_cast<const u32x4*>(gRh + k);
-    pre[1] = *reinterpret_cast<const u32x4*>(gRh + k + 8);
-    pre[2] = *reinterpret_cast<const u32x4*>(gRl + k);
-    pre[3] = *reinterpret_cast<const u32x4*>(gRl + k + 8);
-    pre[4] = *reinterpret_cast<const u32x4*>(gAh + k);
-    pre[5] = *reinterpret_cast<const u32x4*>(gAh + k + 8);
-    if constexpr (ALO) {
-      pre[6] = *reinterpret_cast<const u32x4*>(gAl + k);
-      pre[7] = *reinterpret_cast<const u32x4*>(gAl + k + 8);
-    }
+  // loader: row tid / 2, half tid % 2 of the BK columns of a stage.  The
+  // operands live in global memory: loads through address-space-1 pointers
+  // become global_load (flat loads would also count against the LDS wait
+  // counter and stall every fragment read behind the prefetch).
+  typedef __attribute__((address_space(1))) const u32x4* gvec;
+  const int lrow = tid >> 1, lcol = (tid & 1) * (BK / 2);
+  gvec gsrc[NOP];
+  gsrc[0] = (gvec)(gt.Rh + (long)(t.m0 + lrow) * ld + lcol);
+  if constexpr (RLO) gsrc[1] = (gvec)(gt.Rl + (long)(t.m0 + lrow) * ld + lcol);
+  gsrc[NR] = (gvec)(gt.Ah + (long)(t.n0 + lrow) * ld + lcol);
+  if constexpr (ALO) gsrc[NR + 1] = (gvec)(gt.Al + (long)(t.n0 + lrow) * ld + lcol);
+  const int soff = lrow * LDK + lcol;
+  u32x4 ra[NVT], rb[NVT];
+  // k: first K column of the stage; 8 bf16 per vector
+  auto load = [&](u32x4* dst, int k) {
+#pragma unroll
+    for (int o = 0; o < NOP; ++o)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) dst[o * NV + v] = gsrc[o][k / 8 + v];
   };
-  auto stage = [&](int buf) {
-    *reinterpret_cast<u32x4*>(&sA[buf][0][soff]) = pre[0];
-    *reinterpret_cast<u32x4*>(&sA[buf][0][soff + 8]) = pre[1];
-    *reinterpret_cast<u32x4*>(&sA[buf][1][soff]) = pre[2];
-    *reinterpret_cast<u32x4*>(&sA[buf][1][soff + 8]) = pre[3];
-    *reinterpret_cast<u32x4*>(&sB[buf][0][soff]) = pre[4];
-    *reinterpret_cast<u32x4*>(&sB[buf][0][soff + 8]) = pre[5];
-    if constexpr (ALO) {
-      *reinterpret_cast<u32x4*>(&sB[buf][ALO ? 1 : 0][soff]) = pre[6];
-      *reinterpret_cast<u32x4*>(&sB[buf][ALO ? 1 : 0][soff + 8]) = pre[7];
+  auto stage1 = [&](const u32x4* src, int buf, int q) {
+    if (q < NVT)
+      *reinterpret_cast<u32x4*>(&sm[buf][q / NV][soff + 8 * (q % NV)]) = src[q];
+  };
+  struct Frag {
+    bf16x8 rh[2], rl[2], ah[2], al[2];
+  };
+  auto rd = [&](Frag& f, int buf, int ks) {
+    const int kof = ks * 16 + 8 * (lane >> 5);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int r = (wm * 2 + i) * 32 + (lane & 31);
+      f.rh[i] = *reinterpret_cast<const bf16x8*>(&sm[buf][0][r * LDK + kof]);
+      if constexpr (RLO) f.rl[i] = *reinterpret_cast<const bf16x8*>(&sm[buf][1][r * LDK + kof]);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = (wn * 2 + j) * 32 + (lane & 31);
+      f.ah[j] = *reinterpret_cast<const bf16x8*>(&sm[buf][NR][c * LDK + kof]);
+      if constexpr (ALO) f.al[j] = *reinterpret_cast<const bf16x8*>(&sm[buf][NR + 1][c * LDK + kof]);
     }
   };
   floatx16 acc[2][2];
@@ -132,51 +165,61 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemm(const GemmTile* __restric
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
-  const int nk = (t.k1 - t.k0) / kTK;
-  load(t.k0);
-  stage(0);
-  __syncthreads();
-  for (int kb = 0; kb < nk; ++kb) {
-    const int buf = kb & 1;
-    if (kb + 1 < nk) load(t.k0 + (kb + 1) * kTK);
-#pragma unroll
-    for (int ks = 0; ks < kTK / 16; ++ks) {
-      const int kof = ks * 16 + 8 * (lane >> 5);
-      bf16x8 ah[2], al[2], bh[2], bl[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int r = (wm * 2 + i) * 32 + (lane & 31);
-        ah[i] = *reinterpret_cast<const bf16x8*>(&sA[buf][0][r * kLdsK + kof]);
-        al[i] = *reinterpret_cast<const bf16x8*>(&sA[buf][1][r * kLdsK + kof]);
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int c = (wn * 2 + j) * 32 + (lane & 31);
-        bh[j] = *reinterpret_cast<const bf16x8*>(&sB[buf][0][c * kLdsK + kof]);
-        if constexpr (ALO) bl[j] = *reinterpret_cast<const bf16x8*>(&sB[buf][ALO ? 1 : 0][c * kLdsK + kof]);
-      }
-      // the three products of the split, each over the 4 independent
-      // accumulators, so consecutive MFMAs do not wait on each other
+  // the products of the split, small parts first, each over the 4 independent
+  // accumulators so that consecutive MFMAs do not wait on each other
+  auto mm = [&](const Frag& f) {
+    if constexpr (RLO) {
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-      if constexpr (ALO) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.rl[i], f.ah[j], acc[i][j], 0, 0, 0);
     }
-    if (kb + 1 < nk) stage(buf ^ 1);
+    if constexpr (ALO) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.rh[i], f.al[j], acc[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.rh[i], f.ah[j], acc[i][j], 0, 0, 0);
+  };
+  // stages of the K range; the host splits K into an even number of stages
+  const int nk = (t.k1 - t.k0) / BK;
+  load(ra, t.k0);
+  load(rb, t.k0 + BK);
+#pragma unroll
+  for (int q = 0; q < NVT; ++q) stage1(ra, 0, q);
+  __syncthreads();
+  // stage kb from LDS buffer `buf`: loads of kb + 2 into the register set
+  // staged last, writes of kb + 1 into the other buffer spread over the
+  // sub-steps.  Loads and stores are unconditional (past the end the last
+  // stage is loaded again and staged into a buffer nobody reads), so the loop
+  // body has no branches and the compiler's load counters stay exact; the
+  // scheduling barriers keep the compiler from regrouping the three streams.
+  auto half = [&](u32x4* ld_dst, const u32x4* st_src, int buf, int kb) {
+    load(ld_dst, t.k0 + min(kb + 2, nk - 1) * BK);
+    Frag f[2];
+    rd(f[0], buf, 0);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int ks = 0; ks < NS; ++ks) {
+      if (ks + 1 < NS) rd(f[(ks + 1) & 1], buf, ks + 1);
+#pragma unroll
+      for (int q = 0; q < WPS; ++q) stage1(st_src, buf ^ 1, ks * WPS + q);
+      __builtin_amdgcn_sched_barrier(0);
+      mm(f[ks & 1]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
     __syncthreads();
+  };
+  for (int kb = 0; kb < nk; kb += 2) {
+    half(ra, rb, 0, kb);
+    half(rb, ra, 1, kb + 1);
   }
   // accumulator layout of the 32 x 32 MFMA tile: lane l, element e holds
   // row 8 (e / 4) + 4 (l / 32) + e % 4, column l % 32
@@ -195,9 +238,9 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemm(const GemmTile* __restric
 
 // Classes with at most kGemvMax members (the boundary classes): a streaming
 // matrix-vector product, one wave per output row, reading the row of
-// Ainv_hi + Ainv_lo once with 16-byte loads and multiplying every member's
-// residual (R_hi + R_lo) in FP32.  This is memory-bound on the inverse.
-template <bool ALO>
+// Ainv_hi (+ Ainv_lo) once with 16-byte loads and multiplying every member's
+// residual (R_hi (+ R_lo)) in FP32.  This is memory-bound on the inverse.
+template <bool RLO, bool ALO>
 __global__ void __launch_bounds__(kBlock) k_dense_gemv(const GemvRows* __restrict__ jobs,
                                                        const GemmType* __restrict__ gtypes,
                                                        const PcgState* __restrict__ st) {
@@ -207,7 +250,6 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemv(const GemvRows* __restric
   const int ld = gt.ld, lane = threadIdx.x & 63;
   const int row = job.r0 + (threadIdx.x >> 6);
   if (row >= job.r1) return;
-  typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4;
   float acc[kGemvMax];
 #pragma unroll
   for (int m = 0; m < kGemvMax; ++m) acc[m] = 0.0f;
@@ -229,11 +271,18 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemv(const GemvRows* __restric
     for (int m = 0; m < kGemvMax; ++m) {
       if (m >= job.nmem) break;
       const u32x4 rh4 = *reinterpret_cast<const u32x4*>(gt.Rh + (long)m * ld + k);
-      const u32x4 rl4 = *reinterpret_cast<const u32x4*>(gt.Rl + (long)m * ld + k);
       const __bf16* rh = reinterpret_cast<const __bf16*>(&rh4);
-      const __bf16* rl = reinterpret_cast<const __bf16*>(&rl4);
+      float rv[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) acc[m] += a[e] * ((float)rh[e] + (float)rl[e]);
+      for (int e = 0; e < 8; ++e) rv[e] = (float)rh[e];
+      if constexpr (RLO) {
+        const u32x4 rl4 = *reinterpret_cast<const u32x4*>(gt.Rl + (long)m * ld + k);
+        const __bf16* rl = reinterpret_cast<const __bf16*>(&rl4);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) rv[e] += (float)rl[e];
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc[m] += a[e] * rv[e];
     }
   }
 #pragma unroll
@@ -245,26 +294,28 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemv(const GemvRows* __restric
   }
 }
 
-// Classes with many members: 128 x 128 MFMA tiles (two workgroups per CU).
+// Classes with many members: 128 x 128 MFMA tiles.  local_prec 2 (bf16x3):
+// residual and inverse as hi/lo pairs, three products; local_prec 3: both
+// single bf16, one product.
 void launch_dense_gemm(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
   if (P->ntiles > 0) {
     if (P->opt.local_prec == 2)
-      hipLaunchKernelGGL(k_dense_gemm<true>, dim3(P->ntiles), dim3(kBlock), 0, s, P->dTiles,
-                         P->dGtypes, st);
+      hipLaunchKernelGGL((k_dense_gemm<true, true>), dim3(P->ntiles), dim3(kBlock), 0, s,
+                         P->dTiles, P->dGtypes, st);
     else
-      hipLaunchKernelGGL(k_dense_gemm<false>, dim3(P->ntiles), dim3(kBlock), 0, s, P->dTiles,
-                         P->dGtypes, st);
+      hipLaunchKernelGGL((k_dense_gemm<false, false>), dim3(P->ntiles), dim3(kBlock), 0, s,
+                         P->dTiles, P->dGtypes, st);
   }
 }
 
 void launch_dense_gemv(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
   if (P->ngemv > 0) {
     if (P->opt.local_prec == 2)
-      hipLaunchKernelGGL(k_dense_gemv<true>, dim3(P->ngemv), dim3(kBlock), 0, s, P->dGemv,
+      hipLaunchKernelGGL((k_dense_gemv<true, true>), dim3(P->ngemv), dim3(kBlock), 0, s, P->dGemv,
                          P->dGtypes, st);
     else
-      hipLaunchKernelGGL(k_dense_gemv<false>, dim3(P->ngemv), dim3(kBlock), 0, s, P->dGemv,
-                         P->dGtypes, st);
+      hipLaunchKernelGGL((k_dense_gemv<false, false>), dim3(P->ngemv), dim3(kBlock), 0, s,
+                         P->dGemv, P->dGtypes, st);
   }
 }
 

@@ -84,8 +84,8 @@ __device__ inline double cover_weight(const Geo& g, int delta, int pu, const XCo
   return w;
 }
 
-// Scatter r into the subdomain batches (box natural order; bf16 hi/lo rows for
-// dense classes): node-parallel over row segments of kBlock x1 positions;
+// Scatter r into the subdomain batches (box natural order; bf16 rows, as a
+// hi/lo pair for local_prec 2, for dense classes): node-parallel over row segments of kBlock x1 positions;
 // every node writes its copy into each covering subdomain (at most 2^p), so
 // reads of r and writes of a batch row are both coalesced.  With xr.on the
 // node first takes the CG update of iteration k (x += alpha p, r -= alpha q,
@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Geo g, int ntypes, PcgState
         const long e = a0.u[q0] + (long)td.m[0] * (a1.u[q1] + (long)td.m[1] * i2);
         if (td.dense) {
           td.Rh[(long)ts.slot * td.ld + e] = hi;
-          td.Rl[(long)ts.slot * td.ld + e] = lo;
+          if (td.Rl != nullptr) td.Rl[(long)ts.slot * td.ld + e] = lo;
         } else {
           td.batch[(long)ts.slot * td.nch * td.b + e] = rv;
         }
