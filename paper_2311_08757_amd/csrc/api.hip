@@ -114,25 +114,39 @@ double cell_vmin(const ddeig_problem* P) {
 }
 
 void factor_types(ddeig_problem* P) {
+  if (P->opt.local_prec >= 2) {
+    // dense local solves: FP64 block-chain factors of the unclipped box, its
+    // inverse from the chain solves of the identity columns, the bf16 (hi /
+    // lo) split, then for every clipped class (B~_TT)^{-1} from the rounded
+    // inverse (FP64 Gauss-Jordan, symmetrised) and G = B~_ST (B~_TT)^{-1}
+    ddeig::DenseHost& H = P->dh;
+    chain_factor(P, H.box, P->tabAs, H.W, P->stream);
+    check_launch("local factorisation");
+    double* Ainv = dalloc<double>(P, (size_t)H.m * H.m);
+    launch_identity(Ainv, H.m, P->stream);
+    launch_chain_solve_box(P, H.box, P->tabAs, H.W, Ainv, H.m, P->stream);
+    launch_split_inverse(Ainv, H.m, H.ld, H.Ah, H.Al, P->stream);
+    check_launch("dense inverse");
+    sync(P);
+    dfree(P, Ainv);
+    for (const auto& E : P->emb) {
+      double* C = dalloc<double>(P, (size_t)E.nT * E.nT);
+      launch_embed_gather(P, E, C, P->stream);
+      launch_gj_invert(P, C, E.nT, P->stream);
+      launch_symmetrise(C, E.nT, P->stream);
+      launch_embed_gmat(P, E, C, const_cast<float*>(E.G), P->stream);
+      check_launch("clipped-class corrections");
+      sync(P);
+      dfree(P, C);
+    }
+    return;
+  }
   for (auto& t : P->types) {
     chain_factor(P, t.box, P->tabAs, t.W, P->stream);
     if (P->opt.local_prec == 1)
       launch_to_float(t.W, t.W32, (long)t.box.nch * t.box.b * t.box.b, P->stream);
   }
   check_launch("local factorisation");
-  if (P->opt.local_prec >= 2) {
-    // dense inverses: chain solves of the identity columns, then bf16 hi (/lo) split
-    for (auto& t : P->types) {
-      const int m = t.box.nch * t.box.b;
-      double* Ainv = dalloc<double>(P, (size_t)m * m);
-      launch_identity(Ainv, m, P->stream);
-      launch_chain_solve_box(P, t.box, P->tabAs, t.W, Ainv, m, P->stream);
-      launch_split_inverse(Ainv, m, t.ld, t.Ah, t.Al, P->stream);
-      check_launch("dense inverse");
-      sync(P);
-      dfree(P, Ainv);
-    }
-  }
 }
 
 int read_flag(ddeig_problem* P) {
@@ -164,8 +178,8 @@ ddeig_status finish_shift(ddeig_problem* P) {
   return DDEIG_OK;
 }
 
-// restrict -> {local solves | boundary GEMV + coarse solve on the second
-// stream} -> extend.  xr (nullable) fuses the CG update of x and r into the
+// restrict -> {local solves (+ clipped-class correction) | coarse solve on the
+// second stream} -> extend.  xr (nullable) fuses the CG update of x and r into the
 // restriction (partials of ||r||^2 into *rr); chk (nullable) folds the PCG
 // stopping test into the extension.
 void precond_apply(ddeig_problem* P, double* r, double* z, Red* dot, PcgState* st,
@@ -176,13 +190,13 @@ void precond_apply(ddeig_problem* P, double* r, double* z, Red* dot, PcgState* s
   CheckArgs coff{};
   coff.on = 0;
   launch_restrict(P, r, st, xr ? *xr : xoff, rr, P->stream);
-  const bool side = coarse || (P->opt.local_prec >= 2 && P->ngemv > 0);
+  const bool side = coarse;
   if (side) {
     check_hip(hipEventRecord(P->ev_fork, P->stream), "record fork");
     check_hip(hipStreamWaitEvent(P->aux, P->ev_fork, 0), "wait fork");
   }
   launch_local_solves(P, st, P->stream);
-  if (P->opt.local_prec >= 2) launch_dense_gemv(P, st, P->aux);
+  if (P->opt.local_prec >= 2) launch_embed_fix(P, st, P->stream);
   if (coarse) {
     launch_coarse_rhs(P, r, st, P->aux);
     launch_coarse_solve(P, st, P->aux);
@@ -454,85 +468,167 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
     int maxb = 0;
     std::vector<ddeig::TypeDev> tdev(P->types.size());
     const bool dense = o.local_prec >= 2;
-    // dense classes: 128 x 128 MFMA tiles for classes with more than kGemvMax
-    // members, K split so that the grouped GEMM has enough workgroups; the
-    // small (boundary) classes use the streaming matrix-vector kernel
-    auto big = [](const ddeig::SubType& T) { return T.nmem > ddeig::kGemvMax; };
-    // K columns per GEMM stage (the kernel's pipeline depth): 64 with a single
-    // bf16 inverse, 32 with the hi/lo pair
-    const int bk = o.local_prec == 2 ? 32 : 64;
-    if (dense) {
-      long tiles = 0;
-      int minkb = 1 << 30;
-      for (auto& T : P->types) {
-        const int m = T.box.nch * T.box.b;
-        T.ld = (m + 127) / 128 * 128;
-        T.mp = big(T) ? (T.nmem + 127) / 128 * 128 : ddeig::kGemvMax;
-        if (big(T)) {
-          tiles += (long)(T.mp / 128) * (T.ld / 128);
-          minkb = std::min(minkb, T.ld / bk / 2);
-        }
-      }
-      if (tiles > 0)
-        P->ksplit = (int)std::max<long>(1, std::min<long>(std::min(3, minkb), (256 + tiles - 1) / tiles));
-    }
-    // tiles that read the same rows of an inverse (one group: the member tiles
-    // of one column tile and K split)
-    std::vector<std::vector<ddeig::GemmTile>> groups;
     std::vector<ddeig::GemmTile> tiles;
     std::vector<ddeig::GemvRows> gemv;
-    std::vector<ddeig::GemmType> gtypes;
+    std::vector<ddeig::EmbedJob> embjobs;
+    if (dense) {
+      // the unclipped box of an interior cell (o = n_e - delta in x dims, the
+      // box of cell 2; only the table is read, so it exists for any L)
+      ddeig::DenseHost& H = P->dh;
+      Box hb{};
+      for (int a = 0; a < 3; ++a) {
+        hb.per[a] = 0;
+        if (a >= g.D) { hb.o[a] = 0; hb.m[a] = 1; continue; }
+        if (g.isx[a]) { hb.o[a] = ne - overlap; hb.m[a] = ne + 2 * overlap - 1; }
+        else { hb.o[a] = 0; hb.m[a] = g.N[a]; }
+      }
+      hb.b = 1;
+      for (int a = 0; a < g.D - 1; ++a) hb.b *= hb.m[a];
+      hb.nch = hb.m[g.D - 1];
+      H.box = hb;
+      H.m = hb.b * hb.nch;
+      H.ld = (H.m + 127) / 128 * 128;
+      H.mp = nsub > ddeig::kGemvMax ? (nsub + 127) / 128 * 128 : ddeig::kGemvMax;
+      H.W = dalloc<double>(P, (size_t)hb.nch * hb.b * hb.b);
+      const size_t aa = (size_t)H.ld * H.ld, rr = (size_t)H.mp * H.ld;
+      // K columns per GEMM stage (the kernel's pipeline depth): 64 with a
+      // single bf16 inverse, 32 with the hi/lo pair; K split so that the GEMM
+      // has about one workgroup per CU, at even stage counts (the kernel
+      // multiplies two stages per trip)
+      const int bk = o.local_prec == 2 ? 32 : 64;
+      if (nsub > ddeig::kGemvMax) {
+        const long ntile = (long)(H.mp / 128) * (H.ld / 128);
+        P->ksplit = (int)std::max<long>(1, std::min<long>(std::min(3, H.ld / bk / 2),
+                                                          (256 + ntile - 1) / ntile));
+      } else {
+        P->ksplit = 1;
+      }
+      H.Ah = dalloc<__bf16>(P, aa);
+      H.Al = o.local_prec == 2 ? dalloc<__bf16>(P, aa) : nullptr;
+      H.Rh = dalloc<__bf16>(P, rr);
+      H.Rl = o.local_prec == 2 ? dalloc<__bf16>(P, rr) : nullptr;
+      H.Z = dalloc<float>(P, (size_t)P->ksplit * rr);
+      // rows are zero outside each member's own box, and padding rows stay zero
+      check_hip(hipMemsetAsync(H.Rh, 0, rr * sizeof(__bf16), s), "memset Rh");
+      if (H.Rl) check_hip(hipMemsetAsync(H.Rl, 0, rr * sizeof(__bf16), s), "memset Rl");
+      maxb = std::max(maxb, hb.b);
+      // classes: their box inside the unclipped one, their rows, and for the
+      // clipped ones the node list T of the unclipped box outside their box
+      int row = 0;
+      for (size_t t = 0; t < P->types.size(); ++t) {
+        auto& T = P->types[t];
+        const auto& sd0 = P->subs[T.members[0]];
+        int nS = 1;
+        for (int a = 0; a < 3; ++a) {
+          T.off[a] = (a < g.D && g.isx[a]) ? T.box.o[a] - ((sd0.c[a] - 1) * ne - overlap) : 0;
+          nS *= T.box.m[a];
+          if (T.off[a] < 0 || T.off[a] + T.box.m[a] > hb.m[a])
+            throw Failure{DDEIG_EINTERNAL, "subdomain box outside the unclipped box"};
+        }
+        T.row0 = row;
+        row += T.nmem;
+        const int nT = H.m - nS;
+        if (nT > 0) {
+          if (nT > ddeig::kEmbMaxT)
+            throw Failure{DDEIG_EINVAL, "dense local solves: a clipped subdomain misses more than 1024 "
+                                        "nodes of the unclipped box; use local_prec 0 or 1"};
+          std::vector<int> tl;
+          for (int u2 = 0; u2 < hb.m[2]; ++u2)
+            for (int u1 = 0; u1 < hb.m[1]; ++u1)
+              for (int u0 = 0; u0 < hb.m[0]; ++u0) {
+                const int u[3] = {u0, u1, u2};
+                bool in = true;
+                for (int a = 0; a < 3; ++a)
+                  if (u[a] < T.off[a] || u[a] >= T.off[a] + T.box.m[a]) in = false;
+                if (!in) tl.push_back(u0 + hb.m[0] * (u1 + hb.m[1] * u2));
+              }
+          ddeig::EmbedDev E{};
+          E.nT = nT;
+          E.row0 = T.row0;
+          E.nmem = T.nmem;
+          for (int a = 0; a < 3; ++a) { E.off[a] = T.off[a]; E.m[a] = T.box.m[a]; }
+          int* dT = dalloc<int>(P, tl.size());
+          check_hip(hipMemcpyAsync(dT, tl.data(), sizeof(int) * tl.size(), hipMemcpyHostToDevice, s),
+                    "copy T list");
+          sync(P);  // tl is released at the end of this scope
+          E.Tidx = dT;
+          E.G = dalloc<float>(P, (size_t)nT * H.m);
+          const int ci = (int)P->emb.size();
+          P->emb.push_back(E);
+          P->maxT = std::max(P->maxT, nT);
+          for (int m0 = 0; m0 < T.nmem; m0 += ddeig::kEmbChunk)
+            embjobs.push_back(ddeig::EmbedJob{ci, m0, std::min(ddeig::kEmbChunk, T.nmem - m0)});
+        }
+      }
+      // GEMM over all rows (or the streaming kernel for a handful of rows);
+      // the tiles of one group read the same rows of the inverse
+      if (nsub > ddeig::kGemvMax) {
+        std::vector<std::vector<ddeig::GemmTile>> groups;
+        const int npair = H.ld / bk / 2;
+        for (int sp = 0; sp < P->ksplit; ++sp) {
+          const int kb0 = 2 * (int)((long)npair * sp / P->ksplit);
+          const int kb1 = 2 * (int)((long)npair * (sp + 1) / P->ksplit);
+          for (int nt = 0; nt < H.ld / 128; ++nt) {
+            std::vector<ddeig::GemmTile> grp;
+            for (int mt = 0; mt < H.mp / 128; ++mt)
+              grp.push_back(ddeig::GemmTile{0, mt * 128, nt * 128, kb0 * bk, kb1 * bk, sp});
+            groups.push_back(grp);
+          }
+        }
+        // workgroup i runs on XCD i mod 8: eight groups of equal size at a
+        // time are interleaved so that the tiles of one group get ids 8 apart
+        // and share that XCD's L2 copy of the inverse rows they read
+        size_t gi = 0;
+        while (gi < groups.size()) {
+          size_t gj = gi;
+          while (gj < groups.size() && gj - gi < 8 && groups[gj].size() == groups[gi].size()) ++gj;
+          if (gj - gi == 8) {
+            for (size_t i = 0; i < groups[gi].size(); ++i)
+              for (size_t j = gi; j < gj; ++j) tiles.push_back(groups[j][i]);
+          } else {
+            for (size_t j = gi; j < gj; ++j)
+              for (auto& tl : groups[j]) tiles.push_back(tl);
+          }
+          gi = gj;
+        }
+      } else {
+        for (int r0 = 0; r0 < H.m; r0 += kBlock / 64)
+          gemv.push_back(ddeig::GemvRows{0, r0, std::min(H.m, r0 + kBlock / 64), nsub});
+      }
+    }
     for (size_t t = 0; t < P->types.size(); ++t) {
       auto& T = P->types[t];
       maxb = std::max(maxb, T.box.b);
       const long mm = (long)T.box.nch * T.box.b;
-      T.W = dalloc<double>(P, (size_t)T.box.nch * T.box.b * T.box.b);
-      if (o.local_prec == 1) T.W32 = dalloc<float>(P, (size_t)T.box.nch * T.box.b * T.box.b);
       for (int a = 0; a < 3; ++a) tdev[t].m[a] = T.box.m[a];
       tdev[t].b = T.box.b;
       tdev[t].nch = T.box.nch;
-      tdev[t].W = T.W;
-      tdev[t].W32 = T.W32;
       tdev[t].dense = dense ? 1 : 0;
       if (dense) {
-        const size_t aa = (size_t)T.ld * T.ld, rr = (size_t)T.mp * T.ld;
-        T.Ah = dalloc<__bf16>(P, aa);
-        T.Al = o.local_prec == 2 ? dalloc<__bf16>(P, aa) : nullptr;
-        T.Rh = dalloc<__bf16>(P, rr);
-        T.Rl = o.local_prec == 2 ? dalloc<__bf16>(P, rr) : nullptr;
-        T.Z = dalloc<float>(P, (size_t)P->ksplit * rr);
-        check_hip(hipMemsetAsync(T.Rh, 0, rr * sizeof(__bf16), s), "memset Rh");
-        if (T.Rl) check_hip(hipMemsetAsync(T.Rl, 0, rr * sizeof(__bf16), s), "memset Rl");
-        T.batch = dalloc<double>(P, 1);
-        tdev[t].ld = T.ld;
-        tdev[t].ksplit = P->ksplit;
-        tdev[t].Rh = T.Rh;
-        tdev[t].Rl = T.Rl;
-        tdev[t].Z = T.Z;
-        tdev[t].zsplit = (long)rr;
-        ddeig::GemmType gt{T.Ah, T.Al, T.Rh, T.Rl, T.Z, (long)rr, T.ld};
-        gtypes.push_back(gt);
-        if (big(T)) {
-          // K split at even stage counts (the kernel multiplies two stages per trip)
-          const int npair = T.ld / bk / 2;
-          for (int sp = 0; sp < P->ksplit; ++sp) {
-            const int kb0 = 2 * (int)((long)npair * sp / P->ksplit);
-            const int kb1 = 2 * (int)((long)npair * (sp + 1) / P->ksplit);
-            for (int nt = 0; nt < T.ld / 128; ++nt) {
-              std::vector<ddeig::GemmTile> grp;
-              for (int mt = 0; mt < T.mp / 128; ++mt)
-                grp.push_back(ddeig::GemmTile{(int)t, mt * 128, nt * 128, kb0 * bk, kb1 * bk, sp});
-              groups.push_back(grp);
-            }
-          }
-        } else {
-          tdev[t].ksplit = 1;
-          const int m = T.box.nch * T.box.b;
-          for (int r0 = 0; r0 < m; r0 += kBlock / 64)
-            gemv.push_back(ddeig::GemvRows{(int)t, r0, std::min(m, r0 + kBlock / 64), T.nmem});
+        const ddeig::DenseHost& H = P->dh;
+        for (int a = 0; a < 3; ++a) {
+          tdev[t].hm[a] = H.box.m[a];
+          tdev[t].off[a] = T.off[a];
         }
+        T.batch = dalloc<double>(P, 1);
+        tdev[t].W = nullptr;
+        tdev[t].W32 = nullptr;
+        tdev[t].ld = H.ld;
+        tdev[t].ksplit = P->ksplit;
+        tdev[t].Rh = H.Rh;
+        tdev[t].Rl = H.Rl;
+        tdev[t].Z = H.Z;
+        tdev[t].zsplit = (long)H.mp * H.ld;
       } else {
+        T.W = dalloc<double>(P, (size_t)T.box.nch * T.box.b * T.box.b);
+        if (o.local_prec == 1) T.W32 = dalloc<float>(P, (size_t)T.box.nch * T.box.b * T.box.b);
         T.batch = dalloc<double>(P, (size_t)T.nmem * mm);
+        for (int a = 0; a < 3; ++a) {
+          tdev[t].hm[a] = T.box.m[a];
+          tdev[t].off[a] = 0;
+        }
+        tdev[t].W = T.W;
+        tdev[t].W32 = T.W32;
         tdev[t].ld = 0;
         tdev[t].ksplit = 0;
         tdev[t].Rh = tdev[t].Rl = nullptr;
@@ -547,7 +643,10 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
     if (P->types.size() > (size_t)ddeig::kMaxTypes) throw Failure{DDEIG_EINTERNAL, "too many classes"};
     {
       std::vector<ddeig::SubTS> ts(nsub);
-      for (int sid = 0; sid < nsub; ++sid) ts[sid] = ddeig::SubTS{P->subs[sid].type, P->subs[sid].slot};
+      for (int sid = 0; sid < nsub; ++sid) {
+        const auto& sd = P->subs[sid];
+        ts[sid] = ddeig::SubTS{sd.type, dense ? P->types[sd.type].row0 + sd.slot : sd.slot};
+      }
       std::vector<int> first(P->types.size());
       std::vector<double*> phis(P->types.size());
       for (size_t t = 0; t < P->types.size(); ++t) {
@@ -566,38 +665,36 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
       sync(P);
     }
     if (dense) {
-      // workgroup i runs on XCD i mod 8: eight groups of equal size at a time
-      // are interleaved so that the tiles of one group get ids 8 apart and
-      // share that XCD's L2 copy of the inverse rows they read
-      size_t gi = 0;
-      while (gi < groups.size()) {
-        size_t gj = gi;
-        while (gj < groups.size() && gj - gi < 8 && groups[gj].size() == groups[gi].size()) ++gj;
-        if (gj - gi == 8) {
-          for (size_t i = 0; i < groups[gi].size(); ++i)
-            for (size_t j = gi; j < gj; ++j) tiles.push_back(groups[j][i]);
-        } else {
-          for (size_t j = gi; j < gj; ++j)
-            for (auto& tl : groups[j]) tiles.push_back(tl);
-        }
-        gi = gj;
-      }
+      const ddeig::DenseHost& H = P->dh;
       P->ntiles = (int)tiles.size();
       P->ngemv = (int)gemv.size();
       P->dGemv = dalloc<ddeig::GemvRows>(P, std::max<size_t>(gemv.size(), 1));
       if (!gemv.empty())
         check_hip(hipMemcpyAsync(P->dGemv, gemv.data(), sizeof(ddeig::GemvRows) * gemv.size(),
                                  hipMemcpyHostToDevice, s), "copy gemv rows");
-      P->dTiles = dalloc<ddeig::GemmTile>(P, tiles.size());
-      P->dGtypes = dalloc<ddeig::GemmType>(P, gtypes.size());
-      check_hip(hipMemcpyAsync(P->dTiles, tiles.data(), sizeof(ddeig::GemmTile) * tiles.size(),
-                               hipMemcpyHostToDevice, s), "copy tiles");
-      check_hip(hipMemcpyAsync(P->dGtypes, gtypes.data(), sizeof(ddeig::GemmType) * gtypes.size(),
-                               hipMemcpyHostToDevice, s), "copy gemm types");
+      P->dTiles = dalloc<ddeig::GemmTile>(P, std::max<size_t>(tiles.size(), 1));
+      if (!tiles.empty())
+        check_hip(hipMemcpyAsync(P->dTiles, tiles.data(), sizeof(ddeig::GemmTile) * tiles.size(),
+                                 hipMemcpyHostToDevice, s), "copy tiles");
+      const ddeig::GemmType gt{H.Ah, H.Al, H.Rh, H.Rl, H.Z, (long)H.mp * H.ld, H.ld};
+      P->dGtypes = dalloc<ddeig::GemmType>(P, 1);
+      check_hip(hipMemcpyAsync(P->dGtypes, &gt, sizeof(ddeig::GemmType), hipMemcpyHostToDevice, s),
+                "copy gemm operands");
+      P->nembjobs = (int)embjobs.size();
+      if (!P->emb.empty()) {
+        P->dEmb = dalloc<ddeig::EmbedDev>(P, P->emb.size());
+        check_hip(hipMemcpyAsync(P->dEmb, P->emb.data(), sizeof(ddeig::EmbedDev) * P->emb.size(),
+                                 hipMemcpyHostToDevice, s), "copy clipped classes");
+        P->dEmbJobs = dalloc<ddeig::EmbedJob>(P, embjobs.size());
+        check_hip(hipMemcpyAsync(P->dEmbJobs, embjobs.data(),
+                                 sizeof(ddeig::EmbedJob) * embjobs.size(), hipMemcpyHostToDevice, s),
+                  "copy correction jobs");
+      }
+      sync(P);  // the host vectors above are released at the end of this scope
     }
     P->maxb = std::max(maxb, 1);
     const Box cb = cell_box(g);
-    const int gjmax = std::max(std::max(maxb, cb.b), nsub);
+    const int gjmax = std::max(std::max(std::max(maxb, cb.b), nsub), P->maxT);
     P->dSubs = dalloc<ddeig::SubDev>(P, nsub);
     P->dTypes = dalloc<ddeig::TypeDev>(P, tdev.size());
     check_hip(hipMemcpyAsync(P->dSubs, P->subs.data(), sizeof(ddeig::SubDev) * nsub,
@@ -709,13 +806,11 @@ ddeig_status ddeig_profile_kernel(ddeig_problem* P, int which, int reps, const d
   if (which == 0) {
     w = 16.0 * (double)P->g.n;
   } else if (which == 1) {
-    for (auto& t : P->types) {
-      const double m = (double)t.box.nch * t.box.b;
-      if (P->opt.local_prec >= 2) {
-        if (t.nmem > ddeig::kGemvMax) w += 2.0 * m * m * t.nmem;
-      } else {
-        w += 4.0 * t.box.nch * (double)t.box.b * t.box.b * t.nmem;
-      }
+    if (P->opt.local_prec >= 2) {
+      const double m = (double)P->dh.m;
+      w = 2.0 * m * m * P->nsub;
+    } else {
+      for (auto& t : P->types) w += 4.0 * t.box.nch * (double)t.box.b * t.box.b * t.nmem;
     }
   }
   auto launch = [&]() {

@@ -99,11 +99,41 @@ struct SubType {
   float* W32 = nullptr;     // FP32 copy (local_prec = 1)
   double* batch = nullptr;  // nmem * nch * b local vectors
   double* phi = nullptr;    // coarse weights of the class (box order)
-  // dense-inverse class data (local_prec = 2)
-  int ld = 0, mp = 0;
+  // dense local solves (local_prec >= 2): the class box is the node range
+  // [off, off + m) of the unclipped box along every axis; its members use rows
+  // [row0, row0 + nmem) of the dense batch
+  int off[3] = {0, 0, 0};
+  int row0 = 0;
+};
+
+// Dense local solves: the unclipped, period-aligned subdomain box (the box of
+// an interior cell), its FP64 block-chain factors, its inverse as bf16 (hi /
+// lo) and the batch of all subdomains' restricted residuals R (one row per
+// subdomain, zero outside the subdomain's own box) with the split-K partial
+// products Z[split][row][e].
+struct DenseHost {
+  Box box;
+  int m = 0, ld = 0, mp = 0;
+  double* W = nullptr;
   __bf16 *Ah = nullptr, *Al = nullptr, *Rh = nullptr, *Rl = nullptr;
   float* Z = nullptr;
 };
+
+// A clipped class (a box smaller than the unclipped one): S = its nodes, T =
+// the other nodes of the unclipped box, G = B_ST (B_TT)^{-1} for the rounded
+// unclipped inverse B, stored t-major over the unclipped box (G[t * mH + e],
+// zero for e in T; see k_dense.hip).
+struct EmbedDev {
+  int nT, row0, nmem;
+  int off[3], m[3];
+  const int* Tidx;
+  const float* G;
+};
+struct EmbedJob {
+  int cls, mem0, nm;
+};
+constexpr int kEmbChunk = 8;    // members per correction block
+constexpr int kEmbMaxT = 1024;  // largest T
 
 // Per-subdomain data on the device.
 struct SubDev {
@@ -115,12 +145,14 @@ struct SubDev {
 
 struct TypeDev {
   int m[3];
+  int hm[3], off[3];  // dense batch rows: e = sum_a (u_a + off_a) prod_{b<a} hm_b
   int b, nch;
   const double* W;
   const float* W32;
   double* batch;
-  // dense-inverse classes (local_prec = 2): bf16 hi/lo residual rows and
-  // split-K partial results Z[split][slot][e]
+  // dense local solves (local_prec >= 2): rows of the dense batch (bf16
+  // residual, lo part for local_prec = 2) and split-K partial results
+  // Z[split][row][e]
   int dense, ld, ksplit;
   __bf16* Rh;
   __bf16* Rl;
@@ -202,7 +234,12 @@ struct ddeig_problem {
   ddeig::SubTS* dSubTS = nullptr;
   int* dFirst = nullptr;          // first member of every class
   double** dPhis = nullptr;       // per-class coarse weights (device pointer array)
-  // grouped GEMM of the dense classes
+  // dense local solves
+  ddeig::DenseHost dh;
+  std::vector<ddeig::EmbedDev> emb;   // clipped classes (device pointers inside)
+  ddeig::EmbedDev* dEmb = nullptr;
+  ddeig::EmbedJob* dEmbJobs = nullptr;
+  int nembjobs = 0, maxT = 0;
   int ntiles = 0, ngemv = 0, ksplit = 1;
   ddeig::GemmTile* dTiles = nullptr;
   ddeig::GemvRows* dGemv = nullptr;
@@ -285,6 +322,10 @@ void launch_split_inverse(const double* Ainv, int m, int ld, void* Ah, void* Al,
 void launch_identity(double* v, int m, hipStream_t s);
 void launch_dense_gemm(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 void launch_dense_gemv(const ddeig_problem* P, const PcgState* st, hipStream_t s);
+void launch_embed_gather(const ddeig_problem* P, const EmbedDev& E, double* C, hipStream_t s);
+void launch_embed_gmat(const ddeig_problem* P, const EmbedDev& E, const double* C, float* G,
+                       hipStream_t s);
+void launch_embed_fix(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 void launch_to_float(const double* src, float* dst, long n, hipStream_t s);
 void build_coarse_matrix(ddeig_problem* P, double* A0, hipStream_t s);
 

@@ -268,7 +268,10 @@ void launch_local_solves_fast(const ddeig_problem* P, const PcgState* st, hipStr
 
 void launch_local_solves(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
   if (P->opt.local_prec >= 2) {
-    launch_dense_gemm(P, st, s);  // the small classes go through launch_dense_gemv
+    // one batch of all subdomains: MFMA tiles, or the streaming kernel for a
+    // handful of rows (one of the two has no work)
+    launch_dense_gemm(P, st, s);
+    launch_dense_gemv(P, st, s);
     return;
   }
   if (local_solves_fast_ok(P)) {

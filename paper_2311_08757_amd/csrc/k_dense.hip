@@ -1,12 +1,14 @@
 // Dense-inverse local solves on MFMA.
 //
-// All interior subdomains share one local matrix A_sigma,i (the operator is
-// periodic and the subdomains are period-aligned), so its inverse is built
-// once per subdomain class and the level-1 preconditioner of §3
-// (eq:twoLevelASMPreconditioner) applies it to every member of the class at
-// once: Z = R Ainv, with R the restricted residuals (one row per subdomain).
-// Ainv is symmetric, so the rows of Ainv serve as the columns of the B
-// operand and both operands are read row-wise.
+// Interior subdomains share one local matrix A_sigma,i (the operator is
+// periodic and the subdomains are period-aligned), and a subdomain clipped by
+// the global boundary has a principal submatrix of it, so one inverse of the
+// unclipped box serves the level-1 preconditioner of §3
+// (eq:twoLevelASMPreconditioner) for every subdomain: Z = R Ainv with R the
+// restricted residuals (one row per subdomain), followed by a small
+// Schur-complement correction for the clipped ones.  Ainv is symmetric, so
+// its rows serve as the columns of the B operand and both operands are read
+// row-wise.
 //
 // Precision: with local_prec = 2 the residual and Ainv are split into bf16
 // pairs x = x_hi + x_lo and Z = R_hi A_hi + R_hi A_lo + R_lo A_hi is
@@ -236,10 +238,11 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemm(const GemmTile* __restric
       }
 }
 
-// Classes with at most kGemvMax members (the boundary classes): a streaming
-// matrix-vector product, one wave per output row, reading the row of
-// Ainv_hi (+ Ainv_lo) once with 16-byte loads and multiplying every member's
-// residual (R_hi (+ R_lo)) in FP32.  This is memory-bound on the inverse.
+// Batches of at most kGemvMax rows (domains of at most kGemvMax cells): a
+// streaming matrix-vector product, one wave per output row, reading the row
+// of Ainv_hi (+ Ainv_lo) once with 16-byte loads and multiplying every
+// member's residual (R_hi (+ R_lo)) in FP32.  This is memory-bound on the
+// inverse.
 template <bool RLO, bool ALO>
 __global__ void __launch_bounds__(kBlock) k_dense_gemv(const GemvRows* __restrict__ jobs,
                                                        const GemmType* __restrict__ gtypes,
@@ -294,7 +297,154 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemv(const GemvRows* __restric
   }
 }
 
-// Classes with many members: 128 x 128 MFMA tiles.  local_prec 2 (bf16x3):
+// Clipped classes.  The local matrix of a subdomain clipped by the global
+// boundary is the principal submatrix A_SS of the unclipped box's matrix A
+// (the operator is periodic and the clipped box keeps the unclipped node
+// positions), and for B = A^{-1} the Schur-complement identity gives
+// (A_SS)^{-1} = B_SS - B_ST (B_TT)^{-1} B_TS.  The batch row of a clipped
+// member holds r_S and zeros on T, so the GEMM returns u = B [r_S; 0]; the
+// correction then forms y_S = u_S - G u_T with G = B_ST (B_TT)^{-1}, built
+// once per shift.  With the rounded
+// inverse B~ in place of B this is exactly the Schur complement of B~, which
+// stays symmetric positive definite whenever B~ is.
+
+// B~_TT of a clipped class (hi + lo parts), FP64, row-major nT x nT.
+__global__ void k_embed_gather(const __bf16* __restrict__ Ah, const __bf16* __restrict__ Al,
+                               int ld, const int* __restrict__ Tidx, int nT,
+                               double* __restrict__ C) {
+  const long tot = (long)nT * nT;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / nT), j = (int)(idx % nT);
+    const long a = (long)Tidx[i] * ld + Tidx[j];
+    double v = (double)(float)Ah[a];
+    if (Al != nullptr) v += (double)(float)Al[a];
+    C[idx] = v;
+  }
+}
+
+void launch_embed_gather(const ddeig_problem* P, const EmbedDev& E, double* C, hipStream_t s) {
+  const long tot = (long)E.nT * E.nT;
+  const int blocks = (int)std::min<long>((tot + kBlock - 1) / kBlock, 4096);
+  hipLaunchKernelGGL(k_embed_gather, dim3(blocks), dim3(kBlock), 0, s, P->dh.Ah, P->dh.Al,
+                     P->dh.ld, E.Tidx, E.nT, C);
+}
+
+// Set-up: G = B~_ST (B~_TT)^{-1}, t-major over the unclipped box, zero for
+// the nodes in T; one thread per entry, FP64 sums in index order.
+__device__ inline bool embed_in_box(const EmbedDev& E, int e, int hm0, int hm1) {
+  const int u0 = e % hm0, rest = e / hm0;
+  const int u1 = rest % hm1, u2 = rest / hm1;
+  return u0 >= E.off[0] && u0 < E.off[0] + E.m[0] && u1 >= E.off[1] && u1 < E.off[1] + E.m[1] &&
+         u2 >= E.off[2] && u2 < E.off[2] + E.m[2];
+}
+
+__global__ void k_embed_gmat(EmbedDev E, const __bf16* __restrict__ Ah, const __bf16* __restrict__ Al,
+                             int ld, int hm0, int hm1, int mH, const double* __restrict__ C,
+                             float* __restrict__ G) {
+  const long tot = (long)E.nT * mH;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int t = (int)(idx / mH), e = (int)(idx % mH);
+    double v = 0.0;
+    if (embed_in_box(E, e, hm0, hm1)) {
+      for (int j = 0; j < E.nT; ++j) {
+        const long a = (long)e * ld + E.Tidx[j];
+        double b = (double)(float)Ah[a];
+        if (Al != nullptr) b += (double)(float)Al[a];
+        v += b * C[(long)j * E.nT + t];
+      }
+    }
+    G[idx] = (float)v;
+  }
+}
+
+void launch_embed_gmat(const ddeig_problem* P, const EmbedDev& E, const double* C, float* G,
+                       hipStream_t s) {
+  const DenseHost& H = P->dh;
+  const long tot = (long)E.nT * H.m;
+  const int blocks = (int)std::min<long>((tot + kBlock - 1) / kBlock, 16384);
+  hipLaunchKernelGGL(k_embed_gmat, dim3(blocks), dim3(kBlock), 0, s, E, H.Ah, H.Al, H.ld,
+                     H.box.m[0], H.box.m[1], H.m, C, G);
+}
+
+// Per application: y_S = u_S - G u_T for up to kEmbChunk members of a class,
+// u = B~ [r_S; 0] the GEMM result (split-K partials added in split order).
+// The corrected solution replaces split 0 of Z and the other splits are
+// cleared, so the extension reads clipped and unclipped members alike.
+// Block (job, 32 unknowns of the unclipped box): thread (unknown, phase) adds
+// the terms t = phase mod 8, 16 loads at a time; the 8 phase sums are added
+// in phase order.  Nodes in T are left alone (no member reads them).
+constexpr int kEmbPh = 8, kEmbE = kBlock / kEmbPh, kEmbBatch = 16;
+
+__global__ void __launch_bounds__(kBlock) k_embed_correct(const EmbedJob* __restrict__ jobs,
+                                                          const EmbedDev* __restrict__ cls,
+                                                          float* __restrict__ Z, long zsplit,
+                                                          int ksplit, int ld, int hm0, int hm1,
+                                                          int mH, const PcgState* __restrict__ st) {
+  __shared__ float uT[kEmbChunk * kEmbMaxT];
+  __shared__ float red[kEmbPh][kEmbE][kEmbChunk];
+  if (st != nullptr && st->done) return;
+  const EmbedJob jb = jobs[blockIdx.x];
+  const EmbedDev E = cls[jb.cls];
+  for (int idx = threadIdx.x; idx < jb.nm * E.nT; idx += kBlock) {
+    const int m = idx / E.nT, t = idx - m * E.nT;
+    const long base = (long)(E.row0 + jb.mem0 + m) * ld + E.Tidx[t];
+    float u = 0.0f;
+    for (int sp = 0; sp < ksplit; ++sp) u += Z[sp * zsplit + base];
+    uT[m * E.nT + t] = u;
+  }
+  __syncthreads();
+  const int el = threadIdx.x % kEmbE, ph = threadIdx.x / kEmbE;
+  const int e = blockIdx.y * kEmbE + el;
+  const bool inS = e < mH && embed_in_box(E, e, hm0, hm1);
+  float acc[kEmbChunk];
+#pragma unroll
+  for (int m = 0; m < kEmbChunk; ++m) acc[m] = 0.0f;
+  if (inS) {
+    for (int t0 = ph; t0 < E.nT; t0 += kEmbPh * kEmbBatch) {
+      float gv[kEmbBatch];
+#pragma unroll
+      for (int q = 0; q < kEmbBatch; ++q) {
+        const int t = t0 + q * kEmbPh;
+        gv[q] = t < E.nT ? E.G[(long)t * mH + e] : 0.0f;
+      }
+#pragma unroll
+      for (int q = 0; q < kEmbBatch; ++q) {
+        const int t = t0 + q * kEmbPh;
+        if (t < E.nT) {
+#pragma unroll
+          for (int m = 0; m < kEmbChunk; ++m)
+            if (m < jb.nm) acc[m] += gv[q] * uT[m * E.nT + t];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < kEmbChunk; ++m) red[ph][el][m] = acc[m];
+  __syncthreads();
+  if (ph != 0 || !inS) return;
+  for (int m = 0; m < jb.nm; ++m) {
+    float corr = 0.0f;
+    for (int q = 0; q < kEmbPh; ++q) corr += red[q][el][m];
+    const long base = (long)(E.row0 + jb.mem0 + m) * ld + e;
+    float u = 0.0f;
+    for (int sp = 0; sp < ksplit; ++sp) u += Z[sp * zsplit + base];
+    Z[base] = u - corr;
+    for (int sp = 1; sp < ksplit; ++sp) Z[sp * zsplit + base] = 0.0f;
+  }
+}
+
+void launch_embed_fix(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
+  if (P->nembjobs == 0) return;
+  const DenseHost& H = P->dh;
+  const long zsplit = (long)H.mp * H.ld;
+  hipLaunchKernelGGL(k_embed_correct, dim3(P->nembjobs, (H.m + kEmbE - 1) / kEmbE), dim3(kBlock), 0,
+                     s, P->dEmbJobs, P->dEmb, H.Z, zsplit, P->ksplit, H.ld, H.box.m[0],
+                     H.box.m[1], H.m, st);
+}
+
+// Batches of more rows: 128 x 128 MFMA tiles.  local_prec 2 (bf16x3):
 // residual and inverse as hi/lo pairs, three products; local_prec 3: both
 // single bf16, one product.
 void launch_dense_gemm(const ddeig_problem* P, const PcgState* st, hipStream_t s) {

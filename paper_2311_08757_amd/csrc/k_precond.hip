@@ -143,7 +143,9 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Geo g, int ntypes, PcgState
         const int sid = g.p == 1 ? a0.c[q0] - 1 : (a0.c[q0] - 1) + g.L * (a1.c[q1] - 1);
         const SubTS ts = subts[sid];
         const TypeDev& td = stypes[ts.type];
-        const long e = a0.u[q0] + (long)td.m[0] * (a1.u[q1] + (long)td.m[1] * i2);
+        // row index inside the member's batch row (the unclipped box for dense solves)
+        const long e = (a0.u[q0] + td.off[0]) +
+                       (long)td.hm[0] * ((a1.u[q1] + td.off[1]) + (long)td.hm[1] * (i2 + td.off[2]));
         if (td.dense) {
           td.Rh[(long)ts.slot * td.ld + e] = hi;
           if (td.Rl != nullptr) td.Rl[(long)ts.slot * td.ld + e] = lo;
@@ -306,7 +308,8 @@ __global__ void __launch_bounds__(kBlock) k_extend(Geo g, int delta, int pu, int
         const SubTS ts = subts[sid];
         const TypeDev& td = stypes[ts.type];
         const int u1 = g.p == 2 ? a1.u[q1] : i[1];
-        const long e = a0.u[q0] + (long)td.m[0] * (u1 + (long)td.m[1] * i2);
+        const long e = (a0.u[q0] + td.off[0]) +
+                       (long)td.hm[0] * ((u1 + td.off[1]) + (long)td.hm[1] * (i2 + td.off[2]));
         if (td.dense) {
           const float* zp = td.Z + (long)ts.slot * td.ld + e;
           float zs = 0.0f;
