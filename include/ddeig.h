@@ -169,16 +169,20 @@ ddeig_status ddeig_pcg_solve(ddeig_problem* P, const double* b, double* x, doubl
 ddeig_status ddeig_inverse_iteration(ddeig_problem* P, double* x, double tol_x, int maxit_outer,
                                      double rtol_inner, int maxit_inner, ddeig_eig_info* info);
 
-/* Measurement support: launches one kernel of the hot path `reps` times on the
- * library's stream between two HIP events and returns the mean duration of one
- * launch in *avg_us (synchronises).  which = 0: the A_sigma stencil on x
- * (y receives A_sigma x); 1: the level-1 local solves on the batch left by the
- * last apply_precond (dense classes: the MFMA GEMM of the classes with many
- * members; otherwise the block-chain solves), so call apply_precond first;
- * 2: the whole preconditioner on x (y receives z).  *work receives the
- * algorithmic work of one launch: bytes for which = 0 (16 per unknown), flops
- * for which = 1 (2 m^2 per subdomain solved by the kernel: dense inverse
- * applied once; 4 nch b^2 for block-chain solves), 0 for which = 2. */
+/* Measurement support: launches one kernel (or step) of the hot path `reps`
+ * times on the library's stream between two HIP events and returns the mean
+ * duration of one launch in *avg_us (synchronises).  which = 0: the A_sigma
+ * stencil on x (y receives A_sigma x); 1: the level-1 local solves on the
+ * batch left by the last apply_precond (dense: the MFMA GEMM over all
+ * subdomains, m = unknowns of the unclipped box; otherwise the block-chain
+ * solves), so call apply_precond first; 2: the whole preconditioner on x
+ * (y receives z); 3: the restriction of x into the batch; 4: the extension
+ * (y receives z from the current local and coarse solutions; x plays r);
+ * 5: the clipped-class correction of the dense local solves (no-op
+ * otherwise).  *work receives the algorithmic work of one launch: bytes for
+ * which = 0 (16 per unknown), flops for which = 1 (2 m^2 per subdomain: dense
+ * inverse applied once; 4 nch b^2 per subdomain for block-chain solves), 0
+ * otherwise. */
 ddeig_status ddeig_profile_kernel(ddeig_problem* P, int which, int reps, const double* x, double* y,
                                   double* avg_us, double* work);
 

@@ -200,11 +200,13 @@ void precond_apply(ddeig_problem* P, double* r, double* z, Red* dot, PcgState* s
   if (coarse) {
     launch_coarse_rhs(P, r, st, P->aux);
     launch_coarse_solve(P, st, P->aux);
+    if (P->opt.local_prec >= 2) launch_coarse_field(P, st, P->aux);
   }
   if (side) {
     check_hip(hipEventRecord(P->ev_join, P->aux), "record join");
     check_hip(hipStreamWaitEvent(P->stream, P->ev_join, 0), "wait join");
   }
+
   CheckArgs c = chk ? *chk : coff;
   if (chk && rr) c.rr = *rr;
   launch_extend(P, r, z, coarse, dot, st, c, P->stream);
@@ -514,7 +516,6 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
       maxb = std::max(maxb, hb.b);
       // classes: their box inside the unclipped one, their rows, and for the
       // clipped ones the node list T of the unclipped box outside their box
-      int row = 0;
       for (size_t t = 0; t < P->types.size(); ++t) {
         auto& T = P->types[t];
         const auto& sd0 = P->subs[T.members[0]];
@@ -525,8 +526,6 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
           if (T.off[a] < 0 || T.off[a] + T.box.m[a] > hb.m[a])
             throw Failure{DDEIG_EINTERNAL, "subdomain box outside the unclipped box"};
         }
-        T.row0 = row;
-        row += T.nmem;
         const int nT = H.m - nS;
         if (nT > 0) {
           if (nT > ddeig::kEmbMaxT)
@@ -544,8 +543,11 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
               }
           ddeig::EmbedDev E{};
           E.nT = nT;
-          E.row0 = T.row0;
           E.nmem = T.nmem;
+          int* dR = dalloc<int>(P, T.members.size());
+          check_hip(hipMemcpyAsync(dR, T.members.data(), sizeof(int) * T.members.size(),
+                                   hipMemcpyHostToDevice, s), "copy member rows");
+          E.rows = dR;
           for (int a = 0; a < 3; ++a) { E.off[a] = T.off[a]; E.m[a] = T.box.m[a]; }
           int* dT = dalloc<int>(P, tl.size());
           check_hip(hipMemcpyAsync(dT, tl.data(), sizeof(int) * tl.size(), hipMemcpyHostToDevice, s),
@@ -645,7 +647,7 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
       std::vector<ddeig::SubTS> ts(nsub);
       for (int sid = 0; sid < nsub; ++sid) {
         const auto& sd = P->subs[sid];
-        ts[sid] = ddeig::SubTS{sd.type, dense ? P->types[sd.type].row0 + sd.slot : sd.slot};
+        ts[sid] = ddeig::SubTS{sd.type, dense ? sid : sd.slot};
       }
       std::vector<int> first(P->types.size());
       std::vector<double*> phis(P->types.size());
@@ -764,6 +766,7 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
     }
     if (p == 1) P->dXC[1] = P->dXC[0];  // unused second axis
     P->cy = dalloc<double>(P, nsub);
+    P->cfield = dalloc<double>(P, p == 1 ? (size_t)g.N[0] : (size_t)g.N[0] * g.N[1]);
     P->A0inv = dalloc<double>(P, (size_t)nsub * nsub);
     check_hip(hipMemsetAsync(P->flag, 0, sizeof(int), s), "memset flag");
     check_hip(hipMemsetAsync(P->psi, 0, sizeof(double) * g.tsize, s), "memset psi");
@@ -787,6 +790,7 @@ void ddeig_destroy(ddeig_problem* P) {
     (void)hipStreamSynchronize(P->aux);
     (void)hipStreamDestroy(P->aux);
   }
+
   if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
   if (P->ev_join) (void)hipEventDestroy(P->ev_join);
   for (void* p : P->allocs) (void)hipFree(p);
@@ -797,8 +801,8 @@ void ddeig_destroy(ddeig_problem* P) {
 ddeig_status ddeig_profile_kernel(ddeig_problem* P, int which, int reps, const double* x, double* y,
                                   double* avg_us, double* work) {
   if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
-  if (reps < 1 || which < 0 || which > 2 || !avg_us) return set_error(DDEIG_EINVAL, "invalid arguments");
-  if ((which == 0 || which == 2) && (validate_vec(x, "x") || validate_vec(y, "y"))) return DDEIG_EINVAL;
+  if (reps < 1 || which < 0 || which > 5 || !avg_us) return set_error(DDEIG_EINVAL, "invalid arguments");
+  if (which != 1 && which != 5 && (validate_vec(x, "x") || validate_vec(y, "y"))) return DDEIG_EINVAL;
   if (!P->shifted) return set_error(DDEIG_ESTATE, "profile_kernel before the shift is set");
   API_GUARD_BEGIN
   const hipStream_t s = P->stream;
@@ -813,10 +817,18 @@ ddeig_status ddeig_profile_kernel(ddeig_problem* P, int which, int reps, const d
       for (auto& t : P->types) w += 4.0 * t.box.nch * (double)t.box.b * t.box.b * t.nmem;
     }
   }
+  Red dot = slot(P, 8);
+  XrArgs xoff{};
+  xoff.on = 0;
+  CheckArgs coff{};
+  coff.on = 0;
   auto launch = [&]() {
     if (which == 0) launch_stencil(P, P->tabAs, x, y, nullptr, nullptr, s);
     else if (which == 1) launch_local_solves(P, nullptr, s);
-    else precond_apply(P, const_cast<double*>(x), y, nullptr, nullptr);
+    else if (which == 2) precond_apply(P, const_cast<double*>(x), y, nullptr, nullptr);
+    else if (which == 3) launch_restrict(P, const_cast<double*>(x), nullptr, xoff, nullptr, s);
+    else if (which == 4) launch_extend(P, x, y, P->opt.coarse, &dot, nullptr, coff, s);
+    else if (P->opt.local_prec >= 2) launch_embed_fix(P, nullptr, s);
   };
   launch();
   hipEvent_t e0, e1;

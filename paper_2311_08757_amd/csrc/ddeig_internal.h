@@ -13,6 +13,7 @@
 namespace ddeig {
 
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
+constexpr int kBig = 1024;         // workgroup of the node-parallel restriction / extension
 constexpr int kRedBlocks = 512;    // grid of the coarse-setup style reducing kernels
 constexpr int kMaxRed = 1024;      // largest grid of a reducing kernel (partial-sum capacity)
 constexpr int kRedSlots = 16;
@@ -100,16 +101,14 @@ struct SubType {
   double* batch = nullptr;  // nmem * nch * b local vectors
   double* phi = nullptr;    // coarse weights of the class (box order)
   // dense local solves (local_prec >= 2): the class box is the node range
-  // [off, off + m) of the unclipped box along every axis; its members use rows
-  // [row0, row0 + nmem) of the dense batch
+  // [off, off + m) of the unclipped box along every axis
   int off[3] = {0, 0, 0};
-  int row0 = 0;
 };
 
 // Dense local solves: the unclipped, period-aligned subdomain box (the box of
 // an interior cell), its FP64 block-chain factors, its inverse as bf16 (hi /
-// lo) and the batch of all subdomains' restricted residuals R (one row per
-// subdomain, zero outside the subdomain's own box) with the split-K partial
+// lo) and the batch of all subdomains' restricted residuals R (row = the
+// subdomain id, zero outside the subdomain's own box) with the split-K partial
 // products Z[split][row][e].
 struct DenseHost {
   Box box;
@@ -124,10 +123,19 @@ struct DenseHost {
 // unclipped inverse B, stored t-major over the unclipped box (G[t * mH + e],
 // zero for e in T; see k_dense.hip).
 struct EmbedDev {
-  int nT, row0, nmem;
+  int nT, nmem;
   int off[3], m[3];
+  const int* rows;  // batch rows (subdomain ids) of the members
   const int* Tidx;
   const float* G;
+};
+// Batch operands of the dense-mode restriction / extension kernels.
+struct DenseArgs {
+  __bf16* Rh;
+  __bf16* Rl;
+  const float* Z;
+  long zsplit;
+  int ld, ksplit, hm0, hm1;
 };
 struct EmbedJob {
   int cls, mem0, nm;
@@ -248,6 +256,7 @@ struct ddeig_problem {
   double* A0inv = nullptr;  // nsub x nsub
   double* crhs = nullptr;   // nsub
   double* cy = nullptr;     // nsub
+  double* cfield = nullptr; // coarse field sum_c D_c y0_c per expanding-index point (dense solves)
   // work vectors (n each)
   double *r = nullptr, *z = nullptr, *q = nullptr, *u = nullptr, *w = nullptr;
   double* pp[2] = {nullptr, nullptr};  // CG directions of even / odd iterations
@@ -313,6 +322,7 @@ void launch_restrict(const ddeig_problem* P, double* r, PcgState* st, const XrAr
                      hipStream_t s);
 void launch_local_solves(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 void launch_coarse_solve(const ddeig_problem* P, const PcgState* st, hipStream_t s);
+void launch_coarse_field(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 void launch_coarse_rhs(const ddeig_problem* P, const double* r, const PcgState* st, hipStream_t s);
 void launch_coarse_phi(const ddeig_problem* P, hipStream_t s);
 void launch_extend(const ddeig_problem* P, const double* r, double* z, int coarse, Red* dot,

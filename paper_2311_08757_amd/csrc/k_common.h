@@ -5,11 +5,12 @@
 
 namespace ddeig {
 
-// Sum over a workgroup of kBlock threads; every thread receives the total.
-// The order of additions is fixed (shuffle tree inside each wave64, then the
+// Sum over a workgroup of NT threads; every thread receives the total.  The
+// order of additions is fixed (shuffle tree inside each wave64, then the
 // waves in order), so repeated runs give identical bits.
-__device__ inline double block_sum(double v) {
-  __shared__ double sh_red[kBlock / 64 + 1];
+template <int NT>
+__device__ inline double block_sum_n(double v) {
+  __shared__ double sh_red[NT / 64 + 1];
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();
@@ -17,24 +18,29 @@ __device__ inline double block_sum(double v) {
   __syncthreads();
   if (threadIdx.x == 0) {
     double t = 0.0;
-    for (int i = 0; i < kBlock / 64; ++i) t += sh_red[i];
-    sh_red[kBlock / 64] = t;
+    for (int i = 0; i < NT / 64; ++i) t += sh_red[i];
+    sh_red[NT / 64] = t;
   }
   __syncthreads();
-  return sh_red[kBlock / 64];
+  return sh_red[NT / 64];
 }
 
+__device__ inline double block_sum(double v) { return block_sum_n<kBlock>(v); }
+
 // One partial sum per block (see Red).
+template <int NT = kBlock>
 __device__ inline void write_partial(double v, double* part) {
-  const double b = block_sum(v);
+  const double b = block_sum_n<NT>(v);
   if (threadIdx.x == 0) part[blockIdx.x] = b;
 }
 
-// The sum of the np partials of a producing kernel, added in block order.
+// The sum of the np partials of a producing kernel, added in block order by
+// a workgroup of NT threads.
+template <int NT = kBlock>
 __device__ inline double sum_partials(const double* part, int np) {
   double v = 0.0;
-  for (int i = threadIdx.x; i < np; i += kBlock) v += part[i];
-  return block_sum(v);
+  for (int i = threadIdx.x; i < np; i += NT) v += part[i];
+  return block_sum_n<NT>(v);
 }
 
 // Offsets of tap t; with ntaps = 9 (2-D) there is no third dim and d2 = 0.

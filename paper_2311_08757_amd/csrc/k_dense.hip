@@ -373,46 +373,65 @@ void launch_embed_gmat(const ddeig_problem* P, const EmbedDev& E, const double* 
 // The corrected solution replaces split 0 of Z and the other splits are
 // cleared, so the extension reads clipped and unclipped members alike.
 // Block (job, 32 unknowns of the unclipped box): thread (unknown, phase) adds
-// the terms t = phase mod 8, 16 loads at a time; the 8 phase sums are added
-// in phase order.  Nodes in T are left alone (no member reads them).
-constexpr int kEmbPh = 8, kEmbE = kBlock / kEmbPh, kEmbBatch = 16;
+// the terms t = phase mod 8 in batches of kEmbG; the 8 phase sums are added
+// in phase order.  The loads that do not depend on u_T (the first batch of the
+// thread's column of G, its own Z entries) are issued before u_T is gathered.
+// Nodes in T are left alone (no member reads them).
+constexpr int kEmbPh = 8, kEmbE = kBlock / kEmbPh, kEmbG = 32;  // G loads per batch
 
+template <int KS>
 __global__ void __launch_bounds__(kBlock) k_embed_correct(const EmbedJob* __restrict__ jobs,
                                                           const EmbedDev* __restrict__ cls,
                                                           float* __restrict__ Z, long zsplit,
-                                                          int ksplit, int ld, int hm0, int hm1,
-                                                          int mH, const PcgState* __restrict__ st) {
+                                                          int ld, int hm0, int hm1, int mH,
+                                                          const PcgState* __restrict__ st) {
   __shared__ float uT[kEmbChunk * kEmbMaxT];
   __shared__ float red[kEmbPh][kEmbE][kEmbChunk];
   if (st != nullptr && st->done) return;
   const EmbedJob jb = jobs[blockIdx.x];
   const EmbedDev E = cls[jb.cls];
-  for (int idx = threadIdx.x; idx < jb.nm * E.nT; idx += kBlock) {
-    const int m = idx / E.nT, t = idx - m * E.nT;
-    const long base = (long)(E.row0 + jb.mem0 + m) * ld + E.Tidx[t];
-    float u = 0.0f;
-    for (int sp = 0; sp < ksplit; ++sp) u += Z[sp * zsplit + base];
-    uT[m * E.nT + t] = u;
-  }
-  __syncthreads();
   const int el = threadIdx.x % kEmbE, ph = threadIdx.x / kEmbE;
   const int e = blockIdx.y * kEmbE + el;
   const bool inS = e < mH && embed_in_box(E, e, hm0, hm1);
+  const int nq = (E.nT - ph + kEmbPh - 1) / kEmbPh;  // terms t = ph + kEmbPh q, q < nq
+  float gv[kEmbG];
+  float zown[kEmbChunk][KS];
+  auto load_batch = [&](int q0) {
+#pragma unroll
+    for (int q = 0; q < kEmbG; ++q)
+      if (q0 + q < nq) gv[q] = E.G[(long)(ph + kEmbPh * (q0 + q)) * mH + e];
+  };
+  if (inS) {
+    load_batch(0);
+    if (ph == 0) {
+#pragma unroll
+      for (int m = 0; m < kEmbChunk; ++m)
+        if (m < jb.nm) {
+          const long base = (long)E.rows[jb.mem0 + m] * ld + e;
+#pragma unroll
+          for (int sp = 0; sp < KS; ++sp) zown[m][sp] = Z[sp * zsplit + base];
+        }
+    }
+  }
+  for (int idx = threadIdx.x; idx < jb.nm * E.nT; idx += kBlock) {
+    const int m = idx / E.nT, t = idx - m * E.nT;
+    const long base = (long)E.rows[jb.mem0 + m] * ld + E.Tidx[t];
+    float u = 0.0f;
+#pragma unroll
+    for (int sp = 0; sp < KS; ++sp) u += Z[sp * zsplit + base];
+    uT[m * E.nT + t] = u;
+  }
+  __syncthreads();
   float acc[kEmbChunk];
 #pragma unroll
   for (int m = 0; m < kEmbChunk; ++m) acc[m] = 0.0f;
   if (inS) {
-    for (int t0 = ph; t0 < E.nT; t0 += kEmbPh * kEmbBatch) {
-      float gv[kEmbBatch];
+    for (int q0 = 0; q0 < nq; q0 += kEmbG) {
+      if (q0 > 0) load_batch(q0);
 #pragma unroll
-      for (int q = 0; q < kEmbBatch; ++q) {
-        const int t = t0 + q * kEmbPh;
-        gv[q] = t < E.nT ? E.G[(long)t * mH + e] : 0.0f;
-      }
-#pragma unroll
-      for (int q = 0; q < kEmbBatch; ++q) {
-        const int t = t0 + q * kEmbPh;
-        if (t < E.nT) {
+      for (int q = 0; q < kEmbG; ++q) {
+        if (q0 + q < nq) {
+          const int t = ph + kEmbPh * (q0 + q);
 #pragma unroll
           for (int m = 0; m < kEmbChunk; ++m)
             if (m < jb.nm) acc[m] += gv[q] * uT[m * E.nT + t];
@@ -424,14 +443,18 @@ __global__ void __launch_bounds__(kBlock) k_embed_correct(const EmbedJob* __rest
   for (int m = 0; m < kEmbChunk; ++m) red[ph][el][m] = acc[m];
   __syncthreads();
   if (ph != 0 || !inS) return;
-  for (int m = 0; m < jb.nm; ++m) {
+#pragma unroll
+  for (int m = 0; m < kEmbChunk; ++m) {
+    if (m >= jb.nm) break;
     float corr = 0.0f;
     for (int q = 0; q < kEmbPh; ++q) corr += red[q][el][m];
-    const long base = (long)(E.row0 + jb.mem0 + m) * ld + e;
     float u = 0.0f;
-    for (int sp = 0; sp < ksplit; ++sp) u += Z[sp * zsplit + base];
+#pragma unroll
+    for (int sp = 0; sp < KS; ++sp) u += zown[m][sp];
+    const long base = (long)E.rows[jb.mem0 + m] * ld + e;
     Z[base] = u - corr;
-    for (int sp = 1; sp < ksplit; ++sp) Z[sp * zsplit + base] = 0.0f;
+#pragma unroll
+    for (int sp = 1; sp < KS; ++sp) Z[sp * zsplit + base] = 0.0f;
   }
 }
 
@@ -439,9 +462,11 @@ void launch_embed_fix(const ddeig_problem* P, const PcgState* st, hipStream_t s)
   if (P->nembjobs == 0) return;
   const DenseHost& H = P->dh;
   const long zsplit = (long)H.mp * H.ld;
-  hipLaunchKernelGGL(k_embed_correct, dim3(P->nembjobs, (H.m + kEmbE - 1) / kEmbE), dim3(kBlock), 0,
-                     s, P->dEmbJobs, P->dEmb, H.Z, zsplit, P->ksplit, H.ld, H.box.m[0],
-                     H.box.m[1], H.m, st);
+  // the K split is 1..3 by construction (assemble)
+  auto kern = P->ksplit == 1 ? k_embed_correct<1> : (P->ksplit == 2 ? k_embed_correct<2>
+                                                                     : k_embed_correct<3>);
+  hipLaunchKernelGGL(kern, dim3(P->nembjobs, (H.m + kEmbE - 1) / kEmbE), dim3(kBlock), 0, s,
+                     P->dEmbJobs, P->dEmb, H.Z, zsplit, H.ld, H.box.m[0], H.box.m[1], H.m, st);
 }
 
 // Batches of more rows: 128 x 128 MFMA tiles.  local_prec 2 (bf16x3):

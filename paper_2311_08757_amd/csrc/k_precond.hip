@@ -85,22 +85,25 @@ __device__ inline double cover_weight(const Geo& g, int delta, int pu, const XCo
 }
 
 // Scatter r into the subdomain batches (box natural order; bf16 rows, as a
-// hi/lo pair for local_prec 2, for dense classes): node-parallel over row segments of kBlock x1 positions;
-// every node writes its copy into each covering subdomain (at most 2^p), so
-// reads of r and writes of a batch row are both coalesced.  With xr.on the
-// node first takes the CG update of iteration k (x += alpha p, r -= alpha q,
-// written back) and the kernel leaves the partials of ||r||^2 in rr.
-__global__ void __launch_bounds__(kBlock) k_restrict(Geo g, int ntypes, PcgState* __restrict__ st,
-                                                     XrArgs xr, Red rr, double* __restrict__ r,
-                                                     const TypeDev* __restrict__ types,
-                                                     const SubTS* __restrict__ subts,
-                                                     const XCover* __restrict__ xc0,
-                                                     const XCover* __restrict__ xc1) {
+// hi/lo pair for local_prec 2, for dense classes): node-parallel over row
+// segments of kBlock x1 positions, four segments per workgroup of kBig
+// threads (one node per thread, so the dependent table loads of the nodes
+// overlap); every node writes its copy into each covering subdomain (at most
+// 2^p), so reads of r and writes of a batch row are both coalesced.  With
+// xr.on the node first takes the CG update of iteration k (x += alpha p,
+// r -= alpha q, written back) and the kernel leaves the partials of ||r||^2
+// in rr.
+__global__ void __launch_bounds__(kBig) k_restrict(Geo g, int ntypes, PcgState* __restrict__ st,
+                                                   XrArgs xr, Red rr, double* __restrict__ r,
+                                                   const TypeDev* __restrict__ types,
+                                                   const SubTS* __restrict__ subts,
+                                                   const XCover* __restrict__ xc0,
+                                                   const XCover* __restrict__ xc1) {
   __shared__ TypeDev stypes[kMaxTypes];
   if (st != nullptr && st->done) return;
   double alpha = 0.0;
   if (xr.on) {
-    const double gamma = sum_partials(xr.gam.part, xr.gam.np);
+    const double gamma = sum_partials<kBig>(xr.gam.part, xr.gam.np);
     if (!(gamma > 0.0)) {
       if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->done = 2;
@@ -115,10 +118,13 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Geo g, int ntypes, PcgState
   const int N0 = g.N[0], N1 = g.N[1];
   const int segs = (N0 + kBlock - 1) / kBlock;
   const long items = (long)segs * N1 * g.N[2];
+  const int sub = threadIdx.x / kBlock, tx = threadIdx.x % kBlock;
   double acc = 0.0;
-  for (long it = blockIdx.x; it < items; it += gridDim.x) {
+  for (long grp = blockIdx.x; grp * (kBig / kBlock) < items; grp += gridDim.x) {
+    const long it = grp * (kBig / kBlock) + sub;
+    if (it >= items) continue;
     const int line = (int)(it / segs);
-    const int i0 = (int)(it - (long)line * segs) * kBlock + threadIdx.x;
+    const int i0 = (int)(it - (long)line * segs) * kBlock + tx;
     if (i0 >= N0) continue;
     const int i2 = g.D == 3 ? (int)fdiv((unsigned)line, g.fN1) : 0;
     const int i1 = line - i2 * N1;
@@ -155,22 +161,208 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Geo g, int ntypes, PcgState
       }
     }
   }
-  if (xr.on) write_partial(acc, rr.part);
+  if (xr.on) write_partial<kBig>(acc, rr.part);
+}
+
+// ---- dense local solves: restriction and extension with arithmetic addressing
+//
+// With dense local solves the batch row of a subdomain is its id and every
+// subdomain's box sits inside the unclipped box of its cell, so the batch
+// index of a node follows from the node and cell indices alone: along an
+// expanding axis the unclipped box of cell c starts at node (c - 1) n_e -
+// delta, giving the box-local index i + delta - (c - 1) n_e.  The kernels
+// below therefore issue all of a node's loads at once (no table look-ups in
+// between); the covering cells come from covering() and the partition-of-unity
+// weights from the same per-axis tables as in the generic kernels.
+__device__ inline long dense_index(const Geo& g, int delta, const DenseArgs& da, const int* i,
+                                   int c0, int c1) {
+  const int u0 = i[0] + delta - (c0 - 1) * g.ne;
+  const int u1 = g.p == 2 ? i[1] + delta - (c1 - 1) * g.ne : i[1];
+  return u0 + (long)da.hm0 * (u1 + (long)da.hm1 * i[2]);
+}
+
+// Covering cells of a node: slot q = q0 + 2 q1 (q1 = 0 for one expanding
+// axis) is cell (clo0 + q0, clo1 + q1) when that exists.  Out-of-range slots
+// are clamped to an existing cell so that their loads stay valid and can be
+// issued unconditionally; `val` masks their contributions.
+template <int PX>
+struct Cover {
+  static constexpr int NC = PX == 1 ? 2 : 4;
+  int clo0, chi0, clo1, chi1;
+  __device__ Cover(const Geo& g, int delta, const int* i) {
+    clo1 = chi1 = 1;
+    covering(i[0] + 1, g.ne, g.L, delta, clo0, chi0);
+    if (PX == 2) covering(i[1] + 1, g.ne, g.L, delta, clo1, chi1);
+  }
+  __device__ bool val(int q) const { return clo0 + (q & 1) <= chi0 && clo1 + (q >> 1) <= chi1; }
+  __device__ int c0(int q) const { return min(clo0 + (q & 1), chi0); }
+  __device__ int c1(int q) const { return min(clo1 + (q >> 1), chi1); }
+};
+
+template <int PX>
+__global__ void __launch_bounds__(kBig) k_restrict_dense(Geo g, int delta, PcgState* __restrict__ st,
+                                                         XrArgs xr, Red rr, double* __restrict__ r,
+                                                         DenseArgs da) {
+  if (st != nullptr && st->done) return;
+  double alpha = 0.0;
+  if (xr.on) {
+    const double gamma = sum_partials<kBig>(xr.gam.part, xr.gam.np);
+    if (!(gamma > 0.0)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->done = 2;
+        st->iters = xr.k - 1;
+      }
+      return;
+    }
+    alpha = st->rho[(xr.k - 1) & 1] / gamma;
+  }
+  const int N0 = g.N[0], N1 = g.N[1];
+  const int segs = (N0 + kBlock - 1) / kBlock;
+  const long items = (long)segs * N1 * g.N[2];
+  const int sub = threadIdx.x / kBlock, tx = threadIdx.x % kBlock;
+  double acc = 0.0;
+  for (long grp = blockIdx.x; grp * (kBig / kBlock) < items; grp += gridDim.x) {
+    const long it = grp * (kBig / kBlock) + sub;
+    if (it >= items) continue;
+    const int line = (int)(it / segs);
+    const int i0 = (int)(it - (long)line * segs) * kBlock + tx;
+    if (i0 >= N0) continue;
+    const int i2 = g.D == 3 ? (int)fdiv((unsigned)line, g.fN1) : 0;
+    const int i[3] = {i0, line - i2 * N1, i2};
+    const long k = i0 + (long)N0 * line;
+    double rv = r[k];
+    if (xr.on) {
+      rv -= alpha * xr.q[k];
+      xr.x[k] += alpha * xr.p[k];
+      r[k] = rv;
+      acc += rv * rv;
+    }
+    const __bf16 hi = (__bf16)(float)rv;
+    const __bf16 lo = (__bf16)(float)(rv - (double)(float)hi);
+    const Cover<PX> cv(g, delta, i);
+#pragma unroll
+    for (int q = 0; q < Cover<PX>::NC; ++q) {
+      if (!cv.val(q)) continue;
+      const int c0 = cv.c0(q), c1 = cv.c1(q);
+      const long at = (long)((c0 - 1) + g.L * (c1 - 1)) * da.ld + dense_index(g, delta, da, i, c0, c1);
+      da.Rh[at] = hi;
+      if (da.Rl != nullptr) da.Rl[at] = lo;
+    }
+  }
+  if (xr.on) write_partial<kBig>(acc, rr.part);
+}
+
+// z = sum_c R_c^T y_c + psi_ext cf (cf from k_coarse_field when coarse != 0).
+template <int PX, int KS>
+__global__ void __launch_bounds__(kBig) k_extend_dense(Geo g, int delta, int coarse,
+                                                       PcgState* __restrict__ st, CheckArgs chk,
+                                                       DenseArgs da, const double* __restrict__ psi,
+                                                       const double* __restrict__ cf,
+                                                       const double* __restrict__ r,
+                                                       double* __restrict__ z, int use_dot, Red dot) {
+  constexpr int NC = Cover<PX>::NC;
+  if (st != nullptr && st->done) return;
+  if (chk.on) {
+    const double rn2 = sum_partials<kBig>(chk.rr.part, chk.rr.np);
+    const bool conv = rn2 <= st->tol2, last = chk.k >= chk.maxit;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->relres = sqrt(rn2 / st->r0n2);
+      if (chk.hist && chk.k < chk.hist_cap) chk.hist[chk.k] = st->relres;
+      st->iters = chk.k;
+      if (conv) st->done = 1;
+      else if (last) st->done = 4;
+    }
+    if (conv || last) return;
+  }
+  double acc = 0.0;
+  const int N0 = g.N[0], N1 = g.N[1];
+  const int segs = (N0 + kBlock - 1) / kBlock;
+  const long items = (long)segs * N1 * g.N[2];
+  const int sub = threadIdx.x / kBlock, tx = threadIdx.x % kBlock;
+  for (long grp = blockIdx.x; grp * (kBig / kBlock) < items; grp += gridDim.x) {
+    const long it = grp * (kBig / kBlock) + sub;
+    if (it >= items) continue;
+    const int line = (int)(it / segs);
+    const int i0 = (int)(it - (long)line * segs) * kBlock + tx;
+    if (i0 >= N0) continue;
+    const int i2 = g.D == 3 ? (int)fdiv((unsigned)line, g.fN1) : 0;
+    const int i[3] = {i0, line - i2 * N1, i2};
+    const long k = i0 + (long)N0 * line;
+    const Cover<PX> cv(g, delta, i);
+    // every load of the node first (independent of each other) ...
+    float zs[NC][KS];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const int c0 = cv.c0(q), c1 = cv.c1(q);
+      const int sid = (c0 - 1) + g.L * (c1 - 1);
+      const long at = (long)sid * da.ld + dense_index(g, delta, da, i, c0, c1);
+#pragma unroll
+      for (int sp = 0; sp < KS; ++sp) zs[q][sp] = da.Z[sp * da.zsplit + at];
+    }
+    const double rk = r[k];
+    double ps = 0.0, zc = 0.0;
+    if (coarse) {
+      // cell-local table node: x dims (i + 1) mod n_e
+      const int j0 = (int)((unsigned)(i0 + 1) - g.ne * fdiv((unsigned)(i0 + 1), g.fne));
+      const int j1 = PX == 2 ? (int)((unsigned)(i[1] + 1) - g.ne * fdiv((unsigned)(i[1] + 1), g.fne))
+                             : i[1];
+      ps = psi[j0 + (long)g.P[0] * (j1 + (long)g.P[1] * i2)];
+      zc = cf[PX == 1 ? (long)i0 : i0 + (long)N0 * i[1]];
+    }
+    // ... then the sums, cells in slot order and splits in split order
+    double zl = 0.0;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      if (!cv.val(q)) continue;
+      float zq = 0.0f;
+#pragma unroll
+      for (int sp = 0; sp < KS; ++sp) zq += zs[q][sp];
+      zl += (double)zq;
+    }
+    double zv = zl;
+    if (coarse) zv += ps * zc;
+    z[k] = zv;
+    acc += rk * zv;
+  }
+  if (use_dot) write_partial<kBig>(acc, dot.part);
+}
+
+DenseArgs dense_args(const ddeig_problem* P) {
+  const DenseHost& H = P->dh;
+  return DenseArgs{H.Rh, H.Rl, H.Z, (long)H.mp * H.ld, H.ld, P->ksplit, H.box.m[0], H.box.m[1]};
+}
+
+// Workgroups of the node-parallel kernels: four row segments per workgroup,
+// at most kMaxRed workgroups (partial-sum capacity).
+int node_grid(const Geo& g) {
+  const long segs = (g.N[0] + kBlock - 1) / kBlock;
+  const long items = segs * g.N[1] * g.N[2];
+  const long groups = (items + kBig / kBlock - 1) / (kBig / kBlock);
+  return (int)std::max<long>(1, std::min<long>(groups, kMaxRed));
 }
 
 void launch_restrict(const ddeig_problem* P, double* r, PcgState* st, const XrArgs& xr, Red* rr,
                      hipStream_t s) {
-  const long segs = (P->g.N[0] + kBlock - 1) / kBlock;
-  const long items = segs * P->g.N[1] * P->g.N[2];
-  const int blocks = (int)std::min<long>(items, xr.on ? kMaxRed : 16384);
+  const int blocks = node_grid(P->g);
   const Red none{nullptr, 0, nullptr};
   if (xr.on) rr->np = blocks;
-  hipLaunchKernelGGL(k_restrict, dim3(blocks), dim3(kBlock), 0, s, P->g, (int)P->types.size(),
-                     st, xr, xr.on ? *rr : none, r, P->dTypes, P->dSubTS, P->dXC[0], P->dXC[1]);
+  if (P->opt.local_prec >= 2) {
+    if (P->g.p == 1)
+      hipLaunchKernelGGL(k_restrict_dense<1>, dim3(blocks), dim3(kBig), 0, s, P->g, P->delta, st,
+                         xr, xr.on ? *rr : none, r, dense_args(P));
+    else
+      hipLaunchKernelGGL(k_restrict_dense<2>, dim3(blocks), dim3(kBig), 0, s, P->g, P->delta, st,
+                         xr, xr.on ? *rr : none, r, dense_args(P));
+  } else
+    hipLaunchKernelGGL(k_restrict, dim3(blocks), dim3(kBig), 0, s, P->g, (int)P->types.size(), st,
+                       xr, xr.on ? *rr : none, r, P->dTypes, P->dSubTS, P->dXC[0], P->dXC[1]);
 }
 
 // c_sub = phi_class . R_sub r  (R_0 r of def:algebraic-perfact-coarse-space):
-// one workgroup per subdomain, the box traversed in natural order.
+// one workgroup per subdomain.  Thread t takes the box elements t + kBlock q
+// (natural order; the grid line from a multiply-high division), 8 at a time
+// with all 16 loads issued before the products; the products are added in q
+// order, then the threads in a fixed order.
 __global__ void __launch_bounds__(kBlock) k_coarse_rhs(Geo g, const PcgState* __restrict__ st,
                                                        const double* __restrict__ r,
                                                        const TypeDev* __restrict__ types,
@@ -181,13 +373,24 @@ __global__ void __launch_bounds__(kBlock) k_coarse_rhs(Geo g, const PcgState* __
   const TypeDev td = types[sd.type];
   const int m0 = td.m[0], m1 = td.m[1];
   const int mtot = m0 * m1 * td.m[2];
+  constexpr int U = 8;
   double acc = 0.0;
-  for (int e = threadIdx.x; e < mtot; e += blockDim.x) {
-    const int line = (int)fdiv((unsigned)e, td.fm0);
-    const int u0 = e - line * m0;
-    const int u2 = line / m1, u1 = line - u2 * m1;
-    const long k = (sd.o[0] + u0) + (long)g.N[0] * ((sd.o[1] + u1) + (long)g.N[1] * (sd.o[2] + u2));
-    acc += td.phi[e] * r[k];
+  for (int e0 = threadIdx.x; e0 < mtot; e0 += U * kBlock) {
+    double ph[U], rv[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int e = e0 + q * kBlock;
+      ph[q] = rv[q] = 0.0;
+      if (e < mtot) {
+        const int line = (int)fdiv((unsigned)e, td.fm0);
+        const int u0 = e - line * m0;
+        const int u2 = line / m1, u1 = line - u2 * m1;
+        ph[q] = td.phi[e];
+        rv[q] = r[(sd.o[0] + u0) + (long)g.N[0] * ((sd.o[1] + u1) + (long)g.N[1] * (sd.o[2] + u2))];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) acc += ph[q] * rv[q];
   }
   const double sum = block_sum(acc);
   if (threadIdx.x == 0) crhs[blockIdx.x] = sum;
@@ -248,13 +451,53 @@ void launch_coarse_solve(const ddeig_problem* P, const PcgState* st, hipStream_t
                      dim3(kBlock), 0, s, P->nsub, st, P->A0inv, P->crhs, P->cy);
 }
 
+// The coarse correction R_0^T y0 at a node is psi_ext(node) times
+// sum_c D_c(node) y0_c over the covering cells c, and both the covering cells
+// and the weights depend only on the node's expanding indices.  This kernel
+// forms that sum once per expanding-index point (i0, or (i0, i1) for two
+// expanding axes), cells in slot order, so the extension reads one value.
+template <int PX>
+__global__ void k_coarse_field(Geo g, int delta, int pu, const PcgState* __restrict__ st,
+                               const XCover* __restrict__ xc0, const XCover* __restrict__ xc1,
+                               const double* __restrict__ y0, double* __restrict__ cf) {
+  if (st != nullptr && st->done) return;
+  const XCover* xc[2] = {xc0, xc1};
+  const long npts = PX == 1 ? (long)g.N[0] : (long)g.N[0] * g.N[1];
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < npts;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int i[3] = {(int)(idx % g.N[0]), PX == 2 ? (int)(idx / g.N[0]) : 0, 0};
+    const Cover<PX> cv(g, delta, i);
+    double zc = 0.0;
+#pragma unroll
+    for (int q = 0; q < Cover<PX>::NC; ++q) {
+      if (!cv.val(q)) continue;
+      const int c[3] = {cv.c0(q), PX == 2 ? cv.c1(q) : 0, 0};
+      const int which[2] = {q & 1, q >> 1};
+      zc += cover_weight(g, delta, pu, xc, c, i, which) * y0[(c[0] - 1) + g.L * (cv.c1(q) - 1)];
+    }
+    cf[idx] = zc;
+  }
+}
+
+void launch_coarse_field(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
+  const long npts = P->g.p == 1 ? (long)P->g.N[0] : (long)P->g.N[0] * P->g.N[1];
+  const int blocks = (int)std::min<long>((npts + kBlock - 1) / kBlock, 4096);
+  if (P->g.p == 1)
+    hipLaunchKernelGGL(k_coarse_field<1>, dim3(blocks), dim3(kBlock), 0, s, P->g, P->delta,
+                       P->opt.pu, st, P->dXC[0], P->dXC[1], P->cy, P->cfield);
+  else
+    hipLaunchKernelGGL(k_coarse_field<2>, dim3(blocks), dim3(kBlock), 0, s, P->g, P->delta,
+                       P->opt.pu, st, P->dXC[0], P->dXC[1], P->cy, P->cfield);
+}
+
 // z = sum_c R_c^T y_c (+ R_0^T y0), partials of r.z.  Work items are row
-// segments of kBlock x1 positions (as in the restriction); the covering cells
-// of a node come from the per-axis tables and are summed in a fixed order.
+// segments of kBlock x1 positions, four per workgroup of kBig threads (as in
+// the restriction); the covering cells of a node come from the per-axis
+// tables and are summed in a fixed order.
 // With chk.on the kernel first applies the stopping test of PCG iteration k,
 // ||r_k|| <= rtol ||r_0|| (§4.1), records the history and, once CG stops,
 // does nothing else (every later kernel of the iteration sees `done`).
-__global__ void __launch_bounds__(kBlock) k_extend(Geo g, int delta, int pu, int coarse,
+__global__ void __launch_bounds__(kBig) k_extend(Geo g, int delta, int pu, int coarse,
                                                    int ntypes, PcgState* __restrict__ st,
                                                    CheckArgs chk,
                                                    const TypeDev* __restrict__ types,
@@ -269,7 +512,7 @@ __global__ void __launch_bounds__(kBlock) k_extend(Geo g, int delta, int pu, int
   __shared__ TypeDev stypes[kMaxTypes];
   if (st != nullptr && st->done) return;
   if (chk.on) {
-    const double rn2 = sum_partials(chk.rr.part, chk.rr.np);
+    const double rn2 = sum_partials<kBig>(chk.rr.part, chk.rr.np);
     const bool conv = rn2 <= st->tol2, last = chk.k >= chk.maxit;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       st->relres = sqrt(rn2 / st->r0n2);
@@ -287,9 +530,12 @@ __global__ void __launch_bounds__(kBlock) k_extend(Geo g, int delta, int pu, int
   const int N0 = g.N[0], N1 = g.N[1];
   const int segs = (N0 + kBlock - 1) / kBlock;
   const long items = (long)segs * N1 * g.N[2];
-  for (long it = blockIdx.x; it < items; it += gridDim.x) {
+  const int sub = threadIdx.x / kBlock, tx = threadIdx.x % kBlock;
+  for (long grp = blockIdx.x; grp * (kBig / kBlock) < items; grp += gridDim.x) {
+    const long it = grp * (kBig / kBlock) + sub;
+    if (it >= items) continue;
     const int line = (int)(it / segs);
-    const int i0 = (int)(it - (long)line * segs) * kBlock + threadIdx.x;
+    const int i0 = (int)(it - (long)line * segs) * kBlock + tx;
     if (i0 >= N0) continue;
     const int i2 = g.D == 3 ? (int)fdiv((unsigned)line, g.fN1) : 0;
     const int i[3] = {i0, line - i2 * N1, i2};
@@ -329,17 +575,27 @@ __global__ void __launch_bounds__(kBlock) k_extend(Geo g, int delta, int pu, int
     z[k] = zv;
     acc += r[k] * zv;
   }
-  if (use_dot) write_partial(acc, dot.part);
+  if (use_dot) write_partial<kBig>(acc, dot.part);
 }
 
 void launch_extend(const ddeig_problem* P, const double* r, double* z, int coarse, Red* dot,
                    PcgState* st, const CheckArgs& chk, hipStream_t s) {
-  const long segs = (P->g.N[0] + kBlock - 1) / kBlock;
-  const long items = segs * P->g.N[1] * P->g.N[2];
-  const int blocks = (int)std::min<long>(items, kMaxRed);
+  const int blocks = node_grid(P->g);
   const Red none{nullptr, 0, nullptr};
   if (dot) dot->np = blocks;
-  hipLaunchKernelGGL(k_extend, dim3(blocks), dim3(kBlock), 0, s, P->g, P->delta, P->opt.pu,
+  if (P->opt.local_prec >= 2) {
+    // the K split is 1..3 by construction (assemble)
+    auto kern = k_extend_dense<1, 1>;
+    const int ks = P->ksplit;
+    if (P->g.p == 1)
+      kern = ks == 1 ? k_extend_dense<1, 1> : (ks == 2 ? k_extend_dense<1, 2> : k_extend_dense<1, 3>);
+    else
+      kern = ks == 1 ? k_extend_dense<2, 1> : (ks == 2 ? k_extend_dense<2, 2> : k_extend_dense<2, 3>);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBig), 0, s, P->g, P->delta, coarse, st, chk,
+                       dense_args(P), P->psi, P->cfield, r, z, dot ? 1 : 0, dot ? *dot : none);
+    return;
+  }
+  hipLaunchKernelGGL(k_extend, dim3(blocks), dim3(kBig), 0, s, P->g, P->delta, P->opt.pu,
                      coarse, (int)P->types.size(), st, chk, P->dTypes, P->dSubTS, P->dXC[0],
                      P->dXC[1],
                      P->psi, P->cy, r, z,

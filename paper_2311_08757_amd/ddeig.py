@@ -295,7 +295,8 @@ def profile_kernel(prob, which, reps=20, x=None, y=None):
     work = ctypes.c_double()
     xp = _ptr(x, prob.n_dof, "x") if x is not None else None
     yp = _ptr(y, prob.n_dof, "y") if y is not None else None
-    w = {"stencil": 0, "local": 1, "precond": 2}[which] if isinstance(which, str) else int(which)
+    names = {"stencil": 0, "local": 1, "precond": 2, "restrict": 3, "extend": 4, "correct": 5}
+    w = names[which] if isinstance(which, str) else int(which)
     _check(lib.ddeig_profile_kernel(prob.handle, w, int(reps), xp, yp, ctypes.byref(avg),
                                     ctypes.byref(work)), "ddeig_profile_kernel")
     return avg.value, work.value
