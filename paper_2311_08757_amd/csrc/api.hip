@@ -711,6 +711,8 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
     P->u = dalloc<double>(P, n);
     P->w = dalloc<double>(P, n);
     P->red_part = dalloc<double>(P, (size_t)kRedSlots * kMaxRed);
+    P->big_cap = ddeig::stencil_tiles(g);
+    if (P->big_cap > kMaxRed) P->big_part = dalloc<double>(P, 2 * (size_t)P->big_cap);
     P->red_val = dalloc<double>(P, kRedSlots);
     P->st = dalloc<ddeig::PcgState>(P, 1);
     P->hist_cap = 10001;

@@ -261,6 +261,8 @@ struct ddeig_problem {
   double *r = nullptr, *z = nullptr, *q = nullptr, *u = nullptr, *w = nullptr;
   double* pp[2] = {nullptr, nullptr};  // CG directions of even / odd iterations
   double* red_part = nullptr;   // kRedSlots x kMaxRed partial sums
+  double* big_part = nullptr;   // 2 x big_cap partials of kernels with more than kMaxRed workgroups
+  long big_cap = 0;
   double* red_val = nullptr;    // kRedSlots results
   ddeig::PcgState* st = nullptr;
   double* hist = nullptr;   // device residual history
@@ -277,6 +279,7 @@ namespace ddeig {
 
 // ---- kernels' host launchers (k_*.hip) ------------------------------------
 void launch_build_tables(const ddeig_problem* P, hipStream_t s);
+long stencil_tiles(const Geo& g);
 void launch_shift_table(const ddeig_problem* P, hipStream_t s);
 // y = T x (T one of the tables); dot / sum != nullptr: partial sums of x.y / of y
 void launch_stencil(const ddeig_problem* P, const double* tab, const double* x, double* y,

@@ -200,7 +200,10 @@ __global__ void __launch_bounds__(kBlock) k_stencil(Geo g, const double* __restr
       sv[e] = v;
     }
     __syncthreads();
-    for (int row = w; row < TY * TZ; row += kBlock / 64) {
+    // rows w, w + 4, ... of the tile (a static loop, so cpre stays in registers)
+#pragma unroll
+    for (int jr = 0; jr < TY * TZ / (kBlock / 64); ++jr) {
+      const int row = w + (kBlock / 64) * jr;
       const int ty = row % TY, tz = row / TY;
       const int gy = y0 + ty, gz = z0 + tz;
       if (gy >= N1 || (D == 3 && gz >= N2)) continue;
@@ -240,46 +243,177 @@ __global__ void __launch_bounds__(kBlock) k_stencil(Geo g, const double* __restr
   if (use_sum) write_partial(accs, sum.part);
 }
 
-int stencil_grid(const Geo& g) {
-  long nt;
+// The 2-D sweep when n_e divides 64 (every lane keeps one cell-local x
+// position across its 64-node strides): one 256 x 8 tile per workgroup, the
+// 2 x 9 table coefficients of the thread's rows loaded before the staging so
+// that both latency rounds overlap, and 32-bit tile-local index arithmetic
+// (fewer registers, more resident waves).  Same arithmetic and tap order as
+// k_stencil<2, MODE>.
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_stencil2d(Geo g, const double* __restrict__ T,
+                                                      const double* __restrict__ x,
+                                                      const double* __restrict__ pold,
+                                                      double* __restrict__ pnew,
+                                                      double* __restrict__ y, DirArgs dir,
+                                                      int use_dot, Red dot, int use_sum, Red sum) {
+  constexpr int TX = 256, TY = 8, HX = TX + 2, HY = TY + 2, RX = TX / 64, RY = TY / 4;
+  __shared__ double sv[HX * HY];
+  double beta = 0.0;
+  if constexpr (MODE == 1) {
+    const double rho = sum_partials(dir.rz.part, dir.rz.np);
+    if (dir.st->done) return;
+    if (!(rho > 0.0)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        dir.st->done = 3;
+        dir.st->iters = dir.k - 1;
+      }
+      return;
+    }
+    if (dir.k > 1) beta = rho / dir.st->rho[(dir.k - 2) & 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) dir.st->rho[(dir.k - 1) & 1] = rho;
+  }
+  const int N0 = g.N[0], N1 = g.N[1];
+  const int nbx = (N0 + TX - 1) / TX;
+  const int bx = blockIdx.x % nbx, by = blockIdx.x / nbx;
+  const int x0 = bx * TX, y0 = by * TY;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // cell-local x position of the lane (the same for all its strides)
+  const int j0 = (int)((unsigned)(x0 + lane + 1) - g.ne * fdiv((unsigned)(x0 + lane + 1), g.fne));
+  const long tsize = g.tsize;
+  double c[RY][9];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) {
+    const int gy = min(y0 + w + 4 * j, N1 - 1);
+    const double* tp = T + j0 + g.P[0] * gy;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) c[j][t] = tp[t * tsize];
+  }
+  const double* xb = x + (long)N0 * y0 + x0;
+  for (int e = threadIdx.x; e < HX * HY; e += kBlock) {
+    const int ex = e % HX, ey = e / HX;
+    const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+    double v = 0.0;
+    if (gx >= 0 && gx < N0 && gy >= 0 && gy < N1) {
+      const long off = (long)N0 * (ey - 1) + (ex - 1);
+      v = xb[off];
+      if constexpr (MODE == 1) {
+        if (dir.k > 1) v += beta * pold[(long)N0 * y0 + x0 + off];
+        if (ex >= 1 && ex <= TX && ey >= 1 && ey <= TY) pnew[(long)N0 * y0 + x0 + off] = v;
+      }
+    }
+    sv[e] = v;
+  }
+  __syncthreads();
+  double acc = 0.0, accs = 0.0;
+#pragma unroll
+  for (int j = 0; j < RY; ++j) {
+    const int ty = w + 4 * j, gy = y0 + ty;
+    if (gy >= N1) continue;
+#pragma unroll
+    for (int s = 0; s < RX; ++s) {
+      const int gx = x0 + lane + 64 * s;
+      if (gx >= N0) continue;
+      const int cx = lane + 64 * s + 1;
+      double a = 0.0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) a += c[j][t] * sv[(cx + t % 3 - 1) + HX * (ty + t / 3)];
+      y[gx + (long)N0 * gy] = a;
+      acc += sv[cx + HX * (ty + 1)] * a;
+      accs += a;
+    }
+  }
+  if (use_dot) write_partial(acc, dot.part);
+  if (use_sum) write_partial(accs, sum.part);
+}
+
+long stencil_tiles(const Geo& g) {
   if (g.D == 2)
-    nt = (long)((g.N[0] + TileShape<2>::TX - 1) / TileShape<2>::TX) *
-         ((g.N[1] + TileShape<2>::TY - 1) / TileShape<2>::TY);
-  else
-    nt = (long)((g.N[0] + TileShape<3>::TX - 1) / TileShape<3>::TX) *
+    return (long)((g.N[0] + TileShape<2>::TX - 1) / TileShape<2>::TX) *
+           ((g.N[1] + TileShape<2>::TY - 1) / TileShape<2>::TY);
+  return (long)((g.N[0] + TileShape<3>::TX - 1) / TileShape<3>::TX) *
          ((g.N[1] + TileShape<3>::TY - 1) / TileShape<3>::TY) *
          ((g.N[2] + TileShape<3>::TZ - 1) / TileShape<3>::TZ);
-  return (int)std::max<long>(1, std::min<long>(nt, kMaxRed));
+}
+
+// Sum of np block partials into out[0], in block order, by one workgroup.
+__global__ void __launch_bounds__(kBig) k_reduce_partials(const double* __restrict__ part, long np,
+                                                          double* __restrict__ out) {
+  double v = 0.0;
+  for (long i = threadIdx.x; i < np; i += kBig) v += part[i];
+  v = block_sum_n<kBig>(v);
+  if (threadIdx.x == 0) out[0] = v;
+}
+
+// One tile per workgroup.  Up to kMaxRed tiles the block partials go straight
+// to the consumer's buffer; beyond that they go to a large per-problem buffer
+// and one workgroup adds them into a single partial (np = 1).
+struct TileRed {
+  Red use;    // what the kernel writes
+  Red final;  // what the consumers read
+};
+
+static TileRed tile_red(const ddeig_problem* P, const Red& r, long tiles, int which) {
+  TileRed t{r, r};
+  if (tiles <= kMaxRed) {
+    t.use.np = t.final.np = (int)tiles;
+  } else {
+    t.use.part = P->big_part + (long)which * P->big_cap;
+    t.use.np = (int)tiles;
+    t.final.np = 1;
+  }
+  return t;
+}
+
+static void finish_tile_red(const ddeig_problem* P, const TileRed& t, hipStream_t s) {
+  if (t.use.part != t.final.part)
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBig), 0, s, t.use.part,
+                       (long)t.use.np, t.final.part);
 }
 
 void launch_stencil(const ddeig_problem* P, const double* tab, const double* x, double* y,
                     Red* dot, Red* sum, hipStream_t s) {
-  const int blocks = stencil_grid(P->g);
+  const long tiles = stencil_tiles(P->g);
   const Red none{nullptr, 0, nullptr};
   const DirArgs nodir{nullptr, 0, none};
-  if (dot) dot->np = blocks;
-  if (sum) sum->np = blocks;
-  if (P->g.D == 2)
+  const TileRed td = tile_red(P, dot ? *dot : none, tiles, 0);
+  const TileRed ts = tile_red(P, sum ? *sum : none, tiles, 1);
+  const int blocks = (int)std::max<long>(1, tiles);
+  if (P->g.D == 2 && 64 % P->g.ne == 0)
+    hipLaunchKernelGGL(k_stencil2d<0>, dim3(blocks), dim3(kBlock), 0, s, P->g, tab, x, nullptr,
+                       nullptr, y, nodir, dot ? 1 : 0, td.use, sum ? 1 : 0, ts.use);
+  else if (P->g.D == 2)
     hipLaunchKernelGGL((k_stencil<2, 0>), dim3(blocks), dim3(kBlock), 0, s, P->g, tab, x,
-                       nullptr, nullptr, y, nodir, dot ? 1 : 0, dot ? *dot : none, sum ? 1 : 0,
-                       sum ? *sum : none);
+                       nullptr, nullptr, y, nodir, dot ? 1 : 0, td.use, sum ? 1 : 0, ts.use);
   else
     hipLaunchKernelGGL((k_stencil<3, 0>), dim3(blocks), dim3(kBlock), 0, s, P->g, tab, x,
-                       nullptr, nullptr, y, nodir, dot ? 1 : 0, dot ? *dot : none, sum ? 1 : 0,
-                       sum ? *sum : none);
+                       nullptr, nullptr, y, nodir, dot ? 1 : 0, td.use, sum ? 1 : 0, ts.use);
+  if (dot) {
+    finish_tile_red(P, td, s);
+    *dot = td.final;
+  }
+  if (sum) {
+    finish_tile_red(P, ts, s);
+    *sum = ts.final;
+  }
 }
 
 void launch_stencil_dir(const ddeig_problem* P, const double* z, const double* pold, double* pnew,
                         double* q, const DirArgs& dir, Red& gam, hipStream_t s) {
-  const int blocks = stencil_grid(P->g);
+  const long tiles = stencil_tiles(P->g);
   const Red none{nullptr, 0, nullptr};
-  gam.np = blocks;
-  if (P->g.D == 2)
+  const TileRed tg = tile_red(P, gam, tiles, 0);
+  const int blocks = (int)std::max<long>(1, tiles);
+  if (P->g.D == 2 && 64 % P->g.ne == 0)
+    hipLaunchKernelGGL(k_stencil2d<1>, dim3(blocks), dim3(kBlock), 0, s, P->g, P->tabAs, z, pold,
+                       pnew, q, dir, 1, tg.use, 0, none);
+  else if (P->g.D == 2)
     hipLaunchKernelGGL((k_stencil<2, 1>), dim3(blocks), dim3(kBlock), 0, s, P->g, P->tabAs, z,
-                       pold, pnew, q, dir, 1, gam, 0, none);
+                       pold, pnew, q, dir, 1, tg.use, 0, none);
   else
     hipLaunchKernelGGL((k_stencil<3, 1>), dim3(blocks), dim3(kBlock), 0, s, P->g, P->tabAs, z,
-                       pold, pnew, q, dir, 1, gam, 0, none);
+                       pold, pnew, q, dir, 1, tg.use, 0, none);
+  finish_tile_red(P, tg, s);
+  gam = tg.final;
 }
 
 // Box operator with periodic wrap in the flagged dims (the cell problem of
