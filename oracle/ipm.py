@@ -26,21 +26,38 @@ from .pcg import pcg
 class DirectSolver:
     """Exact solves with A_sigma (SPD)."""
 
-    def __init__(self, A_sigma, grid=None):
+    def __init__(self, A_sigma, grid=None, band_bytes=24e9):
         A = sp.csr_matrix(A_sigma)
         self.n = A.shape[0]
         self.kind = "splu"
+        perm = bw = None
         if grid is not None and grid.d == 2:
-            # reorder with y fastest: half-bandwidth = number of y unknowns
+            # reorder with y fastest: half-bandwidth = number of y unknowns + 1
             nx, ny = grid.ndof_dir
             perm = np.arange(self.n).reshape(ny, nx).T.ravel()
-            Ap = A[perm][:, perm].tocsr()
             bw = ny + 1
+        elif grid is not None and grid.d == 3:
+            # banded Cholesky with the longest direction slowest, when its band fits:
+            # half-bandwidth = n_fast (n_mid + 1) + 1
+            dims = list(grid.ndof_dir)
+            order = sorted(range(3), key=lambda a: dims[a])       # fastest first
+            nf, nm = dims[order[0]], dims[order[1]]
+            b3 = nf * (nm + 1) + 1
+            if self.n * (b3 + 1) * 8 <= band_bytes:
+                idx = np.arange(self.n).reshape(dims[2], dims[1], dims[0])  # [a2][a1][a0]
+                axes = [2 - order[2], 2 - order[1], 2 - order[0]]       # slowest .. fastest
+                perm = idx.transpose(axes).ravel()
+                bw = b3
+        if perm is not None:
+            Ap = A[perm][:, perm].tocsr()
             ab = np.zeros((bw + 1, self.n))
             coo = Ap.tocoo()
-            keep = (coo.row >= coo.col) & (coo.row - coo.col <= bw)
+            keep = coo.row >= coo.col
+            if np.any(coo.row[keep] - coo.col[keep] > bw):
+                raise AssertionError("band estimate too small")
             ab[coo.row[keep] - coo.col[keep], coo.col[keep]] = coo.data[keep]
-            self.cb = sla.cholesky_banded(ab, lower=True)
+            del coo, Ap
+            self.cb = sla.cholesky_banded(ab, lower=True, overwrite_ab=True)
             self.perm = perm
             self.kind = "banded"
         else:
