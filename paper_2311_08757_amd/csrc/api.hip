@@ -598,13 +598,29 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
           gemv.push_back(ddeig::GemvRows{0, r0, std::min(H.m, r0 + kBlock / 64), nsub});
       }
     }
+    // FP64 / FP32 local solves of 3-D boxes: chain solves batched over the
+    // members of a class (one launch per sweep step), when the two LDS slices
+    // of a workgroup fit
+    int maxb_types = 0;
+    for (auto& T : P->types) maxb_types = std::max(maxb_types, T.box.b);
+    const bool batched_chain = !dense && g.D == 3 &&
+                               ddeig::chain_lds_bytes(maxb_types, o.local_prec == 1) <= 160 * 1024;
+    std::vector<ddeig::ChainJob> chainjobs;
     for (size_t t = 0; t < P->types.size(); ++t) {
       auto& T = P->types[t];
       maxb = std::max(maxb, T.box.b);
       const long mm = (long)T.box.nch * T.box.b;
+      if (batched_chain) {
+        const int nm = o.local_prec == 1 ? 16 : 8;
+        for (int m0 = 0; m0 < T.nmem; m0 += nm)
+          for (int r0 = 0; r0 < T.box.b; r0 += 64)
+            chainjobs.push_back(ddeig::ChainJob{(int)t, m0, std::min(nm, T.nmem - m0), r0});
+      }
       for (int a = 0; a < 3; ++a) tdev[t].m[a] = T.box.m[a];
       tdev[t].b = T.box.b;
       tdev[t].nch = T.box.nch;
+      for (int a = 0; a < 3; ++a) tdev[t].o[a] = T.box.o[a];
+      tdev[t].tbatch = nullptr;
       tdev[t].dense = dense ? 1 : 0;
       if (dense) {
         const ddeig::DenseHost& H = P->dh;
@@ -629,6 +645,7 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
           tdev[t].hm[a] = T.box.m[a];
           tdev[t].off[a] = 0;
         }
+        if (batched_chain) tdev[t].tbatch = dalloc<double>(P, (size_t)T.nmem * mm);
         tdev[t].W = T.W;
         tdev[t].W32 = T.W32;
         tdev[t].ld = 0;
@@ -643,6 +660,16 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
       tdev[t].fm0 = ddeig::make_fastdiv((unsigned)T.box.m[0]);
     }
     if (P->types.size() > (size_t)ddeig::kMaxTypes) throw Failure{DDEIG_EINTERNAL, "too many classes"};
+    if (batched_chain) {
+      P->chain_lds = ddeig::chain_lds_bytes(maxb_types, o.local_prec == 1);
+      ddeig::chain_kernel_setup(o.local_prec == 1, P->chain_lds);
+      P->nchainjobs = (int)chainjobs.size();
+      P->dChainJobs = dalloc<ddeig::ChainJob>(P, chainjobs.size());
+      check_hip(hipMemcpyAsync(P->dChainJobs, chainjobs.data(),
+                               sizeof(ddeig::ChainJob) * chainjobs.size(), hipMemcpyHostToDevice, s),
+                "copy chain jobs");
+      sync(P);  // chainjobs is released at the end of this scope
+    }
     {
       std::vector<ddeig::SubTS> ts(nsub);
       for (int sid = 0; sid < nsub; ++sid) {

@@ -153,11 +153,13 @@ struct SubDev {
 
 struct TypeDev {
   int m[3];
+  int o[3];           // box origin of the first member (table positions of the class)
   int hm[3], off[3];  // dense batch rows: e = sum_a (u_a + off_a) prod_{b<a} hm_b
   int b, nch;
   const double* W;
   const float* W32;
   double* batch;
+  double* tbatch;     // forward-sweep results of the batched chain solves
   // dense local solves (local_prec >= 2): rows of the dense batch (bf16
   // residual, lo part for local_prec = 2) and split-K partial results
   // Z[split][row][e]
@@ -188,6 +190,11 @@ struct GemmType {
   float* Z;
   long zsplit;
   int ld;
+};
+
+// Batched chain solves: one workgroup per (class, member tile, 64 rows of a slice).
+struct ChainJob {
+  int type, m0, nm, r0;
 };
 
 struct GemmTile {
@@ -249,6 +256,10 @@ struct ddeig_problem {
   ddeig::EmbedJob* dEmbJobs = nullptr;
   int nembjobs = 0, maxT = 0;
   int ntiles = 0, ngemv = 0, ksplit = 1;
+  // batched chain solves (3-D FP64 / FP32 local solves)
+  ddeig::ChainJob* dChainJobs = nullptr;
+  int nchainjobs = 0, chain_nm = 0;
+  size_t chain_lds = 0;
   ddeig::GemmTile* dTiles = nullptr;
   ddeig::GemvRows* dGemv = nullptr;
   ddeig::GemmType* dGtypes = nullptr;
@@ -324,6 +335,8 @@ struct CheckArgs {
 void launch_restrict(const ddeig_problem* P, double* r, PcgState* st, const XrArgs& xr, Red* rr,
                      hipStream_t s);
 void launch_local_solves(const ddeig_problem* P, const PcgState* st, hipStream_t s);
+size_t chain_lds_bytes(int maxb, int fp32);
+void chain_kernel_setup(int fp32, size_t lds);
 void launch_coarse_solve(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 void launch_coarse_field(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 void launch_coarse_rhs(const ddeig_problem* P, const double* r, const PcgState* st, hipStream_t s);

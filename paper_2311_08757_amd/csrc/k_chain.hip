@@ -263,6 +263,184 @@ __global__ void __launch_bounds__(kBlock) k_local_solves(Geo g, const double* __
   chain_solve_block<WT>(g, bx, T, W, td.batch + (long)sd.slot * td.nch * td.b, sh);
 }
 
+// ---- batched chain solves
+//
+// All members of a class share the factors W_i, so a sweep step is the same
+// for every member: forward t_i = W_i (b_i - E_i t_{i-1}), backward
+// x_i = t_i - W_i E_{i+1}^T x_{i+1}.  One launch per step covers all classes;
+// a workgroup takes NM members of one class and 64 rows of slice i:
+//   1. the members' neighbouring slice (t_{i-1} or x_{i+1}) is staged in LDS,
+//   2. the slice's right-hand side g (coupling taps from the table) is formed
+//      in LDS for all b rows,
+//   3. rows [r0, r0 + 64) of W_i g, lanes over rows (W_i symmetric: its
+//      columns are read, which coalesces), waves over quarters of the K range.
+// W_i is read once per step for NM members instead of once per member.  The
+// forward sweep writes t to a second batch (other workgroups of the step still
+// read b_i), the backward sweep writes x into the batch.  Arithmetic in WT
+// (FP64, or FP32 for local_prec 1).  3-D boxes only (chain along the last
+// dim, slices of the first two).
+
+template <typename WT, int NM, bool FWD>
+__global__ void __launch_bounds__(kBlock) k_chain_step(Geo g, const double* __restrict__ T,
+                                                       const TypeDev* __restrict__ types,
+                                                       const ChainJob* __restrict__ jobs, int i,
+                                                       const PcgState* __restrict__ st) {
+  extern __shared__ unsigned char smem_raw[];
+  if (st != nullptr && st->done) return;
+  const ChainJob jb = jobs[blockIdx.x];
+  const TypeDev td = types[jb.type];
+  const int b = td.b, nch = td.nch;
+  WT* sp = reinterpret_cast<WT*>(smem_raw);  // [b][NM] neighbouring slice
+  WT* sg = sp + (long)b * NM;                // [b][NM] right-hand side of slice i
+  Box bx;
+  for (int a = 0; a < 3; ++a) {
+    bx.o[a] = td.o[a];
+    bx.m[a] = td.m[a];
+    bx.per[a] = 0;
+  }
+  bx.b = b;
+  bx.nch = nch;
+  const long mstride = (long)nch * b;  // one member's batch
+  if (!FWD && i == nch - 1) {
+    // x_{n-1} = t_{n-1}: rows of this workgroup
+    const int r = jb.r0 + (threadIdx.x & 63);
+    for (int m = threadIdx.x >> 6; m < jb.nm; m += kBlock / 64)
+      if (r < b) {
+        const long at = (long)(jb.m0 + m) * mstride + (long)i * b + r;
+        td.batch[at] = td.tbatch[at];
+      }
+    return;
+  }
+  const bool couple = FWD ? i > 0 : true;
+  const int j = FWD ? i - 1 : i + 1;
+  const double* nb = FWD ? td.tbatch : td.batch;
+  if (couple) {
+    for (int idx = threadIdx.x; idx < NM * b; idx += kBlock) {
+      const int m = idx / b, r = idx - m * b;
+      sp[r * NM + m] = m < jb.nm ? (WT)nb[(long)(jb.m0 + m) * mstride + (long)j * b + r] : (WT)0;
+    }
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < b; r += kBlock) {
+    WT acc[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m)
+      acc[m] = (FWD && m < jb.nm) ? (WT)td.batch[(long)(jb.m0 + m) * mstride + (long)i * b + r]
+                                  : (WT)0;
+    if (couple) {
+      // 3-D box, slices (u0, u1) with the chain along u2 = i: the 9 taps
+      // with d2 = -1 (forward) or +1 (backward), in tap order
+      const int m0 = bx.m[0], m1 = bx.m[1];
+      const int u1 = r / m0, u0 = r - u1 * m0;
+      const long tn = table_node(g, bx.o[0] + u0, bx.o[1] + u1, bx.o[2] + i);
+      const int d2 = FWD ? -1 : 1;
+#pragma unroll
+      for (int d1 = -1; d1 <= 1; ++d1)
+#pragma unroll
+        for (int d0 = -1; d0 <= 1; ++d0) {
+          const int w0 = u0 + d0, w1 = u1 + d1;
+          if (w0 < 0 || w0 >= m0 || w1 < 0 || w1 >= m1) continue;
+          const int t = (d0 + 1) + 3 * (d1 + 1) + 9 * (d2 + 1);
+          const WT c = (WT)T[t * g.tsize + tn];
+          const int rn = w0 + m0 * w1;
+#pragma unroll
+          for (int m = 0; m < NM; ++m) acc[m] += (FWD ? -c : c) * sp[rn * NM + m];
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < NM; ++m) sg[r * NM + m] = acc[m];
+  }
+  __syncthreads();
+  // rows [r0, r0 + 64) of W_i g: lane = row, the 4 waves split the K range
+  // and load their W_i entries kChainBatch at a time ahead of the FMAs; the
+  // wave sums are added in wave order through LDS (reusing the slice buffer)
+  constexpr int NW = kBlock / 64, KB = 32;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = jb.r0 + lane;
+  const WT* Wi = (sizeof(WT) == 4 ? reinterpret_cast<const WT*>(td.W32)
+                                  : reinterpret_cast<const WT*>(td.W)) + (long)i * b * b;
+  const int kq = (b + NW - 1) / NW, k0 = wv * kq, k1 = min(b, k0 + kq);
+  WT acc[NM];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) acc[m] = (WT)0;
+  if (r < b) {
+    for (int kc = k0; kc < k1; kc += KB) {
+      WT w[KB];
+#pragma unroll
+      for (int q = 0; q < KB; ++q) w[q] = kc + q < k1 ? Wi[(long)(kc + q) * b + r] : (WT)0;
+#pragma unroll
+      for (int q = 0; q < KB; ++q) {
+        if (kc + q >= k1) break;
+        const WT* gk = sg + (kc + q) * NM;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) acc[m] += w[q] * gk[m];
+      }
+    }
+  }
+  __syncthreads();  // every wave is done with sp / sg
+  WT* red = sp;     // [NW][64][NM]
+#pragma unroll
+  for (int m = 0; m < NM; ++m) red[(wv * 64 + lane) * NM + m] = acc[m];
+  __syncthreads();
+  if (r >= b) return;
+  for (int m = wv; m < jb.nm; m += NW) {
+    WT v = (WT)0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) v += red[(q * 64 + lane) * NM + m];
+    const long at = (long)(jb.m0 + m) * mstride + (long)i * b + r;
+    if (FWD) td.tbatch[at] = (double)v;
+    else td.batch[at] = td.tbatch[at] - (double)v;
+  }
+}
+
+// members per workgroup: the two LDS slices (2 b NM WT) must fit in 160 KB
+template <typename WT>
+constexpr int chain_nm() {
+  return sizeof(WT) == 4 ? 16 : 8;
+}
+
+// LDS of a workgroup: the two slices [b][NM], which the wave sums
+// [4][64][NM] reuse at the end, so at least 256 NM values
+size_t chain_lds_bytes(int maxb, int fp32) {
+  const size_t rows = std::max<size_t>(2 * (size_t)maxb, (size_t)kBlock);
+  return rows * (fp32 ? 16 * sizeof(float) : 8 * sizeof(double));
+}
+
+void chain_kernel_setup(int fp32, size_t lds) {
+  if (fp32) {
+    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_chain_step<float, 16, true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds), "lds");
+    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_chain_step<float, 16, false>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds), "lds");
+  } else {
+    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_chain_step<double, 8, true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds), "lds");
+    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_chain_step<double, 8, false>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds), "lds");
+  }
+}
+
+void launch_chain_batched(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
+  const int nch = P->types[0].box.nch;
+  const dim3 grid(P->nchainjobs), blk(kBlock);
+  for (int i = 0; i < nch; ++i) {
+    if (P->opt.local_prec == 1)
+      hipLaunchKernelGGL((k_chain_step<float, 16, true>), grid, blk, P->chain_lds, s, P->g,
+                         P->tabAs, P->dTypes, P->dChainJobs, i, st);
+    else
+      hipLaunchKernelGGL((k_chain_step<double, 8, true>), grid, blk, P->chain_lds, s, P->g,
+                         P->tabAs, P->dTypes, P->dChainJobs, i, st);
+  }
+  for (int i = nch - 1; i >= 0; --i) {
+    if (P->opt.local_prec == 1)
+      hipLaunchKernelGGL((k_chain_step<float, 16, false>), grid, blk, P->chain_lds, s, P->g,
+                         P->tabAs, P->dTypes, P->dChainJobs, i, st);
+    else
+      hipLaunchKernelGGL((k_chain_step<double, 8, false>), grid, blk, P->chain_lds, s, P->g,
+                         P->tabAs, P->dTypes, P->dChainJobs, i, st);
+  }
+}
+
 bool local_solves_fast_ok(const ddeig_problem* P);
 void launch_local_solves_fast(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 
@@ -276,6 +454,10 @@ void launch_local_solves(const ddeig_problem* P, const PcgState* st, hipStream_t
   }
   if (local_solves_fast_ok(P)) {
     launch_local_solves_fast(P, st, s);
+    return;
+  }
+  if (P->nchainjobs > 0) {
+    launch_chain_batched(P, st, s);
     return;
   }
   const size_t lds = 2 * (size_t)P->maxb * sizeof(double);
