@@ -186,6 +186,21 @@ ddeig_status ddeig_inverse_iteration(ddeig_problem* P, double* x, double tol_x, 
 ddeig_status ddeig_profile_kernel(ddeig_problem* P, int which, int reps, const double* x, double* y,
                                   double* avg_us, double* work);
 
+/* Potential-weighted bilinear form out = x^T M_W y, where M_W is the mass
+ * matrix weighted by the potential W, assembled with the same quadrature as
+ * M_V (§2, eq:discrete-weak-form: A = K + M_V is linear in V, so the
+ * derivative of A with respect to a parameter theta of V is M_{dV/dtheta}).
+ * space = 0: the global grid, x and y are n_dof device values in the
+ * canonical layout; space = 1: the periodic cell, n_cell values in cell
+ * order.  With W = dV/dtheta and x = y the M-normalised eigenvector of
+ * inverse_iteration this is dlambda/dtheta (Hellmann-Feynman); with the
+ * M#-normalised cell vector psi it is dsigma/dtheta; with an adjoint solution
+ * w and u = A_sigma^{-1} b it gives w^T (dA/dtheta) u for the gradient of the
+ * linear solve.  W uses the layout of ddeig_potential; it is copied during the
+ * call.  Needs only ddeig_assemble; synchronises the library stream. */
+ddeig_status ddeig_potential_form(ddeig_problem* P, int space, const ddeig_potential* W,
+                                  const double* x, const double* y, double* out);
+
 /* Sizes: interior unknowns, cell unknowns, number of subdomains (= coarse dimension). */
 ddeig_status ddeig_query(const ddeig_problem* P, long* n_dof, long* n_cell, int* n_sub);
 

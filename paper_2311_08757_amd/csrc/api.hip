@@ -263,6 +263,46 @@ PcgOut pcg_run(ddeig_problem* P, const double* b, double* x, double rtol, int ma
   return o;
 }
 
+// Validated device description of a potential (see ddeig_potential).
+ddeig_status make_vspec(const ddeig_potential* V, int p, int q, double ell, ddeig::VSpec& vs) {
+  if (V->nterms < 0 || V->nterms > DDEIG_MAX_TERMS)
+    return set_error(DDEIG_EINVAL, "nterms out of range");
+  if ((int)V->kind < 0 || (int)V->kind > 4) return set_error(DDEIG_EINVAL, "unknown potential kind");
+  if (V->kind == DDEIG_V_FOURIER2 && p != 2)
+    return set_error(DDEIG_EINVAL, "FOURIER2 potentials need p = 2");
+  vs.kind = (int)V->kind;
+  vs.nterms = V->nterms;
+  vs.p = p;
+  vs.q = q;
+  vs.cy = V->cy;
+  vs.c0 = V->c0;
+  vs.ell = ell;
+  const bool needs_terms = V->kind == DDEIG_V_SEP_FOURIER || V->kind == DDEIG_V_FOURIER2 ||
+                           V->kind == DDEIG_V_SEP_SUM;
+  if (needs_terms && V->nterms > 0) {
+    if (V->a == nullptr || V->k == nullptr) return set_error(DDEIG_EINVAL, "potential arrays are NULL");
+    if ((V->kind != DDEIG_V_SEP_SUM) && V->phi == nullptr)
+      return set_error(DDEIG_EINVAL, "potential phases are NULL");
+    if ((V->kind == DDEIG_V_FOURIER2 || V->kind == DDEIG_V_SEP_SUM) && V->m == nullptr)
+      return set_error(DDEIG_EINVAL, "potential m array is NULL");
+    for (int t = 0; t < V->nterms; ++t) {
+      vs.a[t] = V->a[t];
+      vs.phi[t] = V->phi ? V->phi[t] : 0.0;
+      vs.k[t] = V->k[t];
+      vs.m[t] = V->m ? V->m[t] : 0;
+      if (!std::isfinite(vs.a[t]) || !std::isfinite(vs.phi[t]))
+        return set_error(DDEIG_EINVAL, "non-finite potential coefficient");
+      if (V->kind == DDEIG_V_SEP_SUM && (vs.m[t] < 0 || vs.m[t] >= p + q))
+        return set_error(DDEIG_EINVAL, "SEP_SUM axis out of range");
+    }
+  }
+  if (V->kind == DDEIG_V_SEP_SUM && V->g != nullptr)
+    for (int j = 0; j < q; ++j) vs.g[j] = V->g[j];
+  if (!std::isfinite(vs.cy) || !std::isfinite(vs.c0)) return set_error(DDEIG_EINVAL, "non-finite cy/c0");
+
+  return DDEIG_OK;
+}
+
 ddeig_status validate_vec(const void* p, const char* name) {
   if (p == nullptr) return set_error(DDEIG_EINVAL, std::string(name) + " is NULL");
   return DDEIG_OK;
@@ -334,11 +374,6 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
     return set_error(DDEIG_EINVAL, "ell * n_e must be an integer >= 2");
   if (overlap < 1 || 2 * overlap > ne)
     return set_error(DDEIG_EINVAL, "overlap must satisfy 1 <= overlap and 2 overlap <= n_e");
-  if (V->nterms < 0 || V->nterms > DDEIG_MAX_TERMS)
-    return set_error(DDEIG_EINVAL, "nterms out of range");
-  if ((int)V->kind < 0 || (int)V->kind > 4) return set_error(DDEIG_EINVAL, "unknown potential kind");
-  if (V->kind == DDEIG_V_FOURIER2 && p != 2)
-    return set_error(DDEIG_EINVAL, "FOURIER2 potentials need p = 2");
   ddeig_options o{0, 1, 0, 8};
   if (opts) o = *opts;
   if (o.pu < 0 || o.pu > 1 || o.coarse < 0 || o.coarse > 1 || o.local_prec < 0 ||
@@ -346,35 +381,10 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
     return set_error(DDEIG_EINVAL, "invalid options");
 
   ddeig::VSpec vs{};
-  vs.kind = (int)V->kind;
-  vs.nterms = V->nterms;
-  vs.p = p;
-  vs.q = q;
-  vs.cy = V->cy;
-  vs.c0 = V->c0;
-  vs.ell = ell;
-  const bool needs_terms = V->kind == DDEIG_V_SEP_FOURIER || V->kind == DDEIG_V_FOURIER2 ||
-                           V->kind == DDEIG_V_SEP_SUM;
-  if (needs_terms && V->nterms > 0) {
-    if (V->a == nullptr || V->k == nullptr) return set_error(DDEIG_EINVAL, "potential arrays are NULL");
-    if ((V->kind != DDEIG_V_SEP_SUM) && V->phi == nullptr)
-      return set_error(DDEIG_EINVAL, "potential phases are NULL");
-    if ((V->kind == DDEIG_V_FOURIER2 || V->kind == DDEIG_V_SEP_SUM) && V->m == nullptr)
-      return set_error(DDEIG_EINVAL, "potential m array is NULL");
-    for (int t = 0; t < V->nterms; ++t) {
-      vs.a[t] = V->a[t];
-      vs.phi[t] = V->phi ? V->phi[t] : 0.0;
-      vs.k[t] = V->k[t];
-      vs.m[t] = V->m ? V->m[t] : 0;
-      if (!std::isfinite(vs.a[t]) || !std::isfinite(vs.phi[t]))
-        return set_error(DDEIG_EINVAL, "non-finite potential coefficient");
-      if (V->kind == DDEIG_V_SEP_SUM && (vs.m[t] < 0 || vs.m[t] >= p + q))
-        return set_error(DDEIG_EINVAL, "SEP_SUM axis out of range");
-    }
+  {
+    const ddeig_status sv = make_vspec(V, p, q, ell, vs);
+    if (sv != DDEIG_OK) return sv;
   }
-  if (V->kind == DDEIG_V_SEP_SUM && V->g != nullptr)
-    for (int j = 0; j < q; ++j) vs.g[j] = V->g[j];
-  if (!std::isfinite(vs.cy) || !std::isfinite(vs.c0)) return set_error(DDEIG_EINVAL, "non-finite cy/c0");
 
   ddeig::Geo g{};
   g.p = p; g.q = q; g.D = p + q; g.L = L; g.ne = ne;
@@ -416,6 +426,8 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
     P->tabA = dalloc<double>(P, tt);
     P->tabAs = dalloc<double>(P, tt);
     P->dVS = dalloc<ddeig::VSpec>(P, 1);
+    P->dWS = dalloc<ddeig::VSpec>(P, 1);
+    P->tabW = dalloc<double>(P, tt);
     check_hip(hipMemcpyAsync(P->dVS, &P->vs, sizeof(ddeig::VSpec), hipMemcpyHostToDevice, s), "copy V");
     launch_build_tables(P, s);
     check_launch("build tables");
@@ -736,6 +748,7 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
     P->pp[1] = dalloc<double>(P, n);
     P->q = dalloc<double>(P, n);
     P->u = dalloc<double>(P, n);
+    P->tmpv = dalloc<double>(P, std::max<long>(n, g.tsize));
     P->w = dalloc<double>(P, n);
     P->red_part = dalloc<double>(P, (size_t)kRedSlots * kMaxRed);
     P->big_cap = ddeig::stencil_tiles(g);
@@ -874,6 +887,37 @@ ddeig_status ddeig_profile_kernel(ddeig_problem* P, int which, int reps, const d
   check_launch("profile kernel");
   *avg_us = 1000.0 * ms / reps;
   if (work) *work = w;
+  return DDEIG_OK;
+  API_GUARD_END
+}
+
+ddeig_status ddeig_potential_form(ddeig_problem* P, int space, const ddeig_potential* W,
+                                  const double* x, const double* y, double* out) {
+  if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
+  if (!W || !out) return set_error(DDEIG_EINVAL, "potential or out is NULL");
+  if (space != 0 && space != 1) return set_error(DDEIG_EINVAL, "space must be 0 or 1");
+  if (validate_vec(x, "x") || validate_vec(y, "y")) return DDEIG_EINVAL;
+  ddeig::VSpec ws{};
+  {
+    const ddeig_status sv = make_vspec(W, P->g.p, P->g.q, P->g.ell, ws);
+    if (sv != DDEIG_OK) return sv;
+  }
+  API_GUARD_BEGIN
+  const hipStream_t s = P->stream;
+  check_hip(hipMemcpyAsync(P->dWS, &ws, sizeof(ddeig::VSpec), hipMemcpyHostToDevice, s), "copy W");
+  launch_build_wtable(P, P->dWS, P->tabW, s);
+  long len;
+  if (space == 0) {
+    launch_stencil(P, P->tabW, y, P->tmpv, nullptr, nullptr, s);
+    len = P->g.n;
+  } else {
+    launch_box_stencil(P, cell_box(P->g), P->tabW, y, P->tmpv, nullptr, nullptr, s);
+    len = P->g.tsize;
+  }
+  Red r = slot(P, 9);
+  launch_dot(x, P->tmpv, len, r, s);
+  check_launch("potential form");
+  *out = host_sum(P, r);
   return DDEIG_OK;
   API_GUARD_END
 }

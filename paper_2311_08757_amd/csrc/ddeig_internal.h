@@ -233,6 +233,9 @@ struct ddeig_problem {
   double* tabM = nullptr;
   double* tabA = nullptr;   // K + M_V
   double* tabAs = nullptr;  // A - sigma M
+  double* tabW = nullptr;   // M_W of a weight potential W (potential forms)
+  ddeig::VSpec* dWS = nullptr;
+  double* tmpv = nullptr;   // max(n_dof, n_cell) scratch vector of the potential forms
   ddeig::VSpec* dVS = nullptr;
   // shift
   int shifted = 0;
@@ -290,6 +293,7 @@ namespace ddeig {
 
 // ---- kernels' host launchers (k_*.hip) ------------------------------------
 void launch_build_tables(const ddeig_problem* P, hipStream_t s);
+void launch_build_wtable(const ddeig_problem* P, const VSpec* dws, double* tW, hipStream_t s);
 long stencil_tiles(const Geo& g);
 void launch_shift_table(const ddeig_problem* P, hipStream_t s);
 // y = T x (T one of the tables); dot / sum != nullptr: partial sums of x.y / of y

@@ -15,25 +15,78 @@ namespace ddeig {
 __device__ inline double k1(int d, double h) { return d == 0 ? 2.0 / h : -1.0 / h; }
 __device__ inline double m1(int d, double h) { return d == 0 ? 4.0 * h / 6.0 : h / 6.0; }
 
-// Table entries of one (table node, tap): K, M and M_V.  The loops visit the
-// elements shared by the node and its neighbour in increasing element index
-// and the quadrature points in a fixed order, and the shape-function product
-// is formed symmetrically, so a(j, j+d) and a(j+d, j) come out bit-identical.
+// Potential-weighted mass entry of one (table node, tap): the element
+// integrals of W N_j N_{j+d} over the elements shared by the node and its
+// neighbour, tensor 2-point Gauss-Legendre rule, W at cell-local x.  The
+// loops visit the elements in increasing index and the quadrature points in a
+// fixed order, and the shape-function product is formed symmetrically, so
+// the entries of (j, j+d) and (j+d, j) come out bit-identical.
+__device__ inline double weight_entry(const Geo& g, const VSpec& v, int t, long tn) {
+  const double xi_lo = 0.5 * (1.0 - 0.57735026918962576450914878050196);
+  const double xi_hi = 0.5 * (1.0 + 0.57735026918962576450914878050196);
+  int d[3];
+  tap_offsets(t, g.ntaps, d[0], d[1], d[2]);
+  int j[3];
+  j[0] = (int)(tn % g.P[0]);
+  j[1] = (int)((tn / g.P[0]) % g.P[1]);
+  j[2] = (int)(tn / ((long)g.P[0] * g.P[1]));
+  const double h = g.h;
+  // elements e_a in {gnode-1, gnode} (d=0), {gnode} (d=+1), {gnode-1} (d=-1)
+  int gnode[3], ecount[3], efirst[3];
+  for (int a = 0; a < 3; ++a) {
+    if (a >= g.D) {
+      gnode[a] = 0; ecount[a] = 1; efirst[a] = 0;
+      continue;
+    }
+    gnode[a] = g.isx[a] ? j[a] : j[a] + 1;
+    if (d[a] == 0) { efirst[a] = gnode[a] - 1; ecount[a] = 2; }
+    else if (d[a] == 1) { efirst[a] = gnode[a]; ecount[a] = 1; }
+    else { efirst[a] = gnode[a] - 1; ecount[a] = 1; }
+  }
+  double mv = 0.0;
+  for (int e2 = 0; e2 < ecount[2]; ++e2)
+    for (int e1 = 0; e1 < ecount[1]; ++e1)
+      for (int e0 = 0; e0 < ecount[0]; ++e0) {
+        const int ee[3] = {efirst[0] + e0, efirst[1] + e1, efirst[2] + e2};
+        double lo[3];
+        int lj[3], ln[3];
+        for (int a = 0; a < g.D; ++a) {
+          const int ea = ee[a];
+          lo[a] = g.isx[a] ? (double)(((ea % g.ne) + g.ne) % g.ne) * h : (double)ea * h;
+          lj[a] = gnode[a] - ea;
+          ln[a] = gnode[a] + d[a] - ea;
+        }
+        double sum = 0.0;
+        const int nq = 1 << g.D;
+        for (int qi = 0; qi < nq; ++qi) {
+          double z[3] = {0.0, 0.0, 0.0};
+          double shape = 1.0;
+          for (int a = 0; a < g.D; ++a) {
+            const double xi = ((qi >> a) & 1) ? xi_hi : xi_lo;
+            z[a] = lo[a] + h * xi;
+            const double Nj = lj[a] ? xi : 1.0 - xi;
+            const double Nn = ln[a] ? xi : 1.0 - xi;
+            shape *= Nj * Nn;
+          }
+          sum += eval_V(v, z) * shape;
+        }
+        double wvol = 1.0;
+        for (int a = 0; a < g.D; ++a) wvol *= 0.5 * h;
+        mv += wvol * sum;
+      }
+  return mv;
+}
+
+// Table entries of one (table node, tap): K, M and A = K + M_V.
 __global__ void k_build_tables(Geo g, const VSpec* __restrict__ vs, double* __restrict__ tK,
                                double* __restrict__ tM, double* __restrict__ tA) {
   const long total = g.tsize * g.ntaps;
-  const double xi_lo = 0.5 * (1.0 - 0.57735026918962576450914878050196);
-  const double xi_hi = 0.5 * (1.0 + 0.57735026918962576450914878050196);
   for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
        idx += (long)gridDim.x * blockDim.x) {
     const int t = (int)(idx / g.tsize);
     const long tn = idx % g.tsize;
     int d[3];
     tap_offsets(t, g.ntaps, d[0], d[1], d[2]);
-    int j[3];
-    j[0] = (int)(tn % g.P[0]);
-    j[1] = (int)((tn / g.P[0]) % g.P[1]);
-    j[2] = (int)(tn / ((long)g.P[0] * g.P[1]));
     const double h = g.h;
     // constant-coefficient parts
     double kk = 0.0, mm = 1.0;
@@ -43,53 +96,25 @@ __global__ void k_build_tables(Geo g, const VSpec* __restrict__ vs, double* __re
       for (int a = 0; a < g.D; ++a) term *= (a == dir) ? k1(d[a], h) : m1(d[a], h);
       kk += term;
     }
-    // potential part: elements e_a in {gnode-1, gnode} (d=0), {gnode} (d=+1), {gnode-1} (d=-1)
-    int gnode[3], ecount[3], efirst[3];
-    for (int a = 0; a < 3; ++a) {
-      if (a >= g.D) {
-        gnode[a] = 0; ecount[a] = 1; efirst[a] = 0;
-        continue;
-      }
-      gnode[a] = g.isx[a] ? j[a] : j[a] + 1;
-      if (d[a] == 0) { efirst[a] = gnode[a] - 1; ecount[a] = 2; }
-      else if (d[a] == 1) { efirst[a] = gnode[a]; ecount[a] = 1; }
-      else { efirst[a] = gnode[a] - 1; ecount[a] = 1; }
-    }
-    double mv = 0.0;
-    for (int e2 = 0; e2 < ecount[2]; ++e2)
-      for (int e1 = 0; e1 < ecount[1]; ++e1)
-        for (int e0 = 0; e0 < ecount[0]; ++e0) {
-          const int ee[3] = {efirst[0] + e0, efirst[1] + e1, efirst[2] + e2};
-          double lo[3];
-          int lj[3], ln[3];
-          for (int a = 0; a < g.D; ++a) {
-            const int ea = ee[a];
-            lo[a] = g.isx[a] ? (double)(((ea % g.ne) + g.ne) % g.ne) * h : (double)ea * h;
-            lj[a] = gnode[a] - ea;
-            ln[a] = gnode[a] + d[a] - ea;
-          }
-          double sum = 0.0;
-          const int nq = 1 << g.D;
-          for (int qi = 0; qi < nq; ++qi) {
-            double z[3] = {0.0, 0.0, 0.0};
-            double shape = 1.0;
-            for (int a = 0; a < g.D; ++a) {
-              const double xi = ((qi >> a) & 1) ? xi_hi : xi_lo;
-              z[a] = lo[a] + h * xi;
-              const double Nj = lj[a] ? xi : 1.0 - xi;
-              const double Nn = ln[a] ? xi : 1.0 - xi;
-              shape *= Nj * Nn;
-            }
-            sum += eval_V(*vs, z) * shape;
-          }
-          double wvol = 1.0;
-          for (int a = 0; a < g.D; ++a) wvol *= 0.5 * h;
-          mv += wvol * sum;
-        }
     tK[idx] = kk;
     tM[idx] = mm;
-    tA[idx] = kk + mv;
+    tA[idx] = kk + weight_entry(g, *vs, t, tn);
   }
+}
+
+// The table of the mass matrix weighted by W (M_W, the derivative of A with
+// respect to a parameter of V when W = dV/dtheta).
+__global__ void k_build_wtable(Geo g, const VSpec* __restrict__ ws, double* __restrict__ tW) {
+  const long total = g.tsize * g.ntaps;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x)
+    tW[idx] = weight_entry(g, *ws, (int)(idx / g.tsize), idx % g.tsize);
+}
+
+void launch_build_wtable(const ddeig_problem* P, const VSpec* dws, double* tW, hipStream_t s) {
+  const long total = P->g.tsize * P->g.ntaps;
+  const int blocks = (int)std::min<long>((total + kBlock - 1) / kBlock, 4096);
+  hipLaunchKernelGGL(k_build_wtable, dim3(blocks), dim3(kBlock), 0, s, P->g, dws, tW);
 }
 
 __global__ void k_shift_table(long total, const double* __restrict__ tA,

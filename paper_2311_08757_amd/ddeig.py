@@ -59,7 +59,7 @@ class EigInfo(ctypes.Structure):
 
 EXPORTS = ["ddeig_assemble", "ddeig_cell_shift", "ddeig_set_shift", "ddeig_apply_op",
            "ddeig_apply_precond", "ddeig_pcg_solve", "ddeig_inverse_iteration",
-           "ddeig_profile_kernel", "ddeig_query", "ddeig_destroy", "ddeig_status_string",
+           "ddeig_profile_kernel", "ddeig_potential_form", "ddeig_query", "ddeig_destroy", "ddeig_status_string",
            "ddeig_last_error"]
 
 _lib = None
@@ -87,6 +87,7 @@ def load_library(path=LIB_PATH):
     lib.ddeig_inverse_iteration.argtypes = [P, P, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                             ctypes.c_int, ctypes.POINTER(EigInfo)]
     lib.ddeig_profile_kernel.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, dp, dp]
+    lib.ddeig_potential_form.argtypes = [P, ctypes.c_int, ctypes.POINTER(Potential), P, P, dp]
     lib.ddeig_query.argtypes = [P, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long),
                                 ctypes.POINTER(ctypes.c_int)]
     lib.ddeig_destroy.argtypes = [P]
@@ -300,3 +301,21 @@ def profile_kernel(prob, which, reps=20, x=None, y=None):
     _check(lib.ddeig_profile_kernel(prob.handle, w, int(reps), xp, yp, ctypes.byref(avg),
                                     ctypes.byref(work)), "ddeig_profile_kernel")
     return avg.value, work.value
+
+
+def potential_form(prob, W, x, y, space="global"):
+    """ddeig_potential_form: x^T M_W y for a potential dict W.
+
+    space "global": x, y are n_dof CUDA float64 vectors; "cell": n_cell vectors
+    of the periodic cell (the layout of cell_shift's psi).
+    """
+    lib = load_library()
+    sp = {"global": 0, "cell": 1}[space] if isinstance(space, str) else int(space)
+    n = prob.n_cell if sp == 1 else prob.n_dof
+    Ws, keep = _potential(W)
+    out = ctypes.c_double()
+    st = lib.ddeig_potential_form(prob.handle, sp, ctypes.byref(Ws), _ptr(x, n, "x"),
+                                  _ptr(y, n, "y"), ctypes.byref(out))
+    del keep
+    _check(st, "ddeig_potential_form")
+    return out.value
