@@ -201,6 +201,55 @@ ddeig_status ddeig_profile_kernel(ddeig_problem* P, int which, int reps, const d
 ddeig_status ddeig_potential_form(ddeig_problem* P, int space, const ddeig_potential* W,
                                   const double* x, const double* y, double* out);
 
+/* Batches of independent problems (e.g. many domain lengths L or potentials
+ * at once).  The instances keep their own shift, local inverse, coarse
+ * space and CG state; every kernel of a PCG iteration (§3,
+ * eq:cg-energy-norm-error-reduction, with the preconditioner of
+ * eq:twoLevelASMPreconditioner) runs as one grouped launch over all
+ * instances, and each instance stops on its own test.  Requirements, checked
+ * by ddeig_batch_create (DDEIG_EINVAL otherwise): every instance is 2-D
+ * (p = q = 1) with L > 4, dense local solves (local_prec 2 or 3, the same for
+ * all) and the coarse space, n_e dividing 64 and at most 1024 stencil tiles
+ * ((n_dof x-extent / 256 rounded up) x (ell n_e - 1) / 8 rounded up); all share
+ * n_e, overlap, ell, the partition of unity and the stream.  The batch
+ * borrows the problems: they must outlive it and must not be used on their
+ * own while a batch call runs.  Creation runs a small autotuner that times
+ * the grouped MFMA GEMM for each admissible K split and tile order on the
+ * device and keeps the fastest (synchronises). */
+typedef struct ddeig_batch ddeig_batch;
+
+/* flags: DDEIG_BATCH_GRAPHS replays the grouped iterations (8 per host check)
+ * from HIP graphs captured on first use (one per block start and maxit),
+ * instead of launching the kernels one by one. */
+#define DDEIG_BATCH_GRAPHS 1
+
+ddeig_status ddeig_batch_create(ddeig_problem* const* probs, int n, int flags, ddeig_batch** out);
+
+/* Autotuner result: K split, tile order (0 instance-major, 1 XCD-interleaved),
+ * number of GEMM tiles, and the six measured candidate times in us
+ * (split 1..3 x order 0..1; 0 where a split was not admissible). */
+ddeig_status ddeig_batch_query(const ddeig_batch* B, int* ksplit, int* order, int* ntiles,
+                               double* tune_us);
+
+/* PCG for every instance j: A_sigma,j x[j] = b[j] (host arrays of n device
+ * pointers; x[j] holds x0 on entry).  info (nullable, n entries; hist is
+ * ignored) receives each instance's iterations, relative residual and
+ * breakdown flag.  Returns DDEIG_OK when every instance converged, else the
+ * status of the failing instance (ENOTSPD before ENOCONV). */
+ddeig_status ddeig_batch_pcg_solve(ddeig_batch* B, const double* const* b, double* const* x,
+                                   double rtol, int maxit, ddeig_pcg_info* info);
+
+/* sigma-shifted inverse iteration (as ddeig_inverse_iteration) for every
+ * instance; converged instances drop out of the grouped launches.  x: n
+ * device pointers (all-zero start vectors select 1/||1||_M).  info (nullable,
+ * n entries) receives each instance's result; t_solve_ms is the batch's
+ * wall time.  Returns DDEIG_OK when every instance converged. */
+ddeig_status ddeig_batch_inverse_iteration(ddeig_batch* B, double* const* x, double tol_x,
+                                           int maxit_outer, double rtol_inner, int maxit_inner,
+                                           ddeig_eig_info* info);
+
+void ddeig_batch_destroy(ddeig_batch* B);
+
 /* Sizes: interior unknowns, cell unknowns, number of subdomains (= coarse dimension). */
 ddeig_status ddeig_query(const ddeig_problem* P, long* n_dof, long* n_cell, int* n_sub);
 

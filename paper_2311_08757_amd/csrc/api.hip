@@ -567,6 +567,9 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
           sync(P);  // tl is released at the end of this scope
           E.Tidx = dT;
           E.G = dalloc<float>(P, (size_t)nT * H.m);
+          E.Z = H.Z;
+          E.zsplit = (long)H.mp * H.ld;
+          E.st = nullptr;
           const int ci = (int)P->emb.size();
           P->emb.push_back(E);
           P->maxT = std::max(P->maxT, nT);
@@ -717,7 +720,7 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
       if (!tiles.empty())
         check_hip(hipMemcpyAsync(P->dTiles, tiles.data(), sizeof(ddeig::GemmTile) * tiles.size(),
                                  hipMemcpyHostToDevice, s), "copy tiles");
-      const ddeig::GemmType gt{H.Ah, H.Al, H.Rh, H.Rl, H.Z, (long)H.mp * H.ld, H.ld};
+      const ddeig::GemmType gt{H.Ah, H.Al, H.Rh, H.Rl, H.Z, (long)H.mp * H.ld, H.ld, nullptr};
       P->dGtypes = dalloc<ddeig::GemmType>(P, 1);
       check_hip(hipMemcpyAsync(P->dGtypes, &gt, sizeof(ddeig::GemmType), hipMemcpyHostToDevice, s),
                 "copy gemm operands");
@@ -1132,5 +1135,555 @@ ddeig_status ddeig_inverse_iteration(ddeig_problem* P, double* x, double tol_x, 
   return st;
   API_GUARD_END
 }
+
+}  // extern "C"
+
+// ---- batches of independent problems ---------------------------------------
+//
+// Instances that share the mesh width, the overlap, the fixed-direction
+// extent and the dense local-solve mode (2-D, one expanding axis) have dense
+// boxes of one shape, so every kernel of a PCG iteration can run as one
+// grouped launch over all of them: a block map sends each block to (instance,
+// block within the instance), the MFMA tiles and the clipped-class jobs carry
+// their instance, and every instance keeps its own CG scalars, partial sums
+// and stopping test (its `done` flag turns its blocks into no-ops).  The
+// start of each solve and the inverse-iteration normalisation run per
+// instance.
+
+struct ddeig_batch {
+  std::vector<ddeig_problem*> P;
+  hipStream_t stream = nullptr, aux = nullptr, cap = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int n = 0, local_prec = 0, ksplit = 1, order = 0;
+  int ld = 0, hm0 = 0, hm1 = 0, mH = 0;
+  std::vector<ddeig::InstDev> inst;
+  ddeig::InstDev* dInst = nullptr;
+  ddeig::BlockMap bm_st{}, bm_node{}, bm_crhs{}, bm_csol{}, bm_cf{};
+  ddeig::GemmTile* dTiles = nullptr;
+  int ntiles = 0;
+  ddeig::GemmType* dGt = nullptr;
+  ddeig::EmbedJob* dEmbJobs = nullptr;
+  int nembjobs = 0;
+  ddeig::EmbedDev* dEmb = nullptr;
+  ddeig::PcgState* dStates = nullptr;
+  std::vector<ddeig::PcgState> hStates;
+  double* dRes = nullptr;
+  std::vector<void*> allocs;
+  double tune_us[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // hipGraph replay of the grouped iterations: one executable graph per
+  // (first iteration of a block of 8, maxit), captured on first use
+  int use_graphs = 0;
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+template <typename T>
+T* balloc(ddeig_batch* B, size_t count) {
+  void* p = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Failure{DDEIG_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+  }
+  B->allocs.push_back(p);
+  return static_cast<T*>(p);
+}
+
+template <typename T>
+T* bupload(ddeig_batch* B, const std::vector<T>& v) {
+  T* d = balloc<T>(B, v.size());
+  check_hip(hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice), "batch upload");
+  return d;
+}
+
+ddeig::BlockMap make_map(ddeig_batch* B, const std::vector<int>& counts) {
+  std::vector<int2> m;
+  for (size_t j = 0; j < counts.size(); ++j)
+    for (int b = 0; b < counts[j]; ++b) m.push_back(make_int2((int)j, b));
+  return ddeig::BlockMap{bupload(B, m), (int)m.size()};
+}
+
+// MFMA tiles of every instance for a K split of ks: a group is the row tiles
+// of one (instance, column tile, split), which read the same rows of that
+// instance's inverse.  order 1 interleaves eight groups of equal size so that
+// a group's tiles get workgroup ids 8 apart (one XCD, one L2 copy of the rows).
+std::vector<ddeig::GemmTile> batch_tiles(const ddeig_batch* B, int ks, int order) {
+  const int bk = B->local_prec == 2 ? 32 : 64;
+  const int npair = B->ld / bk / 2;
+  std::vector<std::vector<ddeig::GemmTile>> groups;
+  for (int j = 0; j < B->n; ++j) {
+    const int mp = B->P[j]->dh.mp;
+    for (int sp = 0; sp < ks; ++sp) {
+      const int kb0 = 2 * (int)((long)npair * sp / ks);
+      const int kb1 = 2 * (int)((long)npair * (sp + 1) / ks);
+      for (int nt = 0; nt < B->ld / 128; ++nt) {
+        std::vector<ddeig::GemmTile> grp;
+        for (int mt = 0; mt < mp / 128; ++mt)
+          grp.push_back(ddeig::GemmTile{j, mt * 128, nt * 128, kb0 * bk, kb1 * bk, sp});
+        groups.push_back(grp);
+      }
+    }
+  }
+  std::vector<ddeig::GemmTile> tiles;
+  if (order == 0) {
+    for (auto& g : groups)
+      for (auto& t : g) tiles.push_back(t);
+    return tiles;
+  }
+  std::stable_sort(groups.begin(), groups.end(),
+                   [](const std::vector<ddeig::GemmTile>& a, const std::vector<ddeig::GemmTile>& b) {
+                     return a.size() > b.size();
+                   });
+  size_t gi = 0;
+  while (gi < groups.size()) {
+    size_t gj = gi;
+    while (gj < groups.size() && gj - gi < 8 && groups[gj].size() == groups[gi].size()) ++gj;
+    for (size_t i = 0; i < groups[gi].size(); ++i)
+      for (size_t j = gi; j < gj; ++j) tiles.push_back(groups[j][i]);
+    gi = gj;
+  }
+  return tiles;
+}
+
+void batch_upload_inst(ddeig_batch* B) {
+  check_hip(hipMemcpyAsync(B->dInst, B->inst.data(), sizeof(ddeig::InstDev) * B->n,
+                           hipMemcpyHostToDevice, B->stream), "upload instances");
+  check_hip(hipStreamSynchronize(B->stream), "hipStreamSynchronize");
+}
+
+// One grouped PCG iteration k over every instance (see pcg_run for the kernels),
+// issued on stream s (the batch's stream, or its capture stream).
+void batch_iteration(ddeig_batch* B, int k, int maxit, hipStream_t s) {
+  launch_b_stencil_dir(B->dInst, B->bm_st, k, s);
+  launch_b_restrict(B->dInst, B->bm_node, k, s);
+  check_hip(hipEventRecord(B->ev_fork, s), "record fork");
+  check_hip(hipStreamWaitEvent(B->aux, B->ev_fork, 0), "wait fork");
+  launch_gemm_tiles(B->dTiles, B->ntiles, B->dGt, B->local_prec, s);
+  launch_embed_jobs(B->dEmbJobs, B->nembjobs, B->dEmb, B->ksplit, B->ld, B->hm0, B->hm1, B->mH, s);
+  launch_b_coarse_rhs(B->dInst, B->bm_crhs, B->aux);
+  launch_b_coarse_solve(B->dInst, B->bm_csol, B->aux);
+  launch_b_coarse_field(B->dInst, B->bm_cf, B->aux);
+  check_hip(hipEventRecord(B->ev_join, B->aux), "record join");
+  check_hip(hipStreamWaitEvent(s, B->ev_join, 0), "wait join");
+  launch_b_extend(B->dInst, B->bm_node, k, maxit, B->ksplit, s);
+}
+
+// PCG on A_sigma,j x_j = b_j for the instances with active[j] != 0 (the
+// others stay idle); on return B->hStates holds every instance's final state.
+void batch_pcg(ddeig_batch* B, const std::vector<int>& active, const std::vector<const double*>& b,
+               const std::vector<double*>& x, double rtol, int maxit) {
+  const hipStream_t s = B->stream;
+  for (int j = 0; j < B->n; ++j) B->inst[j].x = x[j];
+  batch_upload_inst(B);
+  launch_b_states(B->dInst, B->n, B->dStates, 1, s);
+  for (int j = 0; j < B->n; ++j) {
+    if (!active[j]) continue;
+    ddeig_problem* P = B->P[j];
+    Red rr = slot(P, 1), rz = slot(P, 2);
+    launch_stencil(P, P->tabAs, x[j], P->q, nullptr, nullptr, s);
+    launch_resid_init(P, b[j], P->q, P->r, rr, s);
+    launch_pcg_init(P, rtol, rr, s);
+    precond_apply(P, P->r, P->z, &rz, P->st);
+  }
+  check_launch("batch pcg start");
+  int k = 0;
+  bool all_done = false;
+  while (!all_done) {
+    const int k0 = k + 1, kend = std::min(maxit, k + 8);
+    if (B->use_graphs && kend >= k0) {
+      const auto key = std::make_pair(k0, maxit);
+      auto it = B->graphs.find(key);
+      if (it == B->graphs.end()) {
+        hipGraph_t gr = nullptr;
+        hipGraphExec_t ge = nullptr;
+        // captured on the batch's own stream (the problems' stream may be the
+        // null stream, which cannot capture), launched on the problems' stream
+        const hipStream_t cs = B->cap;
+        check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+        try {
+          for (int kk = k0; kk <= kend; ++kk) batch_iteration(B, kk, maxit, cs);
+        } catch (...) {
+          (void)hipStreamEndCapture(cs, &gr);
+          if (gr) (void)hipGraphDestroy(gr);
+          throw;
+        }
+        check_hip(hipStreamEndCapture(cs, &gr), "end capture");
+        const hipError_t e = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        check_hip(e, "instantiate graph");
+        it = B->graphs.emplace(key, ge).first;
+      }
+      check_hip(hipGraphLaunch(it->second, s), "launch graph");
+      k = kend;
+    } else {
+      for (++k; k <= kend; ++k) batch_iteration(B, k, maxit, s);
+      --k;
+    }
+    check_launch("batch pcg iteration");
+    launch_b_states(B->dInst, B->n, B->dStates, 0, s);
+    check_hip(hipMemcpyAsync(B->hStates.data(), B->dStates, sizeof(ddeig::PcgState) * B->n,
+                             hipMemcpyDeviceToHost, s), "copy states");
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    all_done = true;
+    for (int j = 0; j < B->n; ++j)
+      if (active[j] && B->hStates[j].done == 0) all_done = false;
+    if (k >= maxit) break;
+  }
+  // maxit reached without a stopping decision (maxit = 0 or a state still running)
+  for (int j = 0; j < B->n; ++j)
+    if (active[j] && B->hStates[j].done == 0) B->hStates[j].done = 4;
+}
+
+float time_gemm(ddeig_batch* B, const ddeig::GemmTile* dT, int nt, const ddeig::GemmType* gt) {
+  hipEvent_t e0, e1;
+  check_hip(hipEventCreate(&e0), "event");
+  check_hip(hipEventCreate(&e1), "event");
+  for (int i = 0; i < 3; ++i) launch_gemm_tiles(dT, nt, gt, B->local_prec, B->stream);
+  check_hip(hipEventRecord(e0, B->stream), "record");
+  const int reps = 10;
+  for (int i = 0; i < reps; ++i) launch_gemm_tiles(dT, nt, gt, B->local_prec, B->stream);
+  check_hip(hipEventRecord(e1, B->stream), "record");
+  check_hip(hipEventSynchronize(e1), "sync");
+  float ms = 0.0f;
+  check_hip(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  check_launch("gemm tuning");
+  return 1000.0f * ms / reps;
+}
+
+void batch_free(ddeig_batch* B) {
+  if (!B) return;
+  if (B->stream) (void)hipStreamSynchronize(B->stream);
+  for (auto& kv : B->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (void* p : B->allocs) (void)hipFree(p);
+  if (B->aux) (void)hipStreamDestroy(B->aux);
+  if (B->cap) (void)hipStreamDestroy(B->cap);
+  if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
+  if (B->ev_join) (void)hipEventDestroy(B->ev_join);
+  delete B;
+}
+
+}  // namespace
+
+extern "C" {
+
+ddeig_status ddeig_batch_create(ddeig_problem* const* probs, int n, int flags, ddeig_batch** out) {
+  if (!probs || !out) return set_error(DDEIG_EINVAL, "probs or out is NULL");
+  *out = nullptr;
+  if (n < 1 || n > 4096) return set_error(DDEIG_EINVAL, "need 1 <= n <= 4096 instances");
+  if (flags & ~DDEIG_BATCH_GRAPHS) return set_error(DDEIG_EINVAL, "unknown batch flags");
+  const ddeig_problem* P0 = probs[0];
+  for (int j = 0; j < n; ++j) {
+    const ddeig_problem* P = probs[j];
+    if (!P) return set_error(DDEIG_EINVAL, "instance " + std::to_string(j) + " is NULL");
+    for (int i = 0; i < j; ++i)
+      if (probs[i] == P) return set_error(DDEIG_EINVAL, "an instance appears twice");
+    const std::string who = "instance " + std::to_string(j) + ": ";
+    if (P->g.D != 2 || P->g.p != 1)
+      return set_error(DDEIG_EINVAL, who + "batches need p = 1, q = 1 (2-D)");
+    if (P->opt.local_prec < 2 || P->opt.coarse != 1)
+      return set_error(DDEIG_EINVAL, who + "batches need dense local solves (local_prec 2 or 3) "
+                                           "and the coarse space");
+    if (64 % P->g.ne != 0) return set_error(DDEIG_EINVAL, who + "batches need n_e dividing 64");
+    if (P->nsub <= ddeig::kGemvMax)
+      return set_error(DDEIG_EINVAL, who + "batches need L > " + std::to_string(ddeig::kGemvMax));
+    if (ddeig::stencil_tiles(P->g) > kMaxRed)
+      return set_error(DDEIG_EINVAL, who + "instance too large for a batch (stencil tiles > 1024)");
+    if (P->opt.local_prec != P0->opt.local_prec || P->g.ne != P0->g.ne ||
+        P->delta != P0->delta || P->g.N[1] != P0->g.N[1] || P->dh.ld != P0->dh.ld ||
+        P->dh.m != P0->dh.m || P->stream != P0->stream || P->opt.pu != P0->opt.pu)
+      return set_error(DDEIG_EINVAL, who + "instances of a batch need the same n_e, overlap, ell, "
+                                           "partition of unity, local_prec and stream");
+  }
+  ddeig_batch* B = nullptr;
+  try {
+    B = new ddeig_batch();
+  } catch (const std::bad_alloc&) {
+    return set_error(DDEIG_ENOMEM, "host allocation failed");
+  }
+  try {
+    B->n = n;
+    B->use_graphs = (flags & DDEIG_BATCH_GRAPHS) ? 1 : 0;
+    B->P.assign(probs, probs + n);
+    B->stream = P0->stream;
+    B->local_prec = P0->opt.local_prec;
+    B->ld = P0->dh.ld;
+    B->hm0 = P0->dh.box.m[0];
+    B->hm1 = P0->dh.box.m[1];
+    B->mH = P0->dh.m;
+    check_hip(hipStreamCreateWithFlags(&B->aux, hipStreamNonBlocking), "create batch stream");
+    if (B->use_graphs)
+      check_hip(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking), "create capture stream");
+    check_hip(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming), "create event");
+    check_hip(hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming), "create event");
+    int ks_max = 3;
+    for (auto* P : B->P) ks_max = std::min(ks_max, P->ksplit);
+    // grouped-GEMM tiles: a small autotuner times every K split the Z buffers
+    // allow, with and without the XCD interleave, and keeps the fastest
+    std::vector<ddeig::GemmType> gts(n), gtt(n);
+    for (int j = 0; j < n; ++j) {
+      const ddeig::DenseHost& H = B->P[j]->dh;
+      gts[j] = ddeig::GemmType{H.Ah, H.Al, H.Rh, H.Rl, H.Z, (long)H.mp * H.ld, H.ld, B->P[j]->st};
+      gtt[j] = gts[j];
+      gtt[j].st = nullptr;
+    }
+    B->dGt = bupload(B, gts);
+    ddeig::GemmType* dGtt = bupload(B, gtt);
+    float best = 1e30f;
+    std::vector<ddeig::GemmTile> best_tiles;
+    int ci = 0;
+    for (int ks = 1; ks <= ks_max; ++ks)
+      for (int order = 0; order < 2; ++order, ++ci) {
+        std::vector<ddeig::GemmTile> t = batch_tiles(B, ks, order);
+        ddeig::GemmTile* dT = bupload(B, t);
+        const float us = time_gemm(B, dT, (int)t.size(), dGtt);
+        if (ci < 8) B->tune_us[ci] = us;
+        if (us < best) {
+          best = us;
+          best_tiles = t;
+          B->ksplit = ks;
+          B->order = order;
+        }
+      }
+    B->dTiles = bupload(B, best_tiles);
+    B->ntiles = (int)best_tiles.size();
+    // clipped classes of every instance, each checked against its instance's state
+    std::vector<ddeig::EmbedDev> emb;
+    std::vector<ddeig::EmbedJob> jobs;
+    for (int j = 0; j < n; ++j)
+      for (const auto& E0 : B->P[j]->emb) {
+        ddeig::EmbedDev E = E0;
+        E.st = B->P[j]->st;
+        const int ci2 = (int)emb.size();
+        emb.push_back(E);
+        for (int m0 = 0; m0 < E.nmem; m0 += ddeig::kEmbChunk)
+          jobs.push_back(ddeig::EmbedJob{ci2, m0, std::min(ddeig::kEmbChunk, E.nmem - m0)});
+      }
+    B->nembjobs = (int)jobs.size();
+    if (!emb.empty()) {
+      B->dEmb = bupload(B, emb);
+      B->dEmbJobs = bupload(B, jobs);
+    }
+    // instance descriptors and block maps
+    B->inst.resize(n);
+    std::vector<int> c_st(n), c_node(n), c_crhs(n), c_csol(n), c_cf(n);
+    for (int j = 0; j < n; ++j) {
+      ddeig_problem* P = B->P[j];
+      const ddeig::DenseHost& H = P->dh;
+      ddeig::InstDev& d = B->inst[j];
+      d.g = P->g;
+      d.delta = P->delta;
+      d.pu = P->opt.pu;
+      d.nsub = P->nsub;
+      d.nb_node = ddeig::node_grid(P->g);
+      d.nb_cf = ddeig::coarse_field_grid(P->g);
+      d.hist_cap = P->hist_cap;
+      d.tabAs = P->tabAs;
+      d.x = P->u;
+      d.r = P->r;
+      d.z = P->z;
+      d.q = P->q;
+      d.pp[0] = P->pp[0];
+      d.pp[1] = P->pp[1];
+      d.st = P->st;
+      d.gam = slot(P, 0);
+      d.gam.np = (int)ddeig::stencil_tiles(P->g);
+      d.rr = slot(P, 1);
+      d.rr.np = d.nb_node;
+      d.rz = slot(P, 2);
+      d.rz.np = d.nb_node;
+      d.da = ddeig::DenseArgs{H.Rh, H.Rl, H.Z, (long)H.mp * H.ld, H.ld, B->ksplit, H.box.m[0],
+                              H.box.m[1]};
+      d.psi = P->psi;
+      d.cf = P->cfield;
+      d.types = P->dTypes;
+      d.subs = P->dSubs;
+      d.crhs = P->crhs;
+      d.A0inv = P->A0inv;
+      d.cy = P->cy;
+      d.xc0 = P->dXC[0];
+      d.hist = P->hist;
+      c_st[j] = d.gam.np;
+      c_node[j] = d.nb_node;
+      c_crhs[j] = P->nsub;
+      c_csol[j] = (P->nsub + kBlock / 64 - 1) / (kBlock / 64);
+      c_cf[j] = d.nb_cf;
+    }
+    B->dInst = balloc<ddeig::InstDev>(B, n);
+    B->bm_st = make_map(B, c_st);
+    B->bm_node = make_map(B, c_node);
+    B->bm_crhs = make_map(B, c_crhs);
+    B->bm_csol = make_map(B, c_csol);
+    B->bm_cf = make_map(B, c_cf);
+    B->dStates = balloc<ddeig::PcgState>(B, n);
+    B->hStates.resize(n);
+    B->dRes = balloc<double>(B, 2 * (size_t)n);
+    check_hip(hipStreamSynchronize(B->stream), "hipStreamSynchronize");
+  } catch (const Failure& f) {
+    batch_free(B);
+    return set_error(f.status, f.msg);
+  } catch (const std::bad_alloc&) {
+    batch_free(B);
+    return set_error(DDEIG_ENOMEM, "host allocation failed");
+  } catch (...) {
+    batch_free(B);
+    return set_error(DDEIG_EINTERNAL, "unexpected internal exception");
+  }
+  *out = B;
+  return DDEIG_OK;
+}
+
+ddeig_status ddeig_batch_query(const ddeig_batch* B, int* ksplit, int* order, int* ntiles,
+                               double* tune_us) {
+  if (!B) return set_error(DDEIG_EINVAL, "batch is NULL");
+  if (ksplit) *ksplit = B->ksplit;
+  if (order) *order = B->order;
+  if (ntiles) *ntiles = B->ntiles;
+  if (tune_us)
+    for (int i = 0; i < 6; ++i) tune_us[i] = B->tune_us[i];
+  return DDEIG_OK;
+}
+
+ddeig_status ddeig_batch_pcg_solve(ddeig_batch* B, const double* const* b, double* const* x,
+                                   double rtol, int maxit, ddeig_pcg_info* info) {
+  if (!B) return set_error(DDEIG_EINVAL, "batch is NULL");
+  if (!b || !x) return set_error(DDEIG_EINVAL, "b or x is NULL");
+  if (!(rtol >= 0.0) || !std::isfinite(rtol) || maxit < 0)
+    return set_error(DDEIG_EINVAL, "need rtol >= 0 and maxit >= 0");
+  for (int j = 0; j < B->n; ++j) {
+    if (validate_vec(b[j], "b") || validate_vec(x[j], "x")) return DDEIG_EINVAL;
+    if (b[j] == x[j]) return set_error(DDEIG_EINVAL, "b and x must not alias");
+    if (!B->P[j]->shifted)
+      return set_error(DDEIG_ESTATE, "instance " + std::to_string(j) + ": shift not set");
+  }
+  API_GUARD_BEGIN
+  std::vector<int> active(B->n, 1);
+  std::vector<const double*> bb(b, b + B->n);
+  std::vector<double*> xx(x, x + B->n);
+  batch_pcg(B, active, bb, xx, rtol, maxit);
+  ddeig_status st = DDEIG_OK;
+  for (int j = B->n - 1; j >= 0; --j) {
+    const ddeig::PcgState& h = B->hStates[j];
+    if (info) {
+      info[j].iters = h.iters;
+      info[j].relres = h.relres;
+      info[j].breakdown = h.done == 2 ? 1 : (h.done == 3 ? 2 : 0);
+    }
+    if (h.done == 2 || h.done == 3)
+      st = set_error(DDEIG_ENOTSPD, "instance " + std::to_string(j) + ": CG breakdown");
+    else if (h.done != 1 && st != DDEIG_ENOTSPD)
+      st = set_error(DDEIG_ENOCONV, "instance " + std::to_string(j) + ": PCG reached maxit");
+  }
+  return st;
+  API_GUARD_END
+}
+
+ddeig_status ddeig_batch_inverse_iteration(ddeig_batch* B, double* const* x, double tol_x,
+                                           int maxit_outer, double rtol_inner, int maxit_inner,
+                                           ddeig_eig_info* info) {
+  if (!B) return set_error(DDEIG_EINVAL, "batch is NULL");
+  if (!x) return set_error(DDEIG_EINVAL, "x is NULL");
+  if (!(tol_x >= 0.0) || maxit_outer < 1 || !(rtol_inner >= 0.0) || maxit_inner < 1)
+    return set_error(DDEIG_EINVAL, "invalid tolerances or iteration limits");
+  for (int j = 0; j < B->n; ++j) {
+    if (validate_vec(x[j], "x")) return DDEIG_EINVAL;
+    if (!B->P[j]->shifted)
+      return set_error(DDEIG_ESTATE, "instance " + std::to_string(j) + ": shift not set");
+  }
+  API_GUARD_BEGIN
+  const hipStream_t s = B->stream;
+  const int n = B->n;
+  const auto t0 = std::chrono::steady_clock::now();
+  // start vectors: x_j, or 1/||1||_M where x_j is all zeros
+  for (int j = 0; j < n; ++j) {
+    ddeig_problem* P = B->P[j];
+    Red s3 = slot(P, 3);
+    launch_dot(x[j], x[j], P->g.n, s3, s);
+    if (host_sum(P, s3) == 0.0) {
+      launch_fill(P->u, P->g.n, 1.0, s);
+      launch_stencil(P, P->tabM, P->u, P->w, &s3, nullptr, s);
+      launch_scale_copy(P->g.n, x[j], P->u, s3, s);
+    }
+  }
+  std::vector<int> active(n, 1), status(n, 0), its(n, 0), inner_max(n, 0);
+  std::vector<long> inner_sum(n, 0);
+  std::vector<double> lam(n, 0.0), dx(n, INFINITY), res(2 * (size_t)n);
+  std::vector<const double*> bb(n);
+  std::vector<double*> uu(n);
+  for (int j = 0; j < n; ++j) {
+    bb[j] = B->P[j]->w;
+    uu[j] = B->P[j]->u;
+  }
+  for (int k = 1; k <= maxit_outer; ++k) {
+    int nact = 0;
+    for (int j = 0; j < n; ++j) {
+      if (!active[j]) continue;
+      ++nact;
+      ddeig_problem* P = B->P[j];
+      launch_stencil(P, P->tabM, x[j], P->w, nullptr, nullptr, s);  // b = M x
+      launch_fill(P->u, P->g.n, 0.0, s);
+    }
+    if (nact == 0) break;
+    batch_pcg(B, active, bb, uu, rtol_inner, maxit_inner);
+    for (int j = 0; j < n; ++j) {
+      if (!active[j]) continue;
+      const ddeig::PcgState& h = B->hStates[j];
+      if (h.done == 2 || h.done == 3) {
+        status[j] = DDEIG_ENOTSPD;
+        active[j] = 0;
+        continue;
+      }
+      inner_sum[j] += h.iters;
+      inner_max[j] = std::max(inner_max[j], h.iters);
+      its[j] = k;
+      ddeig_problem* P = B->P[j];
+      const long nn = P->g.n;
+      Red s4 = slot(P, 4), s5 = slot(P, 5), s6 = slot(P, 6), s7 = slot(P, 7);
+      launch_stencil(P, P->tabM, P->u, P->z, &s4, &s5, s);
+      launch_ipm_normalise(nn, P->u, P->z, x[j], P->w, s4, s5, s6, s);
+      launch_stencil(P, P->tabAs, x[j], P->q, &s7, nullptr, s);
+      launch_finish_sum(s6, s);
+      launch_finish_sum(s7, s);
+      check_hip(hipMemcpyAsync(B->dRes + 2 * j, P->red_val + 6, 2 * sizeof(double),
+                               hipMemcpyDeviceToDevice, s), "gather");
+    }
+    check_launch("batch normalisation");
+    check_hip(hipMemcpyAsync(res.data(), B->dRes, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, s),
+              "copy results");
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    for (int j = 0; j < n; ++j) {
+      if (!active[j]) continue;
+      dx[j] = std::sqrt(std::max(res[2 * j], 0.0));
+      lam[j] = B->P[j]->sigma + res[2 * j + 1];
+      if (dx[j] <= tol_x) {
+        active[j] = 0;
+        status[j] = 1;
+      }
+    }
+  }
+  const auto t1 = std::chrono::steady_clock::now();
+  const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  ddeig_status st = DDEIG_OK;
+  for (int j = n - 1; j >= 0; --j) {
+    if (info) {
+      info[j].lambda = lam[j];
+      info[j].dx_M = dx[j];
+      info[j].outer_its = its[j];
+      info[j].inner_sum = inner_sum[j];
+      info[j].inner_max = inner_max[j];
+      info[j].t_solve_ms = ms;
+    }
+    if (status[j] == DDEIG_ENOTSPD)
+      st = set_error(DDEIG_ENOTSPD, "instance " + std::to_string(j) + ": CG breakdown");
+    else if (status[j] != 1 && st != DDEIG_ENOTSPD)
+      st = set_error(DDEIG_ENOCONV, "instance " + std::to_string(j) + ": reached maxit_outer");
+  }
+  return st;
+  API_GUARD_END
+}
+
+void ddeig_batch_destroy(ddeig_batch* B) { batch_free(B); }
 
 }  // extern "C"

@@ -122,12 +122,16 @@ struct DenseHost {
 // the other nodes of the unclipped box, G = B_ST (B_TT)^{-1} for the rounded
 // unclipped inverse B, stored t-major over the unclipped box (G[t * mH + e],
 // zero for e in T; see k_dense.hip).
+struct PcgState;
 struct EmbedDev {
   int nT, nmem;
   int off[3], m[3];
   const int* rows;  // batch rows (subdomain ids) of the members
   const int* Tidx;
   const float* G;
+  float* Z;         // the problem's split-K products Z[split][row][e]
+  long zsplit;
+  const PcgState* st;  // CG state checked by grouped launches (nullptr: the launch's own)
 };
 // Batch operands of the dense-mode restriction / extension kernels.
 struct DenseArgs {
@@ -190,6 +194,7 @@ struct GemmType {
   float* Z;
   long zsplit;
   int ld;
+  const PcgState* st;  // CG state checked by grouped launches (nullptr: the launch's own)
 };
 
 // Batched chain solves: one workgroup per (class, member tile, 64 rows of a slice).
@@ -209,12 +214,45 @@ struct GemvRows {
 
 // PCG device state (one per problem).
 struct PcgState {
-  int done;      // 0 running, 1 converged, 2 p.Ap <= 0, 3 r.z <= 0, 4 maxit
+  int done;      // 0 running, 1 converged, 2 p.Ap <= 0, 3 r.z <= 0, 4 maxit, 5 idle (batch)
   int iters;
   double rho[2]; // r.z of iterations of even / odd parity
   double r0n2;
   double tol2;
   double relres;
+};
+
+// One instance of a batch of problems advanced together: everything the
+// grouped kernels of a PCG iteration read, copied to the device once per
+// solve.  Each instance keeps its own CG state, scalars and partial sums.
+struct InstDev {
+  Geo g;
+  int delta, pu, nsub;
+  int nb_node;  // blocks of the node-parallel restriction / extension
+  int nb_cf;    // blocks of the coarse field
+  int hist_cap;
+  const double* tabAs;
+  double* x;    // CG iterate
+  double *r, *z, *q;
+  double* pp[2];
+  PcgState* st;
+  Red gam, rr, rz;
+  DenseArgs da;
+  const double* psi;
+  double* cf;
+  const TypeDev* types;
+  const SubDev* subs;
+  double* crhs;
+  const double* A0inv;
+  double* cy;
+  const XCover* xc0;
+  double* hist;
+};
+
+// Block -> (instance, block index within the instance) of a grouped launch.
+struct BlockMap {
+  const int2* map;
+  int nblocks;
 };
 
 }  // namespace ddeig
@@ -358,6 +396,22 @@ void launch_embed_gmat(const ddeig_problem* P, const EmbedDev& E, const double* 
 void launch_embed_fix(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 void launch_to_float(const double* src, float* dst, long n, hipStream_t s);
 void build_coarse_matrix(ddeig_problem* P, double* A0, hipStream_t s);
+
+// grouped launches over the instances of a batch (one PCG iteration k)
+int node_grid(const Geo& g);
+int coarse_field_grid(const Geo& g);
+void launch_b_stencil_dir(const InstDev* I, const BlockMap& bm, int k, hipStream_t s);
+void launch_b_restrict(const InstDev* I, const BlockMap& bm, int k, hipStream_t s);
+void launch_b_extend(const InstDev* I, const BlockMap& bm, int k, int maxit, int ksplit,
+                     hipStream_t s);
+void launch_b_coarse_rhs(const InstDev* I, const BlockMap& bm, hipStream_t s);
+void launch_b_coarse_solve(const InstDev* I, const BlockMap& bm, hipStream_t s);
+void launch_b_coarse_field(const InstDev* I, const BlockMap& bm, hipStream_t s);
+void launch_gemm_tiles(const GemmTile* tiles, int ntiles, const GemmType* gt, int local_prec,
+                       hipStream_t s);
+void launch_embed_jobs(const EmbedJob* jobs, int njobs, const EmbedDev* cls, int ksplit, int ld,
+                       int hm0, int hm1, int mH, hipStream_t s);
+void launch_b_states(const InstDev* I, int n, PcgState* out, int mark_done, hipStream_t s);
 
 // PCG / IPM vector kernels
 int red_grid(long work_items);

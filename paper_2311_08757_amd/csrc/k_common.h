@@ -27,11 +27,18 @@ __device__ inline double block_sum_n(double v) {
 
 __device__ inline double block_sum(double v) { return block_sum_n<kBlock>(v); }
 
-// One partial sum per block (see Red).
+// One partial sum per block (see Red); bid is the block's index among the
+// producers of the sum (its blockIdx.x, or its index within one instance of a
+// grouped launch).
+template <int NT = kBlock>
+__device__ inline void write_partial_at(double v, double* part, int bid) {
+  const double b = block_sum_n<NT>(v);
+  if (threadIdx.x == 0) part[bid] = b;
+}
+
 template <int NT = kBlock>
 __device__ inline void write_partial(double v, double* part) {
-  const double b = block_sum_n<NT>(v);
-  if (threadIdx.x == 0) part[blockIdx.x] = b;
+  write_partial_at<NT>(v, part, blockIdx.x);
 }
 
 // The sum of the np partials of a producing kernel, added in block order by

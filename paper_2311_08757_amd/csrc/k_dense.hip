@@ -115,6 +115,7 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemm(const GemmTile* __restric
   if (st != nullptr && st->done) return;
   const GemmTile t = tiles[blockIdx.x];
   const GemmType gt = gtypes[t.type];
+  if (gt.st != nullptr && gt.st->done) return;
   const int ld = gt.ld;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
@@ -382,7 +383,6 @@ constexpr int kEmbPh = 8, kEmbE = kBlock / kEmbPh, kEmbG = 32;  // G loads per b
 template <int KS>
 __global__ void __launch_bounds__(kBlock) k_embed_correct(const EmbedJob* __restrict__ jobs,
                                                           const EmbedDev* __restrict__ cls,
-                                                          float* __restrict__ Z, long zsplit,
                                                           int ld, int hm0, int hm1, int mH,
                                                           const PcgState* __restrict__ st) {
   __shared__ float uT[kEmbChunk * kEmbMaxT];
@@ -390,6 +390,9 @@ __global__ void __launch_bounds__(kBlock) k_embed_correct(const EmbedJob* __rest
   if (st != nullptr && st->done) return;
   const EmbedJob jb = jobs[blockIdx.x];
   const EmbedDev E = cls[jb.cls];
+  if (E.st != nullptr && E.st->done) return;
+  float* __restrict__ Z = E.Z;
+  const long zsplit = E.zsplit;
   const int el = threadIdx.x % kEmbE, ph = threadIdx.x / kEmbE;
   const int e = blockIdx.y * kEmbE + el;
   const bool inS = e < mH && embed_in_box(E, e, hm0, hm1);
@@ -461,12 +464,11 @@ __global__ void __launch_bounds__(kBlock) k_embed_correct(const EmbedJob* __rest
 void launch_embed_fix(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
   if (P->nembjobs == 0) return;
   const DenseHost& H = P->dh;
-  const long zsplit = (long)H.mp * H.ld;
   // the K split is 1..3 by construction (assemble)
   auto kern = P->ksplit == 1 ? k_embed_correct<1> : (P->ksplit == 2 ? k_embed_correct<2>
                                                                      : k_embed_correct<3>);
   hipLaunchKernelGGL(kern, dim3(P->nembjobs, (H.m + kEmbE - 1) / kEmbE), dim3(kBlock), 0, s,
-                     P->dEmbJobs, P->dEmb, H.Z, zsplit, H.ld, H.box.m[0], H.box.m[1], H.m, st);
+                     P->dEmbJobs, P->dEmb, H.ld, H.box.m[0], H.box.m[1], H.m, st);
 }
 
 // Batches of more rows: 128 x 128 MFMA tiles.  local_prec 2 (bf16x3):
@@ -481,6 +483,29 @@ void launch_dense_gemm(const ddeig_problem* P, const PcgState* st, hipStream_t s
       hipLaunchKernelGGL((k_dense_gemm<false, false>), dim3(P->ntiles), dim3(kBlock), 0, s,
                          P->dTiles, P->dGtypes, st);
   }
+}
+
+// Grouped launches over the instances of a batch: the tiles / correction jobs
+// carry the instance in their type / class index, and each instance's CG
+// state is checked through GemmType::st / EmbedDev::st.
+void launch_gemm_tiles(const GemmTile* tiles, int ntiles, const GemmType* gt, int local_prec,
+                       hipStream_t s) {
+  if (ntiles <= 0) return;
+  if (local_prec == 2)
+    hipLaunchKernelGGL((k_dense_gemm<true, true>), dim3(ntiles), dim3(kBlock), 0, s, tiles, gt,
+                       nullptr);
+  else
+    hipLaunchKernelGGL((k_dense_gemm<false, false>), dim3(ntiles), dim3(kBlock), 0, s, tiles, gt,
+                       nullptr);
+}
+
+void launch_embed_jobs(const EmbedJob* jobs, int njobs, const EmbedDev* cls, int ksplit, int ld,
+                       int hm0, int hm1, int mH, hipStream_t s) {
+  if (njobs <= 0) return;
+  auto kern = ksplit == 1 ? k_embed_correct<1> : (ksplit == 2 ? k_embed_correct<2>
+                                                               : k_embed_correct<3>);
+  hipLaunchKernelGGL(kern, dim3(njobs, (mH + kEmbE - 1) / kEmbE), dim3(kBlock), 0, s, jobs, cls,
+                     ld, hm0, hm1, mH, nullptr);
 }
 
 void launch_dense_gemv(const ddeig_problem* P, const PcgState* st, hipStream_t s) {

@@ -274,13 +274,15 @@ __global__ void __launch_bounds__(kBlock) k_stencil(Geo g, const double* __restr
 // that both latency rounds overlap, and 32-bit tile-local index arithmetic
 // (fewer registers, more resident waves).  Same arithmetic and tap order as
 // k_stencil<2, MODE>.
+// The body takes the block's tile index `bid` (blockIdx.x of a single
+// problem, or the block's index within its instance in a grouped launch).
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_stencil2d(Geo g, const double* __restrict__ T,
-                                                      const double* __restrict__ x,
-                                                      const double* __restrict__ pold,
-                                                      double* __restrict__ pnew,
-                                                      double* __restrict__ y, DirArgs dir,
-                                                      int use_dot, Red dot, int use_sum, Red sum) {
+__device__ __forceinline__ void stencil2d_body(const Geo& g, const double* __restrict__ T,
+                                               const double* __restrict__ x,
+                                               const double* __restrict__ pold,
+                                               double* __restrict__ pnew, double* __restrict__ y,
+                                               const DirArgs& dir, int use_dot, const Red& dot,
+                                               int use_sum, const Red& sum, int bid) {
   constexpr int TX = 256, TY = 8, HX = TX + 2, HY = TY + 2, RX = TX / 64, RY = TY / 4;
   __shared__ double sv[HX * HY];
   double beta = 0.0;
@@ -288,18 +290,18 @@ __global__ void __launch_bounds__(kBlock) k_stencil2d(Geo g, const double* __res
     const double rho = sum_partials(dir.rz.part, dir.rz.np);
     if (dir.st->done) return;
     if (!(rho > 0.0)) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (bid == 0 && threadIdx.x == 0) {
         dir.st->done = 3;
         dir.st->iters = dir.k - 1;
       }
       return;
     }
     if (dir.k > 1) beta = rho / dir.st->rho[(dir.k - 2) & 1];
-    if (blockIdx.x == 0 && threadIdx.x == 0) dir.st->rho[(dir.k - 1) & 1] = rho;
+    if (bid == 0 && threadIdx.x == 0) dir.st->rho[(dir.k - 1) & 1] = rho;
   }
   const int N0 = g.N[0], N1 = g.N[1];
   const int nbx = (N0 + TX - 1) / TX;
-  const int bx = blockIdx.x % nbx, by = blockIdx.x / nbx;
+  const int bx = bid % nbx, by = bid / nbx;
   const int x0 = bx * TX, y0 = by * TY;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   // cell-local x position of the lane (the same for all its strides)
@@ -347,8 +349,34 @@ __global__ void __launch_bounds__(kBlock) k_stencil2d(Geo g, const double* __res
       accs += a;
     }
   }
-  if (use_dot) write_partial(acc, dot.part);
-  if (use_sum) write_partial(accs, sum.part);
+  if (use_dot) write_partial_at(acc, dot.part, bid);
+  if (use_sum) write_partial_at(accs, sum.part, bid);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_stencil2d(Geo g, const double* __restrict__ T,
+                                                      const double* __restrict__ x,
+                                                      const double* __restrict__ pold,
+                                                      double* __restrict__ pnew,
+                                                      double* __restrict__ y, DirArgs dir,
+                                                      int use_dot, Red dot, int use_sum, Red sum) {
+  stencil2d_body<MODE>(g, T, x, pold, pnew, y, dir, use_dot, dot, use_sum, sum, blockIdx.x);
+}
+
+// Grouped direction update + A_sigma p of PCG iteration k over the instances
+// of a batch: block b runs tile map[b].y of instance map[b].x.
+__global__ void __launch_bounds__(kBlock) k_b_stencil_dir(const InstDev* __restrict__ I,
+                                                          const int2* __restrict__ map, int k) {
+  const int2 m = map[blockIdx.x];
+  const InstDev& d = I[m.x];
+  const DirArgs dir{d.st, k, d.rz};
+  const Red none{nullptr, 0, nullptr};
+  stencil2d_body<1>(d.g, d.tabAs, d.z, d.pp[(k - 1) & 1], d.pp[k & 1], d.q, dir, 1, d.gam, 0, none,
+                    m.y);
+}
+
+void launch_b_stencil_dir(const InstDev* I, const BlockMap& bm, int k, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_stencil_dir, dim3(bm.nblocks), dim3(kBlock), 0, s, I, bm.map, k);
 }
 
 long stencil_tiles(const Geo& g) {

@@ -199,16 +199,21 @@ struct Cover {
   __device__ int c1(int q) const { return min(clo1 + (q >> 1), chi1); }
 };
 
+// Bodies of the node-parallel kernels take the block index `bid` and the
+// block count `nblk` of their problem (blockIdx.x / gridDim.x of a single
+// problem, or the block's index and its instance's block count in a grouped
+// launch).
 template <int PX>
-__global__ void __launch_bounds__(kBig) k_restrict_dense(Geo g, int delta, PcgState* __restrict__ st,
-                                                         XrArgs xr, Red rr, double* __restrict__ r,
-                                                         DenseArgs da) {
+__device__ __forceinline__ void restrict_dense_body(const Geo& g, int delta,
+                                                    PcgState* __restrict__ st, const XrArgs& xr,
+                                                    const Red& rr, double* __restrict__ r,
+                                                    const DenseArgs& da, int bid, int nblk) {
   if (st != nullptr && st->done) return;
   double alpha = 0.0;
   if (xr.on) {
     const double gamma = sum_partials<kBig>(xr.gam.part, xr.gam.np);
     if (!(gamma > 0.0)) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (bid == 0 && threadIdx.x == 0) {
         st->done = 2;
         st->iters = xr.k - 1;
       }
@@ -221,7 +226,7 @@ __global__ void __launch_bounds__(kBig) k_restrict_dense(Geo g, int delta, PcgSt
   const long items = (long)segs * N1 * g.N[2];
   const int sub = threadIdx.x / kBlock, tx = threadIdx.x % kBlock;
   double acc = 0.0;
-  for (long grp = blockIdx.x; grp * (kBig / kBlock) < items; grp += gridDim.x) {
+  for (long grp = bid; grp * (kBig / kBlock) < items; grp += nblk) {
     const long it = grp * (kBig / kBlock) + sub;
     if (it >= items) continue;
     const int line = (int)(it / segs);
@@ -249,23 +254,32 @@ __global__ void __launch_bounds__(kBig) k_restrict_dense(Geo g, int delta, PcgSt
       if (da.Rl != nullptr) da.Rl[at] = lo;
     }
   }
-  if (xr.on) write_partial<kBig>(acc, rr.part);
+  if (xr.on) write_partial_at<kBig>(acc, rr.part, bid);
+}
+
+template <int PX>
+__global__ void __launch_bounds__(kBig) k_restrict_dense(Geo g, int delta, PcgState* __restrict__ st,
+                                                         XrArgs xr, Red rr, double* __restrict__ r,
+                                                         DenseArgs da) {
+  restrict_dense_body<PX>(g, delta, st, xr, rr, r, da, blockIdx.x, gridDim.x);
 }
 
 // z = sum_c R_c^T y_c + psi_ext cf (cf from k_coarse_field when coarse != 0).
 template <int PX, int KS>
-__global__ void __launch_bounds__(kBig) k_extend_dense(Geo g, int delta, int coarse,
-                                                       PcgState* __restrict__ st, CheckArgs chk,
-                                                       DenseArgs da, const double* __restrict__ psi,
-                                                       const double* __restrict__ cf,
-                                                       const double* __restrict__ r,
-                                                       double* __restrict__ z, int use_dot, Red dot) {
+__device__ __forceinline__ void extend_dense_body(const Geo& g, int delta, int coarse,
+                                                  PcgState* __restrict__ st, const CheckArgs& chk,
+                                                  const DenseArgs& da,
+                                                  const double* __restrict__ psi,
+                                                  const double* __restrict__ cf,
+                                                  const double* __restrict__ r,
+                                                  double* __restrict__ z, int use_dot,
+                                                  const Red& dot, int bid, int nblk) {
   constexpr int NC = Cover<PX>::NC;
   if (st != nullptr && st->done) return;
   if (chk.on) {
     const double rn2 = sum_partials<kBig>(chk.rr.part, chk.rr.np);
     const bool conv = rn2 <= st->tol2, last = chk.k >= chk.maxit;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
       st->relres = sqrt(rn2 / st->r0n2);
       if (chk.hist && chk.k < chk.hist_cap) chk.hist[chk.k] = st->relres;
       st->iters = chk.k;
@@ -279,7 +293,7 @@ __global__ void __launch_bounds__(kBig) k_extend_dense(Geo g, int delta, int coa
   const int segs = (N0 + kBlock - 1) / kBlock;
   const long items = (long)segs * N1 * g.N[2];
   const int sub = threadIdx.x / kBlock, tx = threadIdx.x % kBlock;
-  for (long grp = blockIdx.x; grp * (kBig / kBlock) < items; grp += gridDim.x) {
+  for (long grp = bid; grp * (kBig / kBlock) < items; grp += nblk) {
     const long it = grp * (kBig / kBlock) + sub;
     if (it >= items) continue;
     const int line = (int)(it / segs);
@@ -319,12 +333,23 @@ __global__ void __launch_bounds__(kBig) k_extend_dense(Geo g, int delta, int coa
       for (int sp = 0; sp < KS; ++sp) zq += zs[q][sp];
       zl += (double)zq;
     }
-    double zv = zl;
-    if (coarse) zv += ps * zc;
+    // one rounding for the coarse term, whatever the compiler knows of `coarse`
+    const double zv = coarse ? fma(ps, zc, zl) : zl;
     z[k] = zv;
     acc += rk * zv;
   }
-  if (use_dot) write_partial<kBig>(acc, dot.part);
+  if (use_dot) write_partial_at<kBig>(acc, dot.part, bid);
+}
+
+template <int PX, int KS>
+__global__ void __launch_bounds__(kBig) k_extend_dense(Geo g, int delta, int coarse,
+                                                       PcgState* __restrict__ st, CheckArgs chk,
+                                                       DenseArgs da, const double* __restrict__ psi,
+                                                       const double* __restrict__ cf,
+                                                       const double* __restrict__ r,
+                                                       double* __restrict__ z, int use_dot, Red dot) {
+  extend_dense_body<PX, KS>(g, delta, coarse, st, chk, da, psi, cf, r, z, use_dot, dot, blockIdx.x,
+                            gridDim.x);
 }
 
 DenseArgs dense_args(const ddeig_problem* P) {
@@ -363,13 +388,13 @@ void launch_restrict(const ddeig_problem* P, double* r, PcgState* st, const XrAr
 // (natural order; the grid line from a multiply-high division), 8 at a time
 // with all 16 loads issued before the products; the products are added in q
 // order, then the threads in a fixed order.
-__global__ void __launch_bounds__(kBlock) k_coarse_rhs(Geo g, const PcgState* __restrict__ st,
-                                                       const double* __restrict__ r,
-                                                       const TypeDev* __restrict__ types,
-                                                       const SubDev* __restrict__ subs,
-                                                       double* __restrict__ crhs) {
+__device__ __forceinline__ void coarse_rhs_body(const Geo& g, const PcgState* __restrict__ st,
+                                                const double* __restrict__ r,
+                                                const TypeDev* __restrict__ types,
+                                                const SubDev* __restrict__ subs,
+                                                double* __restrict__ crhs, int bid) {
   if (st != nullptr && st->done) return;
-  const SubDev sd = subs[blockIdx.x];
+  const SubDev sd = subs[bid];
   const TypeDev td = types[sd.type];
   const int m0 = td.m[0], m1 = td.m[1];
   const int mtot = m0 * m1 * td.m[2];
@@ -393,7 +418,15 @@ __global__ void __launch_bounds__(kBlock) k_coarse_rhs(Geo g, const PcgState* __
     for (int q = 0; q < U; ++q) acc += ph[q] * rv[q];
   }
   const double sum = block_sum(acc);
-  if (threadIdx.x == 0) crhs[blockIdx.x] = sum;
+  if (threadIdx.x == 0) crhs[bid] = sum;
+}
+
+__global__ void __launch_bounds__(kBlock) k_coarse_rhs(Geo g, const PcgState* __restrict__ st,
+                                                       const double* __restrict__ r,
+                                                       const TypeDev* __restrict__ types,
+                                                       const SubDev* __restrict__ subs,
+                                                       double* __restrict__ crhs) {
+  coarse_rhs_body(g, st, r, types, subs, crhs, blockIdx.x);
 }
 
 void launch_coarse_rhs(const ddeig_problem* P, const double* r, const PcgState* st,
@@ -432,17 +465,24 @@ void launch_coarse_phi(const ddeig_problem* P, hipStream_t s) {
 
 // y0 = A0^{-1} c with the dense symmetric inverse: one wave64 per row, lanes
 // stride the row (coalesced), fixed-order shuffle reduction.
-__global__ void k_coarse_solve(int N, const PcgState* __restrict__ st,
-                               const double* __restrict__ A0inv, const double* __restrict__ c,
-                               double* __restrict__ y) {
+__device__ __forceinline__ void coarse_solve_body(int N, const PcgState* __restrict__ st,
+                                                  const double* __restrict__ A0inv,
+                                                  const double* __restrict__ c,
+                                                  double* __restrict__ y, int bid) {
   if (st != nullptr && st->done) return;
   const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int row = bid * (kBlock / 64) + (threadIdx.x >> 6);
   if (row >= N) return;
   double acc = 0.0;
   for (int j = lane; j < N; j += 64) acc += A0inv[(long)row * N + j] * c[j];
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) y[row] = acc;
+}
+
+__global__ void k_coarse_solve(int N, const PcgState* __restrict__ st,
+                               const double* __restrict__ A0inv, const double* __restrict__ c,
+                               double* __restrict__ y) {
+  coarse_solve_body(N, st, A0inv, c, y, blockIdx.x);
 }
 
 void launch_coarse_solve(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
@@ -457,14 +497,17 @@ void launch_coarse_solve(const ddeig_problem* P, const PcgState* st, hipStream_t
 // forms that sum once per expanding-index point (i0, or (i0, i1) for two
 // expanding axes), cells in slot order, so the extension reads one value.
 template <int PX>
-__global__ void k_coarse_field(Geo g, int delta, int pu, const PcgState* __restrict__ st,
-                               const XCover* __restrict__ xc0, const XCover* __restrict__ xc1,
-                               const double* __restrict__ y0, double* __restrict__ cf) {
+__device__ __forceinline__ void coarse_field_body(const Geo& g, int delta, int pu,
+                                                  const PcgState* __restrict__ st,
+                                                  const XCover* __restrict__ xc0,
+                                                  const XCover* __restrict__ xc1,
+                                                  const double* __restrict__ y0,
+                                                  double* __restrict__ cf, int bid, int nblk) {
   if (st != nullptr && st->done) return;
   const XCover* xc[2] = {xc0, xc1};
   const long npts = PX == 1 ? (long)g.N[0] : (long)g.N[0] * g.N[1];
-  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < npts;
-       idx += (long)gridDim.x * blockDim.x) {
+  for (long idx = bid * (long)blockDim.x + threadIdx.x; idx < npts;
+       idx += (long)nblk * blockDim.x) {
     const int i[3] = {(int)(idx % g.N[0]), PX == 2 ? (int)(idx / g.N[0]) : 0, 0};
     const Cover<PX> cv(g, delta, i);
     double zc = 0.0;
@@ -477,6 +520,13 @@ __global__ void k_coarse_field(Geo g, int delta, int pu, const PcgState* __restr
     }
     cf[idx] = zc;
   }
+}
+
+template <int PX>
+__global__ void k_coarse_field(Geo g, int delta, int pu, const PcgState* __restrict__ st,
+                               const XCover* __restrict__ xc0, const XCover* __restrict__ xc1,
+                               const double* __restrict__ y0, double* __restrict__ cf) {
+  coarse_field_body<PX>(g, delta, pu, st, xc0, xc1, y0, cf, blockIdx.x, gridDim.x);
 }
 
 void launch_coarse_field(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
@@ -680,6 +730,90 @@ void build_coarse_matrix(ddeig_problem* P, double* A0, hipStream_t s) {
   hipLaunchKernelGGL(k_coarse_matrix, dim3(N, nnb), dim3(kBlock), 0, s, P->g, P->delta,
                      P->opt.pu, P->tabAs, P->dTypes, P->dSubs, P->psi, A0);
   launch_symmetrise(A0, N, s);
+}
+
+int coarse_field_grid(const Geo& g) {
+  const long npts = g.p == 1 ? (long)g.N[0] : (long)g.N[0] * g.N[1];
+  return (int)std::max<long>(1, std::min<long>((npts + kBlock - 1) / kBlock, 4096));
+}
+
+// Grouped kernels of PCG iteration k over the instances of a batch (2-D,
+// one expanding axis, dense local solves): block b runs block map[b].y of
+// instance map[b].x with that instance's operands, CG state and partials.
+__global__ void __launch_bounds__(kBig) k_b_restrict(const InstDev* __restrict__ I,
+                                                     const int2* __restrict__ map, int k) {
+  const int2 m = map[blockIdx.x];
+  const InstDev& d = I[m.x];
+  const XrArgs xr{1, k, d.gam, d.x, d.pp[k & 1], d.q};
+  restrict_dense_body<1>(d.g, d.delta, d.st, xr, d.rr, d.r, d.da, m.y, d.nb_node);
+}
+
+template <int KS>
+__global__ void __launch_bounds__(kBig) k_b_extend(const InstDev* __restrict__ I,
+                                                   const int2* __restrict__ map, int k, int maxit) {
+  const int2 m = map[blockIdx.x];
+  const InstDev& d = I[m.x];
+  const CheckArgs chk{1, k, maxit, d.hist_cap, d.rr, d.hist};
+  extend_dense_body<1, KS>(d.g, d.delta, 1, d.st, chk, d.da, d.psi, d.cf, d.r, d.z, 1, d.rz, m.y,
+                           d.nb_node);
+}
+
+__global__ void __launch_bounds__(kBlock) k_b_coarse_rhs(const InstDev* __restrict__ I,
+                                                         const int2* __restrict__ map) {
+  const int2 m = map[blockIdx.x];
+  const InstDev& d = I[m.x];
+  coarse_rhs_body(d.g, d.st, d.r, d.types, d.subs, d.crhs, m.y);
+}
+
+__global__ void k_b_coarse_solve(const InstDev* __restrict__ I, const int2* __restrict__ map) {
+  const int2 m = map[blockIdx.x];
+  const InstDev& d = I[m.x];
+  coarse_solve_body(d.nsub, d.st, d.A0inv, d.crhs, d.cy, m.y);
+}
+
+__global__ void k_b_coarse_field(const InstDev* __restrict__ I, const int2* __restrict__ map) {
+  const int2 m = map[blockIdx.x];
+  const InstDev& d = I[m.x];
+  coarse_field_body<1>(d.g, d.delta, d.pu, d.st, d.xc0, nullptr, d.cy, d.cf, m.y, d.nb_cf);
+}
+
+// Copies every instance's CG state into out[] (the host reads them with one
+// copy); with mark_done the states are first set to finished (5), so that an
+// instance whose solve is not started stays idle in the grouped kernels.
+__global__ void k_b_states(const InstDev* __restrict__ I, int n, PcgState* __restrict__ out,
+                           int mark_done) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    PcgState* st = I[j].st;
+    if (mark_done) st->done = 5;
+    out[j] = *st;
+  }
+}
+
+void launch_b_restrict(const InstDev* I, const BlockMap& bm, int k, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_restrict, dim3(bm.nblocks), dim3(kBig), 0, s, I, bm.map, k);
+}
+
+void launch_b_extend(const InstDev* I, const BlockMap& bm, int k, int maxit, int ksplit,
+                     hipStream_t s) {
+  auto kern = ksplit == 1 ? k_b_extend<1> : (ksplit == 2 ? k_b_extend<2> : k_b_extend<3>);
+  hipLaunchKernelGGL(kern, dim3(bm.nblocks), dim3(kBig), 0, s, I, bm.map, k, maxit);
+}
+
+void launch_b_coarse_rhs(const InstDev* I, const BlockMap& bm, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_coarse_rhs, dim3(bm.nblocks), dim3(kBlock), 0, s, I, bm.map);
+}
+
+void launch_b_coarse_solve(const InstDev* I, const BlockMap& bm, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_coarse_solve, dim3(bm.nblocks), dim3(kBlock), 0, s, I, bm.map);
+}
+
+void launch_b_coarse_field(const InstDev* I, const BlockMap& bm, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_coarse_field, dim3(bm.nblocks), dim3(kBlock), 0, s, I, bm.map);
+}
+
+void launch_b_states(const InstDev* I, int n, PcgState* out, int mark_done, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_states, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, I, n, out,
+                     mark_done);
 }
 
 }  // namespace ddeig

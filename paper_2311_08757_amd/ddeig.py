@@ -59,7 +59,9 @@ class EigInfo(ctypes.Structure):
 
 EXPORTS = ["ddeig_assemble", "ddeig_cell_shift", "ddeig_set_shift", "ddeig_apply_op",
            "ddeig_apply_precond", "ddeig_pcg_solve", "ddeig_inverse_iteration",
-           "ddeig_profile_kernel", "ddeig_potential_form", "ddeig_query", "ddeig_destroy", "ddeig_status_string",
+           "ddeig_profile_kernel", "ddeig_potential_form", "ddeig_batch_create",
+           "ddeig_batch_query", "ddeig_batch_pcg_solve", "ddeig_batch_inverse_iteration",
+           "ddeig_batch_destroy", "ddeig_query", "ddeig_destroy", "ddeig_status_string",
            "ddeig_last_error"]
 
 _lib = None
@@ -88,6 +90,17 @@ def load_library(path=LIB_PATH):
                                             ctypes.c_int, ctypes.POINTER(EigInfo)]
     lib.ddeig_profile_kernel.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, dp, dp]
     lib.ddeig_potential_form.argtypes = [P, ctypes.c_int, ctypes.POINTER(Potential), P, P, dp]
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    lib.ddeig_batch_create.argtypes = [PP, ctypes.c_int, ctypes.c_int, PP]
+    lib.ddeig_batch_query.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_int), dp]
+    lib.ddeig_batch_pcg_solve.argtypes = [P, PP, PP, ctypes.c_double, ctypes.c_int,
+                                          ctypes.POINTER(PcgInfo)]
+    lib.ddeig_batch_inverse_iteration.argtypes = [P, PP, ctypes.c_double, ctypes.c_int,
+                                                  ctypes.c_double, ctypes.c_int,
+                                                  ctypes.POINTER(EigInfo)]
+    lib.ddeig_batch_destroy.argtypes = [P]
+    lib.ddeig_batch_destroy.restype = None
     lib.ddeig_query.argtypes = [P, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long),
                                 ctypes.POINTER(ctypes.c_int)]
     lib.ddeig_destroy.argtypes = [P]
@@ -97,7 +110,8 @@ def load_library(path=LIB_PATH):
     lib.ddeig_last_error.argtypes = []
     lib.ddeig_last_error.restype = ctypes.c_char_p
     for f in EXPORTS:
-        if f not in ("ddeig_destroy", "ddeig_status_string", "ddeig_last_error"):
+        if f not in ("ddeig_destroy", "ddeig_batch_destroy", "ddeig_status_string",
+                     "ddeig_last_error"):
             getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -319,3 +333,80 @@ def potential_form(prob, W, x, y, space="global"):
     del keep
     _check(st, "ddeig_potential_form")
     return out.value
+
+
+class Batch:
+    """Owns a ddeig_batch handle; keeps its problems alive while it exists."""
+
+    def __init__(self, handle, probs):
+        self.handle = handle
+        self.probs = list(probs)
+
+    def __len__(self):
+        return len(self.probs)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        self.handle = None
+        if h and _lib is not None:
+            try:
+                _lib.ddeig_batch_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
+
+
+def _ptr_array(ts, ns, name):
+    arr = (ctypes.c_void_p * len(ts))()
+    for j, (t, n) in enumerate(zip(ts, ns)):
+        arr[j] = _ptr(t, n, f"{name}[{j}]").value
+    return arr
+
+
+def batch_create(probs, graphs=True):
+    """ddeig_batch_create over a list of Problems (runs the GEMM autotuner);
+    graphs: replay the grouped iterations from captured HIP graphs."""
+    lib = load_library()
+    arr = (ctypes.c_void_p * len(probs))(*[p.handle.value if isinstance(p.handle, ctypes.c_void_p)
+                                           else p.handle for p in probs])
+    h = ctypes.c_void_p()
+    _check(lib.ddeig_batch_create(arr, len(probs), 1 if graphs else 0, ctypes.byref(h)),
+           "ddeig_batch_create")
+    return Batch(h, probs)
+
+
+def batch_query(batch):
+    lib = load_library()
+    ks, order, nt = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    tune = (ctypes.c_double * 6)()
+    _check(lib.ddeig_batch_query(batch.handle, ctypes.byref(ks), ctypes.byref(order),
+                                 ctypes.byref(nt), tune), "ddeig_batch_query")
+    return dict(ksplit=ks.value, order=order.value, ntiles=nt.value, tune_us=list(tune))
+
+
+def batch_pcg_solve(batch, bs, xs, rtol=1e-10, maxit=1000, raise_on_error=True):
+    """ddeig_batch_pcg_solve; returns (status, [dict(iters, relres, breakdown)])."""
+    lib = load_library()
+    ns = [p.n_dof for p in batch.probs]
+    info = (PcgInfo * len(ns))()
+    st = lib.ddeig_batch_pcg_solve(batch.handle, _ptr_array(bs, ns, "b"), _ptr_array(xs, ns, "x"),
+                                   float(rtol), int(maxit), info)
+    if raise_on_error and st != DDEIG_OK:
+        _check(st, "ddeig_batch_pcg_solve")
+    return STATUS.get(st, st), [dict(iters=i.iters, relres=i.relres, breakdown=i.breakdown)
+                                for i in info]
+
+
+def batch_inverse_iteration(batch, xs, tol_x=1e-9, maxit_outer=100, rtol_inner=1e-10,
+                            maxit_inner=1000, raise_on_error=True):
+    """ddeig_batch_inverse_iteration; returns (status, [dict per instance])."""
+    lib = load_library()
+    ns = [p.n_dof for p in batch.probs]
+    info = (EigInfo * len(ns))()
+    st = lib.ddeig_batch_inverse_iteration(batch.handle, _ptr_array(xs, ns, "x"), float(tol_x),
+                                           int(maxit_outer), float(rtol_inner), int(maxit_inner),
+                                           info)
+    if raise_on_error and st != DDEIG_OK:
+        _check(st, "ddeig_batch_inverse_iteration")
+    return STATUS.get(st, st), [dict(lam=i.lambda_, dx_M=i.dx_M, outer_its=i.outer_its,
+                                     inner_sum=i.inner_sum, inner_max=i.inner_max,
+                                     t_solve_ms=i.t_solve_ms) for i in info]

@@ -4,7 +4,9 @@ Calls only the oracle (plain FP64 CPU): for each configuration the shift
 sigma (cell problem), the smallest eigenpair by sigma-shifted inverse
 iteration with exact solves to ||x_{k+1} - x_k||_M <= 1e-13, the second
 eigenvalue (for the contraction rate), and the eigenvector at seeded sample
-nodes.  Usage:  python tests/golden/make_golden.py 1 2 [3 4]
+nodes.  "batch" writes the same for every instance of the batched 2-D
+workload (oracle_batch.json, 32 sample nodes per instance).
+Usage:  python tests/golden/make_golden.py 1 2 [3 4] [batch]
 """
 import json
 import os
@@ -23,8 +25,8 @@ from oracle.cell import cell_problem  # noqa: E402
 from oracle.ipm import inverse_iteration_direct, spectral_residual  # noqa: E402
 
 
-def golden(c, nsample=256):
-    cfg = W.config(c)
+def golden(c, nsample=256, cfg=None):
+    cfg = W.config(c) if cfg is None else cfg
     t0 = time.time()
     p, q, L, ne = cfg["p"], cfg["q"], cfg["L"], cfg["ne"]
     cell = cell_problem(p, q, ne, cfg["V"], route="kron")
@@ -44,8 +46,21 @@ def golden(c, nsample=256):
     return out
 
 
+def golden_batch(nsample=32):
+    out = []
+    for j, cfg in enumerate(W.batch_config()):
+        d = golden(100 + j, nsample=nsample, cfg=cfg)
+        d["instance"], d["L"] = j, cfg["L"]
+        out.append(d)
+        print("batch", j, cfg["L"], d["lam"], d["outer_its"], f"{d['seconds']:.1f}s", flush=True)
+    return out
+
+
 if __name__ == "__main__":
     for arg in sys.argv[1:]:
+        if arg == "batch":
+            json.dump(golden_batch(), open(os.path.join(HERE, "oracle_batch.json"), "w"), indent=1)
+            continue
         c = int(arg)
         d = golden(c)
         path = os.path.join(HERE, f"oracle_config{c}.json")

@@ -1,0 +1,140 @@
+"""GPU parity of the batched path (ddeig_batch_*): one grouped launch per
+kernel of a PCG iteration over independent instances.
+
+- small instances (n_e = 8): when the autotuner keeps the K split of the
+  single-problem path, each instance's PCG iterate and iteration count from
+  the batch equal those of its own ddeig_pcg_solve bit for bit (the grouped
+  kernels run the same bodies on the same operands in the same order);
+  otherwise only the FP32 order of the split-K sums differs, and the iterates
+  agree to 1e-8 relative with iteration counts within 2;
+- batched inverse iteration against the oracle: lambda to 1e-10 relative and
+  ||x - x_ref||_M <= 1e-8 (the single-problem bar);
+- all 64 instances of the batched workload (2-D, L_j uniform in 16..256,
+  n_e = 32, delta = 2, bf16 local solves): lambda_j to 1e-10 relative and 32
+  sampled eigenvector entries to 1e-8 against tests/golden/oracle_batch.json
+  (written by make_golden.py from the oracle alone);
+- argument errors of ddeig_batch_create.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+SMALL = [(5, 51), (7, 52), (12, 53), (6, 54), (9, 55)]   # (L, potential seed), n_e = 8, delta = 2
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+def _dev(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _small_probs(prec):
+    import paper_2311_08757_amd as dd
+    probs = []
+    for L, seed in SMALL:
+        prob = dd.assemble(1, 1, L, 8, W.sep_fourier(seed), 2, local_prec=prec)
+        dd.cell_shift(prob)
+        probs.append(prob)
+    return probs
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+def test_batch_pcg_bitwise_equals_single(torch, prec, graphs):
+    import paper_2311_08757_amd as dd
+    probs = _small_probs(prec)
+    bs = [_dev(torch, W.random_vector(p.n_dof, 60 + j)) for j, p in enumerate(probs)]
+    single = []
+    for p, b in zip(probs, bs):
+        x = torch.zeros_like(b)
+        out = dd.pcg_solve(p, b, x, rtol=1e-10, maxit=500)
+        single.append((x, out["iters"]))
+    batch = dd.batch_create(probs, graphs=graphs)
+    q = dd.batch_query(batch)
+    # the unclipped box has 11 x 7 = 77 unknowns (ld = 128); the single path
+    # splits K into min(3, ld / BK / 2) parts, BK = 64 (bf16) or 32 (bf16x3)
+    ks_single = min(3, 128 // (64 if prec == "bf16" else 32) // 2)
+    assert 1 <= q["ksplit"] <= ks_single and q["ntiles"] == len(SMALL) * q["ksplit"]
+    xs = [torch.zeros_like(b) for b in bs]
+    st, info = dd.batch_pcg_solve(batch, bs, xs, rtol=1e-10, maxit=500)
+    assert st == "OK"
+    # a second solve replays the captured graphs (or relaunches) and repeats the bits
+    xs2 = [torch.zeros_like(b) for b in bs]
+    st2, info2 = dd.batch_pcg_solve(batch, bs, xs2, rtol=1e-10, maxit=500)
+    assert st2 == "OK" and [i["iters"] for i in info2] == [i["iters"] for i in info]
+    assert all(torch.equal(a, b) for a, b in zip(xs, xs2))
+    for j, ((x1, it1), x2) in enumerate(zip(single, xs)):
+        assert info[j]["relres"] <= 1e-10
+        if q["ksplit"] == ks_single:
+            assert info[j]["iters"] == it1, j
+            assert torch.equal(x1, x2), j
+        else:
+            assert abs(info[j]["iters"] - it1) <= 2, j
+            assert float((x1 - x2).abs().max()) <= 1e-8 * float(x1.abs().max()), j
+
+
+def test_batch_inverse_iteration_small(torch):
+    import paper_2311_08757_amd as dd
+    from oracle.problem import Problem
+    from oracle.ipm import inverse_iteration_direct
+    probs = _small_probs("bf16")
+    batch = dd.batch_create(probs)
+    xs = [torch.zeros(p.n_dof, dtype=torch.float64, device="cuda") for p in probs]
+    st, info = dd.batch_inverse_iteration(batch, xs, tol_x=1e-11, rtol_inner=1e-11,
+                                          maxit_inner=1000)
+    assert st == "OK"
+    for j, (L, seed) in enumerate(SMALL):
+        P = Problem(W.small_config(1, 1, L, 8, 2, W.sep_fourier(seed)))
+        ref = inverse_iteration_direct(P.A, P.M, P.sigma, P.grid, tol=1e-13, maxit=300)
+        assert abs(info[j]["lam"] - ref["lam"]) <= 1e-10 * abs(ref["lam"]), j
+        d = xs[j].cpu().numpy() - ref["x"]
+        assert np.sqrt(d @ (P.M @ d)) <= 1e-8, j
+
+
+def test_batch_create_errors(torch):
+    import paper_2311_08757_amd as dd
+    p8 = dd.assemble(1, 1, 6, 8, W.sep_fourier(1), 2, local_prec="bf16")
+    p_fp64 = dd.assemble(1, 1, 6, 8, W.sep_fourier(2), 2, local_prec="fp64")
+    p_ne16 = dd.assemble(1, 1, 6, 16, W.sep_fourier(3), 2, local_prec="bf16")
+    p_small = dd.assemble(1, 1, 3, 8, W.sep_fourier(4), 2, local_prec="bf16")
+    p_3d = dd.assemble(1, 2, 6, 4, W.sep_fourier(5), 1, local_prec="bf16")
+    for bad in ([p8, p_fp64], [p8, p_ne16], [p_small], [p_3d], [p8, p8], []):
+        with pytest.raises(dd.DdeigError):
+            dd.batch_create(bad)
+
+
+@pytest.mark.timeout(900)
+def test_batch_workload_eigenpairs(torch):
+    """The 64-instance batched workload in one batch (bf16 local solves)."""
+    import paper_2311_08757_amd as dd
+    gold = json.load(open(os.path.join(HERE, "golden", "oracle_batch.json")))
+    inst = W.batch_config()
+    probs = []
+    for cfg in inst:
+        prob = dd.assemble(cfg["p"], cfg["q"], cfg["L"], cfg["ne"], cfg["V"], cfg["delta"],
+                           local_prec="bf16")
+        sigma, _ = dd.cell_shift(prob)
+        probs.append(prob)
+        assert abs(sigma - gold[len(probs) - 1]["sigma"]) <= 1e-12 * abs(sigma)
+    batch = dd.batch_create(probs)
+    xs = [torch.zeros(p.n_dof, dtype=torch.float64, device="cuda") for p in probs]
+    st, info = dd.batch_inverse_iteration(batch, xs, tol_x=1e-9, rtol_inner=1e-10,
+                                          maxit_inner=3000)
+    assert st == "OK"
+    for j, g in enumerate(gold):
+        assert abs(info[j]["lam"] - g["lam"]) <= 1e-10 * abs(g["lam"]), j
+        xj = xs[j].cpu().numpy()
+        assert np.max(np.abs(xj[g["sample_idx"]] - np.array(g["sample_x"]))) <= 1e-8, j
