@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--local-prec", default="bf16", choices=["fp64", "fp32", "bf16x3", "bf16"])
+    ap.add_argument("--graphs", type=int, default=1, choices=[0, 1],
+                    help="replay PCG iteration blocks from captured HIP graphs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison solve")
     ap.add_argument("--kernels-only", action="store_true",
@@ -157,7 +159,7 @@ def bench_batch(args):
                            local_prec=args.local_prec)
         dd.cell_shift(prob)
         probs.append(prob)
-    batch = dd.batch_create(probs)
+    batch = dd.batch_create(probs, graphs=bool(args.graphs))
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     tune = dd.batch_query(batch)
@@ -258,7 +260,7 @@ def main():
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
     prob = dd.assemble(cfg["p"], cfg["q"], cfg["L"], cfg["ne"], cfg["V"], cfg["delta"],
-                       local_prec=args.local_prec)
+                       local_prec=args.local_prec, graphs=bool(args.graphs))
     sigma, _ = dd.cell_shift(prob)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
@@ -346,7 +348,7 @@ def main():
     cmp = None
     if not args.no_compare and args.local_prec != "fp64":
         p64 = dd.assemble(cfg["p"], cfg["q"], cfg["L"], cfg["ne"], cfg["V"], cfg["delta"],
-                          local_prec="fp64")
+                          local_prec="fp64", graphs=bool(args.graphs))
         dd.cell_shift(p64)
         x.zero_()
         dd.inverse_iteration(p64, x, tol_x=1e-9, rtol_inner=1e-10, maxit_inner=2000)
@@ -389,6 +391,7 @@ def main():
         "config": {"workload": cfg["name"], "p": cfg["p"], "q": cfg["q"], "L": cfg["L"],
                    "h": f"1/{cfg['ne']}", "overlap": cfg["delta"], "n_dof": n,
                    "subdomains": prob.n_sub, "local_prec": args.local_prec,
+                   "hip_graphs": bool(args.graphs),
                    "time_to_eigenpair_ms": T / max(args.steps, 1) * 1e3, "setup_s": t_setup,
                    "outer_its": outers[-1] if outers else None,
                    "pcg_iters_per_solve": inner / max(args.steps, 1),

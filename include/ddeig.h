@@ -103,6 +103,9 @@ typedef struct {
                       (bf16x3, FP32 accumulation), 3 dense inverses in bf16 (two MFMA
                       products, FP32 accumulation); the outer CG is FP64 in every case */
   int batch_iters; /* PCG iterations queued between host convergence checks (0: default 8) */
+  int graphs;      /* 1: each block of batch_iters PCG iterations is captured once into a HIP
+                      graph (per first iteration, maxit and iterate pointer) on a stream of the
+                      problem and replayed from then on; 0: kernels are launched one by one */
 } ddeig_options;
 
 typedef struct ddeig_problem ddeig_problem;

@@ -183,20 +183,22 @@ ddeig_status finish_shift(ddeig_problem* P) {
 // restriction (partials of ||r||^2 into *rr); chk (nullable) folds the PCG
 // stopping test into the extension.
 void precond_apply(ddeig_problem* P, double* r, double* z, Red* dot, PcgState* st,
-                   const XrArgs* xr = nullptr, Red* rr = nullptr, const CheckArgs* chk = nullptr) {
+                   const XrArgs* xr = nullptr, Red* rr = nullptr, const CheckArgs* chk = nullptr,
+                   hipStream_t ms = nullptr) {
+  const hipStream_t s = ms ? ms : P->stream;
   const int coarse = P->opt.coarse;
   XrArgs xoff{};
   xoff.on = 0;
   CheckArgs coff{};
   coff.on = 0;
-  launch_restrict(P, r, st, xr ? *xr : xoff, rr, P->stream);
+  launch_restrict(P, r, st, xr ? *xr : xoff, rr, s);
   const bool side = coarse;
   if (side) {
-    check_hip(hipEventRecord(P->ev_fork, P->stream), "record fork");
+    check_hip(hipEventRecord(P->ev_fork, s), "record fork");
     check_hip(hipStreamWaitEvent(P->aux, P->ev_fork, 0), "wait fork");
   }
-  launch_local_solves(P, st, P->stream);
-  if (P->opt.local_prec >= 2) launch_embed_fix(P, st, P->stream);
+  launch_local_solves(P, st, s);
+  if (P->opt.local_prec >= 2) launch_embed_fix(P, st, s);
   if (coarse) {
     launch_coarse_rhs(P, r, st, P->aux);
     launch_coarse_solve(P, st, P->aux);
@@ -204,12 +206,12 @@ void precond_apply(ddeig_problem* P, double* r, double* z, Red* dot, PcgState* s
   }
   if (side) {
     check_hip(hipEventRecord(P->ev_join, P->aux), "record join");
-    check_hip(hipStreamWaitEvent(P->stream, P->ev_join, 0), "wait join");
+    check_hip(hipStreamWaitEvent(s, P->ev_join, 0), "wait join");
   }
 
   CheckArgs c = chk ? *chk : coff;
   if (chk && rr) c.rr = *rr;
-  launch_extend(P, r, z, coarse, dot, st, c, P->stream);
+  launch_extend(P, r, z, coarse, dot, st, c, s);
 }
 
 struct PcgOut {
@@ -238,18 +240,50 @@ PcgOut pcg_run(ddeig_problem* P, const double* b, double* x, double rtol, int ma
     check_hip(hipMemcpyAsync(&hs, P->st, sizeof(PcgState), hipMemcpyDeviceToHost, s), "state");
     sync(P);
   }
+  // iteration k on stream ms
+  auto iteration = [&](int kk, hipStream_t ms) {
+    double* pold = P->pp[(kk - 1) & 1];
+    double* pnew = P->pp[kk & 1];
+    const DirArgs dir{P->st, kk, rz};
+    launch_stencil_dir(P, P->z, pold, pnew, P->q, dir, g, ms);
+    const XrArgs xr{1, kk, g, x, pnew, P->q};
+    const CheckArgs chk{1, kk, maxit, P->hist_cap, rr, P->hist};
+    precond_apply(P, P->r, P->z, &rz, P->st, &xr, &rr, &chk, ms);
+  };
   while (k < maxit) {
-    const int kend = std::min(maxit, k + batch);
-    for (++k; k <= kend; ++k) {
-      double* pold = P->pp[(k - 1) & 1];
-      double* pnew = P->pp[k & 1];
-      const DirArgs dir{P->st, k, rz};
-      launch_stencil_dir(P, P->z, pold, pnew, P->q, dir, g, s);
-      const XrArgs xr{1, k, g, x, pnew, P->q};
-      const CheckArgs chk{1, k, maxit, P->hist_cap, rr, P->hist};
-      precond_apply(P, P->r, P->z, &rz, P->st, &xr, &rr, &chk);
+    const int k0 = k + 1, kend = std::min(maxit, k + batch);
+    if (P->opt.graphs) {
+      // the block of iterations k0..kend, captured once per (k0, kend, maxit, x)
+      // on the problem's own capture stream and replayed on the library stream
+      const auto key = std::make_tuple(k0, kend, maxit, (const void*)x);
+      auto it = P->graphs.find(key);
+      if (it == P->graphs.end()) {
+        if (P->graphs.size() >= 1024) {
+          for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+          P->graphs.clear();
+        }
+        hipGraph_t gr = nullptr;
+        hipGraphExec_t ge = nullptr;
+        check_hip(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+        try {
+          for (int kk = k0; kk <= kend; ++kk) iteration(kk, P->cap);
+        } catch (...) {
+          (void)hipStreamEndCapture(P->cap, &gr);
+          if (gr) (void)hipGraphDestroy(gr);
+          throw;
+        }
+        check_hip(hipStreamEndCapture(P->cap, &gr), "end capture");
+        const hipError_t e = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        check_hip(e, "instantiate graph");
+        it = P->graphs.emplace(key, ge).first;
+      }
+      check_hip(hipGraphLaunch(it->second, s), "launch graph");
+      k = kend;
+    } else {
+      for (k = k0; k <= kend; ++k) iteration(k, s);
+      --k;
     }
-    --k;
     check_launch("pcg iteration");
     check_hip(hipMemcpyAsync(&hs, P->st, sizeof(PcgState), hipMemcpyDeviceToHost, s), "state");
     sync(P);
@@ -377,7 +411,7 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
   ddeig_options o{0, 1, 0, 8};
   if (opts) o = *opts;
   if (o.pu < 0 || o.pu > 1 || o.coarse < 0 || o.coarse > 1 || o.local_prec < 0 ||
-      o.local_prec > 3 || o.batch_iters < 0)
+      o.local_prec > 3 || o.batch_iters < 0 || o.graphs < 0 || o.graphs > 1)
     return set_error(DDEIG_EINVAL, "invalid options");
 
   ddeig::VSpec vs{};
@@ -763,6 +797,8 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
     P->scal = dalloc<double>(P, 8);
     P->flag = dalloc<int>(P, 1);
     check_hip(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking), "create stream");
+    if (o.graphs)
+      check_hip(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking), "create capture stream");
     check_hip(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming), "create event");
     check_hip(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming), "create event");
     P->gjbuf = dalloc<double>(P, 4 * (size_t)gjmax);
@@ -831,6 +867,8 @@ void ddeig_destroy(ddeig_problem* P) {
   if (!P) return;
   if (P->stream) (void)hipStreamSynchronize(P->stream);
   else (void)hipDeviceSynchronize();
+  for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (P->cap) (void)hipStreamDestroy(P->cap);
   if (P->aux) {
     (void)hipStreamSynchronize(P->aux);
     (void)hipStreamDestroy(P->aux);

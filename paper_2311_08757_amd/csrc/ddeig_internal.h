@@ -5,7 +5,9 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/ddeig.h"
@@ -266,6 +268,10 @@ struct ddeig_problem {
   // second stream (default priority) for work that overlaps the local solves
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // HIP-graph replay of PCG iteration blocks (options.graphs): the capture
+  // stream and one executable graph per (first, last iteration, maxit, x)
+  hipStream_t cap = nullptr;
+  std::map<std::tuple<int, int, int, const void*>, hipGraphExec_t> graphs;
   // operator tables, tap-major: tab[tap * tsize + tnode]
   double* tabK = nullptr;
   double* tabM = nullptr;

@@ -218,3 +218,30 @@ def test_reduced_precision_local_solves(torch, case, prec):
     assert abs(out["lam"] - ref["lam"]) <= 1e-10 * abs(ref["lam"])
     d = x.cpu().numpy() - ref["x"]
     assert np.sqrt(d @ (P.M @ d)) <= 1e-8
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_graph_replay_bitwise(torch, prec):
+    """PCG iteration blocks replayed from captured HIP graphs give the bits of
+    the launched kernels, on the first (capturing) solve and on later replays,
+    with eager work and host synchronisation in between; the inverse
+    iteration (graphs replayed across outer steps) too."""
+    import paper_2311_08757_amd as dd
+    case = CASES[0]
+    p, q, L, ne, delta, V = case
+    probs = [dd.assemble(p, q, L, ne, V, delta, local_prec=prec, graphs=g) for g in (False, True)]
+    for pr in probs:
+        dd.cell_shift(pr)
+    b = _dev(torch, W.random_vector(probs[0].n_dof, 7))
+    ref = torch.zeros_like(b)
+    o_ref = dd.pcg_solve(probs[0], b, ref, rtol=1e-11, maxit=500)
+    for rep in range(3):
+        x = torch.zeros_like(b)
+        o = dd.pcg_solve(probs[1], b, x, rtol=1e-11, maxit=500)
+        torch.cuda.synchronize()
+        assert o["iters"] == o_ref["iters"] and torch.equal(x, ref), rep
+        y = torch.empty_like(x)
+        dd.apply_op(probs[1], "A_sigma", x, y)   # eager work between replays
+    xs = [torch.zeros_like(b) for _ in probs]
+    outs = [dd.inverse_iteration(pr, xx, tol_x=1e-10, rtol_inner=1e-10) for pr, xx in zip(probs, xs)]
+    assert outs[0]["lam"] == outs[1]["lam"] and torch.equal(xs[0], xs[1])
