@@ -34,12 +34,13 @@ BF16_PEAK_TFLOPS = 2500.0
 # HBM bytes per launch of the dense local-solve GEMM on the 2-D L=256, h=1/64
 # workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs, each scaled by
 # what the counter read for a plain device copy of known size (FETCH x 2.0,
-# WRITE x 1.0).  Valid only for the kernel source they were taken from: when
-# that file changes the figure is reported as null until the counters are
-# taken again.
+# WRITE x 1.0).  Valid only for the kernel source they were taken from (the
+# text from the tile constants to the end of k_dense_gemm): when it changes the
+# figure is reported as null until the counters are taken again.
 COUNTED_TRAFFIC = {
     "source": "paper_2311_08757_amd/csrc/k_dense.hip",
-    "sha256": "4dfb012ec872575a86169abda7c93fc08017d20e0e098e727d90dee091d015cd",
+    "begin": "constexpr int kTM = 128", "end": "// Batches of at most kGemvMax rows",
+    "sha256": "862378a985bf46b8fb1b1176f956ed4f7edeb7bcafce3e3af10207b71b3d6b29",
     "workload": "2d-L256-ne64", "local_prec": "bf16",
     "fetch_kib": 28812.4, "fetch_factor": 2.0, "write_kib": 13440.0, "write_factor": 1.0,
 }
@@ -49,9 +50,11 @@ def counted_traffic(workload, local_prec):
     c = COUNTED_TRAFFIC
     if workload != c["workload"] or local_prec != c["local_prec"]:
         return None
-    with open(os.path.join(ROOT, c["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != c["sha256"]:
-            return None
+    with open(os.path.join(ROOT, c["source"])) as f:
+        src = f.read()
+    a, b = src.find(c["begin"]), src.find(c["end"])
+    if a < 0 or b < a or hashlib.sha256(src[a:b].encode()).hexdigest() != c["sha256"]:
+        return None
     return 1024.0 * (c["fetch_kib"] * c["fetch_factor"] + c["write_kib"] * c["write_factor"])
 
 

@@ -604,6 +604,20 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
           E.Z = H.Z;
           E.zsplit = (long)H.mp * H.ld;
           E.st = nullptr;
+          E.xonly = (T.off[1] == 0 && T.box.m[1] == hb.m[1] && T.off[2] == 0 &&
+                     T.box.m[2] == hb.m[2]) ? 1 : 0;
+          if (E.xonly) {
+            // the arithmetic T index must reproduce the list
+            const int nmiss = hb.m[0] - T.box.m[0];
+            for (int t = 0; t < nT; ++t) {
+              const int line = t / nmiss, j = t - line * nmiss;
+              const int u0 = j < T.off[0] ? j : j + T.box.m[0];
+              if (u0 + hb.m[0] * line != tl[t]) {
+                E.xonly = 0;
+                break;
+              }
+            }
+          }
           const int ci = (int)P->emb.size();
           P->emb.push_back(E);
           P->maxT = std::max(P->maxT, nT);

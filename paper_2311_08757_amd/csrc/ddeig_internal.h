@@ -134,6 +134,10 @@ struct EmbedDev {
   float* Z;         // the problem's split-K products Z[split][row][e]
   long zsplit;
   const PcgState* st;  // CG state checked by grouped launches (nullptr: the launch's own)
+  // 1 when the box is clipped along axis 0 only: T is then the columns u0
+  // outside [off[0], off[0] + m[0]) of every line, in natural order, and
+  // Tidx[t] = u0 + hm0 * line follows from t without a table look-up
+  int xonly;
 };
 // Batch operands of the dense-mode restriction / extension kernels.
 struct DenseArgs {

@@ -387,9 +387,12 @@ __global__ void __launch_bounds__(kBlock) k_embed_correct(const EmbedJob* __rest
                                                           const PcgState* __restrict__ st) {
   __shared__ float uT[kEmbChunk * kEmbMaxT];
   __shared__ float red[kEmbPh][kEmbE][kEmbChunk];
-  if (st != nullptr && st->done) return;
+  // the job, the state and the class are loaded before the state is tested,
+  // so that their latencies overlap
   const EmbedJob jb = jobs[blockIdx.x];
+  const int done0 = st != nullptr ? st->done : 0;
   const EmbedDev E = cls[jb.cls];
+  if (done0) return;
   if (E.st != nullptr && E.st->done) return;
   float* __restrict__ Z = E.Z;
   const long zsplit = E.zsplit;
@@ -416,9 +419,17 @@ __global__ void __launch_bounds__(kBlock) k_embed_correct(const EmbedJob* __rest
         }
     }
   }
+  const int nmiss = hm0 - E.m[0];
   for (int idx = threadIdx.x; idx < jb.nm * E.nT; idx += kBlock) {
     const int m = idx / E.nT, t = idx - m * E.nT;
-    const long base = (long)E.rows[jb.mem0 + m] * ld + E.Tidx[t];
+    int te;
+    if (E.xonly) {
+      const int line = t / nmiss, j = t - line * nmiss;
+      te = (j < E.off[0] ? j : j + E.m[0]) + hm0 * line;
+    } else {
+      te = E.Tidx[t];
+    }
+    const long base = (long)E.rows[jb.mem0 + m] * ld + te;
     float u = 0.0f;
 #pragma unroll
     for (int sp = 0; sp < KS; ++sp) u += Z[sp * zsplit + base];
