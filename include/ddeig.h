@@ -172,6 +172,34 @@ ddeig_status ddeig_pcg_solve(ddeig_problem* P, const double* b, double* x, doubl
 ddeig_status ddeig_inverse_iteration(ddeig_problem* P, double* x, double tol_x, int maxit_outer,
                                      double rtol_inner, int maxit_inner, ddeig_eig_info* info);
 
+typedef struct {
+  double lambda;      /* x^T A x of the final, M-normalised x */
+  double res_norm;    /* ||A x - lambda M x||_2 */
+  int outer_its;
+  long inner_sum;     /* PCG iterations (modes 0, 1) or preconditioner applications (mode 2) */
+  int inner_max;
+  double t_solve_ms;
+} ddeig_lopcg_info;
+
+/* Inexact shift-and-invert preconditioned LOPCG (alg:si-lopcg, §2.1; inner
+ * variants of §4.3).  From the M-normalised x_k and the spectral residual
+ * r_k = A x_k - R(x_k) M x_k, each outer step solves A_sigma w_k = r_k
+ * inexactly and takes the minimiser of the Rayleigh quotient over
+ * span{w_k, x_k, x_{k-1}} (Rayleigh-Ritz on the directions B-orthogonalised
+ * against x_k, with p = x_k - x_{k-1} for x_{k-1}; directions whose scaled
+ * Gram eigenvalue is below 1e-10 of the largest are dropped), M-normalised
+ * with 1^T M x > 0; it stops when ||r_k||_2 <= tol_o (M-normalised x) or
+ * after maxit_outer steps.  mode 0: PCG from zero to the relative tolerance
+ * rtol_inner; 1: PCG to min(0.1, ||r_k||_2); 2: one application of the
+ * two-level preconditioner, w_k = M_AS^{-1} r_k (no inner Krylov solve).
+ * x: in the start vector x_1 (all zeros selects the constant vector), out
+ * the eigenvector; x_prev (nullable): x_0, default the first unit vector.
+ * Needs the shift; synchronises the library stream.  Returns DDEIG_ENOCONV
+ * at maxit_outer, DDEIG_ENOTSPD on a CG breakdown of an inner solve. */
+ddeig_status ddeig_lopcg(ddeig_problem* P, double* x, const double* x_prev, double tol_o,
+                         int maxit_outer, int mode, double rtol_inner, int maxit_inner,
+                         ddeig_lopcg_info* info);
+
 /* Measurement support: launches one kernel (or step) of the hot path `reps`
  * times on the library's stream between two HIP events and returns the mean
  * duration of one launch in *avg_us (synchronises).  which = 0: the A_sigma

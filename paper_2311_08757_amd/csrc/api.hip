@@ -3,6 +3,7 @@
 // iteration.  Every call returns a ddeig_status; HIP failures and
 // allocation failures are turned into status codes here.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -295,6 +296,96 @@ PcgOut pcg_run(ddeig_problem* P, const double* b, double* x, double rtol, int ma
   o.done = hs.done;
   if (maxit <= 0 && hs.done == 0) o.done = 4;
   return o;
+}
+
+// Eigen-decomposition of a symmetric 3 x 3 matrix by cyclic Jacobi rotations
+// (FP64, fixed sweep order); ev ascending, V's columns the eigenvectors.
+void sym3_eig(const double Ain[3][3], double ev[3], double V[3][3]) {
+  double A[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      A[i][j] = 0.5 * (Ain[i][j] + Ain[j][i]);
+      V[i][j] = i == j ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    const double off = std::fabs(A[0][1]) + std::fabs(A[0][2]) + std::fabs(A[1][2]);
+    const double dia = std::fabs(A[0][0]) + std::fabs(A[1][1]) + std::fabs(A[2][2]);
+    if (off <= 1e-18 * dia || off == 0.0) break;
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        if (A[p][q] == 0.0) continue;
+        const double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < 3; ++k) {  // A := A J on columns p, q
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 3; ++k) {  // A := J^T A on rows p, q
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < 3; ++k) {
+          const double vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - sn * vkq;
+          V[k][q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  int ord[3] = {0, 1, 2};
+  std::sort(ord, ord + 3, [&](int a, int b) { return A[a][a] < A[b][b]; });
+  double W[3][3];
+  for (int j = 0; j < 3; ++j) {
+    ev[j] = A[ord[j]][ord[j]];
+    for (int k = 0; k < 3; ++k) W[k][j] = V[k][ord[j]];
+  }
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < 3; ++j) V[k][j] = W[k][j];
+}
+
+// Rayleigh-Ritz in span(S) from its Gram matrices: GA[i][j] = s_i^T A s_j,
+// GB[i][j] = s_i^T B s_j.  Columns are scaled to unit B-norm (zero columns
+// ignored), directions with scaled Gram eigenvalue <= 1e-10 of the largest
+// are dropped, and c receives the coefficients of the minimiser (not normalised).
+void rayleigh_ritz3(const double GA[3][3], const double GB[3][3], double c[3]) {
+  double sc[3];
+  for (int i = 0; i < 3; ++i) sc[i] = GB[i][i] > 0.0 ? 1.0 / std::sqrt(GB[i][i]) : 0.0;
+  double gb[3][3], ga[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      gb[i][j] = GB[i][j] * sc[i] * sc[j];
+      ga[i][j] = GA[i][j] * sc[i] * sc[j];
+    }
+  double ev[3], V[3][3];
+  sym3_eig(gb, ev, V);
+  double T[3][3];
+  int nk = 0;
+  for (int j = 0; j < 3; ++j)
+    if (ev[j] > 1e-10 * ev[2]) {
+      for (int k = 0; k < 3; ++k) T[k][nk] = V[k][j] / std::sqrt(ev[j]);
+      ++nk;
+    }
+  double H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int a = 0; a < nk; ++a)
+    for (int b = 0; b < nk; ++b) {
+      double v = 0.0;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) v += T[i][a] * ga[i][j] * T[j][b];
+      H[a][b] = v;
+    }
+  // unused directions get a large diagonal so that they are never the minimiser
+  double big = 1.0;
+  for (int a = 0; a < nk; ++a) big += std::fabs(H[a][a]);
+  for (int a = nk; a < 3; ++a) H[a][a] = 1e3 * big;
+  double mu[3], Y[3][3];
+  sym3_eig(H, mu, Y);
+  for (int i = 0; i < 3; ++i) {
+    double v = 0.0;
+    for (int a = 0; a < nk; ++a) v += T[i][a] * Y[a][0];
+    c[i] = sc[i] * v;
+  }
 }
 
 // Validated device description of a potential (see ddeig_potential).
@@ -893,6 +984,145 @@ void ddeig_destroy(ddeig_problem* P) {
   for (void* p : P->allocs) (void)hipFree(p);
   P->allocs.clear();
   delete P;
+}
+
+ddeig_status ddeig_lopcg(ddeig_problem* P, double* x, const double* x_prev, double tol_o,
+                         int maxit_outer, int mode, double rtol_inner, int maxit_inner,
+                         ddeig_lopcg_info* info) {
+  if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
+  if (validate_vec(x, "x")) return DDEIG_EINVAL;
+  if (x_prev != nullptr && x_prev == x) return set_error(DDEIG_EINVAL, "x and x_prev must not alias");
+  if (!(tol_o >= 0.0) || !std::isfinite(tol_o) || maxit_outer < 1 || mode < 0 || mode > 2 ||
+      (mode == 0 && (!(rtol_inner >= 0.0) || !std::isfinite(rtol_inner))) ||
+      (mode < 2 && maxit_inner < 1))
+    return set_error(DDEIG_EINVAL, "invalid tolerances, iteration limits or mode");
+  if (!P->shifted) return set_error(DDEIG_ESTATE, "lopcg before the shift is set");
+  API_GUARD_BEGIN
+  const hipStream_t s = P->stream;
+  const long n = P->g.n;
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!P->lv) {
+    P->lv = dalloc<double>(P, 9 * (size_t)n);
+    P->lvp = dalloc<double*>(P, 9);
+    P->lpart = dalloc<double>(P, (size_t)kLopcgQ * kMaxRed);
+    P->lout = dalloc<double>(P, 16);
+  }
+  double* W = P->lv;
+  double* AX = P->lv + n;
+  double* BX = P->lv + 2 * n;
+  double* XP = P->lv + 3 * n;
+  double* AXP = P->lv + 4 * n;
+  double* BXP = P->lv + 5 * n;
+  double* AW = P->lv + 6 * n;
+  double* BW = P->lv + 7 * n;
+  double* R = P->lv + 8 * n;
+  // pointer table {x, w, p, Ax, Aw, Ap, Bx, Bw, Bp} (p lives in the x_{k-1} buffers)
+  double* tab[9] = {x, W, XP, AX, AW, AXP, BX, BW, BXP};
+  check_hip(hipMemcpyAsync(P->lvp, tab, sizeof(tab), hipMemcpyHostToDevice, s), "copy pointers");
+  auto read = [&](int cnt, double* h) {
+    check_hip(hipMemcpyAsync(h, P->lout, sizeof(double) * cnt, hipMemcpyDeviceToHost, s), "copy");
+    sync(P);
+  };
+  // x_1 (constant if zero) and x_0 (first unit vector if not given), M-normalised
+  Red s3 = slot(P, 3);
+  launch_dot(x, x, n, s3, s);
+  if (host_sum(P, s3) == 0.0) launch_fill(x, n, 1.0, s);
+  if (x_prev) {
+    launch_copy(XP, x_prev, n, s);
+  } else {
+    launch_fill(XP, n, 0.0, s);
+    const double one = 1.0;
+    check_hip(hipMemcpyAsync(XP, &one, sizeof(double), hipMemcpyHostToDevice, s), "unit vector");
+    sync(P);
+  }
+  for (double* v : {x, XP}) {
+    launch_stencil(P, P->tabM, v, W, &s3, nullptr, s);  // partials of v^T M v
+    launch_scale_copy(n, v, v, s3, s);
+  }
+  Red s4 = slot(P, 4);
+  launch_stencil(P, P->tabA, x, AX, &s4, nullptr, s);  // x^T A x
+  launch_stencil(P, P->tabM, x, BX, nullptr, nullptr, s);
+  double lam = host_sum(P, s4);
+  double h[kLopcgQ];
+  launch_lopcg_resid(n, lam, AX, BX, R, P->lpart, P->lout, s);
+  read(1, h);
+  double res = std::sqrt(std::max(h[0], 0.0));
+  long inner_sum = 0;
+  int inner_max = 0, k = 1;
+  ddeig_status st = DDEIG_OK;
+  while (res > tol_o && k <= maxit_outer) {
+    // inner step: w ~ A_sigma^{-1} r
+    launch_fill(W, n, 0.0, s);
+    int its = 1;
+    if (mode == 2) {
+      precond_apply(P, R, W, nullptr, nullptr);
+    } else {
+      const double rt = mode == 0 ? rtol_inner : std::min(0.1, res);
+      const PcgOut o = pcg_run(P, R, W, rt, maxit_inner);
+      if (o.done == 2 || o.done == 3) {
+        st = set_error(DDEIG_ENOTSPD, "CG breakdown inside LOPCG");
+        break;
+      }
+      its = o.iters;
+    }
+    inner_sum += its;
+    inner_max = std::max(inner_max, its);
+    // B-orthogonalise w and p = x_k - x_{k-1} against x_k on the vectors,
+    // then their A and B images, then the Gram data
+    Red s5 = slot(P, 5), s6 = slot(P, 6);
+    launch_dot(BX, W, n, s5, s);
+    launch_dot(BX, XP, n, s6, s);
+    const double alpha = host_sum(P, s5), beta = host_sum(P, s6);
+    launch_lopcg_orth(n, alpha, beta, x, W, XP, s);
+    launch_stencil(P, P->tabA, W, AW, nullptr, nullptr, s);
+    launch_stencil(P, P->tabM, W, BW, nullptr, nullptr, s);
+    launch_stencil(P, P->tabA, XP, AXP, nullptr, nullptr, s);
+    launch_stencil(P, P->tabM, XP, BXP, nullptr, nullptr, s);
+    launch_lopcg_gram(n, P->lvp, P->lpart, P->lout, s);
+    read(kLopcgQ, h);
+    const int ij[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+    double GA[3][3], GB[3][3];
+    for (int q = 0; q < 6; ++q) {
+      const int a = ij[q][0], b = ij[q][1];
+      GA[a][b] = GA[b][a] = h[q];
+      GB[a][b] = GB[b][a] = h[6 + q];
+    }
+    double c[3];
+    rayleigh_ritz3(GA, GB, c);
+    double nrm = 0.0, sgn = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      sgn += c[a] * h[12 + a];
+      for (int b = 0; b < 3; ++b) nrm += c[a] * GB[a][b] * c[b];
+    }
+    if (!(nrm > 0.0)) {
+      st = set_error(DDEIG_ENOTSPD, "LOPCG: the Ritz vector has no positive M-norm");
+      break;
+    }
+    const double f = (sgn < 0.0 ? -1.0 : 1.0) / std::sqrt(nrm);
+    launch_lopcg_update(n, f * c[0], f * c[1], f * c[2], x, W, XP, s);
+    Red s7 = slot(P, 7);
+    launch_stencil(P, P->tabA, x, AX, &s7, nullptr, s);  // x^T A x
+    launch_stencil(P, P->tabM, x, BX, nullptr, nullptr, s);
+    lam = host_sum(P, s7);
+    launch_lopcg_resid(n, lam, AX, BX, R, P->lpart, P->lout, s);
+    read(1, h);
+    res = std::sqrt(std::max(h[0], 0.0));
+    ++k;
+  }
+  check_launch("lopcg");
+  const auto t1 = std::chrono::steady_clock::now();
+  if (info) {
+    info->lambda = lam;
+    info->res_norm = res;
+    info->outer_its = k - 1;
+    info->inner_sum = inner_sum;
+    info->inner_max = inner_max;
+    info->t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  }
+  if (st != DDEIG_OK) return st;
+  if (res > tol_o) return set_error(DDEIG_ENOCONV, "LOPCG reached maxit_outer");
+  return DDEIG_OK;
+  API_GUARD_END
 }
 
 ddeig_status ddeig_profile_kernel(ddeig_problem* P, int which, int reps, const double* x, double* y,

@@ -330,6 +330,12 @@ struct ddeig_problem {
   double* hist = nullptr;   // device residual history
   int hist_cap = 0;
   double* scal = nullptr;   // small device scalars
+  // SI-preconditioned LOPCG work space (allocated by the first ddeig_lopcg call):
+  // 9 vectors, the pointer table of the Gram / update kernels, partial sums
+  double* lv = nullptr;
+  double** lvp = nullptr;
+  double* lpart = nullptr;
+  double* lout = nullptr;
   int* flag = nullptr;      // factorisation error flag
   double* gjbuf = nullptr;  // Gauss-Jordan row/column buffers (4 x gj_stride)
   int gj_stride = 0;
@@ -435,6 +441,17 @@ void launch_scale_copy(long n, double* dst, const double* src, Red nrm2, hipStre
 void launch_ipm_normalise(long n, const double* u, const double* Mu, double* x, const double* b,
                           Red uMu, Red sumMu, Red& dx, hipStream_t s);
 void launch_dot(const double* x, const double* y, long n, Red& out, hipStream_t s);
+
+// SI-preconditioned LOPCG (k_vector.hip); dv: device array of vector pointers
+constexpr int kLopcgQ = 15;  // Gram quantities of one outer step
+void launch_lopcg_orth(long n, double alpha, double beta, const double* x, double* w, double* xp,
+                       hipStream_t s);
+// dv = {x, w, p, Ax, Aw, Ap, Bx, Bw, Bp}; out[0..14] (see k_lopcg_gram)
+int launch_lopcg_gram(long n, const double* const* dv, double* part, double* out, hipStream_t s);
+void launch_lopcg_update(long n, double c0, double c1, double c2, double* x, const double* w,
+                         double* p, hipStream_t s);
+int launch_lopcg_resid(long n, double lambda, const double* Ax, const double* Bx, double* r,
+                       double* part, double* out, hipStream_t s);
 
 void check_hip(hipError_t e, const char* what);
 

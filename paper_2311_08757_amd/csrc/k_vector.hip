@@ -148,4 +148,128 @@ void launch_to_float(const double* src, float* dst, long n, hipStream_t s) {
   if (blocks > 0) hipLaunchKernelGGL(k_to_float, dim3(blocks), dim3(kBlock), 0, s, src, dst, n);
 }
 
+// ---- SI-preconditioned LOPCG (alg:si-lopcg) ---------------------------------
+// Vectors of one outer step, each with its A and B images (B = M):
+// x = x_k (B-normalised), w = the preconditioned residual, p = x_k - x_{k-1}.
+
+// B-orthogonalise the search directions against x_k on the vectors themselves
+// (their A and B images are then formed from the results, so that the small
+// differences near convergence keep their digits): w -= alpha x, and
+// p = x_k - x_{k-1} minus its x_k part, which is beta x_k - x_{k-1}
+// (alpha = x^T B w, beta = x^T B x_{k-1}; x^T B x = 1).
+__global__ void k_lopcg_orth(long n, double alpha, double beta, const double* __restrict__ x,
+                             double* __restrict__ w, double* __restrict__ xp) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x) {
+    const double xi = x[i];
+    w[i] -= alpha * xi;
+    xp[i] = beta * xi - xp[i];
+  }
+}
+
+void launch_lopcg_orth(long n, double alpha, double beta, const double* x, double* w, double* xp,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_lopcg_orth, dim3(red_grid(n)), dim3(kBlock), 0, s, n, alpha, beta, x, w,
+                     xp);
+}
+
+// Gram data of S = [s0, s1, s2] = [x, w, p]: out[0..5] = s_i^T A s_j and
+// out[6..11] = s_i^T B s_j for (i, j) = (0,0), (0,1), (0,2), (1,1), (1,2),
+// (2,2), out[12..14] = 1^T B s_i.  One partial per block and quantity
+// (part[q * np + block]); k_lopcg_finish adds them in block order.
+__global__ void __launch_bounds__(kBlock) k_lopcg_gram(long n, const double* const* __restrict__ v,
+                                                        double* __restrict__ part) {
+  const double* S[3] = {v[0], v[1], v[2]};
+  const double* AS[3] = {v[3], v[4], v[5]};
+  const double* BS[3] = {v[6], v[7], v[8]};
+  double acc[kLopcgQ];
+#pragma unroll
+  for (int q = 0; q < kLopcgQ; ++q) acc[q] = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x) {
+    double s[3], a[3], b[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      s[k] = S[k][i];
+      a[k] = AS[k][i];
+      b[k] = BS[k][i];
+    }
+    int q = 0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = r; c < 3; ++c) {
+        acc[q] += s[r] * a[c];
+        acc[6 + q] += s[r] * b[c];
+        ++q;
+      }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[12 + k] += b[k];
+  }
+#pragma unroll
+  for (int q = 0; q < kLopcgQ; ++q) {
+    const double t = block_sum(acc[q]);
+    if (threadIdx.x == 0) part[(long)q * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// out[q] = sum of the np partials of quantity q, in block order.
+__global__ void k_lopcg_finish(const double* __restrict__ part, int np, int nq,
+                               double* __restrict__ out) {
+  for (int q = 0; q < nq; ++q) {
+    const double t = sum_partials(part + (long)q * np, np);
+    if (threadIdx.x == 0) out[q] = t;
+  }
+}
+
+int launch_lopcg_gram(long n, const double* const* dv, double* part, double* out,
+                      hipStream_t s) {
+  const int np = red_grid(n);
+  hipLaunchKernelGGL(k_lopcg_gram, dim3(np), dim3(kBlock), 0, s, n, dv, part);
+  hipLaunchKernelGGL(k_lopcg_finish, dim3(1), dim3(kBlock), 0, s, part, np, kLopcgQ, out);
+  return np;
+}
+
+// x_{k+1} = c0 x + c1 w + c2 p (the Ritz vector, B-normalised by the
+// coefficients) and x_{k-1} := x_k.
+__global__ void k_lopcg_update(long n, double c0, double c1, double c2, double* __restrict__ x,
+                               const double* __restrict__ w, double* __restrict__ p) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x) {
+    const double xo = x[i];
+    x[i] = c0 * xo + c1 * w[i] + c2 * p[i];
+    p[i] = xo;
+  }
+}
+
+// r = A x - lambda B x with partials of ||r||^2 (quantity 0 of part).
+__global__ void __launch_bounds__(kBlock) k_lopcg_resid(long n, double lambda,
+                                                         const double* __restrict__ Ax,
+                                                         const double* __restrict__ Bx,
+                                                         double* __restrict__ r,
+                                                         double* __restrict__ part) {
+  double acc = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x) {
+    const double v = Ax[i] - lambda * Bx[i];
+    r[i] = v;
+    acc += v * v;
+  }
+  write_partial(acc, part);
+}
+
+void launch_lopcg_update(long n, double c0, double c1, double c2, double* x, const double* w,
+                         double* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_lopcg_update, dim3(red_grid(n)), dim3(kBlock), 0, s, n, c0, c1, c2, x, w,
+                     p);
+}
+
+int launch_lopcg_resid(long n, double lambda, const double* Ax, const double* Bx, double* r,
+                       double* part, double* out, hipStream_t s) {
+  const int np = red_grid(n);
+  hipLaunchKernelGGL(k_lopcg_resid, dim3(np), dim3(kBlock), 0, s, n, lambda, Ax, Bx, r, part);
+  hipLaunchKernelGGL(k_lopcg_finish, dim3(1), dim3(kBlock), 0, s, part, np, 1, out);
+  return np;
+}
+
 }  // namespace ddeig

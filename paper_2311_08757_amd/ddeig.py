@@ -57,8 +57,14 @@ class EigInfo(ctypes.Structure):
                 ("inner_max", ctypes.c_int), ("t_solve_ms", ctypes.c_double)]
 
 
+class LopcgInfo(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("res_norm", ctypes.c_double),
+                ("outer_its", ctypes.c_int), ("inner_sum", ctypes.c_long),
+                ("inner_max", ctypes.c_int), ("t_solve_ms", ctypes.c_double)]
+
+
 EXPORTS = ["ddeig_assemble", "ddeig_cell_shift", "ddeig_set_shift", "ddeig_apply_op",
-           "ddeig_apply_precond", "ddeig_pcg_solve", "ddeig_inverse_iteration",
+           "ddeig_apply_precond", "ddeig_pcg_solve", "ddeig_inverse_iteration", "ddeig_lopcg",
            "ddeig_profile_kernel", "ddeig_potential_form", "ddeig_batch_create",
            "ddeig_batch_query", "ddeig_batch_pcg_solve", "ddeig_batch_inverse_iteration",
            "ddeig_batch_destroy", "ddeig_query", "ddeig_destroy", "ddeig_status_string",
@@ -88,6 +94,8 @@ def load_library(path=LIB_PATH):
                                     ctypes.POINTER(PcgInfo)]
     lib.ddeig_inverse_iteration.argtypes = [P, P, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                             ctypes.c_int, ctypes.POINTER(EigInfo)]
+    lib.ddeig_lopcg.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                ctypes.c_double, ctypes.c_int, ctypes.POINTER(LopcgInfo)]
     lib.ddeig_profile_kernel.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, dp, dp]
     lib.ddeig_potential_form.argtypes = [P, ctypes.c_int, ctypes.POINTER(Potential), P, P, dp]
     PP = ctypes.POINTER(ctypes.c_void_p)
@@ -411,3 +419,24 @@ def batch_inverse_iteration(batch, xs, tol_x=1e-9, maxit_outer=100, rtol_inner=1
     return STATUS.get(st, st), [dict(lam=i.lambda_, dx_M=i.dx_M, outer_its=i.outer_its,
                                      inner_sum=i.inner_sum, inner_max=i.inner_max,
                                      t_solve_ms=i.t_solve_ms) for i in info]
+
+
+LOPCG_MODES = {"fixed": 0, "adaptive": 1, "fused": 2}
+
+
+def lopcg(prob, x, x_prev=None, tol_o=1e-8, maxit_outer=500, mode="fixed", rtol_inner=1e-8,
+          maxit_inner=10000, raise_on_error=True):
+    """ddeig_lopcg: inexact SI-preconditioned LOPCG; x in: start (zeros: constant), out:
+    eigenvector; x_prev: x_0 (None: first unit vector).  mode: fixed / adaptive / fused."""
+    lib = load_library()
+    info = LopcgInfo()
+    m = LOPCG_MODES[mode] if isinstance(mode, str) else int(mode)
+    xp = _ptr(x_prev, prob.n_dof, "x_prev") if x_prev is not None else None
+    st = lib.ddeig_lopcg(prob.handle, _ptr(x, prob.n_dof, "x"), xp, float(tol_o), int(maxit_outer),
+                         m, float(rtol_inner), int(maxit_inner), ctypes.byref(info))
+    out = dict(status=STATUS.get(st, st), lam=info.lambda_, res_norm=info.res_norm,
+               outer_its=info.outer_its, inner_sum=info.inner_sum, inner_max=info.inner_max,
+               t_solve_ms=info.t_solve_ms)
+    if raise_on_error and st != DDEIG_OK:
+        _check(st, "ddeig_lopcg")
+    return out

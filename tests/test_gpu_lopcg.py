@@ -1,0 +1,122 @@
+"""GPU parity of the inexact SI-preconditioned LOPCG (ddeig_lopcg, alg:si-lopcg)
+against the oracle's si_lopcg on the same problems, start vectors (x_0 = e_1,
+x_1 = constant) and inner variants.
+
+- FP64 local solves (the oracle's preconditioner up to rounding): lambda to
+  1e-11 relative, ||x - x_ref||_M <= 1e-8, outer steps within 1 of the
+  oracle's, total inner iterations within 10 % (fixed / adaptive) and the
+  same count of preconditioner applications +-1 (fused);
+- bf16 local solves: the same eigenpair bar (the preconditioner differs, the
+  outer quantities are exact);
+- the ordering of total inner work reported in §4.3: fused < adaptive < fixed;
+- the full-size 2-D L = 256 workload (bf16 local solves, fused): lambda
+  against the stored oracle value to 1e-10 relative.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+CASES = [
+    (1, 1, 8, 8, 2, W.sep_fourier(1000)),
+    (1, 1, 5, 6, 3, W.sep_fourier(17)),
+    (1, 2, 3, 4, 1, W.sep_fourier(3000)),
+    (2, 1, 3, 4, 1, W.fourier2(4000)),
+]
+IDS = [f"p{c[0]}q{c[1]}-L{c[2]}-ne{c[3]}-d{c[4]}" for c in CASES]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+def _oracle(case, mode):
+    from oracle.lopcg import si_lopcg, unit_first
+    from oracle.problem import Problem
+    p, q, L, ne, delta, V = case
+    P = Problem(W.small_config(p, q, L, ne, delta, V))
+    n = P.grid.n
+    out = si_lopcg(P.A, P.M, P.sigma, unit_first(n), np.ones(n), tol_o=1e-10, kmax=500,
+                   mode=mode, rtol_i=1e-10, precond=P.preconditioner(True).apply)
+    return P, out
+
+
+@pytest.mark.parametrize("mode", ["fixed", "adaptive", "fused"])
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_lopcg_parity(torch, case, mode, prec):
+    import paper_2311_08757_amd as dd
+    p, q, L, ne, delta, V = case
+    P, ref = _oracle(case, mode)
+    prob = dd.assemble(p, q, L, ne, V, delta, local_prec=prec)
+    dd.cell_shift(prob)
+    x = torch.zeros(prob.n_dof, dtype=torch.float64, device="cuda")
+    out = dd.lopcg(prob, x, tol_o=1e-10, maxit_outer=500, mode=mode, rtol_inner=1e-10)
+    assert out["res_norm"] <= 1e-10
+    assert abs(out["lam"] - ref["lam"]) <= 1e-11 * abs(ref["lam"])
+    d = x.cpu().numpy() - ref["x"]
+    assert np.sqrt(d @ (P.M @ d)) <= 1e-8
+    if prec == "fp64":
+        assert abs(out["outer_its"] - ref["its"]) <= 1, (out["outer_its"], ref["its"])
+        tot = int(ref["inner"].sum())
+        if mode == "fused":
+            assert abs(out["inner_sum"] - tot) <= 1
+        else:
+            assert abs(out["inner_sum"] - tot) <= max(2, 0.1 * tot), (out["inner_sum"], tot)
+
+
+def test_lopcg_inner_work_ordering(torch):
+    """§4.3: fused < adaptive < fixed in total inner iterations, on the GPU."""
+    import paper_2311_08757_amd as dd
+    case = (1, 1, 16, 8, 2, W.sep_fourier(1000))
+    p, q, L, ne, delta, V = case
+    prob = dd.assemble(p, q, L, ne, V, delta, local_prec="bf16")
+    dd.cell_shift(prob)
+    tot = {}
+    for mode in ("fixed", "adaptive", "fused"):
+        x = torch.zeros(prob.n_dof, dtype=torch.float64, device="cuda")
+        out = dd.lopcg(prob, x, tol_o=1e-8, maxit_outer=2000, mode=mode, rtol_inner=1e-8)
+        tot[mode] = out["inner_sum"]
+    assert tot["fused"] < tot["adaptive"] < tot["fixed"], tot
+
+
+def test_lopcg_errors(torch):
+    import paper_2311_08757_amd as dd
+    p, q, L, ne, delta, V = CASES[0]
+    prob = dd.assemble(p, q, L, ne, V, delta)
+    x = torch.zeros(prob.n_dof, dtype=torch.float64, device="cuda")
+    with pytest.raises(dd.DdeigError):
+        dd.lopcg(prob, x)                       # no shift yet
+    dd.cell_shift(prob)
+    with pytest.raises(dd.DdeigError):
+        dd.lopcg(prob, x, mode=3)
+    with pytest.raises(dd.DdeigError):
+        dd.lopcg(prob, x, x_prev=x)             # aliasing
+    out = dd.lopcg(prob, x, tol_o=1e-14, maxit_outer=2, mode="fused", raise_on_error=False)
+    assert out["status"] == "ENOCONV" and out["outer_its"] == 2
+
+
+@pytest.mark.timeout(600)
+def test_lopcg_config2_fused(torch):
+    """2-D L = 256, h = 1/64 (1,032,129 unknowns), bf16 local solves, fused inner step."""
+    import paper_2311_08757_amd as dd
+    gd = json.load(open(os.path.join(HERE, "golden", "oracle_config2.json")))
+    cfg = W.config(2)
+    prob = dd.assemble(cfg["p"], cfg["q"], cfg["L"], cfg["ne"], cfg["V"], cfg["delta"],
+                       local_prec="bf16")
+    dd.cell_shift(prob)
+    x = torch.zeros(prob.n_dof, dtype=torch.float64, device="cuda")
+    out = dd.lopcg(prob, x, tol_o=1e-9, maxit_outer=3000, mode="fused")
+    assert abs(out["lam"] - gd["lam"]) <= 1e-10 * abs(gd["lam"])
+    xs = x.cpu().numpy()[gd["sample_idx"]]
+    assert np.max(np.abs(xs - np.array(gd["sample_x"]))) <= 1e-7
