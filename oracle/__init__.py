@@ -17,5 +17,13 @@ What it computes (paper: Theisen & Stamm, arXiv 2311.08757):
                  def:algebraic-perfact-coarse-space, §4.1.2 distance PU);
   * pcg       -- preconditioned conjugate gradients (§3, eq:cg-energy-norm-error-reduction);
   * ipm       -- sigma-shifted inverse iteration with B-normalisation (§2),
-                 with an exact direct solver or with PCG inner solves.
+                 with an exact direct solver or with PCG inner solves;
+  * grad      -- derivatives of lambda, sigma and a shifted solve with respect
+                 to the potential's parameters (beyond the paper);
+  * lopcg     -- inexact SI-preconditioned LOPCG (alg:si-lopcg) and its inner
+                 variants of §4.3;
+  * ras       -- restricted additive Schwarz (eq:dd-preconditioners,
+                 eq:two-level-preconditioners), the stationary RAS iteration
+                 (eq:stationary-ras, eq:two-level-stationary-ras-mult-cc) and
+                 right-preconditioned GMRES (§3).
 """
