@@ -158,6 +158,56 @@ ddeig_status ddeig_apply_op(ddeig_problem* P, int which, const double* x, double
  * sum_i R_i^T A_sigma,i^{-1} R_i r + R_0^T A_sigma,0^{-1} R_0 r  (§3). */
 ddeig_status ddeig_apply_precond(ddeig_problem* P, const double* r, double* z);
 
+/* Schwarz preconditioners of §3 (eq:dd-preconditioners,
+ * eq:two-level-preconditioners), selected by `kind`:
+ *   AS1     z = sum_i R_i^T A_sigma,i^{-1} R_i r
+ *   AS2     AS1 + R_0^T A_sigma,0^{-1} R_0 r        (the PerFact coarse space)
+ *   RAS1    z = sum_i R_i^T D_i A_sigma,i^{-1} R_i r (D_i: the partition of unity
+ *           of options.pu; restricted additive Schwarz, not symmetric)
+ *   RAS2    RAS1 + R_0^T A_sigma,0^{-1} R_0 r
+ *   COARSE  R_0^T A_sigma,0^{-1} R_0 r alone (the coarse correction of
+ *           eq:two-level-stationary-ras-mult-cc)
+ * The local solves are those of options.local_prec.  Kinds with the coarse
+ * space need options.coarse = 1 (DDEIG_ESTATE otherwise). */
+#define DDEIG_PREC_AS1 0
+#define DDEIG_PREC_AS2 1
+#define DDEIG_PREC_RAS1 2
+#define DDEIG_PREC_RAS2 3
+#define DDEIG_PREC_COARSE 4
+
+/* z = M^{-1} r for the preconditioner `kind` (asynchronous on the library
+ * stream; needs the shift).  r and z: n_dof device values, not aliased. */
+ddeig_status ddeig_apply_schwarz(ddeig_problem* P, int kind, const double* r, double* z);
+
+/* Stationary RAS for A_sigma x = b: levels = 1 iterates
+ * x_{k+1} = x_k + M_RAS,1^{-1} (b - A_sigma x_k) (eq:stationary-ras); levels = 2
+ * follows every such half step by the coarse correction of the new residual,
+ * x += R_0^T A_sigma,0^{-1} R_0 (b - A_sigma x) (multiplicative,
+ * eq:two-level-stationary-ras-mult-cc; needs options.coarse = 1).  The
+ * residual b - A_sigma x is recomputed after every correction.  x holds x0
+ * on entry; stops when ||r_k||_2 <= rtol ||r_0||_2 or after maxit steps (a
+ * half step and its coarse correction are one step).  info as for pcg_solve
+ * (breakdown = 1 when the residual overflowed).  Synchronises the library
+ * stream.  Returns DDEIG_ENOCONV at maxit or on divergence. */
+ddeig_status ddeig_stationary_ras(ddeig_problem* P, int levels, const double* b, double* x,
+                                  double rtol, int maxit, ddeig_pcg_info* info);
+
+/* GMRES for A_sigma x = b with right preconditioning by `kind` (§3: GMRES
+ * with the unsymmetric M_RAS,2 is the Krylov method for RAS; §4.2).  Arnoldi
+ * by classical Gram-Schmidt applied twice; the preconditioned vectors
+ * z_j = M^{-1} v_j are kept and x = x0 + Z y (y from the Givens-rotated
+ * least-squares problem), which equals x0 + M^{-1} V y for a linear M and
+ * keeps the Arnoldi relation when the local solves round their input (bf16).
+ * Restarts every `restart` steps from the true residual (restart <= 0: no
+ * restart below min(maxit, 300)).  x holds x0 on entry; stops when the
+ * residual norm of the least-squares problem is <= rtol ||r_0||_2 or after
+ * maxit steps.  info as for pcg_solve (relres and hist: the least-squares
+ * residual norms; breakdown = 1 for a zero Hessenberg column).  Work space:
+ * (2 restart + 1) n_dof doubles, kept by the handle.  Synchronises the library
+ * stream.  Returns DDEIG_ENOCONV at maxit or on breakdown. */
+ddeig_status ddeig_gmres_solve(ddeig_problem* P, int kind, const double* b, double* x, double rtol,
+                               int maxit, int restart, ddeig_pcg_info* info);
+
 /* Preconditioned CG for A_sigma x = b (§2.1, §3): x holds x0 on entry and the
  * iterate on exit; stops when ||r_k||_2 <= rtol ||r_0||_2 (§4.1).  Returns
  * DDEIG_ENOCONV after maxit iterations, DDEIG_ENOTSPD on breakdown. */

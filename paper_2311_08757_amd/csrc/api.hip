@@ -179,15 +179,41 @@ ddeig_status finish_shift(ddeig_problem* P) {
   return DDEIG_OK;
 }
 
+// Parts of a Schwarz preconditioner (kind argument of precond_apply): the
+// local solves, the coarse correction, and the partition-of-unity weighting of
+// the local solutions (restricted additive Schwarz).
+constexpr int kPrecLocal = 1, kPrecCoarse = 2, kPrecRas = 4;
+
+int prec_flags(int kind) {
+  switch (kind) {
+    case DDEIG_PREC_AS1: return kPrecLocal;
+    case DDEIG_PREC_AS2: return kPrecLocal | kPrecCoarse;
+    case DDEIG_PREC_RAS1: return kPrecLocal | kPrecRas;
+    case DDEIG_PREC_RAS2: return kPrecLocal | kPrecCoarse | kPrecRas;
+    case DDEIG_PREC_COARSE: return kPrecCoarse;
+    default: return -1;
+  }
+}
+
 // restrict -> {local solves (+ clipped-class correction) | coarse solve on the
 // second stream} -> extend.  xr (nullable) fuses the CG update of x and r into the
 // restriction (partials of ||r||^2 into *rr); chk (nullable) folds the PCG
-// stopping test into the extension.
+// stopping test into the extension.  flags (kPrec*; -1: the problem's additive
+// Schwarz preconditioner) selects the parts; the coarse correction alone runs
+// on the library stream.
 void precond_apply(ddeig_problem* P, double* r, double* z, Red* dot, PcgState* st,
                    const XrArgs* xr = nullptr, Red* rr = nullptr, const CheckArgs* chk = nullptr,
-                   hipStream_t ms = nullptr) {
+                   hipStream_t ms = nullptr, int flags = -1) {
   const hipStream_t s = ms ? ms : P->stream;
-  const int coarse = P->opt.coarse;
+  if (flags < 0) flags = kPrecLocal | (P->opt.coarse ? kPrecCoarse : 0);
+  const int coarse = (flags & kPrecCoarse) ? 1 : 0;
+  if (!(flags & kPrecLocal)) {
+    launch_coarse_rhs(P, r, st, s);
+    launch_coarse_solve(P, st, s);
+    launch_coarse_field(P, st, s);
+    launch_coarse_extend(P, r, z, dot, st, s);
+    return;
+  }
   XrArgs xoff{};
   xoff.on = 0;
   CheckArgs coff{};
@@ -212,7 +238,7 @@ void precond_apply(ddeig_problem* P, double* r, double* z, Red* dot, PcgState* s
 
   CheckArgs c = chk ? *chk : coff;
   if (chk && rr) c.rr = *rr;
-  launch_extend(P, r, z, coarse, dot, st, c, s);
+  launch_extend(P, r, z, coarse, dot, st, c, s, (flags & kPrecRas) ? 1 : 0);
 }
 
 struct PcgOut {
@@ -295,6 +321,179 @@ PcgOut pcg_run(ddeig_problem* P, const double* b, double* x, double rtol, int ma
   o.relres = hs.relres;
   o.done = hs.done;
   if (maxit <= 0 && hs.done == 0) o.done = 4;
+  return o;
+}
+
+// Stationary restricted additive Schwarz for A_sigma x = b (x holds x0):
+// levels 1: x_{k+1} = x_k + M_RAS,1^{-1} r_k (eq:stationary-ras); levels 2:
+// the same half step followed by the coarse correction of the new residual
+// (eq:two-level-stationary-ras-mult-cc).  Each half step: the preconditioner
+// part into z, x += z, then the residual r = b - A_sigma x afresh with the
+// partials of ||r||^2 (no recurrence, so no drift over many steps); the
+// stopping test ||r_k|| <= rtol ||r_0|| closes every step.
+PcgOut sras_run(ddeig_problem* P, int levels, const double* b, double* x, double rtol,
+                int maxit) {
+  const hipStream_t s = P->stream;
+  const int batch = P->opt.batch_iters > 0 ? P->opt.batch_iters : 8;
+  Red rr = slot(P, 1);
+  launch_stencil(P, P->tabAs, x, P->q, nullptr, nullptr, s);
+  launch_resid_init(P, b, P->q, P->r, rr, s);
+  launch_pcg_init(P, rtol, rr, s);
+  check_launch("stationary RAS start");
+  PcgState hs{};
+  check_hip(hipMemcpyAsync(&hs, P->st, sizeof(PcgState), hipMemcpyDeviceToHost, s), "state");
+  sync(P);
+  int k = 0;
+  while (k < maxit && !hs.done) {
+    const int kend = std::min(maxit, k + batch);
+    for (int kk = k + 1; kk <= kend; ++kk) {
+      precond_apply(P, P->r, P->z, nullptr, P->st, nullptr, nullptr, nullptr, s,
+                    kPrecLocal | kPrecRas);
+      launch_sr_update(P, P->z, x, s);
+      launch_stencil(P, P->tabAs, x, P->q, nullptr, nullptr, s);
+      launch_resid_init(P, b, P->q, P->r, rr, s);
+      if (levels == 2) {
+        precond_apply(P, P->r, P->z, nullptr, P->st, nullptr, nullptr, nullptr, s, kPrecCoarse);
+        launch_sr_update(P, P->z, x, s);
+        launch_stencil(P, P->tabAs, x, P->q, nullptr, nullptr, s);
+        launch_resid_init(P, b, P->q, P->r, rr, s);
+      }
+      launch_sr_check(P, rr, kk, maxit, s);
+    }
+    k = kend;
+    check_launch("stationary RAS step");
+    check_hip(hipMemcpyAsync(&hs, P->st, sizeof(PcgState), hipMemcpyDeviceToHost, s), "state");
+    sync(P);
+  }
+  PcgOut o;
+  o.iters = hs.iters;
+  o.relres = hs.relres;
+  o.done = hs.done ? hs.done : 4;
+  return o;
+}
+
+// GMRES work space for restart length m: V (m + 1 vectors), Z (m vectors),
+// the dot partials ((m + 1) x blocks), the norm partials, H ((m + 1) x m),
+// rotations cs, sn (m), g, h1, h2 (m + 1), scalars and y (m).
+struct GmWs {
+  double *V, *Z, *part, *nrm, *H, *cs, *sn, *g, *h1, *h2, *gm, *y;
+  long ldv;
+};
+
+GmWs gm_workspace(ddeig_problem* P, int m) {
+  const long n = P->g.n;
+  const long ldv = (n + 63) / 64 * 64;
+  const long nb = gm_blocks(n);
+  // offsets of the parts in doubles
+  long off = 0;
+  auto take = [&](long cnt) {
+    const long o = off;
+    off += cnt;
+    return o;
+  };
+  const long oV = take((long)(m + 1) * ldv), oZ = take((long)m * ldv);
+  const long oP = take((long)(m + 1) * nb), oN = take(nb), oH = take((long)(m + 1) * m);
+  const long oC = take(m), oS = take(m), oG = take(m + 1), o1 = take(m + 1), o2 = take(m + 1);
+  const long oM = take(8), oY = take(m);
+  if (m > P->gm_cap || ldv != P->gm_ldv || !P->gmws) {
+    dfree(P, P->gmws);
+    P->gmws = nullptr;
+    P->gm_cap = 0;
+    P->gmws = dalloc<double>(P, (size_t)off);
+    P->gm_cap = m;
+    P->gm_ldv = ldv;
+  }
+  double* b = P->gmws;
+  GmWs w{b + oV, b + oZ, b + oP, b + oN, b + oH, b + oC, b + oS, b + oG, b + o1, b + o2, b + oM,
+         b + oY, ldv};
+  return w;
+}
+
+// GMRES for A_sigma x = b (x holds x0) with right preconditioning by the
+// Schwarz preconditioner of `flags`, restarted every m steps (see
+// k_krylov.hip for one step).  At the end of a cycle the host solves the
+// small triangular system R y = g and the device adds Z y to x; a restart
+// begins from the true residual b - A_sigma x.
+PcgOut gmres_run(ddeig_problem* P, int flags, const double* b, double* x, double rtol, int maxit,
+                 int m) {
+  const hipStream_t s = P->stream;
+  const int batch = P->opt.batch_iters > 0 ? P->opt.batch_iters : 8;
+  const GmWs w = gm_workspace(P, m);
+  Red rr = slot(P, 1);
+  launch_stencil(P, P->tabAs, x, P->q, nullptr, nullptr, s);
+  launch_resid_init(P, b, P->q, P->r, rr, s);
+  launch_pcg_init(P, rtol, rr, s);
+  launch_gm_start(P, rr, P->r, w.V, w.g, w.gm, s);
+  check_launch("gmres start");
+  PcgState hs{};
+  check_hip(hipMemcpyAsync(&hs, P->st, sizeof(PcgState), hipMemcpyDeviceToHost, s), "state");
+  sync(P);
+  int k = 0;
+  std::vector<double> Hh, gh, yh;
+  while (!hs.done && k < maxit) {
+    const int kc0 = k;
+    int j = 0;
+    while (j < m && k < maxit) {
+      const int nq = std::min(std::min(batch, m - j), maxit - k);
+      for (int t = 0; t < nq; ++t) {
+        const int jj = j + t, kk = k + t + 1;
+        double* vj = w.V + (long)jj * w.ldv;
+        double* zj = w.Z + (long)jj * w.ldv;
+        double* wn = w.V + (long)(jj + 1) * w.ldv;
+        precond_apply(P, vj, zj, nullptr, P->st, nullptr, nullptr, nullptr, s, flags);
+        launch_stencil(P, P->tabAs, zj, wn, nullptr, nullptr, s);
+        launch_gm_dots(P, jj + 1, w.V, w.ldv, wn, w.part, s);
+        launch_gm_sum(P, jj + 1, w.part, w.h1, s);
+        launch_gm_axpy(P, jj + 1, w.V, w.ldv, w.h1, wn, nullptr, s);
+        launch_gm_dots(P, jj + 1, w.V, w.ldv, wn, w.part, s);
+        launch_gm_sum(P, jj + 1, w.part, w.h2, s);
+        launch_gm_axpy(P, jj + 1, w.V, w.ldv, w.h2, wn, w.nrm, s);
+        launch_gm_finish(P, jj, kk, maxit, m, w.nrm, w.h1, w.h2, w.H, w.cs, w.sn, w.g, w.gm, s);
+        launch_gm_scale(P, wn, w.gm, s);
+      }
+      j += nq;
+      k += nq;
+      check_launch("gmres step");
+      check_hip(hipMemcpyAsync(&hs, P->st, sizeof(PcgState), hipMemcpyDeviceToHost, s), "state");
+      sync(P);
+      if (hs.done) break;
+    }
+    // columns completed in this cycle (a breakdown leaves its column out)
+    int jd = hs.iters - kc0 - (hs.done == 2 ? 1 : 0);
+    k = hs.done ? hs.iters : k;
+    if (jd > 0) {
+      Hh.resize((size_t)(m + 1) * jd);
+      gh.resize(jd);
+      yh.resize(jd);
+      check_hip(hipMemcpyAsync(Hh.data(), w.H, sizeof(double) * Hh.size(), hipMemcpyDeviceToHost,
+                               s), "copy H");
+      check_hip(hipMemcpyAsync(gh.data(), w.g, sizeof(double) * jd, hipMemcpyDeviceToHost, s),
+                "copy g");
+      sync(P);
+      for (int i = jd - 1; i >= 0; --i) {  // R y = g, R upper triangular (column-major)
+        double t = gh[i];
+        for (int c = i + 1; c < jd; ++c) t -= Hh[(size_t)c * (m + 1) + i] * yh[c];
+        yh[i] = t / Hh[(size_t)i * (m + 1) + i];
+      }
+      check_hip(hipMemcpyAsync(w.y, yh.data(), sizeof(double) * jd, hipMemcpyHostToDevice, s),
+                "copy y");
+      launch_gm_update(P, jd, w.Z, w.ldv, w.y, x, s);
+      check_launch("gmres update");
+      sync(P);
+    }
+    if (hs.done != 6) break;
+    // restart from the true residual
+    launch_stencil(P, P->tabAs, x, P->q, nullptr, nullptr, s);
+    launch_resid_init(P, b, P->q, P->r, rr, s);
+    launch_gm_start(P, rr, P->r, w.V, w.g, w.gm, s);
+    check_launch("gmres restart");
+    check_hip(hipMemcpyAsync(&hs, P->st, sizeof(PcgState), hipMemcpyDeviceToHost, s), "state");
+    sync(P);
+  }
+  PcgOut o;
+  o.iters = hs.iters;
+  o.relres = hs.relres;
+  o.done = hs.done == 6 ? 4 : (hs.done ? hs.done : 4);
   return o;
 }
 
@@ -1321,6 +1520,79 @@ ddeig_status ddeig_apply_precond(ddeig_problem* P, const double* r, double* z) {
   API_GUARD_BEGIN
   precond_apply(P, const_cast<double*>(r), z, nullptr, nullptr);
   check_launch("apply_precond");
+  return DDEIG_OK;
+  API_GUARD_END
+}
+
+ddeig_status ddeig_apply_schwarz(ddeig_problem* P, int kind, const double* r, double* z) {
+  if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
+  if (validate_vec(r, "r") || validate_vec(z, "z")) return DDEIG_EINVAL;
+  if (r == z) return set_error(DDEIG_EINVAL, "r and z must not alias");
+  const int flags = prec_flags(kind);
+  if (flags < 0) return set_error(DDEIG_EINVAL, "unknown preconditioner kind");
+  if (!P->shifted) return set_error(DDEIG_ESTATE, "apply_schwarz before the shift is set");
+  if ((flags & kPrecCoarse) && !P->opt.coarse)
+    return set_error(DDEIG_ESTATE, "the problem was assembled without the coarse space");
+  API_GUARD_BEGIN
+  precond_apply(P, const_cast<double*>(r), z, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                flags);
+  check_launch("apply_schwarz");
+  return DDEIG_OK;
+  API_GUARD_END
+}
+
+static void fill_info(ddeig_problem* P, const PcgOut& o, int breakdown, ddeig_pcg_info* info) {
+  if (!info) return;
+  info->iters = o.iters;
+  info->relres = o.relres;
+  info->breakdown = breakdown;
+  if (info->hist && info->hist_cap > 0) {
+    const int cnt = std::min(std::min(info->hist_cap, o.iters + 1), P->hist_cap);
+    check_hip(hipMemcpyAsync(info->hist, P->hist, sizeof(double) * cnt, hipMemcpyDeviceToHost,
+                             P->stream), "copy history");
+    sync(P);
+  }
+}
+
+ddeig_status ddeig_stationary_ras(ddeig_problem* P, int levels, const double* b, double* x,
+                                  double rtol, int maxit, ddeig_pcg_info* info) {
+  if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
+  if (validate_vec(b, "b") || validate_vec(x, "x")) return DDEIG_EINVAL;
+  if (b == x) return set_error(DDEIG_EINVAL, "b and x must not alias");
+  if (levels != 1 && levels != 2) return set_error(DDEIG_EINVAL, "levels must be 1 or 2");
+  if (!(rtol >= 0.0) || !std::isfinite(rtol) || maxit < 0)
+    return set_error(DDEIG_EINVAL, "need rtol >= 0 and maxit >= 0");
+  if (!P->shifted) return set_error(DDEIG_ESTATE, "stationary_ras before the shift is set");
+  if (levels == 2 && !P->opt.coarse)
+    return set_error(DDEIG_ESTATE, "the problem was assembled without the coarse space");
+  API_GUARD_BEGIN
+  const PcgOut o = sras_run(P, levels, b, x, rtol, maxit);
+  fill_info(P, o, o.done == 2 ? 1 : 0, info);
+  if (o.done == 2) return set_error(DDEIG_ENOCONV, "stationary RAS diverged");
+  if (o.done != 1) return set_error(DDEIG_ENOCONV, "stationary RAS reached maxit");
+  return DDEIG_OK;
+  API_GUARD_END
+}
+
+ddeig_status ddeig_gmres_solve(ddeig_problem* P, int kind, const double* b, double* x, double rtol,
+                               int maxit, int restart, ddeig_pcg_info* info) {
+  if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
+  if (validate_vec(b, "b") || validate_vec(x, "x")) return DDEIG_EINVAL;
+  if (b == x) return set_error(DDEIG_EINVAL, "b and x must not alias");
+  const int flags = prec_flags(kind);
+  if (flags < 0) return set_error(DDEIG_EINVAL, "unknown preconditioner kind");
+  if (!(rtol >= 0.0) || !std::isfinite(rtol) || maxit < 0)
+    return set_error(DDEIG_EINVAL, "need rtol >= 0 and maxit >= 0");
+  if (!P->shifted) return set_error(DDEIG_ESTATE, "gmres_solve before the shift is set");
+  if ((flags & kPrecCoarse) && !P->opt.coarse)
+    return set_error(DDEIG_ESTATE, "the problem was assembled without the coarse space");
+  API_GUARD_BEGIN
+  const int m = std::max(1, restart > 0 ? std::min(restart, std::max(maxit, 1))
+                                        : std::min(std::max(maxit, 1), 300));
+  const PcgOut o = gmres_run(P, flags, b, x, rtol, maxit, m);
+  fill_info(P, o, o.done == 2 ? 1 : 0, info);
+  if (o.done == 2) return set_error(DDEIG_ENOCONV, "GMRES breakdown (zero Hessenberg column)");
+  if (o.done != 1) return set_error(DDEIG_ENOCONV, "GMRES reached maxit");
   return DDEIG_OK;
   API_GUARD_END
 }

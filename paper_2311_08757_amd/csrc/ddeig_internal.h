@@ -220,7 +220,9 @@ struct GemvRows {
 
 // PCG device state (one per problem).
 struct PcgState {
-  int done;      // 0 running, 1 converged, 2 p.Ap <= 0, 3 r.z <= 0, 4 maxit, 5 idle (batch)
+  int done;      // 0 running, 1 converged, 2 p.Ap <= 0 (CG) / divergence (stationary RAS) /
+                 // zero Hessenberg column (GMRES), 3 r.z <= 0, 4 maxit, 5 idle (batch),
+                 // 6 end of a GMRES restart cycle
   int iters;
   double rho[2]; // r.z of iterations of even / odd parity
   double r0n2;
@@ -336,6 +338,12 @@ struct ddeig_problem {
   double** lvp = nullptr;
   double* lpart = nullptr;
   double* lout = nullptr;
+  // GMRES work space (grown by ddeig_gmres_solve): basis V (gm_cap + 1 vectors),
+  // preconditioned basis Z (gm_cap vectors), stride gm_ldv; partials, Hessenberg
+  // matrix, rotations and small vectors
+  double* gmws = nullptr;
+  long gm_ldv = 0;
+  int gm_cap = 0;
   int* flag = nullptr;      // factorisation error flag
   double* gjbuf = nullptr;  // Gauss-Jordan row/column buffers (4 x gj_stride)
   int gj_stride = 0;
@@ -400,7 +408,9 @@ void launch_coarse_field(const ddeig_problem* P, const PcgState* st, hipStream_t
 void launch_coarse_rhs(const ddeig_problem* P, const double* r, const PcgState* st, hipStream_t s);
 void launch_coarse_phi(const ddeig_problem* P, hipStream_t s);
 void launch_extend(const ddeig_problem* P, const double* r, double* z, int coarse, Red* dot,
-                   PcgState* st, const CheckArgs& chk, hipStream_t s);
+                   PcgState* st, const CheckArgs& chk, hipStream_t s, int ras = 0);
+void launch_coarse_extend(const ddeig_problem* P, const double* r, double* z, Red* dot,
+                          const PcgState* st, hipStream_t s);
 void launch_symmetrise(double* A, int N, hipStream_t s);
 void launch_split_inverse(const double* Ainv, int m, int ld, void* Ah, void* Al, hipStream_t s);
 void launch_identity(double* v, int m, hipStream_t s);
@@ -452,6 +462,24 @@ void launch_lopcg_update(long n, double c0, double c1, double c2, double* x, con
                          double* p, hipStream_t s);
 int launch_lopcg_resid(long n, double lambda, const double* Ax, const double* Bx, double* r,
                        double* part, double* out, hipStream_t s);
+
+// Stationary RAS and GMRES (k_krylov.hip)
+void launch_sr_update(const ddeig_problem* P, const double* z, double* x, hipStream_t s);
+void launch_sr_check(const ddeig_problem* P, const Red& rr, int k, int maxit, hipStream_t s);
+int gm_blocks(long n);
+void launch_gm_dots(const ddeig_problem* P, int nv, const double* V, long ldv, const double* w,
+                    double* part, hipStream_t s);
+void launch_gm_sum(const ddeig_problem* P, int nv, const double* part, double* out, hipStream_t s);
+void launch_gm_axpy(const ddeig_problem* P, int nv, const double* V, long ldv, const double* h,
+                    double* w, double* nrm, hipStream_t s);
+void launch_gm_finish(const ddeig_problem* P, int j, int k, int maxit, int restart,
+                      const double* nrm, const double* h1, const double* h2, double* H, double* cs,
+                      double* sn, double* g, double* gm, hipStream_t s);
+void launch_gm_scale(const ddeig_problem* P, double* w, const double* gm, hipStream_t s);
+void launch_gm_start(const ddeig_problem* P, const Red& rr, const double* r, double* v0, double* g,
+                     double* gm, hipStream_t s);
+void launch_gm_update(const ddeig_problem* P, int nv, const double* Z, long ldv, const double* y,
+                      double* x, hipStream_t s);
 
 void check_hip(hipError_t e, const char* what);
 

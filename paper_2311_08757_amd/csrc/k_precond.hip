@@ -265,7 +265,10 @@ __global__ void __launch_bounds__(kBig) k_restrict_dense(Geo g, int delta, PcgSt
 }
 
 // z = sum_c R_c^T y_c + psi_ext cf (cf from k_coarse_field when coarse != 0).
-template <int PX, int KS>
+// RAS weights every local solution by the partition of unity,
+// z = sum_c R_c^T D_c y_c (+ the coarse term): the restricted additive Schwarz
+// extension of eq:dd-preconditioners, from the same per-axis covering tables.
+template <int PX, int KS, bool RAS = false>
 __device__ __forceinline__ void extend_dense_body(const Geo& g, int delta, int coarse,
                                                   PcgState* __restrict__ st, const CheckArgs& chk,
                                                   const DenseArgs& da,
@@ -273,7 +276,9 @@ __device__ __forceinline__ void extend_dense_body(const Geo& g, int delta, int c
                                                   const double* __restrict__ cf,
                                                   const double* __restrict__ r,
                                                   double* __restrict__ z, int use_dot,
-                                                  const Red& dot, int bid, int nblk) {
+                                                  const Red& dot, int bid, int nblk, int pu = 0,
+                                                  const XCover* __restrict__ xc0 = nullptr,
+                                                  const XCover* __restrict__ xc1 = nullptr) {
   constexpr int NC = Cover<PX>::NC;
   if (st != nullptr && st->done) return;
   if (chk.on) {
@@ -331,7 +336,14 @@ __device__ __forceinline__ void extend_dense_body(const Geo& g, int delta, int c
       float zq = 0.0f;
 #pragma unroll
       for (int sp = 0; sp < KS; ++sp) zq += zs[q][sp];
-      zl += (double)zq;
+      if constexpr (RAS) {
+        const XCover* xc[2] = {xc0, xc1};
+        const int c[3] = {cv.c0(q), cv.c1(q), 0};
+        const int which[2] = {q & 1, q >> 1};
+        zl += cover_weight(g, delta, pu, xc, c, i, which) * (double)zq;
+      } else {
+        zl += (double)zq;
+      }
     }
     // one rounding for the coarse term, whatever the compiler knows of `coarse`
     const double zv = coarse ? fma(ps, zc, zl) : zl;
@@ -341,15 +353,17 @@ __device__ __forceinline__ void extend_dense_body(const Geo& g, int delta, int c
   if (use_dot) write_partial_at<kBig>(acc, dot.part, bid);
 }
 
-template <int PX, int KS>
+template <int PX, int KS, bool RAS>
 __global__ void __launch_bounds__(kBig) k_extend_dense(Geo g, int delta, int coarse,
                                                        PcgState* __restrict__ st, CheckArgs chk,
                                                        DenseArgs da, const double* __restrict__ psi,
                                                        const double* __restrict__ cf,
                                                        const double* __restrict__ r,
-                                                       double* __restrict__ z, int use_dot, Red dot) {
-  extend_dense_body<PX, KS>(g, delta, coarse, st, chk, da, psi, cf, r, z, use_dot, dot, blockIdx.x,
-                            gridDim.x);
+                                                       double* __restrict__ z, int use_dot, Red dot,
+                                                       int pu, const XCover* __restrict__ xc0,
+                                                       const XCover* __restrict__ xc1) {
+  extend_dense_body<PX, KS, RAS>(g, delta, coarse, st, chk, da, psi, cf, r, z, use_dot, dot,
+                                 blockIdx.x, gridDim.x, pu, xc0, xc1);
 }
 
 DenseArgs dense_args(const ddeig_problem* P) {
@@ -547,7 +561,7 @@ void launch_coarse_field(const ddeig_problem* P, const PcgState* st, hipStream_t
 // With chk.on the kernel first applies the stopping test of PCG iteration k,
 // ||r_k|| <= rtol ||r_0|| (§4.1), records the history and, once CG stops,
 // does nothing else (every later kernel of the iteration sees `done`).
-__global__ void __launch_bounds__(kBig) k_extend(Geo g, int delta, int pu, int coarse,
+__global__ void __launch_bounds__(kBig) k_extend(Geo g, int delta, int pu, int coarse, int ras,
                                                    int ntypes, PcgState* __restrict__ st,
                                                    CheckArgs chk,
                                                    const TypeDev* __restrict__ types,
@@ -606,18 +620,19 @@ __global__ void __launch_bounds__(kBig) k_extend(Geo g, int delta, int pu, int c
         const int u1 = g.p == 2 ? a1.u[q1] : i[1];
         const long e = (a0.u[q0] + td.off[0]) +
                        (long)td.hm[0] * ((u1 + td.off[1]) + (long)td.hm[1] * (i2 + td.off[2]));
+        double zi;
         if (td.dense) {
           const float* zp = td.Z + (long)ts.slot * td.ld + e;
           float zs = 0.0f;
           for (int sp = 0; sp < td.ksplit; ++sp) zs += zp[sp * td.zsplit];
-          zl += (double)zs;
+          zi = (double)zs;
         } else {
-          zl += td.batch[(long)ts.slot * td.nch * td.b + e];
+          zi = td.batch[(long)ts.slot * td.nch * td.b + e];
         }
-        if (coarse) {
-          const int which[2] = {q0, q1};
-          zc += cover_weight(g, delta, pu, xc, c, i, which) * y0[sid];
-        }
+        const int which[2] = {q0, q1};
+        const double wc = (coarse || ras) ? cover_weight(g, delta, pu, xc, c, i, which) : 1.0;
+        zl += ras ? wc * zi : zi;
+        if (coarse) zc += wc * y0[sid];
       }
     }
     double zv = zl;
@@ -628,28 +643,64 @@ __global__ void __launch_bounds__(kBig) k_extend(Geo g, int delta, int pu, int c
   if (use_dot) write_partial<kBig>(acc, dot.part);
 }
 
+template <bool RAS>
+static auto dense_extend_kernel(int p, int ks) {
+  if (p == 1)
+    return ks == 1 ? k_extend_dense<1, 1, RAS>
+                   : (ks == 2 ? k_extend_dense<1, 2, RAS> : k_extend_dense<1, 3, RAS>);
+  return ks == 1 ? k_extend_dense<2, 1, RAS>
+                 : (ks == 2 ? k_extend_dense<2, 2, RAS> : k_extend_dense<2, 3, RAS>);
+}
+
 void launch_extend(const ddeig_problem* P, const double* r, double* z, int coarse, Red* dot,
-                   PcgState* st, const CheckArgs& chk, hipStream_t s) {
+                   PcgState* st, const CheckArgs& chk, hipStream_t s, int ras) {
   const int blocks = node_grid(P->g);
   const Red none{nullptr, 0, nullptr};
   if (dot) dot->np = blocks;
   if (P->opt.local_prec >= 2) {
     // the K split is 1..3 by construction (assemble)
-    auto kern = k_extend_dense<1, 1>;
-    const int ks = P->ksplit;
-    if (P->g.p == 1)
-      kern = ks == 1 ? k_extend_dense<1, 1> : (ks == 2 ? k_extend_dense<1, 2> : k_extend_dense<1, 3>);
-    else
-      kern = ks == 1 ? k_extend_dense<2, 1> : (ks == 2 ? k_extend_dense<2, 2> : k_extend_dense<2, 3>);
+    auto kern = ras ? dense_extend_kernel<true>(P->g.p, P->ksplit)
+                    : dense_extend_kernel<false>(P->g.p, P->ksplit);
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBig), 0, s, P->g, P->delta, coarse, st, chk,
-                       dense_args(P), P->psi, P->cfield, r, z, dot ? 1 : 0, dot ? *dot : none);
+                       dense_args(P), P->psi, P->cfield, r, z, dot ? 1 : 0, dot ? *dot : none,
+                       P->opt.pu, P->dXC[0], P->dXC[1]);
     return;
   }
   hipLaunchKernelGGL(k_extend, dim3(blocks), dim3(kBig), 0, s, P->g, P->delta, P->opt.pu,
-                     coarse, (int)P->types.size(), st, chk, P->dTypes, P->dSubTS, P->dXC[0],
+                     coarse, ras, (int)P->types.size(), st, chk, P->dTypes, P->dSubTS, P->dXC[0],
                      P->dXC[1],
                      P->psi, P->cy, r, z,
                      dot ? 1 : 0, dot ? *dot : none);
+}
+
+// The coarse correction alone, z = R_0^T y0 = psi_ext * cf at every node
+// (cf from k_coarse_field), with the partials of r.z when use_dot: the
+// correction step of eq:two-level-stationary-ras-mult-cc.
+__global__ void __launch_bounds__(kBlock) k_coarse_extend(Geo g, const PcgState* __restrict__ st,
+                                                          const double* __restrict__ psi,
+                                                          const double* __restrict__ cf,
+                                                          const double* __restrict__ r,
+                                                          double* __restrict__ z, int use_dot,
+                                                          Red dot) {
+  if (st != nullptr && st->done) return;
+  double acc = 0.0;
+  for (long k = blockIdx.x * (long)kBlock + threadIdx.x; k < g.n; k += (long)gridDim.x * kBlock) {
+    int i0, i1, i2;
+    unflatten(g, k, i0, i1, i2);
+    const double v = psi[table_node(g, i0, i1, i2)] * cf[g.p == 1 ? (long)i0 : i0 + (long)g.N[0] * i1];
+    z[k] = v;
+    acc += r[k] * v;
+  }
+  if (use_dot) write_partial(acc, dot.part);
+}
+
+void launch_coarse_extend(const ddeig_problem* P, const double* r, double* z, Red* dot,
+                          const PcgState* st, hipStream_t s) {
+  const int blocks = (int)std::max<long>(1, std::min<long>((P->g.n + kBlock - 1) / kBlock, kMaxRed));
+  const Red none{nullptr, 0, nullptr};
+  if (dot) dot->np = blocks;
+  hipLaunchKernelGGL(k_coarse_extend, dim3(blocks), dim3(kBlock), 0, s, P->g, st, P->psi,
+                     P->cfield, r, z, dot ? 1 : 0, dot ? *dot : none);
 }
 
 // phi_c(k) = D_c(k) psi_ext(k) on box c, 0 elsewhere (column c of R_0^T).

@@ -64,7 +64,8 @@ class LopcgInfo(ctypes.Structure):
 
 
 EXPORTS = ["ddeig_assemble", "ddeig_cell_shift", "ddeig_set_shift", "ddeig_apply_op",
-           "ddeig_apply_precond", "ddeig_pcg_solve", "ddeig_inverse_iteration", "ddeig_lopcg",
+           "ddeig_apply_precond", "ddeig_apply_schwarz", "ddeig_stationary_ras",
+           "ddeig_gmres_solve", "ddeig_pcg_solve", "ddeig_inverse_iteration", "ddeig_lopcg",
            "ddeig_profile_kernel", "ddeig_potential_form", "ddeig_batch_create",
            "ddeig_batch_query", "ddeig_batch_pcg_solve", "ddeig_batch_inverse_iteration",
            "ddeig_batch_destroy", "ddeig_query", "ddeig_destroy", "ddeig_status_string",
@@ -90,6 +91,11 @@ def load_library(path=LIB_PATH):
     lib.ddeig_set_shift.argtypes = [P, ctypes.c_double, dp]
     lib.ddeig_apply_op.argtypes = [P, ctypes.c_int, P, P]
     lib.ddeig_apply_precond.argtypes = [P, P, P]
+    lib.ddeig_apply_schwarz.argtypes = [P, ctypes.c_int, P, P]
+    lib.ddeig_stationary_ras.argtypes = [P, ctypes.c_int, P, P, ctypes.c_double, ctypes.c_int,
+                                         ctypes.POINTER(PcgInfo)]
+    lib.ddeig_gmres_solve.argtypes = [P, ctypes.c_int, P, P, ctypes.c_double, ctypes.c_int,
+                                      ctypes.c_int, ctypes.POINTER(PcgInfo)]
     lib.ddeig_pcg_solve.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int,
                                     ctypes.POINTER(PcgInfo)]
     lib.ddeig_inverse_iteration.argtypes = [P, P, ctypes.c_double, ctypes.c_int, ctypes.c_double,
@@ -275,21 +281,56 @@ def apply_precond(prob, r, z):
                                               _ptr(z, prob.n_dof, "z")), "ddeig_apply_precond")
 
 
-def pcg_solve(prob, b, x, rtol=1e-10, maxit=1000, hist_cap=0, raise_on_error=True):
-    """ddeig_pcg_solve; returns dict(status, iters, relres, breakdown, hist)."""
-    lib = load_library()
+def _krylov(fn, name, prob, lead, b, x, tail, hist_cap, raise_on_error):
     info = PcgInfo()
     hist = np.zeros(max(hist_cap, 1))
     info.hist = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if hist_cap > 0 else None
     info.hist_cap = hist_cap
-    st = lib.ddeig_pcg_solve(prob.handle, _ptr(b, prob.n_dof, "b"), _ptr(x, prob.n_dof, "x"),
-                             float(rtol), int(maxit), ctypes.byref(info))
+    st = fn(prob.handle, *lead, _ptr(b, prob.n_dof, "b"), _ptr(x, prob.n_dof, "x"), *tail,
+            ctypes.byref(info))
     out = dict(status=STATUS.get(st, st), iters=info.iters, relres=info.relres,
                breakdown=info.breakdown,
                hist=hist[:min(hist_cap, info.iters + 1)] if hist_cap > 0 else None)
     if raise_on_error and st != DDEIG_OK:
-        _check(st, "ddeig_pcg_solve")
+        _check(st, name)
     return out
+
+
+def pcg_solve(prob, b, x, rtol=1e-10, maxit=1000, hist_cap=0, raise_on_error=True):
+    """ddeig_pcg_solve; returns dict(status, iters, relres, breakdown, hist)."""
+    lib = load_library()
+    return _krylov(lib.ddeig_pcg_solve, "ddeig_pcg_solve", prob, (), b, x,
+                   (float(rtol), int(maxit)), hist_cap, raise_on_error)
+
+
+PREC_KINDS = {"as1": 0, "as2": 1, "ras1": 2, "ras2": 3, "coarse": 4}
+
+
+def _prec_kind(kind):
+    return PREC_KINDS[kind] if isinstance(kind, str) else int(kind)
+
+
+def apply_schwarz(prob, kind, r, z):
+    """ddeig_apply_schwarz: z = M^{-1} r for kind 'as1', 'as2', 'ras1', 'ras2' or 'coarse'."""
+    _check(load_library().ddeig_apply_schwarz(prob.handle, _prec_kind(kind),
+                                              _ptr(r, prob.n_dof, "r"), _ptr(z, prob.n_dof, "z")),
+           "ddeig_apply_schwarz")
+
+
+def stationary_ras(prob, b, x, levels=2, rtol=1e-10, maxit=10000, hist_cap=0,
+                   raise_on_error=True):
+    """ddeig_stationary_ras; returns dict(status, iters, relres, breakdown, hist)."""
+    lib = load_library()
+    return _krylov(lib.ddeig_stationary_ras, "ddeig_stationary_ras", prob, (int(levels),), b, x,
+                   (float(rtol), int(maxit)), hist_cap, raise_on_error)
+
+
+def gmres_solve(prob, b, x, kind="ras2", rtol=1e-10, maxit=1000, restart=0, hist_cap=0,
+                raise_on_error=True):
+    """ddeig_gmres_solve (right-preconditioned); returns dict(status, iters, relres, breakdown, hist)."""
+    lib = load_library()
+    return _krylov(lib.ddeig_gmres_solve, "ddeig_gmres_solve", prob, (_prec_kind(kind),), b, x,
+                   (float(rtol), int(maxit), int(restart)), hist_cap, raise_on_error)
 
 
 def inverse_iteration(prob, x, tol_x=1e-9, maxit_outer=100, rtol_inner=1e-10, maxit_inner=1000,
