@@ -21,10 +21,11 @@ Readings (the paper gives no details of these steps):
   of the directions S represents numerically, and the smallest eigenpair of
   T^T (S^T A S) T gives the coefficients;
 - the Ritz vector's sign is fixed so that 1^T B x > 0 (as in ipm.py);
-- inner solves: PCG from a zero guess with a relative tolerance, either fixed
-  or adaptive, rtol_k = min(0.1, ||r_k||_2) (§4.3); the fused variant skips
-  the inner Krylov solve and applies the preconditioner once, w_k = M^{-1} r_k
-  (§4.3).
+- inner solves: from a zero guess with a relative tolerance, either fixed or
+  adaptive, rtol_k = min(0.1, ||r_k||_2) (§4.3), by PCG or by any other solver
+  of A_sigma w = r_k passed in (GMRES+RAS2 or the stationary RAS iterations of
+  §4.2, from ras.py); the fused variant skips the inner solve and applies the
+  preconditioner once, w_k = M^{-1} r_k (§4.3, with M_RAS,2 there).
 """
 import numpy as np
 import scipy.linalg as sla
@@ -56,11 +57,13 @@ def rayleigh_ritz(S, AS, BS):
 
 
 def si_lopcg(A, B, sigma, x0, x1, tol_o=1e-8, kmax=200, mode="fixed", rtol_i=1e-8,
-             maxit_i=10000, precond=None):
+             maxit_i=10000, precond=None, inner_solve=None):
     """Returns dict(lam, x, its, inner (per outer step), res_hist).
 
-    mode: "fixed" (PCG to rtol_i), "adaptive" (PCG to min(0.1, ||r||_2)),
+    mode: "fixed" (inner solve to rtol_i), "adaptive" (to min(0.1, ||r||_2)),
     "fused" (w = precond(r)).  precond(v) applies the preconditioner M^{-1}.
+    inner_solve(rhs, rtol, maxit) -> (w, iterations) replaces the default PCG
+    with precond.
     """
     A_sigma = (A - sigma * B).tocsr()
 
@@ -80,9 +83,12 @@ def si_lopcg(A, B, sigma, x0, x1, tol_o=1e-8, kmax=200, mode="fixed", rtol_i=1e-
             inner.append(1)
         else:
             rt = rtol_i if mode == "fixed" else min(0.1, res[-1])
-            out = pcg(lambda v: A_sigma @ v, r, precond, rtol=rt, maxit=maxit_i)
-            w = out.x
-            inner.append(out.iters)
+            if inner_solve is None:
+                out = pcg(lambda v: A_sigma @ v, r, precond, rtol=rt, maxit=maxit_i)
+                w, its = out.x, out.iters
+            else:
+                w, its = inner_solve(r, rt, maxit_i)
+            inner.append(its)
         Bx = B @ x
         wt = w - (Bx @ w) * x
         p = x - x_prev

@@ -98,3 +98,65 @@ def test_inner_work_ordering():
         assert out["res_hist"][-1] <= 1e-8
         tot[mode] = int(out["inner"].sum())
     assert tot["fused"] < tot["adaptive"] < tot["fixed"], tot
+
+
+def _inner_solvers(P):
+    from oracle.ras import RestrictedAdditiveSchwarz, gmres_right, stationary_ras
+    As = P.A_sigma
+    r1 = RestrictedAdditiveSchwarz(As, P.subs, P.D)
+    r2 = RestrictedAdditiveSchwarz(As, P.subs, P.D, P.R0T)
+
+    def wrap(f):
+        def solve(b, rt, mi):
+            o = f(b, rt, mi)
+            return o["x"], o["iters"]
+        return solve
+    return {
+        "ras1": wrap(lambda b, rt, mi: stationary_ras(As, b, r1, False, rtol=rt, maxit=mi)),
+        "ras2": wrap(lambda b, rt, mi: stationary_ras(As, b, r2, True, rtol=rt, maxit=mi)),
+        "cg+asm2": None,
+        "gmres+ras2": wrap(lambda b, rt, mi: gmres_right(As, b, r2.apply, rtol=rt, maxit=mi)),
+    }
+
+
+def test_inner_solvers_of_table2():
+    """§4.2 (Table 2): with stationary RAS1 / RAS2, CG+ASM2 or GMRES+RAS2 as the
+    inner solver (fixed rTOL_i = TOL_o = 1e-8, zero initial guesses) the outer
+    iterations do not change, the total inner work orders as
+    GMRES+RAS2 < CG+ASM2 < RAS2 < RAS1, and the worst inner solve of RAS1 grows
+    with L while that of RAS2 stays bounded."""
+    mx = {}
+    for L in (4, 8):
+        P = _P(L=L)
+        w, xr = _dense(P)
+        n = P.grid.n
+        prec = P.preconditioner(True)
+        its, tot = {}, {}
+        for name, solve in _inner_solvers(P).items():
+            out = si_lopcg(P.A, P.M, P.sigma, unit_first(n), np.ones(n), tol_o=1e-8, kmax=500,
+                           mode="fixed", rtol_i=1e-8, maxit_i=10000, precond=prec.apply,
+                           inner_solve=solve)
+            assert out["res_hist"][-1] <= 1e-8
+            assert abs(out["lam"] - w[0]) <= 1e-10 * abs(w[0]), name
+            its[name], tot[name] = out["its"], int(out["inner"].sum())
+            mx[name, L] = int(out["inner"].max())
+        assert max(its.values()) - min(its.values()) <= 1, its
+        assert tot["gmres+ras2"] < tot["cg+asm2"] < tot["ras2"] < tot["ras1"], tot
+    assert mx["ras1", 8] >= 3 * mx["ras1", 4], mx
+    assert mx["ras2", 8] <= 1.3 * mx["ras2", 4], mx
+
+
+def test_fused_with_ras2_preconditioner():
+    """§4.3 uses M_RAS,2 directly as the LOPCG preconditioner; it converges to
+    the dense eigenpair like the M_ASM,2 variant."""
+    from oracle.ras import RestrictedAdditiveSchwarz
+    P = _P(L=6)
+    w, xr = _dense(P)
+    n = P.grid.n
+    r2 = RestrictedAdditiveSchwarz(P.A_sigma, P.subs, P.D, P.R0T)
+    out = si_lopcg(P.A, P.M, P.sigma, unit_first(n), np.ones(n), tol_o=1e-10, kmax=2000,
+                   mode="fused", precond=r2.apply)
+    assert out["res_hist"][-1] <= 1e-10
+    assert abs(out["lam"] - w[0]) <= 1e-11 * abs(w[0])
+    d = out["x"] - xr
+    assert np.sqrt(d @ (P.M @ d)) <= 1e-8
