@@ -371,23 +371,55 @@ def main():
     # the paper's outer variant (alg:si-lopcg) on the same problem and
     # accuracy: time to the eigenpair with fixed / adaptive inner tolerances
     # and with the preconditioner applied directly (fused)
+    # (keys: mode, or inner solver and mode: CG+ASM2 is the default inner
+    # solver, gmres_ras2 / stationary_ras2 those of §4.2, ras2_fused applies
+    # M_RAS,2 once per step as in §4.3)
     outer = None
     if not args.no_compare:
         outer = {}
-        for mode in ("fixed", "adaptive", "fused"):
+        variants = [("fixed", "fixed", "cg"), ("adaptive", "adaptive", "cg"),
+                    ("fused", "fused", "cg"), ("gmres_ras2_fixed", "fixed", "gmres"),
+                    ("gmres_ras2_adaptive", "adaptive", "gmres"), ("ras2_fused", "fused", "gmres"),
+                    ("stationary_ras2_fixed", "fixed", "ras2")]
+        for key, mode, inner_solver in variants:
             for rep in range(2):   # the first run allocates the work space
                 x.zero_()
                 torch.cuda.synchronize()
                 t1 = time.perf_counter()
-                o = dd.lopcg(prob, x, tol_o=1e-9, maxit_outer=5000, mode=mode, rtol_inner=1e-8)
+                o = dd.lopcg(prob, x, tol_o=1e-9, maxit_outer=5000, mode=mode, rtol_inner=1e-8,
+                             inner=inner_solver)
                 torch.cuda.synchronize()
                 tl = time.perf_counter() - t1
             err = abs(o["lam"] - gold["lam"]) / abs(gold["lam"]) if gold is not None else None
-            outer[mode] = {"time_to_eigenpair_ms": tl * 1e3, "outer_its": o["outer_its"],
-                           "inner_sum": o["inner_sum"], "res_norm": o["res_norm"],
-                           "lambda_rel_err_vs_oracle": err}
-            print(f"# SI-LOPCG {mode}: {tl * 1e3:.1f} ms, outer {o['outer_its']}, inner "
+            outer[key] = {"time_to_eigenpair_ms": tl * 1e3, "outer_its": o["outer_its"],
+                          "inner_sum": o["inner_sum"], "inner_max": o["inner_max"],
+                          "res_norm": o["res_norm"], "lambda_rel_err_vs_oracle": err}
+            print(f"# SI-LOPCG {key}: {tl * 1e3:.1f} ms, outer {o['outer_its']}, inner "
                   f"{o['inner_sum']}, lambda err {err}", file=sys.stderr, flush=True)
+
+    # one shifted solve A_sigma u = b (b seeded, rtol 1e-10) by each inner solver
+    solvers = None
+    if not args.no_compare:
+        solvers = {}
+        bvec = torch.as_tensor(W.random_vector(n, 15), dtype=torch.float64, device="cuda")
+        u = torch.zeros_like(bvec)
+        runs = {"cg_asm2": lambda: dd.pcg_solve(prob, bvec, u, rtol=1e-10, maxit=2000),
+                "gmres_ras2": lambda: dd.gmres_solve(prob, bvec, u, kind="ras2", rtol=1e-10,
+                                                     maxit=2000),
+                "stationary_ras2": lambda: dd.stationary_ras(prob, bvec, u, levels=2, rtol=1e-10,
+                                                             maxit=5000)}
+        for key, f in runs.items():
+            for rep in range(2):
+                u.zero_()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                o = f()
+                torch.cuda.synchronize()
+                tl = time.perf_counter() - t1
+            solvers[key] = {"time_ms": tl * 1e3, "iters": o["iters"],
+                            "us_per_iter": tl * 1e6 / max(o["iters"], 1), "relres": o["relres"]}
+            print(f"# solve {key}: {tl * 1e3:.1f} ms, {o['iters']} its", file=sys.stderr,
+                  flush=True)
 
     cpu = None
     if not args.no_cpu:
@@ -424,6 +456,7 @@ def main():
         "stencil_roofline": stencil_roof,
         "fp64_comparison": cmp,
         "si_lopcg": outer,
+        "inner_solvers": solvers,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

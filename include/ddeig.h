@@ -226,7 +226,7 @@ typedef struct {
   double lambda;      /* x^T A x of the final, M-normalised x */
   double res_norm;    /* ||A x - lambda M x||_2 */
   int outer_its;
-  long inner_sum;     /* PCG iterations (modes 0, 1) or preconditioner applications (mode 2) */
+  long inner_sum;     /* inner iterations (modes 0, 1) or preconditioner applications (mode 2) */
   int inner_max;
   double t_solve_ms;
 } ddeig_lopcg_info;
@@ -239,15 +239,28 @@ typedef struct {
  * against x_k, with p = x_k - x_{k-1} for x_{k-1}; directions whose scaled
  * Gram eigenvalue is below 1e-10 of the largest are dropped), M-normalised
  * with 1^T M x > 0; it stops when ||r_k||_2 <= tol_o (M-normalised x) or
- * after maxit_outer steps.  mode 0: PCG from zero to the relative tolerance
- * rtol_inner; 1: PCG to min(0.1, ||r_k||_2); 2: one application of the
- * two-level preconditioner, w_k = M_AS^{-1} r_k (no inner Krylov solve).
- * x: in the start vector x_1 (all zeros selects the constant vector), out
- * the eigenvector; x_prev (nullable): x_0, default the first unit vector.
- * Needs the shift; synchronises the library stream.  Returns DDEIG_ENOCONV
- * at maxit_outer, DDEIG_ENOTSPD on a CG breakdown of an inner solve. */
+ * after maxit_outer steps.  mode 0: the inner solver `inner` from zero to the
+ * relative tolerance rtol_inner; 1: to min(0.1, ||r_k||_2); 2: one
+ * application of the two-level preconditioner, w_k = M^{-1} r_k (no inner
+ * solve; inner selects M_AS,2 (CG_AS2) or M_RAS,2 (GMRES_RAS2), the latter
+ * being the fused variant of §4.3).  Inner solvers (§4.2, Table 2): CG with
+ * the problem's additive Schwarz preconditioner, GMRES with M_RAS,2 (restart
+ * min(maxit_inner, 300)), stationary RAS2 (multiplicative coarse
+ * correction), stationary RAS1; an inner solve that reaches maxit_inner
+ * leaves its last iterate and the outer iteration continues.  x: in the
+ * start vector x_1 (all zeros selects the constant vector), out the
+ * eigenvector; x_prev (nullable): x_0, default the first unit vector.  Needs
+ * the shift (and options.coarse = 1 for the RAS2 solvers); synchronises the
+ * library stream.  Returns DDEIG_ENOCONV at maxit_outer or when an inner
+ * GMRES breaks down or a stationary solve diverges, DDEIG_ENOTSPD on a CG
+ * breakdown of an inner solve. */
+#define DDEIG_INNER_CG_AS2 0
+#define DDEIG_INNER_GMRES_RAS2 1
+#define DDEIG_INNER_RAS2 2
+#define DDEIG_INNER_RAS1 3
+
 ddeig_status ddeig_lopcg(ddeig_problem* P, double* x, const double* x_prev, double tol_o,
-                         int maxit_outer, int mode, double rtol_inner, int maxit_inner,
+                         int maxit_outer, int mode, int inner, double rtol_inner, int maxit_inner,
                          ddeig_lopcg_info* info);
 
 /* Measurement support: launches one kernel (or step) of the hot path `reps`

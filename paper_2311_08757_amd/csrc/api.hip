@@ -1186,7 +1186,7 @@ void ddeig_destroy(ddeig_problem* P) {
 }
 
 ddeig_status ddeig_lopcg(ddeig_problem* P, double* x, const double* x_prev, double tol_o,
-                         int maxit_outer, int mode, double rtol_inner, int maxit_inner,
+                         int maxit_outer, int mode, int inner, double rtol_inner, int maxit_inner,
                          ddeig_lopcg_info* info) {
   if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
   if (validate_vec(x, "x")) return DDEIG_EINVAL;
@@ -1195,7 +1195,12 @@ ddeig_status ddeig_lopcg(ddeig_problem* P, double* x, const double* x_prev, doub
       (mode == 0 && (!(rtol_inner >= 0.0) || !std::isfinite(rtol_inner))) ||
       (mode < 2 && maxit_inner < 1))
     return set_error(DDEIG_EINVAL, "invalid tolerances, iteration limits or mode");
+  if (inner < DDEIG_INNER_CG_AS2 || inner > DDEIG_INNER_RAS1 ||
+      (mode == 2 && inner > DDEIG_INNER_GMRES_RAS2))
+    return set_error(DDEIG_EINVAL, "invalid inner solver for this mode");
   if (!P->shifted) return set_error(DDEIG_ESTATE, "lopcg before the shift is set");
+  if ((inner == DDEIG_INNER_GMRES_RAS2 || inner == DDEIG_INNER_RAS2) && !P->opt.coarse)
+    return set_error(DDEIG_ESTATE, "the problem was assembled without the coarse space");
   API_GUARD_BEGIN
   const hipStream_t s = P->stream;
   const long n = P->g.n;
@@ -1254,12 +1259,28 @@ ddeig_status ddeig_lopcg(ddeig_problem* P, double* x, const double* x_prev, doub
     launch_fill(W, n, 0.0, s);
     int its = 1;
     if (mode == 2) {
-      precond_apply(P, R, W, nullptr, nullptr);
+      precond_apply(P, R, W, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                    inner == DDEIG_INNER_GMRES_RAS2 ? kPrecLocal | kPrecCoarse | kPrecRas : -1);
     } else {
+      // the inner solve; reaching maxit_inner is not an error (the outer
+      // iteration goes on with the last inner iterate, as in §4.2)
       const double rt = mode == 0 ? rtol_inner : std::min(0.1, res);
-      const PcgOut o = pcg_run(P, R, W, rt, maxit_inner);
-      if (o.done == 2 || o.done == 3) {
+      PcgOut o;
+      if (inner == DDEIG_INNER_CG_AS2)
+        o = pcg_run(P, R, W, rt, maxit_inner);
+      else if (inner == DDEIG_INNER_GMRES_RAS2)
+        o = gmres_run(P, kPrecLocal | kPrecCoarse | kPrecRas, R, W, rt, maxit_inner,
+                      std::min(maxit_inner, 300));
+      else
+        o = sras_run(P, inner == DDEIG_INNER_RAS2 ? 2 : 1, R, W, rt, maxit_inner);
+      if (inner == DDEIG_INNER_CG_AS2 && (o.done == 2 || o.done == 3)) {
         st = set_error(DDEIG_ENOTSPD, "CG breakdown inside LOPCG");
+        break;
+      }
+      if (o.done == 2) {
+        st = set_error(DDEIG_ENOCONV, inner == DDEIG_INNER_GMRES_RAS2
+                                          ? "GMRES breakdown inside LOPCG"
+                                          : "the stationary RAS inner solve diverged");
         break;
       }
       its = o.iters;

@@ -101,7 +101,8 @@ def load_library(path=LIB_PATH):
     lib.ddeig_inverse_iteration.argtypes = [P, P, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                             ctypes.c_int, ctypes.POINTER(EigInfo)]
     lib.ddeig_lopcg.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int, ctypes.c_int,
-                                ctypes.c_double, ctypes.c_int, ctypes.POINTER(LopcgInfo)]
+                                ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                ctypes.POINTER(LopcgInfo)]
     lib.ddeig_profile_kernel.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, dp, dp]
     lib.ddeig_potential_form.argtypes = [P, ctypes.c_int, ctypes.POINTER(Potential), P, P, dp]
     PP = ctypes.POINTER(ctypes.c_void_p)
@@ -465,16 +466,22 @@ def batch_inverse_iteration(batch, xs, tol_x=1e-9, maxit_outer=100, rtol_inner=1
 LOPCG_MODES = {"fixed": 0, "adaptive": 1, "fused": 2}
 
 
+LOPCG_INNER = {"cg": 0, "cg+asm2": 0, "gmres": 1, "gmres+ras2": 1, "ras2": 2, "ras1": 3}
+
+
 def lopcg(prob, x, x_prev=None, tol_o=1e-8, maxit_outer=500, mode="fixed", rtol_inner=1e-8,
-          maxit_inner=10000, raise_on_error=True):
+          maxit_inner=10000, inner="cg", raise_on_error=True):
     """ddeig_lopcg: inexact SI-preconditioned LOPCG; x in: start (zeros: constant), out:
-    eigenvector; x_prev: x_0 (None: first unit vector).  mode: fixed / adaptive / fused."""
+    eigenvector; x_prev: x_0 (None: first unit vector).  mode: fixed / adaptive / fused;
+    inner: cg (CG+ASM2), gmres (GMRES+RAS2), ras2, ras1 (stationary); with fused, cg
+    applies M_AS,2 and gmres M_RAS,2."""
     lib = load_library()
     info = LopcgInfo()
     m = LOPCG_MODES[mode] if isinstance(mode, str) else int(mode)
+    inn = LOPCG_INNER[inner] if isinstance(inner, str) else int(inner)
     xp = _ptr(x_prev, prob.n_dof, "x_prev") if x_prev is not None else None
     st = lib.ddeig_lopcg(prob.handle, _ptr(x, prob.n_dof, "x"), xp, float(tol_o), int(maxit_outer),
-                         m, float(rtol_inner), int(maxit_inner), ctypes.byref(info))
+                         m, inn, float(rtol_inner), int(maxit_inner), ctypes.byref(info))
     out = dict(status=STATUS.get(st, st), lam=info.lambda_, res_norm=info.res_norm,
                outer_its=info.outer_its, inner_sum=info.inner_sum, inner_max=info.inner_max,
                t_solve_ms=info.t_solve_ms)

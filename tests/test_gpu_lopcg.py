@@ -10,7 +10,12 @@ x_1 = constant) and inner variants.
   outer quantities are exact);
 - the ordering of total inner work reported in §4.3: fused < adaptive < fixed;
 - the full-size 2-D L = 256 workload (bf16 local solves, fused): lambda
-  against the stored oracle value to 1e-10 relative.
+  against the stored oracle value to 1e-10 relative;
+- the inner solvers of §4.2 (Table 2) -- GMRES+RAS2, stationary RAS2 and
+  RAS1 -- and the fused step with M_RAS,2 (§4.3) against the oracle with the
+  same inner solver (FP64 local solves, the bars above); on the GPU the outer
+  iterations do not depend on the inner solver and the total inner work orders
+  as GMRES+RAS2 < CG+ASM2 < RAS2 < RAS1.
 """
 import json
 import os
@@ -101,6 +106,10 @@ def test_lopcg_errors(torch):
     with pytest.raises(dd.DdeigError):
         dd.lopcg(prob, x, mode=3)
     with pytest.raises(dd.DdeigError):
+        dd.lopcg(prob, x, mode="fused", inner="ras2")  # fused takes AS2 or RAS2 only
+    with pytest.raises(dd.DdeigError):
+        dd.lopcg(prob, x, inner=4)
+    with pytest.raises(dd.DdeigError):
         dd.lopcg(prob, x, x_prev=x)             # aliasing
     out = dd.lopcg(prob, x, tol_o=1e-14, maxit_outer=2, mode="fused", raise_on_error=False)
     assert out["status"] == "ENOCONV" and out["outer_its"] == 2
@@ -120,3 +129,85 @@ def test_lopcg_config2_fused(torch):
     assert abs(out["lam"] - gd["lam"]) <= 1e-10 * abs(gd["lam"])
     xs = x.cpu().numpy()[gd["sample_idx"]]
     assert np.max(np.abs(xs - np.array(gd["sample_x"]))) <= 1e-7
+
+
+def _oracle_inner(P, inner):
+    from oracle.ras import RestrictedAdditiveSchwarz, gmres_right, stationary_ras
+    As = P.A_sigma
+    if inner == "gmres":
+        r2 = RestrictedAdditiveSchwarz(As, P.subs, P.D, P.R0T)
+        f = lambda b, rt, mi: gmres_right(As, b, r2.apply, rtol=rt, maxit=mi, restart=min(mi, 300))
+    else:
+        lv = 2 if inner == "ras2" else 1
+        ras = RestrictedAdditiveSchwarz(As, P.subs, P.D, P.R0T if lv == 2 else None)
+        f = lambda b, rt, mi: stationary_ras(As, b, ras, two_level=lv == 2, rtol=rt, maxit=mi)
+
+    def solve(b, rt, mi):
+        o = f(b, rt, mi)
+        return o["x"], o["iters"]
+    return solve
+
+
+@pytest.mark.parametrize("inner", ["gmres", "ras2", "ras1"])
+@pytest.mark.parametrize("case", [CASES[0], CASES[3]], ids=[IDS[0], IDS[3]])
+def test_lopcg_inner_solver_parity(torch, case, inner):
+    import paper_2311_08757_amd as dd
+    from oracle.lopcg import si_lopcg, unit_first
+    from oracle.problem import Problem
+    p, q, L, ne, delta, V = case
+    P = Problem(W.small_config(p, q, L, ne, delta, V))
+    n = P.grid.n
+    ref = si_lopcg(P.A, P.M, P.sigma, unit_first(n), np.ones(n), tol_o=1e-10, kmax=500,
+                   mode="fixed", rtol_i=1e-10, maxit_i=10000,
+                   precond=P.preconditioner(True).apply, inner_solve=_oracle_inner(P, inner))
+    prob = dd.assemble(p, q, L, ne, V, delta)
+    dd.cell_shift(prob)
+    x = torch.zeros(prob.n_dof, dtype=torch.float64, device="cuda")
+    out = dd.lopcg(prob, x, tol_o=1e-10, maxit_outer=500, mode="fixed", rtol_inner=1e-10,
+                   inner=inner)
+    assert out["res_norm"] <= 1e-10
+    assert abs(out["lam"] - ref["lam"]) <= 1e-11 * abs(ref["lam"])
+    d = x.cpu().numpy() - ref["x"]
+    assert np.sqrt(d @ (P.M @ d)) <= 1e-8
+    assert abs(out["outer_its"] - ref["its"]) <= 1, (out["outer_its"], ref["its"])
+    tot = int(ref["inner"].sum())
+    assert abs(out["inner_sum"] - tot) <= max(2, 0.1 * tot), (out["inner_sum"], tot)
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[3]], ids=[IDS[0], IDS[3]])
+def test_lopcg_fused_ras2_parity(torch, case):
+    """§4.3: M_RAS,2 applied once per outer step."""
+    import paper_2311_08757_amd as dd
+    from oracle.lopcg import si_lopcg, unit_first
+    from oracle.problem import Problem
+    from oracle.ras import RestrictedAdditiveSchwarz
+    p, q, L, ne, delta, V = case
+    P = Problem(W.small_config(p, q, L, ne, delta, V))
+    n = P.grid.n
+    r2 = RestrictedAdditiveSchwarz(P.A_sigma, P.subs, P.D, P.R0T)
+    ref = si_lopcg(P.A, P.M, P.sigma, unit_first(n), np.ones(n), tol_o=1e-10, kmax=3000,
+                   mode="fused", precond=r2.apply)
+    prob = dd.assemble(p, q, L, ne, V, delta)
+    dd.cell_shift(prob)
+    x = torch.zeros(prob.n_dof, dtype=torch.float64, device="cuda")
+    out = dd.lopcg(prob, x, tol_o=1e-10, maxit_outer=3000, mode="fused", inner="gmres")
+    assert abs(out["lam"] - ref["lam"]) <= 1e-11 * abs(ref["lam"])
+    d = x.cpu().numpy() - ref["x"]
+    assert np.sqrt(d @ (P.M @ d)) <= 1e-8
+    assert abs(out["outer_its"] - ref["its"]) <= 1, (out["outer_its"], ref["its"])
+
+
+def test_lopcg_table2_ordering(torch):
+    """§4.2 (Table 2) on the GPU, bf16 local solves, fixed rTOL_i = TOL_o = 1e-8."""
+    import paper_2311_08757_amd as dd
+    p, q, L, ne, delta, V = (1, 1, 8, 8, 2, W.sep_fourier(1000))
+    prob = dd.assemble(p, q, L, ne, V, delta, local_prec="bf16")
+    dd.cell_shift(prob)
+    its, tot = {}, {}
+    for inner in ("ras1", "ras2", "cg", "gmres"):
+        x = torch.zeros(prob.n_dof, dtype=torch.float64, device="cuda")
+        out = dd.lopcg(prob, x, tol_o=1e-8, maxit_outer=500, mode="fixed", rtol_inner=1e-8,
+                       inner=inner)
+        its[inner], tot[inner] = out["outer_its"], out["inner_sum"]
+    assert max(its.values()) - min(its.values()) <= 1, its
+    assert tot["gmres"] < tot["cg"] < tot["ras2"] < tot["ras1"], tot
