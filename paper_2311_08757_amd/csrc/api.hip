@@ -372,11 +372,11 @@ PcgOut sras_run(ddeig_problem* P, int levels, const double* b, double* x, double
   return o;
 }
 
-// GMRES work space for restart length m: V (m + 1 vectors), Z (m vectors),
-// the dot partials ((m + 1) x blocks), the norm partials, H ((m + 1) x m),
-// rotations cs, sn (m), g, h1, h2 (m + 1), scalars and y (m).
+// GMRES work space for restart length m: V (m + 1 vectors), Z (m vectors), w,
+// the dot partials ((2m + 3) rows x blocks) and their sums d, H ((m + 1) x m),
+// rotations cs, sn (m), g (m + 1), the first-pass scales c (m + 1), scalars and y (m).
 struct GmWs {
-  double *V, *Z, *part, *nrm, *H, *cs, *sn, *g, *h1, *h2, *gm, *y;
+  double *V, *Z, *w, *part, *d, *H, *cs, *sn, *g, *cv, *gm, *y;
   long ldv;
 };
 
@@ -384,17 +384,16 @@ GmWs gm_workspace(ddeig_problem* P, int m) {
   const long n = P->g.n;
   const long ldv = (n + 63) / 64 * 64;
   const long nb = gm_blocks(n);
-  // offsets of the parts in doubles
   long off = 0;
   auto take = [&](long cnt) {
     const long o = off;
     off += cnt;
     return o;
   };
-  const long oV = take((long)(m + 1) * ldv), oZ = take((long)m * ldv);
-  const long oP = take((long)(m + 1) * nb), oN = take(nb), oH = take((long)(m + 1) * m);
-  const long oC = take(m), oS = take(m), oG = take(m + 1), o1 = take(m + 1), o2 = take(m + 1);
-  const long oM = take(8), oY = take(m);
+  const long oV = take((long)(m + 1) * ldv), oZ = take((long)m * ldv), oW = take(ldv);
+  const long oP = take((long)(2 * m + 3) * nb), oD = take(2 * m + 3);
+  const long oH = take((long)(m + 1) * m), oC = take(m), oS = take(m), oG = take(m + 1);
+  const long oCv = take(m + 1), oM = take(8), oY = take(m);
   if (m > P->gm_cap || ldv != P->gm_ldv || !P->gmws) {
     dfree(P, P->gmws);
     P->gmws = nullptr;
@@ -404,16 +403,18 @@ GmWs gm_workspace(ddeig_problem* P, int m) {
     P->gm_ldv = ldv;
   }
   double* b = P->gmws;
-  GmWs w{b + oV, b + oZ, b + oP, b + oN, b + oH, b + oC, b + oS, b + oG, b + o1, b + o2, b + oM,
-         b + oY, ldv};
-  return w;
+  return GmWs{b + oV, b + oZ, b + oW, b + oP, b + oD, b + oH, b + oC, b + oS, b + oG, b + oCv,
+              b + oM, b + oY, ldv};
 }
 
 // GMRES for A_sigma x = b (x holds x0) with right preconditioning by the
-// Schwarz preconditioner of `flags`, restarted every m steps (see
-// k_krylov.hip for one step).  At the end of a cycle the host solves the
-// small triangular system R y = g and the device adds Z y to x; a restart
-// begins from the true residual b - A_sigma x.
+// Schwarz preconditioner of `flags`, restarted every m steps; one step is
+// described in k_krylov.hip.  A cycle runs steps j = 0..jmax, jmax =
+// min(m, maxit - k0): step j applies the preconditioner and A_sigma to u_j
+// (not for j = jmax, which only finishes the last column) and completes
+// Hessenberg column j - 1, i.e. iteration k0 + j.  At the end of a cycle the
+// host solves the small triangular system R y = g and the device adds Z y to
+// x; a restart begins from the true residual b - A_sigma x.
 PcgOut gmres_run(ddeig_problem* P, int flags, const double* b, double* x, double rtol, int maxit,
                  int m) {
   const hipStream_t s = P->stream;
@@ -432,35 +433,31 @@ PcgOut gmres_run(ddeig_problem* P, int flags, const double* b, double* x, double
   std::vector<double> Hh, gh, yh;
   while (!hs.done && k < maxit) {
     const int kc0 = k;
-    int j = 0;
-    while (j < m && k < maxit) {
-      const int nq = std::min(std::min(batch, m - j), maxit - k);
-      for (int t = 0; t < nq; ++t) {
-        const int jj = j + t, kk = k + t + 1;
-        double* vj = w.V + (long)jj * w.ldv;
-        double* zj = w.Z + (long)jj * w.ldv;
-        double* wn = w.V + (long)(jj + 1) * w.ldv;
-        precond_apply(P, vj, zj, nullptr, P->st, nullptr, nullptr, nullptr, s, flags);
-        launch_stencil(P, P->tabAs, zj, wn, nullptr, nullptr, s);
-        launch_gm_dots(P, jj + 1, w.V, w.ldv, wn, w.part, s);
-        launch_gm_sum(P, jj + 1, w.part, w.h1, s);
-        launch_gm_axpy(P, jj + 1, w.V, w.ldv, w.h1, wn, nullptr, s);
-        launch_gm_dots(P, jj + 1, w.V, w.ldv, wn, w.part, s);
-        launch_gm_sum(P, jj + 1, w.part, w.h2, s);
-        launch_gm_axpy(P, jj + 1, w.V, w.ldv, w.h2, wn, w.nrm, s);
-        launch_gm_finish(P, jj, kk, maxit, m, w.nrm, w.h1, w.h2, w.H, w.cs, w.sn, w.g, w.gm, s);
-        launch_gm_scale(P, wn, w.gm, s);
+    const int jmax = std::min(m, maxit - kc0);
+    for (int j0 = 0; j0 <= jmax; j0 += batch) {
+      const int j1 = std::min(jmax, j0 + batch - 1);
+      for (int j = j0; j <= j1; ++j) {
+        const bool full = j < jmax;
+        double* uj = w.V + (long)j * w.ldv;
+        if (full) {
+          double* zj = w.Z + (long)j * w.ldv;
+          precond_apply(P, uj, zj, nullptr, P->st, nullptr, nullptr, nullptr, s, flags);
+          launch_stencil(P, P->tabAs, zj, w.w, nullptr, nullptr, s);
+        }
+        launch_gm_dots(P, j, w.V, w.ldv, full ? w.w : nullptr, w.part, s);
+        launch_gm_sum(P, full ? 2 * j + 3 : j + 1, w.part, w.d, s);
+        launch_gm_decide(P, j, kc0 + j, maxit, m, full ? 1 : 0, w.d, w.H, w.cs, w.sn, w.g, w.cv,
+                         w.gm, s);
+        if (full) launch_gm_update_basis(P, j, w.V, w.ldv, w.w, w.d, w.gm, s);
       }
-      j += nq;
-      k += nq;
       check_launch("gmres step");
       check_hip(hipMemcpyAsync(&hs, P->st, sizeof(PcgState), hipMemcpyDeviceToHost, s), "state");
       sync(P);
       if (hs.done) break;
     }
     // columns completed in this cycle (a breakdown leaves its column out)
-    int jd = hs.iters - kc0 - (hs.done == 2 ? 1 : 0);
-    k = hs.done ? hs.iters : k;
+    const int jd = hs.iters - kc0 - (hs.done == 2 ? 1 : 0);
+    k = hs.iters;
     if (jd > 0) {
       Hh.resize((size_t)(m + 1) * jd);
       gh.resize(jd);

@@ -467,15 +467,15 @@ int launch_lopcg_resid(long n, double lambda, const double* Ax, const double* Bx
 void launch_sr_update(const ddeig_problem* P, const double* z, double* x, hipStream_t s);
 void launch_sr_check(const ddeig_problem* P, const Red& rr, int k, int maxit, hipStream_t s);
 int gm_blocks(long n);
-void launch_gm_dots(const ddeig_problem* P, int nv, const double* V, long ldv, const double* w,
+void launch_gm_dots(const ddeig_problem* P, int j, const double* V, long ldv, const double* w,
                     double* part, hipStream_t s);
-void launch_gm_sum(const ddeig_problem* P, int nv, const double* part, double* out, hipStream_t s);
-void launch_gm_axpy(const ddeig_problem* P, int nv, const double* V, long ldv, const double* h,
-                    double* w, double* nrm, hipStream_t s);
-void launch_gm_finish(const ddeig_problem* P, int j, int k, int maxit, int restart,
-                      const double* nrm, const double* h1, const double* h2, double* H, double* cs,
-                      double* sn, double* g, double* gm, hipStream_t s);
-void launch_gm_scale(const ddeig_problem* P, double* w, const double* gm, hipStream_t s);
+void launch_gm_sum(const ddeig_problem* P, int rows, const double* part, double* out,
+                   hipStream_t s);
+void launch_gm_decide(const ddeig_problem* P, int j, int k, int maxit, int restart, int has_w,
+                      const double* d, double* H, double* cs, double* sn, double* g, double* cv,
+                      double* gm, hipStream_t s);
+void launch_gm_update_basis(const ddeig_problem* P, int j, double* V, long ldv, const double* w,
+                            const double* d, const double* gm, hipStream_t s);
 void launch_gm_start(const ddeig_problem* P, const Red& rr, const double* r, double* v0, double* g,
                      double* gm, hipStream_t s);
 void launch_gm_update(const ddeig_problem* P, int nv, const double* Z, long ldv, const double* y,

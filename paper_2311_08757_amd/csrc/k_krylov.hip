@@ -8,16 +8,23 @@
 // state's `done` flag is set.
 //
 // GMRES keeps its Arnoldi basis V (restart + 1 vectors) and the preconditioned
-// vectors Z_j = M^{-1} v_j (restart vectors) in one workspace, each vector at
-// a stride of ldv doubles.  One step j: z_j = M^{-1} v_j, w = A_sigma z_j
-// written into v_{j+1}, classical Gram-Schmidt applied twice against
-// v_0..v_j (each pass: block partials of the dots, their fixed-order sums,
-// then the update), ||w|| folded into the second update, and one single-block
-// kernel that completes column j of the Hessenberg matrix, applies the
-// previous Givens rotations and the new one, and decides whether to stop.
-// The solution update x += Z y uses the stored Z (flexible form), so a
-// preconditioner that rounds its input (bf16 local solves) still gives the
-// Arnoldi relation A Z_m = V_{m+1} H_m exactly as computed.
+// vectors z_j = M^{-1} u_j (restart vectors) in one workspace, each vector at a
+// stride of ldv doubles.  The Arnoldi process is classical Gram-Schmidt with
+// the second (re-)orthogonalisation pass delayed by one step (DCGS2, Bielich,
+// Langou, Thomas, Swirydowicz, Yamazaki and Boman, 2022): step j applies the
+// preconditioner and the operator to u_j, the vector left by step j-1 after
+// one projection (scaled, not yet normalised), then
+//   one dot sweep over v_0..v_{j-1} gives V^T u_j, V^T w, u.u, u.w, w.w;
+//   a single-thread kernel finishes column j-1 of the Hessenberg matrix with
+//   the second projection of u_j, applies the Givens rotations and the
+//   stopping test, and forms column j's first-pass entries;
+//   one update sweep writes v_j (u_j reorthogonalised and normalised) and
+//   u_{j+1} (w projected once).
+// That is two sweeps over the basis per step instead of four for classical
+// Gram-Schmidt applied twice.  Since w_j = A z_j is expressed exactly in the
+// orthonormal V, the relation A Z = V H holds for the vectors actually used
+// (flexible GMRES), so x = x0 + Z y is right also when the local solves round
+// their input (bf16).
 #include "k_common.h"
 
 namespace ddeig {
@@ -61,35 +68,90 @@ void launch_sr_check(const ddeig_problem* P, const Red& rr, int k, int maxit, hi
 // Nodes per thread of the basis kernels: a block owns kBlock * kGmE consecutive
 // nodes, so the partial-sum grid is n / (kBlock * kGmE) rounded up.
 constexpr int kGmE = 4;
+// Basis vectors per batched block reduction of the dot kernel.
+constexpr int kGmVB = 8;
 
 int gm_blocks(long n) { return (int)std::max<long>(1, (n + kBlock * kGmE - 1) / (kBlock * kGmE)); }
 
-// part[v * nblk + b] = block b's partial of v_v . w, v = 0..nv-1.
-__global__ void __launch_bounds__(kBlock) k_gm_dots(long n, int nv, const double* __restrict__ V,
+// Reduces VB values per thread over the workgroup (fixed order: shuffle tree in
+// each wave64, then the waves in order); thread b < VB receives total b.
+template <int VB>
+__device__ inline double block_sum_batch(double (&v)[VB]) {
+  __shared__ double sh[VB][kBlock / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int b = 0; b < VB; ++b)
+    for (int off = 32; off > 0; off >>= 1) v[b] += __shfl_down(v[b], off, 64);
+  __syncthreads();  // earlier readers of sh are done
+  if (lane == 0)
+#pragma unroll
+    for (int b = 0; b < VB; ++b) sh[b][w] = v[b];
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x < VB)
+    for (int i = 0; i < kBlock / 64; ++i) t += sh[threadIdx.x][i];
+  return t;
+}
+
+// The dot products of step j of the delayed Gram-Schmidt Arnoldi process
+// (one sweep over v_0..v_{j-1}): with u = u_j (basis slot j) and w = A z_j,
+// rows of part (nblk partials each):
+//   i < j: v_i.u;  j: u.u;  and when w is given  j+1+i: v_i.w (i < j),
+//   2j+1: u.w,  2j+2: w.w.
+__global__ void __launch_bounds__(kBlock) k_gm_dots(long n, int j, const double* __restrict__ V,
                                                     long ldv, const double* __restrict__ w,
                                                     const PcgState* __restrict__ st,
                                                     double* __restrict__ part) {
   if (st->done) return;
   const long base = (long)blockIdx.x * kBlock * kGmE + threadIdx.x;
-  double wr[kGmE];
+  const long nb = gridDim.x;
+  const double* u = V + (long)j * ldv;
+  double ur[kGmE], wr[kGmE];
 #pragma unroll
   for (int e = 0; e < kGmE; ++e) {
     const long k = base + (long)kBlock * e;
-    wr[e] = k < n ? w[k] : 0.0;
+    ur[e] = k < n ? u[k] : 0.0;
+    wr[e] = (w != nullptr && k < n) ? w[k] : 0.0;
   }
-  for (int v = 0; v < nv; ++v) {
-    const double* vp = V + (long)v * ldv;
-    double acc = 0.0;
+  for (int v0 = 0; v0 < j; v0 += kGmVB) {
+    double acc[2 * kGmVB];
 #pragma unroll
-    for (int e = 0; e < kGmE; ++e) {
-      const long k = base + (long)kBlock * e;
-      if (k < n) acc += vp[k] * wr[e];
+    for (int b = 0; b < kGmVB; ++b) {
+      acc[b] = acc[kGmVB + b] = 0.0;
+      if (v0 + b < j) {
+        const double* vp = V + (long)(v0 + b) * ldv;
+#pragma unroll
+        for (int e = 0; e < kGmE; ++e) {
+          const long k = base + (long)kBlock * e;
+          if (k < n) {
+            const double x = vp[k];
+            acc[b] += x * ur[e];
+            acc[kGmVB + b] += x * wr[e];
+          }
+        }
+      }
     }
-    write_partial_at(acc, part + (long)v * gridDim.x, blockIdx.x);
+    const double t = block_sum_batch<2 * kGmVB>(acc);
+    const int b = threadIdx.x % kGmVB;
+    if (threadIdx.x < 2 * kGmVB && v0 + b < j) {
+      if (threadIdx.x < kGmVB) part[(long)(v0 + b) * nb + blockIdx.x] = t;
+      else if (w != nullptr) part[(long)(j + 1 + v0 + b) * nb + blockIdx.x] = t;
+    }
   }
+  double sc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int e = 0; e < kGmE; ++e) {
+    sc[0] += ur[e] * ur[e];
+    sc[1] += ur[e] * wr[e];
+    sc[2] += wr[e] * wr[e];
+  }
+  const double t = block_sum_batch<3>(sc);
+  if (threadIdx.x == 0) part[(long)j * nb + blockIdx.x] = t;
+  if (w != nullptr && threadIdx.x >= 1 && threadIdx.x < 3)
+    part[(long)(2 * j + threadIdx.x) * nb + blockIdx.x] = t;
 }
 
-// out[v] = sum over the nblk partials of vector v, in block order (one block per v).
+// out[row] = the sum of the nblk partials of the row, in block order (one block per row).
 __global__ void __launch_bounds__(kBlock) k_gm_sum(const double* __restrict__ part, int nblk,
                                                    const PcgState* __restrict__ st,
                                                    double* __restrict__ out) {
@@ -98,94 +160,131 @@ __global__ void __launch_bounds__(kBlock) k_gm_sum(const double* __restrict__ pa
   if (threadIdx.x == 0) out[blockIdx.x] = v;
 }
 
-// w -= sum_v h[v] v_v (v in order); with nrm, the partials of ||w||^2 go to nrm.
-__global__ void __launch_bounds__(kBlock) k_gm_axpy(long n, int nv, const double* __restrict__ V,
-                                                    long ldv, const double* __restrict__ h,
-                                                    double* __restrict__ w,
-                                                    const PcgState* __restrict__ st,
-                                                    double* __restrict__ nrm) {
-  if (st->done) return;
-  const long base = (long)blockIdx.x * kBlock * kGmE + threadIdx.x;
-  double wr[kGmE];
-#pragma unroll
-  for (int e = 0; e < kGmE; ++e) {
-    const long k = base + (long)kBlock * e;
-    wr[e] = k < n ? w[k] : 0.0;
-  }
-  for (int v = 0; v < nv; ++v) {
-    const double c = h[v];
-    const double* vp = V + (long)v * ldv;
-#pragma unroll
-    for (int e = 0; e < kGmE; ++e) {
-      const long k = base + (long)kBlock * e;
-      if (k < n) wr[e] -= c * vp[k];
-    }
-  }
-  double acc = 0.0;
-#pragma unroll
-  for (int e = 0; e < kGmE; ++e) {
-    const long k = base + (long)kBlock * e;
-    if (k < n) {
-      w[k] = wr[e];
-      acc += wr[e] * wr[e];
-    }
-  }
-  if (nrm) write_partial_at(acc, nrm, blockIdx.x);
-}
-
-// Column j of the Hessenberg matrix (column-major, ldh = restart + 1 rows):
-// H[0..j, j] = h1 + h2, H[j+1, j] = ||w||, then the rotations of the columns
-// before and the new rotation that zeroes H[j+1, j]; g (the rotated
-// right-hand side beta e_1) gives the residual norm |g[j+1]| of step k (the
-// k-th of the whole solve).  done: 1 converged (including ||w|| = 0), 2
-// breakdown (a zero column), 4 maxit, 6 end of the restart cycle.
-// gm[0] receives 1 / ||w|| for the normalisation of v_{j+1}.
-__global__ void k_gm_finish(int j, int k, int maxit, int restart, const double* __restrict__ nrm,
-                            int nblk, const double* __restrict__ h1, const double* __restrict__ h2,
-                            double* __restrict__ H, double* __restrict__ cs,
-                            double* __restrict__ sn, double* __restrict__ g,
-                            double* __restrict__ gm, PcgState* __restrict__ st,
-                            double* __restrict__ hist, int hist_cap) {
-  if (st->done) return;
-  const double nw2 = sum_partials(nrm, nblk);
-  if (threadIdx.x != 0) return;
-  double* Hc = H + (long)j * (restart + 1);
-  for (int i = 0; i <= j; ++i) Hc[i] = h1[i] + h2[i];
-  const double hn = sqrt(nw2);
-  Hc[j + 1] = hn;
-  gm[0] = hn > 0.0 ? 1.0 / hn : 0.0;
-  for (int i = 0; i < j; ++i) {
+// Givens rotations on column c of H (previous rotations, then the new one that
+// zeroes H[c+1, c] = nu), the update of g and the stopping decision of step k.
+__device__ void gm_rotate(int c, int k, int maxit, int restart, double* Hc, double* cs, double* sn,
+                          double* g, double nu, PcgState* st, double* hist, int hist_cap) {
+  Hc[c + 1] = nu;
+  for (int i = 0; i < c; ++i) {
     const double t = cs[i] * Hc[i] + sn[i] * Hc[i + 1];
     Hc[i + 1] = -sn[i] * Hc[i] + cs[i] * Hc[i + 1];
     Hc[i] = t;
   }
-  const double den = hypot(Hc[j], Hc[j + 1]);
+  const double den = hypot(Hc[c], Hc[c + 1]);
   st->iters = k;
   if (!(den > 0.0)) {
     st->done = 2;
     return;
   }
-  cs[j] = Hc[j] / den;
-  sn[j] = Hc[j + 1] / den;
-  Hc[j] = den;
-  Hc[j + 1] = 0.0;
-  g[j + 1] = -sn[j] * g[j];
-  g[j] = cs[j] * g[j];
-  const double res2 = g[j + 1] * g[j + 1];
+  cs[c] = Hc[c] / den;
+  sn[c] = Hc[c + 1] / den;
+  Hc[c] = den;
+  Hc[c + 1] = 0.0;
+  g[c + 1] = -sn[c] * g[c];
+  g[c] = cs[c] * g[c];
+  const double res2 = g[c + 1] * g[c + 1];
   st->relres = sqrt(res2 / st->r0n2);
   if (hist && k < hist_cap) hist[k] = st->relres;
-  if (res2 <= st->tol2 || hn == 0.0) st->done = 1;
+  if (res2 <= st->tol2 || nu == 0.0) st->done = 1;
   else if (k >= maxit) st->done = 4;
-  else if (j + 1 >= restart) st->done = 6;
+  else if (c + 1 >= restart) st->done = 6;
 }
 
-// v = w * gm[0] in place (the normalised next basis vector).
-__global__ void k_gm_scale(long n, double* __restrict__ w, const double* __restrict__ gm,
-                           const PcgState* __restrict__ st) {
+// Scalars of step j (one thread), from the sums d of k_gm_dots:
+// 1. the second projection of u_j: u_j = V_j s + alpha v_j, s = d[0..j-1],
+//    alpha^2 = u.u - ||s||^2 (u_j was projected once already, so little cancels);
+// 2. column j-1 of H gets its second-pass terms: the first-pass entries stored at
+//    step j-1 plus s / c_{j-1}, and H[j, j-1] = alpha / c_{j-1} (u_j was w_{j-1}'s
+//    remainder scaled by c_{j-1}); then the rotations and the stopping test of
+//    iteration kc0 + j;
+// 3. with w (a full step, not done): the projections of w on v_0..v_j,
+//    p_i = d[j+1+i] and h = v_j.w = (u.w - s.p) / alpha, stored as column j's
+//    first-pass entries, and the scale c_j = 1 / ||w - V p - h v_j|| from
+//    Pythagoras (any positive scale keeps the recurrence exact: it is carried
+//    into step j+1).
+// gm[0] = 1 / alpha, gm[1] = h, gm[2] = c_j for the update.  Step 0 takes
+// v_0 = u_0 (alpha = 1).
+__global__ void k_gm_decide(int j, int k, int maxit, int restart, int has_w,
+                            const double* __restrict__ d, double* __restrict__ H,
+                            double* __restrict__ cs, double* __restrict__ sn,
+                            double* __restrict__ g, double* __restrict__ cv,
+                            double* __restrict__ gm, PcgState* __restrict__ st,
+                            double* __restrict__ hist, int hist_cap) {
+  if (st->done || threadIdx.x != 0) return;
+  const long ldh = restart + 1;
+  double alpha = 1.0;
+  if (j > 0) {
+    double ss = 0.0;
+    for (int i = 0; i < j; ++i) ss += d[i] * d[i];
+    const double a2 = d[j] - ss;
+    alpha = a2 > 0.0 ? sqrt(a2) : 0.0;
+    double* Hp = H + (long)(j - 1) * ldh;
+    const double c = cv[j - 1];
+    for (int i = 0; i < j; ++i) Hp[i] += d[i] / c;
+    gm_rotate(j - 1, k, maxit, restart, Hp, cs, sn, g, alpha / c, st, hist, hist_cap);
+    if (st->done) return;
+  }
+  if (!has_w) {  // a closing step always ends the cycle
+    st->done = 6;
+    return;
+  }
+  double sp = 0.0, pp = 0.0;
+  for (int i = 0; i < j; ++i) {
+    sp += d[i] * d[j + 1 + i];
+    pp += d[j + 1 + i] * d[j + 1 + i];
+  }
+  const double uw = d[2 * j + 1], ww = d[2 * j + 2];
+  const double h = (uw - sp) / alpha;
+  double* Hc = H + (long)j * ldh;
+  for (int i = 0; i < j; ++i) Hc[i] = d[j + 1 + i];
+  Hc[j] = h;
+  const double nu2 = ww - pp - h * h;
+  const double c = nu2 > 1e-30 * ww ? 1.0 / sqrt(nu2) : (ww > 0.0 ? 1.0 / sqrt(ww) : 1.0);
+  cv[j] = c;
+  gm[0] = 1.0 / alpha;
+  gm[1] = h;
+  gm[2] = c;
+}
+
+// The update sweep of step j over v_0..v_{j-1}: v_j = (u_j - V s) / alpha in
+// place of u_j (basis slot j), and u_{j+1} = (w - V p - h v_j) c_j into slot
+// j+1, with s = d[0..j-1], p = d[j+1..2j] (sums in index order).
+__global__ void __launch_bounds__(kBlock) k_gm_update_basis(long n, int j, double* __restrict__ V,
+                                                            long ldv, const double* __restrict__ w,
+                                                            const double* __restrict__ d,
+                                                            const double* __restrict__ gm,
+                                                            const PcgState* __restrict__ st) {
   if (st->done) return;
-  const double c = gm[0];
-  for (long k = blockIdx.x * (long)kBlock + threadIdx.x; k < n; k += (long)gridDim.x * kBlock)
-    w[k] *= c;
+  const double ia = gm[0], h = gm[1], c = gm[2];
+  double* u = V + (long)j * ldv;
+  double* un = V + (long)(j + 1) * ldv;
+  const long base = (long)blockIdx.x * kBlock * kGmE + threadIdx.x;
+  double su[kGmE], sw[kGmE];
+#pragma unroll
+  for (int e = 0; e < kGmE; ++e) su[e] = sw[e] = 0.0;
+#pragma unroll 4
+  for (int i = 0; i < j; ++i) {
+    const double a = d[i], b = d[j + 1 + i];
+    const double* vp = V + (long)i * ldv;
+#pragma unroll
+    for (int e = 0; e < kGmE; ++e) {
+      const long k = base + (long)kBlock * e;
+      if (k < n) {
+        const double x = vp[k];
+        su[e] += a * x;
+        sw[e] += b * x;
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < kGmE; ++e) {
+    const long k = base + (long)kBlock * e;
+    if (k < n) {
+      const double vj = (u[k] - su[e]) * ia;
+      u[k] = vj;
+      un[k] = (w[k] - sw[e] - h * vj) * c;
+    }
+  }
 }
 
 // Start of a cycle from the residual r (partials rr): beta = ||r||, g = beta e_1,
@@ -220,6 +319,7 @@ __global__ void __launch_bounds__(kBlock) k_gm_update(long n, int nv, const doub
     const long k = base + (long)kBlock * e;
     xr[e] = k < n ? x[k] : 0.0;
   }
+#pragma unroll 8
   for (int v = 0; v < nv; ++v) {
     const double c = y[v];
     const double* zp = Z + (long)v * ldv;
@@ -240,33 +340,28 @@ static int elem_grid(long n) {
   return (int)std::max<long>(1, std::min<long>((n + kBlock - 1) / kBlock, 4096));
 }
 
-void launch_gm_dots(const ddeig_problem* P, int nv, const double* V, long ldv, const double* w,
+void launch_gm_dots(const ddeig_problem* P, int j, const double* V, long ldv, const double* w,
                     double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_dots, dim3(gm_blocks(P->g.n)), dim3(kBlock), 0, s, P->g.n, nv, V, ldv, w,
+  hipLaunchKernelGGL(k_gm_dots, dim3(gm_blocks(P->g.n)), dim3(kBlock), 0, s, P->g.n, j, V, ldv, w,
                      P->st, part);
 }
 
-void launch_gm_sum(const ddeig_problem* P, int nv, const double* part, double* out,
+void launch_gm_sum(const ddeig_problem* P, int rows, const double* part, double* out,
                    hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_sum, dim3(nv), dim3(kBlock), 0, s, part, gm_blocks(P->g.n), P->st, out);
+  hipLaunchKernelGGL(k_gm_sum, dim3(rows), dim3(kBlock), 0, s, part, gm_blocks(P->g.n), P->st, out);
 }
 
-void launch_gm_axpy(const ddeig_problem* P, int nv, const double* V, long ldv, const double* h,
-                    double* w, double* nrm, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_axpy, dim3(gm_blocks(P->g.n)), dim3(kBlock), 0, s, P->g.n, nv, V, ldv, h,
-                     w, P->st, nrm);
+void launch_gm_decide(const ddeig_problem* P, int j, int k, int maxit, int restart, int has_w,
+                      const double* d, double* H, double* cs, double* sn, double* g, double* cv,
+                      double* gm, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_decide, dim3(1), dim3(64), 0, s, j, k, maxit, restart, has_w, d, H, cs,
+                     sn, g, cv, gm, P->st, P->hist, P->hist_cap);
 }
 
-void launch_gm_finish(const ddeig_problem* P, int j, int k, int maxit, int restart,
-                      const double* nrm, const double* h1, const double* h2, double* H, double* cs,
-                      double* sn, double* g, double* gm, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_finish, dim3(1), dim3(kBlock), 0, s, j, k, maxit, restart, nrm,
-                     gm_blocks(P->g.n), h1, h2, H, cs, sn, g, gm, P->st, P->hist, P->hist_cap);
-}
-
-void launch_gm_scale(const ddeig_problem* P, double* w, const double* gm, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_scale, dim3(elem_grid(P->g.n)), dim3(kBlock), 0, s, P->g.n, w, gm,
-                     P->st);
+void launch_gm_update_basis(const ddeig_problem* P, int j, double* V, long ldv, const double* w,
+                            const double* d, const double* gm, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_update_basis, dim3(gm_blocks(P->g.n)), dim3(kBlock), 0, s, P->g.n, j, V,
+                     ldv, w, d, gm, P->st);
 }
 
 void launch_gm_start(const ddeig_problem* P, const Red& rr, const double* r, double* v0, double* g,
