@@ -76,6 +76,10 @@ def parse():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     ap.add_argument("--cpu-sample", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--solver", default=None,
+                    choices=["cg_asm2", "gmres_ras2", "stationary_ras2", "stationary_ras1"],
+                    help="time only shifted solves A_sigma u = b (b seeded, rtol 1e-10) with this "
+                         "inner solver, one per step (for kernel profiles of that solver)")
     return ap.parse_args()
 
 
@@ -239,6 +243,42 @@ def bench_batch(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_solver(args, dd, W, prob, cfg, t_setup):
+    """--solver: one shifted solve per step with the named inner solver."""
+    import torch
+    n = prob.n_dof
+    b = torch.as_tensor(W.random_vector(n, 15), dtype=torch.float64, device="cuda")
+    u = torch.zeros_like(b)
+    run = {"cg_asm2": lambda: dd.pcg_solve(prob, b, u, rtol=1e-10, maxit=5000),
+           "gmres_ras2": lambda: dd.gmres_solve(prob, b, u, kind="ras2", rtol=1e-10, maxit=5000),
+           "stationary_ras2": lambda: dd.stationary_ras(prob, b, u, levels=2, rtol=1e-10,
+                                                        maxit=10000),
+           "stationary_ras1": lambda: dd.stationary_ras(prob, b, u, levels=1, rtol=1e-10,
+                                                        maxit=100000)}[args.solver]
+    for i in range(args.warmup):
+        u.zero_()
+        run()
+    torch.cuda.synchronize()
+    its = 0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        u.zero_()
+        its += run()["iters"]
+    torch.cuda.synchronize()
+    T = max(time.perf_counter() - t0, 1e-9)
+    print(f"# {args.solver}: {args.steps} solves in {T * 1e3:.1f} ms, {its} iterations",
+          file=sys.stderr, flush=True)
+    print(json.dumps({
+        "metric": f"shifted-solve DOF*iter/s ({args.solver}, rtol 1e-10)", "value": n * its / T,
+        "unit": "DOF*iter/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": T / max(args.steps, 1) * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": f"f64 ({args.local_prec} local solves)",
+        "data": "synthetic (seeded periodic potential, seeded right-hand side)",
+        "config": {"workload": cfg["name"], "n_dof": n, "solver": args.solver,
+                   "iters_per_solve": its / max(args.steps, 1), "setup_s": t_setup}}),
+        flush=True)
+
+
 def main():
     args = parse()
     if args.cpu_sample:
@@ -270,6 +310,9 @@ def main():
     n = prob.n_dof
     x = torch.zeros(n, dtype=torch.float64, device="cuda")
     print(f"# setup {t_setup:.2f}s n={n} sigma={sigma:.12f}", file=sys.stderr, flush=True)
+    if args.solver:
+        bench_solver(args, dd, W, prob, cfg, t_setup)
+        return
     if args.kernels_only:
         args.warmup = 0
         args.steps = 0

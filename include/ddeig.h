@@ -198,8 +198,8 @@ ddeig_status ddeig_stationary_ras(ddeig_problem* P, int levels, const double* b,
  * z_j = M^{-1} v_j are kept and x = x0 + Z y (y from the Givens-rotated
  * least-squares problem), which equals x0 + M^{-1} V y for a linear M and
  * keeps the Arnoldi relation when the local solves round their input (bf16).
- * Restarts every `restart` steps from the true residual (restart <= 0: no
- * restart below min(maxit, 300)).  x holds x0 on entry; stops when the
+ * Restarts every `restart` steps from the true residual (restart <= 0: every
+ * min(maxit, 300) steps; at most 1024).  x holds x0 on entry; stops when the
  * residual norm of the least-squares problem is <= rtol ||r_0||_2 or after
  * maxit steps.  info as for pcg_solve (relres and hist: the least-squares
  * residual norms; breakdown = 1 for a zero Hessenberg column).  Work space:

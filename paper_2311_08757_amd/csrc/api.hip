@@ -382,7 +382,7 @@ struct GmWs {
 
 GmWs gm_workspace(ddeig_problem* P, int m) {
   const long n = P->g.n;
-  const long ldv = (n + 63) / 64 * 64;
+  const long ldv = gm_stride(n);
   const long nb = gm_blocks(n);
   long off = 0;
   auto take = [&](long cnt) {
@@ -401,6 +401,9 @@ GmWs gm_workspace(ddeig_problem* P, int m) {
     P->gmws = dalloc<double>(P, (size_t)off);
     P->gm_cap = m;
     P->gm_ldv = ldv;
+    // the basis kernels read every vector up to the stride: the entries beyond
+    // n stay zero (nothing writes them)
+    check_hip(hipMemsetAsync(P->gmws, 0, sizeof(double) * (size_t)off, P->stream), "clear");
   }
   double* b = P->gmws;
   return GmWs{b + oV, b + oZ, b + oW, b + oP, b + oD, b + oH, b + oC, b + oS, b + oG, b + oCv,
@@ -1605,8 +1608,9 @@ ddeig_status ddeig_gmres_solve(ddeig_problem* P, int kind, const double* b, doub
   if ((flags & kPrecCoarse) && !P->opt.coarse)
     return set_error(DDEIG_ESTATE, "the problem was assembled without the coarse space");
   API_GUARD_BEGIN
-  const int m = std::max(1, restart > 0 ? std::min(restart, std::max(maxit, 1))
-                                        : std::min(std::max(maxit, 1), 300));
+  const int m = std::min(kGmMaxRestart,
+                         std::max(1, restart > 0 ? std::min(restart, std::max(maxit, 1))
+                                                 : std::min(std::max(maxit, 1), 300)));
   const PcgOut o = gmres_run(P, flags, b, x, rtol, maxit, m);
   fill_info(P, o, o.done == 2 ? 1 : 0, info);
   if (o.done == 2) return set_error(DDEIG_ENOCONV, "GMRES breakdown (zero Hessenberg column)");

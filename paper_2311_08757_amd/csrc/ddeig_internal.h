@@ -467,6 +467,8 @@ int launch_lopcg_resid(long n, double lambda, const double* Ax, const double* Bx
 void launch_sr_update(const ddeig_problem* P, const double* z, double* x, hipStream_t s);
 void launch_sr_check(const ddeig_problem* P, const Red& rr, int k, int maxit, hipStream_t s);
 int gm_blocks(long n);
+long gm_stride(long n);
+constexpr int kGmMaxRestart = 1024;  // largest GMRES restart length (LDS of k_gm_decide)
 void launch_gm_dots(const ddeig_problem* P, int j, const double* V, long ldv, const double* w,
                     double* part, hipStream_t s);
 void launch_gm_sum(const ddeig_problem* P, int rows, const double* part, double* out,

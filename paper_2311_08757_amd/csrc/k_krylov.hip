@@ -98,46 +98,52 @@ __device__ inline double block_sum_batch(double (&v)[VB]) {
 // rows of part (nblk partials each):
 //   i < j: v_i.u;  j: u.u;  and when w is given  j+1+i: v_i.w (i < j),
 //   2j+1: u.w,  2j+2: w.w.
-__global__ void __launch_bounds__(kBlock) k_gm_dots(long n, int j, const double* __restrict__ V,
-                                                    long ldv, const double* __restrict__ w,
+// Block (c, q) takes node chunk c (kBlock * kGmE nodes) and basis vectors
+// q kGmVG .. q kGmVG + kGmVG - 1 (group 0 also the three scalars), so a step
+// has chunks x groups workgroups.  Vectors are zero beyond n up to ldv (the
+// work space is cleared when allocated and only entries below n are written),
+// so the loads need no bounds test.
+constexpr int kGmVG = 16;
+
+__global__ void __launch_bounds__(kBlock) k_gm_dots(int j, const double* __restrict__ V, long ldv,
+                                                    const double* __restrict__ w,
                                                     const PcgState* __restrict__ st,
                                                     double* __restrict__ part) {
   if (st->done) return;
-  const long base = (long)blockIdx.x * kBlock * kGmE + threadIdx.x;
   const long nb = gridDim.x;
+  const long base = (long)blockIdx.x * kBlock * kGmE + threadIdx.x;
   const double* u = V + (long)j * ldv;
   double ur[kGmE], wr[kGmE];
 #pragma unroll
   for (int e = 0; e < kGmE; ++e) {
     const long k = base + (long)kBlock * e;
-    ur[e] = k < n ? u[k] : 0.0;
-    wr[e] = (w != nullptr && k < n) ? w[k] : 0.0;
+    ur[e] = u[k];
+    wr[e] = w != nullptr ? w[k] : 0.0;
   }
-  for (int v0 = 0; v0 < j; v0 += kGmVB) {
+  const int vend = min(j, (int)(blockIdx.y + 1) * kGmVG);
+  for (int v0 = blockIdx.y * kGmVG; v0 < vend; v0 += kGmVB) {
     double acc[2 * kGmVB];
 #pragma unroll
     for (int b = 0; b < kGmVB; ++b) {
       acc[b] = acc[kGmVB + b] = 0.0;
-      if (v0 + b < j) {
+      if (v0 + b < vend) {
         const double* vp = V + (long)(v0 + b) * ldv;
 #pragma unroll
         for (int e = 0; e < kGmE; ++e) {
-          const long k = base + (long)kBlock * e;
-          if (k < n) {
-            const double x = vp[k];
-            acc[b] += x * ur[e];
-            acc[kGmVB + b] += x * wr[e];
-          }
+          const double x = vp[base + (long)kBlock * e];
+          acc[b] += x * ur[e];
+          acc[kGmVB + b] += x * wr[e];
         }
       }
     }
     const double t = block_sum_batch<2 * kGmVB>(acc);
     const int b = threadIdx.x % kGmVB;
-    if (threadIdx.x < 2 * kGmVB && v0 + b < j) {
+    if (threadIdx.x < 2 * kGmVB && v0 + b < vend) {
       if (threadIdx.x < kGmVB) part[(long)(v0 + b) * nb + blockIdx.x] = t;
       else if (w != nullptr) part[(long)(j + 1 + v0 + b) * nb + blockIdx.x] = t;
     }
   }
+  if (blockIdx.y != 0) return;
   double sc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int e = 0; e < kGmE; ++e) {
@@ -160,90 +166,119 @@ __global__ void __launch_bounds__(kBlock) k_gm_sum(const double* __restrict__ pa
   if (threadIdx.x == 0) out[blockIdx.x] = v;
 }
 
-// Givens rotations on column c of H (previous rotations, then the new one that
-// zeroes H[c+1, c] = nu), the update of g and the stopping decision of step k.
-__device__ void gm_rotate(int c, int k, int maxit, int restart, double* Hc, double* cs, double* sn,
-                          double* g, double nu, PcgState* st, double* hist, int hist_cap) {
-  Hc[c + 1] = nu;
-  for (int i = 0; i < c; ++i) {
-    const double t = cs[i] * Hc[i] + sn[i] * Hc[i + 1];
-    Hc[i + 1] = -sn[i] * Hc[i] + cs[i] * Hc[i + 1];
-    Hc[i] = t;
-  }
-  const double den = hypot(Hc[c], Hc[c + 1]);
-  st->iters = k;
-  if (!(den > 0.0)) {
-    st->done = 2;
-    return;
-  }
-  cs[c] = Hc[c] / den;
-  sn[c] = Hc[c + 1] / den;
-  Hc[c] = den;
-  Hc[c + 1] = 0.0;
-  g[c + 1] = -sn[c] * g[c];
-  g[c] = cs[c] * g[c];
-  const double res2 = g[c + 1] * g[c + 1];
-  st->relres = sqrt(res2 / st->r0n2);
-  if (hist && k < hist_cap) hist[k] = st->relres;
-  if (res2 <= st->tol2 || nu == 0.0) st->done = 1;
-  else if (k >= maxit) st->done = 4;
-  else if (c + 1 >= restart) st->done = 6;
-}
-
-// Scalars of step j (one thread), from the sums d of k_gm_dots:
+// Scalars of step j, from the sums d of k_gm_dots (one wave64: the vectors of
+// the step are staged in LDS and reduced across the wave; only the rotation
+// chain is serial):
 // 1. the second projection of u_j: u_j = V_j s + alpha v_j, s = d[0..j-1],
 //    alpha^2 = u.u - ||s||^2 (u_j was projected once already, so little cancels);
 // 2. column j-1 of H gets its second-pass terms: the first-pass entries stored at
 //    step j-1 plus s / c_{j-1}, and H[j, j-1] = alpha / c_{j-1} (u_j was w_{j-1}'s
 //    remainder scaled by c_{j-1}); then the rotations and the stopping test of
-//    iteration kc0 + j;
+//    iteration k;
 // 3. with w (a full step, not done): the projections of w on v_0..v_j,
 //    p_i = d[j+1+i] and h = v_j.w = (u.w - s.p) / alpha, stored as column j's
 //    first-pass entries, and the scale c_j = 1 / ||w - V p - h v_j|| from
 //    Pythagoras (any positive scale keeps the recurrence exact: it is carried
 //    into step j+1).
 // gm[0] = 1 / alpha, gm[1] = h, gm[2] = c_j for the update.  Step 0 takes
-// v_0 = u_0 (alpha = 1).
-__global__ void k_gm_decide(int j, int k, int maxit, int restart, int has_w,
-                            const double* __restrict__ d, double* __restrict__ H,
-                            double* __restrict__ cs, double* __restrict__ sn,
-                            double* __restrict__ g, double* __restrict__ cv,
-                            double* __restrict__ gm, PcgState* __restrict__ st,
-                            double* __restrict__ hist, int hist_cap) {
-  if (st->done || threadIdx.x != 0) return;
+// v_0 = u_0 (alpha = 1).  The wave's sums use a fixed shuffle order.
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ void __launch_bounds__(64) k_gm_decide(int j, int k, int maxit, int restart, int has_w,
+                                                  const double* __restrict__ d,
+                                                  double* __restrict__ H, double* __restrict__ cs,
+                                                  double* __restrict__ sn, double* __restrict__ g,
+                                                  double* __restrict__ cv, double* __restrict__ gm,
+                                                  PcgState* __restrict__ st,
+                                                  double* __restrict__ hist, int hist_cap) {
+  __shared__ double hc[kGmMaxRestart + 1], lc[kGmMaxRestart], ls[kGmMaxRestart];
+  __shared__ int done;
+  const int t = threadIdx.x;
+  if (t == 0) done = st->done;
+  __syncthreads();
+  if (done) return;
   const long ldh = restart + 1;
   double alpha = 1.0;
   if (j > 0) {
     double ss = 0.0;
-    for (int i = 0; i < j; ++i) ss += d[i] * d[i];
+    for (int i = t; i < j; i += 64) ss += d[i] * d[i];
+    ss = wave_sum(ss);
     const double a2 = d[j] - ss;
     alpha = a2 > 0.0 ? sqrt(a2) : 0.0;
     double* Hp = H + (long)(j - 1) * ldh;
     const double c = cv[j - 1];
-    for (int i = 0; i < j; ++i) Hp[i] += d[i] / c;
-    gm_rotate(j - 1, k, maxit, restart, Hp, cs, sn, g, alpha / c, st, hist, hist_cap);
-    if (st->done) return;
+    for (int i = t; i < j; i += 64) hc[i] = Hp[i] + d[i] / c;
+    for (int i = t; i < j - 1; i += 64) {
+      lc[i] = cs[i];
+      ls[i] = sn[i];
+    }
+    __syncthreads();
+    if (t == 0) {
+      // rotations of the earlier columns, then the new one, on column j-1
+      const int col = j - 1;
+      const double nu = alpha / c;
+      double carry = hc[0];
+      for (int i = 0; i < col; ++i) {
+        const double a = carry, b = hc[i + 1];
+        hc[i] = lc[i] * a + ls[i] * b;
+        carry = -ls[i] * a + lc[i] * b;
+      }
+      hc[col] = carry;
+      hc[col + 1] = nu;
+      const double den = hypot(hc[col], hc[col + 1]);
+      st->iters = k;
+      if (!(den > 0.0)) {
+        st->done = 2;
+      } else {
+        const double cc = hc[col] / den, sc = hc[col + 1] / den;
+        cs[col] = cc;
+        sn[col] = sc;
+        hc[col] = den;
+        hc[col + 1] = 0.0;
+        const double gc = g[col];
+        g[col + 1] = -sc * gc;
+        g[col] = cc * gc;
+        const double res2 = g[col + 1] * g[col + 1];
+        st->relres = sqrt(res2 / st->r0n2);
+        if (hist && k < hist_cap) hist[k] = st->relres;
+        if (res2 <= st->tol2 || nu == 0.0) st->done = 1;
+        else if (k >= maxit) st->done = 4;
+        else if (col + 1 >= restart) st->done = 6;
+      }
+      done = st->done;
+    }
+    __syncthreads();
+    for (int i = t; i <= j; i += 64) Hp[i] = hc[i];
+    if (done) return;
   }
   if (!has_w) {  // a closing step always ends the cycle
-    st->done = 6;
+    if (t == 0) st->done = 6;
     return;
   }
   double sp = 0.0, pp = 0.0;
-  for (int i = 0; i < j; ++i) {
-    sp += d[i] * d[j + 1 + i];
-    pp += d[j + 1 + i] * d[j + 1 + i];
+  for (int i = t; i < j; i += 64) {
+    const double pi = d[j + 1 + i];
+    sp += d[i] * pi;
+    pp += pi * pi;
   }
+  sp = wave_sum(sp);
+  pp = wave_sum(pp);
   const double uw = d[2 * j + 1], ww = d[2 * j + 2];
   const double h = (uw - sp) / alpha;
   double* Hc = H + (long)j * ldh;
-  for (int i = 0; i < j; ++i) Hc[i] = d[j + 1 + i];
-  Hc[j] = h;
-  const double nu2 = ww - pp - h * h;
-  const double c = nu2 > 1e-30 * ww ? 1.0 / sqrt(nu2) : (ww > 0.0 ? 1.0 / sqrt(ww) : 1.0);
-  cv[j] = c;
-  gm[0] = 1.0 / alpha;
-  gm[1] = h;
-  gm[2] = c;
+  for (int i = t; i < j; i += 64) Hc[i] = d[j + 1 + i];
+  if (t == 0) {
+    Hc[j] = h;
+    const double nu2 = ww - pp - h * h;
+    const double c = nu2 > 1e-30 * ww ? 1.0 / sqrt(nu2) : (ww > 0.0 ? 1.0 / sqrt(ww) : 1.0);
+    cv[j] = c;
+    gm[0] = 1.0 / alpha;
+    gm[1] = h;
+    gm[2] = c;
+  }
 }
 
 // The update sweep of step j over v_0..v_{j-1}: v_j = (u_j - V s) / alpha in
@@ -268,12 +303,9 @@ __global__ void __launch_bounds__(kBlock) k_gm_update_basis(long n, int j, doubl
     const double* vp = V + (long)i * ldv;
 #pragma unroll
     for (int e = 0; e < kGmE; ++e) {
-      const long k = base + (long)kBlock * e;
-      if (k < n) {
-        const double x = vp[k];
-        su[e] += a * x;
-        sw[e] += b * x;
-      }
+      const double x = vp[base + (long)kBlock * e];
+      su[e] += a * x;
+      sw[e] += b * x;
     }
   }
 #pragma unroll
@@ -342,8 +374,16 @@ static int elem_grid(long n) {
 
 void launch_gm_dots(const ddeig_problem* P, int j, const double* V, long ldv, const double* w,
                     double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_dots, dim3(gm_blocks(P->g.n)), dim3(kBlock), 0, s, P->g.n, j, V, ldv, w,
+  const int groups = std::max(1, (j + kGmVG - 1) / kGmVG);
+  hipLaunchKernelGGL(k_gm_dots, dim3(gm_blocks(P->g.n), groups), dim3(kBlock), 0, s, j, V, ldv, w,
                      P->st, part);
+}
+
+// Vector stride of the GMRES work space: n rounded up to whole node chunks of
+// the basis kernels (their loads run unguarded to the stride).
+long gm_stride(long n) {
+  const long chunk = (long)kBlock * kGmE;
+  return (n + chunk - 1) / chunk * chunk;
 }
 
 void launch_gm_sum(const ddeig_problem* P, int rows, const double* part, double* out,
