@@ -161,8 +161,37 @@ void clear_flag(ddeig_problem* P) {
   check_hip(hipMemsetAsync(P->flag, 0, sizeof(int), P->stream), "memset flag");
 }
 
+void clear_graphs(ddeig_problem* P) {
+  for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+  P->graphs.clear();
+  for (auto& kv : P->gm_graphs) (void)hipGraphExecDestroy(kv.second);
+  P->gm_graphs.clear();
+}
+
+// Captures the launches of `body` on the problem's capture stream into a HIP
+// graph and instantiates it.
+template <typename F>
+hipGraphExec_t capture_graph(ddeig_problem* P, F&& body) {
+  hipGraph_t gr = nullptr;
+  hipGraphExec_t ge = nullptr;
+  check_hip(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+  try {
+    body(P->cap);
+  } catch (...) {
+    (void)hipStreamEndCapture(P->cap, &gr);
+    if (gr) (void)hipGraphDestroy(gr);
+    throw;
+  }
+  check_hip(hipStreamEndCapture(P->cap, &gr), "end capture");
+  const hipError_t e = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(gr);
+  check_hip(e, "instantiate graph");
+  return ge;
+}
+
 // sigma-dependent set-up: shifted table, local factors, coarse matrix.
 ddeig_status finish_shift(ddeig_problem* P) {
+  clear_graphs(P);
   launch_shift_table(P, P->stream);
   clear_flag(P);
   factor_types(P);
@@ -395,6 +424,8 @@ GmWs gm_workspace(ddeig_problem* P, int m) {
   const long oH = take((long)(m + 1) * m), oC = take(m), oS = take(m), oG = take(m + 1);
   const long oCv = take(m + 1), oM = take(8), oY = take(m);
   if (m > P->gm_cap || ldv != P->gm_ldv || !P->gmws) {
+    for (auto& kv : P->gm_graphs) (void)hipGraphExecDestroy(kv.second);
+    P->gm_graphs.clear();
     dfree(P, P->gmws);
     P->gmws = nullptr;
     P->gm_cap = 0;
@@ -437,21 +468,41 @@ PcgOut gmres_run(ddeig_problem* P, int flags, const double* b, double* x, double
   while (!hs.done && k < maxit) {
     const int kc0 = k;
     const int jmax = std::min(m, maxit - kc0);
-    for (int j0 = 0; j0 <= jmax; j0 += batch) {
-      const int j1 = std::min(jmax, j0 + batch - 1);
+    // steps j0..j1 on stream ms
+    auto steps = [&](int j0, int j1, hipStream_t ms) {
       for (int j = j0; j <= j1; ++j) {
         const bool full = j < jmax;
         double* uj = w.V + (long)j * w.ldv;
         if (full) {
           double* zj = w.Z + (long)j * w.ldv;
-          precond_apply(P, uj, zj, nullptr, P->st, nullptr, nullptr, nullptr, s, flags);
-          launch_stencil(P, P->tabAs, zj, w.w, nullptr, nullptr, s);
+          precond_apply(P, uj, zj, nullptr, P->st, nullptr, nullptr, nullptr, ms, flags);
+          launch_stencil(P, P->tabAs, zj, w.w, nullptr, nullptr, ms);
         }
-        launch_gm_dots(P, j, w.V, w.ldv, full ? w.w : nullptr, w.part, s);
-        launch_gm_sum(P, full ? 2 * j + 3 : j + 1, w.part, w.d, s);
+        launch_gm_dots(P, j, w.V, w.ldv, full ? w.w : nullptr, w.part, ms);
+        launch_gm_sum(P, full ? 2 * j + 3 : j + 1, w.part, w.d, ms);
         launch_gm_decide(P, j, kc0 + j, maxit, m, full ? 1 : 0, w.d, w.H, w.cs, w.sn, w.g, w.cv,
-                         w.gm, s);
-        if (full) launch_gm_update_basis(P, j, w.V, w.ldv, w.w, w.d, w.gm, s);
+                         w.gm, ms);
+        if (full) launch_gm_update_basis(P, j, w.V, w.ldv, w.w, w.d, w.gm, ms);
+      }
+    };
+    for (int j0 = 0; j0 <= jmax; j0 += batch) {
+      const int j1 = std::min(jmax, j0 + batch - 1);
+      if (P->opt.graphs) {
+        // each block of steps is captured once per key and replayed on the library stream
+        const auto key = std::make_tuple(kc0, j0, j1, jmax, maxit, m, flags, (const void*)w.V);
+        auto it = P->gm_graphs.find(key);
+        if (it == P->gm_graphs.end()) {
+          if (P->gm_graphs.size() >= 4096) {
+            for (auto& kv : P->gm_graphs) (void)hipGraphExecDestroy(kv.second);
+            P->gm_graphs.clear();
+          }
+          it = P->gm_graphs
+                   .emplace(key, capture_graph(P, [&](hipStream_t cs) { steps(j0, j1, cs); }))
+                   .first;
+        }
+        check_hip(hipGraphLaunch(it->second, s), "launch graph");
+      } else {
+        steps(j0, j1, s);
       }
       check_launch("gmres step");
       check_hip(hipMemcpyAsync(&hs, P->st, sizeof(PcgState), hipMemcpyDeviceToHost, s), "state");
@@ -1171,7 +1222,7 @@ void ddeig_destroy(ddeig_problem* P) {
   if (!P) return;
   if (P->stream) (void)hipStreamSynchronize(P->stream);
   else (void)hipDeviceSynchronize();
-  for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+  clear_graphs(P);
   if (P->cap) (void)hipStreamDestroy(P->cap);
   if (P->aux) {
     (void)hipStreamSynchronize(P->aux);

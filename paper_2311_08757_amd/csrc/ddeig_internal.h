@@ -278,6 +278,9 @@ struct ddeig_problem {
   // stream and one executable graph per (first, last iteration, maxit, x)
   hipStream_t cap = nullptr;
   std::map<std::tuple<int, int, int, const void*>, hipGraphExec_t> graphs;
+  // GMRES step blocks: (cycle start, first step, last step, last step of the
+  // cycle, maxit, restart, preconditioner flags, work space)
+  std::map<std::tuple<int, int, int, int, int, int, int, const void*>, hipGraphExec_t> gm_graphs;
   // operator tables, tap-major: tab[tap * tsize + tnode]
   double* tabK = nullptr;
   double* tabM = nullptr;

@@ -295,3 +295,34 @@ def test_config2_gmres_and_stationary(torch):
     rs = _true_relres(torch, prob, b, xs)
     print(f"stationary RAS2 {rs:.3e} ({os_['iters']} steps)")
     assert rs <= 1.1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_gmres_graph_replay_bitwise(torch, prec):
+    """Blocks of GMRES steps replayed from captured HIP graphs give the bits of
+    the same steps launched one by one, on every replay (three solves, with
+    eager work and synchronisation in between), also across a restart."""
+    import paper_2311_08757_amd as dd
+    case = CASES[4]
+    P = _oracle(case)
+    p, q, L, ne, delta, V = case
+    probs = []
+    for graphs in (False, True):
+        prob = dd.assemble(p, q, L, ne, V, delta, local_prec=prec, graphs=graphs)
+        dd.set_shift(prob, P.sigma, P.cell["psi"])
+        probs.append(prob)
+    b = _dev(torch, W.random_vector(P.grid.n, 16))
+    for restart in (0, 6):
+        ref = torch.zeros_like(b)
+        o_ref = dd.gmres_solve(probs[0], b, ref, kind="ras2", rtol=1e-11, maxit=500,
+                               restart=restart)
+        for rep in range(3):
+            x = torch.zeros_like(b)
+            o = dd.gmres_solve(probs[1], b, x, kind="ras2", rtol=1e-11, maxit=500,
+                               restart=restart)
+            torch.cuda.synchronize()
+            assert o["iters"] == o_ref["iters"], (restart, rep)
+            assert torch.equal(x, ref), (restart, rep)
+            y = torch.empty_like(b)
+            dd.apply_op(probs[1], "A_sigma", x, y)   # eager work between replays
+            torch.cuda.synchronize()
