@@ -268,8 +268,10 @@ ddeig_status ddeig_lopcg(ddeig_problem* P, double* x, const double* x_prev, doub
  * duration of one launch in *avg_us (synchronises).  which = 0: the A_sigma
  * stencil on x (y receives A_sigma x); 1: the level-1 local solves on the
  * batch left by the last apply_precond (dense: the MFMA GEMM over all
- * subdomains, m = unknowns of the unclipped box; otherwise the block-chain
- * solves), so call apply_precond first; 2: the whole preconditioner on x
+ * subdomains, m = unknowns of the unclipped box, with the coarse
+ * right-hand-side workgroups it carries inside the preconditioner when the
+ * problem has the coarse space and clipped subdomains; otherwise the
+ * block-chain solves), so call apply_precond first; 2: the whole preconditioner on x
  * (y receives z); 3: the restriction of x into the batch; 4: the extension
  * (y receives z from the current local and coarse solutions; x plays r);
  * 5: the clipped-class correction of the dense local solves (no-op

@@ -248,6 +248,16 @@ void precond_apply(ddeig_problem* P, double* r, double* z, Red* dot, PcgState* s
   CheckArgs coff{};
   coff.on = 0;
   launch_restrict(P, r, st, xr ? *xr : xoff, rr, s);
+  if (coarse && fused_coarse(P)) {
+    // one stream: R_0 r rides in the GEMM launch, A_0^{-1} c in the
+    // clipped-class correction launch, the coarse field in the extension
+    launch_local_solves(P, st, s, r);
+    launch_embed_fix(P, st, s, true);
+    CheckArgs c = chk ? *chk : coff;
+    if (chk && rr) c.rr = *rr;
+    launch_extend(P, r, z, 1, dot, st, c, s, (flags & kPrecRas) ? 1 : 0, 1);
+    return;
+  }
   const bool side = coarse;
   if (side) {
     check_hip(hipEventRecord(P->ev_fork, s), "record fork");
@@ -1420,13 +1430,17 @@ ddeig_status ddeig_profile_kernel(ddeig_problem* P, int which, int reps, const d
   xoff.on = 0;
   CheckArgs coff{};
   coff.on = 0;
+  const int fused = fused_coarse(P) ? 1 : 0;
   auto launch = [&]() {
     if (which == 0) launch_stencil(P, P->tabAs, x, y, nullptr, nullptr, s);
-    else if (which == 1) launch_local_solves(P, nullptr, s);
+    // as launched inside the preconditioner: with the coarse space riding in
+    // the dense launches, the GEMM carries R_0 r (of the internal residual),
+    // the correction A_0^{-1} c and the extension forms the coarse field
+    else if (which == 1) launch_local_solves(P, nullptr, s, fused ? P->r : nullptr);
     else if (which == 2) precond_apply(P, const_cast<double*>(x), y, nullptr, nullptr);
     else if (which == 3) launch_restrict(P, const_cast<double*>(x), nullptr, xoff, nullptr, s);
-    else if (which == 4) launch_extend(P, x, y, P->opt.coarse, &dot, nullptr, coff, s);
-    else if (P->opt.local_prec >= 2) launch_embed_fix(P, nullptr, s);
+    else if (which == 4) launch_extend(P, x, y, P->opt.coarse, &dot, nullptr, coff, s, 0, fused);
+    else if (P->opt.local_prec >= 2) launch_embed_fix(P, nullptr, s, fused);
   };
   launch();
   hipEvent_t e0, e1;

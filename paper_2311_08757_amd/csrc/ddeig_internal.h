@@ -204,6 +204,25 @@ struct GemmType {
 };
 
 // Batched chain solves: one workgroup per (class, member tile, 64 rows of a slice).
+// Extra workgroups of the dense GEMM launch that form the coarse right-hand
+// side R_0 r (one per subdomain), and of the clipped-class correction launch
+// that apply the coarse inverse y0 = A_0^{-1} c (four rows per workgroup).
+struct CoarseRhsArgs {
+  int n;  // subdomains (0: none)
+  Geo g;
+  const double* r;
+  const TypeDev* types;
+  const SubDev* subs;
+  double* crhs;
+};
+
+struct CoarseSolveArgs {
+  int n;  // coarse dimension (0: none)
+  const double* A0inv;
+  const double* c;
+  double* y;
+};
+
 struct ChainJob {
   int type, m0, nm, r0;
 };
@@ -403,7 +422,9 @@ struct CheckArgs {
 };
 void launch_restrict(const ddeig_problem* P, double* r, PcgState* st, const XrArgs& xr, Red* rr,
                      hipStream_t s);
-void launch_local_solves(const ddeig_problem* P, const PcgState* st, hipStream_t s);
+void launch_local_solves(const ddeig_problem* P, const PcgState* st, hipStream_t s,
+                         const double* coarse_r = nullptr);
+bool fused_coarse(const ddeig_problem* P);
 size_t chain_lds_bytes(int maxb, int fp32);
 void chain_kernel_setup(int fp32, size_t lds);
 void launch_coarse_solve(const ddeig_problem* P, const PcgState* st, hipStream_t s);
@@ -411,18 +432,21 @@ void launch_coarse_field(const ddeig_problem* P, const PcgState* st, hipStream_t
 void launch_coarse_rhs(const ddeig_problem* P, const double* r, const PcgState* st, hipStream_t s);
 void launch_coarse_phi(const ddeig_problem* P, hipStream_t s);
 void launch_extend(const ddeig_problem* P, const double* r, double* z, int coarse, Red* dot,
-                   PcgState* st, const CheckArgs& chk, hipStream_t s, int ras = 0);
+                   PcgState* st, const CheckArgs& chk, hipStream_t s, int ras = 0,
+                   int inline_field = 0);
 void launch_coarse_extend(const ddeig_problem* P, const double* r, double* z, Red* dot,
                           const PcgState* st, hipStream_t s);
 void launch_symmetrise(double* A, int N, hipStream_t s);
 void launch_split_inverse(const double* Ainv, int m, int ld, void* Ah, void* Al, hipStream_t s);
 void launch_identity(double* v, int m, hipStream_t s);
-void launch_dense_gemm(const ddeig_problem* P, const PcgState* st, hipStream_t s);
+void launch_dense_gemm(const ddeig_problem* P, const PcgState* st, hipStream_t s,
+                       const double* coarse_r = nullptr);
 void launch_dense_gemv(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 void launch_embed_gather(const ddeig_problem* P, const EmbedDev& E, double* C, hipStream_t s);
 void launch_embed_gmat(const ddeig_problem* P, const EmbedDev& E, const double* C, float* G,
                        hipStream_t s);
-void launch_embed_fix(const ddeig_problem* P, const PcgState* st, hipStream_t s);
+void launch_embed_fix(const ddeig_problem* P, const PcgState* st, hipStream_t s,
+                      bool coarse_solve = false);
 void launch_to_float(const double* src, float* dst, long n, hipStream_t s);
 void build_coarse_matrix(ddeig_problem* P, double* A0, hipStream_t s);
 

@@ -444,11 +444,13 @@ void launch_chain_batched(const ddeig_problem* P, const PcgState* st, hipStream_
 bool local_solves_fast_ok(const ddeig_problem* P);
 void launch_local_solves_fast(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 
-void launch_local_solves(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
+void launch_local_solves(const ddeig_problem* P, const PcgState* st, hipStream_t s,
+                         const double* coarse_r) {
   if (P->opt.local_prec >= 2) {
     // one batch of all subdomains: MFMA tiles, or the streaming kernel for a
-    // handful of rows (one of the two has no work)
-    launch_dense_gemm(P, st, s);
+    // handful of rows (one of the two has no work); coarse_r (nullable): the
+    // GEMM launch also forms R_0 coarse_r
+    launch_dense_gemm(P, st, s, coarse_r);
     launch_dense_gemv(P, st, s);
     return;
   }

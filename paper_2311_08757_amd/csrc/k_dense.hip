@@ -27,6 +27,7 @@
 // extension kernel.  Classes with at most kGemvMax members (the
 // boundary cells) use a streaming matrix-vector kernel instead.
 #include "k_common.h"
+#include "k_coarse.h"
 
 namespace ddeig {
 
@@ -103,16 +104,24 @@ struct GemmCfg {
 
 typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4;
 
+// Workgroups beyond the ntiles tiles form the coarse right-hand side R_0 r
+// (ca.n of them, one per subdomain) on the CUs the tiles leave free; they
+// share nothing with the tiles, so no workgroup waits for another.
 template <bool RLO, bool ALO>
 __global__ void __launch_bounds__(kBlock) k_dense_gemm(const GemmTile* __restrict__ tiles,
                                                        const GemmType* __restrict__ gtypes,
-                                                       const PcgState* __restrict__ st) {
+                                                       const PcgState* __restrict__ st,
+                                                       int ntiles, CoarseRhsArgs ca) {
   using C = GemmCfg<RLO, ALO>;
   constexpr int BK = C::BK, LDK = C::LDK, NR = C::NR, NOP = C::NOP, NV = C::NV, NVT = C::NVT;
   constexpr int NS = C::NS, WPS = C::WPS;
   // [buffer][operand][row * LDK + k]; operands: R parts first, then A parts
   __shared__ __bf16 sm[2][NOP][kTM * LDK];
   if (st != nullptr && st->done) return;
+  if ((int)blockIdx.x >= ntiles) {
+    coarse_rhs_body(ca.g, nullptr, ca.r, ca.types, ca.subs, ca.crhs, blockIdx.x - ntiles);
+    return;
+  }
   const GemmTile t = tiles[blockIdx.x];
   const GemmType gt = gtypes[t.type];
   if (gt.st != nullptr && gt.st->done) return;
@@ -380,13 +389,22 @@ void launch_embed_gmat(const ddeig_problem* P, const EmbedDev& E, const double* 
 // Nodes in T are left alone (no member reads them).
 constexpr int kEmbPh = 8, kEmbE = kBlock / kEmbPh, kEmbG = 32;  // G loads per batch
 
+// Rows blockIdx.y >= ceil(mH / kEmbE) of the grid apply the coarse inverse
+// (column 0 only: rows 4 (blockIdx.y - ychunks) .. + 3 of y0 = A_0^{-1} c),
+// independent of the correction workgroups.
 template <int KS>
 __global__ void __launch_bounds__(kBlock) k_embed_correct(const EmbedJob* __restrict__ jobs,
                                                           const EmbedDev* __restrict__ cls,
                                                           int ld, int hm0, int hm1, int mH,
-                                                          const PcgState* __restrict__ st) {
+                                                          const PcgState* __restrict__ st,
+                                                          CoarseSolveArgs cs) {
   __shared__ float uT[kEmbChunk * kEmbMaxT];
   __shared__ float red[kEmbPh][kEmbE][kEmbChunk];
+  const int ychunks = (mH + kEmbE - 1) / kEmbE;
+  if ((int)blockIdx.y >= ychunks) {
+    if (blockIdx.x == 0) coarse_solve_body(cs.n, st, cs.A0inv, cs.c, cs.y, blockIdx.y - ychunks);
+    return;
+  }
   // the job, the state and the class are loaded before the state is tested,
   // so that their latencies overlap
   const EmbedJob jb = jobs[blockIdx.x];
@@ -472,28 +490,50 @@ __global__ void __launch_bounds__(kBlock) k_embed_correct(const EmbedJob* __rest
   }
 }
 
-void launch_embed_fix(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
+// With coarse_solve the launch also applies A_0^{-1} to the coarse right-hand
+// side (P->crhs into P->cy).
+void launch_embed_fix(const ddeig_problem* P, const PcgState* st, hipStream_t s,
+                      bool coarse_solve) {
   if (P->nembjobs == 0) return;
   const DenseHost& H = P->dh;
   // the K split is 1..3 by construction (assemble)
   auto kern = P->ksplit == 1 ? k_embed_correct<1> : (P->ksplit == 2 ? k_embed_correct<2>
                                                                      : k_embed_correct<3>);
-  hipLaunchKernelGGL(kern, dim3(P->nembjobs, (H.m + kEmbE - 1) / kEmbE), dim3(kBlock), 0, s,
-                     P->dEmbJobs, P->dEmb, H.ld, H.box.m[0], H.box.m[1], H.m, st);
+  CoarseSolveArgs cs{0, nullptr, nullptr, nullptr};
+  int extra = 0;
+  if (coarse_solve) {
+    cs = CoarseSolveArgs{P->nsub, P->A0inv, P->crhs, P->cy};
+    extra = (P->nsub + kBlock / 64 - 1) / (kBlock / 64);
+  }
+  hipLaunchKernelGGL(kern, dim3(P->nembjobs, (H.m + kEmbE - 1) / kEmbE + extra), dim3(kBlock), 0,
+                     s, P->dEmbJobs, P->dEmb, H.ld, H.box.m[0], H.box.m[1], H.m, st, cs);
 }
 
 // Batches of more rows: 128 x 128 MFMA tiles.  local_prec 2 (bf16x3):
 // residual and inverse as hi/lo pairs, three products; local_prec 3: both
-// single bf16, one product.
-void launch_dense_gemm(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
+// single bf16, one product.  coarse_r (nullable): one more workgroup per
+// subdomain forms R_0 coarse_r into P->crhs.
+void launch_dense_gemm(const ddeig_problem* P, const PcgState* st, hipStream_t s,
+                       const double* coarse_r) {
   if (P->ntiles > 0) {
+    CoarseRhsArgs ca{};
+    ca.n = 0;
+    if (coarse_r != nullptr)
+      ca = CoarseRhsArgs{P->nsub, P->g, coarse_r, P->dTypes, P->dSubs, P->crhs};
+    const dim3 grid(P->ntiles + ca.n);
     if (P->opt.local_prec == 2)
-      hipLaunchKernelGGL((k_dense_gemm<true, true>), dim3(P->ntiles), dim3(kBlock), 0, s,
-                         P->dTiles, P->dGtypes, st);
+      hipLaunchKernelGGL((k_dense_gemm<true, true>), grid, dim3(kBlock), 0, s, P->dTiles,
+                         P->dGtypes, st, P->ntiles, ca);
     else
-      hipLaunchKernelGGL((k_dense_gemm<false, false>), dim3(P->ntiles), dim3(kBlock), 0, s,
-                         P->dTiles, P->dGtypes, st);
+      hipLaunchKernelGGL((k_dense_gemm<false, false>), grid, dim3(kBlock), 0, s, P->dTiles,
+                         P->dGtypes, st, P->ntiles, ca);
   }
+}
+
+// The coarse space rides in the GEMM and correction launches (and the coarse
+// field is formed inside the extension) when the dense path has both.
+bool fused_coarse(const ddeig_problem* P) {
+  return P->opt.coarse && P->opt.local_prec >= 2 && P->ntiles > 0 && P->nembjobs > 0;
 }
 
 // Grouped launches over the instances of a batch: the tiles / correction jobs
@@ -502,12 +542,14 @@ void launch_dense_gemm(const ddeig_problem* P, const PcgState* st, hipStream_t s
 void launch_gemm_tiles(const GemmTile* tiles, int ntiles, const GemmType* gt, int local_prec,
                        hipStream_t s) {
   if (ntiles <= 0) return;
+  CoarseRhsArgs none{};
+  none.n = 0;
   if (local_prec == 2)
     hipLaunchKernelGGL((k_dense_gemm<true, true>), dim3(ntiles), dim3(kBlock), 0, s, tiles, gt,
-                       nullptr);
+                       nullptr, ntiles, none);
   else
     hipLaunchKernelGGL((k_dense_gemm<false, false>), dim3(ntiles), dim3(kBlock), 0, s, tiles, gt,
-                       nullptr);
+                       nullptr, ntiles, none);
 }
 
 void launch_embed_jobs(const EmbedJob* jobs, int njobs, const EmbedDev* cls, int ksplit, int ld,
@@ -515,8 +557,9 @@ void launch_embed_jobs(const EmbedJob* jobs, int njobs, const EmbedDev* cls, int
   if (njobs <= 0) return;
   auto kern = ksplit == 1 ? k_embed_correct<1> : (ksplit == 2 ? k_embed_correct<2>
                                                                : k_embed_correct<3>);
+  const CoarseSolveArgs none{0, nullptr, nullptr, nullptr};
   hipLaunchKernelGGL(kern, dim3(njobs, (mH + kEmbE - 1) / kEmbE), dim3(kBlock), 0, s, jobs, cls,
-                     ld, hm0, hm1, mH, nullptr);
+                     ld, hm0, hm1, mH, nullptr, none);
 }
 
 void launch_dense_gemv(const ddeig_problem* P, const PcgState* st, hipStream_t s) {

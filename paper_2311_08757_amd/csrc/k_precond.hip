@@ -9,6 +9,7 @@
 // lies in at most two cells per axis.  The extension sums, for every node, the
 // local solutions of the subdomains covering it in a fixed order (no atomics).
 #include "k_common.h"
+#include "k_coarse.h"
 
 namespace ddeig {
 
@@ -268,7 +269,10 @@ __global__ void __launch_bounds__(kBig) k_restrict_dense(Geo g, int delta, PcgSt
 // RAS weights every local solution by the partition of unity,
 // z = sum_c R_c^T D_c y_c (+ the coarse term): the restricted additive Schwarz
 // extension of eq:dd-preconditioners, from the same per-axis covering tables.
-template <int PX, int KS, bool RAS = false>
+// INL forms the coarse field at the node from y0 itself (cf then points to
+// y0): sum_c D_c y0_c over the covering cells in slot order, the arithmetic of
+// k_coarse_field.
+template <int PX, int KS, bool RAS = false, bool INL = false>
 __device__ __forceinline__ void extend_dense_body(const Geo& g, int delta, int coarse,
                                                   PcgState* __restrict__ st, const CheckArgs& chk,
                                                   const DenseArgs& da,
@@ -309,6 +313,17 @@ __device__ __forceinline__ void extend_dense_body(const Geo& g, int delta, int c
     const long k = i0 + (long)N0 * line;
     const Cover<PX> cv(g, delta, i);
     // every load of the node first (independent of each other) ...
+    // (the inline coarse field with one expanding axis: the covering-table
+    // entry and the two y0 values)
+    XCover xa;
+    double ya[2] = {0.0, 0.0};
+    if constexpr (INL && PX == 1) {
+      if (coarse) {
+        xa = xc0[i0];
+        ya[0] = cf[cv.c0(0) - 1];
+        ya[1] = cf[cv.c0(1) - 1];
+      }
+    }
     float zs[NC][KS];
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
@@ -326,7 +341,22 @@ __device__ __forceinline__ void extend_dense_body(const Geo& g, int delta, int c
       const int j1 = PX == 2 ? (int)((unsigned)(i[1] + 1) - g.ne * fdiv((unsigned)(i[1] + 1), g.fne))
                              : i[1];
       ps = psi[j0 + (long)g.P[0] * (j1 + (long)g.P[1] * i2)];
-      zc = cf[PX == 1 ? (long)i0 : i0 + (long)N0 * i[1]];
+      if constexpr (INL && PX == 1) {
+        // the weights of the one expanding axis (cover_weight for p = 1)
+        zc = xa.w[0] * ya[0];
+        if (cv.val(1)) zc = fma(xa.w[1], ya[1], zc);
+      } else if constexpr (INL) {
+        const XCover* xc[2] = {xc0, xc1};
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          if (!cv.val(q)) continue;
+          const int c[3] = {cv.c0(q), PX == 2 ? cv.c1(q) : 0, 0};
+          const int which[2] = {q & 1, q >> 1};
+          zc += cover_weight(g, delta, pu, xc, c, i, which) * cf[(c[0] - 1) + g.L * (cv.c1(q) - 1)];
+        }
+      } else {
+        zc = cf[PX == 1 ? (long)i0 : i0 + (long)N0 * i[1]];
+      }
     }
     // ... then the sums, cells in slot order and splits in split order
     double zl = 0.0;
@@ -353,7 +383,7 @@ __device__ __forceinline__ void extend_dense_body(const Geo& g, int delta, int c
   if (use_dot) write_partial_at<kBig>(acc, dot.part, bid);
 }
 
-template <int PX, int KS, bool RAS>
+template <int PX, int KS, bool RAS, bool INL>
 __global__ void __launch_bounds__(kBig) k_extend_dense(Geo g, int delta, int coarse,
                                                        PcgState* __restrict__ st, CheckArgs chk,
                                                        DenseArgs da, const double* __restrict__ psi,
@@ -362,8 +392,8 @@ __global__ void __launch_bounds__(kBig) k_extend_dense(Geo g, int delta, int coa
                                                        double* __restrict__ z, int use_dot, Red dot,
                                                        int pu, const XCover* __restrict__ xc0,
                                                        const XCover* __restrict__ xc1) {
-  extend_dense_body<PX, KS, RAS>(g, delta, coarse, st, chk, da, psi, cf, r, z, use_dot, dot,
-                                 blockIdx.x, gridDim.x, pu, xc0, xc1);
+  extend_dense_body<PX, KS, RAS, INL>(g, delta, coarse, st, chk, da, psi, cf, r, z, use_dot, dot,
+                                      blockIdx.x, gridDim.x, pu, xc0, xc1);
 }
 
 DenseArgs dense_args(const ddeig_problem* P) {
@@ -395,44 +425,6 @@ void launch_restrict(const ddeig_problem* P, double* r, PcgState* st, const XrAr
   } else
     hipLaunchKernelGGL(k_restrict, dim3(blocks), dim3(kBig), 0, s, P->g, (int)P->types.size(), st,
                        xr, xr.on ? *rr : none, r, P->dTypes, P->dSubTS, P->dXC[0], P->dXC[1]);
-}
-
-// c_sub = phi_class . R_sub r  (R_0 r of def:algebraic-perfact-coarse-space):
-// one workgroup per subdomain.  Thread t takes the box elements t + kBlock q
-// (natural order; the grid line from a multiply-high division), 8 at a time
-// with all 16 loads issued before the products; the products are added in q
-// order, then the threads in a fixed order.
-__device__ __forceinline__ void coarse_rhs_body(const Geo& g, const PcgState* __restrict__ st,
-                                                const double* __restrict__ r,
-                                                const TypeDev* __restrict__ types,
-                                                const SubDev* __restrict__ subs,
-                                                double* __restrict__ crhs, int bid) {
-  if (st != nullptr && st->done) return;
-  const SubDev sd = subs[bid];
-  const TypeDev td = types[sd.type];
-  const int m0 = td.m[0], m1 = td.m[1];
-  const int mtot = m0 * m1 * td.m[2];
-  constexpr int U = 8;
-  double acc = 0.0;
-  for (int e0 = threadIdx.x; e0 < mtot; e0 += U * kBlock) {
-    double ph[U], rv[U];
-#pragma unroll
-    for (int q = 0; q < U; ++q) {
-      const int e = e0 + q * kBlock;
-      ph[q] = rv[q] = 0.0;
-      if (e < mtot) {
-        const int line = (int)fdiv((unsigned)e, td.fm0);
-        const int u0 = e - line * m0;
-        const int u2 = line / m1, u1 = line - u2 * m1;
-        ph[q] = td.phi[e];
-        rv[q] = r[(sd.o[0] + u0) + (long)g.N[0] * ((sd.o[1] + u1) + (long)g.N[1] * (sd.o[2] + u2))];
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < U; ++q) acc += ph[q] * rv[q];
-  }
-  const double sum = block_sum(acc);
-  if (threadIdx.x == 0) crhs[bid] = sum;
 }
 
 __global__ void __launch_bounds__(kBlock) k_coarse_rhs(Geo g, const PcgState* __restrict__ st,
@@ -475,22 +467,6 @@ void launch_coarse_phi(const ddeig_problem* P, hipStream_t s) {
   const int nt = (int)P->types.size();
   hipLaunchKernelGGL(k_coarse_phi, dim3(64, nt), dim3(kBlock), 0, s, P->g, P->delta, P->opt.pu,
                      P->dTypes, P->dSubs, P->dFirst, P->dXC[0], P->dXC[1], P->psi, P->dPhis);
-}
-
-// y0 = A0^{-1} c with the dense symmetric inverse: one wave64 per row, lanes
-// stride the row (coalesced), fixed-order shuffle reduction.
-__device__ __forceinline__ void coarse_solve_body(int N, const PcgState* __restrict__ st,
-                                                  const double* __restrict__ A0inv,
-                                                  const double* __restrict__ c,
-                                                  double* __restrict__ y, int bid) {
-  if (st != nullptr && st->done) return;
-  const int lane = threadIdx.x & 63;
-  const int row = bid * (kBlock / 64) + (threadIdx.x >> 6);
-  if (row >= N) return;
-  double acc = 0.0;
-  for (int j = lane; j < N; j += 64) acc += A0inv[(long)row * N + j] * c[j];
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) y[row] = acc;
 }
 
 __global__ void k_coarse_solve(int N, const PcgState* __restrict__ st,
@@ -643,27 +619,32 @@ __global__ void __launch_bounds__(kBig) k_extend(Geo g, int delta, int pu, int c
   if (use_dot) write_partial<kBig>(acc, dot.part);
 }
 
-template <bool RAS>
+template <bool RAS, bool INL>
 static auto dense_extend_kernel(int p, int ks) {
   if (p == 1)
-    return ks == 1 ? k_extend_dense<1, 1, RAS>
-                   : (ks == 2 ? k_extend_dense<1, 2, RAS> : k_extend_dense<1, 3, RAS>);
-  return ks == 1 ? k_extend_dense<2, 1, RAS>
-                 : (ks == 2 ? k_extend_dense<2, 2, RAS> : k_extend_dense<2, 3, RAS>);
+    return ks == 1 ? k_extend_dense<1, 1, RAS, INL>
+                   : (ks == 2 ? k_extend_dense<1, 2, RAS, INL> : k_extend_dense<1, 3, RAS, INL>);
+  return ks == 1 ? k_extend_dense<2, 1, RAS, INL>
+                 : (ks == 2 ? k_extend_dense<2, 2, RAS, INL> : k_extend_dense<2, 3, RAS, INL>);
 }
 
+// inline_field: the coarse field is formed in the extension from y0 (P->cy)
+// instead of read from k_coarse_field's output (dense local solves only).
 void launch_extend(const ddeig_problem* P, const double* r, double* z, int coarse, Red* dot,
-                   PcgState* st, const CheckArgs& chk, hipStream_t s, int ras) {
+                   PcgState* st, const CheckArgs& chk, hipStream_t s, int ras, int inline_field) {
   const int blocks = node_grid(P->g);
   const Red none{nullptr, 0, nullptr};
   if (dot) dot->np = blocks;
   if (P->opt.local_prec >= 2) {
     // the K split is 1..3 by construction (assemble)
-    auto kern = ras ? dense_extend_kernel<true>(P->g.p, P->ksplit)
-                    : dense_extend_kernel<false>(P->g.p, P->ksplit);
+    const bool inl = coarse && inline_field;
+    auto kern = ras ? (inl ? dense_extend_kernel<true, true>(P->g.p, P->ksplit)
+                           : dense_extend_kernel<true, false>(P->g.p, P->ksplit))
+                    : (inl ? dense_extend_kernel<false, true>(P->g.p, P->ksplit)
+                           : dense_extend_kernel<false, false>(P->g.p, P->ksplit));
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBig), 0, s, P->g, P->delta, coarse, st, chk,
-                       dense_args(P), P->psi, P->cfield, r, z, dot ? 1 : 0, dot ? *dot : none,
-                       P->opt.pu, P->dXC[0], P->dXC[1]);
+                       dense_args(P), P->psi, inl ? P->cy : P->cfield, r, z, dot ? 1 : 0,
+                       dot ? *dot : none, P->opt.pu, P->dXC[0], P->dXC[1]);
     return;
   }
   hipLaunchKernelGGL(k_extend, dim3(blocks), dim3(kBig), 0, s, P->g, P->delta, P->opt.pu,
