@@ -62,7 +62,7 @@ def extend_periodic(psi_cell, grid):
     for a in range(grid.d):
         i = np.arange(1, grid.nel[a])  # 1-based interior node index
         axes.append(np.mod(i, ne) if a < grid.p else i - 1)
-    cell_dims = [ne] * grid.p + [grid.ell * ne - 1] * grid.q
+    cell_dims = [ne] * grid.p + [grid.nel[grid.p + j] - 1 for j in range(grid.q)]
     mesh = np.meshgrid(*axes, indexing="ij")
     lin = np.zeros(mesh[0].shape, dtype=np.int64)
     stride = 1

@@ -65,9 +65,13 @@ class Grid:
         self.ne = int(ne)
         self.h = 1.0 / self.ne
         self.L = 1 if cell else int(L)
-        self.ell = int(ell)
+        # ell is real (eq:geometry-description); the mesh needs ell n_e elements
+        self.ell = float(ell)
+        nely = int(round(self.ell * self.ne))
+        if abs(nely - self.ell * self.ne) > 1e-9:
+            raise ValueError("ell * n_e must be an integer")
         self.cell = cell
-        self.nel = [self.L * self.ne] * p + [self.ell * self.ne] * q
+        self.nel = [self.L * self.ne] * p + [nely] * q
         self.periodic = [cell] * p + [False] * q
         # number of unknowns per direction
         self.ndof_dir = [self.ne if per else m - 1

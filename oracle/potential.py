@@ -75,6 +75,29 @@ def vfun(spec, p, q, ell=1):
                 out = out + gj * z[p + j]
             return out
         return f
+    if kind == "quad_table":
+        # V known only at the quadrature points of the period cell: a point's
+        # element is floor(z / h) (x cell-local), its Gauss point along each axis
+        # the lower or upper one of that element
+        ne = int(spec["ne"])
+        h = 1.0 / ne
+        tab = np.asarray(spec["table"], dtype=np.float64)
+        nel = [ne] * p + [int(round(ell * ne))] * q
+
+        def f(z):
+            d = p + q
+            elem = np.zeros(np.shape(z[0]), dtype=np.int64)
+            pt = np.zeros(np.shape(z[0]), dtype=np.int64)
+            stride = 1
+            for a in range(d):
+                u = np.asarray(z[a]) / h
+                e = np.floor(u).astype(np.int64)
+                upper = (u - e) > 0.5
+                elem += stride * e
+                pt += upper.astype(np.int64) << a
+                stride *= nel[a]
+            return tab[elem * (1 << d) + pt]
+        return f
     raise ValueError(f"unknown potential kind {kind!r}")
 
 

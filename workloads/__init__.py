@@ -72,6 +72,52 @@ def batch_config(n_instances=64, seed=5000):
                  V=sep_fourier(seed + 1 + j)) for j in range(n_instances)]
 
 
+def quad_points(p, q, ne, ell=1):
+    """Coordinates (one array per axis) of the quadrature points of one period
+    cell, in the order of a tabulated potential: the cell's elements (n_e per
+    expanding, ell n_e per fixed direction) lexicographically with axis 0
+    fastest, in each element its 2^(p+q) tensor 2-point Gauss points with point
+    index sum_a b_a 2^a, b_a = 0 at (e_a + (1 - 1/sqrt 3) / 2) h."""
+    d = p + q
+    h = 1.0 / ne
+    nel = [ne] * p + [int(round(ell * ne))] * q
+    off = (0.5 * (1.0 - 1.0 / np.sqrt(3.0)), 0.5 * (1.0 + 1.0 / np.sqrt(3.0)))
+    E = np.meshgrid(*[np.arange(m) for m in nel], indexing="ij")
+    E = [e.ravel(order="F") for e in E]
+    out = []
+    for a in range(d):
+        pts = np.array([off[(qi >> a) & 1] for qi in range(2 ** d)])
+        out.append(((E[a][:, None] + pts[None, :]) * h).ravel())
+    return out
+
+
+def quad_table(p, q, ne, ell, values):
+    """A tabulated potential dict from values at quad_points(p, q, ne, ell)."""
+    values = np.ascontiguousarray(values, dtype=np.float64)
+    return {"kind": "quad_table", "p": p, "q": q, "ne": ne, "ell": ell, "table": values}
+
+
+def coulomb_well(p, q, ne, ell=1, Z=1.0, b=1e-4):
+    """A truncated Coulomb well at the centre c of every period cell,
+    V = -Z / max(|z - c|, b) (the radial potential of §4.2, Z = 1, b = 1e-4)."""
+    z = quad_points(p, q, ne, ell)
+    r2 = sum((z[a] - 0.5) ** 2 for a in range(p)) + sum((z[p + j] - 0.5 * ell) ** 2
+                                                        for j in range(q))
+    return quad_table(p, q, ne, ell, -Z / np.maximum(np.sqrt(r2), b))
+
+
+def union_of_disks(ne, R=0.75, Z=1.0, b=1e-4, penalty=1.0e3):
+    """The linear chain of §4.2 on the box (0, L) x (0, 2R): disks of radius R
+    around the cell centres (i - 1/2, R) carry the truncated Coulomb potential
+    -Z / max(r, b), the rest of the box the penalty a (the penalised potential
+    of §4.2 that confines the eigenfunctions to the union of disks as a grows).
+    Adjacent disks overlap for R > 1/2.  ell = 2R must be a multiple of h."""
+    ell = 2.0 * R
+    z = quad_points(1, 1, ne, ell)
+    r = np.sqrt((z[0] - 0.5) ** 2 + (z[1] - R) ** 2)
+    return quad_table(1, 1, ne, ell, np.where(r <= R, -Z / np.maximum(r, b), penalty))
+
+
 def small_config(p, q, L, ne, delta, V, ell=1):
     return dict(name=f"p{p}q{q}-L{L}-ne{ne}-d{delta}", p=p, q=q, L=L, ell=ell, ne=ne,
                 delta=delta, V=V)
