@@ -69,13 +69,21 @@ typedef struct {
  *   SIN4         V = c0 prod_i sin^4(pi x_i) prod_j sin^4(pi y_j / ell)    (§4.1)
  *   SEP_SUM      V = c0 + sum_t a_t sin(2 pi k_t z_{m_t}) + sum_j g_j y_j  (§4.3;
  *                m_t is the 0-based coordinate index of term t)
+ *   QUAD_TABLE   any V (periodic in x by construction), given by its values at
+ *                the quadrature points of one period cell: the cell's elements
+ *                (n_e per expanding, ell n_e per fixed direction) in lexicographic
+ *                order, axis 0 fastest, each with its 2^(p+q) tensor Gauss points,
+ *                point index sum_a b_a 2^a where b_a = 0 selects the coordinate
+ *                (e_a + (1 - 1/sqrt 3) / 2) h and b_a = 1 (e_a + (1 + 1/sqrt 3) / 2) h;
+ *                table_len = n_e^p (ell n_e)^q 2^(p+q) values, copied by the call.
  * Arrays have nterms entries (g has q); at most DDEIG_MAX_TERMS terms. */
 typedef enum {
   DDEIG_V_CONST = 0,
   DDEIG_V_SEP_FOURIER = 1,
   DDEIG_V_FOURIER2 = 2,
   DDEIG_V_SIN4 = 3,
-  DDEIG_V_SEP_SUM = 4
+  DDEIG_V_SEP_SUM = 4,
+  DDEIG_V_QUAD_TABLE = 5
 } ddeig_vkind;
 
 #define DDEIG_MAX_TERMS 64
@@ -90,6 +98,8 @@ typedef struct {
   double cy;
   double c0;
   const double* g;
+  const double* table;  /* QUAD_TABLE: host array of table_len values */
+  long table_len;
 } ddeig_potential;
 
 typedef struct {

@@ -97,6 +97,8 @@ double mu_min(int nel, double h) {
 // min of V over the 2-point Gauss points of the cell elements
 double cell_vmin(const ddeig_problem* P) {
   const Geo& g = P->g;
+  if (P->vs.kind == DDEIG_V_QUAD_TABLE)
+    return *std::min_element(P->vtab_host.begin(), P->vtab_host.end());
   const double xs[2] = {0.5 * (1.0 - 1.0 / std::sqrt(3.0)), 0.5 * (1.0 + 1.0 / std::sqrt(3.0))};
   int ecount[3] = {1, 1, 1};
   for (int a = 0; a < g.D; ++a) ecount[a] = g.isx[a] ? g.ne : g.nel[a];
@@ -652,7 +654,7 @@ void rayleigh_ritz3(const double GA[3][3], const double GB[3][3], double c[3]) {
 ddeig_status make_vspec(const ddeig_potential* V, int p, int q, double ell, ddeig::VSpec& vs) {
   if (V->nterms < 0 || V->nterms > DDEIG_MAX_TERMS)
     return set_error(DDEIG_EINVAL, "nterms out of range");
-  if ((int)V->kind < 0 || (int)V->kind > 4) return set_error(DDEIG_EINVAL, "unknown potential kind");
+  if ((int)V->kind < 0 || (int)V->kind > 5) return set_error(DDEIG_EINVAL, "unknown potential kind");
   if (V->kind == DDEIG_V_FOURIER2 && p != 2)
     return set_error(DDEIG_EINVAL, "FOURIER2 potentials need p = 2");
   vs.kind = (int)V->kind;
@@ -684,7 +686,28 @@ ddeig_status make_vspec(const ddeig_potential* V, int p, int q, double ell, ddei
   if (V->kind == DDEIG_V_SEP_SUM && V->g != nullptr)
     for (int j = 0; j < q; ++j) vs.g[j] = V->g[j];
   if (!std::isfinite(vs.cy) || !std::isfinite(vs.c0)) return set_error(DDEIG_EINVAL, "non-finite cy/c0");
+  vs.table = nullptr;  // QUAD_TABLE: the caller sets the device copy (quad_table_len, upload)
+  return DDEIG_OK;
+}
 
+// Length of a QUAD_TABLE potential on the period cell of (p, q, n_e, ell).
+long quad_table_len(int p, int q, int ne, double ell) {
+  long len = 1L << (p + q);
+  for (int a = 0; a < p; ++a) len *= ne;
+  const long ely = std::lround(ell * ne);
+  for (int a = 0; a < q; ++a) len *= ely;
+  return len;
+}
+
+ddeig_status check_quad_table(const ddeig_potential* V, long expect) {
+  if (V->kind != DDEIG_V_QUAD_TABLE) return DDEIG_OK;
+  if (V->table == nullptr) return set_error(DDEIG_EINVAL, "QUAD_TABLE potential without a table");
+  if (V->table_len != expect)
+    return set_error(DDEIG_EINVAL, "QUAD_TABLE length is " + std::to_string(V->table_len) +
+                                       ", the period cell has " + std::to_string(expect) +
+                                       " quadrature points");
+  for (long i = 0; i < expect; ++i)
+    if (!std::isfinite(V->table[i])) return set_error(DDEIG_EINVAL, "non-finite QUAD_TABLE value");
   return DDEIG_OK;
 }
 
@@ -769,6 +792,8 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
   {
     const ddeig_status sv = make_vspec(V, p, q, ell, vs);
     if (sv != DDEIG_OK) return sv;
+    const ddeig_status st = check_quad_table(V, quad_table_len(p, q, ne, ell));
+    if (st != DDEIG_OK) return st;
   }
 
   ddeig::Geo g{};
@@ -812,6 +837,13 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
     P->tabAs = dalloc<double>(P, tt);
     P->dVS = dalloc<ddeig::VSpec>(P, 1);
     P->dWS = dalloc<ddeig::VSpec>(P, 1);
+    if (V->kind == DDEIG_V_QUAD_TABLE) {
+      P->vtab_host.assign(V->table, V->table + V->table_len);
+      P->dVtab = dalloc<double>(P, (size_t)V->table_len);
+      check_hip(hipMemcpy(P->dVtab, V->table, sizeof(double) * V->table_len,
+                          hipMemcpyHostToDevice), "copy potential table");
+      P->vs.table = P->dVtab;
+    }
     P->tabW = dalloc<double>(P, tt);
     check_hip(hipMemcpyAsync(P->dVS, &P->vs, sizeof(ddeig::VSpec), hipMemcpyHostToDevice, s), "copy V");
     launch_build_tables(P, s);
@@ -1471,9 +1503,24 @@ ddeig_status ddeig_potential_form(ddeig_problem* P, int space, const ddeig_poten
   {
     const ddeig_status sv = make_vspec(W, P->g.p, P->g.q, P->g.ell, ws);
     if (sv != DDEIG_OK) return sv;
+    const ddeig_status st = check_quad_table(W, quad_table_len(P->g.p, P->g.q, P->g.ne, P->g.ell));
+    if (st != DDEIG_OK) return st;
   }
   API_GUARD_BEGIN
   const hipStream_t s = P->stream;
+  if (W->kind == DDEIG_V_QUAD_TABLE) {
+    if (W->table_len > P->wtab_cap) {
+      dfree(P, P->dWtab);
+      P->dWtab = nullptr;
+      P->wtab_cap = 0;
+      P->dWtab = dalloc<double>(P, (size_t)W->table_len);
+      P->wtab_cap = W->table_len;
+    }
+    sync(P);  // an earlier form may still read the table
+    check_hip(hipMemcpy(P->dWtab, W->table, sizeof(double) * W->table_len,
+                        hipMemcpyHostToDevice), "copy weight table");
+    ws.table = P->dWtab;
+  }
   check_hip(hipMemcpyAsync(P->dWS, &ws, sizeof(ddeig::VSpec), hipMemcpyHostToDevice, s), "copy W");
   launch_build_wtable(P, P->dWS, P->tabW, s);
   long len;

@@ -78,6 +78,7 @@ struct VSpec {
   double a[DDEIG_MAX_TERMS], phi[DDEIG_MAX_TERMS];
   int k[DDEIG_MAX_TERMS], m[DDEIG_MAX_TERMS];
   double g[3];
+  const double* table;  // QUAD_TABLE: device copy of the quadrature-point values
 };
 
 // A box of unknowns: origin o[a] (0-based interior unknown index of the first
@@ -360,6 +361,12 @@ struct ddeig_problem {
   double** lvp = nullptr;
   double* lpart = nullptr;
   double* lout = nullptr;
+  // quadrature-point tables of a QUAD_TABLE potential (device) and of the last
+  // QUAD_TABLE weight of potential_form; host copy of the potential's table
+  double* dVtab = nullptr;
+  double* dWtab = nullptr;
+  long wtab_cap = 0;
+  std::vector<double> vtab_host;
   // GMRES work space (grown by ddeig_gmres_solve): basis V (gm_cap + 1 vectors),
   // preconditioned basis Z (gm_cap vectors), stride gm_ldv; partials, Hessenberg
   // matrix, rotations and small vectors

@@ -58,6 +58,17 @@ __device__ inline double weight_entry(const Geo& g, const VSpec& v, int t, long 
         }
         double sum = 0.0;
         const int nq = 1 << g.D;
+        // QUAD_TABLE: the element's place in the period cell (x cell-local)
+        long tab0 = 0;
+        if (v.kind == DDEIG_V_QUAD_TABLE) {
+          long stride = nq;
+          for (int a = 0; a < g.D; ++a) {
+            const int nel = g.isx[a] ? g.ne : g.nel[a];
+            const int ea = g.isx[a] ? ((ee[a] % g.ne) + g.ne) % g.ne : ee[a];
+            tab0 += stride * ea;
+            stride *= nel;
+          }
+        }
         for (int qi = 0; qi < nq; ++qi) {
           double z[3] = {0.0, 0.0, 0.0};
           double shape = 1.0;
@@ -68,7 +79,8 @@ __device__ inline double weight_entry(const Geo& g, const VSpec& v, int t, long 
             const double Nn = ln[a] ? xi : 1.0 - xi;
             shape *= Nj * Nn;
           }
-          sum += eval_V(v, z) * shape;
+          const double vq = v.kind == DDEIG_V_QUAD_TABLE ? v.table[tab0 + qi] : eval_V(v, z);
+          sum += vq * shape;
         }
         double wvol = 1.0;
         for (int a = 0; a < g.D; ++a) wvol *= 0.5 * h;

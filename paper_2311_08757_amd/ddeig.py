@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libddeig.so")
 DDEIG_OK = 0
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTSPD", -5: "ENOCONV",
           -6: "ESTATE", -7: "EINTERNAL"}
-V_KINDS = {"const": 0, "sep_fourier": 1, "fourier2": 2, "sin4": 3, "sep_sum": 4}
+V_KINDS = {"const": 0, "sep_fourier": 1, "fourier2": 2, "sin4": 3, "sep_sum": 4,
+           "quad_table": 5}
 OPS = {"A_sigma": 0, "A": 1, "M": 2, "K": 3}
 MAX_TERMS = 64
 
@@ -38,7 +39,8 @@ class Potential(ctypes.Structure):
                 ("a", ctypes.POINTER(ctypes.c_double)), ("phi", ctypes.POINTER(ctypes.c_double)),
                 ("k", ctypes.POINTER(ctypes.c_int)), ("m", ctypes.POINTER(ctypes.c_int)),
                 ("cy", ctypes.c_double), ("c0", ctypes.c_double),
-                ("g", ctypes.POINTER(ctypes.c_double))]
+                ("g", ctypes.POINTER(ctypes.c_double)),
+                ("table", ctypes.POINTER(ctypes.c_double)), ("table_len", ctypes.c_long)]
 
 
 class Options(ctypes.Structure):
@@ -207,6 +209,11 @@ def _potential(spec):
         V.k = iarr([t[2] for t in terms])
         V.c0 = float(spec["c0"])
         V.g = darr(spec.get("g", []))
+    elif kind == "quad_table":
+        tab = np.ascontiguousarray(spec["table"], dtype=np.float64)
+        keep.append(tab)
+        V.table = tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        V.table_len = tab.size
     else:
         raise ValueError(kind)
     return V, keep
