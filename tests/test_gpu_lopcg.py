@@ -211,3 +211,36 @@ def test_lopcg_table2_ordering(torch):
         its[inner], tot[inner] = out["outer_its"], out["inner_sum"]
     assert max(its.values()) - min(its.values()) <= 1, its
     assert tot["gmres"] < tot["cg"] < tot["ras2"] < tot["ras1"], tot
+
+
+@pytest.mark.timeout(300)
+def test_table2_union_of_disks(torch):
+    """§4.2 (Table 2) on the union-of-disks chain (disks of radius 3/4 around the
+    cell centres, truncated Coulomb potential Z = 1, b = 1e-4, penalty 1e3
+    outside, h = 1/8, delta = 2), N = 2..128 cells, FP64 local solves,
+    rTOL_i = TOL_o = 1e-8: outer iterations independent of the inner solver;
+    the worst inner solve of RAS1 grows about fourfold per doubling of N (run to
+    N = 32, as in the paper) while those of RAS2, CG+ASM2 and GMRES+RAS2 level
+    off; GMRES+RAS2 needs no more inner work than CG+ASM2 up to N = 16."""
+    import paper_2311_08757_amd as dd
+    V = W.union_of_disks(8)
+    mx, tot = {}, {}
+    for N in (2, 4, 8, 16, 32, 64, 128):
+        prob = dd.assemble(1, 1, N, 8, V, 2, ell=V["ell"])
+        dd.cell_shift(prob)
+        outer = set()
+        for inner in ("ras1", "ras2", "cg", "gmres"):
+            if inner == "ras1" and N > 32:
+                continue
+            x = torch.zeros(prob.n_dof, dtype=torch.float64, device="cuda")
+            o = dd.lopcg(prob, x, tol_o=1e-8, maxit_outer=500, mode="fixed", rtol_inner=1e-8,
+                         maxit_inner=10000, inner=inner)
+            outer.add(o["outer_its"])
+            mx[inner, N], tot[inner, N] = o["inner_max"], o["inner_sum"]
+        assert max(outer) - min(outer) <= 1, (N, outer)
+    for N in (4, 8, 16, 32):
+        assert mx["ras1", N] >= 3 * mx["ras1", N // 2], mx
+    for inner in ("ras2", "cg", "gmres"):
+        assert mx[inner, 128] <= 1.25 * mx[inner, 32], (inner, mx)
+    for N in (2, 4, 8, 16):
+        assert tot["gmres", N] <= tot["cg", N] < tot["ras2", N] < tot["ras1", N], (N, tot)
