@@ -244,3 +244,36 @@ def test_table2_union_of_disks(torch):
         assert mx[inner, 128] <= 1.25 * mx[inner, 32], (inner, mx)
     for N in (2, 4, 8, 16):
         assert tot["gmres", N] <= tot["cg", N] < tot["ras2", N] < tot["ras1", N], (N, tot)
+
+
+@pytest.mark.timeout(300)
+def test_fused_loops_43(torch):
+    """§4.3's setting: (0, L)^2 x (0, 1) with the unsymmetric potential
+    10 (4 + sin 2pi x + sin 4pi x + 2 sin 2pi y + 2 sin 4pi y + z), h = 1/10,
+    delta = 1 (a structured partition in place of METIS), TOL_o = 1e-10, bf16
+    local solves; fixed (rTOL_i = 1e-8) and adaptive inner steps by GMRES+RAS2,
+    fused with M_RAS,2.  Total inner work orders fused < adaptive < fixed and
+    stays bounded in L; all three reach the same eigenvalue, which at L = 4
+    matches the oracle's direct inverse iteration to 1e-10."""
+    import paper_2311_08757_amd as dd
+    from oracle.ipm import inverse_iteration_direct
+    from oracle.problem import Problem
+    V = W.sep_sum_43()
+    tot = {}
+    for L in (4, 8, 16):
+        prob = dd.assemble(2, 1, L, 10, V, 1, local_prec="bf16")
+        dd.cell_shift(prob)
+        lams = []
+        for mode in ("fixed", "adaptive", "fused"):
+            x = torch.zeros(prob.n_dof, dtype=torch.float64, device="cuda")
+            o = dd.lopcg(prob, x, tol_o=1e-10, maxit_outer=5000, mode=mode, rtol_inner=1e-8,
+                         inner="gmres")
+            tot[mode, L] = o["inner_sum"]
+            lams.append(o["lam"])
+        assert max(lams) - min(lams) <= 1e-10 * abs(lams[0]), lams
+        assert tot["fused", L] < tot["adaptive", L] < tot["fixed", L], tot
+        if L == 4:
+            P = Problem(W.small_config(2, 1, 4, 10, 1, V))
+            ref = inverse_iteration_direct(P.A, P.M, P.sigma, None, tol=1e-13, maxit=500)
+            assert abs(lams[2] - ref["lam"]) <= 1e-10 * abs(ref["lam"])
+    assert tot["fused", 16] <= 1.5 * tot["fused", 4], tot
