@@ -2178,6 +2178,7 @@ ddeig_status ddeig_batch_create(ddeig_problem* const* probs, int n, int flags, d
       d.st = P->st;
       d.gam = slot(P, 0);
       d.gam.np = (int)ddeig::stencil_tiles(P->g);
+      d.sty = ddeig::stencil2d_ty(P->g);
       d.rr = slot(P, 1);
       d.rr.np = d.nb_node;
       d.rz = slot(P, 2);

@@ -258,6 +258,7 @@ struct InstDev {
   int delta, pu, nsub;
   int nb_node;  // blocks of the node-parallel restriction / extension
   int nb_cf;    // blocks of the coarse field
+  int sty;      // rows of the 2-D stencil tiles (stencil2d_ty)
   int hist_cap;
   const double* tabAs;
   double* x;    // CG iterate
@@ -386,6 +387,7 @@ namespace ddeig {
 void launch_build_tables(const ddeig_problem* P, hipStream_t s);
 void launch_build_wtable(const ddeig_problem* P, const VSpec* dws, double* tW, hipStream_t s);
 long stencil_tiles(const Geo& g);
+int stencil2d_ty(const Geo& g);
 void launch_shift_table(const ddeig_problem* P, hipStream_t s);
 // y = T x (T one of the tables); dot / sum != nullptr: partial sums of x.y / of y
 void launch_stencil(const ddeig_problem* P, const double* tab, const double* x, double* y,

@@ -288,14 +288,14 @@ __global__ void __launch_bounds__(kBlock) k_stencil(Geo g, const double* __restr
 // k_stencil<2, MODE>.
 // The body takes the block's tile index `bid` (blockIdx.x of a single
 // problem, or the block's index within its instance in a grouped launch).
-template <int MODE>
+template <int MODE, int TY = 8>
 __device__ __forceinline__ void stencil2d_body(const Geo& g, const double* __restrict__ T,
                                                const double* __restrict__ x,
                                                const double* __restrict__ pold,
                                                double* __restrict__ pnew, double* __restrict__ y,
                                                const DirArgs& dir, int use_dot, const Red& dot,
                                                int use_sum, const Red& sum, int bid) {
-  constexpr int TX = 256, TY = 8, HX = TX + 2, HY = TY + 2, RX = TX / 64, RY = TY / 4;
+  constexpr int TX = 256, HX = TX + 2, HY = TY + 2, RX = TX / 64, RY = TY / 4;
   __shared__ double sv[HX * HY];
   double beta = 0.0;
   if constexpr (MODE == 1) {
@@ -365,14 +365,14 @@ __device__ __forceinline__ void stencil2d_body(const Geo& g, const double* __res
   if (use_sum) write_partial_at(accs, sum.part, bid);
 }
 
-template <int MODE>
+template <int MODE, int TY>
 __global__ void __launch_bounds__(kBlock) k_stencil2d(Geo g, const double* __restrict__ T,
                                                       const double* __restrict__ x,
                                                       const double* __restrict__ pold,
                                                       double* __restrict__ pnew,
                                                       double* __restrict__ y, DirArgs dir,
                                                       int use_dot, Red dot, int use_sum, Red sum) {
-  stencil2d_body<MODE>(g, T, x, pold, pnew, y, dir, use_dot, dot, use_sum, sum, blockIdx.x);
+  stencil2d_body<MODE, TY>(g, T, x, pold, pnew, y, dir, use_dot, dot, use_sum, sum, blockIdx.x);
 }
 
 // Grouped direction update + A_sigma p of PCG iteration k over the instances
@@ -383,15 +383,35 @@ __global__ void __launch_bounds__(kBlock) k_b_stencil_dir(const InstDev* __restr
   const InstDev& d = I[m.x];
   const DirArgs dir{d.st, k, d.rz};
   const Red none{nullptr, 0, nullptr};
-  stencil2d_body<1>(d.g, d.tabAs, d.z, d.pp[(k - 1) & 1], d.pp[k & 1], d.q, dir, 1, d.gam, 0, none,
-                    m.y);
+  // the instance's tile rows, as in its own sweep (uniform per block)
+  if (d.sty == 4)
+    stencil2d_body<1, 4>(d.g, d.tabAs, d.z, d.pp[(k - 1) & 1], d.pp[k & 1], d.q, dir, 1, d.gam, 0,
+                         none, m.y);
+  else
+    stencil2d_body<1, 8>(d.g, d.tabAs, d.z, d.pp[(k - 1) & 1], d.pp[k & 1], d.q, dir, 1, d.gam, 0,
+                         none, m.y);
 }
 
 void launch_b_stencil_dir(const InstDev* I, const BlockMap& bm, int k, hipStream_t s) {
   hipLaunchKernelGGL(k_b_stencil_dir, dim3(bm.nblocks), dim3(kBlock), 0, s, I, bm.map, k);
 }
 
+// Rows of the 2-D sweep's tiles (n_e dividing 64): 4 while 4-row tiles number
+// at most 1024 (one partial each), else 8.  Small grids, whose vectors sit in
+// the Infinity Cache and whose sweep is latency-bound, get twice the
+// workgroups (config 2: 1024 tiles, 7.2 -> 5.9 us per sweep).
+int stencil2d_ty(const Geo& g) {
+  const long t4 = (long)((g.N[0] + 255) / 256) * ((g.N[1] + 3) / 4);
+  return t4 <= kMaxRed ? 4 : 8;
+}
+
+static bool stencil2d_fast(const Geo& g) { return g.D == 2 && 64 % g.ne == 0; }
+
 long stencil_tiles(const Geo& g) {
+  if (stencil2d_fast(g)) {
+    const int ty = stencil2d_ty(g);
+    return (long)((g.N[0] + 255) / 256) * ((g.N[1] + ty - 1) / ty);
+  }
   if (g.D == 2)
     return (long)((g.N[0] + TileShape<2>::TX - 1) / TileShape<2>::TX) *
            ((g.N[1] + TileShape<2>::TY - 1) / TileShape<2>::TY);
@@ -443,9 +463,11 @@ void launch_stencil(const ddeig_problem* P, const double* tab, const double* x, 
   const TileRed td = tile_red(P, dot ? *dot : none, tiles, 0);
   const TileRed ts = tile_red(P, sum ? *sum : none, tiles, 1);
   const int blocks = (int)std::max<long>(1, tiles);
-  if (P->g.D == 2 && 64 % P->g.ne == 0)
-    hipLaunchKernelGGL(k_stencil2d<0>, dim3(blocks), dim3(kBlock), 0, s, P->g, tab, x, nullptr,
-                       nullptr, y, nodir, dot ? 1 : 0, td.use, sum ? 1 : 0, ts.use);
+  if (stencil2d_fast(P->g)) {
+    auto kern = stencil2d_ty(P->g) == 4 ? k_stencil2d<0, 4> : k_stencil2d<0, 8>;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, P->g, tab, x, nullptr, nullptr, y,
+                       nodir, dot ? 1 : 0, td.use, sum ? 1 : 0, ts.use);
+  }
   else if (P->g.D == 2)
     hipLaunchKernelGGL((k_stencil<2, 0>), dim3(blocks), dim3(kBlock), 0, s, P->g, tab, x,
                        nullptr, nullptr, y, nodir, dot ? 1 : 0, td.use, sum ? 1 : 0, ts.use);
@@ -468,9 +490,11 @@ void launch_stencil_dir(const ddeig_problem* P, const double* z, const double* p
   const Red none{nullptr, 0, nullptr};
   const TileRed tg = tile_red(P, gam, tiles, 0);
   const int blocks = (int)std::max<long>(1, tiles);
-  if (P->g.D == 2 && 64 % P->g.ne == 0)
-    hipLaunchKernelGGL(k_stencil2d<1>, dim3(blocks), dim3(kBlock), 0, s, P->g, P->tabAs, z, pold,
-                       pnew, q, dir, 1, tg.use, 0, none);
+  if (stencil2d_fast(P->g)) {
+    auto kern = stencil2d_ty(P->g) == 4 ? k_stencil2d<1, 4> : k_stencil2d<1, 8>;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, P->g, P->tabAs, z, pold, pnew, q,
+                       dir, 1, tg.use, 0, none);
+  }
   else if (P->g.D == 2)
     hipLaunchKernelGGL((k_stencil<2, 1>), dim3(blocks), dim3(kBlock), 0, s, P->g, P->tabAs, z,
                        pold, pnew, q, dir, 1, tg.use, 0, none);
