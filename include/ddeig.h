@@ -126,6 +126,7 @@ typedef struct {
   int breakdown;      /* 1 if p.A_sigma p <= 0, 2 if r.z <= 0 */
   double* hist;       /* optional host array: hist[k] = ||r_k|| / ||r_0||, k = 0..iters */
   int hist_cap;       /* capacity of hist */
+  double true_relres; /* ||b - A_sigma x||_2 / ||r_0||_2 recomputed from the returned x */
 } ddeig_pcg_info;
 
 typedef struct {
@@ -135,6 +136,8 @@ typedef struct {
   long inner_sum;
   int inner_max;
   double t_solve_ms;
+  double spec_res;    /* ||A x - lambda M x||_2 of the returned (M-normalised) x */
+  double t_setup_ms;  /* wall time of ddeig_assemble and the shift calls of the problem */
 } ddeig_eig_info;
 
 /* Builds the period-cell operator tables (K, M, M_V at one period cell: §2,

@@ -763,6 +763,7 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
                             ddeig_problem** out) {
   if (out == nullptr) return set_error(DDEIG_EINVAL, "out is NULL");
   *out = nullptr;
+  const auto t_start = std::chrono::steady_clock::now();
   if (geom == nullptr || V == nullptr) return set_error(DDEIG_EINVAL, "geometry or potential is NULL");
   const int p = geom->p, q = geom->q, L = geom->L;
   if (p < 1 || q < 1 || p + q < 2 || p + q > 3)
@@ -1256,6 +1257,8 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
     ddeig_destroy(P);
     return set_error(DDEIG_EINTERNAL, "unexpected exception in assemble");
   }
+  P->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                            t_start).count();
   *out = P;
   return DDEIG_OK;
 }
@@ -1553,19 +1556,24 @@ ddeig_status ddeig_set_shift(ddeig_problem* P, double sigma, const double* psi_c
   if (psi_cell_host == nullptr && P->opt.coarse)
     return set_error(DDEIG_EINVAL, "the two-level preconditioner needs the cell vector psi");
   API_GUARD_BEGIN
+  const auto t_start = std::chrono::steady_clock::now();
   P->shifted = 0;
   P->sigma = sigma;
   if (psi_cell_host)
     check_hip(hipMemcpyAsync(P->psi, psi_cell_host, sizeof(double) * P->g.tsize,
                              hipMemcpyHostToDevice, P->stream), "copy psi");
   sync(P);
-  return finish_shift(P);
+  const ddeig_status st = finish_shift(P);
+  P->t_setup_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                             t_start).count();
+  return st;
   API_GUARD_END
 }
 
 ddeig_status ddeig_cell_shift(ddeig_problem* P, double* sigma_out, double* psi_cell_host) {
   if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
   API_GUARD_BEGIN
+  const auto t_start = std::chrono::steady_clock::now();
   P->shifted = 0;
   const Geo& g = P->g;
   const hipStream_t s = P->stream;
@@ -1619,7 +1627,10 @@ ddeig_status ddeig_cell_shift(ddeig_problem* P, double* sigma_out, double* psi_c
   dfree(P, Wc); dfree(P, v0); dfree(P, v1); dfree(P, v2); dfree(P, v3);
   P->sigma = sig;
   if (sigma_out) *sigma_out = sig;
-  return finish_shift(P);
+  const ddeig_status st = finish_shift(P);
+  P->t_setup_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                             t_start).count();
+  return st;
   API_GUARD_END
 }
 
@@ -1674,11 +1685,47 @@ ddeig_status ddeig_apply_schwarz(ddeig_problem* P, int kind, const double* r, do
   API_GUARD_END
 }
 
-static void fill_info(ddeig_problem* P, const PcgOut& o, int breakdown, ddeig_pcg_info* info) {
+}  // extern "C"
+
+namespace ddeig {
+
+// ||b - A_sigma x||_2 / ||r_0||_2 recomputed from x (r_0 of the solve that
+// left its state in P->st; 0 when r_0 = 0).
+double true_relres(ddeig_problem* P, const double* b, const double* x) {
+  const hipStream_t s = P->stream;
+  Red rr = slot(P, 10);
+  launch_stencil(P, P->tabAs, x, P->q, nullptr, nullptr, s);
+  launch_resid_init(P, b, P->q, P->r, rr, s);
+  const double rn2 = host_sum(P, rr);
+  PcgState hs{};
+  check_hip(hipMemcpy(&hs, P->st, sizeof(PcgState), hipMemcpyDeviceToHost), "state");
+  return hs.r0n2 > 0.0 ? std::sqrt(std::max(rn2, 0.0) / hs.r0n2) : 0.0;
+}
+
+// ||A x - lambda M x||_2 of an M-normalised x.
+double spectral_residual(ddeig_problem* P, const double* x, double lambda) {
+  const hipStream_t s = P->stream;
+  launch_stencil(P, P->tabA, x, P->q, nullptr, nullptr, s);
+  launch_stencil(P, P->tabM, x, P->z, nullptr, nullptr, s);
+  Red rr = slot(P, 11);
+  launch_lopcg_resid(P->g.n, lambda, P->q, P->z, P->w, rr.part, rr.val, s);
+  double v = 0.0;
+  check_hip(hipMemcpyAsync(&v, rr.val, sizeof(double), hipMemcpyDeviceToHost, s), "copy scalar");
+  sync(P);
+  return std::sqrt(std::max(v, 0.0));
+}
+
+}  // namespace ddeig
+
+extern "C" {
+
+static void fill_info(ddeig_problem* P, const PcgOut& o, int breakdown, ddeig_pcg_info* info,
+                      const double* b = nullptr, const double* x = nullptr) {
   if (!info) return;
   info->iters = o.iters;
   info->relres = o.relres;
   info->breakdown = breakdown;
+  info->true_relres = b ? ddeig::true_relres(P, b, x) : o.relres;
   if (info->hist && info->hist_cap > 0) {
     const int cnt = std::min(std::min(info->hist_cap, o.iters + 1), P->hist_cap);
     check_hip(hipMemcpyAsync(info->hist, P->hist, sizeof(double) * cnt, hipMemcpyDeviceToHost,
@@ -1700,7 +1747,7 @@ ddeig_status ddeig_stationary_ras(ddeig_problem* P, int levels, const double* b,
     return set_error(DDEIG_ESTATE, "the problem was assembled without the coarse space");
   API_GUARD_BEGIN
   const PcgOut o = sras_run(P, levels, b, x, rtol, maxit);
-  fill_info(P, o, o.done == 2 ? 1 : 0, info);
+  fill_info(P, o, o.done == 2 ? 1 : 0, info, b, x);
   if (o.done == 2) return set_error(DDEIG_ENOCONV, "stationary RAS diverged");
   if (o.done != 1) return set_error(DDEIG_ENOCONV, "stationary RAS reached maxit");
   return DDEIG_OK;
@@ -1724,7 +1771,7 @@ ddeig_status ddeig_gmres_solve(ddeig_problem* P, int kind, const double* b, doub
                          std::max(1, restart > 0 ? std::min(restart, std::max(maxit, 1))
                                                  : std::min(std::max(maxit, 1), 300)));
   const PcgOut o = gmres_run(P, flags, b, x, rtol, maxit, m);
-  fill_info(P, o, o.done == 2 ? 1 : 0, info);
+  fill_info(P, o, o.done == 2 ? 1 : 0, info, b, x);
   if (o.done == 2) return set_error(DDEIG_ENOCONV, "GMRES breakdown (zero Hessenberg column)");
   if (o.done != 1) return set_error(DDEIG_ENOCONV, "GMRES reached maxit");
   return DDEIG_OK;
@@ -1741,17 +1788,7 @@ ddeig_status ddeig_pcg_solve(ddeig_problem* P, const double* b, double* x, doubl
   if (!P->shifted) return set_error(DDEIG_ESTATE, "pcg_solve before the shift is set");
   API_GUARD_BEGIN
   const PcgOut o = pcg_run(P, b, x, rtol, maxit);
-  if (info) {
-    info->iters = o.iters;
-    info->relres = o.relres;
-    info->breakdown = o.done == 2 ? 1 : (o.done == 3 ? 2 : 0);
-    if (info->hist && info->hist_cap > 0) {
-      const int cnt = std::min(std::min(info->hist_cap, o.iters + 1), P->hist_cap);
-      check_hip(hipMemcpyAsync(info->hist, P->hist, sizeof(double) * cnt, hipMemcpyDeviceToHost,
-                               P->stream), "copy history");
-      sync(P);
-    }
-  }
+  fill_info(P, o, o.done == 2 ? 1 : (o.done == 3 ? 2 : 0), info, b, x);
   if (o.done == 2 || o.done == 3)
     return set_error(DDEIG_ENOTSPD, o.done == 2 ? "CG breakdown: p.A_sigma p <= 0"
                                                 : "CG breakdown: r.z <= 0");
@@ -1818,6 +1855,8 @@ ddeig_status ddeig_inverse_iteration(ddeig_problem* P, double* x, double tol_x, 
     info->inner_sum = inner_sum;
     info->inner_max = inner_max;
     info->t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    info->spec_res = ddeig::spectral_residual(P, x, lam);
+    info->t_setup_ms = P->t_setup_ms;
   }
   if (st == DDEIG_ENOCONV) return set_error(st, "inverse iteration reached maxit_outer");
   return st;
@@ -2259,6 +2298,7 @@ ddeig_status ddeig_batch_pcg_solve(ddeig_batch* B, const double* const* b, doubl
       info[j].iters = h.iters;
       info[j].relres = h.relres;
       info[j].breakdown = h.done == 2 ? 1 : (h.done == 3 ? 2 : 0);
+      info[j].true_relres = ddeig::true_relres(B->P[j], b[j], x[j]);
     }
     if (h.done == 2 || h.done == 3)
       st = set_error(DDEIG_ENOTSPD, "instance " + std::to_string(j) + ": CG breakdown");
@@ -2363,6 +2403,8 @@ ddeig_status ddeig_batch_inverse_iteration(ddeig_batch* B, double* const* x, dou
       info[j].inner_sum = inner_sum[j];
       info[j].inner_max = inner_max[j];
       info[j].t_solve_ms = ms;
+      info[j].spec_res = ddeig::spectral_residual(B->P[j], x[j], lam[j]);
+      info[j].t_setup_ms = B->P[j]->t_setup_ms;
     }
     if (status[j] == DDEIG_ENOTSPD)
       st = set_error(DDEIG_ENOTSPD, "instance " + std::to_string(j) + ": CG breakdown");

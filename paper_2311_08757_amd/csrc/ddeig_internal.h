@@ -364,6 +364,7 @@ struct ddeig_problem {
   double* lout = nullptr;
   // quadrature-point tables of a QUAD_TABLE potential (device) and of the last
   // QUAD_TABLE weight of potential_form; host copy of the potential's table
+  double t_setup_ms = 0.0;  // assemble + shift calls so far (wall time)
   double* dVtab = nullptr;
   double* dWtab = nullptr;
   long wtab_cap = 0;

@@ -50,13 +50,15 @@ class Options(ctypes.Structure):
 
 class PcgInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("relres", ctypes.c_double), ("breakdown", ctypes.c_int),
-                ("hist", ctypes.POINTER(ctypes.c_double)), ("hist_cap", ctypes.c_int)]
+                ("hist", ctypes.POINTER(ctypes.c_double)), ("hist_cap", ctypes.c_int),
+                ("true_relres", ctypes.c_double)]
 
 
 class EigInfo(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("dx_M", ctypes.c_double),
                 ("outer_its", ctypes.c_int), ("inner_sum", ctypes.c_long),
-                ("inner_max", ctypes.c_int), ("t_solve_ms", ctypes.c_double)]
+                ("inner_max", ctypes.c_int), ("t_solve_ms", ctypes.c_double),
+                ("spec_res", ctypes.c_double), ("t_setup_ms", ctypes.c_double)]
 
 
 class LopcgInfo(ctypes.Structure):
@@ -297,7 +299,7 @@ def _krylov(fn, name, prob, lead, b, x, tail, hist_cap, raise_on_error):
     st = fn(prob.handle, *lead, _ptr(b, prob.n_dof, "b"), _ptr(x, prob.n_dof, "x"), *tail,
             ctypes.byref(info))
     out = dict(status=STATUS.get(st, st), iters=info.iters, relres=info.relres,
-               breakdown=info.breakdown,
+               true_relres=info.true_relres, breakdown=info.breakdown,
                hist=hist[:min(hist_cap, info.iters + 1)] if hist_cap > 0 else None)
     if raise_on_error and st != DDEIG_OK:
         _check(st, name)
@@ -351,7 +353,7 @@ def inverse_iteration(prob, x, tol_x=1e-9, maxit_outer=100, rtol_inner=1e-10, ma
                                      ctypes.byref(info))
     out = dict(status=STATUS.get(st, st), lam=info.lambda_, dx_M=info.dx_M,
                outer_its=info.outer_its, inner_sum=info.inner_sum, inner_max=info.inner_max,
-               t_solve_ms=info.t_solve_ms)
+               t_solve_ms=info.t_solve_ms, spec_res=info.spec_res, t_setup_ms=info.t_setup_ms)
     if raise_on_error and st != DDEIG_OK:
         _check(st, "ddeig_inverse_iteration")
     return out
@@ -450,8 +452,8 @@ def batch_pcg_solve(batch, bs, xs, rtol=1e-10, maxit=1000, raise_on_error=True):
                                    float(rtol), int(maxit), info)
     if raise_on_error and st != DDEIG_OK:
         _check(st, "ddeig_batch_pcg_solve")
-    return STATUS.get(st, st), [dict(iters=i.iters, relres=i.relres, breakdown=i.breakdown)
-                                for i in info]
+    return STATUS.get(st, st), [dict(iters=i.iters, relres=i.relres, breakdown=i.breakdown,
+                                     true_relres=i.true_relres) for i in info]
 
 
 def batch_inverse_iteration(batch, xs, tol_x=1e-9, maxit_outer=100, rtol_inner=1e-10,
@@ -467,7 +469,8 @@ def batch_inverse_iteration(batch, xs, tol_x=1e-9, maxit_outer=100, rtol_inner=1
         _check(st, "ddeig_batch_inverse_iteration")
     return STATUS.get(st, st), [dict(lam=i.lambda_, dx_M=i.dx_M, outer_its=i.outer_its,
                                      inner_sum=i.inner_sum, inner_max=i.inner_max,
-                                     t_solve_ms=i.t_solve_ms) for i in info]
+                                     t_solve_ms=i.t_solve_ms, spec_res=i.spec_res,
+                                     t_setup_ms=i.t_setup_ms) for i in info]
 
 
 LOPCG_MODES = {"fixed": 0, "adaptive": 1, "fused": 2}

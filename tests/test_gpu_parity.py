@@ -245,3 +245,32 @@ def test_graph_replay_bitwise(torch, prec):
     xs = [torch.zeros_like(b) for _ in probs]
     outs = [dd.inverse_iteration(pr, xx, tol_x=1e-10, rtol_inner=1e-10) for pr, xx in zip(probs, xs)]
     assert outs[0]["lam"] == outs[1]["lam"] and torch.equal(xs[0], xs[1])
+
+
+def test_info_fields(torch):
+    """true_relres is ||b - A_sigma x|| / ||r_0|| of the returned x (checked against
+    the oracle's matrix on the host), spec_res is ||A x - lambda M x|| of the
+    returned eigenvector, t_setup_ms the time spent in assemble and the shift."""
+    import paper_2311_08757_amd as dd
+    case = CASES[0]
+    P = _oracle(case)
+    prob = _assemble(case)
+    dd.cell_shift(prob)
+    b = W.random_vector(P.grid.n, 21)
+    bd = _dev(torch, b)
+    for run in (lambda x: dd.pcg_solve(prob, bd, x, rtol=1e-10, maxit=500),
+                lambda x: dd.gmres_solve(prob, bd, x, rtol=1e-10, maxit=500),
+                lambda x: dd.stationary_ras(prob, bd, x, rtol=1e-10, maxit=5000)):
+        x = torch.zeros_like(bd)
+        out = run(x)
+        xs = x.cpu().numpy()
+        ref = np.linalg.norm(b - P.A_sigma @ xs) / np.linalg.norm(b)
+        assert abs(out["true_relres"] - ref) <= 1e-6 * ref + 1e-15
+        assert out["true_relres"] <= 1.1e-10
+    x = torch.zeros_like(bd)
+    out = dd.inverse_iteration(prob, x, tol_x=1e-10, rtol_inner=1e-11)
+    xs = x.cpu().numpy()
+    ref = np.linalg.norm(P.A @ xs - out["lam"] * (P.M @ xs))
+    assert abs(out["spec_res"] - ref) <= 1e-6 * ref + 1e-13
+    assert out["spec_res"] <= 1e-6
+    assert out["t_setup_ms"] > 0.0
