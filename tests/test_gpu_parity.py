@@ -274,3 +274,39 @@ def test_info_fields(torch):
     assert abs(out["spec_res"] - ref) <= 1e-6 * ref + 1e-13
     assert out["spec_res"] <= 1e-6
     assert out["t_setup_ms"] > 0.0
+
+
+@pytest.mark.timeout(300)
+def test_source_problem_41(torch):
+    """§4.1: A_sigma u = M 1 (f = 1) by CG from x0 = 1 to rTOL = 1e-8 with the
+    distance-based partition of unity, V = 100 sin^4 sin^4, FP64 local solves.
+    Iteration counts equal the oracle's (+-1) at L = 8; AS2's stay bounded in L
+    (L = 512 within 1.25 of L = 32) while AS1's grow about linearly; a thicker
+    overlap helps AS2."""
+    import paper_2311_08757_amd as dd
+    from oracle.pcg import pcg
+    from oracle.problem import Problem
+    V = W.sin4()
+
+    def run(L, ne, delta, coarse):
+        prob = dd.assemble(1, 1, L, ne, V, delta, pu="distance", coarse=coarse)
+        dd.cell_shift(prob)
+        one = torch.ones(prob.n_dof, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(one)
+        dd.apply_op(prob, "M", one, b)
+        x = torch.ones_like(one)
+        return dd.pcg_solve(prob, b, x, rtol=1e-8, maxit=20000)["iters"]
+
+    P = Problem(W.small_config(1, 1, 8, 10, 1, V), pu="distance")
+    n = P.grid.n
+    b = P.M @ np.ones(n)
+    for coarse in (False, True):
+        ref = pcg(lambda v: P.A_sigma @ v, b, P.preconditioner(coarse).apply, x0=np.ones(n),
+                  rtol=1e-8, maxit=5000)
+        assert abs(run(8, 10, 1, coarse) - ref.iters) <= 1, coarse
+    for ne, delta in ((10, 1), (30, 3)):
+        as1 = {L: run(L, ne, delta, False) for L in (32, 512)}
+        as2 = {L: run(L, ne, delta, True) for L in (32, 512)}
+        assert as2[512] <= 1.25 * as2[32], (ne, delta, as2)
+        assert as1[512] >= 8 * as1[32], (ne, delta, as1)
+    assert run(512, 10, 3, True) < run(512, 10, 1, True)
