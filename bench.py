@@ -337,12 +337,17 @@ def main():
     inner = 0
     lams = []
     outers = []
+    per_solve = []
+    spec_res = None
     for i in range(args.steps):
+        ts = time.perf_counter()
         x.zero_()
         out = dd.inverse_iteration(prob, x, tol_x=1e-9, rtol_inner=1e-10, maxit_inner=2000)
+        per_solve.append((time.perf_counter() - ts) * 1e3)  # the call synchronises
         inner += out["inner_sum"]
         lams.append(out["lam"])
         outers.append(out["outer_its"])
+        spec_res = out["spec_res"]
     torch.cuda.synchronize()
     T = max(time.perf_counter() - t0, 1e-9)
     print(f"# timed {args.steps} solves in {T:.3f}s, inner={inner}", file=sys.stderr, flush=True)
@@ -401,8 +406,9 @@ def main():
     # the same eigen-solve with FP64 block-chain local solves
     cmp = None
     if not args.no_compare and args.local_prec != "fp64":
+        # the plain FP64 baseline: FP64 block-chain local solves, no graph capture
         p64 = dd.assemble(cfg["p"], cfg["q"], cfg["L"], cfg["ne"], cfg["V"], cfg["delta"],
-                          local_prec="fp64", graphs=bool(args.graphs))
+                          local_prec="fp64", graphs=False)
         dd.cell_shift(p64)
         x.zero_()
         dd.inverse_iteration(p64, x, tol_x=1e-9, rtol_inner=1e-10, maxit_inner=2000)
@@ -502,7 +508,12 @@ def main():
                    "time_to_eigenpair_ms": T / max(args.steps, 1) * 1e3, "setup_s": t_setup,
                    "outer_its": outers[-1] if outers else None,
                    "pcg_iters_per_solve": inner / max(args.steps, 1),
-                   "lambda": lams[-1] if lams else None, "lambda_rel_err_vs_oracle": lam_err},
+                   "solve_ms_median": float(np.median(per_solve)) if per_solve else None,
+                   "solve_ms_min": min(per_solve) if per_solve else None,
+                   "lambda": lams[-1] if lams else None, "lambda_rel_err_vs_oracle": lam_err,
+                   "spectral_residual": spec_res},
+        "env": {"torch": torch.__version__, "hip": torch.version.hip,
+                "device": torch.cuda.get_device_name(0)},
         "roofline": roof,
         "stencil_roofline": stencil_roof,
         "fp64_comparison": cmp,
