@@ -1046,22 +1046,21 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
       }
     }
     // FP64 / FP32 local solves of 3-D boxes: chain solves batched over the
-    // members of a class (one launch per sweep step), when the two LDS slices
-    // of a workgroup fit
+    // members of a class (two launches per sweep step)
     int maxb_types = 0;
     for (auto& T : P->types) maxb_types = std::max(maxb_types, T.box.b);
-    const bool batched_chain = !dense && g.D == 3 &&
-                               ddeig::chain_lds_bytes(maxb_types, o.local_prec == 1) <= 160 * 1024;
+    const bool batched_chain = !dense && g.D == 3;
     std::vector<ddeig::ChainJob> chainjobs;
+    int mtot = 0;
     for (size_t t = 0; t < P->types.size(); ++t) {
       auto& T = P->types[t];
       maxb = std::max(maxb, T.box.b);
       const long mm = (long)T.box.nch * T.box.b;
       if (batched_chain) {
-        const int nm = o.local_prec == 1 ? 16 : 8;
-        for (int m0 = 0; m0 < T.nmem; m0 += nm)
-          for (int r0 = 0; r0 < T.box.b; r0 += 64)
-            chainjobs.push_back(ddeig::ChainJob{(int)t, m0, std::min(nm, T.nmem - m0), r0});
+        const int mg = ddeig::chain_group_members();
+        for (int m0 = 0; m0 < T.nmem; m0 += mg)
+          chainjobs.push_back(ddeig::ChainJob{(int)t, m0, std::min(mg, T.nmem - m0), mtot + m0});
+        mtot += T.nmem;
       }
       for (int a = 0; a < 3; ++a) tdev[t].m[a] = T.box.m[a];
       tdev[t].b = T.box.b;
@@ -1108,8 +1107,10 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
     }
     if (P->types.size() > (size_t)ddeig::kMaxTypes) throw Failure{DDEIG_EINTERNAL, "too many classes"};
     if (batched_chain) {
-      P->chain_lds = ddeig::chain_lds_bytes(maxb_types, o.local_prec == 1);
-      ddeig::chain_kernel_setup(o.local_prec == 1, P->chain_lds);
+      P->chain_bmax = maxb_types;
+      P->chain_mtot = mtot;
+      P->chain_part = dalloc<unsigned char>(
+          P, ddeig::chain_part_bytes(maxb_types, mtot, o.local_prec == 1));
       P->nchainjobs = (int)chainjobs.size();
       P->dChainJobs = dalloc<ddeig::ChainJob>(P, chainjobs.size());
       check_hip(hipMemcpyAsync(P->dChainJobs, chainjobs.data(),

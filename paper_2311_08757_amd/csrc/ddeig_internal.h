@@ -224,8 +224,11 @@ struct CoarseSolveArgs {
   double* y;
 };
 
+// A group of at most 64 members of one class in the batched chain solves:
+// class, first member within the class, count, and the group's first member
+// in the partial-product buffer (members of all classes numbered in order).
 struct ChainJob {
-  int type, m0, nm, r0;
+  int type, m0, nm, mg0;
 };
 
 struct GemmTile {
@@ -335,8 +338,9 @@ struct ddeig_problem {
   int ntiles = 0, ngemv = 0, ksplit = 1;
   // batched chain solves (3-D FP64 / FP32 local solves)
   ddeig::ChainJob* dChainJobs = nullptr;
-  int nchainjobs = 0, chain_nm = 0;
-  size_t chain_lds = 0;
+  int nchainjobs = 0;
+  int chain_bmax = 0, chain_mtot = 0;  // largest slice, all members of all classes
+  void* chain_part = nullptr;          // K-chunk partial products of a sweep step
   ddeig::GemmTile* dTiles = nullptr;
   ddeig::GemvRows* dGemv = nullptr;
   ddeig::GemmType* dGtypes = nullptr;
@@ -435,8 +439,8 @@ void launch_restrict(const ddeig_problem* P, double* r, PcgState* st, const XrAr
 void launch_local_solves(const ddeig_problem* P, const PcgState* st, hipStream_t s,
                          const double* coarse_r = nullptr);
 bool fused_coarse(const ddeig_problem* P);
-size_t chain_lds_bytes(int maxb, int fp32);
-void chain_kernel_setup(int fp32, size_t lds);
+int chain_group_members();
+size_t chain_part_bytes(int bmax, int mtot, int fp32);
 void launch_coarse_solve(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 void launch_coarse_field(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 void launch_coarse_rhs(const ddeig_problem* P, const double* r, const PcgState* st, hipStream_t s);

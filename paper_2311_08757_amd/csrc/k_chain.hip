@@ -267,178 +267,204 @@ __global__ void __launch_bounds__(kBlock) k_local_solves(Geo g, const double* __
 //
 // All members of a class share the factors W_i, so a sweep step is the same
 // for every member: forward t_i = W_i (b_i - E_i t_{i-1}), backward
-// x_i = t_i - W_i E_{i+1}^T x_{i+1}.  One launch per step covers all classes;
-// a workgroup takes NM members of one class and 64 rows of slice i:
-//   1. the members' neighbouring slice (t_{i-1} or x_{i+1}) is staged in LDS,
-//   2. the slice's right-hand side g (coupling taps from the table) is formed
-//      in LDS for all b rows,
-//   3. rows [r0, r0 + 64) of W_i g, lanes over rows (W_i symmetric: its
-//      columns are read, which coalesces), waves over quarters of the K range.
-// W_i is read once per step for NM members instead of once per member.  The
-// forward sweep writes t to a second batch (other workgroups of the step still
-// read b_i), the backward sweep writes x into the batch.  Arithmetic in WT
-// (FP64, or FP32 for local_prec 1).  3-D boxes only (chain along the last
-// dim, slices of the first two).
+// x_i = t_i - W_i E_{i+1}^T x_{i+1}.  A step is three launches:
+//   k_chain_rhs: the right-hand sides g of every member (the coupling taps
+//     from the table), thread per row, into a buffer [member][row];
+//   k_chain_mm: workgroup (row tile of 64 rows, K chunk, member group of up
+//     to 64 members of one class) stages its K chunk of g in LDS and
+//     multiplies it by rows [r0, r0 + 64) of W_i restricted to the chunk
+//     (lane = row, reading W_i by columns since it is symmetric, which
+//     coalesces; wave = 16 members); the partial products go to a buffer
+//     [K chunk][member][row];
+//   k_chain_fin: adds the K-chunk partials of each (member, row) in chunk
+//     order and writes t_i (forward) or x_i = t_i - (sum) (backward).
+// W_i is read once per member group and step, and a step has row tiles x
+// K chunks x groups workgroups.  Arithmetic in WT (FP64, or FP32 for
+// local_prec 1) with the right-hand sides formed in FP64.  3-D boxes only
+// (chain along the last dim, slices of the first two).
+template <typename WT>
+struct ChainCfg {
+  static constexpr int RT = 64;                         // rows per workgroup
+  static constexpr int KC = 64;                         // K chunk (16 or 32 KB of LDS)
+  static constexpr int MG = 64;                         // members per group
+};
 
-template <typename WT, int NM, bool FWD>
-__global__ void __launch_bounds__(kBlock) k_chain_step(Geo g, const double* __restrict__ T,
-                                                       const TypeDev* __restrict__ types,
-                                                       const ChainJob* __restrict__ jobs, int i,
-                                                       const PcgState* __restrict__ st) {
-  extern __shared__ unsigned char smem_raw[];
+// The right-hand sides g of step i for every member of a job, once per step:
+// row r of member m into G[(mg0 + m) * bmax + r] (thread per row).
+template <typename WT, bool FWD>
+__global__ void __launch_bounds__(kBlock) k_chain_rhs(Geo g, const double* __restrict__ T,
+                                                      const TypeDev* __restrict__ types,
+                                                      const ChainJob* __restrict__ jobs, int i,
+                                                      int bmax, WT* __restrict__ G,
+                                                      const PcgState* __restrict__ st) {
   if (st != nullptr && st->done) return;
-  const ChainJob jb = jobs[blockIdx.x];
+  const ChainJob jb = jobs[blockIdx.y];
   const TypeDev td = types[jb.type];
   const int b = td.b, nch = td.nch;
-  WT* sp = reinterpret_cast<WT*>(smem_raw);  // [b][NM] neighbouring slice
-  WT* sg = sp + (long)b * NM;                // [b][NM] right-hand side of slice i
-  Box bx;
-  for (int a = 0; a < 3; ++a) {
-    bx.o[a] = td.o[a];
-    bx.m[a] = td.m[a];
-    bx.per[a] = 0;
-  }
-  bx.b = b;
-  bx.nch = nch;
-  const long mstride = (long)nch * b;  // one member's batch
-  if (!FWD && i == nch - 1) {
-    // x_{n-1} = t_{n-1}: rows of this workgroup
-    const int r = jb.r0 + (threadIdx.x & 63);
-    for (int m = threadIdx.x >> 6; m < jb.nm; m += kBlock / 64)
-      if (r < b) {
-        const long at = (long)(jb.m0 + m) * mstride + (long)i * b + r;
-        td.batch[at] = td.tbatch[at];
-      }
-    return;
-  }
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r >= b || (int)blockIdx.z >= jb.nm) return;
+  const long mstride = (long)nch * b;
+  const int m0 = td.m[0], m1 = td.m[1];
   const bool couple = FWD ? i > 0 : true;
   const int j = FWD ? i - 1 : i + 1;
   const double* nb = FWD ? td.tbatch : td.batch;
+  // the 9 taps with d2 = -1 (forward) or +1 (backward), in tap order
+  const int u1 = r / m0, u0 = r - u1 * m0;
+  const long tn = table_node(g, td.o[0] + u0, td.o[1] + u1, td.o[2] + i);
+  const int d2 = FWD ? -1 : 1;
+  double c[9];
+  int nbr[9];
+#pragma unroll
+  for (int t9 = 0; t9 < 9; ++t9) {
+    const int d0 = t9 % 3 - 1, d1 = t9 / 3 - 1;
+    const int w0 = u0 + d0, w1 = u1 + d1;
+    const bool in = couple && w0 >= 0 && w0 < m0 && w1 >= 0 && w1 < m1;
+    c[t9] = in ? T[(t9 + 9 * (d2 + 1)) * g.tsize + tn] : 0.0;
+    nbr[t9] = in ? w0 + m0 * w1 : r;
+  }
+  const int m = blockIdx.z;  // the member (grid z covers a job's members)
+  const long base = (long)(jb.m0 + m) * mstride;
+  double acc = FWD ? td.batch[base + (long)i * b + r] : 0.0;
   if (couple) {
-    for (int idx = threadIdx.x; idx < NM * b; idx += kBlock) {
-      const int m = idx / b, r = idx - m * b;
-      sp[r * NM + m] = m < jb.nm ? (WT)nb[(long)(jb.m0 + m) * mstride + (long)j * b + r] : (WT)0;
-    }
+    const double* nbs = nb + base + (long)j * b;
+#pragma unroll
+    for (int t9 = 0; t9 < 9; ++t9) acc += (FWD ? -c[t9] : c[t9]) * nbs[nbr[t9]];
+  }
+  G[(long)(jb.mg0 + m) * bmax + r] = (WT)acc;
+}
+
+template <typename WT>
+__global__ void __launch_bounds__(kBlock) k_chain_mm(const TypeDev* __restrict__ types,
+                                                     const ChainJob* __restrict__ jobs, int i,
+                                                     int mtot, int bmax,
+                                                     const WT* __restrict__ G,
+                                                     WT* __restrict__ part,
+                                                     const PcgState* __restrict__ st) {
+  using C = ChainCfg<WT>;
+  __shared__ __attribute__((aligned(16))) WT gs[C::KC][C::MG];
+  if (st != nullptr && st->done) return;
+  const ChainJob jb = jobs[blockIdx.z];
+  const TypeDev td = types[jb.type];
+  const int b = td.b;
+  const int r0 = blockIdx.x * C::RT, k0 = blockIdx.y * C::KC;
+  if (r0 >= b || k0 >= b) return;
+  const int kn = min(C::KC, b - k0);
+  // the chunk of the right-hand sides (row fastest: coalesced reads)
+  for (int idx = threadIdx.x; idx < kn * C::MG; idx += kBlock) {
+    const int m = idx / kn, k = idx - m * kn;
+    gs[k][m] = m < jb.nm ? G[(long)(jb.mg0 + m) * bmax + k0 + k] : (WT)0;
   }
   __syncthreads();
-  for (int r = threadIdx.x; r < b; r += kBlock) {
-    WT acc[NM];
-#pragma unroll
-    for (int m = 0; m < NM; ++m)
-      acc[m] = (FWD && m < jb.nm) ? (WT)td.batch[(long)(jb.m0 + m) * mstride + (long)i * b + r]
-                                  : (WT)0;
-    if (couple) {
-      // 3-D box, slices (u0, u1) with the chain along u2 = i: the 9 taps
-      // with d2 = -1 (forward) or +1 (backward), in tap order
-      const int m0 = bx.m[0], m1 = bx.m[1];
-      const int u1 = r / m0, u0 = r - u1 * m0;
-      const long tn = table_node(g, bx.o[0] + u0, bx.o[1] + u1, bx.o[2] + i);
-      const int d2 = FWD ? -1 : 1;
-#pragma unroll
-      for (int d1 = -1; d1 <= 1; ++d1)
-#pragma unroll
-        for (int d0 = -1; d0 <= 1; ++d0) {
-          const int w0 = u0 + d0, w1 = u1 + d1;
-          if (w0 < 0 || w0 >= m0 || w1 < 0 || w1 >= m1) continue;
-          const int t = (d0 + 1) + 3 * (d1 + 1) + 9 * (d2 + 1);
-          const WT c = (WT)T[t * g.tsize + tn];
-          const int rn = w0 + m0 * w1;
-#pragma unroll
-          for (int m = 0; m < NM; ++m) acc[m] += (FWD ? -c : c) * sp[rn * NM + m];
-        }
-    }
-#pragma unroll
-    for (int m = 0; m < NM; ++m) sg[r * NM + m] = acc[m];
-  }
-  __syncthreads();
-  // rows [r0, r0 + 64) of W_i g: lane = row, the 4 waves split the K range
-  // and load their W_i entries kChainBatch at a time ahead of the FMAs; the
-  // wave sums are added in wave order through LDS (reusing the slice buffer)
-  constexpr int NW = kBlock / 64, KB = 32;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int r = jb.r0 + lane;
-  const WT* Wi = (sizeof(WT) == 4 ? reinterpret_cast<const WT*>(td.W32)
-                                  : reinterpret_cast<const WT*>(td.W)) + (long)i * b * b;
-  const int kq = (b + NW - 1) / NW, k0 = wv * kq, k1 = min(b, k0 + kq);
-  WT acc[NM];
+  const int r = r0 + lane;
+  constexpr int MW = C::MG / (kBlock / 64);  // members per wave
+  WT acc[MW];
 #pragma unroll
-  for (int m = 0; m < NM; ++m) acc[m] = (WT)0;
-  if (r < b) {
-    for (int kc = k0; kc < k1; kc += KB) {
+  for (int q = 0; q < MW; ++q) acc[q] = (WT)0;
+  if (r < b && wv * MW < jb.nm) {
+    const WT* Wi = (sizeof(WT) == 4 ? reinterpret_cast<const WT*>(td.W32)
+                                    : reinterpret_cast<const WT*>(td.W)) +
+                   (long)i * b * b + (long)k0 * b + r;
+    constexpr int KB = 32;  // loads of W_i in flight per lane
+    for (int kk = 0; kk < kn; kk += KB) {
       WT w[KB];
 #pragma unroll
-      for (int q = 0; q < KB; ++q) w[q] = kc + q < k1 ? Wi[(long)(kc + q) * b + r] : (WT)0;
+      for (int q = 0; q < KB; ++q) w[q] = kk + q < kn ? Wi[(long)(kk + q) * b] : (WT)0;
 #pragma unroll
       for (int q = 0; q < KB; ++q) {
-        if (kc + q >= k1) break;
-        const WT* gk = sg + (kc + q) * NM;
+        // (past the chunk w[q] = 0 multiplies the chunk's last, written, row);
+        // the wave's MW values of the row are read 16 bytes at a time (every
+        // lane reads the same address: a broadcast)
+        typedef __attribute__((__vector_size__(16))) WT wvec;
+        constexpr int VW = 16 / sizeof(WT);
+        const wvec* gk = reinterpret_cast<const wvec*>(&gs[min(kk + q, kn - 1)][wv * MW]);
 #pragma unroll
-        for (int m = 0; m < NM; ++m) acc[m] += w[q] * gk[m];
+        for (int v4 = 0; v4 < MW / VW; ++v4) {
+          const wvec gv = gk[v4];
+#pragma unroll
+          for (int e = 0; e < VW; ++e) acc[v4 * VW + e] += w[q] * gv[e];
+        }
       }
     }
   }
-  __syncthreads();  // every wave is done with sp / sg
-  WT* red = sp;     // [NW][64][NM]
-#pragma unroll
-  for (int m = 0; m < NM; ++m) red[(wv * 64 + lane) * NM + m] = acc[m];
-  __syncthreads();
   if (r >= b) return;
-  for (int m = wv; m < jb.nm; m += NW) {
-    WT v = (WT)0;
 #pragma unroll
-    for (int q = 0; q < NW; ++q) v += red[(q * 64 + lane) * NM + m];
-    const long at = (long)(jb.m0 + m) * mstride + (long)i * b + r;
-    if (FWD) td.tbatch[at] = (double)v;
-    else td.batch[at] = td.tbatch[at] - (double)v;
+  for (int mm = 0; mm < MW; ++mm) {
+    const int m = wv * MW + mm;
+    if (m < jb.nm) part[((long)blockIdx.y * mtot + jb.mg0 + m) * bmax + r] = acc[mm];
   }
 }
 
-// members per workgroup: the two LDS slices (2 b NM WT) must fit in 160 KB
+// t_i = sum of the K-chunk partials (forward), x_i = t_i - sum (backward),
+// x_{n-1} = t_{n-1} (copy, the first backward step).
+template <typename WT, bool FWD>
+__global__ void __launch_bounds__(kBlock) k_chain_fin(const TypeDev* __restrict__ types,
+                                                      const ChainJob* __restrict__ jobs, int i,
+                                                      int mtot, int bmax,
+                                                      const WT* __restrict__ part, int copy,
+                                                      const PcgState* __restrict__ st) {
+  if (st != nullptr && st->done) return;
+  const ChainJob jb = jobs[blockIdx.y];
+  const TypeDev td = types[jb.type];
+  const int b = td.b;
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  const int m = blockIdx.z;  // the member (grid z covers a job's members)
+  if (r >= b || m >= jb.nm) return;
+  const int nkc = (b + ChainCfg<WT>::KC - 1) / ChainCfg<WT>::KC;
+  const long mstride = (long)td.nch * b;
+  const long at = (long)(jb.m0 + m) * mstride + (long)i * b + r;
+  if (copy) {
+    td.batch[at] = td.tbatch[at];
+    return;
+  }
+  double v = 0.0;
+  for (int kc = 0; kc < nkc; ++kc) v += (double)part[((long)kc * mtot + jb.mg0 + m) * bmax + r];
+  if (FWD) td.tbatch[at] = v;
+  else td.batch[at] = td.tbatch[at] - v;
+}
+
+// Members per group of the batched chain solves and the partial buffer size.
+int chain_group_members() { return ChainCfg<double>::MG; }
+
+size_t chain_part_bytes(int bmax, int mtot, int fp32) {
+  // the K-chunk partials, then the right-hand sides
+  const int kc = fp32 ? ChainCfg<float>::KC : ChainCfg<double>::KC;
+  return (size_t)((bmax + kc - 1) / kc + 1) * mtot * bmax * (fp32 ? sizeof(float) : sizeof(double));
+}
+
 template <typename WT>
-constexpr int chain_nm() {
-  return sizeof(WT) == 4 ? 16 : 8;
-}
-
-// LDS of a workgroup: the two slices [b][NM], which the wave sums
-// [4][64][NM] reuse at the end, so at least 256 NM values
-size_t chain_lds_bytes(int maxb, int fp32) {
-  const size_t rows = std::max<size_t>(2 * (size_t)maxb, (size_t)kBlock);
-  return rows * (fp32 ? 16 * sizeof(float) : 8 * sizeof(double));
-}
-
-void chain_kernel_setup(int fp32, size_t lds) {
-  if (fp32) {
-    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_chain_step<float, 16, true>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds), "lds");
-    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_chain_step<float, 16, false>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds), "lds");
-  } else {
-    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_chain_step<double, 8, true>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds), "lds");
-    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_chain_step<double, 8, false>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds), "lds");
+static void chain_sweeps(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
+  using C = ChainCfg<WT>;
+  const int nch = P->types[0].box.nch;
+  const int bmax = P->chain_bmax, mtot = P->chain_mtot;
+  const int nkc = (bmax + C::KC - 1) / C::KC;
+  WT* part = reinterpret_cast<WT*>(P->chain_part);
+  WT* G = part + (long)nkc * mtot * bmax;
+  const dim3 gmm((bmax + C::RT - 1) / C::RT, nkc, P->nchainjobs);
+  const dim3 gnode((bmax + kBlock - 1) / kBlock, P->nchainjobs, C::MG);
+  for (int i = 0; i < nch; ++i) {
+    hipLaunchKernelGGL((k_chain_rhs<WT, true>), gnode, dim3(kBlock), 0, s, P->g, P->tabAs,
+                       P->dTypes, P->dChainJobs, i, bmax, G, st);
+    hipLaunchKernelGGL((k_chain_mm<WT>), gmm, dim3(kBlock), 0, s, P->dTypes, P->dChainJobs, i,
+                       mtot, bmax, G, part, st);
+    hipLaunchKernelGGL((k_chain_fin<WT, true>), gnode, dim3(kBlock), 0, s, P->dTypes,
+                       P->dChainJobs, i, mtot, bmax, part, 0, st);
+  }
+  hipLaunchKernelGGL((k_chain_fin<WT, false>), gnode, dim3(kBlock), 0, s, P->dTypes,
+                     P->dChainJobs, nch - 1, mtot, bmax, part, 1, st);
+  for (int i = nch - 2; i >= 0; --i) {
+    hipLaunchKernelGGL((k_chain_rhs<WT, false>), gnode, dim3(kBlock), 0, s, P->g, P->tabAs,
+                       P->dTypes, P->dChainJobs, i, bmax, G, st);
+    hipLaunchKernelGGL((k_chain_mm<WT>), gmm, dim3(kBlock), 0, s, P->dTypes, P->dChainJobs, i,
+                       mtot, bmax, G, part, st);
+    hipLaunchKernelGGL((k_chain_fin<WT, false>), gnode, dim3(kBlock), 0, s, P->dTypes,
+                       P->dChainJobs, i, mtot, bmax, part, 0, st);
   }
 }
 
 void launch_chain_batched(const ddeig_problem* P, const PcgState* st, hipStream_t s) {
-  const int nch = P->types[0].box.nch;
-  const dim3 grid(P->nchainjobs), blk(kBlock);
-  for (int i = 0; i < nch; ++i) {
-    if (P->opt.local_prec == 1)
-      hipLaunchKernelGGL((k_chain_step<float, 16, true>), grid, blk, P->chain_lds, s, P->g,
-                         P->tabAs, P->dTypes, P->dChainJobs, i, st);
-    else
-      hipLaunchKernelGGL((k_chain_step<double, 8, true>), grid, blk, P->chain_lds, s, P->g,
-                         P->tabAs, P->dTypes, P->dChainJobs, i, st);
-  }
-  for (int i = nch - 1; i >= 0; --i) {
-    if (P->opt.local_prec == 1)
-      hipLaunchKernelGGL((k_chain_step<float, 16, false>), grid, blk, P->chain_lds, s, P->g,
-                         P->tabAs, P->dTypes, P->dChainJobs, i, st);
-    else
-      hipLaunchKernelGGL((k_chain_step<double, 8, false>), grid, blk, P->chain_lds, s, P->g,
-                         P->tabAs, P->dTypes, P->dChainJobs, i, st);
-  }
+  if (P->opt.local_prec == 1) chain_sweeps<float>(P, st, s);
+  else chain_sweeps<double>(P, st, s);
 }
 
 bool local_solves_fast_ok(const ddeig_problem* P);
