@@ -961,6 +961,9 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
           if (nT > ddeig::kEmbMaxT)
             throw Failure{DDEIG_EINVAL, "dense local solves: a clipped subdomain misses more than 1024 "
                                         "nodes of the unclipped box; use local_prec 0 or 1"};
+          if ((long)nT * H.m >= (1L << 31))
+            throw Failure{DDEIG_EINVAL, "dense local solves: a clipped-class correction matrix "
+                                        "has 2^31 entries or more; use local_prec 0 or 1"};
           std::vector<int> tl;
           for (int u2 = 0; u2 < hb.m[2]; ++u2)
             for (int u1 = 0; u1 < hb.m[1]; ++u1)
@@ -1005,8 +1008,9 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
           const int ci = (int)P->emb.size();
           P->emb.push_back(E);
           P->maxT = std::max(P->maxT, nT);
-          for (int m0 = 0; m0 < T.nmem; m0 += ddeig::kEmbChunk)
-            embjobs.push_back(ddeig::EmbedJob{ci, m0, std::min(ddeig::kEmbChunk, T.nmem - m0)});
+          const int per = ddeig::emb_members_per_job(nT);
+          for (int m0 = 0; m0 < T.nmem; m0 += per)
+            embjobs.push_back(ddeig::EmbedJob{ci, m0, std::min(per, T.nmem - m0)});
         }
       }
       // GEMM over all rows (or the streaming kernel for a handful of rows);
@@ -1157,6 +1161,9 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
       P->dGtypes = dalloc<ddeig::GemmType>(P, 1);
       check_hip(hipMemcpyAsync(P->dGtypes, &gt, sizeof(ddeig::GemmType), hipMemcpyHostToDevice, s),
                 "copy gemm operands");
+      if (embjobs.size() > (size_t)ddeig::kEmbMaxJobs)
+        throw Failure{DDEIG_EINVAL, "dense local solves: more than 65535 clipped-subdomain "
+                                    "correction jobs; use local_prec 0 or 1"};
       P->nembjobs = (int)embjobs.size();
       if (!P->emb.empty()) {
         P->dEmb = dalloc<ddeig::EmbedDev>(P, P->emb.size());
@@ -2186,9 +2193,13 @@ ddeig_status ddeig_batch_create(ddeig_problem* const* probs, int n, int flags, d
         E.st = B->P[j]->st;
         const int ci2 = (int)emb.size();
         emb.push_back(E);
-        for (int m0 = 0; m0 < E.nmem; m0 += ddeig::kEmbChunk)
-          jobs.push_back(ddeig::EmbedJob{ci2, m0, std::min(ddeig::kEmbChunk, E.nmem - m0)});
+        const int per = ddeig::emb_members_per_job(E.nT);
+        for (int m0 = 0; m0 < E.nmem; m0 += per)
+          jobs.push_back(ddeig::EmbedJob{ci2, m0, std::min(per, E.nmem - m0)});
       }
+    if (jobs.size() > (size_t)ddeig::kEmbMaxJobs)
+      throw Failure{DDEIG_EINVAL, "batch: more than 65535 clipped-subdomain correction jobs; "
+                                  "use fewer instances"};
     B->nembjobs = (int)jobs.size();
     if (!emb.empty()) {
       B->dEmb = bupload(B, emb);

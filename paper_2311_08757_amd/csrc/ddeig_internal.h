@@ -151,8 +151,16 @@ struct DenseArgs {
 struct EmbedJob {
   int cls, mem0, nm;
 };
-constexpr int kEmbChunk = 8;    // members per correction block
+constexpr int kEmbChunk = 8;    // most members per correction block
 constexpr int kEmbMaxT = 1024;  // largest T
+constexpr int kEmbUT = 8192;    // u_T values per correction block (members x T)
+constexpr int kEmbMaxJobs = 65535;  // correction jobs per launch (grid y)
+// Members per correction job of a class with nT missing nodes: as many as the
+// block's u_T buffer holds (8 at the largest T), at most kEmbChunk.
+inline int emb_members_per_job(int nT) {
+  const int fit = nT > 0 ? kEmbUT / nT : kEmbChunk;
+  return fit < kEmbChunk ? fit : kEmbChunk;
+}
 
 // Per-subdomain data on the device.
 struct SubDev {

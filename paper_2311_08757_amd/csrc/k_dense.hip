@@ -378,36 +378,78 @@ void launch_embed_gmat(const ddeig_problem* P, const EmbedDev& E, const double* 
                      H.box.m[0], H.box.m[1], H.m, C, G);
 }
 
-// Per application: y_S = u_S - G u_T for up to kEmbChunk members of a class,
-// u = B~ [r_S; 0] the GEMM result (split-K partials added in split order).
-// The corrected solution replaces split 0 of Z and the other splits are
-// cleared, so the extension reads clipped and unclipped members alike.
-// Block (job, 32 unknowns of the unclipped box): thread (unknown, phase) adds
-// the terms t = phase mod 8 in batches of kEmbG; the 8 phase sums are added
-// in phase order.  The loads that do not depend on u_T (the first batch of the
-// thread's column of G, its own Z entries) are issued before u_T is gathered.
-// Nodes in T are left alone (no member reads them).
-constexpr int kEmbPh = 8, kEmbE = kBlock / kEmbPh, kEmbG = 32;  // G loads per batch
+// Per application: y_S = u_S - G u_T for the members of one job of a class
+// (at most kEmbChunk), u = B~ [r_S; 0] the GEMM result (split-K partials added
+// in split order).  The corrected solution replaces split 0 of Z and the other
+// splits are cleared, so the extension reads clipped and unclipped members
+// alike.
+// Block (64 unknowns of the unclipped box, job): thread (unknown, phase) adds
+// the terms t = phase mod 4 in batches of kEmbG for every member (a wave reads
+// 256 contiguous bytes of a row of G per load); the 4 phase sums of a member
+// are added in phase order by the thread of phase m mod 4.
+// u_T sits in LDS with the members of one t next to each other (two 16-byte
+// reads per term).  The first batch of the thread's column of G and its
+// members' own Z entries are loaded before u_T is gathered (kEmbGU values per
+// thread in flight), and each later batch of G is loaded while the previous
+// one is used.  Nodes in T are left alone (no member reads them).
+constexpr int kEmbPh = 4, kEmbE = kBlock / kEmbPh, kEmbG = 32;  // G loads per batch
+constexpr int kEmbGU = 8;                                         // gather depth
+constexpr int kEmbOwn = kEmbChunk / kEmbPh;                        // members finished per thread
+static_assert(kEmbChunk % kEmbPh == 0, "members are finished round-robin over the phases");
+static_assert(kEmbChunk == 8 && kEmbUT == kEmbMaxT * kEmbChunk,
+              "u_T rows are two float4 of members, for every t < kEmbMaxT");
 
-// Rows blockIdx.y >= ceil(mH / kEmbE) of the grid apply the coarse inverse
-// (column 0 only: rows 4 (blockIdx.y - ychunks) .. + 3 of y0 = A_0^{-1} c),
+// The terms of one thread for NM members: gv holds the first batch of G on
+// entry (G[g0 + q gs], q < nq, is the thread's column; nT mH < 2^31 is checked
+// at set-up); each register is refilled with its term of the next batch as
+// soon as it has been used.
+template <int NM>
+__device__ __forceinline__ void embed_accumulate(const float* __restrict__ G, unsigned g0,
+                                                 unsigned gs, int nq,
+                                                 const float* __restrict__ uT, int ph,
+                                                 float (&gv)[kEmbG], float (&acc)[kEmbChunk]) {
+  for (int q0 = 0; q0 < nq; q0 += kEmbG) {
+#pragma unroll
+    for (int q = 0; q < kEmbG; ++q) {
+      const float g = gv[q];
+      if (q0 + kEmbG + q < nq) gv[q] = G[g0 + (unsigned)(q0 + kEmbG + q) * gs];
+      if (q0 + q < nq) {
+        const float4* u4 =
+            reinterpret_cast<const float4*>(uT + (ph + kEmbPh * (q0 + q)) * kEmbChunk);
+        const float4 a = u4[0];
+        float u[kEmbChunk] = {a.x, a.y, a.z, a.w, 0.0f, 0.0f, 0.0f, 0.0f};
+        if constexpr (NM > 4) {
+          const float4 b = u4[1];
+          u[4] = b.x; u[5] = b.y; u[6] = b.z; u[7] = b.w;
+        }
+#pragma unroll
+        for (int m = 0; m < NM; ++m) acc[m] += g * u[m];
+      }
+    }
+  }
+}
+
+// Grid (row chunk, job): the chunks of one job are consecutive in dispatch
+// order, so the blocks that run together read neighbouring pieces of the same
+// rows of G.  Chunks blockIdx.x >= ceil(mH / kEmbE) of job 0 apply the coarse
+// inverse instead (rows 4 (blockIdx.x - ychunks) .. + 3 of y0 = A_0^{-1} c),
 // independent of the correction workgroups.
 template <int KS>
-__global__ void __launch_bounds__(kBlock) k_embed_correct(const EmbedJob* __restrict__ jobs,
-                                                          const EmbedDev* __restrict__ cls,
-                                                          int ld, int hm0, int hm1, int mH,
-                                                          const PcgState* __restrict__ st,
-                                                          CoarseSolveArgs cs) {
-  __shared__ float uT[kEmbChunk * kEmbMaxT];
+// At most 128 VGPRs (4 waves per SIMD, as many as the LDS allows): with more
+// the compiler hoists LDS reads and the kernel runs at 3 waves, markedly slower.
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+k_embed_correct(const EmbedJob* __restrict__ jobs, const EmbedDev* __restrict__ cls, int ld,
+                int hm0, int hm1, int mH, const PcgState* __restrict__ st, CoarseSolveArgs cs) {
+  __shared__ __align__(16) float uT[kEmbUT];  // uT[t kEmbChunk + m] = u_T of member m
   __shared__ float red[kEmbPh][kEmbE][kEmbChunk];
   const int ychunks = (mH + kEmbE - 1) / kEmbE;
-  if ((int)blockIdx.y >= ychunks) {
-    if (blockIdx.x == 0) coarse_solve_body(cs.n, st, cs.A0inv, cs.c, cs.y, blockIdx.y - ychunks);
+  if ((int)blockIdx.x >= ychunks) {
+    if (blockIdx.y == 0) coarse_solve_body(cs.n, st, cs.A0inv, cs.c, cs.y, blockIdx.x - ychunks);
     return;
   }
   // the job, the state and the class are loaded before the state is tested,
   // so that their latencies overlap
-  const EmbedJob jb = jobs[blockIdx.x];
+  const EmbedJob jb = jobs[blockIdx.y];
   const int done0 = st != nullptr ? st->done : 0;
   const EmbedDev E = cls[jb.cls];
   if (done0) return;
@@ -415,74 +457,87 @@ __global__ void __launch_bounds__(kBlock) k_embed_correct(const EmbedJob* __rest
   float* __restrict__ Z = E.Z;
   const long zsplit = E.zsplit;
   const int el = threadIdx.x % kEmbE, ph = threadIdx.x / kEmbE;
-  const int e = blockIdx.y * kEmbE + el;
+  const int e = blockIdx.x * kEmbE + el;
   const bool inS = e < mH && embed_in_box(E, e, hm0, hm1);
   const int nq = (E.nT - ph + kEmbPh - 1) / kEmbPh;  // terms t = ph + kEmbPh q, q < nq
+  const float* __restrict__ G = E.G;
+  const unsigned g0 = (unsigned)(ph * mH + e), gs = (unsigned)(kEmbPh * mH);  // G[g0 + q gs]
   float gv[kEmbG];
-  float zown[kEmbChunk][KS];
-  auto load_batch = [&](int q0) {
+  float zown[kEmbOwn][KS];
+  if (inS) {
 #pragma unroll
     for (int q = 0; q < kEmbG; ++q)
-      if (q0 + q < nq) gv[q] = E.G[(long)(ph + kEmbPh * (q0 + q)) * mH + e];
-  };
-  if (inS) {
-    load_batch(0);
-    if (ph == 0) {
+      if (q < nq) gv[q] = G[g0 + (unsigned)q * gs];
 #pragma unroll
-      for (int m = 0; m < kEmbChunk; ++m)
-        if (m < jb.nm) {
-          const long base = (long)E.rows[jb.mem0 + m] * ld + e;
+    for (int k = 0; k < kEmbOwn; ++k) {
+      const int m = ph + kEmbPh * k;
+      if (m < jb.nm) {
+        const long base = (long)E.rows[jb.mem0 + m] * ld + e;
 #pragma unroll
-          for (int sp = 0; sp < KS; ++sp) zown[m][sp] = Z[sp * zsplit + base];
-        }
+        for (int sp = 0; sp < KS; ++sp) zown[k][sp] = Z[sp * zsplit + base];
+      }
     }
   }
   const int nmiss = hm0 - E.m[0];
-  for (int idx = threadIdx.x; idx < jb.nm * E.nT; idx += kBlock) {
-    const int m = idx / E.nT, t = idx - m * E.nT;
-    int te;
-    if (E.xonly) {
-      const int line = t / nmiss, j = t - line * nmiss;
-      te = (j < E.off[0] ? j : j + E.m[0]) + hm0 * line;
-    } else {
-      te = E.Tidx[t];
-    }
-    const long base = (long)E.rows[jb.mem0 + m] * ld + te;
-    float u = 0.0f;
+  const int tot = jb.nm * E.nT;  // gather index m nT + t
+  for (int i0 = 0; i0 < tot; i0 += kBlock * kEmbGU) {
+    float v[kEmbGU];
 #pragma unroll
-    for (int sp = 0; sp < KS; ++sp) u += Z[sp * zsplit + base];
-    uT[m * E.nT + t] = u;
+    for (int g = 0; g < kEmbGU; ++g) {
+      const int idx = i0 + g * kBlock + threadIdx.x;
+      v[g] = 0.0f;
+      if (idx < tot) {
+        const int m = idx / E.nT, t = idx - m * E.nT;
+        int te;
+        if (E.xonly) {
+          const int line = t / nmiss, j = t - line * nmiss;
+          te = (j < E.off[0] ? j : j + E.m[0]) + hm0 * line;
+        } else {
+          te = E.Tidx[t];
+        }
+        const long base = (long)E.rows[jb.mem0 + m] * ld + te;
+#pragma unroll
+        for (int sp = 0; sp < KS; ++sp) v[g] += Z[sp * zsplit + base];
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < kEmbGU; ++g) {
+      const int idx = i0 + g * kBlock + threadIdx.x;
+      if (idx < tot) {
+        const int m = idx / E.nT;
+        uT[(idx - m * E.nT) * kEmbChunk + m] = v[g];
+      }
+    }
   }
   __syncthreads();
   float acc[kEmbChunk];
 #pragma unroll
   for (int m = 0; m < kEmbChunk; ++m) acc[m] = 0.0f;
   if (inS) {
-    for (int q0 = 0; q0 < nq; q0 += kEmbG) {
-      if (q0 > 0) load_batch(q0);
-#pragma unroll
-      for (int q = 0; q < kEmbG; ++q) {
-        if (q0 + q < nq) {
-          const int t = ph + kEmbPh * (q0 + q);
-#pragma unroll
-          for (int m = 0; m < kEmbChunk; ++m)
-            if (m < jb.nm) acc[m] += gv[q] * uT[m * E.nT + t];
-        }
-      }
+    switch (jb.nm) {  // 1 <= nm <= kEmbChunk by construction of the jobs
+      case 1: embed_accumulate<1>(G, g0, gs, nq, uT, ph, gv, acc); break;
+      case 2: embed_accumulate<2>(G, g0, gs, nq, uT, ph, gv, acc); break;
+      case 3: embed_accumulate<3>(G, g0, gs, nq, uT, ph, gv, acc); break;
+      case 4: embed_accumulate<4>(G, g0, gs, nq, uT, ph, gv, acc); break;
+      case 5: embed_accumulate<5>(G, g0, gs, nq, uT, ph, gv, acc); break;
+      case 6: embed_accumulate<6>(G, g0, gs, nq, uT, ph, gv, acc); break;
+      case 7: embed_accumulate<7>(G, g0, gs, nq, uT, ph, gv, acc); break;
+      default: embed_accumulate<8>(G, g0, gs, nq, uT, ph, gv, acc); break;
     }
   }
 #pragma unroll
   for (int m = 0; m < kEmbChunk; ++m) red[ph][el][m] = acc[m];
   __syncthreads();
-  if (ph != 0 || !inS) return;
+  if (!inS) return;
 #pragma unroll
-  for (int m = 0; m < kEmbChunk; ++m) {
+  for (int k = 0; k < kEmbOwn; ++k) {
+    const int m = ph + kEmbPh * k;
     if (m >= jb.nm) break;
     float corr = 0.0f;
     for (int q = 0; q < kEmbPh; ++q) corr += red[q][el][m];
     float u = 0.0f;
 #pragma unroll
-    for (int sp = 0; sp < KS; ++sp) u += zown[m][sp];
+    for (int sp = 0; sp < KS; ++sp) u += zown[k][sp];
     const long base = (long)E.rows[jb.mem0 + m] * ld + e;
     Z[base] = u - corr;
 #pragma unroll
@@ -505,7 +560,7 @@ void launch_embed_fix(const ddeig_problem* P, const PcgState* st, hipStream_t s,
     cs = CoarseSolveArgs{P->nsub, P->A0inv, P->crhs, P->cy};
     extra = (P->nsub + kBlock / 64 - 1) / (kBlock / 64);
   }
-  hipLaunchKernelGGL(kern, dim3(P->nembjobs, (H.m + kEmbE - 1) / kEmbE + extra), dim3(kBlock), 0,
+  hipLaunchKernelGGL(kern, dim3((H.m + kEmbE - 1) / kEmbE + extra, P->nembjobs), dim3(kBlock), 0,
                      s, P->dEmbJobs, P->dEmb, H.ld, H.box.m[0], H.box.m[1], H.m, st, cs);
 }
 
@@ -558,7 +613,7 @@ void launch_embed_jobs(const EmbedJob* jobs, int njobs, const EmbedDev* cls, int
   auto kern = ksplit == 1 ? k_embed_correct<1> : (ksplit == 2 ? k_embed_correct<2>
                                                                : k_embed_correct<3>);
   const CoarseSolveArgs none{0, nullptr, nullptr, nullptr};
-  hipLaunchKernelGGL(kern, dim3(njobs, (mH + kEmbE - 1) / kEmbE), dim3(kBlock), 0, s, jobs, cls,
+  hipLaunchKernelGGL(kern, dim3((mH + kEmbE - 1) / kEmbE, njobs), dim3(kBlock), 0, s, jobs, cls,
                      ld, hm0, hm1, mH, nullptr, none);
 }
 
