@@ -176,7 +176,7 @@ struct TileShape<2> {
 };
 template <>
 struct TileShape<3> {
-  static constexpr int TX = 64, TY = 4, TZ = 4;
+  static constexpr int TX = 256, TY = 1, TZ = 4;
 };
 
 template <int D, int MODE>
@@ -274,6 +274,129 @@ __global__ void __launch_bounds__(kBlock) k_stencil(Geo g, const double* __restr
         acc += sv[cx + HX * ((ty + 1) + HY * (D == 3 ? tz + 1 : 0))] * a;
         accs += a;
       }
+    }
+  }
+  if (use_dot) write_partial(acc, dot.part);
+  if (use_sum) write_partial(accs, sum.part);
+}
+
+// Workgroup b runs on XCD b mod 8 (round-robin dispatch): XCD k takes the
+// k-th contiguous eighth of the n tiles, so that neighbouring tiles, which
+// read each other's nodes as halo, share one L2.
+__device__ __forceinline__ int xcd_slab(int b, int n) {
+  const int per = n / 8, rem = n % 8, k = b % 8, i = b / 8;
+  return (k < rem ? k * (per + 1) : rem * (per + 1) + (k - rem) * per) + i;
+}
+
+// The 3-D sweep with one 256 x 1 x 4 tile per workgroup: wave w takes the row
+// z = z0 + w, lane l its nodes x0 + l + 64 s (s < 4).  When n_e divides 64 the
+// four nodes of a lane share one cell-local position, so the 27 table
+// coefficients are loaded once for four nodes: the table, not the vector, is
+// what the 3-D sweep reads most.  Tiles are numbered with z fastest, then x,
+// then y, and handed out by xcd_slab, so an XCD holds a slab of whole x-z
+// planes of tiles and most halo reads hit its L2.  The halo staging is
+// unrolled in rounds of 8 entries per thread, all loads of a round in flight
+// together.  Arithmetic and tap order per node are those of k_stencil<3, MODE>;
+// the block partials are stored by workgroup.
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_stencil3d(Geo g, const double* __restrict__ T,
+                                                      const double* __restrict__ x,
+                                                      const double* __restrict__ pold,
+                                                      double* __restrict__ pnew,
+                                                      double* __restrict__ y, DirArgs dir,
+                                                      int use_dot, Red dot, int use_sum, Red sum) {
+  constexpr int TX = TileShape<3>::TX, TY = TileShape<3>::TY, TZ = TileShape<3>::TZ;
+  constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2, NH = HX * HY * HZ;
+  constexpr int RX = TX / 64, NR = TY * TZ / (kBlock / 64);  // strides per lane, rows per wave
+  constexpr int NS = (NH + kBlock - 1) / kBlock, SB = 8;    // staged entries per thread, per round
+  static_assert(TX % 64 == 0 && (TY * TZ) % (kBlock / 64) == 0, "rows of whole waves");
+  __shared__ double sv[NH];
+  double beta = 0.0;
+  if constexpr (MODE == 1) {
+    const double rho = sum_partials(dir.rz.part, dir.rz.np);
+    if (dir.st->done) return;
+    if (!(rho > 0.0)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        dir.st->done = 3;
+        dir.st->iters = dir.k - 1;
+      }
+      return;
+    }
+    if (dir.k > 1) beta = rho / dir.st->rho[(dir.k - 2) & 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) dir.st->rho[(dir.k - 1) & 1] = rho;
+  }
+  const int N0 = g.N[0], N1 = g.N[1], N2 = g.N[2];
+  const long N01 = (long)N0 * N1;
+  const int nbx = (N0 + TX - 1) / TX, nby = (N1 + TY - 1) / TY, nbz = (N2 + TZ - 1) / TZ;
+  const int tile = xcd_slab(blockIdx.x, nbx * nby * nbz);
+  const int bz = tile % nbz, rest = tile / nbz;
+  const int x0 = (rest % nbx) * TX, y0 = (rest / nbx) * TY, z0 = bz * TZ;
+  const long tsize = g.tsize;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int s0 = 0; s0 < NS; s0 += SB) {
+    double v[SB], vo[SB];
+    long kk[SB];
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+      const int e = threadIdx.x + kBlock * (s0 + u);
+      const int ex = e % HX, er = e / HX, ey = er % HY, ez = er / HY;
+      const int gx = x0 - 1 + ex, gy = y0 - 1 + ey, gz = z0 - 1 + ez;
+      const bool in = e < NH && gx >= 0 && gx < N0 && gy >= 0 && gy < N1 && gz >= 0 && gz < N2;
+      kk[u] = in ? gx + (long)N0 * gy + N01 * gz : -1;
+      v[u] = in ? x[kk[u]] : 0.0;
+      if constexpr (MODE == 1) vo[u] = (in && dir.k > 1) ? pold[kk[u]] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+      const int e = threadIdx.x + kBlock * (s0 + u);
+      if (e >= NH) continue;
+      double val = v[u];
+      if constexpr (MODE == 1) {
+        if (kk[u] >= 0) {
+          if (dir.k > 1) val += beta * vo[u];
+          const int ex = e % HX, er = e / HX, ey = er % HY, ez = er / HY;
+          if (ex >= 1 && ex <= TX && ey >= 1 && ey <= TY && ez >= 1 && ez <= TZ)
+            pnew[kk[u]] = val;
+        }
+      }
+      sv[e] = val;
+    }
+  }
+  __syncthreads();
+  double acc = 0.0, accs = 0.0;
+#pragma unroll
+  for (int jr = 0; jr < NR; ++jr) {
+    const int row = w + (kBlock / 64) * jr;
+    const int ty = row % TY, tz = row / TY;
+    const int gy = y0 + ty, gz = z0 + tz;
+    if (gy >= N1 || gz >= N2) continue;
+    const int j1 = g.isx[1] ? (int)((unsigned)(gy + 1) - g.ne * fdiv((unsigned)(gy + 1), g.fne)) : gy;
+    const int j2 = g.isx[2] ? (int)((unsigned)(gz + 1) - g.ne * fdiv((unsigned)(gz + 1), g.fne)) : gz;
+    const long trow = (long)g.P[0] * (j1 + (long)g.P[1] * j2);
+    double c[27];
+    long tn_prev = -1;
+#pragma unroll
+    for (int s = 0; s < RX; ++s) {
+      const int gx = x0 + lane + 64 * s;
+      if (gx >= N0) continue;
+      const int j0 = (int)((unsigned)(gx + 1) - g.ne * fdiv((unsigned)(gx + 1), g.fne));
+      const long tn = j0 + trow;
+      if (tn != tn_prev) {
+#pragma unroll
+        for (int t = 0; t < 27; ++t) c[t] = T[t * tsize + tn];
+        tn_prev = tn;
+      }
+      const int cx = lane + 64 * s + 1;
+      double a = 0.0;
+#pragma unroll
+      for (int t = 0; t < 27; ++t) {
+        const int d0 = t % 3 - 1, d1 = (t / 3) % 3 - 1, d2 = t / 9 - 1;
+        a += c[t] * sv[(cx + d0) + HX * ((ty + 1 + d1) + HY * (tz + 1 + d2))];
+      }
+      y[gx + (long)N0 * gy + N01 * gz] = a;
+      acc += sv[cx + HX * ((ty + 1) + HY * (tz + 1))] * a;
+      accs += a;
     }
   }
   if (use_dot) write_partial(acc, dot.part);
@@ -472,8 +595,8 @@ void launch_stencil(const ddeig_problem* P, const double* tab, const double* x, 
     hipLaunchKernelGGL((k_stencil<2, 0>), dim3(blocks), dim3(kBlock), 0, s, P->g, tab, x,
                        nullptr, nullptr, y, nodir, dot ? 1 : 0, td.use, sum ? 1 : 0, ts.use);
   else
-    hipLaunchKernelGGL((k_stencil<3, 0>), dim3(blocks), dim3(kBlock), 0, s, P->g, tab, x,
-                       nullptr, nullptr, y, nodir, dot ? 1 : 0, td.use, sum ? 1 : 0, ts.use);
+    hipLaunchKernelGGL((k_stencil3d<0>), dim3(blocks), dim3(kBlock), 0, s, P->g, tab, x, nullptr,
+                       nullptr, y, nodir, dot ? 1 : 0, td.use, sum ? 1 : 0, ts.use);
   if (dot) {
     finish_tile_red(P, td, s);
     *dot = td.final;
@@ -499,7 +622,7 @@ void launch_stencil_dir(const ddeig_problem* P, const double* z, const double* p
     hipLaunchKernelGGL((k_stencil<2, 1>), dim3(blocks), dim3(kBlock), 0, s, P->g, P->tabAs, z,
                        pold, pnew, q, dir, 1, tg.use, 0, none);
   else
-    hipLaunchKernelGGL((k_stencil<3, 1>), dim3(blocks), dim3(kBlock), 0, s, P->g, P->tabAs, z,
+    hipLaunchKernelGGL((k_stencil3d<1>), dim3(blocks), dim3(kBlock), 0, s, P->g, P->tabAs, z,
                        pold, pnew, q, dir, 1, tg.use, 0, none);
   finish_tile_red(P, tg, s);
   gam = tg.final;
