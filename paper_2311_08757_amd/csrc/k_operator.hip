@@ -450,20 +450,39 @@ __device__ __forceinline__ void stencil2d_body(const Geo& g, const double* __res
 #pragma unroll
     for (int t = 0; t < 9; ++t) c[j][t] = tp[t * tsize];
   }
-  const double* xb = x + (long)N0 * y0 + x0;
-  for (int e = threadIdx.x; e < HX * HY; e += kBlock) {
-    const int ex = e % HX, ey = e / HX;
-    const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
-    double v = 0.0;
-    if (gx >= 0 && gx < N0 && gy >= 0 && gy < N1) {
-      const long off = (long)N0 * (ey - 1) + (ex - 1);
-      v = xb[off];
-      if constexpr (MODE == 1) {
-        if (dir.k > 1) v += beta * pold[(long)N0 * y0 + x0 + off];
-        if (ex >= 1 && ex <= TX && ey >= 1 && ey <= TY) pnew[(long)N0 * y0 + x0 + off] = v;
-      }
+  // the halo staging, unrolled in rounds of SB entries per thread so that all
+  // loads of a round are in flight together
+  constexpr int NH = HX * HY, NS = (NH + kBlock - 1) / kBlock, SB = 8;
+  const long base = (long)N0 * y0 + x0;
+#pragma unroll
+  for (int s0 = 0; s0 < NS; s0 += SB) {
+    double v[SB], vo[SB];
+    long off[SB];
+    bool in[SB];
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+      const int e = threadIdx.x + kBlock * (s0 + u);
+      const int ex = e % HX, ey = e / HX;
+      const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+      in[u] = e < NH && gx >= 0 && gx < N0 && gy >= 0 && gy < N1;
+      off[u] = (long)N0 * (ey - 1) + (ex - 1);
+      v[u] = in[u] ? x[base + off[u]] : 0.0;
+      if constexpr (MODE == 1) vo[u] = (in[u] && dir.k > 1) ? pold[base + off[u]] : 0.0;
     }
-    sv[e] = v;
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+      const int e = threadIdx.x + kBlock * (s0 + u);
+      if (e >= NH) continue;
+      double val = v[u];
+      if constexpr (MODE == 1) {
+        if (in[u]) {
+          if (dir.k > 1) val += beta * vo[u];
+          const int ex = e % HX, ey = e / HX;
+          if (ex >= 1 && ex <= TX && ey >= 1 && ey <= TY) pnew[base + off[u]] = val;
+        }
+      }
+      sv[e] = val;
+    }
   }
   __syncthreads();
   double acc = 0.0, accs = 0.0;
