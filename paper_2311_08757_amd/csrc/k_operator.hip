@@ -394,7 +394,8 @@ __global__ void __launch_bounds__(kBlock) k_stencil3d(Geo g, const double* __res
         const int d0 = t % 3 - 1, d1 = (t / 3) % 3 - 1, d2 = t / 9 - 1;
         a += c[t] * sv[(cx + d0) + HX * ((ty + 1 + d1) + HY * (tz + 1 + d2))];
       }
-      y[gx + (long)N0 * gy + N01 * gz] = a;
+      if constexpr (MODE == 0) __builtin_nontemporal_store(a, &y[gx + (long)N0 * gy + N01 * gz]);
+      else y[gx + (long)N0 * gy + N01 * gz] = a;
       acc += sv[cx + HX * ((ty + 1) + HY * (tz + 1))] * a;
       accs += a;
     }
@@ -498,7 +499,10 @@ __device__ __forceinline__ void stencil2d_body(const Geo& g, const double* __res
       double a = 0.0;
 #pragma unroll
       for (int t = 0; t < 9; ++t) a += c[j][t] * sv[(cx + t % 3 - 1) + HX * (ty + t / 3)];
-      y[gx + (long)N0 * gy] = a;
+      // the plain sweep's result is not read again by the sweep: streamed past
+      // the caches (non-temporal), which helps when the vectors exceed them
+      if constexpr (MODE == 0) __builtin_nontemporal_store(a, &y[gx + (long)N0 * gy]);
+      else y[gx + (long)N0 * gy] = a;
       acc += sv[cx + HX * (ty + 1)] * a;
       accs += a;
     }
