@@ -23,6 +23,7 @@ CASES = [
     (1, 2, 3, 4, 1, W.sep_fourier(3000)),
     (2, 1, 3, 4, 1, W.fourier2(4000)),
     (2, 1, 2, 6, 2, W.sep_sum_43()),
+    (1, 2, 60, 6, 1, W.sep_fourier(5)),   # 3-D, two x tiles of 256, n_e not dividing 64
 ]
 IDS = [f"p{c[0]}q{c[1]}-L{c[2]}-ne{c[3]}-d{c[4]}-{c[5]['kind']}" for c in CASES]
 
