@@ -187,8 +187,11 @@ def test_errors(torch):
     assert out["status"] == "ENOCONV" and out["iters"] == 3
 
 
-PREC_CASES = [CASES[0], CASES[1], CASES[4], CASES[5]]
-PREC_IDS = [IDS[0], IDS[1], IDS[4], IDS[5]]
+PREC_CASES = [CASES[0], CASES[1], CASES[4], CASES[5],
+              # two expanding axes, L = 11: edge classes of 9 clipped members, whose
+              # corrections run as jobs of 8 and 1 members
+              (2, 1, 11, 4, 1, W.fourier2(4000))]
+PREC_IDS = [IDS[0], IDS[1], IDS[4], IDS[5], "p2q1-L11-ne4-d1-fourier2"]
 
 
 @pytest.mark.parametrize("case", PREC_CASES, ids=PREC_IDS)
