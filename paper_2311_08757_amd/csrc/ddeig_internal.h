@@ -474,6 +474,7 @@ void build_coarse_matrix(ddeig_problem* P, double* A0, hipStream_t s);
 
 // grouped launches over the instances of a batch (one PCG iteration k)
 int node_grid(const Geo& g);
+int node_grid_dense(const Geo& g);
 int coarse_field_grid(const Geo& g);
 void launch_b_stencil_dir(const InstDev* I, const BlockMap& bm, int k, hipStream_t s);
 void launch_b_restrict(const InstDev* I, const BlockMap& bm, int k, hipStream_t s);

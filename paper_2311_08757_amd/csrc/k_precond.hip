@@ -227,32 +227,57 @@ __device__ __forceinline__ void restrict_dense_body(const Geo& g, int delta,
   const long items = (long)segs * N1 * g.N[2];
   const int sub = threadIdx.x / kBlock, tx = threadIdx.x % kBlock;
   double acc = 0.0;
-  for (long grp = bid; grp * (kBig / kBlock) < items; grp += nblk) {
-    const long it = grp * (kBig / kBlock) + sub;
-    if (it >= items) continue;
-    const int line = (int)(it / segs);
-    const int i0 = (int)(it - (long)line * segs) * kBlock + tx;
-    if (i0 >= N0) continue;
-    const int i2 = g.D == 3 ? (int)fdiv((unsigned)line, g.fN1) : 0;
-    const int i[3] = {i0, line - i2 * N1, i2};
-    const long k = i0 + (long)N0 * line;
-    double rv = r[k];
-    if (xr.on) {
-      rv -= alpha * xr.q[k];
-      xr.x[k] += alpha * xr.p[k];
-      r[k] = rv;
-      acc += rv * rv;
-    }
-    const __bf16 hi = (__bf16)(float)rv;
-    const __bf16 lo = (__bf16)(float)(rv - (double)(float)hi);
-    const Cover<PX> cv(g, delta, i);
+  // two nodes per thread and pass (items it and it + IPB), all their loads
+  // issued before either is updated: the grid (node_grid_dense) fits on the
+  // chip in one round
+  constexpr int IPB = kBig / kBlock;
+  for (long grp = bid; grp * 2 * IPB < items; grp += nblk) {
+    bool ok[2];
+    long kk[2];
+    int ii[2][3];
+    double rv[2], qv[2], pv[2], xv[2];
 #pragma unroll
-    for (int q = 0; q < Cover<PX>::NC; ++q) {
-      if (!cv.val(q)) continue;
-      const int c0 = cv.c0(q), c1 = cv.c1(q);
-      const long at = (long)((c0 - 1) + g.L * (c1 - 1)) * da.ld + dense_index(g, delta, da, i, c0, c1);
-      da.Rh[at] = hi;
-      if (da.Rl != nullptr) da.Rl[at] = lo;
+    for (int u = 0; u < 2; ++u) {
+      const long it = grp * 2 * IPB + u * IPB + sub;
+      const int line = (int)(it / segs);
+      const int i0 = (int)(it - (long)line * segs) * kBlock + tx;
+      ok[u] = it < items && i0 < N0;
+      const int i2 = g.D == 3 ? (int)fdiv((unsigned)line, g.fN1) : 0;
+      ii[u][0] = i0; ii[u][1] = line - i2 * N1; ii[u][2] = i2;
+      kk[u] = i0 + (long)N0 * line;
+      rv[u] = qv[u] = pv[u] = xv[u] = 0.0;
+      if (ok[u]) {
+        rv[u] = r[kk[u]];
+        if (xr.on) {
+          qv[u] = xr.q[kk[u]];
+          pv[u] = xr.p[kk[u]];
+          xv[u] = xr.x[kk[u]];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (!ok[u]) continue;
+      const long k = kk[u];
+      const int* i = ii[u];
+      double rvv = rv[u];
+      if (xr.on) {
+        rvv -= alpha * qv[u];
+        xr.x[k] = xv[u] + alpha * pv[u];
+        r[k] = rvv;
+        acc += rvv * rvv;
+      }
+      const __bf16 hi = (__bf16)(float)rvv;
+      const __bf16 lo = (__bf16)(float)(rvv - (double)(float)hi);
+      const Cover<PX> cv(g, delta, i);
+#pragma unroll
+      for (int q = 0; q < Cover<PX>::NC; ++q) {
+        if (!cv.val(q)) continue;
+        const int c0 = cv.c0(q), c1 = cv.c1(q);
+        const long at = (long)((c0 - 1) + g.L * (c1 - 1)) * da.ld + dense_index(g, delta, da, i, c0, c1);
+        da.Rh[at] = hi;
+        if (da.Rl != nullptr) da.Rl[at] = lo;
+      }
     }
   }
   if (xr.on) write_partial_at<kBig>(acc, rr.part, bid);
@@ -410,9 +435,20 @@ int node_grid(const Geo& g) {
   return (int)std::max<long>(1, std::min<long>(groups, kMaxRed));
 }
 
+// The dense restriction takes two items per thread and pass.  (The grouped
+// restriction of a batch keeps node_grid's count: its second half of
+// workgroups finds no items and writes partial sums of exactly zero, so the
+// sums match the single problem's bit for bit.)
+int node_grid_dense(const Geo& g) {
+  const long segs = (g.N[0] + kBlock - 1) / kBlock;
+  const long items = segs * g.N[1] * g.N[2];
+  const long groups = (items + 2 * (kBig / kBlock) - 1) / (2 * (kBig / kBlock));
+  return (int)std::max<long>(1, std::min<long>(groups, kMaxRed));
+}
+
 void launch_restrict(const ddeig_problem* P, double* r, PcgState* st, const XrArgs& xr, Red* rr,
                      hipStream_t s) {
-  const int blocks = node_grid(P->g);
+  const int blocks = P->opt.local_prec >= 2 ? node_grid_dense(P->g) : node_grid(P->g);
   const Red none{nullptr, 0, nullptr};
   if (xr.on) rr->np = blocks;
   if (P->opt.local_prec >= 2) {
