@@ -2216,7 +2216,7 @@ ddeig_status ddeig_batch_create(ddeig_problem* const* probs, int n, int flags, d
       d.delta = P->delta;
       d.pu = P->opt.pu;
       d.nsub = P->nsub;
-      d.nb_node = ddeig::node_grid(P->g);
+      d.nb_node = ddeig::node_grid_dense(P->g);  // the single problem's grid (2 nodes per thread)
       d.nb_cf = ddeig::coarse_field_grid(P->g);
       d.hist_cap = P->hist_cap;
       d.tabAs = P->tabAs;

@@ -297,7 +297,7 @@ __global__ void __launch_bounds__(kBig) k_restrict_dense(Geo g, int delta, PcgSt
 // INL forms the coarse field at the node from y0 itself (cf then points to
 // y0): sum_c D_c y0_c over the covering cells in slot order, the arithmetic of
 // k_coarse_field.
-template <int PX, int KS, bool RAS = false, bool INL = false>
+template <int PX, int KS, bool RAS = false, bool INL = false, int NPT = 1>
 __device__ __forceinline__ void extend_dense_body(const Geo& g, int delta, int coarse,
                                                   PcgState* __restrict__ st, const CheckArgs& chk,
                                                   const DenseArgs& da,
@@ -327,38 +327,60 @@ __device__ __forceinline__ void extend_dense_body(const Geo& g, int delta, int c
   const int segs = (N0 + kBlock - 1) / kBlock;
   const long items = (long)segs * N1 * g.N[2];
   const int sub = threadIdx.x / kBlock, tx = threadIdx.x % kBlock;
-  for (long grp = bid; grp * (kBig / kBlock) < items; grp += nblk) {
-    const long it = grp * (kBig / kBlock) + sub;
-    if (it >= items) continue;
-    const int line = (int)(it / segs);
-    const int i0 = (int)(it - (long)line * segs) * kBlock + tx;
-    if (i0 >= N0) continue;
-    const int i2 = g.D == 3 ? (int)fdiv((unsigned)line, g.fN1) : 0;
-    const int i[3] = {i0, line - i2 * N1, i2};
-    const long k = i0 + (long)N0 * line;
-    const Cover<PX> cv(g, delta, i);
-    // every load of the node first (independent of each other) ...
-    // (the inline coarse field with one expanding axis: the covering-table
-    // entry and the two y0 values)
-    XCover xa;
-    double ya[2] = {0.0, 0.0};
-    if constexpr (INL && PX == 1) {
-      if (coarse) {
-        xa = xc0[i0];
-        ya[0] = cf[cv.c0(0) - 1];
-        ya[1] = cf[cv.c0(1) - 1];
+  // NPT nodes per thread and pass (items it + u IPB): every load of them
+  // first, then their sums
+  constexpr int IPB = kBig / kBlock;
+  for (long grp = bid; grp * NPT * IPB < items; grp += nblk) {
+    bool okn[NPT];
+    long kn[NPT];
+    int in_[NPT][3];
+    XCover xan[NPT];
+    double yan[NPT][2], rkn[NPT];
+    float zsn[NPT][NC][KS];
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+      const long it = grp * NPT * IPB + u * IPB + sub;
+      const int line = (int)(it / segs);
+      const int i0 = (int)(it - (long)line * segs) * kBlock + tx;
+      okn[u] = it < items && i0 < N0;
+      const int i2 = g.D == 3 ? (int)fdiv((unsigned)line, g.fN1) : 0;
+      in_[u][0] = i0;
+      in_[u][1] = line - i2 * N1;
+      in_[u][2] = i2;
+      kn[u] = i0 + (long)N0 * line;
+      yan[u][0] = yan[u][1] = 0.0;
+      if (!okn[u]) continue;
+      const Cover<PX> cv(g, delta, in_[u]);
+      // (the inline coarse field with one expanding axis: the covering-table
+      // entry and the two y0 values)
+      if constexpr (INL && PX == 1) {
+        if (coarse) {
+          xan[u] = xc0[i0];
+          yan[u][0] = cf[cv.c0(0) - 1];
+          yan[u][1] = cf[cv.c0(1) - 1];
+        }
       }
-    }
-    float zs[NC][KS];
 #pragma unroll
-    for (int q = 0; q < NC; ++q) {
-      const int c0 = cv.c0(q), c1 = cv.c1(q);
-      const int sid = (c0 - 1) + g.L * (c1 - 1);
-      const long at = (long)sid * da.ld + dense_index(g, delta, da, i, c0, c1);
+      for (int q = 0; q < NC; ++q) {
+        const int c0 = cv.c0(q), c1 = cv.c1(q);
+        const int sid = (c0 - 1) + g.L * (c1 - 1);
+        const long at = (long)sid * da.ld + dense_index(g, delta, da, in_[u], c0, c1);
 #pragma unroll
-      for (int sp = 0; sp < KS; ++sp) zs[q][sp] = da.Z[sp * da.zsplit + at];
+        for (int sp = 0; sp < KS; ++sp) zsn[u][q][sp] = da.Z[sp * da.zsplit + at];
+      }
+      rkn[u] = r[kn[u]];
     }
-    const double rk = r[k];
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+    if (!okn[u]) continue;
+    const int* i = in_[u];
+    const int i0 = i[0], i2 = i[2];
+    const long k = kn[u];
+    const Cover<PX> cv(g, delta, i);
+    const XCover& xa = xan[u];
+    const double* ya = yan[u];
+    float (&zs)[NC][KS] = zsn[u];
+    const double rk = rkn[u];
     double ps = 0.0, zc = 0.0;
     if (coarse) {
       // cell-local table node: x dims (i + 1) mod n_e
@@ -404,6 +426,7 @@ __device__ __forceinline__ void extend_dense_body(const Geo& g, int delta, int c
     const double zv = coarse ? fma(ps, zc, zl) : zl;
     z[k] = zv;
     acc += rk * zv;
+    }
   }
   if (use_dot) write_partial_at<kBig>(acc, dot.part, bid);
 }
@@ -421,6 +444,22 @@ __global__ void __launch_bounds__(kBig) k_extend_dense(Geo g, int delta, int coa
                                       blockIdx.x, gridDim.x, pu, xc0, xc1);
 }
 
+// One expanding axis: two nodes per thread on node_grid_dense's grid, at most
+// 64 VGPRs so that two 1024-thread workgroups fit on a CU (one round).
+template <int KS, bool RAS, bool INL>
+__global__ void __launch_bounds__(kBig) __attribute__((amdgpu_waves_per_eu(8)))
+k_extend_dense_p1(Geo g, int delta, int coarse,
+                                                       PcgState* __restrict__ st, CheckArgs chk,
+                                                       DenseArgs da, const double* __restrict__ psi,
+                                                       const double* __restrict__ cf,
+                                                       const double* __restrict__ r,
+                                                       double* __restrict__ z, int use_dot, Red dot,
+                                                       int pu, const XCover* __restrict__ xc0,
+                                                       const XCover* __restrict__ xc1) {
+  extend_dense_body<1, KS, RAS, INL, 2>(g, delta, coarse, st, chk, da, psi, cf, r, z, use_dot, dot,
+                                      blockIdx.x, gridDim.x, pu, xc0, xc1);
+}
+
 DenseArgs dense_args(const ddeig_problem* P) {
   const DenseHost& H = P->dh;
   return DenseArgs{H.Rh, H.Rl, H.Z, (long)H.mp * H.ld, H.ld, P->ksplit, H.box.m[0], H.box.m[1]};
@@ -435,10 +474,9 @@ int node_grid(const Geo& g) {
   return (int)std::max<long>(1, std::min<long>(groups, kMaxRed));
 }
 
-// The dense restriction takes two items per thread and pass.  (The grouped
-// restriction of a batch keeps node_grid's count: its second half of
-// workgroups finds no items and writes partial sums of exactly zero, so the
-// sums match the single problem's bit for bit.)
+// The dense restriction and (one expanding axis, additive) extension take two
+// items per thread and pass; a batch uses the same count per instance, so its
+// partial sums match the single problem's bit for bit.
 int node_grid_dense(const Geo& g) {
   const long segs = (g.N[0] + kBlock - 1) / kBlock;
   const long items = segs * g.N[1] * g.N[2];
@@ -657,6 +695,9 @@ __global__ void __launch_bounds__(kBig) k_extend(Geo g, int delta, int pu, int c
 
 template <bool RAS, bool INL>
 static auto dense_extend_kernel(int p, int ks) {
+  if (p == 1 && !RAS)  // (the RAS weights would spill at 64 VGPRs)
+    return ks == 1 ? k_extend_dense_p1<1, RAS, INL>
+                   : (ks == 2 ? k_extend_dense_p1<2, RAS, INL> : k_extend_dense_p1<3, RAS, INL>);
   if (p == 1)
     return ks == 1 ? k_extend_dense<1, 1, RAS, INL>
                    : (ks == 2 ? k_extend_dense<1, 2, RAS, INL> : k_extend_dense<1, 3, RAS, INL>);
@@ -668,7 +709,8 @@ static auto dense_extend_kernel(int p, int ks) {
 // instead of read from k_coarse_field's output (dense local solves only).
 void launch_extend(const ddeig_problem* P, const double* r, double* z, int coarse, Red* dot,
                    PcgState* st, const CheckArgs& chk, hipStream_t s, int ras, int inline_field) {
-  const int blocks = node_grid(P->g);
+  const int blocks = P->opt.local_prec >= 2 && P->g.p == 1 && !ras ? node_grid_dense(P->g)
+                                                                   : node_grid(P->g);
   const Red none{nullptr, 0, nullptr};
   if (dot) dot->np = blocks;
   if (P->opt.local_prec >= 2) {
@@ -817,13 +859,14 @@ __global__ void __launch_bounds__(kBig) k_b_restrict(const InstDev* __restrict__
 }
 
 template <int KS>
-__global__ void __launch_bounds__(kBig) k_b_extend(const InstDev* __restrict__ I,
-                                                   const int2* __restrict__ map, int k, int maxit) {
+// Two nodes per thread on node_grid_dense's grid, as the single problem's extension.
+__global__ void __launch_bounds__(kBig) __attribute__((amdgpu_waves_per_eu(8)))
+k_b_extend(const InstDev* __restrict__ I, const int2* __restrict__ map, int k, int maxit) {
   const int2 m = map[blockIdx.x];
   const InstDev& d = I[m.x];
   const CheckArgs chk{1, k, maxit, d.hist_cap, d.rr, d.hist};
-  extend_dense_body<1, KS>(d.g, d.delta, 1, d.st, chk, d.da, d.psi, d.cf, d.r, d.z, 1, d.rz, m.y,
-                           d.nb_node);
+  extend_dense_body<1, KS, false, false, 2>(d.g, d.delta, 1, d.st, chk, d.da, d.psi, d.cf, d.r,
+                                            d.z, 1, d.rz, m.y, d.nb_node);
 }
 
 __global__ void __launch_bounds__(kBlock) k_b_coarse_rhs(const InstDev* __restrict__ I,
