@@ -110,8 +110,9 @@ typedef struct {
                       def:algebraic-perfact-coarse-space) */
   int local_prec;  /* local subdomain solves: 0 FP64 block-chain factors, 1 FP32 factors with
                       FP32 arithmetic, 2 dense inverses as bf16 hi/lo pairs applied on MFMA
-                      (bf16x3, FP32 accumulation), 3 dense inverses in bf16 (two MFMA
-                      products, FP32 accumulation); the outer CG is FP64 in every case */
+                      (bf16x3, FP32 accumulation), 3 dense inverse and residual in single
+                      bf16 (one MFMA product, FP32 accumulation); the outer CG is FP64 in
+                      every case */
   int batch_iters; /* PCG iterations queued between host convergence checks (0: default 8) */
   int graphs;      /* 1: each block of batch_iters PCG iterations is captured once into a HIP
                       graph (per first iteration, maxit and iterate pointer) on a stream of the
@@ -138,6 +139,8 @@ typedef struct {
   double t_solve_ms;
   double spec_res;    /* ||A x - lambda M x||_2 of the returned (M-normalised) x */
   double t_setup_ms;  /* wall time of ddeig_assemble and the shift calls of the problem */
+  int inner_unconverged; /* inner solves that stopped at maxit_inner (the call then
+                            returns DDEIG_ENOCONV even if the outer test was met) */
 } ddeig_eig_info;
 
 /* Builds the period-cell operator tables (K, M, M_V at one period cell: §2,
@@ -207,7 +210,9 @@ ddeig_status ddeig_stationary_ras(ddeig_problem* P, int levels, const double* b,
 
 /* GMRES for A_sigma x = b with right preconditioning by `kind` (§3: GMRES
  * with the unsymmetric M_RAS,2 is the Krylov method for RAS; §4.2).  Arnoldi
- * by classical Gram-Schmidt applied twice; the preconditioned vectors
+ * by delayed classical Gram-Schmidt with reorthogonalisation (DCGS2: the
+ * second projection of v_j shares its sweep over the basis with the first
+ * projection of the next vector); the preconditioned vectors
  * z_j = M^{-1} v_j are kept and x = x0 + Z y (y from the Givens-rotated
  * least-squares problem), which equals x0 + M^{-1} V y for a linear M and
  * keeps the Arnoldi relation when the local solves round their input (bf16).
@@ -231,7 +236,11 @@ ddeig_status ddeig_pcg_solve(ddeig_problem* P, const double* b, double* x, doubl
  * PCG from a zero guess to rtol_inner, M-normalised, sign fixed so that
  * 1^T M x > 0; stops when ||x_{k+1} - x_k||_M <= tol_x or after maxit_outer
  * steps.  x: on entry the start vector (all zeros selects 1/||1||_M); on exit
- * the M-normalised eigenvector. */
+ * the M-normalised eigenvector (the last iterate on any error).  Returns
+ * DDEIG_ENOTSPD on a CG breakdown of an inner solve, DDEIG_ENOCONV at
+ * maxit_outer or when any inner solve stopped at maxit_inner (counted in
+ * info->inner_unconverged: the outer test may then have settled on the fixed
+ * point of the inexact solve). */
 ddeig_status ddeig_inverse_iteration(ddeig_problem* P, double* x, double tol_x, int maxit_outer,
                                      double rtol_inner, int maxit_inner, ddeig_eig_info* info);
 
@@ -294,6 +303,21 @@ ddeig_status ddeig_lopcg(ddeig_problem* P, double* x, const double* x_prev, doub
  * otherwise. */
 ddeig_status ddeig_profile_kernel(ddeig_problem* P, int which, int reps, const double* x, double* y,
                                   double* avg_us, double* work);
+
+/* Measurement support: runs reps + 1 iterations of a PCG on A_sigma x = b from
+ * x = 0 that cannot stop (rtol 0) on the library stream, with HIP events
+ * between the parts of each iteration, and returns in us[0..4] the mean
+ * duration (us) of each part over the last reps iterations: 0 the stencil with
+ * the direction update (p = z + beta p, q = A_sigma p, p.q), 1 the restriction
+ * with the update of x and r (||r||^2), 2 the local solves (the MFMA GEMM over
+ * all subdomains, carrying R_0 r when the coarse space rides in the dense
+ * launches; or the block-chain solves), 3 the clipped-class correction with
+ * the coarse solve (dense local solves; 0 otherwise), 4 the extension with the
+ * stopping test and r.z (with the wait for the coarse correction when that
+ * runs on the second stream).  Uses the problem's internal vectors (any
+ * earlier solve state is overwritten); b: n_dof device values.  Needs the
+ * shift; synchronises.  1 <= reps <= 200. */
+ddeig_status ddeig_profile_iteration(ddeig_problem* P, const double* b, int reps, double* us);
 
 /* Potential-weighted bilinear form out = x^T M_W y, where M_W is the mass
  * matrix weighted by the potential W, assembled with the same quadrature as

@@ -12,8 +12,8 @@ in §4.2); sign fixed so that 1^T M x > 0; stop when ||x_{k+1} - x_k||_M
 <= tol (the paper fixes no stopping rule for the plain inverse iteration).
 
 The linear solves are either exact (a direct factorisation of A_sigma:
-banded Cholesky with the fixed directions fastest in 2-D, SuperLU otherwise)
-or PCG with a supplied preconditioner.
+banded Cholesky with the fixed direction fastest for a 2-D grid passed as
+`grid`, SuperLU without a grid) or PCG with a supplied preconditioner.
 """
 import numpy as np
 import scipy.linalg as sla
@@ -26,7 +26,7 @@ from .pcg import pcg
 class DirectSolver:
     """Exact solves with A_sigma (SPD)."""
 
-    def __init__(self, A_sigma, grid=None, band_bytes=24e9):
+    def __init__(self, A_sigma, grid=None):
         A = sp.csr_matrix(A_sigma)
         self.n = A.shape[0]
         self.kind = "splu"
@@ -36,18 +36,8 @@ class DirectSolver:
             nx, ny = grid.ndof_dir
             perm = np.arange(self.n).reshape(ny, nx).T.ravel()
             bw = ny + 1
-        elif grid is not None and grid.d == 3:
-            # banded Cholesky with the longest direction slowest, when its band fits:
-            # half-bandwidth = n_fast (n_mid + 1) + 1
-            dims = list(grid.ndof_dir)
-            order = sorted(range(3), key=lambda a: dims[a])       # fastest first
-            nf, nm = dims[order[0]], dims[order[1]]
-            b3 = nf * (nm + 1) + 1
-            if self.n * (b3 + 1) * 8 <= band_bytes:
-                idx = np.arange(self.n).reshape(dims[2], dims[1], dims[0])  # [a2][a1][a0]
-                axes = [2 - order[2], 2 - order[1], 2 - order[0]]       # slowest .. fastest
-                perm = idx.transpose(axes).ravel()
-                bw = b3
+        elif grid is not None:
+            raise ValueError("the banded route is for 2-D grids; pass grid=None for SuperLU")
         if perm is not None:
             Ap = A[perm][:, perm].tocsr()
             ab = np.zeros((bw + 1, self.n))

@@ -1,29 +1,52 @@
-"""Builds libddeig.so in-tree with hipcc for gfx950 (cross-compiles without a GPU)."""
+"""Builds libddeig.so in-tree with hipcc for gfx950 (cross-compiles without a GPU).
+
+Every source is compiled to its own object in parallel (the kernels of one
+file only call device functions from headers), then the objects are linked.
+"""
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libddeig.so")
+OBJDIR = os.path.join(os.path.dirname(HERE), "_build")
 SOURCES = ["api.hip", "k_operator.hip", "k_chain.hip", "k_precond.hip", "k_vector.hip",
            "k_dense.hip", "k_krylov.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]
 
 
-def build(verbose=False):
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + srcs + ["-o", tmp]
+def _compile(src, verbose):
+    obj = os.path.join(OBJDIR, os.path.splitext(os.path.basename(src))[0] + ".o")
+    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
+    return obj, res
+
+
+def build(verbose=False, jobs=None):
+    os.makedirs(OBJDIR, exist_ok=True)
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    jobs = jobs or min(len(srcs), max(1, os.cpu_count() or 1), 8)
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(lambda s: _compile(s, verbose), srcs))
+    failed = [(o, r) for o, r in results if r.returncode != 0]
+    if failed:
+        for o, r in failed:
+            sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed building libddeig.so")
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + [o for o, _ in results] + \
+        ["-o", tmp]
+    res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libddeig.so")
+        raise RuntimeError("hipcc failed linking libddeig.so")
     os.replace(tmp, LIB)
     return LIB
 

@@ -1504,6 +1504,90 @@ ddeig_status ddeig_profile_kernel(ddeig_problem* P, int which, int reps, const d
   API_GUARD_END
 }
 
+ddeig_status ddeig_profile_iteration(ddeig_problem* P, const double* b, int reps, double* us) {
+  if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
+  if (validate_vec(b, "b")) return DDEIG_EINVAL;
+  if (!us || reps < 1 || reps > 200) return set_error(DDEIG_EINVAL, "need us and 1 <= reps <= 200");
+  if (!P->shifted) return set_error(DDEIG_ESTATE, "profile_iteration before the shift is set");
+  if (b == P->u) return set_error(DDEIG_EINVAL, "b must not be an internal vector");
+  API_GUARD_BEGIN
+  const hipStream_t s = P->stream;
+  const long n = P->g.n;
+  double* x = P->u;
+  Red g = slot(P, 0), rr = slot(P, 1), rz = slot(P, 2);
+  // a CG on A_sigma x = b from x = 0 that cannot stop: rtol 0 and maxit beyond
+  // the iterations run, so no kernel takes its early exit
+  const int maxit = reps + 2;
+  launch_fill(x, n, 0.0, s);
+  launch_stencil(P, P->tabAs, x, P->q, nullptr, nullptr, s);
+  launch_resid_init(P, b, P->q, P->r, rr, s);
+  launch_pcg_init(P, 0.0, rr, s);
+  precond_apply(P, P->r, P->z, &rz, P->st);
+  check_launch("profile start");
+  const int coarse = P->opt.coarse;
+  const bool fused = coarse && fused_coarse(P);
+  constexpr int kParts = 5;
+  std::vector<hipEvent_t> ev((size_t)(kParts + 1) * (reps + 1), nullptr);
+  for (auto& e : ev) check_hip(hipEventCreate(&e), "event");
+  for (int kk = 1; kk <= reps + 1; ++kk) {
+    hipEvent_t* e = ev.data() + (size_t)(kParts + 1) * (kk - 1);
+    double* pold = P->pp[(kk - 1) & 1];
+    double* pnew = P->pp[kk & 1];
+    const DirArgs dir{P->st, kk, rz};
+    check_hip(hipEventRecord(e[0], s), "record");
+    launch_stencil_dir(P, P->z, pold, pnew, P->q, dir, g, s);
+    check_hip(hipEventRecord(e[1], s), "record");
+    const XrArgs xr{1, kk, g, x, pnew, P->q};
+    launch_restrict(P, P->r, P->st, xr, &rr, s);
+    check_hip(hipEventRecord(e[2], s), "record");
+    CheckArgs chk{1, kk, maxit, P->hist_cap, rr, P->hist};
+    if (fused) {
+      launch_local_solves(P, P->st, s, P->r);
+      check_hip(hipEventRecord(e[3], s), "record");
+      launch_embed_fix(P, P->st, s, true);
+      check_hip(hipEventRecord(e[4], s), "record");
+      launch_extend(P, P->r, P->z, 1, &rz, P->st, chk, s, 0, 1);
+    } else {
+      if (coarse) {
+        check_hip(hipEventRecord(P->ev_fork, s), "record fork");
+        check_hip(hipStreamWaitEvent(P->aux, P->ev_fork, 0), "wait fork");
+      }
+      launch_local_solves(P, P->st, s);
+      check_hip(hipEventRecord(e[3], s), "record");
+      if (P->opt.local_prec >= 2) launch_embed_fix(P, P->st, s);
+      if (coarse) {
+        launch_coarse_rhs(P, P->r, P->st, P->aux);
+        launch_coarse_solve(P, P->st, P->aux);
+        if (P->opt.local_prec >= 2) launch_coarse_field(P, P->st, P->aux);
+        check_hip(hipEventRecord(P->ev_join, P->aux), "record join");
+      }
+      check_hip(hipEventRecord(e[4], s), "record");
+      if (coarse) check_hip(hipStreamWaitEvent(s, P->ev_join, 0), "wait join");
+      launch_extend(P, P->r, P->z, coarse, &rz, P->st, chk, s, 0);
+    }
+    check_hip(hipEventRecord(e[5], s), "record");
+  }
+  check_launch("profile iteration");
+  check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+  for (int k = 0; k < kParts; ++k) us[k] = 0.0;
+  for (int kk = 2; kk <= reps + 1; ++kk) {  // the first iteration is a warm-up
+    hipEvent_t* e = ev.data() + (size_t)(kParts + 1) * (kk - 1);
+    for (int k = 0; k < kParts; ++k) {
+      float ms = 0.0f;
+      check_hip(hipEventElapsedTime(&ms, e[k], e[k + 1]), "elapsed");
+      us[k] += 1000.0 * ms / reps;
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  PcgState hs{};
+  check_hip(hipMemcpy(&hs, P->st, sizeof(PcgState), hipMemcpyDeviceToHost), "state");
+  if (hs.done != 0)
+    return set_error(DDEIG_EINTERNAL, "the profiled CG stopped early (state " +
+                                          std::to_string(hs.done) + "); times are not valid");
+  return DDEIG_OK;
+  API_GUARD_END
+}
+
 ddeig_status ddeig_potential_form(ddeig_problem* P, int space, const ddeig_potential* W,
                                   const double* x, const double* y, double* out) {
   if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
@@ -1826,7 +1910,7 @@ ddeig_status ddeig_inverse_iteration(ddeig_problem* P, double* x, double tol_x, 
   }
   double lam = 0.0, dx = INFINITY;
   long inner_sum = 0;
-  int inner_max = 0, k = 0;
+  int inner_max = 0, k = 0, inner_unconv = 0;
   ddeig_status st = DDEIG_ENOCONV;
   for (k = 1; k <= maxit_outer; ++k) {
     launch_stencil(P, P->tabM, x, P->w, nullptr, nullptr, s);  // b = M x
@@ -1838,6 +1922,7 @@ ddeig_status ddeig_inverse_iteration(ddeig_problem* P, double* x, double tol_x, 
     }
     inner_sum += o.iters;
     inner_max = std::max(inner_max, o.iters);
+    if (o.done != 1) ++inner_unconv;  // stopped at maxit_inner
     Red s4 = slot(P, 4), s5 = slot(P, 5), s6 = slot(P, 6), s7 = slot(P, 7);
     launch_stencil(P, P->tabM, P->u, P->z, &s4, &s5, s);  // Mu, u.Mu, sum(Mu)
     launch_ipm_normalise(n, P->u, P->z, x, P->w, s4, s5, s6, s);
@@ -1865,8 +1950,14 @@ ddeig_status ddeig_inverse_iteration(ddeig_problem* P, double* x, double tol_x, 
     info->t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     info->spec_res = ddeig::spectral_residual(P, x, lam);
     info->t_setup_ms = P->t_setup_ms;
+    info->inner_unconverged = inner_unconv;
   }
   if (st == DDEIG_ENOCONV) return set_error(st, "inverse iteration reached maxit_outer");
+  // an inner solve that stopped at maxit_inner can leave the outer test on the
+  // fixed point of the inexact solve, so the pair is not reported as converged
+  if (st == DDEIG_OK && inner_unconv > 0)
+    return set_error(DDEIG_ENOCONV, std::to_string(inner_unconv) +
+                                        " inner solve(s) stopped at maxit_inner");
   return st;
   API_GUARD_END
 }
@@ -2348,7 +2439,7 @@ ddeig_status ddeig_batch_inverse_iteration(ddeig_batch* B, double* const* x, dou
       launch_scale_copy(P->g.n, x[j], P->u, s3, s);
     }
   }
-  std::vector<int> active(n, 1), status(n, 0), its(n, 0), inner_max(n, 0);
+  std::vector<int> active(n, 1), status(n, 0), its(n, 0), inner_max(n, 0), unconv(n, 0);
   std::vector<long> inner_sum(n, 0);
   std::vector<double> lam(n, 0.0), dx(n, INFINITY), res(2 * (size_t)n);
   std::vector<const double*> bb(n);
@@ -2378,6 +2469,7 @@ ddeig_status ddeig_batch_inverse_iteration(ddeig_batch* B, double* const* x, dou
       }
       inner_sum[j] += h.iters;
       inner_max[j] = std::max(inner_max[j], h.iters);
+      if (h.done != 1) ++unconv[j];
       its[j] = k;
       ddeig_problem* P = B->P[j];
       const long nn = P->g.n;
@@ -2417,11 +2509,15 @@ ddeig_status ddeig_batch_inverse_iteration(ddeig_batch* B, double* const* x, dou
       info[j].t_solve_ms = ms;
       info[j].spec_res = ddeig::spectral_residual(B->P[j], x[j], lam[j]);
       info[j].t_setup_ms = B->P[j]->t_setup_ms;
+      info[j].inner_unconverged = unconv[j];
     }
     if (status[j] == DDEIG_ENOTSPD)
       st = set_error(DDEIG_ENOTSPD, "instance " + std::to_string(j) + ": CG breakdown");
     else if (status[j] != 1 && st != DDEIG_ENOTSPD)
       st = set_error(DDEIG_ENOCONV, "instance " + std::to_string(j) + ": reached maxit_outer");
+    else if (unconv[j] > 0 && st != DDEIG_ENOTSPD)
+      st = set_error(DDEIG_ENOCONV, "instance " + std::to_string(j) +
+                                        ": an inner solve stopped at maxit_inner");
   }
   return st;
   API_GUARD_END

@@ -58,7 +58,8 @@ class EigInfo(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("dx_M", ctypes.c_double),
                 ("outer_its", ctypes.c_int), ("inner_sum", ctypes.c_long),
                 ("inner_max", ctypes.c_int), ("t_solve_ms", ctypes.c_double),
-                ("spec_res", ctypes.c_double), ("t_setup_ms", ctypes.c_double)]
+                ("spec_res", ctypes.c_double), ("t_setup_ms", ctypes.c_double),
+                ("inner_unconverged", ctypes.c_int)]
 
 
 class LopcgInfo(ctypes.Structure):
@@ -70,7 +71,7 @@ class LopcgInfo(ctypes.Structure):
 EXPORTS = ["ddeig_assemble", "ddeig_cell_shift", "ddeig_set_shift", "ddeig_apply_op",
            "ddeig_apply_precond", "ddeig_apply_schwarz", "ddeig_stationary_ras",
            "ddeig_gmres_solve", "ddeig_pcg_solve", "ddeig_inverse_iteration", "ddeig_lopcg",
-           "ddeig_profile_kernel", "ddeig_potential_form", "ddeig_batch_create",
+           "ddeig_profile_kernel", "ddeig_profile_iteration", "ddeig_potential_form", "ddeig_batch_create",
            "ddeig_batch_query", "ddeig_batch_pcg_solve", "ddeig_batch_inverse_iteration",
            "ddeig_batch_destroy", "ddeig_query", "ddeig_destroy", "ddeig_status_string",
            "ddeig_last_error"]
@@ -108,6 +109,7 @@ def load_library(path=LIB_PATH):
                                 ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                 ctypes.POINTER(LopcgInfo)]
     lib.ddeig_profile_kernel.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, dp, dp]
+    lib.ddeig_profile_iteration.argtypes = [P, P, ctypes.c_int, dp]
     lib.ddeig_potential_form.argtypes = [P, ctypes.c_int, ctypes.POINTER(Potential), P, P, dp]
     PP = ctypes.POINTER(ctypes.c_void_p)
     lib.ddeig_batch_create.argtypes = [PP, ctypes.c_int, ctypes.c_int, PP]
@@ -353,7 +355,8 @@ def inverse_iteration(prob, x, tol_x=1e-9, maxit_outer=100, rtol_inner=1e-10, ma
                                      ctypes.byref(info))
     out = dict(status=STATUS.get(st, st), lam=info.lambda_, dx_M=info.dx_M,
                outer_its=info.outer_its, inner_sum=info.inner_sum, inner_max=info.inner_max,
-               t_solve_ms=info.t_solve_ms, spec_res=info.spec_res, t_setup_ms=info.t_setup_ms)
+               t_solve_ms=info.t_solve_ms, spec_res=info.spec_res, t_setup_ms=info.t_setup_ms,
+               inner_unconverged=info.inner_unconverged)
     if raise_on_error and st != DDEIG_OK:
         _check(st, "ddeig_inverse_iteration")
     return out
@@ -375,6 +378,18 @@ def profile_kernel(prob, which, reps=20, x=None, y=None):
     _check(lib.ddeig_profile_kernel(prob.handle, w, int(reps), xp, yp, ctypes.byref(avg),
                                     ctypes.byref(work)), "ddeig_profile_kernel")
     return avg.value, work.value
+
+
+ITERATION_PARTS = ("stencil_dir", "restrict_xr", "local_solves", "correction", "extend_check")
+
+
+def profile_iteration(prob, b, reps=30):
+    """ddeig_profile_iteration: mean time (us) of each part of one PCG iteration."""
+    lib = load_library()
+    us = (ctypes.c_double * len(ITERATION_PARTS))()
+    _check(lib.ddeig_profile_iteration(prob.handle, _ptr(b, prob.n_dof, "b"), int(reps), us),
+           "ddeig_profile_iteration")
+    return dict(zip(ITERATION_PARTS, list(us)))
 
 
 def potential_form(prob, W, x, y, space="global"):
@@ -470,7 +485,8 @@ def batch_inverse_iteration(batch, xs, tol_x=1e-9, maxit_outer=100, rtol_inner=1
     return STATUS.get(st, st), [dict(lam=i.lambda_, dx_M=i.dx_M, outer_its=i.outer_its,
                                      inner_sum=i.inner_sum, inner_max=i.inner_max,
                                      t_solve_ms=i.t_solve_ms, spec_res=i.spec_res,
-                                     t_setup_ms=i.t_setup_ms) for i in info]
+                                     t_setup_ms=i.t_setup_ms,
+                                     inner_unconverged=i.inner_unconverged) for i in info]
 
 
 LOPCG_MODES = {"fixed": 0, "adaptive": 1, "fused": 2}

@@ -314,3 +314,65 @@ def test_source_problem_41(torch):
         assert as2[512] <= 1.25 * as2[32], (ne, delta, as2)
         assert as1[512] >= 8 * as1[32], (ne, delta, as1)
     assert run(512, 10, 3, True) < run(512, 10, 1, True)
+
+
+def test_shift_above_ground_state(torch):
+    """A shift override at or above lambda_1 makes A_sigma indefinite (failure
+    paths detected on the host from the kernels' own tests, nothing forced):
+    - sigma = lambda_1 + 0.05 (lambda_2 - lambda_1): the local matrices and the
+      coarse matrix stay positive definite (checked on the oracle's matrices),
+      so set_shift succeeds, but CG meets p.A_sigma p <= 0 or r.z <= 0, as the
+      oracle's PCG does: pcg_solve and inverse_iteration return ENOTSPD;
+    - sigma = lambda_1 + 2 (lambda_2 - lambda_1): the coarse matrix has a
+      negative eigenvalue (oracle), and set_shift returns ENOTSPD from its
+      factorisation."""
+    import scipy.linalg as sla
+    import paper_2311_08757_amd as dd
+    from oracle.pcg import pcg
+    from oracle.dd import AdditiveSchwarz
+    case = CASES[0]
+    P = _oracle(case)
+    ev = sla.eigh(P.A.toarray(), P.M.toarray(), eigvals_only=True, subset_by_index=[0, 1])
+    b = P.M @ np.ones(P.grid.n)
+    for frac, expect_shift_ok in ((0.05, True), (2.0, False)):
+        s = float(ev[0] + frac * (ev[1] - ev[0]))
+        As = (P.A - s * P.M).tocsr()
+        a0_min = np.linalg.eigvalsh((P.R0T.T @ As @ P.R0T).toarray())[0]
+        loc_min = min(np.linalg.eigvalsh(As[sd][:, sd].toarray())[0] for sd in P.subs)
+        assert loc_min > 0.0
+        assert (a0_min > 0.0) == expect_shift_ok
+        prob = _assemble(case)
+        if not expect_shift_ok:
+            with pytest.raises(dd.DdeigError) as e:
+                dd.set_shift(prob, s, P.cell["psi"])
+            assert e.value.code == "ENOTSPD"
+            continue
+        dd.set_shift(prob, s, P.cell["psi"])
+        ref = pcg(lambda v: As @ v, b, AdditiveSchwarz(As, P.subs, P.R0T).apply, rtol=1e-10,
+                  maxit=500)
+        assert ref.status == "not_spd"
+        x = torch.zeros(P.grid.n, dtype=torch.float64, device="cuda")
+        out = dd.pcg_solve(prob, _dev(torch, b), x, rtol=1e-10, maxit=500, raise_on_error=False)
+        assert out["status"] == "ENOTSPD" and out["breakdown"] in (1, 2)
+        assert abs(out["iters"] - ref.iters) <= 1
+        x.zero_()
+        out = dd.inverse_iteration(prob, x, raise_on_error=False)
+        assert out["status"] == "ENOTSPD"
+
+
+def test_inner_maxit_is_enoconv(torch):
+    """An inner solve stopped at maxit_inner is not a converged eigenpair:
+    inverse_iteration returns ENOCONV and counts the unconverged inner solves,
+    even when the outer test is met on the fixed point of the inexact solve."""
+    import paper_2311_08757_amd as dd
+    case = CASES[0]
+    prob = _assemble(case)
+    dd.cell_shift(prob)
+    x = torch.zeros(prob.n_dof, dtype=torch.float64, device="cuda")
+    out = dd.inverse_iteration(prob, x, tol_x=1e-9, rtol_inner=1e-10, maxit_inner=2,
+                               maxit_outer=300, raise_on_error=False)
+    assert out["status"] == "ENOCONV"
+    assert out["inner_unconverged"] == out["outer_its"] >= 1
+    x.zero_()
+    out = dd.inverse_iteration(prob, x, tol_x=1e-9, rtol_inner=1e-10)
+    assert out["status"] == "OK" and out["inner_unconverged"] == 0
