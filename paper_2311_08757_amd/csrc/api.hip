@@ -146,8 +146,13 @@ void factor_types(ddeig_problem* P) {
   }
   for (auto& t : P->types) {
     chain_factor(P, t.box, P->tabAs, t.W, P->stream);
-    if (P->opt.local_prec == 1)
-      launch_to_float(t.W, t.W32, (long)t.box.nch * t.box.b * t.box.b, P->stream);
+    if (P->opt.local_prec == 1) {
+      if (P->chain_mfma)
+        launch_pad_float(t.W, t.W32, (long)t.box.nch * t.box.b, t.box.b, (t.box.b + 3) / 4 * 4,
+                         P->stream);
+      else
+        launch_to_float(t.W, t.W32, (long)t.box.nch * t.box.b * t.box.b, P->stream);
+    }
   }
   check_launch("local factorisation");
 }
@@ -1054,14 +1059,21 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
     int maxb_types = 0;
     for (auto& T : P->types) maxb_types = std::max(maxb_types, T.box.b);
     const bool batched_chain = !dense && g.D == 3;
+    // FP32 factors of 3-D boxes: the chain solves run on MFMA
+    bool chain_mfma = batched_chain && o.local_prec == 1;
+    for (auto& T : P->types)
+      if (!ddeig::chain_mfma_ok(T.box.b, T.box.m[0])) chain_mfma = false;
+    P->chain_mfma = chain_mfma ? 1 : 0;
     std::vector<ddeig::ChainJob> chainjobs;
     int mtot = 0;
     for (size_t t = 0; t < P->types.size(); ++t) {
       auto& T = P->types[t];
       maxb = std::max(maxb, T.box.b);
       const long mm = (long)T.box.nch * T.box.b;
+      const int ldw = chain_mfma ? (T.box.b + 3) / 4 * 4 : T.box.b;
+      tdev[t].ldw = ldw;
       if (batched_chain) {
-        const int mg = ddeig::chain_group_members();
+        const int mg = chain_mfma ? ddeig::chain_mfma_members() : ddeig::chain_group_members();
         for (int m0 = 0; m0 < T.nmem; m0 += mg)
           chainjobs.push_back(ddeig::ChainJob{(int)t, m0, std::min(mg, T.nmem - m0), mtot + m0});
         mtot += T.nmem;
@@ -1089,7 +1101,7 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
         tdev[t].zsplit = (long)H.mp * H.ld;
       } else {
         T.W = dalloc<double>(P, (size_t)T.box.nch * T.box.b * T.box.b);
-        if (o.local_prec == 1) T.W32 = dalloc<float>(P, (size_t)T.box.nch * T.box.b * T.box.b);
+        if (o.local_prec == 1) T.W32 = dalloc<float>(P, (size_t)T.box.nch * T.box.b * ldw);
         T.batch = dalloc<double>(P, (size_t)T.nmem * mm);
         for (int a = 0; a < 3; ++a) {
           tdev[t].hm[a] = T.box.m[a];
@@ -1114,7 +1126,8 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
       P->chain_bmax = maxb_types;
       P->chain_mtot = mtot;
       P->chain_part = dalloc<unsigned char>(
-          P, ddeig::chain_part_bytes(maxb_types, mtot, o.local_prec == 1));
+          P, chain_mfma ? ddeig::chain_mfma_part_bytes(maxb_types, mtot)
+                        : ddeig::chain_part_bytes(maxb_types, mtot, o.local_prec == 1));
       P->nchainjobs = (int)chainjobs.size();
       P->dChainJobs = dalloc<ddeig::ChainJob>(P, chainjobs.size());
       check_hip(hipMemcpyAsync(P->dChainJobs, chainjobs.data(),

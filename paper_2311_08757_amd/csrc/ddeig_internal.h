@@ -191,6 +191,9 @@ struct TypeDev {
   // member (equal for all members by periodicity), and division by m[0]
   const double* phi;
   FastDiv fm0;
+  // row stride of the FP32 factors W32 (b, or b rounded up to a multiple of 4
+  // for the MFMA chain solves, whose rows are zero padded)
+  int ldw;
 };
 
 constexpr int kMaxTypes = 9;  // 3 classes per expanding axis, p <= 2
@@ -349,6 +352,7 @@ struct ddeig_problem {
   int nchainjobs = 0;
   int chain_bmax = 0, chain_mtot = 0;  // largest slice, all members of all classes
   void* chain_part = nullptr;          // K-chunk partial products of a sweep step
+  int chain_mfma = 0;                  // FP32 chain solves on MFMA (k_chain_mfma.hip)
   ddeig::GemmTile* dTiles = nullptr;
   ddeig::GemvRows* dGemv = nullptr;
   ddeig::GemmType* dGtypes = nullptr;
@@ -449,6 +453,12 @@ void launch_local_solves(const ddeig_problem* P, const PcgState* st, hipStream_t
 bool fused_coarse(const ddeig_problem* P);
 int chain_group_members();
 size_t chain_part_bytes(int bmax, int mtot, int fp32);
+// FP32 batched chain solves on MFMA (k_chain_mfma.hip)
+int chain_mfma_members();
+bool chain_mfma_ok(int b, int m0);
+size_t chain_mfma_part_bytes(int bmax, int mtot);
+void launch_chain_mfma(const ddeig_problem* P, const PcgState* st, hipStream_t s);
+void launch_pad_float(const double* src, float* dst, long rows, int b, int ldw, hipStream_t s);
 void launch_coarse_solve(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 void launch_coarse_field(const ddeig_problem* P, const PcgState* st, hipStream_t s);
 void launch_coarse_rhs(const ddeig_problem* P, const double* r, const PcgState* st, hipStream_t s);

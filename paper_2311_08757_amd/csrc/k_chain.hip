@@ -485,7 +485,8 @@ void launch_local_solves(const ddeig_problem* P, const PcgState* st, hipStream_t
     return;
   }
   if (P->nchainjobs > 0) {
-    launch_chain_batched(P, st, s);
+    if (P->chain_mfma) launch_chain_mfma(P, st, s);
+    else launch_chain_batched(P, st, s);
     return;
   }
   const size_t lds = 2 * (size_t)P->maxb * sizeof(double);

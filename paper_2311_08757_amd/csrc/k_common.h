@@ -5,6 +5,11 @@
 
 namespace ddeig {
 
+// FP64 -> bf16 correctly rounded (to nearest, ties to even) in one step; the
+// residuals and inverses of the bf16 local solves are rounded with it.
+__device__ inline __bf16 to_bf16(double x) { return (__bf16)x; }
+
+
 // Sum over a workgroup of NT threads; every thread receives the total.  The
 // order of additions is fixed (shuffle tree inside each wave64, then the
 // waves in order), so repeated runs give identical bits.

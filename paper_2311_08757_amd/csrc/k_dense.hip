@@ -36,8 +36,8 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
 
 
 __device__ inline void split_bf16(double x, __bf16& hi, __bf16& lo) {
-  hi = (__bf16)(float)x;
-  lo = (__bf16)(float)(x - (double)(float)hi);
+  hi = to_bf16(x);
+  lo = to_bf16(x - (double)hi);
 }
 
 // Ainv (m x m FP64, row-major, from the chain solves of the identity) ->

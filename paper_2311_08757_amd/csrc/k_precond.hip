@@ -137,8 +137,8 @@ __global__ void __launch_bounds__(kBig) k_restrict(Geo g, int ntypes, PcgState* 
       r[k] = rv;
       acc += rv * rv;
     }
-    const __bf16 hi = (__bf16)(float)rv;
-    const __bf16 lo = (__bf16)(float)(rv - (double)(float)hi);
+    const __bf16 hi = to_bf16(rv);
+    const __bf16 lo = to_bf16(rv - (double)hi);
     const XCover a0 = xc0[i0];
     XCover a1;
     a1.c[0] = 1; a1.c[1] = 0; a1.u[0] = i1; a1.u[1] = 0;
@@ -267,8 +267,8 @@ __device__ __forceinline__ void restrict_dense_body(const Geo& g, int delta,
         r[k] = rvv;
         acc += rvv * rvv;
       }
-      const __bf16 hi = (__bf16)(float)rvv;
-      const __bf16 lo = (__bf16)(float)(rvv - (double)(float)hi);
+      const __bf16 hi = to_bf16(rvv);
+      const __bf16 lo = to_bf16(rvv - (double)hi);
       const Cover<PX> cv(g, delta, i);
 #pragma unroll
       for (int q = 0; q < Cover<PX>::NC; ++q) {

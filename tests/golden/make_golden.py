@@ -10,7 +10,9 @@ the Hellmann-Feynman derivative dlambda/dtheta of every instance for its
 eight Fourier parameters.  "pcg<c>" adds to oracle_config<c>.json the
 iteration count of the oracle's PCG with the two-level additive Schwarz
 preconditioner (exact local solves, equal weights) on A_sigma u = M 1 from
-u = 0 to rtol 1e-10: the first inner solve of the inverse iteration.
+u = 0 to rtol 1e-10 (the first inner solve of the inverse iteration) and
+the true relative residual ||b - A_sigma u|| / ||b|| of the returned u (the
+recursively updated residual drifts from it by the rounding of the updates).
 Usage:  python tests/golden/make_golden.py 1 2 [3 4] [batch] [pcg2 pcg4]
 """
 import json
@@ -72,7 +74,8 @@ def pcg_count(c):
     b = P.M @ np.ones(P.grid.n)
     res = pcg(lambda v: P.A_sigma @ v, b, P.preconditioner(True).apply, rtol=1e-10, maxit=2000)
     assert res.status == "ok", res.status
-    return int(res.iters)
+    true_rel = float(np.linalg.norm(b - P.A_sigma @ res.x) / np.linalg.norm(b))
+    return int(res.iters), true_rel
 
 
 if __name__ == "__main__":
@@ -81,9 +84,9 @@ if __name__ == "__main__":
             c = int(arg[3:])
             path = os.path.join(HERE, f"oracle_config{c}.json")
             d = json.load(open(path))
-            d["pcg_iters_M1"] = pcg_count(c)
+            d["pcg_iters_M1"], d["pcg_true_relres_M1"] = pcg_count(c)
             json.dump(d, open(path, "w"), indent=1)
-            print("pcg", c, d["pcg_iters_M1"], flush=True)
+            print("pcg", c, d["pcg_iters_M1"], d["pcg_true_relres_M1"], flush=True)
             continue
         if arg == "batch":
             json.dump(golden_batch(), open(os.path.join(HERE, "oracle_batch.json"), "w"), indent=1)

@@ -6,22 +6,25 @@ or FP64 block-chain ones).
 
 Checks against the oracle at full size:
 - the preconditioner z = M_AS,2^{-1} r element by element against the
-  oracle's AdditiveSchwarz (exact local solves) on a seeded r: 1e-11
+  oracle's AdditiveSchwarz (exact local solves) on a seeded r, also split
+  into its local part (AS1) and its coarse part: the local part to 1e-11
   relative in 2-norm with FP64 local solves, 3e-2 with the single bf16
   inverse (its entries carry 2^-9 relative rounding; the bar of the small
-  cases).  For bf16 also node by node against a model of the bf16
-  arithmetic written here from the definition: the inverse of the unclipped
-  box and the restricted residuals rounded to bf16 as the device rounds them
-  (double -> float -> bf16, both to nearest even), their products exact, plus
-  the oracle's coarse correction.  On every node covered by interior
-  subdomains only, the device must agree with that model to the FP32
+  cases); the coarse part to 32 kappa(A_0) u (see _precond_fullsize).  For
+  bf16 also node by node against a model of the bf16 arithmetic written here
+  from the definition: the inverse of the unclipped box and the restricted
+  residuals rounded to bf16 as the device rounds them (correctly rounded from
+  FP64), their products exact.  On every node covered by interior subdomains
+  only, the device's local part must agree with that model to the FP32
   accumulation bound 4 sqrt(m) 2^-24 sum_k |r~_k||B~_ke| (m terms per output),
   which a wrong tile, K split or row order exceeds by orders of magnitude;
 - PCG iteration counts of A_sigma u = M 1 from u = 0 to rtol 1e-10 against
   the oracle's count with exact local solves (stored by make_golden.py):
   +-1 (2-D) / +-2 (3-D) with FP64 local solves; with bf16 local solves at
   most 15% + 2 above it (the rounded preconditioner is a perturbation of the
-  exact one; a broken tile would cost far more or break CG down);
+  exact one; a broken tile would cost far more or break CG down); the true
+  residual at most rtol + 1.5 x the oracle's own true residual (the FP64
+  residual-update floor, 3.8e-8 relative at config 2);
 - config 2: the eigenvector against the oracle's own eigenvector (banded
   Cholesky inverse iteration, recomputed here): ||x - x_ref||_M <= 1e-8 and
   the eigenvalue to 1e-10 relative, for bf16 and FP64 local solves;
@@ -131,17 +134,20 @@ def _check_eigenpair(torch, c, prec, sigma, out, xd, prob):
 
 
 def _bf16(a):
-    """Round to bf16 as the device does: double -> float (nearest even), then
-    float -> bf16 (nearest even on the upper 16 bits); returned as float64."""
-    f = np.asarray(a, dtype=np.float64).astype(np.float32)
-    u = f.view(np.uint32).astype(np.uint64)
-    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
-    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+    """Round to bf16 as the device does: the FP64 value correctly rounded to 8
+    significant bits (nearest, ties to even), in one step from double.  (The
+    device's double -> float -> bf16 conversion compiles to one correctly
+    rounded conversion: the float step rounds to odd.)  Returned as float64."""
+    u = np.ascontiguousarray(a, dtype=np.float64).view(np.uint64)
+    u = ((u + np.uint64((1 << 44) - 1) + ((u >> np.uint64(45)) & np.uint64(1)))
+         >> np.uint64(45)) << np.uint64(45)
+    return u.view(np.float64)
 
 
-def _bf16_model_check(P, AS, r, z):
-    """Node-by-node agreement of the device's bf16 local solves with the bf16
-    model on the nodes that only interior (unclipped) subdomains cover."""
+def _bf16_model_check(P, zloc):
+    """Node-by-node agreement of the device's bf16 local solves (the additive
+    Schwarz sum without the coarse part) with the bf16 model on the nodes that
+    only interior (unclipped) subdomains cover."""
     n = P.grid.n
     m = max(s.size for s in P.subs)
     inter = [i for i, s in enumerate(P.subs) if s.size == m]
@@ -150,6 +156,7 @@ def _bf16_model_check(P, AS, r, z):
     Binv = np.linalg.inv(Ab)
     Bt = _bf16(0.5 * (Binv + Binv.T))
     del Binv, Ab
+    r = _RVEC[P.grid.n]
     R = np.stack([_bf16(r[P.subs[i]]) for i in inter])
     Z, Zabs = R @ Bt, np.abs(R) @ np.abs(Bt)
     zl, za = np.zeros(n), np.zeros(n)
@@ -160,34 +167,56 @@ def _bf16_model_check(P, AS, r, z):
     for i, s in enumerate(P.subs):
         if s.size != m:
             clipped[s] = True
-    coarse = AS.R0T @ AS.coarse_solve(AS.R0T.T @ r)
-    ze = zl + coarse
-    bound = 4.0 * math.sqrt(m) * 2.0 ** -24 * za + 1e-12 * np.max(np.abs(coarse))
+    # FP32 accumulation of m products; 1e-13 max|z| for forming zloc on the host
+    bound = 4.0 * math.sqrt(m) * 2.0 ** -24 * za + 1e-13 * np.max(np.abs(zl))
     mask = ~clipped
-    assert mask.sum() > 0.9 * n
-    err = np.abs(z - ze)
+    assert mask.sum() > 0.5 * n
+    err = np.abs(zloc - zl)
     bad = np.flatnonzero(mask & (err > bound))
     assert bad.size == 0, (bad[:10], err[bad[:10]], bound[bad[:10]])
-    return np.median(np.abs(zl - (AS.apply(r) - coarse))[mask]), np.median(bound[mask])
+
+
+_RVEC = {}
 
 
 def _precond_fullsize(torch, c, prec):
+    """z = M_AS,2^{-1} r and its two parts (the local solves, ddeig_apply_schwarz
+    AS1; the coarse correction, COARSE) against the oracle.  The local part
+    meets the bar of the precision; the coarse part R_0^T A_0^{-1} R_0 r is as
+    sensitive to rounding as A_0 is ill-conditioned (A_0 annihilates the
+    periodic ground state up to lambda_1 - sigma), so it is held to
+    32 kappa(A_0) u of its norm: 32 u bounds the relative rounding of the
+    assembled A_0 (two summation orders of R_0^T A_sigma R_0 already differ by
+    about 22 u at config 2), kappa(A_0) from the oracle's A_0."""
     import paper_2311_08757_amd as dd
     P, AS = _oracle_problem(c)
     prob = _assemble(c, prec)
     assert prob.n_dof == P.grid.n
     dd.set_shift(prob, P.sigma, P.cell["psi"])
     r = W.random_vector(P.grid.n, 7)
-    z = torch.empty(P.grid.n, dtype=torch.float64, device="cuda")
+    _RVEC[P.grid.n] = r
+    rd = _dev(torch, r)
+    z, zl, zc = (torch.empty(P.grid.n, dtype=torch.float64, device="cuda") for _ in range(3))
     print(f"# config {c} apply_precond {prec} n={P.grid.n}", flush=True)
-    dd.apply_precond(prob, _dev(torch, r), z)
+    dd.apply_precond(prob, rd, z)
+    dd.apply_schwarz(prob, "as1", rd, zl)
+    dd.apply_schwarz(prob, "coarse", rd, zc)
     torch.cuda.synchronize()
-    zg = z.cpu().numpy()
+    zg, zlg, zcg = z.cpu().numpy(), zl.cpu().numpy(), zc.cpu().numpy()
+    cref = AS.R0T @ AS.coarse_solve(AS.R0T.T @ r)
     zr = AS.apply(r)
+    lref = zr - cref
+    ev = np.linalg.eigvalsh(AS.A0)
+    bar_c = 32.0 * (ev[-1] / ev[0]) * 2.0 ** -53 * np.linalg.norm(cref)
+    assert np.linalg.norm(zcg - cref) <= bar_c
     tol = {"fp64": 1e-11, "bf16": 3e-2}[prec]
-    assert np.linalg.norm(zg - zr) <= tol * np.linalg.norm(zr)
+    assert np.linalg.norm(zlg - lref) <= tol * np.linalg.norm(lref)
+    assert np.linalg.norm(zg - zr) <= tol * np.linalg.norm(zr) + bar_c
+    # the bench's fused launch (coarse space riding in the dense launches)
+    # against the separate parts: the same arithmetic, bitwise up to the final sum
+    assert np.max(np.abs(zg - (zlg + zcg))) <= 1e-13 * np.max(np.abs(zg))
     if prec == "bf16":
-        _bf16_model_check(P, AS, r, zg)
+        _bf16_model_check(P, zg - zcg)
 
 
 def _pcg_count(torch, c, prec):
@@ -202,7 +231,11 @@ def _pcg_count(torch, c, prec):
     x = torch.zeros_like(one)
     print(f"# config {c} pcg {prec}", flush=True)
     out = dd.pcg_solve(prob, b, x, rtol=1e-10, maxit=3000)
-    assert out["true_relres"] <= 1.1e-10
+    # the recursively updated residual drifts from b - A_sigma x by the rounding
+    # of the updates (u ||A|| ||x|| with ||x|| ~ ||b|| / (lambda_1 - sigma)); the
+    # oracle's own FP64 PCG ends at the same floor, so the true residual is held
+    # to rtol or to that floor
+    assert out["true_relres"] <= 1.1e-10 + 1.5 * gd["pcg_true_relres_M1"]
     if prec == "fp64":
         assert abs(out["iters"] - ref) <= (1 if W.config(c)["p"] + W.config(c)["q"] == 2 else 2)
     else:
