@@ -16,7 +16,9 @@
 //     step's values are gathered into LDS for the workgroup's rows and a halo
 //     of one slice line on each side, which covers every coupling tap.
 //   k_cm_mm: the product W_i g on v_mfma_f32_32x32x2f32: workgroup = 128 rows
-//     x 32 members x one K chunk of 64, four waves of 32 x 32 tiles; W_i rows
+//     x 64 members x one K chunk of 64, four waves of 32 rows x 64 members (two
+//     32 x 32 tiles sharing the W_i fragment; the second is skipped when the
+//     job has at most 32 members), so W_i is read once per class; W_i rows
 //     of the chunk and g are staged through LDS with coalesced loads (W_i is
 //     symmetric, so its rows are the columns of the A operand), the partial
 //     tile goes out through LDS so that every wave writes whole rows.
@@ -32,9 +34,11 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 constexpr int kCmRows = 128;    // output rows per product workgroup
 constexpr int kCmKc = 64;       // K chunk per product workgroup
-constexpr int kCmMembers = 32;  // members per job (the MFMA N dimension)
+constexpr int kCmMembers = 64;  // members per job: two 32-wide MFMA tiles per wave
 constexpr int kCmRb = 256;      // rows per right-hand-side workgroup
 constexpr int kCmHalo = 256;    // largest halo (one slice line + 1) of the rhs kernel
+constexpr int kCmMaxKc = 32;    // largest number of K chunks (slices of at most 2048 nodes)
+constexpr int kCmLdw = kCmRows + 4;  // LDS row of the staged W_i chunk (bank offset per row)
 
 // FP64 factors (rows of b values) -> FP32 rows of ldw values, zero padded.
 __global__ void k_pad_float(const double* __restrict__ src, float* __restrict__ dst, long rows,
@@ -57,16 +61,25 @@ void launch_pad_float(const double* src, float* dst, long rows, int b, int ldw, 
 
 int chain_mfma_members() { return kCmMembers; }
 
-bool chain_mfma_ok(int b, int m0) { return m0 + 1 <= kCmHalo && b >= 1; }
+bool chain_mfma_ok(int b, int m0) {
+  return m0 + 1 <= kCmHalo && b >= 1 && b <= kCmMaxKc * kCmKc;
+}
 
 // Previous step's value of row r of member (slot) m: the sum of the nkc K-chunk
-// partials of its class (b / 64 rounded up) in chunk order, subtracted from t
-// (backward, sub != nullptr).
+// partials of its class (b / 64 rounded up, at most kCmMaxKc) in chunk order,
+// subtracted from t (backward, sub != nullptr).  Every load is issued before
+// the first add (clamped addresses, masked values), so their latencies overlap.
 __device__ inline double cm_prev(const float* __restrict__ part, int nkc, int mtot, int bmax,
                                  int slot, int r, const double* sub) {
-  double v = 0.0;
-  for (int kc = 0; kc < nkc; ++kc) v += (double)part[((long)kc * mtot + slot) * bmax + r];
-  return sub != nullptr ? *sub - v : v;
+  float v[kCmMaxKc];
+#pragma unroll
+  for (int kc = 0; kc < kCmMaxKc; ++kc)
+    v[kc] = part[((long)min(kc, nkc - 1) * mtot + slot) * bmax + r];
+  double acc = 0.0;
+#pragma unroll
+  for (int kc = 0; kc < kCmMaxKc; ++kc)
+    if (kc < nkc) acc += (double)v[kc];
+  return sub != nullptr ? *sub - acc : acc;
 }
 
 // Right-hand sides of sweep step i.  Grid: (row blocks, jobs, members of a job).
@@ -144,8 +157,9 @@ __global__ void __launch_bounds__(kBlock) k_cm_mm(const TypeDev* __restrict__ ty
                                                   const float* __restrict__ G,
                                                   float* __restrict__ part,
                                                   const PcgState* __restrict__ st) {
-  // W_i rows of the chunk [k][row]; reused for the output tile [member][row]
-  __shared__ __attribute__((aligned(16))) float ws[kCmKc * kCmRows];
+  // W_i rows of the chunk [k][row] (row stride kCmLdw); reused for the output
+  // tile [row][member] (row stride kCmMembers + 1)
+  __shared__ __attribute__((aligned(16))) float ws[kCmKc * kCmLdw];
   __shared__ float gs[kCmKc][kCmMembers + 1];
   if (st != nullptr && st->done) return;
   const ChainJob jb = jobs[blockIdx.z];
@@ -154,49 +168,82 @@ __global__ void __launch_bounds__(kBlock) k_cm_mm(const TypeDev* __restrict__ ty
   const int R0 = blockIdx.x * kCmRows, K0 = blockIdx.y * kCmKc;
   if (R0 >= b || K0 >= b) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // W_i through an address-space-1 pointer: its loads are global loads (a flat
+  // load would also hold up the LDS wait counter)
+  typedef __attribute__((address_space(1))) const f32x4* gvec4;
   const float* Wi = td.W32 + (long)i * b * ldw;
-  // W_i rows K0.. of the chunk, columns R0..R0+127: 16-byte loads (ldw and R0
-  // are multiples of 4; columns b..ldw-1 of the padded rows are zero)
+  // W_i rows K0.. of the chunk, columns R0..R0+127 (16-byte loads: ldw and R0
+  // are multiples of 4; columns b..ldw-1 of the padded rows are zero), and g
+  // of the job's members on the chunk.  All loads are issued before any is
+  // used: out-of-range ones read a valid address and are masked afterwards.
+  constexpr int NW = (kCmKc * kCmRows / 4) / kBlock, NG = (kCmKc * kCmMembers) / kBlock;
+  f32x4 wv[NW];
+  float gv[NG];
 #pragma unroll
-  for (int q = 0; q < (kCmKc * kCmRows / 4) / kBlock; ++q) {
+  for (int q = 0; q < NW; ++q) {
     const int idx = tid + q * kBlock;
-    const int k = idx / (kCmRows / 4), c4 = idx - k * (kCmRows / 4);
-    const int col = R0 + 4 * c4;
-    f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (K0 + k < b && col < ldw) v = *reinterpret_cast<const f32x4*>(Wi + (long)(K0 + k) * ldw + col);
-    *reinterpret_cast<f32x4*>(&ws[k * kCmRows + 4 * c4]) = v;
+    const int k = idx / (kCmRows / 4), col = R0 + 4 * (idx % (kCmRows / 4));
+    const bool ok = K0 + k < b && col < ldw;
+    wv[q] = *(gvec4)(Wi + (ok ? (long)(K0 + k) * ldw + col : 0));
   }
-  // g of the job's members on the chunk, transposed to [k][member]
 #pragma unroll
-  for (int q = 0; q < (kCmKc * kCmMembers) / kBlock; ++q) {
+  for (int q = 0; q < NG; ++q) {
     const int idx = tid + q * kBlock;
-    const int j = idx / kCmKc, k = idx - j * kCmKc;
-    gs[k][j] = (j < jb.nm && K0 + k < b) ? G[(long)(jb.mg0 + j) * bmax + K0 + k] : 0.0f;
+    const int j = idx / kCmKc, k = idx % kCmKc;
+    const bool ok = j < jb.nm && K0 + k < b;
+    gv[q] = G[ok ? (long)(jb.mg0 + j) * bmax + K0 + k : 0];
+  }
+#pragma unroll
+  for (int q = 0; q < NW; ++q) {
+    const int idx = tid + q * kBlock;
+    const int k = idx / (kCmRows / 4), c4 = idx % (kCmRows / 4);
+    const bool ok = K0 + k < b && R0 + 4 * c4 < ldw;
+    const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+    *reinterpret_cast<f32x4*>(&ws[k * kCmLdw + 4 * c4]) = ok ? wv[q] : zero;
+  }
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    const int idx = tid + q * kBlock;
+    const int j = idx / kCmKc, k = idx % kCmKc;
+    gs[k][j] = (j < jb.nm && K0 + k < b) ? gv[q] : 0.0f;
   }
   __syncthreads();
-  f32x16 acc;
+  f32x16 acc[2];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) acc[e] = 0.0f;
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[t][e] = 0.0f;
   const int kh = lane >> 5, l32 = lane & 31;
+  if (jb.nm > 32) {
 #pragma unroll 8
-  for (int kk = 0; kk < kCmKc; kk += 2) {
-    const float a = ws[(kk + kh) * kCmRows + w * 32 + l32];
-    const float bv = gs[kk + kh][l32];
-    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, acc, 0, 0, 0);
+    for (int kk = 0; kk < kCmKc; kk += 2) {
+      const float a = ws[(kk + kh) * kCmLdw + w * 32 + l32];
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, gs[kk + kh][l32], acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, gs[kk + kh][32 + l32], acc[1], 0, 0, 0);
+    }
+  } else {
+#pragma unroll 8
+    for (int kk = 0; kk < kCmKc; kk += 2) {
+      const float a = ws[(kk + kh) * kCmLdw + w * 32 + l32];
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, gs[kk + kh][l32], acc[0], 0, 0, 0);
+    }
   }
   __syncthreads();
   // accumulator layout: lane l, element e holds row 8 (e / 4) + 4 (l / 32) + e % 4
-  // of the wave's 32 rows and member l % 32
+  // of the wave's 32 rows and member l % 32 of the tile
+  constexpr int LO = kCmMembers + 1;
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int row = w * 32 + 8 * (e >> 2) + 4 * kh + (e & 3);
-    ws[l32 * kCmRows + row] = acc[e];
-  }
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int row = w * 32 + 8 * (e >> 2) + 4 * kh + (e & 3);
+      ws[row * LO + 32 * t + l32] = acc[t][e];
+    }
   __syncthreads();
   for (int idx = tid; idx < kCmMembers * kCmRows; idx += kBlock) {
-    const int j = idx / kCmRows, rr = idx - j * kCmRows;
+    const int j = idx / kCmRows, rr = idx % kCmRows;
     if (j < jb.nm && R0 + rr < b)
-      part[((long)blockIdx.y * mtot + jb.mg0 + j) * bmax + R0 + rr] = ws[j * kCmRows + rr];
+      part[((long)blockIdx.y * mtot + jb.mg0 + j) * bmax + R0 + rr] = ws[rr * LO + j];
   }
 }
 
