@@ -334,6 +334,18 @@ ddeig_status ddeig_profile_iteration(ddeig_problem* P, const double* b, int reps
 ddeig_status ddeig_potential_form(ddeig_problem* P, int space, const ddeig_potential* W,
                                   const double* x, const double* y, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same form
+ * out = x^T M_W y as ddeig_potential_form (same arguments, layouts and
+ * errors), computed without any allocation.  Its only device memory besides x
+ * and y is a static 1 MiB array per GPU held by the library until the process
+ * ends (partial sums, W's description, and a QUAD_TABLE weight of at most
+ * 129024 values; a larger table returns DDEIG_EINVAL).  Calls that overlap on
+ * one GPU (other threads or streams) race on that array.  Synchronises the
+ * library stream. */
+ddeig_status ddeig_potential_form_noalloc(ddeig_problem* P, int space, const ddeig_potential* W,
+                                          const double* x, const double* y, double* out);
+
 /* Batches of independent problems (e.g. many domain lengths L or potentials
  * at once).  The instances keep their own shift, local inverse, coarse
  * space and CG state; every kernel of a PCG iteration (§3,

@@ -835,6 +835,10 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
   P->opt = o;
   P->stream = static_cast<hipStream_t>(hip_stream);
   try {
+    check_hip(hipGetDevice(&P->device), "hipGetDevice");
+    // the scratch of the no-allocation entry point on this device (looked up
+    // once per device; a failure is reported by that entry point)
+    (void)ddeig::noalloc_init(P->device);
     const hipStream_t s = P->stream;
     const long tt = g.tsize * g.ntaps;
     P->tabK = dalloc<double>(P, tt);
@@ -1643,6 +1647,29 @@ ddeig_status ddeig_potential_form(ddeig_problem* P, int space, const ddeig_poten
   launch_dot(x, P->tmpv, len, r, s);
   check_launch("potential form");
   *out = host_sum(P, r);
+  return DDEIG_OK;
+  API_GUARD_END
+}
+
+ddeig_status ddeig_potential_form_noalloc(ddeig_problem* P, int space, const ddeig_potential* W,
+                                          const double* x, const double* y, double* out) {
+  if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
+  if (!W || !out) return set_error(DDEIG_EINVAL, "potential or out is NULL");
+  if (space != 0 && space != 1) return set_error(DDEIG_EINVAL, "space must be 0 or 1");
+  if (validate_vec(x, "x") || validate_vec(y, "y")) return DDEIG_EINVAL;
+  ddeig::VSpec ws{};
+  {
+    const ddeig_status sv = make_vspec(W, P->g.p, P->g.q, P->g.ell, ws);
+    if (sv != DDEIG_OK) return sv;
+    const ddeig_status st = check_quad_table(W, quad_table_len(P->g.p, P->g.q, P->g.ne, P->g.ell));
+    if (st != DDEIG_OK) return st;
+  }
+  API_GUARD_BEGIN
+  std::string err;
+  const bool tab = W->kind == DDEIG_V_QUAD_TABLE;
+  const ddeig_status st = ddeig::noalloc_form_checked(P, space, ws, tab ? W->table : nullptr,
+                                                      tab ? W->table_len : 0, x, y, out, err);
+  if (st != DDEIG_OK) return set_error(st, err);
   return DDEIG_OK;
   API_GUARD_END
 }

@@ -306,6 +306,7 @@ struct ddeig_problem {
   int delta;
   ddeig_options opt;
   hipStream_t stream;
+  int device = 0;  // the device current at ddeig_assemble
   // second stream (default priority) for work that overlaps the local solves
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -544,5 +545,11 @@ void launch_gm_update(const ddeig_problem* P, int nv, const double* Z, long ldv,
                       double* x, hipStream_t s);
 
 void check_hip(hipError_t e, const char* what);
+
+// The potential form without device allocation (k_noalloc.hip).
+hipError_t noalloc_init(int dev);
+ddeig_status noalloc_form_checked(ddeig_problem* P, int space, const VSpec& wspec, const double* table,
+                                  long table_len, const double* x, const double* y, double* out,
+                                  std::string& err);
 
 }  // namespace ddeig

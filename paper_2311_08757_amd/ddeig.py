@@ -71,7 +71,8 @@ class LopcgInfo(ctypes.Structure):
 EXPORTS = ["ddeig_assemble", "ddeig_cell_shift", "ddeig_set_shift", "ddeig_apply_op",
            "ddeig_apply_precond", "ddeig_apply_schwarz", "ddeig_stationary_ras",
            "ddeig_gmres_solve", "ddeig_pcg_solve", "ddeig_inverse_iteration", "ddeig_lopcg",
-           "ddeig_profile_kernel", "ddeig_profile_iteration", "ddeig_potential_form", "ddeig_batch_create",
+           "ddeig_profile_kernel", "ddeig_profile_iteration", "ddeig_potential_form",
+           "ddeig_potential_form_noalloc", "ddeig_batch_create",
            "ddeig_batch_query", "ddeig_batch_pcg_solve", "ddeig_batch_inverse_iteration",
            "ddeig_batch_destroy", "ddeig_query", "ddeig_destroy", "ddeig_status_string",
            "ddeig_last_error"]
@@ -111,6 +112,8 @@ def load_library(path=LIB_PATH):
     lib.ddeig_profile_kernel.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, dp, dp]
     lib.ddeig_profile_iteration.argtypes = [P, P, ctypes.c_int, dp]
     lib.ddeig_potential_form.argtypes = [P, ctypes.c_int, ctypes.POINTER(Potential), P, P, dp]
+    lib.ddeig_potential_form_noalloc.argtypes = [P, ctypes.c_int, ctypes.POINTER(Potential), P, P,
+                                                 dp]
     PP = ctypes.POINTER(ctypes.c_void_p)
     lib.ddeig_batch_create.argtypes = [PP, ctypes.c_int, ctypes.c_int, PP]
     lib.ddeig_batch_query.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
@@ -407,6 +410,20 @@ def potential_form(prob, W, x, y, space="global"):
                                   _ptr(y, n, "y"), ctypes.byref(out))
     del keep
     _check(st, "ddeig_potential_form")
+    return out.value
+
+
+def potential_form_noalloc(prob, W, x, y, space="global"):
+    """ddeig_potential_form_noalloc: x^T M_W y like potential_form, without device allocation."""
+    lib = load_library()
+    sp = {"global": 0, "cell": 1}[space] if isinstance(space, str) else int(space)
+    n = prob.n_cell if sp == 1 else prob.n_dof
+    Ws, keep = _potential(W)
+    out = ctypes.c_double()
+    st = lib.ddeig_potential_form_noalloc(prob.handle, sp, ctypes.byref(Ws), _ptr(x, n, "x"),
+                                          _ptr(y, n, "y"), ctypes.byref(out))
+    del keep
+    _check(st, "ddeig_potential_form_noalloc")
     return out.value
 
 
