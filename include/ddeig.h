@@ -334,6 +334,31 @@ ddeig_status ddeig_profile_iteration(ddeig_problem* P, const double* b, int reps
 ddeig_status ddeig_potential_form(ddeig_problem* P, int space, const ddeig_potential* W,
                                   const double* x, const double* y, double* out);
 
+/* Derivatives with respect to the Fourier parameters theta = (a_1..a_T,
+ * phi_1..phi_T) of the problem's own SEP_FOURIER or FOURIER2 potential (beyond
+ * the paper).  A = K + M_V (§2, eq:discrete-weak-form) is linear in V, so
+ * dA/dtheta_j = M_{dV/dtheta_j} with the quadrature of M_V, where
+ * dV/da_t = cos(arg_t) env and dV/dphi_t = -a_t sin(arg_t) env (the t-th term
+ * of the potential without, and with its amplitude, and its argument advanced
+ * by pi / 2).  All 2T forms and x^T M y come from one element-walking kernel.
+ * grad: host array of ngrad = 2T values (a_1..a_T, then phi_1..phi_T); other
+ * kinds of potential or another ngrad return DDEIG_EINVAL.  Synchronise.
+ *
+ * ddeig_eig_grad: dlambda/dtheta = x^T M_{dV} x / x^T M x (Hellmann-Feynman)
+ *   for the ground state x (any scaling, n_dof device values) of A x = lambda M x.
+ * ddeig_shift_grad: dsigma/dtheta = psi^T M#_{dV} psi / psi^T M# psi for the
+ *   cell eigenvector of the last cell_shift (eq:cell-problem; DDEIG_ESTATE
+ *   without a shift or after set_shift without psi).
+ * ddeig_solve_grad: for u = A_sigma^{-1} b (b independent of theta) and a
+ *   scalar l(u) with w = A_sigma^{-1} dl/du (the adjoint solve: A_sigma is
+ *   symmetric, so w comes from ddeig_pcg_solve with the same preconditioner),
+ *   dl/dtheta = -(w^T M_{dV} u - dsigma/dtheta w^T M u), the shift moving with
+ *   theta.  u, w: n_dof device values. */
+ddeig_status ddeig_eig_grad(ddeig_problem* P, const double* x, double* grad, int ngrad);
+ddeig_status ddeig_shift_grad(ddeig_problem* P, double* grad, int ngrad);
+ddeig_status ddeig_solve_grad(ddeig_problem* P, const double* u, const double* w, double* grad,
+                              int ngrad);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops, harnesses that forbid hipMalloc): the same form
  * out = x^T M_W y as ddeig_potential_form (same arguments, layouts and
@@ -392,6 +417,18 @@ ddeig_status ddeig_batch_pcg_solve(ddeig_batch* B, const double* const* b, doubl
 ddeig_status ddeig_batch_inverse_iteration(ddeig_batch* B, double* const* x, double tol_x,
                                            int maxit_outer, double rtol_inner, int maxit_inner,
                                            ddeig_eig_info* info);
+
+/* The derivatives above for every instance of a batch in one grouped launch
+ * (all instances must have T terms; ngrad = 2T).  x, u, w: host arrays of n
+ * device pointers; grad: host array of n x 2T values, instance-major.
+ * ddeig_batch_eig_grad: dlambda_j/dtheta_j from the eigenvectors x[j] (e.g.
+ * those of ddeig_batch_inverse_iteration).  ddeig_batch_solve_grad: the
+ * linear-solve gradients for u[j] = A_sigma,j^{-1} b[j] and the adjoint
+ * solutions w[j] (e.g. from ddeig_batch_pcg_solve on dl/du[j]). */
+ddeig_status ddeig_batch_eig_grad(ddeig_batch* B, const double* const* x, double* grad,
+                                  int ngrad);
+ddeig_status ddeig_batch_solve_grad(ddeig_batch* B, const double* const* u, const double* const* w,
+                                    double* grad, int ngrad);
 
 void ddeig_batch_destroy(ddeig_batch* B);
 

@@ -7,12 +7,14 @@ from .ddeig import (assemble, cell_shift, set_shift, apply_op, apply_precond, pc
                     apply_schwarz, stationary_ras, gmres_solve, PREC_KINDS,
                     inverse_iteration, lopcg, profile_kernel, profile_iteration,
                     ITERATION_PARTS, potential_form, potential_form_noalloc, query,
+                    eig_grad, shift_grad, solve_grad, batch_eig_grad, batch_solve_grad,
                     Batch, batch_create, batch_query, batch_pcg_solve, batch_inverse_iteration, status_string, load_library, DdeigError, Problem,
                     EXPORTS, LIB_PATH)
 
 __all__ = ["assemble", "cell_shift", "set_shift", "apply_op", "apply_precond", "pcg_solve",
            "apply_schwarz", "stationary_ras", "gmres_solve", "PREC_KINDS",
            "inverse_iteration", "lopcg", "profile_kernel", "profile_iteration",
-           "ITERATION_PARTS", "potential_form", "potential_form_noalloc", "query", "Batch", "batch_create",
+           "ITERATION_PARTS", "potential_form", "potential_form_noalloc", "eig_grad",
+           "shift_grad", "solve_grad", "batch_eig_grad", "batch_solve_grad", "query", "Batch", "batch_create",
            "batch_query", "batch_pcg_solve", "batch_inverse_iteration", "status_string", "load_library", "DdeigError",
            "Problem", "EXPORTS", "LIB_PATH"]

@@ -19,9 +19,12 @@ assembled with the same quadrature.  With that:
   preconditioner, and
       dl/dtheta_j = -w^T (M_{dV_j} - dsigma/dtheta_j M) u,   dl/db = w.
 
-Derivative potentials need no new kernel: dV/da_t is term t alone with unit
-amplitude, and dV/dphi_t = -a_t sin(...) is term t with its phase advanced by
-pi/2.  Every form x^T M_W y runs in ddeig_potential_form.
+All 2T derivative forms (and the mass form) of a vector pair come from one
+element-walking kernel of the library (ddeig_eig_grad, ddeig_shift_grad,
+ddeig_solve_grad, and their batch versions over all instances of a batch in
+one grouped launch); this module only calls them.  dpotential() gives dV/dtheta
+as a potential dict (term t with unit amplitude, or with its phase advanced by
+pi/2) for ddeig_potential_form.
 """
 import math
 
@@ -67,36 +70,21 @@ def dpotential(spec, j):
     return one
 
 
-def _mass_spec():
-    return {"kind": "const", "c": 1.0}
-
-
-def forms(prob, spec, x, y, space="global"):
-    """(x^T M_{dV_j} y for every parameter j, x^T M y)."""
-    T = len(spec["a"])
-    vals = np.array([_dd.potential_form(prob, dpotential(spec, j), x, y, space)
-                     for j in range(2 * T)])
-    return vals, _dd.potential_form(prob, _mass_spec(), x, y, space)
-
-
 def eigenvalue_grad(prob, spec, x):
-    """dlambda/dtheta for the ground state x (any scaling) of the problem."""
-    vals, xmx = forms(prob, spec, x, x)
-    return vals / xmx
+    """dlambda/dtheta for the ground state x (any scaling) of the problem
+    (ddeig_eig_grad; spec must be the problem's own potential)."""
+    return _dd.eig_grad(prob, x)
 
 
-def shift_grad(prob, spec, psi):
-    """dsigma/dtheta from the cell eigenvector psi (n_cell values, cell order)."""
-    if not isinstance(psi, torch.Tensor):
-        psi = torch.as_tensor(np.ascontiguousarray(psi, dtype=np.float64), device="cuda")
-    vals, pmp = forms(prob, spec, psi, psi, space="cell")
-    return vals / pmp
+def shift_grad(prob, spec, psi=None):
+    """dsigma/dtheta from the problem's cell eigenvector (ddeig_shift_grad)."""
+    return _dd.shift_grad(prob)
 
 
-def solve_grad(prob, spec, u, w, dsigma):
-    """dl/dtheta = -(w^T M_{dV} u - dsigma w^T M u) for u = A_sigma^{-1} b, A_sigma w = dl/du."""
-    vals, wmu = forms(prob, spec, w, u)
-    return -(vals - np.asarray(dsigma) * wmu)
+def solve_grad(prob, spec, u, w, dsigma=None):
+    """dl/dtheta = -(w^T M_{dV} u - dsigma w^T M u) for u = A_sigma^{-1} b,
+    A_sigma w = dl/du (ddeig_solve_grad, which forms dsigma itself)."""
+    return _dd.solve_grad(prob, u, w)
 
 
 def _assemble(geom, spec, opts):
@@ -138,7 +126,7 @@ class EigenvalueFn(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        grad = eigenvalue_grad(ctx.prob, ctx.spec, ctx.x)
+        grad = _dd.eig_grad(ctx.prob, ctx.x)
         gt = torch.as_tensor(grad, dtype=torch.float64, device=g.device)
         return g * gt, None, None
 
@@ -172,13 +160,95 @@ class ShiftedSolveFn(torch.autograd.Function):
         g = gu.detach().to(torch.float64).contiguous()
         w = torch.zeros_like(g)
         _dd.pcg_solve(prob, g, w, rtol=ctx.rtol, maxit=ctx.maxit)
-        ds = shift_grad(prob, ctx.spec, ctx.psi)
-        grad = solve_grad(prob, ctx.spec, ctx.u, w, ds)
+        grad = _dd.solve_grad(prob, ctx.u, w)
         gtheta = torch.as_tensor(grad, dtype=torch.float64, device=ctx.theta_device)
         return (gtheta if ctx.needs_input_grad[0] else None,
                 w if ctx.needs_input_grad[1] else None, None, None)
 
 
+def _batch_problems(thetas, geoms, opts):
+    specs = [with_params(g["V"], t) for g, t in zip(geoms, thetas)]
+    probs = [_assemble(g, sp, opts)[0] for g, sp in zip(geoms, specs)]
+    batch = _dd.batch_create(probs, graphs=opts.get("graphs", True))
+    return specs, probs, batch
+
+
+class BatchEigenvaluesFn(torch.autograd.Function):
+    """lambda_j(theta_j) for independent instances solved as one batch.
+
+    thetas: (n, 2T) tensor, row j the parameters of instance j; geoms: list of
+    n geometry dicts (as for EigenvalueFn; 2-D with dense local solves, as the
+    batch requires).  Forward: every instance's cell shift and set-up, then
+    ddeig_batch_inverse_iteration with grouped launches; backward: the
+    Hellmann-Feynman forms of all instances in one grouped launch
+    (ddeig_batch_eig_grad).  opts: local_prec (default bf16), tol_x,
+    rtol_inner, maxit_inner, maxit_outer, graphs.  Returns an (n,) tensor.
+    """
+
+    @staticmethod
+    def forward(ctx, thetas, geoms, opts=None):
+        opts = dict(opts or {})
+        opts.setdefault("local_prec", "bf16")
+        th = thetas.detach().to("cpu", torch.float64).numpy()
+        if th.ndim != 2 or th.shape[0] != len(geoms):
+            raise ValueError("thetas must be (n instances, 2T)")
+        specs, probs, batch = _batch_problems(th, geoms, opts)
+        xs = [torch.zeros(p.n_dof, dtype=torch.float64, device="cuda") for p in probs]
+        _, info = _dd.batch_inverse_iteration(batch, xs, tol_x=opts.get("tol_x", 1e-11),
+                                              maxit_outer=opts.get("maxit_outer", 200),
+                                              rtol_inner=opts.get("rtol_inner", 1e-12),
+                                              maxit_inner=opts.get("maxit_inner", 3000))
+        ctx.batch, ctx.xs = batch, xs
+        ctx.info = info
+        return torch.tensor([f["lam"] for f in info], dtype=torch.float64, device=thetas.device)
+
+    @staticmethod
+    def backward(ctx, g):
+        grad = _dd.batch_eig_grad(ctx.batch, ctx.xs)
+        gt = torch.as_tensor(grad, dtype=torch.float64, device=g.device)
+        return g[:, None] * gt, None, None
+
+
+class BatchShiftedSolveFn(torch.autograd.Function):
+    """u_j = A_sigma,j(theta_j)^{-1} b_j for independent instances solved as one batch.
+
+    thetas: (n, 2T) tensor; bs: list of n CUDA float64 vectors; geoms as for
+    BatchEigenvaluesFn.  Forward: ddeig_batch_pcg_solve; backward: the adjoint
+    batch solve A_sigma,j w_j = dl/du_j with the same operators and
+    preconditioners, then ddeig_batch_solve_grad (one grouped launch, the
+    shifts moving with theta).  Returns the list of solutions as one
+    concatenated tensor (instance-major) so that autograd sees one output;
+    dl/db_j = w_j.  opts: local_prec (default bf16), rtol, maxit.
+    """
+
+    @staticmethod
+    def forward(ctx, thetas, geoms, opts, *bs):
+        opts = dict(opts or {})
+        opts.setdefault("local_prec", "bf16")
+        th = thetas.detach().to("cpu", torch.float64).numpy()
+        specs, probs, batch = _batch_problems(th, geoms, opts)
+        bb = [b.detach().contiguous() for b in bs]
+        us = [torch.zeros_like(b) for b in bb]
+        rtol, maxit = opts.get("rtol", 1e-12), opts.get("maxit", 3000)
+        _dd.batch_pcg_solve(batch, bb, us, rtol=rtol, maxit=maxit)
+        ctx.batch, ctx.us, ctx.rtol, ctx.maxit = batch, us, rtol, maxit
+        ctx.sizes = [u.numel() for u in us]
+        ctx.theta_device = thetas.device
+        return torch.cat(us)
+
+    @staticmethod
+    def backward(ctx, gu):
+        gs = [g.detach().to(torch.float64).contiguous()
+              for g in torch.split(gu, ctx.sizes)]
+        ws = [torch.zeros_like(g) for g in gs]
+        _dd.batch_pcg_solve(ctx.batch, gs, ws, rtol=ctx.rtol, maxit=ctx.maxit)
+        grad = _dd.batch_solve_grad(ctx.batch, ctx.us, ws)
+        gtheta = torch.as_tensor(grad, dtype=torch.float64, device=ctx.theta_device)
+        return (gtheta, None, None) + tuple(ws)
+
+
 def eigenvalues(thetas, geoms, opts=None):
-    """lambda_j(theta_j) for independent instances (a list of EigenvalueFn applications)."""
-    return torch.stack([EigenvalueFn.apply(t, g, opts) for t, g in zip(thetas, geoms)])
+    """lambda_j(theta_j) for independent instances as one batch (BatchEigenvaluesFn)."""
+    if not isinstance(thetas, torch.Tensor):
+        thetas = torch.stack(list(thetas))
+    return BatchEigenvaluesFn.apply(thetas, geoms, opts)

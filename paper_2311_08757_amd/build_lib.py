@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libddeig.so")
 OBJDIR = os.path.join(os.path.dirname(HERE), "_build")
 SOURCES = ["api.hip", "k_operator.hip", "k_chain.hip", "k_precond.hip", "k_vector.hip",
-           "k_dense.hip", "k_krylov.hip", "k_chain_mfma.hip", "k_noalloc.hip"]
+           "k_dense.hip", "k_krylov.hip", "k_chain_mfma.hip", "k_noalloc.hip", "k_grad.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

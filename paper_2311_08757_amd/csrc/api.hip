@@ -53,6 +53,80 @@ void dfree(ddeig_problem* P, void* p) {
 
 void sync(ddeig_problem* P) { check_hip(hipStreamSynchronize(P->stream), "hipStreamSynchronize"); }
 
+// A device buffer of at least `need` elements, replacing a smaller one (owned
+// through `allocs`).
+template <typename T>
+T* grow(std::vector<void*>& allocs, T* old, long& cap, long need) {
+  if (old != nullptr && cap >= need) return old;
+  if (old != nullptr) {
+    auto it = std::find(allocs.begin(), allocs.end(), (void*)old);
+    if (it != allocs.end()) allocs.erase(it);
+    (void)hipFree(old);
+    cap = 0;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, sizeof(T) * (size_t)std::max<long>(need, 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Failure{DDEIG_ENOMEM, "hipMalloc of the derivative-form buffers failed"};
+  }
+  allocs.push_back(p);
+  cap = need;
+  return static_cast<T*>(p);
+}
+
+// All 2T + 1 forms x^T M_W y (W = dV/da_t, dV/dphi_t, 1) of every job in one
+// grouped launch; out receives njobs x (2T + 1) values.  Synchronises s.
+void grad_run(std::vector<void*>& allocs, GradBuf& gb, std::vector<GradJob>& jobs, int T,
+              hipStream_t s, std::vector<double>& out) {
+  const int nf = 2 * T + 1;
+  std::vector<int2> map;
+  long part = 0;
+  for (int j = 0; j < (int)jobs.size(); ++j) {
+    jobs[j].nblk = grad_blocks(jobs[j].nelem);
+    jobs[j].part0 = part;
+    part += (long)nf * jobs[j].nblk;
+    for (int b = 0; b < jobs[j].nblk; ++b) map.push_back(make_int2(j, b));
+  }
+  gb.jobs = grow(allocs, gb.jobs, gb.cap_jobs, (long)jobs.size());
+  gb.map = grow(allocs, gb.map, gb.cap_map, (long)map.size());
+  gb.part = grow(allocs, gb.part, gb.cap_part, part);
+  gb.out = grow(allocs, gb.out, gb.cap_out, (long)jobs.size() * nf);
+  check_hip(hipMemcpyAsync(gb.jobs, jobs.data(), sizeof(GradJob) * jobs.size(),
+                           hipMemcpyHostToDevice, s), "copy derivative jobs");
+  check_hip(hipMemcpyAsync(gb.map, map.data(), sizeof(int2) * map.size(), hipMemcpyHostToDevice, s),
+            "copy block map");
+  launch_grad_forms(gb.jobs, gb.map, (int)map.size(), (int)jobs.size(), T, gb.part, gb.out, s);
+  check_hip(hipGetLastError(), "derivative forms");
+  out.assign(jobs.size() * (size_t)nf, 0.0);
+  check_hip(hipMemcpyAsync(out.data(), gb.out, sizeof(double) * out.size(), hipMemcpyDeviceToHost, s),
+            "copy forms");
+  check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+// The job of the pair (x, y) of problem P on its grid (cell = 0) or periodic cell.
+GradJob grad_job(const ddeig_problem* P, const double* x, const double* y, int cell) {
+  GradJob jb{};
+  jb.g = P->g;
+  jb.vs = P->dVS;
+  jb.x = x;
+  jb.y = y;
+  jb.cell = cell;
+  long ne = 1;
+  for (int a = 0; a < P->g.D; ++a) ne *= (cell && P->g.isx[a]) ? P->g.ne : P->g.nel[a];
+  jb.nelem = ne;
+  return jb;
+}
+
+// The number of Fourier parameters of the problem's potential (2T), or an error.
+ddeig_status grad_params(const ddeig_problem* P, int ngrad, int& T) {
+  if (P->vs.kind != DDEIG_V_SEP_FOURIER && P->vs.kind != DDEIG_V_FOURIER2)
+    return set_error(DDEIG_EINVAL, "derivatives need a SEP_FOURIER or FOURIER2 potential");
+  T = P->vs.nterms;
+  if (ngrad != 2 * T)
+    return set_error(DDEIG_EINVAL, "ngrad must be 2 nterms = " + std::to_string(2 * T));
+  return DDEIG_OK;
+}
+
 void check_launch(const char* what) { check_hip(hipGetLastError(), what); }
 
 Red slot(ddeig_problem* P, int i) {
@@ -1674,6 +1748,62 @@ ddeig_status ddeig_potential_form_noalloc(ddeig_problem* P, int space, const dde
   API_GUARD_END
 }
 
+ddeig_status ddeig_eig_grad(ddeig_problem* P, const double* x, double* grad, int ngrad) {
+  if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
+  if (validate_vec(x, "x")) return DDEIG_EINVAL;
+  if (!grad) return set_error(DDEIG_EINVAL, "grad is NULL");
+  int T = 0;
+  if (grad_params(P, ngrad, T) != DDEIG_OK) return DDEIG_EINVAL;
+  API_GUARD_BEGIN
+  std::vector<GradJob> jobs{grad_job(P, x, x, 0)};
+  std::vector<double> f;
+  grad_run(P->allocs, P->gb, jobs, T, P->stream, f);
+  if (!(f[2 * T] > 0.0)) return set_error(DDEIG_EINVAL, "x^T M x is not positive");
+  for (int j = 0; j < 2 * T; ++j) grad[j] = f[j] / f[2 * T];
+  return DDEIG_OK;
+  API_GUARD_END
+}
+
+ddeig_status ddeig_shift_grad(ddeig_problem* P, double* grad, int ngrad) {
+  if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
+  if (!grad) return set_error(DDEIG_EINVAL, "grad is NULL");
+  if (!P->shifted) return set_error(DDEIG_ESTATE, "shift_grad before the shift is set");
+  int T = 0;
+  if (grad_params(P, ngrad, T) != DDEIG_OK) return DDEIG_EINVAL;
+  API_GUARD_BEGIN
+  std::vector<GradJob> jobs{grad_job(P, P->psi, P->psi, 1)};
+  std::vector<double> f;
+  grad_run(P->allocs, P->gb, jobs, T, P->stream, f);
+  if (!(f[2 * T] > 0.0))
+    return set_error(DDEIG_ESTATE, "no cell eigenvector (set_shift without psi)");
+  for (int j = 0; j < 2 * T; ++j) grad[j] = f[j] / f[2 * T];
+  return DDEIG_OK;
+  API_GUARD_END
+}
+
+ddeig_status ddeig_solve_grad(ddeig_problem* P, const double* u, const double* w, double* grad,
+                              int ngrad) {
+  if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
+  if (validate_vec(u, "u") || validate_vec(w, "w")) return DDEIG_EINVAL;
+  if (!grad) return set_error(DDEIG_EINVAL, "grad is NULL");
+  if (!P->shifted) return set_error(DDEIG_ESTATE, "solve_grad before the shift is set");
+  int T = 0;
+  if (grad_params(P, ngrad, T) != DDEIG_OK) return DDEIG_EINVAL;
+  API_GUARD_BEGIN
+  std::vector<GradJob> jobs{grad_job(P, P->psi, P->psi, 1), grad_job(P, w, u, 0)};
+  std::vector<double> f;
+  grad_run(P->allocs, P->gb, jobs, T, P->stream, f);
+  const int nf = 2 * T + 1;
+  if (!(f[2 * T] > 0.0))
+    return set_error(DDEIG_ESTATE, "no cell eigenvector (set_shift without psi)");
+  for (int j = 0; j < 2 * T; ++j) {
+    const double dsigma = f[j] / f[2 * T];
+    grad[j] = -(f[nf + j] - dsigma * f[nf + 2 * T]);
+  }
+  return DDEIG_OK;
+  API_GUARD_END
+}
+
 ddeig_status ddeig_query(const ddeig_problem* P, long* n_dof, long* n_cell, int* n_sub) {
   if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
   if (n_dof) *n_dof = P->g.n;
@@ -2040,6 +2170,7 @@ struct ddeig_batch {
   // (first iteration of a block of 8, maxit), captured on first use
   int use_graphs = 0;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  ddeig::GradBuf gb;  // derivative forms of ddeig_batch_eig_grad / ddeig_batch_solve_grad
 };
 
 namespace {
@@ -2560,6 +2691,61 @@ ddeig_status ddeig_batch_inverse_iteration(ddeig_batch* B, double* const* x, dou
                                         ": an inner solve stopped at maxit_inner");
   }
   return st;
+  API_GUARD_END
+}
+
+ddeig_status ddeig_batch_eig_grad(ddeig_batch* B, const double* const* x, double* grad,
+                                  int ngrad) {
+  if (!B) return set_error(DDEIG_EINVAL, "batch is NULL");
+  if (!x || !grad) return set_error(DDEIG_EINVAL, "x or grad is NULL");
+  int T = 0;
+  for (int j = 0; j < B->n; ++j) {
+    if (validate_vec(x[j], "x")) return DDEIG_EINVAL;
+    if (grad_params(B->P[j], ngrad, T) != DDEIG_OK) return DDEIG_EINVAL;
+  }
+  API_GUARD_BEGIN
+  std::vector<GradJob> jobs;
+  for (int j = 0; j < B->n; ++j) jobs.push_back(grad_job(B->P[j], x[j], x[j], 0));
+  std::vector<double> f;
+  grad_run(B->allocs, B->gb, jobs, T, B->stream, f);
+  const int nf = 2 * T + 1;
+  for (int j = 0; j < B->n; ++j) {
+    const double* fj = f.data() + (size_t)j * nf;
+    if (!(fj[2 * T] > 0.0))
+      return set_error(DDEIG_EINVAL, "instance " + std::to_string(j) + ": x^T M x is not positive");
+    for (int t = 0; t < 2 * T; ++t) grad[(size_t)j * 2 * T + t] = fj[t] / fj[2 * T];
+  }
+  return DDEIG_OK;
+  API_GUARD_END
+}
+
+ddeig_status ddeig_batch_solve_grad(ddeig_batch* B, const double* const* u, const double* const* w,
+                                    double* grad, int ngrad) {
+  if (!B) return set_error(DDEIG_EINVAL, "batch is NULL");
+  if (!u || !w || !grad) return set_error(DDEIG_EINVAL, "u, w or grad is NULL");
+  int T = 0;
+  for (int j = 0; j < B->n; ++j) {
+    if (validate_vec(u[j], "u") || validate_vec(w[j], "w")) return DDEIG_EINVAL;
+    if (grad_params(B->P[j], ngrad, T) != DDEIG_OK) return DDEIG_EINVAL;
+    if (!B->P[j]->shifted)
+      return set_error(DDEIG_ESTATE, "instance " + std::to_string(j) + ": shift not set");
+  }
+  API_GUARD_BEGIN
+  std::vector<GradJob> jobs;
+  for (int j = 0; j < B->n; ++j) jobs.push_back(grad_job(B->P[j], B->P[j]->psi, B->P[j]->psi, 1));
+  for (int j = 0; j < B->n; ++j) jobs.push_back(grad_job(B->P[j], w[j], u[j], 0));
+  std::vector<double> f;
+  grad_run(B->allocs, B->gb, jobs, T, B->stream, f);
+  const int nf = 2 * T + 1;
+  for (int j = 0; j < B->n; ++j) {
+    const double* cj = f.data() + (size_t)j * nf;
+    const double* gj = f.data() + (size_t)(B->n + j) * nf;
+    if (!(cj[2 * T] > 0.0))
+      return set_error(DDEIG_ESTATE, "instance " + std::to_string(j) + ": no cell eigenvector");
+    for (int t = 0; t < 2 * T; ++t)
+      grad[(size_t)j * 2 * T + t] = -(gj[t] - cj[t] / cj[2 * T] * gj[2 * T]);
+  }
+  return DDEIG_OK;
   API_GUARD_END
 }
 

@@ -292,6 +292,29 @@ struct InstDev {
   double* hist;
 };
 
+// One job of the grouped derivative forms (k_grad.hip): the pair x, y of one
+// problem on its grid (cell = 0) or on its periodic cell (cell = 1), the
+// problem's potential, its element count, its workgroups and the offset of its
+// partial sums (2T + 1 forms x nblk).
+struct GradJob {
+  Geo g;
+  const VSpec* vs;
+  const double* x;
+  const double* y;
+  long nelem;
+  int cell, nblk;
+  long part0;
+};
+
+// Device buffers of the derivative forms, grown on demand.
+struct GradBuf {
+  GradJob* jobs = nullptr;
+  int2* map = nullptr;
+  double* part = nullptr;
+  double* out = nullptr;
+  long cap_jobs = 0, cap_map = 0, cap_part = 0, cap_out = 0;
+};
+
 // Block -> (instance, block index within the instance) of a grouped launch.
 struct BlockMap {
   const int2* map;
@@ -382,6 +405,7 @@ struct ddeig_problem {
   // quadrature-point tables of a QUAD_TABLE potential (device) and of the last
   // QUAD_TABLE weight of potential_form; host copy of the potential's table
   double t_setup_ms = 0.0;  // assemble + shift calls so far (wall time)
+  ddeig::GradBuf gb;        // derivative forms (ddeig_eig_grad and relatives)
   double* dVtab = nullptr;
   double* dWtab = nullptr;
   long wtab_cap = 0;
@@ -545,6 +569,11 @@ void launch_gm_update(const ddeig_problem* P, int nv, const double* Z, long ldv,
                       double* x, hipStream_t s);
 
 void check_hip(hipError_t e, const char* what);
+
+// Derivative forms (k_grad.hip): grouped launch over jobs, T Fourier terms.
+int grad_blocks(long nelem);
+void launch_grad_forms(const GradJob* dJobs, const int2* dMap, int nblocks, int njobs, int T,
+                       double* part, double* out, hipStream_t s);
 
 // The potential form without device allocation (k_noalloc.hip).
 hipError_t noalloc_init(int dev);

@@ -72,7 +72,8 @@ EXPORTS = ["ddeig_assemble", "ddeig_cell_shift", "ddeig_set_shift", "ddeig_apply
            "ddeig_apply_precond", "ddeig_apply_schwarz", "ddeig_stationary_ras",
            "ddeig_gmres_solve", "ddeig_pcg_solve", "ddeig_inverse_iteration", "ddeig_lopcg",
            "ddeig_profile_kernel", "ddeig_profile_iteration", "ddeig_potential_form",
-           "ddeig_potential_form_noalloc", "ddeig_batch_create",
+           "ddeig_potential_form_noalloc", "ddeig_eig_grad", "ddeig_shift_grad",
+           "ddeig_solve_grad", "ddeig_batch_eig_grad", "ddeig_batch_solve_grad", "ddeig_batch_create",
            "ddeig_batch_query", "ddeig_batch_pcg_solve", "ddeig_batch_inverse_iteration",
            "ddeig_batch_destroy", "ddeig_query", "ddeig_destroy", "ddeig_status_string",
            "ddeig_last_error"]
@@ -89,6 +90,7 @@ def load_library(path=LIB_PATH):
         raise RuntimeError(f"{path} is missing: build it with paper_2311_08757_amd.build_lib.build()")
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
+    PP = ctypes.POINTER(ctypes.c_void_p)
     dp = ctypes.POINTER(ctypes.c_double)
     lib.ddeig_assemble.argtypes = [ctypes.POINTER(Geometry), ctypes.c_double,
                                    ctypes.POINTER(Potential), ctypes.c_int,
@@ -114,7 +116,11 @@ def load_library(path=LIB_PATH):
     lib.ddeig_potential_form.argtypes = [P, ctypes.c_int, ctypes.POINTER(Potential), P, P, dp]
     lib.ddeig_potential_form_noalloc.argtypes = [P, ctypes.c_int, ctypes.POINTER(Potential), P, P,
                                                  dp]
-    PP = ctypes.POINTER(ctypes.c_void_p)
+    lib.ddeig_eig_grad.argtypes = [P, P, dp, ctypes.c_int]
+    lib.ddeig_shift_grad.argtypes = [P, dp, ctypes.c_int]
+    lib.ddeig_solve_grad.argtypes = [P, P, P, dp, ctypes.c_int]
+    lib.ddeig_batch_eig_grad.argtypes = [P, PP, dp, ctypes.c_int]
+    lib.ddeig_batch_solve_grad.argtypes = [P, PP, PP, dp, ctypes.c_int]
     lib.ddeig_batch_create.argtypes = [PP, ctypes.c_int, ctypes.c_int, PP]
     lib.ddeig_batch_query.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_int), dp]
@@ -166,6 +172,7 @@ class Problem:
         self.n_dof, self.n_cell, self.n_sub = n_dof, n_cell, n_sub
         self.stream = stream
         self.sigma = None
+        self.nterms = 0
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -245,7 +252,10 @@ def assemble(p, q, L, ne, V, delta, ell=1, pu="equal", coarse=True, local_prec="
     del keep
     _check(st, "ddeig_assemble")
     n_dof, n_cell, n_sub = query_handle(handle)
-    return Problem(handle, n_dof, n_cell, n_sub, stream)
+    prob = Problem(handle, n_dof, n_cell, n_sub, stream)
+    # Fourier terms of the potential (the parameters of the derivative calls)
+    prob.nterms = len(V["a"]) if V["kind"] in ("sep_fourier", "fourier2") else 0
+    return prob
 
 
 def query_handle(handle):
@@ -427,6 +437,36 @@ def potential_form_noalloc(prob, W, x, y, space="global"):
     return out.value
 
 
+def _nparams(prob):
+    return 2 * int(prob.nterms)
+
+
+def eig_grad(prob, x):
+    """ddeig_eig_grad: dlambda/dtheta (numpy, 2T values) for the eigenvector x."""
+    n = _nparams(prob)
+    g = (ctypes.c_double * n)()
+    _check(load_library().ddeig_eig_grad(prob.handle, _ptr(x, prob.n_dof, "x"), g, n),
+           "ddeig_eig_grad")
+    return np.array(g[:], dtype=np.float64)
+
+
+def shift_grad(prob):
+    """ddeig_shift_grad: dsigma/dtheta (numpy, 2T values)."""
+    n = _nparams(prob)
+    g = (ctypes.c_double * n)()
+    _check(load_library().ddeig_shift_grad(prob.handle, g, n), "ddeig_shift_grad")
+    return np.array(g[:], dtype=np.float64)
+
+
+def solve_grad(prob, u, w):
+    """ddeig_solve_grad: dl/dtheta for u = A_sigma^{-1} b and the adjoint solution w."""
+    n = _nparams(prob)
+    g = (ctypes.c_double * n)()
+    _check(load_library().ddeig_solve_grad(prob.handle, _ptr(u, prob.n_dof, "u"),
+                                           _ptr(w, prob.n_dof, "w"), g, n), "ddeig_solve_grad")
+    return np.array(g[:], dtype=np.float64)
+
+
 class Batch:
     """Owns a ddeig_batch handle; keeps its problems alive while it exists."""
 
@@ -504,6 +544,27 @@ def batch_inverse_iteration(batch, xs, tol_x=1e-9, maxit_outer=100, rtol_inner=1
                                      t_solve_ms=i.t_solve_ms, spec_res=i.spec_res,
                                      t_setup_ms=i.t_setup_ms,
                                      inner_unconverged=i.inner_unconverged) for i in info]
+
+
+def batch_eig_grad(batch, xs):
+    """ddeig_batch_eig_grad: (n, 2T) numpy array of dlambda_j/dtheta_j."""
+    ns = [p.n_dof for p in batch.probs]
+    npar = _nparams(batch.probs[0])
+    g = (ctypes.c_double * (npar * len(ns)))()
+    _check(load_library().ddeig_batch_eig_grad(batch.handle, _ptr_array(xs, ns, "x"), g, npar),
+           "ddeig_batch_eig_grad")
+    return np.array(g[:], dtype=np.float64).reshape(len(ns), npar)
+
+
+def batch_solve_grad(batch, us, ws):
+    """ddeig_batch_solve_grad: (n, 2T) numpy array of dl/dtheta_j."""
+    ns = [p.n_dof for p in batch.probs]
+    npar = _nparams(batch.probs[0])
+    g = (ctypes.c_double * (npar * len(ns)))()
+    _check(load_library().ddeig_batch_solve_grad(batch.handle, _ptr_array(us, ns, "u"),
+                                                 _ptr_array(ws, ns, "w"), g, npar),
+           "ddeig_batch_solve_grad")
+    return np.array(g[:], dtype=np.float64).reshape(len(ns), npar)
 
 
 LOPCG_MODES = {"fixed": 0, "adaptive": 1, "fused": 2}

@@ -12,14 +12,24 @@ ddeig_potential_form) against the oracle's own derivative forms.
 - ShiftedSolveFn backward (adjoint PCG + shift derivative) against the
   oracle's adjoint form with direct solves: 1e-9 relative.
 - instances of the batched workload (2-D, L_j in 16..256, n_e = 32,
-  delta = 2, bf16 local solves): lambda_j and dlambda_j/dtheta.
+  delta = 2, bf16 local solves): lambda_j and dlambda_j/dtheta one by one,
+  and all 64 as one batch (BatchEigenvaluesFn: grouped inverse iteration and
+  one grouped launch of the Hellmann-Feynman forms) against the oracle's
+  Hellmann-Feynman derivative stored by make_golden.py (1e-9 relative), two
+  of them against central differences of the batched eigenvalue (step 1e-6);
+  the batched shifted solve and its adjoint (BatchShiftedSolveFn) against
+  the oracle's adjoint form with direct solves (1e-9 relative).
+- ddeig_shift_grad against the oracle's cell Hellmann-Feynman form.
 """
+import json
+import os
 import numpy as np
 import pytest
 
 import workloads as W
 
 pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 CASES = [
     # p, q, L, ne, delta, potential
@@ -186,3 +196,102 @@ def test_batch_instance_grad(torch, inst):
     lam_ref, g_ref = _oracle_eig(case)
     assert abs(lam.item() - lam_ref) <= 1e-11 * abs(lam_ref)
     assert np.max(np.abs(theta.grad.numpy() - g_ref)) <= 1e-9 * np.max(np.abs(g_ref))
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_shift_grad(torch, case):
+    import paper_2311_08757_amd as dd
+    from oracle import grad as G
+    from oracle.cell import cell_problem
+    p, q, L, ne, delta, V = case
+    prob = dd.assemble(p, q, L, ne, V, delta)
+    dd.cell_shift(prob)
+    g = dd.shift_grad(prob)
+    ref = G.shift_grad(cell_problem(p, q, ne, V), V)
+    assert np.max(np.abs(g - ref)) <= 1e-9 * np.max(np.abs(ref))
+
+
+def _geom_of(inst):
+    return dict(p=inst["p"], q=inst["q"], L=inst["L"], ne=inst["ne"], delta=inst["delta"],
+                V=inst["V"])
+
+
+@pytest.mark.timeout(900)
+def test_batch_eig_grad_all_instances(torch):
+    """All 64 instances of the batched workload as one batch, bf16 local solves."""
+    from paper_2311_08757_amd import autograd as AG
+    inst = W.batch_config()
+    gold = json.load(open(os.path.join(HERE, "golden", "oracle_batch.json")))
+    thetas = torch.tensor(np.stack([AG.param_vector(c["V"]) for c in inst]), dtype=torch.float64,
+                          requires_grad=True)
+    print("# batch of 64: forward", flush=True)
+    lam = AG.BatchEigenvaluesFn.apply(thetas, [_geom_of(c) for c in inst],
+                                      {"tol_x": 1e-12, "local_prec": "bf16"})
+    lam.sum().backward()
+    g = thetas.grad.numpy()
+    for j, gd in enumerate(gold):
+        assert abs(lam[j].item() - gd["lam"]) <= 1e-10 * abs(gd["lam"]), j
+        ref = np.array(gd["grad"])
+        assert np.max(np.abs(g[j] - ref)) <= 1e-9 * np.max(np.abs(ref)), (j, g[j], ref)
+
+
+@pytest.mark.timeout(900)
+def test_batch_eig_grad_finite_differences(torch):
+    """Central differences (step 1e-6) of the batched eigenvalues of two
+    instances of the batched workload (bf16 local solves) against the batched
+    Hellmann-Feynman gradient."""
+    from paper_2311_08757_amd import autograd as AG
+    inst = W.batch_config()
+    Ls = [c["L"] for c in inst]
+    pick = [inst[int(np.argmin(Ls))], inst[7]]
+    geoms = [_geom_of(c) for c in pick]
+    th0 = np.stack([AG.param_vector(c["V"]) for c in pick])
+    opts = {"tol_x": 1e-12, "local_prec": "bf16"}
+    thetas = torch.tensor(th0, dtype=torch.float64, requires_grad=True)
+    AG.BatchEigenvaluesFn.apply(thetas, geoms, opts).sum().backward()
+    g = thetas.grad.numpy()
+    h = 1e-6
+    fd = np.zeros_like(th0)
+    for k in range(th0.shape[1]):
+        tp, tm = th0.copy(), th0.copy()
+        tp[:, k] += h
+        tm[:, k] -= h
+        lp = AG.BatchEigenvaluesFn.apply(torch.tensor(tp), geoms, opts).numpy()
+        lm = AG.BatchEigenvaluesFn.apply(torch.tensor(tm), geoms, opts).numpy()
+        fd[:, k] = (lp - lm) / (2 * h)
+    for j in range(2):
+        assert np.max(np.abs(fd[j] - g[j])) <= 2e-6 * _scale(g[j]), (j, fd[j], g[j])
+
+
+@pytest.mark.timeout(600)
+def test_batch_solve_grad(torch):
+    """Batched shifted solves and their adjoint against the oracle (direct solves)."""
+    import scipy.sparse.linalg as spla
+    from paper_2311_08757_amd import autograd as AG
+    from oracle import grad as G
+    from oracle.cell import cell_problem
+    from oracle.fem import assemble_elements
+    from oracle.potential import vfun
+    cases = [(1, 1, L, 8, 2, W.sep_fourier(600 + L)) for L in (5, 6, 8)]
+    geoms = [_geom(c) for c in cases]
+    thetas = torch.tensor(np.stack([AG.param_vector(c[5]) for c in cases]), dtype=torch.float64,
+                          requires_grad=True)
+    grids = [G.grid_of(dict(p=c[0], q=c[1], L=c[2], ne=c[3])) for c in cases]
+    bs = [W.random_vector(gr.n, 50 + j) for j, gr in enumerate(grids)]
+    cs = [W.random_vector(gr.n, 60 + j) for j, gr in enumerate(grids)]
+    bd = [_dev(torch, b).requires_grad_(True) for b in bs]
+    u = AG.BatchShiftedSolveFn.apply(thetas, geoms, {"rtol": 1e-13, "local_prec": "bf16"}, *bd)
+    (u * _dev(torch, np.concatenate(cs))).sum().backward()
+    off = 0
+    for j, (c, gr) in enumerate(zip(cases, grids)):
+        p, q, L, ne, delta, V = c
+        K, M, MV = assemble_elements(gr, vfun(V, p, q))
+        cell = cell_problem(p, q, ne, V)
+        As = (K + MV - cell["sigma"] * M).tocsc()
+        uo, wo = spla.spsolve(As, bs[j]), spla.spsolve(As, cs[j])
+        uj = u.detach()[off:off + gr.n].cpu().numpy()
+        off += gr.n
+        assert np.max(np.abs(uj - uo)) <= 1e-8 * np.max(np.abs(uo))
+        ref = G.solve_grad(gr, M, uo, wo, V, G.shift_grad(cell, V))
+        assert np.max(np.abs(thetas.grad.numpy()[j] - ref)) <= 1e-9 * np.max(np.abs(ref)), j
+        assert np.max(np.abs(bd[j].grad.cpu().numpy() - wo)) <= 1e-8 * np.max(np.abs(wo))
