@@ -397,11 +397,12 @@ PcgOut pcg_run(ddeig_problem* P, const double* b, double* x, double rtol, int ma
     const CheckArgs chk{1, kk, maxit, P->hist_cap, rr, P->hist};
     precond_apply(P, P->r, P->z, &rz, P->st, &xr, &rr, &chk, ms);
   };
-  while (k < maxit) {
-    const int k0 = k + 1, kend = std::min(maxit, k + batch);
+  // queues the block of iterations k0..kend and a copy of the CG state behind
+  // it (into pinned host slot `sl`, signalled by ev_state[sl])
+  auto submit = [&](int k0, int kend, int sl) {
     if (P->opt.graphs) {
-      // the block of iterations k0..kend, captured once per (k0, kend, maxit, x)
-      // on the problem's own capture stream and replayed on the library stream
+      // the block, captured once per (k0, kend, maxit, x) on the problem's own
+      // capture stream and replayed on the library stream
       const auto key = std::make_tuple(k0, kend, maxit, (const void*)x);
       auto it = P->graphs.find(key);
       if (it == P->graphs.end()) {
@@ -426,15 +427,36 @@ PcgOut pcg_run(ddeig_problem* P, const double* b, double* x, double rtol, int ma
         it = P->graphs.emplace(key, ge).first;
       }
       check_hip(hipGraphLaunch(it->second, s), "launch graph");
-      k = kend;
     } else {
-      for (k = k0; k <= kend; ++k) iteration(k, s);
-      --k;
+      for (int kk = k0; kk <= kend; ++kk) iteration(kk, s);
     }
     check_launch("pcg iteration");
-    check_hip(hipMemcpyAsync(&hs, P->st, sizeof(PcgState), hipMemcpyDeviceToHost, s), "state");
-    sync(P);
-    if (hs.done) break;
+    check_hip(hipMemcpyAsync(&P->hst[sl], P->st, sizeof(PcgState), hipMemcpyDeviceToHost, s),
+              "state");
+    check_hip(hipEventRecord(P->ev_state[sl], s), "record state");
+  };
+  // One block runs ahead: while the host waits for the state after block j,
+  // block j + 1 is already queued, so the device does not idle during the
+  // check.  Once CG has stopped, the block run ahead finds the done flag and
+  // its kernels return at once.
+  if (k < maxit) {
+    const int kend = std::min(maxit, k + batch);
+    submit(k + 1, kend, 0);
+    k = kend;
+    int cur = 0;
+    for (;;) {
+      bool ahead = false;
+      if (k < maxit) {
+        const int kend2 = std::min(maxit, k + batch);
+        submit(k + 1, kend2, 1 - cur);
+        k = kend2;
+        ahead = true;
+      }
+      check_hip(hipEventSynchronize(P->ev_state[cur]), "state");
+      hs = P->hst[cur];
+      if (hs.done || !ahead) break;
+      cur = 1 - cur;
+    }
   }
   PcgOut o;
   o.iters = hs.iters;
@@ -1298,6 +1320,10 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
       check_hip(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking), "create capture stream");
     check_hip(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming), "create event");
     check_hip(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming), "create event");
+    for (int e = 0; e < 2; ++e)
+      check_hip(hipEventCreateWithFlags(&P->ev_state[e], hipEventDisableTiming), "create event");
+    check_hip(hipHostMalloc(reinterpret_cast<void**>(&P->hst), 2 * sizeof(ddeig::PcgState)),
+              "pinned state");
     P->gjbuf = dalloc<double>(P, 4 * (size_t)gjmax);
     P->gj_stride = gjmax;
     P->psi = dalloc<double>(P, g.tsize);
@@ -1375,6 +1401,9 @@ void ddeig_destroy(ddeig_problem* P) {
 
   if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
   if (P->ev_join) (void)hipEventDestroy(P->ev_join);
+  for (int e = 0; e < 2; ++e)
+    if (P->ev_state[e]) (void)hipEventDestroy(P->ev_state[e]);
+  if (P->hst) (void)hipHostFree(P->hst);
   for (void* p : P->allocs) (void)hipFree(p);
   P->allocs.clear();
   delete P;

@@ -333,6 +333,10 @@ struct ddeig_problem {
   // second stream (default priority) for work that overlaps the local solves
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // CG state copies of the last two blocks of queued iterations (pinned host
+  // memory, so the copies run behind the queued work) and their events
+  ddeig::PcgState* hst = nullptr;
+  hipEvent_t ev_state[2] = {nullptr, nullptr};
   // HIP-graph replay of PCG iteration blocks (options.graphs): the capture
   // stream and one executable graph per (first, last iteration, maxit, x)
   hipStream_t cap = nullptr;
