@@ -128,6 +128,9 @@ typedef struct {
   double* hist;       /* optional host array: hist[k] = ||r_k|| / ||r_0||, k = 0..iters */
   int hist_cap;       /* capacity of hist */
   double true_relres; /* ||b - A_sigma x||_2 / ||r_0||_2 recomputed from the returned x */
+  int fallback;       /* pcg_solve: 1 if r.z <= 0 under dense reduced-precision local solves
+                         switched the problem to FP32 chain local solves and the solve was
+                         repeated (2-D problems) */
 } ddeig_pcg_info;
 
 typedef struct {
@@ -141,6 +144,8 @@ typedef struct {
   double t_setup_ms;  /* wall time of ddeig_assemble and the shift calls of the problem */
   int inner_unconverged; /* inner solves that stopped at maxit_inner (the call then
                             returns DDEIG_ENOCONV even if the outer test was met) */
+  int fallback;          /* 1 if an inner solve switched the local solves to FP32 (as for
+                            ddeig_pcg_info.fallback) and was repeated */
 } ddeig_eig_info;
 
 /* Builds the period-cell operator tables (K, M, M_V at one period cell: §2,
@@ -160,6 +165,13 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
  * (eq:twoLevelASMPreconditioner), the coarse basis and coarse matrix.
  * psi_cell_host (nullable) receives n_cell values. */
 ddeig_status ddeig_cell_shift(ddeig_problem* P, double* sigma_out, double* psi_cell_host);
+
+/* Test/debug override of the CG breakdown test: the next `count` PCG solves
+ * of the problem that run with dense reduced-precision local solves report
+ * r.z <= 0 at their first iteration (the test compares r.z with +inf instead
+ * of 0), which exercises the FP32 fallback of ddeig_pcg_solve and
+ * ddeig_inverse_iteration without a genuinely indefinite preconditioner. */
+ddeig_status ddeig_debug_force_breakdown(ddeig_problem* P, int count);
 
 /* Test/debug override of the shift: uses the given sigma and cell vector
  * (n_cell host values, nullable for one-level preconditioning only) instead of
@@ -228,7 +240,12 @@ ddeig_status ddeig_gmres_solve(ddeig_problem* P, int kind, const double* b, doub
 
 /* Preconditioned CG for A_sigma x = b (§2.1, §3): x holds x0 on entry and the
  * iterate on exit; stops when ||r_k||_2 <= rtol ||r_0||_2 (§4.1).  Returns
- * DDEIG_ENOCONV after maxit iterations, DDEIG_ENOTSPD on breakdown. */
+ * DDEIG_ENOCONV after maxit iterations, DDEIG_ENOTSPD on breakdown.  With
+ * dense reduced-precision local solves (local_prec 2, 3) on a 2-D problem, a
+ * breakdown with r.z <= 0 (the rounded inverse made the preconditioner
+ * indefinite) switches the problem to FP32 block-chain local solves for the
+ * rest of its life and repeats the solve from x0 (info->fallback = 1); the
+ * same holds for the inner solves of ddeig_inverse_iteration. */
 ddeig_status ddeig_pcg_solve(ddeig_problem* P, const double* b, double* x, double rtol,
                              int maxit, ddeig_pcg_info* info);
 
@@ -405,7 +422,8 @@ ddeig_status ddeig_batch_query(const ddeig_batch* B, int* ksplit, int* order, in
  * pointers; x[j] holds x0 on entry).  info (nullable, n entries; hist is
  * ignored) receives each instance's iterations, relative residual and
  * breakdown flag.  Returns DDEIG_OK when every instance converged, else the
- * status of the failing instance (ENOTSPD before ENOCONV). */
+ * status of the failing instance (ENOTSPD before ENOCONV).  Batches have no
+ * FP32 fallback: a breakdown is reported in that instance's info. */
 ddeig_status ddeig_batch_pcg_solve(ddeig_batch* B, const double* const* b, double* const* x,
                                    double rtol, int maxit, ddeig_pcg_info* info);
 

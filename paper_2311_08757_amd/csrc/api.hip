@@ -305,6 +305,61 @@ int prec_flags(int kind) {
   }
 }
 
+// Automatic fallback when CG breaks down with r.z <= 0 under the dense
+// reduced-precision local solves (the rounded inverse made M^{-1} indefinite):
+// the problem switches to FP32 block-chain local solves (FP64 factors of
+// every class, rounded to FP32) for the rest of its life, and the caller
+// repeats the solve.  2-D problems only (their chain solves need no further
+// set-up); returns false where no fallback exists.
+bool fallback_fp32(ddeig_problem* P) {
+  if (P->opt.local_prec < 2 || P->g.D != 2) return false;
+  const hipStream_t s = P->stream;
+  std::vector<TypeDev> tdev(P->types.size());
+  check_hip(hipMemcpy(tdev.data(), P->dTypes, sizeof(TypeDev) * tdev.size(), hipMemcpyDeviceToHost),
+            "read classes");
+  for (size_t t = 0; t < P->types.size(); ++t) {
+    auto& T = P->types[t];
+    const long mm = (long)T.box.nch * T.box.b;
+    T.W = dalloc<double>(P, (size_t)T.box.nch * T.box.b * T.box.b);
+    T.W32 = dalloc<float>(P, (size_t)T.box.nch * T.box.b * T.box.b);
+    dfree(P, T.batch);
+    T.batch = dalloc<double>(P, (size_t)T.nmem * mm);
+    TypeDev& d = tdev[t];
+    for (int a = 0; a < 3; ++a) {
+      d.hm[a] = T.box.m[a];
+      d.off[a] = 0;
+    }
+    d.dense = 0;
+    d.W = T.W;
+    d.W32 = T.W32;
+    d.batch = T.batch;
+    d.tbatch = nullptr;
+    d.ld = 0;
+    d.ksplit = 0;
+    d.Rh = d.Rl = nullptr;
+    d.Z = nullptr;
+    d.zsplit = 0;
+    d.ldw = T.box.b;
+  }
+  std::vector<SubTS> ts(P->nsub);
+  for (int sid = 0; sid < P->nsub; ++sid) ts[sid] = SubTS{P->subs[sid].type, P->subs[sid].slot};
+  check_hip(hipMemcpy(P->dTypes, tdev.data(), sizeof(TypeDev) * tdev.size(), hipMemcpyHostToDevice),
+            "write classes");
+  check_hip(hipMemcpy(P->dSubTS, ts.data(), sizeof(SubTS) * ts.size(), hipMemcpyHostToDevice),
+            "write subdomain table");
+  P->opt.local_prec = 1;
+  clear_graphs(P);
+  clear_flag(P);
+  for (auto& T : P->types) {
+    chain_factor(P, T.box, P->tabAs, T.W, s);
+    launch_to_float(T.W, T.W32, (long)T.box.nch * T.box.b * T.box.b, s);
+  }
+  check_launch("fallback factorisation");
+  if (read_flag(P)) throw Failure{DDEIG_ENOTSPD, "a local matrix A_sigma,i is not positive definite"};
+  ++P->fallbacks;
+  return true;
+}
+
 // restrict -> {local solves (+ clipped-class correction) | coarse solve on the
 // second stream} -> extend.  xr (nullable) fuses the CG update of x and r into the
 // restriction (partials of ||r||^2 into *rr); chk (nullable) folds the PCG
@@ -378,7 +433,13 @@ PcgOut pcg_run(ddeig_problem* P, const double* b, double* x, double rtol, int ma
   Red g = slot(P, 0), rr = slot(P, 1), rz = slot(P, 2);
   launch_stencil(P, P->tabAs, x, P->q, nullptr, nullptr, s);
   launch_resid_init(P, b, P->q, P->r, rr, s);
-  launch_pcg_init(P, rtol, rr, s);
+  // a test override makes the breakdown test of a reduced-precision solve fire
+  double rz_floor = 0.0;
+  if (P->force_rz > 0 && P->opt.local_prec >= 2) {
+    rz_floor = INFINITY;
+    --P->force_rz;
+  }
+  launch_pcg_init(P, rtol, rr, s, rz_floor);
   precond_apply(P, P->r, P->z, &rz, P->st);
   check_launch("pcg start");
   PcgState hs{};
@@ -1861,6 +1922,13 @@ ddeig_status ddeig_set_shift(ddeig_problem* P, double sigma, const double* psi_c
   API_GUARD_END
 }
 
+ddeig_status ddeig_debug_force_breakdown(ddeig_problem* P, int count) {
+  if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
+  if (count < 0) return set_error(DDEIG_EINVAL, "count must be >= 0");
+  P->force_rz = count;
+  return DDEIG_OK;
+}
+
 ddeig_status ddeig_cell_shift(ddeig_problem* P, double* sigma_out, double* psi_cell_host) {
   if (!P) return set_error(DDEIG_EINVAL, "problem is NULL");
   API_GUARD_BEGIN
@@ -2016,6 +2084,7 @@ static void fill_info(ddeig_problem* P, const PcgOut& o, int breakdown, ddeig_pc
   info->iters = o.iters;
   info->relres = o.relres;
   info->breakdown = breakdown;
+  info->fallback = 0;
   info->true_relres = b ? ddeig::true_relres(P, b, x) : o.relres;
   if (info->hist && info->hist_cap > 0) {
     const int cnt = std::min(std::min(info->hist_cap, o.iters + 1), P->hist_cap);
@@ -2078,8 +2147,16 @@ ddeig_status ddeig_pcg_solve(ddeig_problem* P, const double* b, double* x, doubl
     return set_error(DDEIG_EINVAL, "need rtol >= 0 and maxit >= 0");
   if (!P->shifted) return set_error(DDEIG_ESTATE, "pcg_solve before the shift is set");
   API_GUARD_BEGIN
-  const PcgOut o = pcg_run(P, b, x, rtol, maxit);
+  const int fb0 = P->fallbacks;
+  const bool can_fall_back = P->opt.local_prec >= 2 && P->g.D == 2;
+  if (can_fall_back) launch_copy(P->tmpv, x, P->g.n, P->stream);  // x0, for a repeat
+  PcgOut o = pcg_run(P, b, x, rtol, maxit);
+  if (o.done == 3 && can_fall_back && fallback_fp32(P)) {
+    launch_copy(x, P->tmpv, P->g.n, P->stream);
+    o = pcg_run(P, b, x, rtol, maxit);
+  }
   fill_info(P, o, o.done == 2 ? 1 : (o.done == 3 ? 2 : 0), info, b, x);
+  if (info) info->fallback = P->fallbacks - fb0;
   if (o.done == 2 || o.done == 3)
     return set_error(DDEIG_ENOTSPD, o.done == 2 ? "CG breakdown: p.A_sigma p <= 0"
                                                 : "CG breakdown: r.z <= 0");
@@ -2111,10 +2188,15 @@ ddeig_status ddeig_inverse_iteration(ddeig_problem* P, double* x, double tol_x, 
   long inner_sum = 0;
   int inner_max = 0, k = 0, inner_unconv = 0;
   ddeig_status st = DDEIG_ENOCONV;
+  const int fb0 = P->fallbacks;
   for (k = 1; k <= maxit_outer; ++k) {
     launch_stencil(P, P->tabM, x, P->w, nullptr, nullptr, s);  // b = M x
     launch_fill(P->u, n, 0.0, s);
-    const PcgOut o = pcg_run(P, P->w, P->u, rtol_inner, maxit_inner);
+    PcgOut o = pcg_run(P, P->w, P->u, rtol_inner, maxit_inner);
+    if (o.done == 3 && fallback_fp32(P)) {
+      launch_fill(P->u, n, 0.0, s);
+      o = pcg_run(P, P->w, P->u, rtol_inner, maxit_inner);
+    }
     if (o.done == 2 || o.done == 3) {
       st = set_error(DDEIG_ENOTSPD, "CG breakdown inside inverse iteration");
       break;
@@ -2150,6 +2232,7 @@ ddeig_status ddeig_inverse_iteration(ddeig_problem* P, double* x, double tol_x, 
     info->spec_res = ddeig::spectral_residual(P, x, lam);
     info->t_setup_ms = P->t_setup_ms;
     info->inner_unconverged = inner_unconv;
+    info->fallback = P->fallbacks - fb0;
   }
   if (st == DDEIG_ENOCONV) return set_error(st, "inverse iteration reached maxit_outer");
   // an inner solve that stopped at maxit_inner can leave the outer test on the
@@ -2601,6 +2684,7 @@ ddeig_status ddeig_batch_pcg_solve(ddeig_batch* B, const double* const* b, doubl
       info[j].iters = h.iters;
       info[j].relres = h.relres;
       info[j].breakdown = h.done == 2 ? 1 : (h.done == 3 ? 2 : 0);
+      info[j].fallback = 0;
       info[j].true_relres = ddeig::true_relres(B->P[j], b[j], x[j]);
     }
     if (h.done == 2 || h.done == 3)
@@ -2710,6 +2794,7 @@ ddeig_status ddeig_batch_inverse_iteration(ddeig_batch* B, double* const* x, dou
       info[j].spec_res = ddeig::spectral_residual(B->P[j], x[j], lam[j]);
       info[j].t_setup_ms = B->P[j]->t_setup_ms;
       info[j].inner_unconverged = unconv[j];
+      info[j].fallback = 0;
     }
     if (status[j] == DDEIG_ENOTSPD)
       st = set_error(DDEIG_ENOTSPD, "instance " + std::to_string(j) + ": CG breakdown");

@@ -262,6 +262,7 @@ struct PcgState {
   double r0n2;
   double tol2;
   double relres;
+  double rz_floor;  // CG stops with done = 3 when r.z <= rz_floor (0; +inf when a test forces it)
 };
 
 // One instance of a batch of problems advanced together: everything the
@@ -409,6 +410,8 @@ struct ddeig_problem {
   // quadrature-point tables of a QUAD_TABLE potential (device) and of the last
   // QUAD_TABLE weight of potential_form; host copy of the potential's table
   double t_setup_ms = 0.0;  // assemble + shift calls so far (wall time)
+  int force_rz = 0;         // PCG solves left that report r.z <= 0 at once (test override)
+  int fallbacks = 0;        // switches from dense reduced-precision to FP32 chain local solves
   ddeig::GradBuf gb;        // derivative forms (ddeig_eig_grad and relatives)
   double* dVtab = nullptr;
   double* dWtab = nullptr;
@@ -533,7 +536,8 @@ int red_grid(long work_items);
 void launch_resid_init(const ddeig_problem* P, const double* b, const double* q, double* r,
                        Red& rr, hipStream_t s);
 void launch_finish_sum(const Red& r, hipStream_t s);
-void launch_pcg_init(const ddeig_problem* P, double rtol, Red rr, hipStream_t s);
+void launch_pcg_init(const ddeig_problem* P, double rtol, Red rr, hipStream_t s,
+                     double rz_floor = 0.0);
 void launch_fill(double* x, long n, double v, hipStream_t s);
 void launch_copy(double* dst, const double* src, long n, hipStream_t s);
 void launch_scale_copy(long n, double* dst, const double* src, Red nrm2, hipStream_t s);

@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(kBlock) k_stencil(Geo g, const double* __restr
   if constexpr (MODE == 1) {
     const double rho = sum_partials(dir.rz.part, dir.rz.np);
     if (dir.st->done) return;
-    if (!(rho > 0.0)) {
+    if (!(rho > 0.0) || !(rho > dir.st->rz_floor)) {
       if (blockIdx.x == 0 && threadIdx.x == 0) {
         dir.st->done = 3;
         dir.st->iters = dir.k - 1;
@@ -315,7 +315,7 @@ __global__ void __launch_bounds__(kBlock) k_stencil3d(Geo g, const double* __res
   if constexpr (MODE == 1) {
     const double rho = sum_partials(dir.rz.part, dir.rz.np);
     if (dir.st->done) return;
-    if (!(rho > 0.0)) {
+    if (!(rho > 0.0) || !(rho > dir.st->rz_floor)) {
       if (blockIdx.x == 0 && threadIdx.x == 0) {
         dir.st->done = 3;
         dir.st->iters = dir.k - 1;
@@ -425,7 +425,7 @@ __device__ __forceinline__ void stencil2d_body(const Geo& g, const double* __res
   if constexpr (MODE == 1) {
     const double rho = sum_partials(dir.rz.part, dir.rz.np);
     if (dir.st->done) return;
-    if (!(rho > 0.0)) {
+    if (!(rho > 0.0) || !(rho > dir.st->rz_floor)) {
       if (bid == 0 && threadIdx.x == 0) {
         dir.st->done = 3;
         dir.st->iters = dir.k - 1;

@@ -45,9 +45,11 @@ void launch_finish_sum(const Red& r, hipStream_t s) {
   hipLaunchKernelGGL(k_finish_sum, dim3(1), dim3(kBlock), 0, s, r);
 }
 
-__global__ void k_pcg_init(PcgState* st, double rtol, Red rr, double* __restrict__ hist) {
+__global__ void k_pcg_init(PcgState* st, double rtol, Red rr, double* __restrict__ hist,
+                           double rz_floor) {
   const double r0n2 = sum_partials(rr.part, rr.np);
   if (threadIdx.x == 0) {
+    st->rz_floor = rz_floor;
     st->r0n2 = r0n2;
     st->tol2 = rtol * rtol * r0n2;
     st->iters = 0;
@@ -58,8 +60,9 @@ __global__ void k_pcg_init(PcgState* st, double rtol, Red rr, double* __restrict
   }
 }
 
-void launch_pcg_init(const ddeig_problem* P, double rtol, Red rr, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(kBlock), 0, s, P->st, rtol, rr, P->hist);
+void launch_pcg_init(const ddeig_problem* P, double rtol, Red rr, hipStream_t s,
+                     double rz_floor) {
+  hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(kBlock), 0, s, P->st, rtol, rr, P->hist, rz_floor);
 }
 
 __global__ void k_fill(double* x, long n, double v) {

@@ -51,7 +51,7 @@ class Options(ctypes.Structure):
 class PcgInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("relres", ctypes.c_double), ("breakdown", ctypes.c_int),
                 ("hist", ctypes.POINTER(ctypes.c_double)), ("hist_cap", ctypes.c_int),
-                ("true_relres", ctypes.c_double)]
+                ("true_relres", ctypes.c_double), ("fallback", ctypes.c_int)]
 
 
 class EigInfo(ctypes.Structure):
@@ -59,7 +59,7 @@ class EigInfo(ctypes.Structure):
                 ("outer_its", ctypes.c_int), ("inner_sum", ctypes.c_long),
                 ("inner_max", ctypes.c_int), ("t_solve_ms", ctypes.c_double),
                 ("spec_res", ctypes.c_double), ("t_setup_ms", ctypes.c_double),
-                ("inner_unconverged", ctypes.c_int)]
+                ("inner_unconverged", ctypes.c_int), ("fallback", ctypes.c_int)]
 
 
 class LopcgInfo(ctypes.Structure):
@@ -68,7 +68,7 @@ class LopcgInfo(ctypes.Structure):
                 ("inner_max", ctypes.c_int), ("t_solve_ms", ctypes.c_double)]
 
 
-EXPORTS = ["ddeig_assemble", "ddeig_cell_shift", "ddeig_set_shift", "ddeig_apply_op",
+EXPORTS = ["ddeig_assemble", "ddeig_cell_shift", "ddeig_set_shift", "ddeig_apply_op", "ddeig_debug_force_breakdown",
            "ddeig_apply_precond", "ddeig_apply_schwarz", "ddeig_stationary_ras",
            "ddeig_gmres_solve", "ddeig_pcg_solve", "ddeig_inverse_iteration", "ddeig_lopcg",
            "ddeig_profile_kernel", "ddeig_profile_iteration", "ddeig_potential_form",
@@ -97,6 +97,7 @@ def load_library(path=LIB_PATH):
                                    ctypes.POINTER(Options), P, ctypes.POINTER(P)]
     lib.ddeig_cell_shift.argtypes = [P, dp, dp]
     lib.ddeig_set_shift.argtypes = [P, ctypes.c_double, dp]
+    lib.ddeig_debug_force_breakdown.argtypes = [P, ctypes.c_int]
     lib.ddeig_apply_op.argtypes = [P, ctypes.c_int, P, P]
     lib.ddeig_apply_precond.argtypes = [P, P, P]
     lib.ddeig_apply_schwarz.argtypes = [P, ctypes.c_int, P, P]
@@ -294,6 +295,12 @@ def set_shift(prob, sigma, psi=None):
     prob.sigma = float(sigma)
 
 
+def debug_force_breakdown(prob, count=1):
+    """ddeig_debug_force_breakdown: the next `count` reduced-precision PCG solves report r.z <= 0."""
+    _check(load_library().ddeig_debug_force_breakdown(prob.handle, int(count)),
+           "ddeig_debug_force_breakdown")
+
+
 def apply_op(prob, which, x, y):
     """ddeig_apply_op: y = Op x, which in {"A_sigma", "A", "M", "K"} or 0..3."""
     w = OPS[which] if isinstance(which, str) else int(which)
@@ -314,7 +321,7 @@ def _krylov(fn, name, prob, lead, b, x, tail, hist_cap, raise_on_error):
     st = fn(prob.handle, *lead, _ptr(b, prob.n_dof, "b"), _ptr(x, prob.n_dof, "x"), *tail,
             ctypes.byref(info))
     out = dict(status=STATUS.get(st, st), iters=info.iters, relres=info.relres,
-               true_relres=info.true_relres, breakdown=info.breakdown,
+               true_relres=info.true_relres, breakdown=info.breakdown, fallback=info.fallback,
                hist=hist[:min(hist_cap, info.iters + 1)] if hist_cap > 0 else None)
     if raise_on_error and st != DDEIG_OK:
         _check(st, name)
@@ -369,7 +376,7 @@ def inverse_iteration(prob, x, tol_x=1e-9, maxit_outer=100, rtol_inner=1e-10, ma
     out = dict(status=STATUS.get(st, st), lam=info.lambda_, dx_M=info.dx_M,
                outer_its=info.outer_its, inner_sum=info.inner_sum, inner_max=info.inner_max,
                t_solve_ms=info.t_solve_ms, spec_res=info.spec_res, t_setup_ms=info.t_setup_ms,
-               inner_unconverged=info.inner_unconverged)
+               inner_unconverged=info.inner_unconverged, fallback=info.fallback)
     if raise_on_error and st != DDEIG_OK:
         _check(st, "ddeig_inverse_iteration")
     return out

@@ -360,6 +360,64 @@ def test_shift_above_ground_state(torch):
         assert out["status"] == "ENOTSPD"
 
 
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+def test_fp32_fallback_on_breakdown(torch, prec):
+    """r.z <= 0 under dense reduced-precision local solves (forced from the host:
+    the breakdown test compares r.z with +inf for one solve) switches a 2-D
+    problem to FP32 chain local solves and repeats the solve from x0: the
+    result is bit for bit that of a problem assembled with local_prec fp32,
+    later solves need no fallback, and inverse iteration repeats its inner
+    solve the same way.  3-D problems have no fallback and report ENOTSPD;
+    FP64 local solves ignore the override."""
+    import paper_2311_08757_amd as dd
+    case = CASES[0]
+    prob = _assemble(case, local_prec=prec)
+    ref = _assemble(case, local_prec="fp32")
+    sig, _ = dd.cell_shift(prob)
+    assert dd.cell_shift(ref)[0] == sig
+    b = _dev(torch, W.random_vector(prob.n_dof, 7))
+    x0 = _dev(torch, W.random_vector(prob.n_dof, 8))
+    xr = x0.clone()
+    o_ref = dd.pcg_solve(ref, b, xr, rtol=1e-10, maxit=500)
+    dd.debug_force_breakdown(prob, 1)
+    x = x0.clone()
+    o = dd.pcg_solve(prob, b, x, rtol=1e-10, maxit=500)
+    torch.cuda.synchronize()
+    assert o["status"] == "OK" and o["fallback"] == 1
+    assert o["iters"] == o_ref["iters"] and torch.equal(x, xr)
+    x = x0.clone()
+    o = dd.pcg_solve(prob, b, x, rtol=1e-10, maxit=500)
+    assert o["fallback"] == 0 and torch.equal(x, xr)
+    # inverse iteration: the first inner solve breaks down and is repeated
+    prob = _assemble(case, local_prec=prec)
+    dd.cell_shift(prob)
+    dd.debug_force_breakdown(prob, 1)
+    u = torch.zeros(prob.n_dof, dtype=torch.float64, device="cuda")
+    ur = torch.zeros_like(u)
+    out = dd.inverse_iteration(prob, u, tol_x=1e-9, rtol_inner=1e-10)
+    out_ref = dd.inverse_iteration(ref, ur, tol_x=1e-9, rtol_inner=1e-10)
+    assert out["status"] == "OK" and out["fallback"] == 1 and out_ref["fallback"] == 0
+    assert out["lam"] == out_ref["lam"] and torch.equal(u, ur)
+    # FP64 local solves: the override does nothing
+    p64 = _assemble(case, local_prec="fp64")
+    dd.cell_shift(p64)
+    dd.debug_force_breakdown(p64, 1)
+    x = torch.zeros_like(b)
+    o = dd.pcg_solve(p64, b, x, rtol=1e-10, maxit=500)
+    assert o["status"] == "OK" and o["fallback"] == 0
+    # 3-D: no fallback, the forced breakdown is reported at the first iteration
+    p3 = _assemble(CASES[4], local_prec=prec)
+    dd.cell_shift(p3)
+    dd.debug_force_breakdown(p3, 1)
+    b3 = _dev(torch, W.random_vector(p3.n_dof, 7))
+    x = torch.zeros_like(b3)
+    o = dd.pcg_solve(p3, b3, x, rtol=1e-10, maxit=500, raise_on_error=False)
+    assert o["status"] == "ENOTSPD" and o["fallback"] == 0 and o["iters"] == 0
+    x.zero_()
+    o = dd.pcg_solve(p3, b3, x, rtol=1e-10, maxit=500)
+    assert o["status"] == "OK"
+
+
 def test_inner_maxit_is_enoconv(torch):
     """An inner solve stopped at maxit_inner is not a converged eigenpair:
     inverse_iteration returns ENOCONV and counts the unconverged inner solves,

@@ -59,6 +59,30 @@ def test_pcg_detects_indefinite_operator():
     assert res.status == "not_spd"
 
 
+def test_pcg_detects_indefinite_preconditioner():
+    """r.z <= 0 (an indefinite preconditioner, as a rounded local inverse can
+    make) is reported as not_spd with the iterations done so far: at once for
+    -M^{-1}, after two iterations for a preconditioner whose third application
+    flips sign; the SPD preconditioner itself converges."""
+    P = _P(L=3, ne=4, delta=1)
+    b = P.M @ np.ones(P.grid.n)
+    M = P.preconditioner(True)
+    A = lambda v: P.A_sigma @ v
+    ok = pcg(A, b, M.apply, rtol=1e-10, maxit=500)
+    assert ok.status == "ok" and ok.iters > 3
+    res = pcg(A, b, lambda r: -M.apply(r), rtol=1e-10, maxit=500)
+    assert res.status == "not_spd" and res.iters == 0
+    calls = []
+
+    def flip_third(r):
+        calls.append(1)
+        return -M.apply(r) if len(calls) == 3 else M.apply(r)
+
+    res = pcg(A, b, flip_third, rtol=1e-10, maxit=500)
+    assert res.status == "not_spd" and res.iters == 2
+    assert np.array_equal(res.alphas, ok.alphas[:2])
+
+
 def test_as2_iterations_bounded_in_L_and_as1_grows():
     """§4.1.1 and eq:conditionNumberBound: with the PerFact coarse space the
     spectrum of M^{-1} A_sigma (Ritz estimates) and the CG iteration count stop
