@@ -274,13 +274,22 @@ def run_cpu_baseline(cfgno, tol_x):
     return out
 
 
-def hbm_stencil(dd, W, torch):
-    """The A_sigma stencil on 2-D L = 16384, h = 1/64 (66,060,225 unknowns,
-    1.06 GB per apply: far beyond the Infinity Cache), timed live with HIP
-    events, next to a plain device copy of the same 1.06 GB."""
-    cfg = W.config(2)
-    prob = dd.assemble(1, 1, 16384, 64, cfg["V"], 4, coarse=False, local_prec="fp64")
-    dd.set_shift(prob, 8.857340073504364)
+HBM_WORKLOADS = {
+    # name: (p, q, L, n_e, delta, potential config) -- vectors far beyond the
+    # 256 MB Infinity Cache, so the sweep streams from HBM
+    "2d": ("2d-L16384-ne64", 1, 1, 16384, 64, 4, 2),
+    "3d": ("3d-p1q2-L2048-ne32", 1, 2, 2048, 32, 2, 3),
+}
+
+
+def hbm_stencil(dd, W, torch, which="2d"):
+    """The A_sigma stencil at HBM scale, timed live with HIP events next to a
+    plain device copy of the same bytes: 2-D L = 16384, h = 1/64 (66,060,225
+    unknowns, 1.06 GB per apply) or 3-D p = 1, q = 2, L = 2048, h = 1/32
+    (62,980,096 unknowns, 1.01 GB per apply)."""
+    name, p, q, L, ne, delta, cfgno = HBM_WORKLOADS[which]
+    prob = dd.assemble(p, q, L, ne, W.config(cfgno)["V"], delta, coarse=False, local_prec="fp64")
+    dd.cell_shift(prob)
     n = prob.n_dof
     x = torch.randn(n, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
@@ -295,7 +304,7 @@ def hbm_stencil(dd, W, torch):
     t_copy = e0.elapsed_time(e1) * 1e3 / 20
     del prob, x, y
     torch.cuda.empty_cache()
-    return {"workload": "2d-L16384-ne64 (66,060,225 unknowns)", "launch_us": t_us,
+    return {"workload": f"{name} ({n:,} unknowns)", "launch_us": t_us,
             "bytes_per_launch": nbytes, "achieved": nbytes / t_us / 1e3, "unit": "GB/s",
             "peak": HBM_PEAK_GBS, "frac": nbytes / t_us / 1e3 / HBM_PEAK_GBS,
             "device_copy_same_bytes_GBs": nbytes / t_copy / 1e3}
@@ -553,7 +562,8 @@ def main():
                     "frac": bytes_op / t_op / 1e3 / HBM_PEAK_GBS, "launch_us": t_op,
                     "bytes_per_launch": bytes_op}
     if not args.no_hbm:
-        stencil_roof["hbm_scale"] = hbm_stencil(dd, W, torch)
+        stencil_roof["hbm_scale"] = hbm_stencil(dd, W, torch, "2d")
+        stencil_roof["hbm_scale_3d"] = hbm_stencil(dd, W, torch, "3d")
     if args.calib_copy_mib > 0:
         # plain copy of known size for counter calibration; a larger buffer is
         # written in between so that the source is not in the Infinity Cache

@@ -117,6 +117,9 @@ typedef struct {
   int graphs;      /* 1: each block of batch_iters PCG iterations is captured once into a HIP
                       graph (per first iteration, maxit and iterate pointer) on a stream of the
                       problem and replayed from then on; 0: kernels are launched one by one */
+  int sweep;       /* A_sigma sweep of 2-D grids with n_e dividing 64: 0 by size (the row march
+                      once the grid is 1024 x 512 columns wide, tiles below), 1 tiles, 2 the row
+                      march; the two give identical A_sigma x */
 } ddeig_options;
 
 typedef struct ddeig_problem ddeig_problem;

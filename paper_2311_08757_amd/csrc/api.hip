@@ -945,10 +945,11 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
     return set_error(DDEIG_EINVAL, "ell * n_e must be an integer >= 2");
   if (overlap < 1 || 2 * overlap > ne)
     return set_error(DDEIG_EINVAL, "overlap must satisfy 1 <= overlap and 2 overlap <= n_e");
-  ddeig_options o{0, 1, 0, 8};
+  ddeig_options o{0, 1, 0, 8, 0, 0};
   if (opts) o = *opts;
   if (o.pu < 0 || o.pu > 1 || o.coarse < 0 || o.coarse > 1 || o.local_prec < 0 ||
-      o.local_prec > 3 || o.batch_iters < 0 || o.graphs < 0 || o.graphs > 1)
+      o.local_prec > 3 || o.batch_iters < 0 || o.graphs < 0 || o.graphs > 1 || o.sweep < 0 ||
+      o.sweep > 2)
     return set_error(DDEIG_EINVAL, "invalid options");
 
   ddeig::VSpec vs{};

@@ -436,6 +436,7 @@ namespace ddeig {
 void launch_build_tables(const ddeig_problem* P, hipStream_t s);
 void launch_build_wtable(const ddeig_problem* P, const VSpec* dws, double* tW, hipStream_t s);
 long stencil_tiles(const Geo& g);
+long stencil_blocks(const ddeig_problem* P);
 int stencil2d_ty(const Geo& g);
 void launch_shift_table(const ddeig_problem* P, hipStream_t s);
 // y = T x (T one of the tables); dot / sum != nullptr: partial sums of x.y / of y

@@ -292,9 +292,10 @@ __device__ __forceinline__ int xcd_slab(int b, int n) {
 // z = z0 + w, lane l its nodes x0 + l + 64 s (s < 4).  When n_e divides 64 the
 // four nodes of a lane share one cell-local position, so the 27 table
 // coefficients are loaded once for four nodes: the table, not the vector, is
-// what the 3-D sweep reads most.  Tiles are numbered with z fastest, then x,
-// then y, and handed out by xcd_slab, so an XCD holds a slab of whole x-z
-// planes of tiles and most halo reads hit its L2.  The halo staging is
+// what the 3-D sweep reads most.  Tiles are numbered with z fastest, then the
+// one of x, y with fewer tiles, then the other, and handed out by xcd_slab, so
+// an XCD holds a slab of whole planes of tiles across the two short tile
+// directions and most halo reads hit its L2.  The halo staging is
 // unrolled in rounds of 8 entries per thread, all loads of a round in flight
 // together.  Arithmetic and tap order per node are those of k_stencil<3, MODE>;
 // the block partials are stored by workgroup.
@@ -330,7 +331,9 @@ __global__ void __launch_bounds__(kBlock) k_stencil3d(Geo g, const double* __res
   const int nbx = (N0 + TX - 1) / TX, nby = (N1 + TY - 1) / TY, nbz = (N2 + TZ - 1) / TZ;
   const int tile = xcd_slab(blockIdx.x, nbx * nby * nbz);
   const int bz = tile % nbz, rest = tile / nbz;
-  const int x0 = (rest % nbx) * TX, y0 = (rest / nbx) * TY, z0 = bz * TZ;
+  const bool xmid = nbx <= nby;  // the shorter of x, y runs second fastest
+  const int bx = xmid ? rest % nbx : rest / nby, by = xmid ? rest / nbx : rest % nby;
+  const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
   const long tsize = g.tsize;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
@@ -412,7 +415,11 @@ __global__ void __launch_bounds__(kBlock) k_stencil3d(Geo g, const double* __res
 // k_stencil<2, MODE>.
 // The body takes the block's tile index `bid` (blockIdx.x of a single
 // problem, or the block's index within its instance in a grouped launch).
-template <int MODE, int TY = 8>
+// YFAST numbers the tiles y fastest: with bid = xcd_slab(blockIdx.x) an XCD
+// then holds a run of whole tile columns, so the halo rows a tile shares with
+// its y neighbours come from that XCD's L2 instead of HBM (the grids of these
+// problems are a few tiles tall and very wide).
+template <int MODE, int TY = 8, bool YFAST = false>
 __device__ __forceinline__ void stencil2d_body(const Geo& g, const double* __restrict__ T,
                                                const double* __restrict__ x,
                                                const double* __restrict__ pold,
@@ -436,8 +443,8 @@ __device__ __forceinline__ void stencil2d_body(const Geo& g, const double* __res
     if (bid == 0 && threadIdx.x == 0) dir.st->rho[(dir.k - 1) & 1] = rho;
   }
   const int N0 = g.N[0], N1 = g.N[1];
-  const int nbx = (N0 + TX - 1) / TX;
-  const int bx = bid % nbx, by = bid / nbx;
+  const int nbx = (N0 + TX - 1) / TX, nby = (N1 + TY - 1) / TY;
+  const int bx = YFAST ? bid / nby : bid % nbx, by = YFAST ? bid % nby : bid / nbx;
   const int x0 = bx * TX, y0 = by * TY;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   // cell-local x position of the lane (the same for all its strides)
@@ -518,7 +525,178 @@ __global__ void __launch_bounds__(kBlock) k_stencil2d(Geo g, const double* __res
                                                       double* __restrict__ pnew,
                                                       double* __restrict__ y, DirArgs dir,
                                                       int use_dot, Red dot, int use_sum, Red sum) {
-  stencil2d_body<MODE, TY>(g, T, x, pold, pnew, y, dir, use_dot, dot, use_sum, sum, blockIdx.x);
+  stencil2d_body<MODE, TY, true>(g, T, x, pold, pnew, y, dir, use_dot, dot, use_sum, sum,
+                                 xcd_slab(blockIdx.x, gridDim.x));
+}
+
+// The 2-D sweep of wide grids (n_e dividing 64): one wave per workgroup owns
+// kMarchX = 512 columns, lane l the columns x0 + l + 64 s (s < 8), which share
+// one cell-local position and so every table coefficient the lane loads, and
+// marches through all N1 rows.  With input row k staged in LDS (plus its two
+// halo columns) the lane adds taps 6..8 to output row k - 1, taps 3..5 to row
+// k and taps 0..2 to row k + 1; every output so receives its taps in the
+// order t = 0..8 of the tile sweep, from the same values, and equals the tile
+// sweep's result bit for bit.  Row k - 1 is then complete and stored.  Each
+// input row is read once (tiles re-read their halo rows), and the next row
+// and the next step's coefficients are loaded one step ahead into registers:
+// this is the sweep that streams wide grids at near-copy bandwidth.
+// Loads use clamped in-range addresses; the masks (Dirichlet ends, columns
+// past N0) are applied when a row is staged.  MODE 1 stages
+// p_k = z + beta p_{k-1} as the tile sweep does, writes the owned entries of
+// p_k and forms the partials of p_k.q; one partial per workgroup.
+constexpr int kMarchRX = 8, kMarchX = 64 * kMarchRX;
+
+template <int MODE>
+__global__ void __launch_bounds__(64) k_stencil2d_march(Geo g, const double* __restrict__ T,
+                                                        const double* __restrict__ x,
+                                                        const double* __restrict__ pold,
+                                                        double* __restrict__ pnew,
+                                                        double* __restrict__ y, DirArgs dir,
+                                                        int use_dot, Red dot, int use_sum, Red sum) {
+  constexpr int RX = kMarchRX, TX = kMarchX, HX = TX + 2;
+  __shared__ double rows[2][HX];
+  double beta = 0.0;
+  if constexpr (MODE == 1) {
+    const double rho = sum_partials<64>(dir.rz.part, dir.rz.np);
+    if (dir.st->done) return;
+    if (!(rho > 0.0) || !(rho > dir.st->rz_floor)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        dir.st->done = 3;
+        dir.st->iters = dir.k - 1;
+      }
+      return;
+    }
+    if (dir.k > 1) beta = rho / dir.st->rho[(dir.k - 2) & 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) dir.st->rho[(dir.k - 1) & 1] = rho;
+  }
+  const bool upd = MODE == 1 && dir.k > 1;
+  const int N0 = g.N[0], N1 = g.N[1];
+  const int x0 = xcd_slab(blockIdx.x, gridDim.x) * TX;
+  const int lane = threadIdx.x;
+  const int j0 = (int)((unsigned)(x0 + lane + 1) - g.ne * fdiv((unsigned)(x0 + lane + 1), g.fne));
+  const long tsize = g.tsize;
+  const int P0 = g.P[0];
+  // lane 0 stages the halo column x0 - 1, lane 1 the column x0 + TX
+  const int hx = lane == 0 ? x0 - 1 : x0 + TX;
+  const bool hin = lane < 2 && hx >= 0 && hx < N0;
+  const long hxc = hin ? hx : x0;
+  bool in[RX];
+  long xs[RX];
+#pragma unroll
+  for (int s = 0; s < RX; ++s) {
+    in[s] = x0 + lane + 64 * s < N0;
+    xs[s] = in[s] ? x0 + lane + 64 * s : x0;
+  }
+  double bx[RX + 1], bp[RX + 1];
+  auto load_row = [&](int r) {
+    const long ro = (long)N0 * min(r, N1 - 1);
+#pragma unroll
+    for (int s = 0; s < RX; ++s) bx[s] = x[xs[s] + ro];
+    bx[RX] = x[hxc + ro];
+    if (upd) {
+#pragma unroll
+      for (int s = 0; s < RX; ++s) bp[s] = pold[xs[s] + ro];
+      bp[RX] = pold[hxc + ro];
+    }
+  };
+  // coefficients of the taps that input row k gives to output rows k - 1, k,
+  // k + 1 (row indices clamped: the sums of rows -1 and N1 are never used)
+  auto coef = [&](int k, double* c) {
+    const double* tm = T + j0 + (long)P0 * max(k - 1, 0);
+    const double* t0 = T + j0 + (long)P0 * min(k, N1 - 1);
+    const double* tp = T + j0 + (long)P0 * min(k + 1, N1 - 1);
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      c[t] = tm[(6 + t) * tsize];
+      c[3 + t] = t0[(3 + t) * tsize];
+      c[6 + t] = tp[t * tsize];
+    }
+  };
+  double cn[9];
+  load_row(0);
+  coef(0, cn);
+  double am[RX], a0[RX], ap[RX], vp[RX];
+#pragma unroll
+  for (int s = 0; s < RX; ++s) {
+    am[s] = 0.0;
+    a0[s] = 0.0;
+    ap[s] = 0.0;
+    vp[s] = 0.0;
+  }
+  double acc = 0.0, accs = 0.0;
+  for (int k = 0; k < N1; ++k) {
+    double* rw = rows[k & 1];
+    double vc[RX];
+#pragma unroll
+    for (int s = 0; s < RX; ++s) {
+      double v = bx[s];
+      if (upd) v += beta * bp[s];
+      v = in[s] ? v : 0.0;
+      vc[s] = v;
+      rw[1 + lane + 64 * s] = v;
+      if constexpr (MODE == 1) {
+        if (in[s]) pnew[xs[s] + (long)N0 * k] = v;
+      }
+    }
+    if (lane < 2) {
+      double v = bx[RX];
+      if (upd) v += beta * bp[RX];
+      rw[lane == 0 ? 0 : HX - 1] = hin ? v : 0.0;
+    }
+    double c[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) c[t] = cn[t];
+    coef(k + 1, cn);
+    load_row(k + 1);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < RX; ++s) {
+      const int cx = 1 + lane + 64 * s;
+      const double vl = rw[cx - 1], vm = rw[cx], vr = rw[cx + 1];
+      if (k > 0) {
+        am[s] += c[0] * vl;
+        am[s] += c[1] * vm;
+        am[s] += c[2] * vr;
+      }
+      a0[s] += c[3] * vl;
+      a0[s] += c[4] * vm;
+      a0[s] += c[5] * vr;
+      if (k + 1 < N1) {
+        ap[s] += c[6] * vl;
+        ap[s] += c[7] * vm;
+        ap[s] += c[8] * vr;
+      }
+    }
+    if (k > 0) {
+#pragma unroll
+      for (int s = 0; s < RX; ++s) {
+        if (!in[s]) continue;
+        double* yp = &y[xs[s] + (long)N0 * (k - 1)];
+        if constexpr (MODE == 0) __builtin_nontemporal_store(am[s], yp);
+        else *yp = am[s];
+        acc += vp[s] * am[s];
+        accs += am[s];
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < RX; ++s) {
+      am[s] = a0[s];
+      a0[s] = ap[s];
+      ap[s] = 0.0;
+      vp[s] = vc[s];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < RX; ++s) {
+    if (!in[s]) continue;
+    double* yp = &y[xs[s] + (long)N0 * (N1 - 1)];
+    if constexpr (MODE == 0) __builtin_nontemporal_store(am[s], yp);
+    else *yp = am[s];
+    acc += vp[s] * am[s];
+    accs += am[s];
+  }
+  if (use_dot) write_partial<64>(acc, dot.part);
+  if (use_sum) write_partial<64>(accs, sum.part);
 }
 
 // Grouped direction update + A_sigma p of PCG iteration k over the instances
@@ -552,6 +730,21 @@ int stencil2d_ty(const Geo& g) {
 }
 
 static bool stencil2d_fast(const Geo& g) { return g.D == 2 && 64 % g.ne == 0; }
+
+// The row march serves 2-D grids with n_e dividing 64 whose width gives at
+// least 1024 of its 512-column workgroups (ddeig_options.sweep 0), or on
+// request (sweep 2); sweep 1 keeps the tiles.
+static bool stencil2d_march(const ddeig_problem* P) {
+  const Geo& g = P->g;
+  if (!stencil2d_fast(g) || P->opt.sweep == 1) return false;
+  return P->opt.sweep == 2 || (g.N[0] + kMarchX - 1) / kMarchX >= 1024;
+}
+
+// Workgroups (and block partials) of the sweep launch_stencil runs.
+long stencil_blocks(const ddeig_problem* P) {
+  if (stencil2d_march(P)) return (P->g.N[0] + kMarchX - 1) / kMarchX;
+  return stencil_tiles(P->g);
+}
 
 long stencil_tiles(const Geo& g) {
   if (stencil2d_fast(g)) {
@@ -603,13 +796,17 @@ static void finish_tile_red(const ddeig_problem* P, const TileRed& t, hipStream_
 
 void launch_stencil(const ddeig_problem* P, const double* tab, const double* x, double* y,
                     Red* dot, Red* sum, hipStream_t s) {
-  const long tiles = stencil_tiles(P->g);
+  const long tiles = stencil_blocks(P);
   const Red none{nullptr, 0, nullptr};
   const DirArgs nodir{nullptr, 0, none};
   const TileRed td = tile_red(P, dot ? *dot : none, tiles, 0);
   const TileRed ts = tile_red(P, sum ? *sum : none, tiles, 1);
   const int blocks = (int)std::max<long>(1, tiles);
-  if (stencil2d_fast(P->g)) {
+  if (stencil2d_march(P)) {
+    hipLaunchKernelGGL(k_stencil2d_march<0>, dim3(blocks), dim3(64), 0, s, P->g, tab, x, nullptr,
+                       nullptr, y, nodir, dot ? 1 : 0, td.use, sum ? 1 : 0, ts.use);
+  }
+  else if (stencil2d_fast(P->g)) {
     auto kern = stencil2d_ty(P->g) == 4 ? k_stencil2d<0, 4> : k_stencil2d<0, 8>;
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, P->g, tab, x, nullptr, nullptr, y,
                        nodir, dot ? 1 : 0, td.use, sum ? 1 : 0, ts.use);
@@ -632,11 +829,15 @@ void launch_stencil(const ddeig_problem* P, const double* tab, const double* x, 
 
 void launch_stencil_dir(const ddeig_problem* P, const double* z, const double* pold, double* pnew,
                         double* q, const DirArgs& dir, Red& gam, hipStream_t s) {
-  const long tiles = stencil_tiles(P->g);
+  const long tiles = stencil_blocks(P);
   const Red none{nullptr, 0, nullptr};
   const TileRed tg = tile_red(P, gam, tiles, 0);
   const int blocks = (int)std::max<long>(1, tiles);
-  if (stencil2d_fast(P->g)) {
+  if (stencil2d_march(P)) {
+    hipLaunchKernelGGL(k_stencil2d_march<1>, dim3(blocks), dim3(64), 0, s, P->g, P->tabAs, z,
+                       pold, pnew, q, dir, 1, tg.use, 0, none);
+  }
+  else if (stencil2d_fast(P->g)) {
     auto kern = stencil2d_ty(P->g) == 4 ? k_stencil2d<1, 4> : k_stencil2d<1, 8>;
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, P->g, P->tabAs, z, pold, pnew, q,
                        dir, 1, tg.use, 0, none);

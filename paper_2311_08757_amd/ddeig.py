@@ -45,7 +45,7 @@ class Potential(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("pu", ctypes.c_int), ("coarse", ctypes.c_int), ("local_prec", ctypes.c_int),
-                ("batch_iters", ctypes.c_int), ("graphs", ctypes.c_int)]
+                ("batch_iters", ctypes.c_int), ("graphs", ctypes.c_int), ("sweep", ctypes.c_int)]
 
 
 class PcgInfo(ctypes.Structure):
@@ -235,15 +235,16 @@ def _potential(spec):
 
 
 def assemble(p, q, L, ne, V, delta, ell=1, pu="equal", coarse=True, local_prec="fp64",
-             batch_iters=8, graphs=False, stream=None):
-    """ddeig_assemble: geometry (0,L)^p x (0,ell)^q, h = 1/ne, potential dict V."""
+             batch_iters=8, graphs=False, stream=None, sweep="auto"):
+    """ddeig_assemble: geometry (0,L)^p x (0,ell)^q, h = 1/ne, potential dict V;
+    sweep: the A_sigma sweep ("auto", "tiles" or "march")."""
     import torch
     lib = load_library()
     geom = Geometry(p, q, L, float(ell))
     Vs, keep = _potential(V)
     opts = Options({"equal": 0, "distance": 1}[pu], 1 if coarse else 0,
                    {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16": 3}[local_prec], batch_iters,
-                   1 if graphs else 0)
+                   1 if graphs else 0, {"auto": 0, "tiles": 1, "march": 2}[sweep])
     if stream is None:
         stream = torch.cuda.current_stream()
     handle = ctypes.c_void_p()

@@ -1,0 +1,153 @@
+"""The row-march A_sigma sweep of wide 2-D grids (ddeig_options.sweep 2, and
+the size-based choice once a grid is 1024 x 512 columns wide) against the
+tile sweep and the oracle.
+
+- A_sigma x, A x, M x and K x from the march equal the tile sweep's bit for bit
+  (every output takes its taps in the same order from the same values), on
+  grids of one ragged workgroup, of several workgroups with a ragged last one,
+  and at the 66,060,225-unknown HBM-scale grid (sweep chosen by size) over the
+  whole vector;
+- at that size, sampled rows of A_sigma x against the oracle: the operator is
+  periodic in x with the period cell's coefficients, so the row of node (i, j)
+  is the row of the node with the same cell-local position in a small oracle
+  problem on the same cell (the Dirichlet end nodes map to the small
+  problem's end nodes); 1e-13 of the row's absolute sum times max |x|;
+- the fused direction-update sweep inside PCG: iteration counts within +-1 of
+  the oracle's PCG, the true residual below 1.1 rtol, residual histories to
+  1e-6, and the eigenpair of inverse iteration to 1e-10 / 1e-8 (M-norm).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # p, q, L, ne, delta, potential
+    (1, 1, 4, 8, 2, W.sep_fourier(1000)),    # 31 columns: one ragged workgroup
+    (1, 1, 130, 8, 2, W.sep_fourier(17)),    # 1039 columns: 512 + 512 + 15
+    (1, 1, 67, 16, 4, W.sin4()),             # 1071 columns, 15 rows
+]
+IDS = [f"L{c[2]}-ne{c[3]}-d{c[4]}-{c[5]['kind']}" for c in CASES]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+def _oracle(case):
+    from oracle.problem import Problem
+    p, q, L, ne, delta, V = case
+    return Problem(W.small_config(p, q, L, ne, delta, V))
+
+
+def _dev(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _assemble(case, sweep, **kw):
+    import paper_2311_08757_amd as dd
+    p, q, L, ne, delta, V = case
+    return dd.assemble(p, q, L, ne, V, delta, sweep=sweep, **kw)
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_march_equals_tiles(torch, case):
+    import paper_2311_08757_amd as dd
+    pm, pt = _assemble(case, "march"), _assemble(case, "tiles")
+    sig, psi = dd.cell_shift(pt)
+    dd.set_shift(pm, sig, psi)
+    x = _dev(torch, W.random_vector(pm.n_dof, 5))
+    for op in ("A_sigma", "A", "M", "K"):
+        ym, yt = torch.empty_like(x), torch.empty_like(x)
+        dd.apply_op(pm, op, x, ym)
+        dd.apply_op(pt, op, x, yt)
+        torch.cuda.synchronize()
+        assert torch.equal(ym, yt), op
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_march_pcg_and_eigenpair(torch, case):
+    import paper_2311_08757_amd as dd
+    from oracle.pcg import pcg
+    from oracle.ipm import inverse_iteration_direct
+    P = _oracle(case)
+    prob = _assemble(case, "march")
+    dd.set_shift(prob, P.sigma, P.cell["psi"])
+    b = W.random_vector(P.grid.n, 8)
+    x = torch.zeros(P.grid.n, dtype=torch.float64, device="cuda")
+    out = dd.pcg_solve(prob, _dev(torch, b), x, rtol=1e-10, maxit=500, hist_cap=501)
+    ref = pcg(lambda v: P.A_sigma @ v, b, P.preconditioner(True).apply, rtol=1e-10, maxit=500)
+    assert abs(out["iters"] - ref.iters) <= 1
+    xs = x.cpu().numpy()
+    assert np.linalg.norm(b - P.A_sigma @ xs) <= 1.1e-10 * np.linalg.norm(b)
+    k = min(out["iters"], ref.iters)
+    assert np.allclose(out["hist"][:k + 1], ref.hist[:k + 1], rtol=1e-6, atol=1e-13)
+    prob = _assemble(case, "march")
+    dd.cell_shift(prob)
+    u = torch.zeros(P.grid.n, dtype=torch.float64, device="cuda")
+    eo = dd.inverse_iteration(prob, u, tol_x=1e-9, rtol_inner=1e-10)
+    er = inverse_iteration_direct(P.A, P.M, P.sigma, P.grid)
+    assert abs(eo["lam"] - er["lam"]) <= 1e-10 * abs(er["lam"])
+    d = u.cpu().numpy() - er["x"]
+    assert np.sqrt(d @ (P.M @ d)) <= 1e-8
+
+
+def test_march_hbm_scale(torch):
+    """The 2-D grid L = 16384, h = 1/64 (1,048,575 x 63 unknowns): the sweep
+    chosen by size is the march; whole-vector equality with the tile sweep and
+    sampled rows against the oracle."""
+    import paper_2311_08757_amd as dd
+    from oracle.problem import Problem
+    cfg = W.config(2)
+    L, ne, delta, V = 16384, 64, 4, cfg["V"]
+    case = (1, 1, L, ne, delta, V)
+    pa = _assemble(case, "auto", coarse=False)
+    sig, psi = dd.cell_shift(pa)
+    n = pa.n_dof
+    N0, N1 = L * ne - 1, ne - 1
+    assert n == N0 * N1
+    x = torch.randn(n, dtype=torch.float64, device="cuda",
+                    generator=torch.Generator(device="cuda").manual_seed(3))
+    ya = torch.empty_like(x)
+    dd.apply_op(pa, "A_sigma", x, ya)
+    torch.cuda.synchronize()
+    ys = ya.cpu().numpy()
+    xh = x.cpu().numpy()
+    del pa
+    pt = _assemble(case, "tiles", coarse=False)
+    dd.set_shift(pt, sig, psi)
+    yt = torch.empty_like(x)
+    dd.apply_op(pt, "A_sigma", x, yt)
+    torch.cuda.synchronize()
+    assert torch.equal(ya, yt)
+    del pt, yt
+    # sampled rows against a small oracle problem on the same period cell
+    Ls = 4
+    Ps = Problem(W.small_config(1, 1, Ls, ne, delta, V))
+    N0s = Ls * ne - 1
+    As = (Ps.A - sig * Ps.M).tocsr()
+    rng = np.random.default_rng(21)
+    ii = np.concatenate([[0, 1, N0 - 2, N0 - 1], rng.integers(0, N0, size=1020)])
+    jj = np.concatenate([[0, N1 - 1, 0, N1 - 1], rng.integers(0, N1, size=1020)])
+    xmax = float(np.max(np.abs(xh)))
+    for i, j in zip(ii, jj):
+        if i == 0:
+            i_s = 0
+        elif i == N0 - 1:
+            i_s = N0s - 1
+        else:
+            i_s = ne + (i + 1) % ne - 1
+        row = As.getrow(i_s + N0s * j)
+        cols = row.indices
+        d0 = cols % N0s - i_s
+        d1 = cols // N0s - j
+        big = (i + d0) + N0 * (j + d1)
+        expect = float(row.data @ xh[big])
+        bar = 1e-13 * float(np.abs(row.data).sum()) * xmax
+        assert abs(ys[i + N0 * j] - expect) <= bar, (i, j)
