@@ -117,9 +117,11 @@ typedef struct {
   int graphs;      /* 1: each block of batch_iters PCG iterations is captured once into a HIP
                       graph (per first iteration, maxit and iterate pointer) on a stream of the
                       problem and replayed from then on; 0: kernels are launched one by one */
-  int sweep;       /* A_sigma sweep of 2-D grids with n_e dividing 64: 0 by size (the row march
-                      once the grid is 1024 x 512 columns wide, tiles below), 1 tiles, 2 the row
-                      march; the two give identical A_sigma x */
+  int sweep;       /* A_sigma sweep: 0 by size, 1 tiles, 2 march.  2-D grids with n_e dividing
+                      64: the row march (512 columns per workgroup) once the grid has >= 1024
+                      such column blocks; 3-D grids with n_e dividing 32 and 8 n < 2^31: the
+                      plane march (256 x 8 lines per workgroup) once there are >= 1024 such
+                      blocks.  Tiles and march give identical A_sigma x */
 } ddeig_options;
 
 typedef struct ddeig_problem ddeig_problem;

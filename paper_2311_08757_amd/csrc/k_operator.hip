@@ -699,6 +699,189 @@ __global__ void __launch_bounds__(64) k_stencil2d_march(Geo g, const double* __r
   if (use_sum) write_partial<64>(accs, sum.part);
 }
 
+// The 3-D sweep of wide grids (n_e dividing 32): a workgroup owns a 256 x 8
+// block of (x, y) lines and marches through all N2 planes.  Lane l of wave w
+// takes the row y0 + 2 w + l / 32 and the columns x0 + l % 32 + 32 s (s < 8),
+// which share one cell-local position, so each of the 27 table coefficients a
+// lane loads per plane serves eight outputs.  With input plane k staged in LDS
+// (the block plus a one-node halo in x and y) every lane adds taps 18..26 to
+// its outputs in plane k - 1, taps 9..17 to plane k and taps 0..8 to plane
+// k + 1: each output receives its taps in the order t = 0..26 of the tile
+// sweep, from the same values, and equals the tile sweep's result bit for
+// bit.  Plane k - 1 is then complete and stored.  Each plane of the block is
+// read once and the next plane is loaded one step ahead; the loads are buffer
+// loads whose per-lane offsets stay in one register each (the tap and plane
+// offsets ride in scalar registers), from clamped in-range offsets, the masks
+// applied when a plane is staged.  MODE 1 stages p_k = z + beta p_{k-1} as
+// the tile sweep does, writes the owned entries of p_k and forms the partials
+// of p_k.q.  One partial per workgroup; needs 8 N < 2^31 (stencil3d_march).
+constexpr int kPlaneTX = 256, kPlaneTY = 8;
+
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_stencil3d_march(Geo g, const double* __restrict__ T,
+                                                            const double* __restrict__ x,
+                                                            const double* __restrict__ pold,
+                                                            double* __restrict__ pnew,
+                                                            double* __restrict__ y, DirArgs dir,
+                                                            int use_dot, Red dot, int use_sum, Red sum) {
+  constexpr int TX = kPlaneTX, TY = kPlaneTY, HX = TX + 2, HY = TY + 2, NH = HX * HY, RX = 8;
+  constexpr int NS = (NH + kBlock - 1) / kBlock;
+  static_assert(TY == 2 * (kBlock / 64) && TX == 32 * RX, "two rows per wave, 32 lanes per row");
+  __shared__ double pl[2][NH];
+  double beta = 0.0;
+  if constexpr (MODE == 1) {
+    const double rho = sum_partials(dir.rz.part, dir.rz.np);
+    if (dir.st->done) return;
+    if (!(rho > 0.0) || !(rho > dir.st->rz_floor)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        dir.st->done = 3;
+        dir.st->iters = dir.k - 1;
+      }
+      return;
+    }
+    if (dir.k > 1) beta = rho / dir.st->rho[(dir.k - 2) & 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) dir.st->rho[(dir.k - 1) & 1] = rho;
+  }
+  const bool upd = MODE == 1 && dir.k > 1;
+  const int N0 = g.N[0], N1 = g.N[1], N2 = g.N[2];
+  const long N01 = (long)N0 * N1;
+  const int nby = (N1 + TY - 1) / TY;
+  const int bid = xcd_slab(blockIdx.x, gridDim.x);
+  const int x0 = (bid / nby) * TX, y0 = (bid % nby) * TY;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int xl = lane & 31, ty = 2 * w + (lane >> 5);
+  const unsigned tsz8 = (unsigned)(g.tsize * 8);
+  const unsigned pp8 = (unsigned)(g.P[0] * g.P[1] * 8);
+  const unsigned pl8 = (unsigned)(N01 * 8);
+  const int nbytes = (int)(N01 * N2 * 8);
+  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc((void*)x, (short)0, nbytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc((void*)pold, (short)0, nbytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc((void*)T, (short)0,
+                                                                      (int)(27 * g.tsize * 8), 0x00020000);
+  const int j0 = (int)((unsigned)(x0 + xl + 1) - g.ne * fdiv((unsigned)(x0 + xl + 1), g.fne));
+  const int gy = y0 + ty;
+  const bool rowin = gy < N1;
+  const int gyc = min(gy, N1 - 1);
+  const int j1 = g.isx[1] ? (int)((unsigned)(gyc + 1) - g.ne * fdiv((unsigned)(gyc + 1), g.fne)) : gyc;
+  const unsigned coff = (unsigned)(j0 + g.P[0] * j1) * 8u;
+  // staging slots of this thread: in-plane offsets (0 when outside the grid),
+  // in-grid and owned masks
+  unsigned voff[NS];
+  unsigned inm = 0, own = 0;
+#pragma unroll
+  for (int u = 0; u < NS; ++u) {
+    const int e = threadIdx.x + kBlock * u;
+    const int ex = e % HX, ey = e / HX;
+    const int gx = x0 - 1 + ex, gyy = y0 - 1 + ey;
+    const bool in = e < NH && gx >= 0 && gx < N0 && gyy >= 0 && gyy < N1;
+    voff[u] = in ? (unsigned)(gx + N0 * gyy) * 8u : 0u;
+    inm |= in ? (1u << u) : 0u;
+    own |= (in && ex >= 1 && ex <= TX && ey >= 1 && ey <= TY) ? (1u << u) : 0u;
+  }
+  double nx[NS], np[NS];
+#pragma unroll
+  for (int u = 0; u < NS; ++u) {
+    nx[u] = buf_load(rx, voff[u], 0);
+    if (upd) np[u] = buf_load(rp, voff[u], 0);
+  }
+  double am[RX], a0[RX], ap[RX], vc[RX], vp[RX];
+#pragma unroll
+  for (int s = 0; s < RX; ++s) {
+    am[s] = 0.0;
+    a0[s] = 0.0;
+    ap[s] = 0.0;
+    vp[s] = 0.0;
+  }
+  double acc = 0.0, accs = 0.0;
+  for (int k = 0; k < N2; ++k) {
+    double* P = pl[k & 1];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int e = threadIdx.x + kBlock * u;
+      if (e >= NH) continue;
+      double v = nx[u];
+      if (upd) v += beta * np[u];
+      v = (inm >> u) & 1 ? v : 0.0;
+      P[e] = v;
+      if constexpr (MODE == 1) {
+        if ((own >> u) & 1) pnew[voff[u] / 8 + N01 * k] = v;
+      }
+    }
+    if (k + 1 < N2) {
+#pragma unroll
+      for (int u = 0; u < NS; ++u) {
+        nx[u] = buf_load(rx, voff[u], pl8 * (k + 1));
+        if (upd) np[u] = buf_load(rp, voff[u], pl8 * (k + 1));
+      }
+    }
+    // coefficients of the taps plane k gives to planes k - 1, k, k + 1 (plane
+    // indices clamped: the sums of planes -1 and N2 are never used)
+    double c[27];
+    {
+      const unsigned om = pp8 * (unsigned)max(k - 1, 0), o0 = pp8 * (unsigned)k,
+                     op = pp8 * (unsigned)min(k + 1, N2 - 1);
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        c[t] = buf_load(rt, coff, (18 + t) * tsz8 + om);
+        c[9 + t] = buf_load(rt, coff, (9 + t) * tsz8 + o0);
+        c[18 + t] = buf_load(rt, coff, t * tsz8 + op);
+      }
+    }
+    __syncthreads();
+    if (rowin) {
+#pragma unroll
+      for (int s = 0; s < RX; ++s) {
+        const int cx = xl + 32 * s + 1;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          const double v = P[(cx + t % 3 - 1) + HX * (ty + t / 3)];
+          if (t == 4) vc[s] = v;
+          am[s] += c[t] * v;
+          a0[s] += c[9 + t] * v;
+          ap[s] += c[18 + t] * v;
+        }
+      }
+      if (k > 0) {
+#pragma unroll
+        for (int s = 0; s < RX; ++s) {
+          const int gx = x0 + xl + 32 * s;
+          if (gx >= N0) continue;
+          double* yp = &y[gx + (long)N0 * gy + N01 * (k - 1)];
+          if constexpr (MODE == 0) __builtin_nontemporal_store(am[s], yp);
+          else *yp = am[s];
+          acc += vp[s] * am[s];
+          accs += am[s];
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < RX; ++s) {
+        am[s] = a0[s];
+        a0[s] = ap[s];
+        ap[s] = 0.0;
+        vp[s] = vc[s];
+      }
+    }
+  }
+  if (rowin) {
+#pragma unroll
+    for (int s = 0; s < RX; ++s) {
+      const int gx = x0 + xl + 32 * s;
+      if (gx >= N0) continue;
+      double* yp = &y[gx + (long)N0 * gy + N01 * (N2 - 1)];
+      if constexpr (MODE == 0) __builtin_nontemporal_store(am[s], yp);
+      else *yp = am[s];
+      acc += vp[s] * am[s];
+      accs += am[s];
+    }
+  }
+  if (use_dot) write_partial(acc, dot.part);
+  if (use_sum) write_partial(accs, sum.part);
+}
+
 // Grouped direction update + A_sigma p of PCG iteration k over the instances
 // of a batch: block b runs tile map[b].y of instance map[b].x.
 __global__ void __launch_bounds__(kBlock) k_b_stencil_dir(const InstDev* __restrict__ I,
@@ -733,16 +916,31 @@ static bool stencil2d_fast(const Geo& g) { return g.D == 2 && 64 % g.ne == 0; }
 
 // The row march serves 2-D grids with n_e dividing 64 whose width gives at
 // least 1024 of its 512-column workgroups (ddeig_options.sweep 0), or on
-// request (sweep 2); sweep 1 keeps the tiles.
+// request (sweep 2); sweep 1 keeps the tiles (in 3-D as well).
 static bool stencil2d_march(const ddeig_problem* P) {
   const Geo& g = P->g;
   if (!stencil2d_fast(g) || P->opt.sweep == 1) return false;
   return P->opt.sweep == 2 || (g.N[0] + kMarchX - 1) / kMarchX >= 1024;
 }
 
+// The plane march serves 3-D grids with n_e dividing 32 whose (x, y) extent
+// gives at least 1024 of its 256 x 8 blocks (sweep 0), or on request (sweep 2);
+// its buffer offsets need 8 N < 2^31.
+static long stencil3d_march_blocks(const Geo& g) {
+  return (long)((g.N[0] + kPlaneTX - 1) / kPlaneTX) * ((g.N[1] + kPlaneTY - 1) / kPlaneTY);
+}
+
+static bool stencil3d_march(const ddeig_problem* P) {
+  const Geo& g = P->g;
+  if (g.D != 3 || 32 % g.ne != 0 || P->opt.sweep == 1) return false;
+  if (g.n * 8 >= (1L << 31) || 27 * g.tsize * 8 >= (1L << 31)) return false;
+  return P->opt.sweep == 2 || stencil3d_march_blocks(g) >= 1024;
+}
+
 // Workgroups (and block partials) of the sweep launch_stencil runs.
 long stencil_blocks(const ddeig_problem* P) {
   if (stencil2d_march(P)) return (P->g.N[0] + kMarchX - 1) / kMarchX;
+  if (stencil3d_march(P)) return stencil3d_march_blocks(P->g);
   return stencil_tiles(P->g);
 }
 
@@ -806,6 +1004,10 @@ void launch_stencil(const ddeig_problem* P, const double* tab, const double* x, 
     hipLaunchKernelGGL(k_stencil2d_march<0>, dim3(blocks), dim3(64), 0, s, P->g, tab, x, nullptr,
                        nullptr, y, nodir, dot ? 1 : 0, td.use, sum ? 1 : 0, ts.use);
   }
+  else if (stencil3d_march(P)) {
+    hipLaunchKernelGGL(k_stencil3d_march<0>, dim3(blocks), dim3(kBlock), 0, s, P->g, tab, x,
+                       nullptr, nullptr, y, nodir, dot ? 1 : 0, td.use, sum ? 1 : 0, ts.use);
+  }
   else if (stencil2d_fast(P->g)) {
     auto kern = stencil2d_ty(P->g) == 4 ? k_stencil2d<0, 4> : k_stencil2d<0, 8>;
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, P->g, tab, x, nullptr, nullptr, y,
@@ -835,6 +1037,10 @@ void launch_stencil_dir(const ddeig_problem* P, const double* z, const double* p
   const int blocks = (int)std::max<long>(1, tiles);
   if (stencil2d_march(P)) {
     hipLaunchKernelGGL(k_stencil2d_march<1>, dim3(blocks), dim3(64), 0, s, P->g, P->tabAs, z,
+                       pold, pnew, q, dir, 1, tg.use, 0, none);
+  }
+  else if (stencil3d_march(P)) {
+    hipLaunchKernelGGL(k_stencil3d_march<1>, dim3(blocks), dim3(kBlock), 0, s, P->g, P->tabAs, z,
                        pold, pnew, q, dir, 1, tg.use, 0, none);
   }
   else if (stencil2d_fast(P->g)) {

@@ -1,5 +1,5 @@
-"""The row-march A_sigma sweep of wide 2-D grids (ddeig_options.sweep 2, and
-the size-based choice once a grid is 1024 x 512 columns wide) against the
+"""The march A_sigma sweeps of wide grids (the 2-D row march and the 3-D
+plane march; ddeig_options.sweep 2, and the size-based choice) against the
 tile sweep and the oracle.
 
 - A_sigma x, A x, M x and K x from the march equal the tile sweep's bit for bit
@@ -11,7 +11,9 @@ tile sweep and the oracle.
   periodic in x with the period cell's coefficients, so the row of node (i, j)
   is the row of the node with the same cell-local position in a small oracle
   problem on the same cell (the Dirichlet end nodes map to the small
-  problem's end nodes); 1e-13 of the row's absolute sum times max |x|;
+  problem's end nodes); 1e-13 of the row's absolute sum times max |x|; the
+  same for the 3-D plane march (p = 1, q = 2, L = 2048, h = 1/32, 62,979,135
+  unknowns) and on small 3-D grids (one expanding axis and two);
 - the fused direction-update sweep inside PCG: iteration counts within +-1 of
   the oracle's PCG, the true residual below 1.1 rtol, residual histories to
   1e-6, and the eigenpair of inverse iteration to 1e-10 / 1e-8 (M-norm).
@@ -28,8 +30,11 @@ CASES = [
     (1, 1, 4, 8, 2, W.sep_fourier(1000)),    # 31 columns: one ragged workgroup
     (1, 1, 130, 8, 2, W.sep_fourier(17)),    # 1039 columns: 512 + 512 + 15
     (1, 1, 67, 16, 4, W.sin4()),             # 1071 columns, 15 rows
+    (1, 2, 3, 4, 1, W.sep_fourier(3000)),    # 3-D: one ragged 256 x 8 block
+    (1, 2, 70, 8, 2, W.sep_fourier(7)),      # 3-D: 559 columns in 3 blocks, 7 x 7 lines
+    (2, 1, 3, 4, 1, W.fourier2(4000)),       # 3-D, two expanding axes (y periodic table)
 ]
-IDS = [f"L{c[2]}-ne{c[3]}-d{c[4]}-{c[5]['kind']}" for c in CASES]
+IDS = [f"p{c[0]}q{c[1]}-L{c[2]}-ne{c[3]}-d{c[4]}-{c[5]['kind']}" for c in CASES]
 
 
 @pytest.fixture(scope="module")
@@ -83,7 +88,7 @@ def test_march_pcg_and_eigenpair(torch, case):
     x = torch.zeros(P.grid.n, dtype=torch.float64, device="cuda")
     out = dd.pcg_solve(prob, _dev(torch, b), x, rtol=1e-10, maxit=500, hist_cap=501)
     ref = pcg(lambda v: P.A_sigma @ v, b, P.preconditioner(True).apply, rtol=1e-10, maxit=500)
-    assert abs(out["iters"] - ref.iters) <= 1
+    assert abs(out["iters"] - ref.iters) <= (1 if P.grid.d == 2 else 2)
     xs = x.cpu().numpy()
     assert np.linalg.norm(b - P.A_sigma @ xs) <= 1.1e-10 * np.linalg.norm(b)
     k = min(out["iters"], ref.iters)
@@ -92,26 +97,23 @@ def test_march_pcg_and_eigenpair(torch, case):
     dd.cell_shift(prob)
     u = torch.zeros(P.grid.n, dtype=torch.float64, device="cuda")
     eo = dd.inverse_iteration(prob, u, tol_x=1e-9, rtol_inner=1e-10)
-    er = inverse_iteration_direct(P.A, P.M, P.sigma, P.grid)
+    er = inverse_iteration_direct(P.A, P.M, P.sigma, P.grid if P.grid.d == 2 else None)
     assert abs(eo["lam"] - er["lam"]) <= 1e-10 * abs(er["lam"])
     d = u.cpu().numpy() - er["x"]
     assert np.sqrt(d @ (P.M @ d)) <= 1e-8
 
 
-def test_march_hbm_scale(torch):
-    """The 2-D grid L = 16384, h = 1/64 (1,048,575 x 63 unknowns): the sweep
-    chosen by size is the march; whole-vector equality with the tile sweep and
-    sampled rows against the oracle."""
+def _hbm_scale(torch, p, q, L, ne, delta, V, Ls):
+    """Whole-vector equality of the size-chosen sweep (the march) with the tile
+    sweep, and sampled rows against a small oracle problem (L = Ls) on the same
+    period cell."""
     import paper_2311_08757_amd as dd
     from oracle.problem import Problem
-    cfg = W.config(2)
-    L, ne, delta, V = 16384, 64, 4, cfg["V"]
-    case = (1, 1, L, ne, delta, V)
+    case = (p, q, L, ne, delta, V)
     pa = _assemble(case, "auto", coarse=False)
     sig, psi = dd.cell_shift(pa)
     n = pa.n_dof
-    N0, N1 = L * ne - 1, ne - 1
-    assert n == N0 * N1
+    N0 = L * ne - 1
     x = torch.randn(n, dtype=torch.float64, device="cuda",
                     generator=torch.Generator(device="cuda").manual_seed(3))
     ya = torch.empty_like(x)
@@ -127,14 +129,14 @@ def test_march_hbm_scale(torch):
     torch.cuda.synchronize()
     assert torch.equal(ya, yt)
     del pt, yt
-    # sampled rows against a small oracle problem on the same period cell
-    Ls = 4
-    Ps = Problem(W.small_config(1, 1, Ls, ne, delta, V))
+    Ps = Problem(W.small_config(p, q, Ls, ne, delta, V))
     N0s = Ls * ne - 1
+    rest = n // N0          # the other axes, unchanged in the small problem
+    assert Ps.grid.n == N0s * rest
     As = (Ps.A - sig * Ps.M).tocsr()
     rng = np.random.default_rng(21)
     ii = np.concatenate([[0, 1, N0 - 2, N0 - 1], rng.integers(0, N0, size=1020)])
-    jj = np.concatenate([[0, N1 - 1, 0, N1 - 1], rng.integers(0, N1, size=1020)])
+    jj = np.concatenate([[0, rest - 1, 0, rest - 1], rng.integers(0, rest, size=1020)])
     xmax = float(np.max(np.abs(xh)))
     for i, j in zip(ii, jj):
         if i == 0:
@@ -146,8 +148,17 @@ def test_march_hbm_scale(torch):
         row = As.getrow(i_s + N0s * j)
         cols = row.indices
         d0 = cols % N0s - i_s
-        d1 = cols // N0s - j
-        big = (i + d0) + N0 * (j + d1)
+        big = (i + d0) + N0 * (cols // N0s)
         expect = float(row.data @ xh[big])
         bar = 1e-13 * float(np.abs(row.data).sum()) * xmax
         assert abs(ys[i + N0 * j] - expect) <= bar, (i, j)
+
+
+def test_march_hbm_scale_2d(torch):
+    """2-D, L = 16384, h = 1/64: 1,048,575 x 63 unknowns (row march)."""
+    _hbm_scale(torch, 1, 1, 16384, 64, 4, W.config(2)["V"], 4)
+
+
+def test_march_hbm_scale_3d(torch):
+    """3-D p = 1, q = 2, L = 2048, h = 1/32: 65,535 x 31 x 31 unknowns (plane march)."""
+    _hbm_scale(torch, 1, 2, 2048, 32, 2, W.config(3)["V"], 3)
