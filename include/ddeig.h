@@ -412,14 +412,24 @@ typedef struct ddeig_batch ddeig_batch;
 
 /* flags: DDEIG_BATCH_GRAPHS replays the grouped iterations (8 per host check)
  * from HIP graphs captured on first use (one per block start and maxit),
- * instead of launching the kernels one by one. */
+ * instead of launching the kernels one by one.  DDEIG_BATCH_REPRODUCIBLE
+ * skips the timing: the GEMM keeps the K split of the instances' own
+ * single-problem path (the smallest over the instances) in XCD-interleaved
+ * order, so the batch's results are fixed by the inputs alone (and equal
+ * the single-problem path's bit for bit when all instances share that
+ * split).  Without it the autotuner's choice is remembered per shape
+ * (local_prec, ld, the instances' subdomain counts) for the life of the
+ * process: a later batch of the same shapes reuses it without timing and
+ * repeats the first batch's bits. */
 #define DDEIG_BATCH_GRAPHS 1
+#define DDEIG_BATCH_REPRODUCIBLE 2
 
 ddeig_status ddeig_batch_create(ddeig_problem* const* probs, int n, int flags, ddeig_batch** out);
 
 /* Autotuner result: K split, tile order (0 instance-major, 1 XCD-interleaved),
  * number of GEMM tiles, and the six measured candidate times in us
- * (split 1..3 x order 0..1; 0 where a split was not admissible). */
+ * (split 1..3 x order 0..1; 0 where a split was not admissible, and all 0
+ * when nothing was timed: DDEIG_BATCH_REPRODUCIBLE or a remembered choice). */
 ddeig_status ddeig_batch_query(const ddeig_batch* B, int* ksplit, int* order, int* ntiles,
                                double* tune_us);
 

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -2277,6 +2278,8 @@ struct ddeig_batch {
   ddeig::PcgState* dStates = nullptr;
   std::vector<ddeig::PcgState> hStates;
   double* dRes = nullptr;
+  int* dAct = nullptr;   // 2 n activity flags of the grouped outer-iteration launches
+  int* hAct = nullptr;   // pinned host copy
   std::vector<void*> allocs;
   double tune_us[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   // hipGraph replay of the grouped iterations: one executable graph per
@@ -2287,6 +2290,10 @@ struct ddeig_batch {
 };
 
 namespace {
+
+// GEMM choices of the batch autotuner by shape, for the life of the process
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune;
 
 template <typename T>
 T* balloc(ddeig_batch* B, size_t count) {
@@ -2381,20 +2388,39 @@ void batch_iteration(ddeig_batch* B, int k, int maxit, hipStream_t s) {
 
 // PCG on A_sigma,j x_j = b_j for the instances with active[j] != 0 (the
 // others stay idle); on return B->hStates holds every instance's final state.
+// With act (device flags of the active instances, already on the stream) the
+// start is grouped: x_0 = 0 and b = the instance's w, as in the inverse
+// iteration; otherwise each instance starts from its own x_0 and b.
 void batch_pcg(ddeig_batch* B, const std::vector<int>& active, const std::vector<const double*>& b,
-               const std::vector<double*>& x, double rtol, int maxit) {
+               const std::vector<double*>& x, double rtol, int maxit, const int* act = nullptr) {
   const hipStream_t s = B->stream;
   for (int j = 0; j < B->n; ++j) B->inst[j].x = x[j];
   batch_upload_inst(B);
   launch_b_states(B->dInst, B->n, B->dStates, 1, s);
-  for (int j = 0; j < B->n; ++j) {
-    if (!active[j]) continue;
-    ddeig_problem* P = B->P[j];
-    Red rr = slot(P, 1), rz = slot(P, 2);
-    launch_stencil(P, P->tabAs, x[j], P->q, nullptr, nullptr, s);
-    launch_resid_init(P, b[j], P->q, P->r, rr, s);
-    launch_pcg_init(P, rtol, rr, s);
-    precond_apply(P, P->r, P->z, &rz, P->st);
+  if (act != nullptr) {
+    launch_b_restrict_start(B->dInst, B->bm_node, act, s);
+    launch_b_pcg_init(B->dInst, B->n, act, rtol, s);
+    check_hip(hipEventRecord(B->ev_fork, s), "record fork");
+    check_hip(hipStreamWaitEvent(B->aux, B->ev_fork, 0), "wait fork");
+    launch_gemm_tiles(B->dTiles, B->ntiles, B->dGt, B->local_prec, s);
+    launch_embed_jobs(B->dEmbJobs, B->nembjobs, B->dEmb, B->ksplit, B->ld, B->hm0, B->hm1, B->mH,
+                      s);
+    launch_b_coarse_rhs(B->dInst, B->bm_crhs, B->aux);
+    launch_b_coarse_solve(B->dInst, B->bm_csol, B->aux);
+    launch_b_coarse_field(B->dInst, B->bm_cf, B->aux);
+    check_hip(hipEventRecord(B->ev_join, B->aux), "record join");
+    check_hip(hipStreamWaitEvent(s, B->ev_join, 0), "wait join");
+    launch_b_extend(B->dInst, B->bm_node, 0, maxit, B->ksplit, s, 0);
+  } else {
+    for (int j = 0; j < B->n; ++j) {
+      if (!active[j]) continue;
+      ddeig_problem* P = B->P[j];
+      Red rr = slot(P, 1), rz = slot(P, 2);
+      launch_stencil(P, P->tabAs, x[j], P->q, nullptr, nullptr, s);
+      launch_resid_init(P, b[j], P->q, P->r, rr, s);
+      launch_pcg_init(P, rtol, rr, s);
+      precond_apply(P, P->r, P->z, &rz, P->st);
+    }
   }
   check_launch("batch pcg start");
   int k = 0;
@@ -2472,6 +2498,7 @@ void batch_free(ddeig_batch* B) {
   if (B->cap) (void)hipStreamDestroy(B->cap);
   if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
   if (B->ev_join) (void)hipEventDestroy(B->ev_join);
+  if (B->hAct) (void)hipHostFree(B->hAct);
   delete B;
 }
 
@@ -2483,7 +2510,8 @@ ddeig_status ddeig_batch_create(ddeig_problem* const* probs, int n, int flags, d
   if (!probs || !out) return set_error(DDEIG_EINVAL, "probs or out is NULL");
   *out = nullptr;
   if (n < 1 || n > 4096) return set_error(DDEIG_EINVAL, "need 1 <= n <= 4096 instances");
-  if (flags & ~DDEIG_BATCH_GRAPHS) return set_error(DDEIG_EINVAL, "unknown batch flags");
+  if (flags & ~(DDEIG_BATCH_GRAPHS | DDEIG_BATCH_REPRODUCIBLE))
+    return set_error(DDEIG_EINVAL, "unknown batch flags");
   const ddeig_problem* P0 = probs[0];
   for (int j = 0; j < n; ++j) {
     const ddeig_problem* P = probs[j];
@@ -2540,23 +2568,42 @@ ddeig_status ddeig_batch_create(ddeig_problem* const* probs, int n, int flags, d
       gtt[j].st = nullptr;
     }
     B->dGt = bupload(B, gts);
-    ddeig::GemmType* dGtt = bupload(B, gtt);
-    float best = 1e30f;
     std::vector<ddeig::GemmTile> best_tiles;
-    int ci = 0;
-    for (int ks = 1; ks <= ks_max; ++ks)
-      for (int order = 0; order < 2; ++order, ++ci) {
-        std::vector<ddeig::GemmTile> t = batch_tiles(B, ks, order);
-        ddeig::GemmTile* dT = bupload(B, t);
-        const float us = time_gemm(B, dT, (int)t.size(), dGtt);
-        if (ci < 8) B->tune_us[ci] = us;
-        if (us < best) {
-          best = us;
-          best_tiles = t;
-          B->ksplit = ks;
-          B->order = order;
+    std::string shape = std::to_string(B->local_prec) + "/" + std::to_string(B->ld) + "/" +
+                        std::to_string(ks_max);
+    for (auto* P : B->P) shape += "/" + std::to_string(P->nsub);
+    std::pair<int, int> choice{0, 0};
+    if (flags & DDEIG_BATCH_REPRODUCIBLE) {
+      choice = {ks_max, 1};
+    } else {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune.find(shape);
+      if (it != g_tune.end()) choice = it->second;
+    }
+    if (choice.first > 0) {
+      B->ksplit = choice.first;
+      B->order = choice.second;
+      best_tiles = batch_tiles(B, B->ksplit, B->order);
+    } else {
+      ddeig::GemmType* dGtt = bupload(B, gtt);
+      float best = 1e30f;
+      int ci = 0;
+      for (int ks = 1; ks <= ks_max; ++ks)
+        for (int order = 0; order < 2; ++order, ++ci) {
+          std::vector<ddeig::GemmTile> t = batch_tiles(B, ks, order);
+          ddeig::GemmTile* dT = bupload(B, t);
+          const float us = time_gemm(B, dT, (int)t.size(), dGtt);
+          if (ci < 8) B->tune_us[ci] = us;
+          if (us < best) {
+            best = us;
+            best_tiles = t;
+            B->ksplit = ks;
+            B->order = order;
+          }
         }
-      }
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune.emplace(shape, std::make_pair(B->ksplit, B->order));
+    }
     B->dTiles = bupload(B, best_tiles);
     B->ntiles = (int)best_tiles.size();
     // clipped classes of every instance, each checked against its instance's state
@@ -2620,6 +2667,17 @@ ddeig_status ddeig_batch_create(ddeig_problem* const* probs, int n, int flags, d
       d.cy = P->cy;
       d.xc0 = P->dXC[0];
       d.hist = P->hist;
+      d.tabM = P->tabM;
+      d.xo = nullptr;
+      d.w = P->w;
+      d.nm_uMu = slot(P, 4);
+      d.nm_uMu.np = d.gam.np;
+      d.nm_sum = slot(P, 5);
+      d.nm_sum.np = d.gam.np;
+      d.nm_dx = slot(P, 6);
+      d.nm_dx.np = d.nb_node;
+      d.nm_xq = slot(P, 7);
+      d.nm_xq.np = d.gam.np;
       c_st[j] = d.gam.np;
       c_node[j] = d.nb_node;
       c_crhs[j] = P->nsub;
@@ -2635,6 +2693,9 @@ ddeig_status ddeig_batch_create(ddeig_problem* const* probs, int n, int flags, d
     B->dStates = balloc<ddeig::PcgState>(B, n);
     B->hStates.resize(n);
     B->dRes = balloc<double>(B, 2 * (size_t)n);
+    B->dAct = balloc<int>(B, 2 * (size_t)n);
+    check_hip(hipHostMalloc(reinterpret_cast<void**>(&B->hAct), 2 * (size_t)n * sizeof(int)),
+              "hipHostMalloc");
     check_hip(hipStreamSynchronize(B->stream), "hipStreamSynchronize");
   } catch (const Failure& f) {
     batch_free(B);
@@ -2732,19 +2793,28 @@ ddeig_status ddeig_batch_inverse_iteration(ddeig_batch* B, double* const* x, dou
   for (int j = 0; j < n; ++j) {
     bb[j] = B->P[j]->w;
     uu[j] = B->P[j]->u;
+    B->inst[j].xo = x[j];
   }
+  // every outer step is a fixed set of grouped launches over the active
+  // instances: b = M x, the PCG start and iterations, M u, the normalisation,
+  // A_sigma x and the two sums per instance
+  int* const act_start = B->dAct;
+  int* const act_norm = B->dAct + n;
   for (int k = 1; k <= maxit_outer; ++k) {
     int nact = 0;
     for (int j = 0; j < n; ++j) {
-      if (!active[j]) continue;
-      ++nact;
-      ddeig_problem* P = B->P[j];
-      launch_stencil(P, P->tabM, x[j], P->w, nullptr, nullptr, s);  // b = M x
-      launch_fill(P->u, P->g.n, 0.0, s);
+      B->hAct[j] = active[j];
+      nact += active[j] ? 1 : 0;
     }
     if (nact == 0) break;
-    batch_pcg(B, active, bb, uu, rtol_inner, maxit_inner);
+    check_hip(hipMemcpyAsync(act_start, B->hAct, sizeof(int) * n, hipMemcpyHostToDevice, s),
+              "copy activity");
+    batch_upload_inst(B);
+    launch_b_stencil_plain(B->dInst, B->bm_st, act_start, 0, s);  // b = M x
+    batch_pcg(B, active, bb, uu, rtol_inner, maxit_inner, act_start);
+    int nnorm = 0;
     for (int j = 0; j < n; ++j) {
+      B->hAct[n + j] = 0;
       if (!active[j]) continue;
       const ddeig::PcgState& h = B->hStates[j];
       if (h.done == 2 || h.done == 3) {
@@ -2756,17 +2826,16 @@ ddeig_status ddeig_batch_inverse_iteration(ddeig_batch* B, double* const* x, dou
       inner_max[j] = std::max(inner_max[j], h.iters);
       if (h.done != 1) ++unconv[j];
       its[j] = k;
-      ddeig_problem* P = B->P[j];
-      const long nn = P->g.n;
-      Red s4 = slot(P, 4), s5 = slot(P, 5), s6 = slot(P, 6), s7 = slot(P, 7);
-      launch_stencil(P, P->tabM, P->u, P->z, &s4, &s5, s);
-      launch_ipm_normalise(nn, P->u, P->z, x[j], P->w, s4, s5, s6, s);
-      launch_stencil(P, P->tabAs, x[j], P->q, &s7, nullptr, s);
-      launch_finish_sum(s6, s);
-      launch_finish_sum(s7, s);
-      check_hip(hipMemcpyAsync(B->dRes + 2 * j, P->red_val + 6, 2 * sizeof(double),
-                               hipMemcpyDeviceToDevice, s), "gather");
+      B->hAct[n + j] = 1;
+      ++nnorm;
     }
+    if (nnorm == 0) break;
+    check_hip(hipMemcpyAsync(act_norm, B->hAct + n, sizeof(int) * n, hipMemcpyHostToDevice, s),
+              "copy activity");
+    launch_b_stencil_plain(B->dInst, B->bm_st, act_norm, 1, s);   // M u
+    launch_b_normalise(B->dInst, B->bm_node, act_norm, s);         // x = scale u
+    launch_b_stencil_plain(B->dInst, B->bm_st, act_norm, 2, s);   // A_sigma x
+    launch_b_finish_norm(B->dInst, n, act_norm, B->dRes, s);
     check_launch("batch normalisation");
     check_hip(hipMemcpyAsync(res.data(), B->dRes, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, s),
               "copy results");

@@ -291,6 +291,13 @@ struct InstDev {
   double* cy;
   const XCover* xc0;
   double* hist;
+  // the outer inverse iteration (ddeig_batch_inverse_iteration): mass table,
+  // eigenvector iterate, b = M x and the partials of u.Mu, sum(Mu),
+  // ||x_new - x||_M^2 and x.A_sigma x
+  const double* tabM;
+  double* xo;
+  double* w;
+  Red nm_uMu, nm_sum, nm_dx, nm_xq;
 };
 
 // One job of the grouped derivative forms (k_grad.hip): the pair x, y of one
@@ -522,7 +529,7 @@ int coarse_field_grid(const Geo& g);
 void launch_b_stencil_dir(const InstDev* I, const BlockMap& bm, int k, hipStream_t s);
 void launch_b_restrict(const InstDev* I, const BlockMap& bm, int k, hipStream_t s);
 void launch_b_extend(const InstDev* I, const BlockMap& bm, int k, int maxit, int ksplit,
-                     hipStream_t s);
+                     hipStream_t s, int check = 1);
 void launch_b_coarse_rhs(const InstDev* I, const BlockMap& bm, hipStream_t s);
 void launch_b_coarse_solve(const InstDev* I, const BlockMap& bm, hipStream_t s);
 void launch_b_coarse_field(const InstDev* I, const BlockMap& bm, hipStream_t s);
@@ -531,6 +538,12 @@ void launch_gemm_tiles(const GemmTile* tiles, int ntiles, const GemmType* gt, in
 void launch_embed_jobs(const EmbedJob* jobs, int njobs, const EmbedDev* cls, int ksplit, int ld,
                        int hm0, int hm1, int mH, hipStream_t s);
 void launch_b_states(const InstDev* I, int n, PcgState* out, int mark_done, hipStream_t s);
+void launch_b_restrict_start(const InstDev* I, const BlockMap& bm, const int* act, hipStream_t s);
+void launch_b_pcg_init(const InstDev* I, int n, const int* act, double rtol, hipStream_t s);
+void launch_b_normalise(const InstDev* I, const BlockMap& bm, const int* act, hipStream_t s);
+void launch_b_finish_norm(const InstDev* I, int n, const int* act, double* res, hipStream_t s);
+void launch_b_stencil_plain(const InstDev* I, const BlockMap& bm, const int* act, int which,
+                            hipStream_t s);
 
 // PCG / IPM vector kernels
 int red_grid(long work_items);

@@ -55,6 +55,24 @@ __device__ inline double sum_partials(const double* part, int np) {
   return block_sum_n<NT>(v);
 }
 
+// Start of PCG (stopping rule of §4.1): ||r_0||^2 from the partials of rr,
+// the tolerance, an empty direction history; CG is finished at once when
+// r_0 = 0.  Run by one workgroup of kBlock threads.
+__device__ inline void pcg_init_body(PcgState* st, double rtol, const Red& rr,
+                                     double* __restrict__ hist, double rz_floor) {
+  const double r0n2 = sum_partials(rr.part, rr.np);
+  if (threadIdx.x == 0) {
+    st->rz_floor = rz_floor;
+    st->r0n2 = r0n2;
+    st->tol2 = rtol * rtol * r0n2;
+    st->iters = 0;
+    st->rho[0] = st->rho[1] = 0.0;
+    st->relres = r0n2 > 0.0 ? 1.0 : 0.0;
+    st->done = r0n2 > 0.0 ? 0 : 1;
+    if (hist) hist[0] = st->relres;
+  }
+}
+
 // Offsets of tap t; with ntaps = 9 (2-D) there is no third dim and d2 = 0.
 __device__ inline void tap_offsets(int t, int ntaps, int& d0, int& d1, int& d2) {
   d0 = t % 3 - 1;

@@ -903,6 +903,37 @@ void launch_b_stencil_dir(const InstDev* I, const BlockMap& bm, int k, hipStream
   hipLaunchKernelGGL(k_b_stencil_dir, dim3(bm.nblocks), dim3(kBlock), 0, s, I, bm.map, k);
 }
 
+// Grouped plain sweeps of the batch's outer inverse iteration over the
+// instances with act[j] != 0 (block b runs tile map[b].y of instance
+// map[b].x): which 0: w = M x; 1: Mu = M u (into z) with the partials of u.Mu
+// and sum(Mu); 2: q = A_sigma x with the partials of x.q.
+__global__ void __launch_bounds__(kBlock) k_b_stencil_plain(const InstDev* __restrict__ I,
+                                                            const int2* __restrict__ map,
+                                                            const int* __restrict__ act, int which) {
+  const int2 m = map[blockIdx.x];
+  if (!act[m.x]) return;
+  const InstDev& d = I[m.x];
+  const Red none{nullptr, 0, nullptr};
+  const DirArgs nodir{nullptr, 0, none};
+  const double* T = which == 2 ? d.tabAs : d.tabM;
+  const double* xin = which == 1 ? d.x : d.xo;
+  double* yout = which == 0 ? d.w : (which == 1 ? d.z : d.q);
+  const Red dot = which == 1 ? d.nm_uMu : d.nm_xq;
+  const int use_dot = which != 0, use_sum = which == 1;
+  if (d.sty == 4)
+    stencil2d_body<0, 4>(d.g, T, xin, nullptr, nullptr, yout, nodir, use_dot, dot, use_sum,
+                         d.nm_sum, m.y);
+  else
+    stencil2d_body<0, 8>(d.g, T, xin, nullptr, nullptr, yout, nodir, use_dot, dot, use_sum,
+                         d.nm_sum, m.y);
+}
+
+void launch_b_stencil_plain(const InstDev* I, const BlockMap& bm, const int* act, int which,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_b_stencil_plain, dim3(bm.nblocks), dim3(kBlock), 0, s, I, bm.map, act,
+                     which);
+}
+
 // Rows of the 2-D sweep's tiles (n_e dividing 64): 4 while 4-row tiles number
 // at most 1024 (one partial each), else 8.  Small grids, whose vectors sit in
 // the Infinity Cache and whose sweep is latency-bound, get twice the

@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(kBig) k_restrict(Geo g, int ntypes, PcgState* 
   __shared__ TypeDev stypes[kMaxTypes];
   if (st != nullptr && st->done) return;
   double alpha = 0.0;
-  if (xr.on) {
+  if (xr.on == 1) {
     const double gamma = sum_partials<kBig>(xr.gam.part, xr.gam.np);
     if (!(gamma > 0.0)) {
       if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -211,7 +211,7 @@ __device__ __forceinline__ void restrict_dense_body(const Geo& g, int delta,
                                                     const DenseArgs& da, int bid, int nblk) {
   if (st != nullptr && st->done) return;
   double alpha = 0.0;
-  if (xr.on) {
+  if (xr.on == 1) {
     const double gamma = sum_partials<kBig>(xr.gam.part, xr.gam.np);
     if (!(gamma > 0.0)) {
       if (bid == 0 && threadIdx.x == 0) {
@@ -247,8 +247,8 @@ __device__ __forceinline__ void restrict_dense_body(const Geo& g, int delta,
       kk[u] = i0 + (long)N0 * line;
       rv[u] = qv[u] = pv[u] = xv[u] = 0.0;
       if (ok[u]) {
-        rv[u] = r[kk[u]];
-        if (xr.on) {
+        rv[u] = xr.on == 2 ? xr.q[kk[u]] : r[kk[u]];
+        if (xr.on == 1) {
           qv[u] = xr.q[kk[u]];
           pv[u] = xr.p[kk[u]];
           xv[u] = xr.x[kk[u]];
@@ -261,9 +261,13 @@ __device__ __forceinline__ void restrict_dense_body(const Geo& g, int delta,
       const long k = kk[u];
       const int* i = ii[u];
       double rvv = rv[u];
-      if (xr.on) {
+      if (xr.on == 1) {
         rvv -= alpha * qv[u];
         xr.x[k] = xv[u] + alpha * pv[u];
+        r[k] = rvv;
+        acc += rvv * rvv;
+      } else if (xr.on == 2) {
+        xr.x[k] = 0.0;
         r[k] = rvv;
         acc += rvv * rvv;
       }
@@ -858,13 +862,71 @@ __global__ void __launch_bounds__(kBig) k_b_restrict(const InstDev* __restrict__
   restrict_dense_body<1>(d.g, d.delta, d.st, xr, d.rr, d.r, d.da, m.y, d.nb_node);
 }
 
+// PCG from x_0 = 0 with b = w (the batch's inverse iteration): r_0 = w,
+// x_0 = 0, the partials of ||r_0||^2 and the restriction of r_0, for the
+// instances with act[j] != 0 (their CG state is set afterwards).
+__global__ void __launch_bounds__(kBig) k_b_restrict_start(const InstDev* __restrict__ I,
+                                                           const int2* __restrict__ map,
+                                                           const int* __restrict__ act) {
+  const int2 m = map[blockIdx.x];
+  if (!act[m.x]) return;
+  const InstDev& d = I[m.x];
+  const XrArgs xr{2, 0, d.rr, d.x, nullptr, d.w};
+  restrict_dense_body<1>(d.g, d.delta, nullptr, xr, d.rr, d.r, d.da, m.y, d.nb_node);
+}
+
+__global__ void k_b_pcg_init(const InstDev* __restrict__ I, const int* __restrict__ act,
+                             double rtol) {
+  const int j = blockIdx.x;
+  if (!act[j]) return;
+  pcg_init_body(I[j].st, rtol, I[j].rr, I[j].hist, 0.0);
+}
+
+// Inverse-iteration normalisation (as k_ipm_normalise) of every instance with
+// act[j] != 0: x_new = sign(1^T M u) u / sqrt(u^T M u) into xo, and the
+// partials of ||x_new - x||_M^2 = (x_new - x)^T (scale Mu - b) (Mu in z, b in w).
+__global__ void __launch_bounds__(kBig) k_b_normalise(const InstDev* __restrict__ I,
+                                                      const int2* __restrict__ map,
+                                                      const int* __restrict__ act) {
+  const int2 m = map[blockIdx.x];
+  if (!act[m.x]) return;
+  const InstDev& d = I[m.x];
+  const double ssum = sum_partials<kBig>(d.nm_sum.part, d.nm_sum.np);
+  const double uu = sum_partials<kBig>(d.nm_uMu.part, d.nm_uMu.np);
+  const double sc = (ssum < 0.0 ? -1.0 : 1.0) / sqrt(uu);
+  const long n = d.g.n;
+  double acc = 0.0;
+  for (long i = m.y * (long)kBig + threadIdx.x; i < n; i += (long)d.nb_node * kBig) {
+    const double xn = sc * d.x[i];
+    const double dd = xn - d.xo[i];
+    acc += dd * (sc * d.z[i] - d.w[i]);
+    d.xo[i] = xn;
+  }
+  write_partial_at<kBig>(acc, d.nm_dx.part, m.y);
+}
+
+// res[2 j] = ||x_new - x||_M^2, res[2 j + 1] = x_new^T A_sigma x_new (act[j] != 0).
+__global__ void k_b_finish_norm(const InstDev* __restrict__ I, const int* __restrict__ act,
+                                double* __restrict__ res) {
+  const int j = blockIdx.x;
+  if (!act[j]) return;
+  const double dx = sum_partials(I[j].nm_dx.part, I[j].nm_dx.np);
+  const double xq = sum_partials(I[j].nm_xq.part, I[j].nm_xq.np);
+  if (threadIdx.x == 0) {
+    res[2 * j] = dx;
+    res[2 * j + 1] = xq;
+  }
+}
+
 template <int KS>
-// Two nodes per thread on node_grid_dense's grid, as the single problem's extension.
+// Two nodes per thread on node_grid_dense's grid, as the single problem's
+// extension; check = 0 at the start of CG (z_0 and the partials of r_0.z_0 only).
 __global__ void __launch_bounds__(kBig) __attribute__((amdgpu_waves_per_eu(8)))
-k_b_extend(const InstDev* __restrict__ I, const int2* __restrict__ map, int k, int maxit) {
+k_b_extend(const InstDev* __restrict__ I, const int2* __restrict__ map, int k, int maxit,
+           int check) {
   const int2 m = map[blockIdx.x];
   const InstDev& d = I[m.x];
-  const CheckArgs chk{1, k, maxit, d.hist_cap, d.rr, d.hist};
+  const CheckArgs chk{check, k, maxit, d.hist_cap, d.rr, d.hist};
   extend_dense_body<1, KS, false, false, 2>(d.g, d.delta, 1, d.st, chk, d.da, d.psi, d.cf, d.r,
                                             d.z, 1, d.rz, m.y, d.nb_node);
 }
@@ -905,9 +967,25 @@ void launch_b_restrict(const InstDev* I, const BlockMap& bm, int k, hipStream_t 
 }
 
 void launch_b_extend(const InstDev* I, const BlockMap& bm, int k, int maxit, int ksplit,
-                     hipStream_t s) {
+                     hipStream_t s, int check) {
   auto kern = ksplit == 1 ? k_b_extend<1> : (ksplit == 2 ? k_b_extend<2> : k_b_extend<3>);
-  hipLaunchKernelGGL(kern, dim3(bm.nblocks), dim3(kBig), 0, s, I, bm.map, k, maxit);
+  hipLaunchKernelGGL(kern, dim3(bm.nblocks), dim3(kBig), 0, s, I, bm.map, k, maxit, check);
+}
+
+void launch_b_restrict_start(const InstDev* I, const BlockMap& bm, const int* act, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_restrict_start, dim3(bm.nblocks), dim3(kBig), 0, s, I, bm.map, act);
+}
+
+void launch_b_pcg_init(const InstDev* I, int n, const int* act, double rtol, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_pcg_init, dim3(n), dim3(kBlock), 0, s, I, act, rtol);
+}
+
+void launch_b_normalise(const InstDev* I, const BlockMap& bm, const int* act, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_normalise, dim3(bm.nblocks), dim3(kBig), 0, s, I, bm.map, act);
+}
+
+void launch_b_finish_norm(const InstDev* I, int n, const int* act, double* res, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_finish_norm, dim3(n), dim3(kBlock), 0, s, I, act, res);
 }
 
 void launch_b_coarse_rhs(const InstDev* I, const BlockMap& bm, hipStream_t s) {

@@ -47,17 +47,7 @@ void launch_finish_sum(const Red& r, hipStream_t s) {
 
 __global__ void k_pcg_init(PcgState* st, double rtol, Red rr, double* __restrict__ hist,
                            double rz_floor) {
-  const double r0n2 = sum_partials(rr.part, rr.np);
-  if (threadIdx.x == 0) {
-    st->rz_floor = rz_floor;
-    st->r0n2 = r0n2;
-    st->tol2 = rtol * rtol * r0n2;
-    st->iters = 0;
-    st->rho[0] = st->rho[1] = 0.0;
-    st->relres = r0n2 > 0.0 ? 1.0 : 0.0;
-    st->done = r0n2 > 0.0 ? 0 : 1;
-    if (hist) hist[0] = st->relres;
-  }
+  pcg_init_body(st, rtol, rr, hist, rz_floor);
 }
 
 void launch_pcg_init(const ddeig_problem* P, double rtol, Red rr, hipStream_t s,

@@ -502,14 +502,17 @@ def _ptr_array(ts, ns, name):
     return arr
 
 
-def batch_create(probs, graphs=True):
-    """ddeig_batch_create over a list of Problems (runs the GEMM autotuner);
-    graphs: replay the grouped iterations from captured HIP graphs."""
+def batch_create(probs, graphs=True, reproducible=False):
+    """ddeig_batch_create over a list of Problems (runs the GEMM autotuner, or
+    reuses its choice for the same shapes); graphs: replay the grouped
+    iterations from captured HIP graphs; reproducible: no timing, the
+    single-problem K split (DDEIG_BATCH_REPRODUCIBLE)."""
     lib = load_library()
     arr = (ctypes.c_void_p * len(probs))(*[p.handle.value if isinstance(p.handle, ctypes.c_void_p)
                                            else p.handle for p in probs])
     h = ctypes.c_void_p()
-    _check(lib.ddeig_batch_create(arr, len(probs), 1 if graphs else 0, ctypes.byref(h)),
+    flags = (1 if graphs else 0) | (2 if reproducible else 0)
+    _check(lib.ddeig_batch_create(arr, len(probs), flags, ctypes.byref(h)),
            "ddeig_batch_create")
     return Batch(h, probs)
 

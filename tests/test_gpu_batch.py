@@ -13,6 +13,9 @@ kernel of a PCG iteration over independent instances.
   n_e = 32, delta = 2, bf16 local solves): lambda_j to 1e-10 relative and 32
   sampled eigenvector entries to 1e-8 against tests/golden/oracle_batch.json
   (written by make_golden.py from the oracle alone);
+- DDEIG_BATCH_REPRODUCIBLE (no timing, the single-problem K split: bitwise
+  equal to the single path) and the per-shape memory of the autotuner (a
+  second batch of the same shapes repeats the first one's choice and bits);
 - argument errors of ddeig_batch_create.
 """
 import json
@@ -84,6 +87,42 @@ def test_batch_pcg_bitwise_equals_single(torch, prec, graphs):
         else:
             assert abs(info[j]["iters"] - it1) <= 2, j
             assert float((x1 - x2).abs().max()) <= 1e-8 * float(x1.abs().max()), j
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+def test_batch_reproducible(torch, prec):
+    """DDEIG_BATCH_REPRODUCIBLE: nothing is timed and the GEMM keeps the
+    single-problem K split, so every instance's iterate equals its own
+    ddeig_pcg_solve bit for bit; a timed batch of the same shapes created twice
+    reuses the first choice (nothing timed the second time) and repeats its bits."""
+    import paper_2311_08757_amd as dd
+    probs = _small_probs(prec)
+    bs = [_dev(torch, W.random_vector(p.n_dof, 60 + j)) for j, p in enumerate(probs)]
+    single = []
+    for p, b in zip(probs, bs):
+        x = torch.zeros_like(b)
+        out = dd.pcg_solve(p, b, x, rtol=1e-10, maxit=500)
+        single.append((x, out["iters"]))
+    ks_single = min(3, 128 // (64 if prec == "bf16" else 32) // 2)
+    br = dd.batch_create(probs, reproducible=True)
+    q = dd.batch_query(br)
+    assert q["ksplit"] == ks_single and q["order"] == 1 and not any(q["tune_us"])
+    xs = [torch.zeros_like(b) for b in bs]
+    st, info = dd.batch_pcg_solve(br, bs, xs, rtol=1e-10, maxit=500)
+    assert st == "OK"
+    for j, ((x1, it1), x2) in enumerate(zip(single, xs)):
+        assert info[j]["iters"] == it1 and torch.equal(x1, x2), j
+    b1 = dd.batch_create(probs)
+    b2 = dd.batch_create(probs)
+    q1, q2 = dd.batch_query(b1), dd.batch_query(b2)
+    assert (q2["ksplit"], q2["order"]) == (q1["ksplit"], q1["order"]) and not any(q2["tune_us"])
+    outs = []
+    for bt in (b1, b2):
+        xx = [torch.zeros_like(b) for b in bs]
+        st, _ = dd.batch_pcg_solve(bt, bs, xx, rtol=1e-10, maxit=500)
+        assert st == "OK"
+        outs.append(xx)
+    assert all(torch.equal(a, b) for a, b in zip(*outs))
 
 
 def test_batch_inverse_iteration_small(torch):
