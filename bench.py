@@ -178,11 +178,14 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison solve")
     ap.add_argument("--kernels-only", action="store_true",
                     help="set-up, then only the per-kernel timings (for counter runs)")
+    ap.add_argument("--hbm-only", action="store_true",
+                    help="only the HBM-scale stencil sweeps (2-D and 3-D), one JSON line each")
     ap.add_argument("--no-hbm", action="store_true",
                     help="skip the stencil measurement at the HBM-sized 2-D workload")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     ap.add_argument("--cpu-sample", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-pcg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-tol", type=float, default=1e-9, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-pin", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--solver", default=None,
@@ -249,11 +252,46 @@ def cpu_direct(cfgno, tol_x):
                 affinity=sorted(os.sched_getaffinity(0)))
 
 
+def cpu_pcg(cfgno, iters=10):
+    """The oracle's PCG with its two-level additive Schwarz preconditioner
+    (exact local solves) on the same workload: `iters` iterations of one
+    inner solve (b = M 1) after the oracle's own set-up, as DOF*iter/s."""
+    import numpy as np
+    import workloads as W
+    from oracle.problem import Problem
+    from oracle.pcg import pcg
+    cfg = W.config(cfgno)
+    t0 = time.perf_counter()
+    P = Problem(cfg, route="kron")
+    M2 = P.preconditioner(True)
+    t_setup = time.perf_counter() - t0
+    b = P.M @ np.ones(P.grid.n)
+    t1 = time.perf_counter()
+    res = pcg(lambda v: P.A_sigma @ v, b, M2.apply, rtol=0.0, maxit=iters)
+    dt = time.perf_counter() - t1
+    return dict(value=P.grid.n * res.iters / dt, iters=res.iters, seconds=dt, setup_s=t_setup,
+                n=int(P.grid.n), affinity=sorted(os.sched_getaffinity(0)))
+
+
 def run_cpu_baseline(cfgno, tol_x):
-    """cpu_direct in child processes: one pinned to a single core with one BLAS
-    thread, one with all usable cores."""
+    """The oracle in child processes: its PCG rate on one pinned core (the
+    metric's unit), and its direct route to the eigenpair (cpu_direct) on one
+    pinned core and on all usable cores."""
     out = {}
     ncores = len(os.sched_getaffinity(0))
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        env[k] = "1"
+    env["CUDA_VISIBLE_DEVICES"] = ""
+    env["HIP_VISIBLE_DEVICES"] = ""
+    res = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-sample", "--cpu-pcg",
+                          "--cpu-pin", "--config", str(cfgno)], capture_output=True, text=True,
+                         env=env, timeout=900)
+    if res.returncode != 0:
+        raise RuntimeError("cpu baseline failed: " + res.stderr[-2000:])
+    out["pcg"] = json.loads(res.stdout.strip().splitlines()[-1])
+    print(f"# oracle PCG (one core): {out['pcg']['iters']} iterations in "
+          f"{out['pcg']['seconds']:.2f} s", file=sys.stderr, flush=True)
     for leg, threads in (("one_core", 1), ("all_cores", ncores)):
         env = dict(os.environ)
         for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
@@ -451,12 +489,23 @@ def main():
     if args.cpu_sample:
         if args.cpu_pin:
             os.sched_setaffinity(0, {min(os.sched_getaffinity(0))})
-        print(json.dumps(cpu_direct(args.config, args.cpu_tol)))
+        if args.cpu_pcg:
+            print(json.dumps(cpu_pcg(args.config)))
+        else:
+            print(json.dumps(cpu_direct(args.config, args.cpu_tol)))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding "
               "of this path is a design note, not a built component.", file=sys.stderr)
         sys.exit(2)
+    if args.hbm_only:
+        import torch
+        import paper_2311_08757_amd as dd
+        import workloads as W
+        torch.cuda.set_device(0)
+        for which in ("2d", "3d"):
+            print(json.dumps(hbm_stencil(dd, W, torch, which)), flush=True)
+        return
     if args.config == 5:
         bench_batch(args)
         return
@@ -606,6 +655,34 @@ def main():
               f"inner={o64['inner_sum']}", file=sys.stderr, flush=True)
         del p64
 
+    # the same dense-inverse local solves at the other MFMA precision: one
+    # algorithm, bf16 hi/lo pairs (three products) against single bf16, set-up
+    # (the dense inverse) timed too
+    prec_cmp = None
+    if not args.no_compare and args.local_prec in ("bf16", "bf16x3"):
+        other = "bf16x3" if args.local_prec == "bf16" else "bf16"
+        torch.cuda.synchronize()
+        ts0 = time.perf_counter()
+        po = dd.assemble(cfg["p"], cfg["q"], cfg["L"], cfg["ne"], cfg["V"], cfg["delta"],
+                         local_prec=other, graphs=bool(args.graphs))
+        dd.cell_shift(po)
+        torch.cuda.synchronize()
+        to_setup = time.perf_counter() - ts0
+        x.zero_()
+        dd.inverse_iteration(po, x, tol_x=1e-9, rtol_inner=1e-10, maxit_inner=2000)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x.zero_()
+        oo = dd.inverse_iteration(po, x, tol_x=1e-9, rtol_inner=1e-10, maxit_inner=2000)
+        torch.cuda.synchronize()
+        to = time.perf_counter() - t1
+        prec_cmp = {"local_prec": other, "time_to_eigenpair_ms": to * 1e3, "setup_s": to_setup,
+                    "pcg_iters": oo["inner_sum"], "lambda": oo["lam"],
+                    "time_ratio_vs_this_run": to / (T / max(args.steps, 1))}
+        print(f"# {other} comparison (same dense algorithm): {to * 1e3:.1f} ms "
+              f"(+ {to_setup:.2f} s set-up), inner={oo['inner_sum']}", file=sys.stderr, flush=True)
+        del po
+
     # the paper's outer variant (alg:si-lopcg) on the same problem and
     # accuracy: time to the eigenpair with fixed / adaptive inner tolerances
     # and with the preconditioner applied directly (fused)
@@ -662,18 +739,25 @@ def main():
     cpu = None
     if not args.no_cpu and cfg["p"] + cfg["q"] == 2:
         c = run_cpu_baseline(args.config, 1e-9)
-        one = c["one_core"]
-        cpu = {"value": one["phases"]["total_s"] * 1e3, "unit": "ms (time to eigenpair incl. set-up)",
-               "cores": 1, "kind": "oracle",
-               "sample": f"oracle direct route on the same {one['n']}-unknown workload: Kronecker "
-                         f"assembly, dense-eigh cell problem, banded Cholesky of A_sigma, inverse "
-                         f"iteration with exact solves to ||dx||_M <= 1e-9 ({one['outer_its']} "
-                         f"steps); one thread pinned to one core",
-               "phases_s": one["phases"], "lambda_rel_err_vs_gpu": abs(one["lam"] - lams[-1]) /
-               abs(lams[-1]) if lams else None,
-               "all_cores": {"cores": c["all_cores"]["cores"],
-                             "value": c["all_cores"]["phases"]["total_s"] * 1e3,
-                             "phases_s": c["all_cores"]["phases"]},
+        one, pc = c["one_core"], c["pcg"]
+        cpu = {"value": pc["value"], "unit": "DOF*iter/s", "cores": 1, "kind": "oracle",
+               "sample": f"oracle PCG with its two-level additive Schwarz preconditioner (exact "
+                         f"local solves) on the same {pc['n']}-unknown workload: {pc['iters']} "
+                         f"iterations of one inner solve (b = M 1) in {pc['seconds']:.2f} s after "
+                         f"its {pc['setup_s']:.1f} s set-up; one thread pinned to one core",
+               "time_to_eigenpair": {
+                   "unit": "ms (incl. set-up)",
+                   "route": f"oracle direct route: Kronecker assembly, dense-eigh cell problem, "
+                            f"banded Cholesky of A_sigma, inverse iteration with exact solves to "
+                            f"||dx||_M <= 1e-9 ({one['outer_its']} steps)",
+                   "one_core": {"cores": 1, "value": one["phases"]["total_s"] * 1e3,
+                                "phases_s": one["phases"]},
+                   "all_cores": {"cores": c["all_cores"]["cores"],
+                                 "value": c["all_cores"]["phases"]["total_s"] * 1e3,
+                                 "phases_s": c["all_cores"]["phases"]},
+                   "gpu_ms_with_setup": T / max(args.steps, 1) * 1e3 + t_setup * 1e3,
+                   "lambda_rel_err_vs_gpu": abs(one["lam"] - lams[-1]) / abs(lams[-1])
+                   if lams else None},
                "host": host_info()}
     res = {
         "metric": "PCG DOF*iter/s inside time-to-eigenpair (sigma-shifted inverse iteration, "
@@ -709,6 +793,7 @@ def main():
         "pcg_iteration": per_iter,
         "stencil_roofline": stencil_roof,
         "fp64_comparison": cmp,
+        "dense_precision_comparison": prec_cmp,
         "si_lopcg": outer,
         "inner_solvers": solvers,
         "cpu_baseline": cpu,
