@@ -2280,6 +2280,8 @@ struct ddeig_batch {
   double* dRes = nullptr;
   int* dAct = nullptr;   // 2 n activity flags of the grouped outer-iteration launches
   int* hAct = nullptr;   // pinned host copy
+  ddeig::PcgState* hst = nullptr;             // pinned: CG states behind two blocks of iterations
+  hipEvent_t ev_st[2] = {nullptr, nullptr};   // recorded after each block's state copy
   std::vector<void*> allocs;
   double tune_us[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   // hipGraph replay of the grouped iterations: one executable graph per
@@ -2423,10 +2425,12 @@ void batch_pcg(ddeig_batch* B, const std::vector<int>& active, const std::vector
     }
   }
   check_launch("batch pcg start");
-  int k = 0;
-  bool all_done = false;
-  while (!all_done) {
-    const int k0 = k + 1, kend = std::min(maxit, k + 8);
+  // blocks of 8 iterations; the next block is queued before the host looks at
+  // the states copied behind the current one (pinned slot sl), so the device
+  // does not idle during the check (a block queued after every instance has
+  // stopped is a no-op: its kernels see the final states)
+  const int n = B->n;
+  auto submit = [&](int k0, int kend, int sl) {
     if (B->use_graphs && kend >= k0) {
       const auto key = std::make_pair(k0, maxit);
       auto it = B->graphs.find(key);
@@ -2451,20 +2455,29 @@ void batch_pcg(ddeig_batch* B, const std::vector<int>& active, const std::vector
         it = B->graphs.emplace(key, ge).first;
       }
       check_hip(hipGraphLaunch(it->second, s), "launch graph");
-      k = kend;
     } else {
-      for (++k; k <= kend; ++k) batch_iteration(B, k, maxit, s);
-      --k;
+      for (int kk = k0; kk <= kend; ++kk) batch_iteration(B, kk, maxit, s);
     }
     check_launch("batch pcg iteration");
-    launch_b_states(B->dInst, B->n, B->dStates, 0, s);
-    check_hip(hipMemcpyAsync(B->hStates.data(), B->dStates, sizeof(ddeig::PcgState) * B->n,
+    launch_b_states(B->dInst, n, B->dStates, 0, s);
+    check_hip(hipMemcpyAsync(B->hst + (size_t)sl * n, B->dStates, sizeof(ddeig::PcgState) * n,
                              hipMemcpyDeviceToHost, s), "copy states");
-    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
-    all_done = true;
-    for (int j = 0; j < B->n; ++j)
+    check_hip(hipEventRecord(B->ev_st[sl], s), "record states");
+  };
+  int k = std::min(maxit, 8), sl = 0;
+  submit(1, k, 0);
+  for (;;) {
+    const bool more = k < maxit;
+    const int knext = std::min(maxit, k + 8);
+    if (more) submit(k + 1, knext, sl ^ 1);
+    check_hip(hipEventSynchronize(B->ev_st[sl]), "wait states");
+    std::copy(B->hst + (size_t)sl * n, B->hst + (size_t)(sl + 1) * n, B->hStates.begin());
+    bool all_done = true;
+    for (int j = 0; j < n; ++j)
       if (active[j] && B->hStates[j].done == 0) all_done = false;
-    if (k >= maxit) break;
+    if (all_done || !more) break;
+    k = knext;
+    sl ^= 1;
   }
   // maxit reached without a stopping decision (maxit = 0 or a state still running)
   for (int j = 0; j < B->n; ++j)
@@ -2499,6 +2512,9 @@ void batch_free(ddeig_batch* B) {
   if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
   if (B->ev_join) (void)hipEventDestroy(B->ev_join);
   if (B->hAct) (void)hipHostFree(B->hAct);
+  if (B->hst) (void)hipHostFree(B->hst);
+  for (auto& e : B->ev_st)
+    if (e) (void)hipEventDestroy(e);
   delete B;
 }
 
@@ -2696,6 +2712,10 @@ ddeig_status ddeig_batch_create(ddeig_problem* const* probs, int n, int flags, d
     B->dAct = balloc<int>(B, 2 * (size_t)n);
     check_hip(hipHostMalloc(reinterpret_cast<void**>(&B->hAct), 2 * (size_t)n * sizeof(int)),
               "hipHostMalloc");
+    check_hip(hipHostMalloc(reinterpret_cast<void**>(&B->hst),
+                            2 * (size_t)n * sizeof(ddeig::PcgState)), "hipHostMalloc");
+    for (auto& e : B->ev_st)
+      check_hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "create event");
     check_hip(hipStreamSynchronize(B->stream), "hipStreamSynchronize");
   } catch (const Failure& f) {
     batch_free(B);
