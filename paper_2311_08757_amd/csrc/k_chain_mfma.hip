@@ -16,7 +16,7 @@
 //     step's values are gathered into LDS for the workgroup's rows and a halo
 //     of one slice line on each side, which covers every coupling tap.
 //   k_cm_mm: the product W_i g on v_mfma_f32_32x32x2f32: workgroup = 128 rows
-//     x 64 members x one K chunk of 64, four waves of 32 rows x 64 members (two
+//     x 64 members x one K chunk of 72, four waves of 32 rows x 64 members (two
 //     32 x 32 tiles sharing the W_i fragment; the second is skipped when the
 //     job has at most 32 members), so W_i is read once per class; W_i rows
 //     of the chunk and g are staged through LDS with coalesced loads (W_i is
@@ -33,11 +33,11 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 constexpr int kCmRows = 128;    // output rows per product workgroup
-constexpr int kCmKc = 64;       // K chunk per product workgroup
+constexpr int kCmKc = 72;       // K chunk per product workgroup (a slice of 35 x 31 in 16 chunks)
 constexpr int kCmMembers = 64;  // members per job: two 32-wide MFMA tiles per wave
 constexpr int kCmRb = 256;      // rows per right-hand-side workgroup
 constexpr int kCmHalo = 256;    // largest halo (one slice line + 1) of the rhs kernel
-constexpr int kCmMaxKc = 32;    // largest number of K chunks (slices of at most 2048 nodes)
+constexpr int kCmMaxKc = 32;    // largest number of K chunks (slices of at most 2304 nodes)
 constexpr int kCmLdw = kCmRows + 4;  // LDS row of the staged W_i chunk (bank offset per row)
 
 // FP64 factors (rows of b values) -> FP32 rows of ldw values, zero padded.
@@ -66,18 +66,20 @@ bool chain_mfma_ok(int b, int m0) {
 }
 
 // Previous step's value of row r of member (slot) m: the sum of the nkc K-chunk
-// partials of its class (b / 64 rounded up, at most kCmMaxKc) in chunk order,
+// partials of its class (b / kCmKc rounded up, at most MAXK) in chunk order,
 // subtracted from t (backward, sub != nullptr).  Every load is issued before
-// the first add (clamped addresses, masked values), so their latencies overlap.
+// the first add (clamped addresses, masked values), so their latencies overlap;
+// MAXK (16 or 32, the batch's largest chunk count rounded up) bounds the loads.
+template <int MAXK>
 __device__ inline double cm_prev(const float* __restrict__ part, int nkc, int mtot, int bmax,
                                  int slot, int r, const double* sub) {
-  float v[kCmMaxKc];
+  float v[MAXK];
 #pragma unroll
-  for (int kc = 0; kc < kCmMaxKc; ++kc)
+  for (int kc = 0; kc < MAXK; ++kc)
     v[kc] = part[((long)min(kc, nkc - 1) * mtot + slot) * bmax + r];
   double acc = 0.0;
 #pragma unroll
-  for (int kc = 0; kc < kCmMaxKc; ++kc)
+  for (int kc = 0; kc < MAXK; ++kc)
     if (kc < nkc) acc += (double)v[kc];
   return sub != nullptr ? *sub - acc : acc;
 }
@@ -87,7 +89,7 @@ __device__ inline double cm_prev(const float* __restrict__ part, int nkc, int mt
 // BWD: x_{i+1} = (i + 1 == nch - 1 ? 0 : t_{i+1}) - ... : the partials of the
 // product of step i + 1 are W_{i+1} E_{i+2}^T x_{i+2}, or t_{n-1} itself after
 // the last forward step; x_{i+1} into batch, g = E_{i+1}^T x_{i+1}.
-template <bool FWD>
+template <bool FWD, int MAXK>
 __global__ void __launch_bounds__(kBlock) k_cm_rhs(Geo g, const double* __restrict__ T,
                                                    const TypeDev* __restrict__ types,
                                                    const ChainJob* __restrict__ jobs, int i,
@@ -117,10 +119,10 @@ __global__ void __launch_bounds__(kBlock) k_cm_rhs(Geo g, const double* __restri
     for (int r = lo + threadIdx.x; r < hi; r += kBlock) {
       double v;
       if (FWD || j == nch - 1) {
-        v = cm_prev(part, nkc, mtot, bmax, slot, r, nullptr);
+        v = cm_prev<MAXK>(part, nkc, mtot, bmax, slot, r, nullptr);
       } else {
         const double t = td.tbatch[base + (long)j * b + r];
-        v = cm_prev(part, nkc, mtot, bmax, slot, r, &t);
+        v = cm_prev<MAXK>(part, nkc, mtot, bmax, slot, r, &t);
       }
       prev[r - (R0 - H)] = v;
       if (r >= R0 && r < R0 + kCmRb) {
@@ -150,7 +152,7 @@ __global__ void __launch_bounds__(kBlock) k_cm_rhs(Geo g, const double* __restri
 }
 
 // Partial product of sweep step i: rows [R0, R0 + 128) x the job's members x
-// K chunk [K0, K0 + 64) of W_i g, into part[kc][slot][row].
+// K chunk [K0, K0 + kCmKc) of W_i g, into part[kc][slot][row].
 __global__ void __launch_bounds__(kBlock) k_cm_mm(const TypeDev* __restrict__ types,
                                                   const ChainJob* __restrict__ jobs, int i,
                                                   int mtot, int bmax,
@@ -249,6 +251,7 @@ __global__ void __launch_bounds__(kBlock) k_cm_mm(const TypeDev* __restrict__ ty
 
 // x_0 = t_0 - (partials) after the backward sweep, or x_0 = t_0 = (partials)
 // for a chain of one slice.  Grid: (row blocks, jobs, members).
+template <int MAXK>
 __global__ void __launch_bounds__(kBlock) k_cm_fin(const TypeDev* __restrict__ types,
                                                    const ChainJob* __restrict__ jobs, int mtot,
                                                    int bmax, const float* __restrict__ part,
@@ -265,10 +268,10 @@ __global__ void __launch_bounds__(kBlock) k_cm_fin(const TypeDev* __restrict__ t
   const long at = (long)(jb.m0 + m) * td.nch * b + r;
   const int slot = jb.mg0 + m;
   if (td.nch == 1) {
-    td.batch[at] = cm_prev(part, nkc, mtot, bmax, slot, r, nullptr);
+    td.batch[at] = cm_prev<MAXK>(part, nkc, mtot, bmax, slot, r, nullptr);
   } else {
     const double t = td.tbatch[at];
-    td.batch[at] = cm_prev(part, nkc, mtot, bmax, slot, r, &t);
+    td.batch[at] = cm_prev<MAXK>(part, nkc, mtot, bmax, slot, r, &t);
   }
 }
 
@@ -286,21 +289,24 @@ void launch_chain_mfma(const ddeig_problem* P, const PcgState* st, hipStream_t s
   float* G = part + (long)nkc * mtot * bmax;
   const dim3 grhs((bmax + kCmRb - 1) / kCmRb, P->nchainjobs, kCmMembers);
   const dim3 gmm((bmax + kCmRows - 1) / kCmRows, nkc, P->nchainjobs);
+  const bool k16 = nkc <= 16;
+  auto rhs_f = k16 ? k_cm_rhs<true, 16> : k_cm_rhs<true, kCmMaxKc>;
+  auto rhs_b = k16 ? k_cm_rhs<false, 16> : k_cm_rhs<false, kCmMaxKc>;
+  auto fin = k16 ? k_cm_fin<16> : k_cm_fin<kCmMaxKc>;
   for (int i = 0; i < nch; ++i) {
-    hipLaunchKernelGGL(k_cm_rhs<true>, grhs, dim3(kBlock), 0, s, P->g, P->tabAs, P->dTypes,
+    hipLaunchKernelGGL(rhs_f, grhs, dim3(kBlock), 0, s, P->g, P->tabAs, P->dTypes,
                        P->dChainJobs, i, mtot, bmax, part, G, st);
     hipLaunchKernelGGL(k_cm_mm, gmm, dim3(kBlock), 0, s, P->dTypes, P->dChainJobs, i, mtot, bmax,
                        G, part, st);
   }
   for (int i = nch - 2; i >= 0; --i) {
-    hipLaunchKernelGGL(k_cm_rhs<false>, grhs, dim3(kBlock), 0, s, P->g, P->tabAs, P->dTypes,
+    hipLaunchKernelGGL(rhs_b, grhs, dim3(kBlock), 0, s, P->g, P->tabAs, P->dTypes,
                        P->dChainJobs, i, mtot, bmax, part, G, st);
     hipLaunchKernelGGL(k_cm_mm, gmm, dim3(kBlock), 0, s, P->dTypes, P->dChainJobs, i, mtot, bmax,
                        G, part, st);
   }
   const dim3 gfin((bmax + kBlock - 1) / kBlock, P->nchainjobs, kCmMembers);
-  hipLaunchKernelGGL(k_cm_fin, gfin, dim3(kBlock), 0, s, P->dTypes, P->dChainJobs, mtot, bmax, part,
-                     st);
+  hipLaunchKernelGGL(fin, gfin, dim3(kBlock), 0, s, P->dTypes, P->dChainJobs, mtot, bmax, part, st);
 }
 
 }  // namespace ddeig
