@@ -224,6 +224,36 @@ def test_reduced_precision_local_solves(torch, case, prec):
     assert np.sqrt(d @ (P.M @ d)) <= 1e-8
 
 
+def test_fp32_chains_of_wide_slices(torch):
+    """FP32 chain local solves on MFMA with slices of 39 x 31 = 1209 unknowns:
+    17 K chunks of the product, so the partial sums take the 32-load path.
+    The preconditioner against the oracle's exact AS2 (FP32 factors: 1e-4
+    relative in 2-norm), and PCG to rtol 1e-10 in at most 15% + 2 iterations
+    more than the oracle's exact-local-solve count (the bar of the rounded
+    preconditioners at full size: near rtol the FP32 perturbation of M^{-1}
+    costs a few iterations), with the true residual below 1.1 rtol."""
+    import paper_2311_08757_amd as dd
+    from oracle.pcg import pcg
+    case = (1, 2, 3, 32, 4, W.sep_fourier(7))
+    P = _oracle(case)
+    prob = _assemble(case, local_prec="fp32")
+    dd.set_shift(prob, P.sigma, P.cell["psi"])
+    M2 = P.preconditioner(True)
+    r = W.random_vector(P.grid.n, 7)
+    z = torch.empty(P.grid.n, dtype=torch.float64, device="cuda")
+    dd.apply_precond(prob, _dev(torch, r), z)
+    torch.cuda.synchronize()
+    zr = M2.apply(r)
+    assert np.linalg.norm(z.cpu().numpy() - zr) <= 1e-4 * np.linalg.norm(zr)
+    b = P.M @ np.ones(P.grid.n)
+    x = torch.zeros(P.grid.n, dtype=torch.float64, device="cuda")
+    out = dd.pcg_solve(prob, _dev(torch, b), x, rtol=1e-10, maxit=500)
+    ref = pcg(lambda v: P.A_sigma @ v, b, M2.apply, rtol=1e-10, maxit=500)
+    assert ref.iters - 2 <= out["iters"] <= 1.15 * ref.iters + 2
+    xs = x.cpu().numpy()
+    assert np.linalg.norm(b - P.A_sigma @ xs) <= 1.1e-10 * np.linalg.norm(b)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "bf16"])
 def test_graph_replay_bitwise(torch, prec):
     """PCG iteration blocks replayed from captured HIP graphs give the bits of
