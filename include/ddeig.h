@@ -423,15 +423,24 @@ typedef struct ddeig_batch ddeig_batch;
  * repeats the first batch's bits. */
 #define DDEIG_BATCH_GRAPHS 1
 #define DDEIG_BATCH_REPRODUCIBLE 2
+/* With DDEIG_BATCH_REPRODUCIBLE only: 64-row GEMM tiles instead of 128 (the
+ * tile rows do not change the arithmetic: the results are the same bits). */
+#define DDEIG_BATCH_TILE64 4
 
 ddeig_status ddeig_batch_create(ddeig_problem* const* probs, int n, int flags, ddeig_batch** out);
 
 /* Autotuner result: K split, tile order (0 instance-major, 1 XCD-interleaved),
- * number of GEMM tiles, and the six measured candidate times in us
+ * number of GEMM tiles, and the six measured times in us of the 128-row tiles
  * (split 1..3 x order 0..1; 0 where a split was not admissible, and all 0
  * when nothing was timed: DDEIG_BATCH_REPRODUCIBLE or a remembered choice). */
 ddeig_status ddeig_batch_query(const ddeig_batch* B, int* ksplit, int* order, int* ntiles,
                                double* tune_us);
+
+/* The tile shape of the autotuner's choice and all twelve timings: tile_rows
+ * (128, or 64 when the instances' padding rows make smaller row tiles pay),
+ * tune_us[12] in us, index (tile rows 128: 0, 64: 1) x 6 + (split - 1) x 2 +
+ * order (0 where a candidate was not timed). */
+ddeig_status ddeig_batch_tuning(const ddeig_batch* B, int* tile_rows, double* tune_us);
 
 /* PCG for every instance j: A_sigma,j x[j] = b[j] (host arrays of n device
  * pointers; x[j] holds x0 on entry).  info (nullable, n entries; hist is

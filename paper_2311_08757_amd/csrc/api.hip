@@ -2283,7 +2283,8 @@ struct ddeig_batch {
   ddeig::PcgState* hst = nullptr;             // pinned: CG states behind two blocks of iterations
   hipEvent_t ev_st[2] = {nullptr, nullptr};   // recorded after each block's state copy
   std::vector<void*> allocs;
-  double tune_us[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int tile_rows = 128;      // GEMM tile rows (128, or 64 to skip padding rows)
+  double tune_us[12] = {};  // [tile rows 128, 64][split 1..3][order 0..1]
   // hipGraph replay of the grouped iterations: one executable graph per
   // (first iteration of a block of 8, maxit), captured on first use
   int use_graphs = 0;
@@ -2295,7 +2296,7 @@ namespace {
 
 // GEMM choices of the batch autotuner by shape, for the life of the process
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, int>> g_tune;
+std::map<std::string, std::array<int, 3>> g_tune;
 
 template <typename T>
 T* balloc(ddeig_batch* B, size_t count) {
@@ -2327,19 +2328,21 @@ ddeig::BlockMap make_map(ddeig_batch* B, const std::vector<int>& counts) {
 // of one (instance, column tile, split), which read the same rows of that
 // instance's inverse.  order 1 interleaves eight groups of equal size so that
 // a group's tiles get workgroup ids 8 apart (one XCD, one L2 copy of the rows).
-std::vector<ddeig::GemmTile> batch_tiles(const ddeig_batch* B, int ks, int order) {
+std::vector<ddeig::GemmTile> batch_tiles(const ddeig_batch* B, int ks, int order, int tm) {
   const int bk = B->local_prec == 2 ? 32 : 64;
   const int npair = B->ld / bk / 2;
   std::vector<std::vector<ddeig::GemmTile>> groups;
   for (int j = 0; j < B->n; ++j) {
-    const int mp = B->P[j]->dh.mp;
+    // row tiles of tm rows covering the instance's subdomains (the rows past
+    // them, up to its padded row count, are skipped when tm = 64)
+    const int nrt = (B->P[j]->nsub + tm - 1) / tm;
     for (int sp = 0; sp < ks; ++sp) {
       const int kb0 = 2 * (int)((long)npair * sp / ks);
       const int kb1 = 2 * (int)((long)npair * (sp + 1) / ks);
       for (int nt = 0; nt < B->ld / 128; ++nt) {
         std::vector<ddeig::GemmTile> grp;
-        for (int mt = 0; mt < mp / 128; ++mt)
-          grp.push_back(ddeig::GemmTile{j, mt * 128, nt * 128, kb0 * bk, kb1 * bk, sp});
+        for (int mt = 0; mt < nrt; ++mt)
+          grp.push_back(ddeig::GemmTile{j, mt * tm, nt * 128, kb0 * bk, kb1 * bk, sp});
         groups.push_back(grp);
       }
     }
@@ -2378,7 +2381,7 @@ void batch_iteration(ddeig_batch* B, int k, int maxit, hipStream_t s) {
   launch_b_restrict(B->dInst, B->bm_node, k, s);
   check_hip(hipEventRecord(B->ev_fork, s), "record fork");
   check_hip(hipStreamWaitEvent(B->aux, B->ev_fork, 0), "wait fork");
-  launch_gemm_tiles(B->dTiles, B->ntiles, B->dGt, B->local_prec, s);
+  launch_gemm_tiles(B->dTiles, B->ntiles, B->dGt, B->local_prec, s, B->tile_rows);
   launch_embed_jobs(B->dEmbJobs, B->nembjobs, B->dEmb, B->ksplit, B->ld, B->hm0, B->hm1, B->mH, s);
   launch_b_coarse_rhs(B->dInst, B->bm_crhs, B->aux);
   launch_b_coarse_solve(B->dInst, B->bm_csol, B->aux);
@@ -2404,7 +2407,7 @@ void batch_pcg(ddeig_batch* B, const std::vector<int>& active, const std::vector
     launch_b_pcg_init(B->dInst, B->n, act, rtol, s);
     check_hip(hipEventRecord(B->ev_fork, s), "record fork");
     check_hip(hipStreamWaitEvent(B->aux, B->ev_fork, 0), "wait fork");
-    launch_gemm_tiles(B->dTiles, B->ntiles, B->dGt, B->local_prec, s);
+    launch_gemm_tiles(B->dTiles, B->ntiles, B->dGt, B->local_prec, s, B->tile_rows);
     launch_embed_jobs(B->dEmbJobs, B->nembjobs, B->dEmb, B->ksplit, B->ld, B->hm0, B->hm1, B->mH,
                       s);
     launch_b_coarse_rhs(B->dInst, B->bm_crhs, B->aux);
@@ -2484,14 +2487,15 @@ void batch_pcg(ddeig_batch* B, const std::vector<int>& active, const std::vector
     if (active[j] && B->hStates[j].done == 0) B->hStates[j].done = 4;
 }
 
-float time_gemm(ddeig_batch* B, const ddeig::GemmTile* dT, int nt, const ddeig::GemmType* gt) {
+float time_gemm(ddeig_batch* B, const ddeig::GemmTile* dT, int nt, const ddeig::GemmType* gt,
+                int tm) {
   hipEvent_t e0, e1;
   check_hip(hipEventCreate(&e0), "event");
   check_hip(hipEventCreate(&e1), "event");
-  for (int i = 0; i < 3; ++i) launch_gemm_tiles(dT, nt, gt, B->local_prec, B->stream);
+  for (int i = 0; i < 3; ++i) launch_gemm_tiles(dT, nt, gt, B->local_prec, B->stream, tm);
   check_hip(hipEventRecord(e0, B->stream), "record");
   const int reps = 10;
-  for (int i = 0; i < reps; ++i) launch_gemm_tiles(dT, nt, gt, B->local_prec, B->stream);
+  for (int i = 0; i < reps; ++i) launch_gemm_tiles(dT, nt, gt, B->local_prec, B->stream, tm);
   check_hip(hipEventRecord(e1, B->stream), "record");
   check_hip(hipEventSynchronize(e1), "sync");
   float ms = 0.0f;
@@ -2526,8 +2530,10 @@ ddeig_status ddeig_batch_create(ddeig_problem* const* probs, int n, int flags, d
   if (!probs || !out) return set_error(DDEIG_EINVAL, "probs or out is NULL");
   *out = nullptr;
   if (n < 1 || n > 4096) return set_error(DDEIG_EINVAL, "need 1 <= n <= 4096 instances");
-  if (flags & ~(DDEIG_BATCH_GRAPHS | DDEIG_BATCH_REPRODUCIBLE))
+  if (flags & ~(DDEIG_BATCH_GRAPHS | DDEIG_BATCH_REPRODUCIBLE | DDEIG_BATCH_TILE64))
     return set_error(DDEIG_EINVAL, "unknown batch flags");
+  if ((flags & DDEIG_BATCH_TILE64) && !(flags & DDEIG_BATCH_REPRODUCIBLE))
+    return set_error(DDEIG_EINVAL, "DDEIG_BATCH_TILE64 needs DDEIG_BATCH_REPRODUCIBLE");
   const ddeig_problem* P0 = probs[0];
   for (int j = 0; j < n; ++j) {
     const ddeig_problem* P = probs[j];
@@ -2588,37 +2594,44 @@ ddeig_status ddeig_batch_create(ddeig_problem* const* probs, int n, int flags, d
     std::string shape = std::to_string(B->local_prec) + "/" + std::to_string(B->ld) + "/" +
                         std::to_string(ks_max);
     for (auto* P : B->P) shape += "/" + std::to_string(P->nsub);
-    std::pair<int, int> choice{0, 0};
+    std::array<int, 3> choice{0, 0, 0};  // K split, order, tile rows
     if (flags & DDEIG_BATCH_REPRODUCIBLE) {
-      choice = {ks_max, 1};
+      choice = {ks_max, 1, (flags & DDEIG_BATCH_TILE64) ? 64 : 128};
     } else {
       std::lock_guard<std::mutex> lk(g_tune_mu);
       auto it = g_tune.find(shape);
       if (it != g_tune.end()) choice = it->second;
     }
-    if (choice.first > 0) {
-      B->ksplit = choice.first;
-      B->order = choice.second;
-      best_tiles = batch_tiles(B, B->ksplit, B->order);
+    if (choice[0] > 0) {
+      B->ksplit = choice[0];
+      B->order = choice[1];
+      B->tile_rows = choice[2];
+      best_tiles = batch_tiles(B, B->ksplit, B->order, B->tile_rows);
     } else {
+      // every tile shape (128 or 64 rows), K split and order; the tile rows do
+      // not change the arithmetic (each output sums the same K stages in the
+      // same order), the K split does
       ddeig::GemmType* dGtt = bupload(B, gtt);
       float best = 1e30f;
-      int ci = 0;
-      for (int ks = 1; ks <= ks_max; ++ks)
-        for (int order = 0; order < 2; ++order, ++ci) {
-          std::vector<ddeig::GemmTile> t = batch_tiles(B, ks, order);
-          ddeig::GemmTile* dT = bupload(B, t);
-          const float us = time_gemm(B, dT, (int)t.size(), dGtt);
-          if (ci < 8) B->tune_us[ci] = us;
-          if (us < best) {
-            best = us;
-            best_tiles = t;
-            B->ksplit = ks;
-            B->order = order;
+      for (int ti = 0; ti < 2; ++ti) {
+        const int tm = ti == 0 ? 128 : 64;
+        for (int ks = 1; ks <= ks_max; ++ks)
+          for (int order = 0; order < 2; ++order) {
+            std::vector<ddeig::GemmTile> t = batch_tiles(B, ks, order, tm);
+            ddeig::GemmTile* dT = bupload(B, t);
+            const float us = time_gemm(B, dT, (int)t.size(), dGtt, tm);
+            B->tune_us[ti * 6 + (ks - 1) * 2 + order] = us;
+            if (us < best) {
+              best = us;
+              best_tiles = t;
+              B->ksplit = ks;
+              B->order = order;
+              B->tile_rows = tm;
+            }
           }
-        }
+      }
       std::lock_guard<std::mutex> lk(g_tune_mu);
-      g_tune.emplace(shape, std::make_pair(B->ksplit, B->order));
+      g_tune.emplace(shape, std::array<int, 3>{B->ksplit, B->order, B->tile_rows});
     }
     B->dTiles = bupload(B, best_tiles);
     B->ntiles = (int)best_tiles.size();
@@ -2739,6 +2752,14 @@ ddeig_status ddeig_batch_query(const ddeig_batch* B, int* ksplit, int* order, in
   if (ntiles) *ntiles = B->ntiles;
   if (tune_us)
     for (int i = 0; i < 6; ++i) tune_us[i] = B->tune_us[i];
+  return DDEIG_OK;
+}
+
+ddeig_status ddeig_batch_tuning(const ddeig_batch* B, int* tile_rows, double* tune_us) {
+  if (!B) return set_error(DDEIG_EINVAL, "batch is NULL");
+  if (tile_rows) *tile_rows = B->tile_rows;
+  if (tune_us)
+    for (int i = 0; i < 12; ++i) tune_us[i] = B->tune_us[i];
   return DDEIG_OK;
 }
 

@@ -534,7 +534,7 @@ void launch_b_coarse_rhs(const InstDev* I, const BlockMap& bm, hipStream_t s);
 void launch_b_coarse_solve(const InstDev* I, const BlockMap& bm, hipStream_t s);
 void launch_b_coarse_field(const InstDev* I, const BlockMap& bm, hipStream_t s);
 void launch_gemm_tiles(const GemmTile* tiles, int ntiles, const GemmType* gt, int local_prec,
-                       hipStream_t s);
+                       hipStream_t s, int tile_rows = 128);
 void launch_embed_jobs(const EmbedJob* jobs, int njobs, const EmbedDev* cls, int ksplit, int ld,
                        int hm0, int hm1, int mH, hipStream_t s);
 void launch_b_states(const InstDev* I, int n, PcgState* out, int mark_done, hipStream_t s);

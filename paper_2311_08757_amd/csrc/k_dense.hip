@@ -21,10 +21,11 @@
 // changes the iteration count a little, not the attainable accuracy.  The
 // extension adds Z to the FP64 residual path.
 //
-// Tiling: 128 x 128 output tiles (4 waves of 2 x 2 MFMA tiles), 64 (bf16) or
-// 32 (bf16x3) K columns per stage, two stages of global loads in flight and
-// LDS double buffering, split-K partial tiles summed in a fixed order by the
-// extension kernel.  Classes with at most kGemvMax members (the
+// Tiling: 128 x 128 output tiles (4 waves of 2 x 2 MFMA tiles), or 64 x 128
+// (4 waves of 1 x 2; batches choose them where instances have few subdomain
+// rows, to skip padding rows), 64 (bf16) or 32 (bf16x3) K columns per stage,
+// two stages of global loads in flight and LDS double buffering, split-K
+// partial tiles summed in a fixed order by the extension kernel.  Classes with at most kGemvMax members (the
 // boundary cells) use a streaming matrix-vector kernel instead.
 #include "k_common.h"
 #include "k_coarse.h"
@@ -90,14 +91,16 @@ void launch_identity(double* v, int m, hipStream_t s) {
 // Operands: R_hi, R_lo (RLO), A_hi, A_lo (ALO).
 constexpr int kTM = 128, kTN = 128;
 
-template <bool RLO, bool ALO>
+template <bool RLO, bool ALO, int MI>
 struct GemmCfg {
   static constexpr int BK = (RLO && ALO) ? 32 : 64;  // K columns per stage
   static constexpr int LDK = BK + 8;                 // padded LDS row
   static constexpr int NR = RLO ? 2 : 1, NA = ALO ? 2 : 1;
   static constexpr int NOP = NR + NA;                // operands staged per stage
-  static constexpr int NV = BK / 16;                 // 16-byte vectors per thread and operand
-  static constexpr int NVT = NOP * NV;               // vectors per thread per stage
+  static constexpr int TM = 64 * MI;                 // rows of the tile (R operand)
+  static constexpr int NV = BK / 16;                 // 16-byte vectors per thread, A operand
+  static constexpr int NVR = NV * MI / 2;            // 16-byte vectors per thread, R operand
+  static constexpr int NVT = NR * NVR + NA * NV;     // vectors per thread per stage
   static constexpr int NS = BK / 16;                 // MFMA sub-steps per stage
   static constexpr int WPS = (NVT + NS - 1) / NS;    // vectors staged per sub-step
 };
@@ -107,14 +110,15 @@ typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4;
 // Workgroups beyond the ntiles tiles form the coarse right-hand side R_0 r
 // (ca.n of them, one per subdomain) on the CUs the tiles leave free; they
 // share nothing with the tiles, so no workgroup waits for another.
-template <bool RLO, bool ALO>
+template <bool RLO, bool ALO, int MI = 2>
 __global__ void __launch_bounds__(kBlock) k_dense_gemm(const GemmTile* __restrict__ tiles,
                                                        const GemmType* __restrict__ gtypes,
                                                        const PcgState* __restrict__ st,
                                                        int ntiles, CoarseRhsArgs ca) {
-  using C = GemmCfg<RLO, ALO>;
+  using C = GemmCfg<RLO, ALO, MI>;
   constexpr int BK = C::BK, LDK = C::LDK, NR = C::NR, NOP = C::NOP, NV = C::NV, NVT = C::NVT;
-  constexpr int NS = C::NS, WPS = C::WPS;
+  constexpr int NVR = C::NVR, NS = C::NS, WPS = C::WPS;
+  static_assert(MI == 1 || MI == 2, "64- or 128-row tiles");
   // [buffer][operand][row * LDK + k]; operands: R parts first, then A parts
   __shared__ __bf16 sm[2][NOP][kTM * LDK];
   if (st != nullptr && st->done) return;
@@ -128,38 +132,47 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemm(const GemmTile* __restric
   const int ld = gt.ld;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
-  // loader: row tid / 2, half tid % 2 of the BK columns of a stage.  The
-  // operands live in global memory: loads through address-space-1 pointers
-  // become global_load (flat loads would also count against the LDS wait
-  // counter and stall every fragment read behind the prefetch).
+  // loader: A operand row tid / 2, half tid % 2 of the BK columns of a stage;
+  // R operand (TM rows) row tid / (256 / TM), the matching share of the
+  // columns.  The operands live in global memory: loads through
+  // address-space-1 pointers become global_load (flat loads would also count
+  // against the LDS wait counter and stall every fragment read behind the
+  // prefetch).
   typedef __attribute__((address_space(1))) const u32x4* gvec;
   const int lrow = tid >> 1, lcol = (tid & 1) * (BK / 2);
+  constexpr int RPT = kBlock / C::TM;  // threads per R row
+  static_assert(RPT * C::TM == kBlock && (BK / RPT) % 8 == 0, "whole vectors per thread");
+  const int rrow = tid / RPT, rcol = (tid % RPT) * (BK / RPT);
   gvec gsrc[NOP];
-  gsrc[0] = (gvec)(gt.Rh + (long)(t.m0 + lrow) * ld + lcol);
-  if constexpr (RLO) gsrc[1] = (gvec)(gt.Rl + (long)(t.m0 + lrow) * ld + lcol);
+  gsrc[0] = (gvec)(gt.Rh + (long)(t.m0 + rrow) * ld + rcol);
+  if constexpr (RLO) gsrc[1] = (gvec)(gt.Rl + (long)(t.m0 + rrow) * ld + rcol);
   gsrc[NR] = (gvec)(gt.Ah + (long)(t.n0 + lrow) * ld + lcol);
   if constexpr (ALO) gsrc[NR + 1] = (gvec)(gt.Al + (long)(t.n0 + lrow) * ld + lcol);
-  const int soff = lrow * LDK + lcol;
+  const int soff = lrow * LDK + lcol, sroff = rrow * LDK + rcol;
   u32x4 ra[NVT], rb[NVT];
+  // vector q of a stage: operand and vector within the operand (R operands
+  // first, NVR vectors each, then the A operands, NV each)
+  auto qop = [](int q) { return q < NR * NVR ? q / NVR : NR + (q - NR * NVR) / NV; };
+  auto qv = [](int q) { return q < NR * NVR ? q % NVR : (q - NR * NVR) % NV; };
   // k: first K column of the stage; 8 bf16 per vector
   auto load = [&](u32x4* dst, int k) {
 #pragma unroll
-    for (int o = 0; o < NOP; ++o)
-#pragma unroll
-      for (int v = 0; v < NV; ++v) dst[o * NV + v] = gsrc[o][k / 8 + v];
+    for (int q = 0; q < NVT; ++q) dst[q] = gsrc[qop(q)][k / 8 + qv(q)];
   };
   auto stage1 = [&](const u32x4* src, int buf, int q) {
-    if (q < NVT)
-      *reinterpret_cast<u32x4*>(&sm[buf][q / NV][soff + 8 * (q % NV)]) = src[q];
+    if (q < NVT) {
+      const int o = qop(q);
+      *reinterpret_cast<u32x4*>(&sm[buf][o][(o < NR ? sroff : soff) + 8 * qv(q)]) = src[q];
+    }
   };
   struct Frag {
-    bf16x8 rh[2], rl[2], ah[2], al[2];
+    bf16x8 rh[MI], rl[MI], ah[2], al[2];
   };
   auto rd = [&](Frag& f, int buf, int ks) {
     const int kof = ks * 16 + 8 * (lane >> 5);
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int r = (wm * 2 + i) * 32 + (lane & 31);
+    for (int i = 0; i < MI; ++i) {
+      const int r = (wm * MI + i) * 32 + (lane & 31);
       f.rh[i] = *reinterpret_cast<const bf16x8*>(&sm[buf][0][r * LDK + kof]);
       if constexpr (RLO) f.rl[i] = *reinterpret_cast<const bf16x8*>(&sm[buf][1][r * LDK + kof]);
     }
@@ -170,9 +183,9 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemm(const GemmTile* __restric
       if constexpr (ALO) f.al[j] = *reinterpret_cast<const bf16x8*>(&sm[buf][NR + 1][c * LDK + kof]);
     }
   };
-  floatx16 acc[2][2];
+  floatx16 acc[MI][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -182,20 +195,20 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemm(const GemmTile* __restric
   auto mm = [&](const Frag& f) {
     if constexpr (RLO) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.rl[i], f.ah[j], acc[i][j], 0, 0, 0);
     }
     if constexpr (ALO) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.rh[i], f.al[j], acc[i][j], 0, 0, 0);
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.rh[i], f.ah[j], acc[i][j], 0, 0, 0);
@@ -237,12 +250,12 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemm(const GemmTile* __restric
   // row 8 (e / 4) + 4 (l / 32) + e % 4, column l % 32
   float* Zp = gt.Z + (long)t.split * gt.zsplit + (long)t.m0 * ld + t.n0;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        const int r = (wm * 2 + i) * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        const int r = (wm * MI + i) * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
         const int c = (wn * 2 + j) * 32 + (lane & 31);
         Zp[(long)r * ld + c] = acc[i][j][e];
       }
@@ -595,16 +608,14 @@ bool fused_coarse(const ddeig_problem* P) {
 // carry the instance in their type / class index, and each instance's CG
 // state is checked through GemmType::st / EmbedDev::st.
 void launch_gemm_tiles(const GemmTile* tiles, int ntiles, const GemmType* gt, int local_prec,
-                       hipStream_t s) {
+                       hipStream_t s, int tile_rows) {
   if (ntiles <= 0) return;
   CoarseRhsArgs none{};
   none.n = 0;
-  if (local_prec == 2)
-    hipLaunchKernelGGL((k_dense_gemm<true, true>), dim3(ntiles), dim3(kBlock), 0, s, tiles, gt,
-                       nullptr, ntiles, none);
-  else
-    hipLaunchKernelGGL((k_dense_gemm<false, false>), dim3(ntiles), dim3(kBlock), 0, s, tiles, gt,
-                       nullptr, ntiles, none);
+  auto kern = local_prec == 2
+                  ? (tile_rows == 64 ? k_dense_gemm<true, true, 1> : k_dense_gemm<true, true, 2>)
+                  : (tile_rows == 64 ? k_dense_gemm<false, false, 1> : k_dense_gemm<false, false, 2>);
+  hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kBlock), 0, s, tiles, gt, nullptr, ntiles, none);
 }
 
 void launch_embed_jobs(const EmbedJob* jobs, int njobs, const EmbedDev* cls, int ksplit, int ld,

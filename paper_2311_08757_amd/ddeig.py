@@ -74,7 +74,7 @@ EXPORTS = ["ddeig_assemble", "ddeig_cell_shift", "ddeig_set_shift", "ddeig_apply
            "ddeig_profile_kernel", "ddeig_profile_iteration", "ddeig_potential_form",
            "ddeig_potential_form_noalloc", "ddeig_eig_grad", "ddeig_shift_grad",
            "ddeig_solve_grad", "ddeig_batch_eig_grad", "ddeig_batch_solve_grad", "ddeig_batch_create",
-           "ddeig_batch_query", "ddeig_batch_pcg_solve", "ddeig_batch_inverse_iteration",
+           "ddeig_batch_query", "ddeig_batch_tuning", "ddeig_batch_pcg_solve", "ddeig_batch_inverse_iteration",
            "ddeig_batch_destroy", "ddeig_query", "ddeig_destroy", "ddeig_status_string",
            "ddeig_last_error"]
 
@@ -125,6 +125,8 @@ def load_library(path=LIB_PATH):
     lib.ddeig_batch_create.argtypes = [PP, ctypes.c_int, ctypes.c_int, PP]
     lib.ddeig_batch_query.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_int), dp]
+    lib.ddeig_batch_tuning.argtypes = [P, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_double)]
     lib.ddeig_batch_pcg_solve.argtypes = [P, PP, PP, ctypes.c_double, ctypes.c_int,
                                           ctypes.POINTER(PcgInfo)]
     lib.ddeig_batch_inverse_iteration.argtypes = [P, PP, ctypes.c_double, ctypes.c_int,
@@ -502,28 +504,34 @@ def _ptr_array(ts, ns, name):
     return arr
 
 
-def batch_create(probs, graphs=True, reproducible=False):
+def batch_create(probs, graphs=True, reproducible=False, tile64=False):
     """ddeig_batch_create over a list of Problems (runs the GEMM autotuner, or
     reuses its choice for the same shapes); graphs: replay the grouped
     iterations from captured HIP graphs; reproducible: no timing, the
-    single-problem K split (DDEIG_BATCH_REPRODUCIBLE)."""
+    single-problem K split (DDEIG_BATCH_REPRODUCIBLE); tile64 (with
+    reproducible): 64-row GEMM tiles (DDEIG_BATCH_TILE64)."""
     lib = load_library()
     arr = (ctypes.c_void_p * len(probs))(*[p.handle.value if isinstance(p.handle, ctypes.c_void_p)
                                            else p.handle for p in probs])
     h = ctypes.c_void_p()
-    flags = (1 if graphs else 0) | (2 if reproducible else 0)
+    flags = (1 if graphs else 0) | (2 if reproducible else 0) | (4 if tile64 else 0)
     _check(lib.ddeig_batch_create(arr, len(probs), flags, ctypes.byref(h)),
            "ddeig_batch_create")
     return Batch(h, probs)
 
 
 def batch_query(batch):
+    """ddeig_batch_query + ddeig_batch_tuning: the autotuner's K split, order,
+    tile rows, tile count, the six 128-row timings and all twelve."""
     lib = load_library()
-    ks, order, nt = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    ks, order, nt, tr = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     tune = (ctypes.c_double * 6)()
+    tune12 = (ctypes.c_double * 12)()
     _check(lib.ddeig_batch_query(batch.handle, ctypes.byref(ks), ctypes.byref(order),
                                  ctypes.byref(nt), tune), "ddeig_batch_query")
-    return dict(ksplit=ks.value, order=order.value, ntiles=nt.value, tune_us=list(tune))
+    _check(lib.ddeig_batch_tuning(batch.handle, ctypes.byref(tr), tune12), "ddeig_batch_tuning")
+    return dict(ksplit=ks.value, order=order.value, tile_rows=tr.value, ntiles=nt.value,
+                tune_us=list(tune), tune_us_all=list(tune12))
 
 
 def batch_pcg_solve(batch, bs, xs, rtol=1e-10, maxit=1000, raise_on_error=True):

@@ -104,14 +104,17 @@ def test_batch_reproducible(torch, prec):
         out = dd.pcg_solve(p, b, x, rtol=1e-10, maxit=500)
         single.append((x, out["iters"]))
     ks_single = min(3, 128 // (64 if prec == "bf16" else 32) // 2)
-    br = dd.batch_create(probs, reproducible=True)
-    q = dd.batch_query(br)
-    assert q["ksplit"] == ks_single and q["order"] == 1 and not any(q["tune_us"])
-    xs = [torch.zeros_like(b) for b in bs]
-    st, info = dd.batch_pcg_solve(br, bs, xs, rtol=1e-10, maxit=500)
-    assert st == "OK"
-    for j, ((x1, it1), x2) in enumerate(zip(single, xs)):
-        assert info[j]["iters"] == it1 and torch.equal(x1, x2), j
+    for tile64 in (False, True):
+        # 128- and 64-row GEMM tiles: the same arithmetic, so the same bits
+        br = dd.batch_create(probs, reproducible=True, tile64=tile64)
+        q = dd.batch_query(br)
+        assert q["ksplit"] == ks_single and q["order"] == 1 and not any(q["tune_us_all"])
+        assert q["tile_rows"] == (64 if tile64 else 128)
+        xs = [torch.zeros_like(b) for b in bs]
+        st, info = dd.batch_pcg_solve(br, bs, xs, rtol=1e-10, maxit=500)
+        assert st == "OK"
+        for j, ((x1, it1), x2) in enumerate(zip(single, xs)):
+            assert info[j]["iters"] == it1 and torch.equal(x1, x2), (tile64, j)
     b1 = dd.batch_create(probs)
     b2 = dd.batch_create(probs)
     q1, q2 = dd.batch_query(b1), dd.batch_query(b2)
@@ -153,6 +156,9 @@ def test_batch_create_errors(torch):
     for bad in ([p8, p_fp64], [p8, p_ne16], [p_small], [p_3d], [p8, p8], []):
         with pytest.raises(dd.DdeigError):
             dd.batch_create(bad)
+    with pytest.raises(dd.DdeigError) as e:   # 64-row tiles only without timing
+        dd.batch_create([p8], tile64=True)
+    assert e.value.code == "EINVAL"
 
 
 @pytest.mark.timeout(900)
