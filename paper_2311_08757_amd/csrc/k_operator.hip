@@ -832,19 +832,33 @@ __global__ void __launch_bounds__(kBlock) k_stencil3d_march(Geo g, const double*
       }
     }
     __syncthreads();
-    if (rowin) {
+    // MODE 0 takes the columns in two halves with a barrier between them
+    // (outside the divergent row test): left to itself the compiler issues
+    // all 72 LDS reads of a plane before the first FMA and the kernel needs
+    // ~270 VGPRs (one wave per SIMD); by halves it needs ~200 and two waves
+    // fit (62,979,135 unknowns: 411 -> 350 us).  MODE 1 holds the previous
+    // direction's plane as well and stays near 270 VGPRs either way; the
+    // barrier only costs it time, so it keeps one group.
+    constexpr int NG = MODE == 0 ? 2 : 1;
 #pragma unroll
-      for (int s = 0; s < RX; ++s) {
-        const int cx = xl + 32 * s + 1;
+    for (int h = 0; h < NG; ++h) {
+      if (h > 0) __syncthreads();
+      if (rowin) {
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-          const double v = P[(cx + t % 3 - 1) + HX * (ty + t / 3)];
-          if (t == 4) vc[s] = v;
-          am[s] += c[t] * v;
-          a0[s] += c[9 + t] * v;
-          ap[s] += c[18 + t] * v;
+        for (int s = h * (RX / NG); s < (h + 1) * (RX / NG); ++s) {
+          const int cx = xl + 32 * s + 1;
+#pragma unroll
+          for (int t = 0; t < 9; ++t) {
+            const double v = P[(cx + t % 3 - 1) + HX * (ty + t / 3)];
+            if (t == 4) vc[s] = v;
+            am[s] += c[t] * v;
+            a0[s] += c[9 + t] * v;
+            ap[s] += c[18 + t] * v;
+          }
         }
       }
+    }
+    if (rowin) {
       if (k > 0) {
 #pragma unroll
         for (int s = 0; s < RX; ++s) {

@@ -6,7 +6,8 @@ tile sweep and the oracle.
   (every output takes its taps in the same order from the same values), on
   grids of one ragged workgroup, of several workgroups with a ragged last one,
   and at the 66,060,225-unknown HBM-scale grid (sweep chosen by size) over the
-  whole vector;
+  whole vector; also with x and y at element offsets within a 128-byte line,
+  writing nothing outside y;
 - at that size, sampled rows of A_sigma x against the oracle: the operator is
   periodic in x with the period cell's coefficients, so the row of node (i, j)
   is the row of the node with the same cell-local position in a small oracle
@@ -74,6 +75,30 @@ def test_march_equals_tiles(torch, case):
         dd.apply_op(pt, op, x, yt)
         torch.cuda.synchronize()
         assert torch.equal(ym, yt), op
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_march_unaligned_vectors(torch, case):
+    """x and y at element offsets within a 128-byte line (views into larger
+    buffers): the march gives the tile sweep's bits at every offset and writes
+    nothing outside y."""
+    import paper_2311_08757_amd as dd
+    pm, pt = _assemble(case, "march"), _assemble(case, "tiles")
+    sig, psi = dd.cell_shift(pt)
+    dd.set_shift(pm, sig, psi)
+    n = pm.n_dof
+    xb = _dev(torch, W.random_vector(n + 16, 6))
+    yt = torch.empty(n, dtype=torch.float64, device="cuda")
+    for ox, oy in [(0, 1), (1, 0), (3, 7), (5, 15), (15, 9)]:
+        x = xb[ox:ox + n]
+        yb = torch.full((n + 16,), float("nan"), dtype=torch.float64, device="cuda")
+        y = yb[oy:oy + n]
+        dd.apply_op(pt, "A_sigma", x, yt)
+        dd.apply_op(pm, "A_sigma", x, y)
+        torch.cuda.synchronize()
+        assert torch.equal(y, yt), (ox, oy)
+        # nothing written outside y
+        assert torch.isnan(yb[:oy]).all() and torch.isnan(yb[oy + n:]).all(), (ox, oy)
 
 
 @pytest.mark.parametrize("case", CASES, ids=IDS)
