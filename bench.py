@@ -596,6 +596,12 @@ def main():
             "achieved_executed": work_exec / t_loc / 1e6,
             "frac_executed": work_exec / t_loc / 1e6 / path["peak"],
             "executed_basis": path["executed"]}
+    if roof["traffic"] is not None:
+        # the counted HBM-side bytes of the same launch against the HBM peak:
+        # at about 120 executed flop per counted byte the dense GEMM sits below
+        # the bf16 ridge (2.5 PFLOP/s / 8 TB/s = 312 flop/B)
+        roof["achieved_traffic_GBs"] = roof["traffic"] / t_loc / 1e3
+        roof["frac_traffic_hbm"] = roof["traffic"] / t_loc / 1e3 / HBM_PEAK_GBS
     # one PCG iteration part by part (events between the launches of the loop)
     bvec0 = torch.as_tensor(W.random_vector(n, 15), dtype=torch.float64, device="cuda")
     parts = dd.profile_iteration(prob, bvec0, reps=30)
