@@ -1333,7 +1333,7 @@ ddeig_status ddeig_assemble(const ddeig_geometry* geom, double h, const ddeig_po
       if (!tiles.empty())
         check_hip(hipMemcpyAsync(P->dTiles, tiles.data(), sizeof(ddeig::GemmTile) * tiles.size(),
                                  hipMemcpyHostToDevice, s), "copy tiles");
-      const ddeig::GemmType gt{H.Ah, H.Al, H.Rh, H.Rl, H.Z, (long)H.mp * H.ld, H.ld, nullptr};
+      const ddeig::GemmType gt{H.Ah, H.Al, H.Rh, H.Rl, H.Z, (long)H.mp * H.ld, H.ld, nsub, nullptr};
       P->dGtypes = dalloc<ddeig::GemmType>(P, 1);
       check_hip(hipMemcpyAsync(P->dGtypes, &gt, sizeof(ddeig::GemmType), hipMemcpyHostToDevice, s),
                 "copy gemm operands");
@@ -2585,7 +2585,8 @@ ddeig_status ddeig_batch_create(ddeig_problem* const* probs, int n, int flags, d
     std::vector<ddeig::GemmType> gts(n), gtt(n);
     for (int j = 0; j < n; ++j) {
       const ddeig::DenseHost& H = B->P[j]->dh;
-      gts[j] = ddeig::GemmType{H.Ah, H.Al, H.Rh, H.Rl, H.Z, (long)H.mp * H.ld, H.ld, B->P[j]->st};
+      gts[j] = ddeig::GemmType{H.Ah, H.Al, H.Rh, H.Rl, H.Z, (long)H.mp * H.ld, H.ld,
+                               B->P[j]->nsub, B->P[j]->st};
       gtt[j] = gts[j];
       gtt[j].st = nullptr;
     }

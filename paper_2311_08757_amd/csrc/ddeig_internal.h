@@ -212,8 +212,10 @@ struct GemmType {
   float* Z;
   long zsplit;
   int ld;
+  int rows;            // rows of R that hold subdomains (read by the batch's kernels only)
   const PcgState* st;  // CG state checked by grouped launches (nullptr: the launch's own)
 };
+static_assert(sizeof(GemmType) == 64, "rows sits in the padding after ld");
 
 // Batched chain solves: one workgroup per (class, member tile, 64 rows of a slice).
 // Extra workgroups of the dense GEMM launch that form the coarse right-hand

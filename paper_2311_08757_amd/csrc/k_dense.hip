@@ -110,7 +110,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4;
 // Workgroups beyond the ntiles tiles form the coarse right-hand side R_0 r
 // (ca.n of them, one per subdomain) on the CUs the tiles leave free; they
 // share nothing with the tiles, so no workgroup waits for another.
-template <bool RLO, bool ALO, int MI = 2>
+template <bool RLO, bool ALO, int MI = 2, bool BND = false>
 __global__ void __launch_bounds__(kBlock) k_dense_gemm(const GemmTile* __restrict__ tiles,
                                                        const GemmType* __restrict__ gtypes,
                                                        const PcgState* __restrict__ st,
@@ -148,6 +148,19 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemm(const GemmTile* __restric
   if constexpr (RLO) gsrc[1] = (gvec)(gt.Rl + (long)(t.m0 + rrow) * ld + rcol);
   gsrc[NR] = (gvec)(gt.Ah + (long)(t.n0 + lrow) * ld + lcol);
   if constexpr (ALO) gsrc[NR + 1] = (gvec)(gt.Al + (long)(t.n0 + lrow) * ld + lcol);
+  // BND (batches, whose instances leave tile rows unused): R through buffer
+  // resources that end at the instance's last subdomain row, so that padding
+  // rows read as zero without a memory request (the rows hold zeros), and the
+  // padding rows of Z are not stored
+  __amdgpu_buffer_rsrc_t rsrc[NR];
+  unsigned roff = 0;
+  if constexpr (BND) {
+    const int rbytes = gt.rows * ld * 2;
+    rsrc[0] = __builtin_amdgcn_make_buffer_rsrc((void*)gt.Rh, (short)0, rbytes, 0x00020000);
+    if constexpr (RLO)
+      rsrc[1] = __builtin_amdgcn_make_buffer_rsrc((void*)gt.Rl, (short)0, rbytes, 0x00020000);
+    roff = (unsigned)(((t.m0 + rrow) * ld + rcol) * 2);
+  }
   const int soff = lrow * LDK + lcol, sroff = rrow * LDK + rcol;
   u32x4 ra[NVT], rb[NVT];
   // vector q of a stage: operand and vector within the operand (R operands
@@ -157,7 +170,17 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemm(const GemmTile* __restric
   // k: first K column of the stage; 8 bf16 per vector
   auto load = [&](u32x4* dst, int k) {
 #pragma unroll
-    for (int q = 0; q < NVT; ++q) dst[q] = gsrc[qop(q)][k / 8 + qv(q)];
+    for (int q = 0; q < NVT; ++q) {
+      if constexpr (BND) {
+        const int o = qop(q);
+        if (o < NR) {
+          dst[q] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                 rsrc[o], roff + 16u * qv(q), (unsigned)k * 2u, 0));
+          continue;
+        }
+      }
+      dst[q] = gsrc[qop(q)][k / 8 + qv(q)];
+    }
   };
   auto stage1 = [&](const u32x4* src, int buf, int q) {
     if (q < NVT) {
@@ -257,7 +280,7 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemm(const GemmTile* __restric
       for (int e = 0; e < 16; ++e) {
         const int r = (wm * MI + i) * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
         const int c = (wn * 2 + j) * 32 + (lane & 31);
-        Zp[(long)r * ld + c] = acc[i][j][e];
+        if (!BND || t.m0 + r < gt.rows) Zp[(long)r * ld + c] = acc[i][j][e];
       }
 }
 
@@ -612,9 +635,10 @@ void launch_gemm_tiles(const GemmTile* tiles, int ntiles, const GemmType* gt, in
   if (ntiles <= 0) return;
   CoarseRhsArgs none{};
   none.n = 0;
-  auto kern = local_prec == 2
-                  ? (tile_rows == 64 ? k_dense_gemm<true, true, 1> : k_dense_gemm<true, true, 2>)
-                  : (tile_rows == 64 ? k_dense_gemm<false, false, 1> : k_dense_gemm<false, false, 2>);
+  auto kern = local_prec == 2 ? (tile_rows == 64 ? k_dense_gemm<true, true, 1, true>
+                                                 : k_dense_gemm<true, true, 2, true>)
+                              : (tile_rows == 64 ? k_dense_gemm<false, false, 1, true>
+                                                 : k_dense_gemm<false, false, 2, true>);
   hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kBlock), 0, s, tiles, gt, nullptr, ntiles, none);
 }
 
