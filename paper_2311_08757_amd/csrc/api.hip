@@ -2551,6 +2551,9 @@ ddeig_status ddeig_batch_create(ddeig_problem* const* probs, int n, int flags, d
       return set_error(DDEIG_EINVAL, who + "batches need L > " + std::to_string(ddeig::kGemvMax));
     if (ddeig::stencil_tiles(P->g) > kMaxRed)
       return set_error(DDEIG_EINVAL, who + "instance too large for a batch (stencil tiles > 1024)");
+    // the grouped GEMM reads R through buffer resources with 32-bit byte counts
+    if ((long)P->dh.mp * P->dh.ld * 2 >= (1L << 31))
+      return set_error(DDEIG_EINVAL, who + "instance too large for a batch (restricted residuals)");
     if (P->opt.local_prec != P0->opt.local_prec || P->g.ne != P0->g.ne ||
         P->delta != P0->delta || P->g.N[1] != P0->g.N[1] || P->dh.ld != P0->dh.ld ||
         P->dh.m != P0->dh.m || P->stream != P0->stream || P->opt.pu != P0->opt.pu)
